@@ -1,0 +1,421 @@
+/*
+ * sx_oracle.c -- CPU reference ("oracle") for SimpleX2 direction-conserving
+ * transport with on-the-spot hydrogen chemistry.
+ *
+ * TEST INFRASTRUCTURE ONLY: called by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg.  The product library never uses it.
+ *
+ * Plain sequential FP64, compiled with -ffp-contract=off.  Every loop runs in
+ * a fixed order: vertex ascending, bin ascending, neighbour slot ascending,
+ * source ascending.  Each step cites the passage of Paardekooper, Kruip &
+ * Icke (2010) it follows; where the paper leaves a detail open the chosen
+ * reading is stated next to the code.
+ */
+#include "sx_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+static char g_err[256];
+const char *ora_last_error(void) { return g_err; }
+
+struct ora_grid {
+    int64_t n;
+    int64_t n_edges;
+    int32_t K, mpb;
+    double cos_min, sigma, alpha_B, dt;
+    int32_t n_sub;
+    int64_t *ptr;        /* [N+1] */
+    int32_t *nbr;        /* [E]   */
+    double *edir;        /* [E*3] unit edge vectors (Sect. 2.2) */
+    double *elen;        /* [E]   edge lengths */
+    double *bins;        /* [K*3] */
+    double *nH, *vol, *dL, *tau; /* [N] */
+    int32_t *sel;        /* [N*K*mpb] selected neighbour ids, best first */
+    int32_t *m;          /* [N*K] number selected */
+    int32_t *ebin;       /* [E] bin of each directed edge */
+    int32_t n_src;
+    int32_t *src_v;
+    double *src_rate;
+    double *src_dir;     /* [S*3], zero row = isotropic */
+    double *y;           /* [N] neutral fraction */
+    double *O;           /* [N*K] outgoing photons per selected neighbour */
+    double *I;           /* [N*K] scratch: incoming photons */
+    double *nin;         /* [N] last sweep's incoming photons */
+    double sweeps, emitted, absorbed, escaped, in_flight;
+};
+
+static void *xcalloc(size_t n, size_t s) {
+    void *p = calloc(n ? n : 1, s);
+    return p;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Direction cosine of a unit edge vector with a unit direction: the
+ * "straightforwardness" used to rank neighbours (Sect. 2.2.2-2.2.3).
+ * Evaluated as ((ex*ux + ey*uy) + ez*uz) with no fused multiply-add. */
+static double cosine(const double *e, const double *u) {
+    double a = e[0] * u[0];
+    double b = e[1] * u[1];
+    double c = e[2] * u[2];
+    return (a + b) + c;
+}
+
+/* The <= mpb neighbours of vertex i most aligned with direction u, keeping
+ * only those with cosine > cos_min (photons never travel backwards: the 90
+ * degree cone of Sect. 2.2.2).  Ties go to the lower neighbour id.  Writes
+ * the chosen slots (row positions) into out, returns how many. */
+static int select_slots(const ora_grid *g, int64_t i, const double *u,
+                        int32_t *out) {
+    int64_t b = g->ptr[i], deg = g->ptr[i + 1] - g->ptr[i];
+    int cnt = 0;
+    for (int r = 0; r < g->mpb; r++) {
+        int64_t best = -1;
+        double cb = 0.0;
+        for (int64_t s = 0; s < deg; s++) {
+            double c = cosine(&g->edir[3 * (b + s)], u);
+            if (!(c > g->cos_min)) continue;
+            int taken = 0;
+            for (int q = 0; q < cnt; q++) if (out[q] == s) taken = 1;
+            if (taken) continue;
+            if (best < 0 || c > cb ||
+                (c == cb && g->nbr[b + s] < g->nbr[b + best])) {
+                best = s;
+                cb = c;
+            }
+        }
+        if (best < 0) break;
+        out[cnt++] = (int32_t)best;
+    }
+    return cnt;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Chemistry of one vertex over one transport step (Sect. 4.5).
+ *
+ * The rate equation dn_HII/dt = n_HI Gamma - n_e n_HII alpha_B (Eq. rate_eq,
+ * on-the-spot, pure hydrogen so n_e = n_HII, no collisional ionisation) is
+ * subcycled with the photo-ionisation rate rescaled so that the incoming
+ * photon flux n_in/dt stays constant over the step (Eqs. rate_eq_subcycle,
+ * phot_ion_rate_subcycle).  With y the neutral fraction and tau the optical
+ * depth of the fully neutral cell, the ionisations per atom per second are
+ * a (1 - exp(-y tau)) with a = n_in / (dt n_H V), recombinations per atom per
+ * second are b (1 - y)^2 with b = alpha_B n_H.
+ *
+ * Reading of the subcycle step (the paper fixes neither the step nor the
+ * integrator): n_sub equal substeps h = dt/n_sub, each backward Euler in y,
+ *     y' = y - h a (1 - exp(-y' tau)) + h b (1 - y')^2 ,
+ * which is stable for any h, keeps the equilibrium points of the rate
+ * equation, and absorbs exactly as many photons as it ionises atoms.  The
+ * substep equation G(y') = 0 is monotone decreasing in y' on [0,1] with
+ * G(0) >= 0 >= G(1); it is solved by Newton's method from y' = y inside that
+ * bracket, falling back to bisection when a Newton step leaves it. */
+static double be_substep(double y0, double ha, double hb, double tau) {
+    double lo = 0.0, hi = 1.0, yn = y0;
+    for (int it = 0; it < 200; it++) {
+        double ion = -expm1(-yn * tau);          /* 1 - exp(-y tau) */
+        double x = 1.0 - yn;
+        double g = (y0 - yn) - ha * ion + hb * (x * x);
+        if (g == 0.0) return yn;
+        if (g > 0.0) lo = yn; else hi = yn;
+        double gp = -1.0 - ha * tau * exp(-yn * tau) - 2.0 * hb * x;
+        double yc = yn - g / gp;
+        if (!(yc > lo && yc < hi)) yc = 0.5 * (lo + hi);
+        double step = fabs(yc - yn);
+        yn = yc;
+        if (step <= 4.0e-16 * yn || hi - lo <= 4.0e-16 * hi) break;
+    }
+    return yn;
+}
+
+/* Returns the new y; *A = photons absorbed (= atoms ionised, summed over the
+ * substeps), *T = fraction of the incoming photons passed on, the mean over
+ * the substeps of exp(-y' tau) (Eqs. intensity_absorbed, intensity_out, with
+ * the optical depth of Eq. optical_depth re-evaluated every substep). */
+static double chem(double y, double n_in, double dt, double nHV, double tau,
+                   double b, int n_sub, double *A, double *T) {
+    double h = dt / (double)n_sub;
+    double a = n_in / (dt * nHV);
+    double ha = h * a, hb = h * b;
+    double abs_sum = 0.0, tr_sum = 0.0;
+    double share = n_in / (double)n_sub;
+    for (int s = 0; s < n_sub; s++) {
+        y = be_substep(y, ha, hb, tau);
+        abs_sum += share * (-expm1(-y * tau));
+        tr_sum += exp(-y * tau);
+    }
+    *A = abs_sum;
+    *T = (n_in > 0.0) ? tr_sum / (double)n_sub : 1.0;
+    return y;
+}
+
+double ora_chem_cell(double y, double n_in, double dt, double nHV, double tau,
+                     double b, int32_t n_sub, double *absorbed,
+                     double *transmitted) {
+    double A, T;
+    double yn = chem(y, n_in, dt, nHV, tau, b, n_sub, &A, &T);
+    if (absorbed) *absorbed = A;
+    if (transmitted) *transmitted = n_in * T;
+    return yn;
+}
+
+/* ---------------------------------------------------------------------- */
+ora_grid *ora_create(int64_t n, const double *pos, const int64_t *nbr_ptr,
+                     const int32_t *nbr_idx, const double *n_H,
+                     const double *volume, const double *dL, double kappa,
+                     const double *x_init, int32_t n_bins,
+                     const double *bin_dirs, int32_t max_per_bin,
+                     double cos_min, int32_t n_src, const int32_t *src_vertex,
+                     const double *src_rate, const double *src_dir,
+                     double sigma, double alpha_B, double dt,
+                     int32_t n_subcycles) {
+    g_err[0] = 0;
+    if (n <= 0 || n_bins <= 0 || max_per_bin <= 0 || n_subcycles <= 0 ||
+        !(dt > 0.0) || n_src < 0) {
+        snprintf(g_err, sizeof g_err, "bad sizes");
+        return NULL;
+    }
+    ora_grid *g = (ora_grid *)xcalloc(1, sizeof *g);
+    g->n = n;
+    g->n_edges = nbr_ptr[n];
+    g->K = n_bins;
+    g->mpb = max_per_bin;
+    g->cos_min = cos_min;
+    g->sigma = sigma;
+    g->alpha_B = alpha_B;
+    g->dt = dt;
+    g->n_sub = n_subcycles;
+    int64_t E = g->n_edges, K = n_bins;
+    g->ptr = (int64_t *)xcalloc(n + 1, sizeof(int64_t));
+    memcpy(g->ptr, nbr_ptr, (n + 1) * sizeof(int64_t));
+    g->nbr = (int32_t *)xcalloc(E, sizeof(int32_t));
+    memcpy(g->nbr, nbr_idx, E * sizeof(int32_t));
+    g->bins = (double *)xcalloc(K * 3, sizeof(double));
+    memcpy(g->bins, bin_dirs, K * 3 * sizeof(double));
+    g->nH = (double *)xcalloc(n, sizeof(double));
+    g->vol = (double *)xcalloc(n, sizeof(double));
+    memcpy(g->nH, n_H, n * sizeof(double));
+    memcpy(g->vol, volume, n * sizeof(double));
+    g->dL = (double *)xcalloc(n, sizeof(double));
+    g->tau = (double *)xcalloc(n, sizeof(double));
+    g->edir = (double *)xcalloc(E * 3, sizeof(double));
+    g->elen = (double *)xcalloc(E, sizeof(double));
+    g->sel = (int32_t *)xcalloc(n * K * max_per_bin, sizeof(int32_t));
+    g->m = (int32_t *)xcalloc(n * K, sizeof(int32_t));
+    g->ebin = (int32_t *)xcalloc(E, sizeof(int32_t));
+    g->y = (double *)xcalloc(n, sizeof(double));
+    g->O = (double *)xcalloc(n * K, sizeof(double));
+    g->I = (double *)xcalloc(n * K, sizeof(double));
+    g->nin = (double *)xcalloc(n, sizeof(double));
+    g->n_src = n_src;
+    g->src_v = (int32_t *)xcalloc(n_src, sizeof(int32_t));
+    g->src_rate = (double *)xcalloc(n_src, sizeof(double));
+    g->src_dir = (double *)xcalloc(n_src * 3, sizeof(double));
+    if (n_src) {
+        memcpy(g->src_v, src_vertex, n_src * sizeof(int32_t));
+        memcpy(g->src_rate, src_rate, n_src * sizeof(double));
+        if (src_dir) memcpy(g->src_dir, src_dir, n_src * 3 * sizeof(double));
+    }
+
+    /* Edge geometry: unit vector and length of every directed Delaunay edge
+     * i -> j (Sect. 2.2: photons travel along the edges). */
+    for (int64_t i = 0; i < n; i++) {
+        double sum = 0.0;
+        int64_t deg = g->ptr[i + 1] - g->ptr[i];
+        for (int64_t e = g->ptr[i]; e < g->ptr[i + 1]; e++) {
+            int32_t j = g->nbr[e];
+            double dx = pos[3 * j + 0] - pos[3 * i + 0];
+            double dy = pos[3 * j + 1] - pos[3 * i + 1];
+            double dz = pos[3 * j + 2] - pos[3 * i + 2];
+            double xx = dx * dx, yy = dy * dy, zz = dz * dz;
+            double len = sqrt((xx + yy) + zz);
+            g->edir[3 * e + 0] = dx / len;
+            g->edir[3 * e + 1] = dy / len;
+            g->edir[3 * e + 2] = dz / len;
+            g->elen[e] = len;
+            sum += len;
+        }
+        /* Path length through the cell (Sect. 4.4, Eq. optical_depth): a
+         * grid property fixed when the grid is made.  Reading: the mean
+         * length of the incident Delaunay edges times the global path-length
+         * correction factor kappa of Sect. 2.2.3, unless given. */
+        if (dL) g->dL[i] = dL[i];
+        else g->dL[i] = deg > 0 ? kappa * (sum / (double)deg) : 0.0;
+        /* Optical depth of the fully neutral cell, n_H sigma dL; the
+         * printed second form of Eq. optical_depth omits sigma. */
+        g->tau[i] = (g->nH[i] * sigma) * g->dL[i];
+        g->y[i] = x_init ? 1.0 - x_init[i] : 1.0;
+    }
+
+    /* Direction-bin -> neighbour selection of direction-conserving transport
+     * (Sect. 2.2.3): every bin goes to the mpb (= dimension d = 3) most
+     * straightforward neighbours w.r.t. the bin's own direction. */
+    for (int64_t i = 0; i < n; i++) {
+        for (int64_t k = 0; k < K; k++) {
+            int32_t slots[16];
+            int c = select_slots(g, i, &g->bins[3 * k], slots);
+            int32_t *dst = &g->sel[(i * K + k) * max_per_bin];
+            for (int r = 0; r < max_per_bin; r++)
+                dst[r] = r < c ? g->nbr[g->ptr[i] + slots[r]] : -1;
+            g->m[i * K + k] = c;
+        }
+    }
+
+    /* Bin of each directed edge: photons sent along an edge are filed in
+     * the solid angle whose direction is closest to the edge (Sect. 2.2.4);
+     * ties go to the lower bin. */
+    for (int64_t e = 0; e < E; e++) {
+        int32_t best = 0;
+        double cb = cosine(&g->edir[3 * e], &g->bins[0]);
+        for (int32_t k = 1; k < K; k++) {
+            double c = cosine(&g->edir[3 * e], &g->bins[3 * k]);
+            if (c > cb) { cb = c; best = k; }
+        }
+        g->ebin[e] = best;
+    }
+    return g;
+}
+
+/* ---------------------------------------------------------------------- */
+/* One radiative-transfer time step: photons move one Delaunay edge and
+ * interact once, at the vertex they arrive at (Sect. 4.6). */
+static void sweep(ora_grid *g) {
+    int64_t n = g->n, K = g->K;
+    int mpb = g->mpb;
+    memset(g->I, 0, (size_t)(n * K) * sizeof(double));
+
+    /* Transport: every bin of every vertex is handed to its selected
+     * neighbours, keeping its bin (direction-conserving transport).  O
+     * already holds the share of each selected neighbour. */
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t k = 0; k < K; k++) {
+            int32_t mm = g->m[i * K + k];
+            double v = g->O[i * K + k];
+            const int32_t *s = &g->sel[(i * K + k) * mpb];
+            for (int t = 0; t < mm; t++) g->I[(int64_t)s[t] * K + k] += v;
+        }
+
+    /* Sources: a source is a vertex that sends its photons N_dot dt to all
+     * its neighbours (Sects. 2.2, 4.3); each receiver files them in the bin
+     * of the edge they came along (Sect. 2.2.4).  The source itself does
+     * not absorb them.  A source with a direction emits a beam instead: the
+     * photons are split over the neighbours selected for that direction by
+     * the rule used for bins (used for a plane-parallel front). */
+    for (int32_t s = 0; s < g->n_src; s++) {
+        int64_t v = g->src_v[s];
+        double E = g->src_rate[s] * g->dt;
+        g->emitted += E;
+        const double *d = &g->src_dir[3 * s];
+        int64_t b = g->ptr[v], deg = g->ptr[v + 1] - g->ptr[v];
+        if (d[0] == 0.0 && d[1] == 0.0 && d[2] == 0.0) {
+            if (deg == 0) { g->escaped += E; continue; }
+            double share = E / (double)deg;
+            for (int64_t e = b; e < b + deg; e++)
+                g->I[(int64_t)g->nbr[e] * K + g->ebin[e]] += share;
+        } else {
+            int32_t slots[16];
+            int c = select_slots(g, v, d, slots);
+            if (c == 0) { g->escaped += E; continue; }
+            double share = E / (double)c;
+            for (int t = 0; t < c; t++) {
+                int64_t e = b + slots[t];
+                g->I[(int64_t)g->nbr[e] * K + g->ebin[e]] += share;
+            }
+        }
+    }
+
+    /* Interaction and chemistry at every vertex, then the outgoing photons
+     * of every bin are split equally over its selected neighbours; a bin
+     * with no neighbour in its forward cone leaves the domain. */
+    for (int64_t j = 0; j < n; j++) {
+        double nin = 0.0;
+        for (int64_t k = 0; k < K; k++) nin += g->I[j * K + k];
+        g->nin[j] = nin;
+        double A, T;
+        g->y[j] = chem(g->y[j], nin, g->dt, g->nH[j] * g->vol[j], g->tau[j],
+                       g->alpha_B * g->nH[j], g->n_sub, &A, &T);
+        g->absorbed += A;
+        for (int64_t k = 0; k < K; k++) {
+            double out = g->I[j * K + k] * T;
+            int32_t mm = g->m[j * K + k];
+            if (mm > 0) {
+                g->O[j * K + k] = out / (double)mm;
+            } else {
+                g->escaped += out;
+                g->O[j * K + k] = 0.0;
+            }
+        }
+    }
+
+    /* Photons still travelling. */
+    double f = 0.0;
+    for (int64_t j = 0; j < n; j++)
+        for (int64_t k = 0; k < K; k++)
+            f += g->O[j * K + k] * (double)g->m[j * K + k];
+    g->in_flight = f;
+    g->sweeps += 1.0;
+}
+
+int ora_run(ora_grid *g, int32_t n_sweeps, double *history) {
+    for (int32_t s = 0; s < n_sweeps; s++) {
+        sweep(g);
+        if (history) {
+            history[4 * s + 0] = g->emitted;
+            history[4 * s + 1] = g->absorbed;
+            history[4 * s + 2] = g->escaped;
+            history[4 * s + 3] = g->in_flight;
+        }
+    }
+    return 0;
+}
+
+void ora_get_state(const ora_grid *g, double *y, double *x, double *photons,
+                   double *nin, double *tallies) {
+    int64_t n = g->n, K = g->K;
+    if (y) memcpy(y, g->y, n * sizeof(double));
+    if (x) for (int64_t i = 0; i < n; i++) x[i] = 1.0 - g->y[i];
+    if (photons) memcpy(photons, g->O, (size_t)(n * K) * sizeof(double));
+    if (nin) memcpy(nin, g->nin, n * sizeof(double));
+    if (tallies) {
+        tallies[0] = g->sweeps;
+        tallies[1] = g->emitted;
+        tallies[2] = g->absorbed;
+        tallies[3] = g->escaped;
+        tallies[4] = g->in_flight;
+    }
+}
+
+void ora_set_state(ora_grid *g, const double *y, const double *photons,
+                   const double *tallies) {
+    int64_t n = g->n, K = g->K;
+    if (y) memcpy(g->y, y, n * sizeof(double));
+    if (photons) memcpy(g->O, photons, (size_t)(n * K) * sizeof(double));
+    if (tallies) {
+        g->sweeps = tallies[0];
+        g->emitted = tallies[1];
+        g->absorbed = tallies[2];
+        g->escaped = tallies[3];
+        g->in_flight = tallies[4];
+    }
+}
+
+void ora_get_tables(const ora_grid *g, int32_t *sel_nbr, int32_t *sel_m,
+                    int32_t *edge_bin, double *dL, double *tau) {
+    int64_t n = g->n, K = g->K;
+    if (sel_nbr) memcpy(sel_nbr, g->sel, (size_t)(n * K * g->mpb) * sizeof(int32_t));
+    if (sel_m) memcpy(sel_m, g->m, (size_t)(n * K) * sizeof(int32_t));
+    if (edge_bin) memcpy(edge_bin, g->ebin, (size_t)g->n_edges * sizeof(int32_t));
+    if (dL) memcpy(dL, g->dL, n * sizeof(double));
+    if (tau) memcpy(tau, g->tau, n * sizeof(double));
+}
+
+void ora_free(ora_grid *g) {
+    if (!g) return;
+    free(g->ptr); free(g->nbr); free(g->edir); free(g->elen); free(g->bins);
+    free(g->nH); free(g->vol); free(g->dL); free(g->tau); free(g->sel);
+    free(g->m); free(g->ebin); free(g->src_v); free(g->src_rate);
+    free(g->src_dir); free(g->y); free(g->O); free(g->I); free(g->nin);
+    free(g);
+}

@@ -1,0 +1,83 @@
+/*
+ * sx_oracle.h -- CPU reference ("oracle") for SimpleX2 direction-conserving
+ * photon transport with on-the-spot hydrogen photo-ionisation chemistry.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, sequential FP64
+ * implementation written to be checked against the paper by eye.  It is
+ * called by the test-suite, by the smoke check and by the CPU-baseline leg of
+ * the benchmark; the product library never links or calls it, and it shares
+ * no code, header or table with the GPU library.
+ *
+ * Paper: Paardekooper, Kruip & Icke (2010), "SimpleX2: radiative transfer on
+ * an unstructured, dynamic grid", A&A (arXiv:0912.4273).
+ *
+ * Conventions: vertices, neighbour rows and bins are used in the order the
+ * caller gives them.  Units are CGS.  All arithmetic is IEEE double.
+ */
+#ifndef SX_ORACLE_H
+#define SX_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ora_grid ora_grid;
+
+/* Build the oracle state for one grid.  Arrays are copied.  src_dir may be
+ * NULL (every source isotropic); a row of zeros also means isotropic.
+ * dL may be NULL (then dL_i = kappa * mean incident edge length).
+ * x_init may be NULL (then x = 0, fully neutral).  Returns NULL on invalid
+ * input (message in ora_last_error()). */
+ora_grid *ora_create(int64_t n, const double *pos, const int64_t *nbr_ptr,
+                     const int32_t *nbr_idx, const double *n_H,
+                     const double *volume, const double *dL, double kappa,
+                     const double *x_init, int32_t n_bins,
+                     const double *bin_dirs, int32_t max_per_bin,
+                     double cos_min, int32_t n_src, const int32_t *src_vertex,
+                     const double *src_rate, const double *src_dir,
+                     double sigma, double alpha_B, double dt,
+                     int32_t n_subcycles);
+
+/* Run n_sweeps sweeps.  history (nullable, [n_sweeps*4]) receives the
+ * cumulative tallies emitted, absorbed, escaped, in_flight after each sweep. */
+int ora_run(ora_grid *g, int32_t n_sweeps, double *history);
+
+/* Copy out the state.  Any pointer may be NULL.
+ *   y, x        [N]   neutral and ionised fraction
+ *   photons     [N*K] outgoing photons per selected neighbour, O[j][k]
+ *   nin         [N]   photons that entered each vertex in the last sweep
+ *   tallies     [5]   sweeps, emitted, absorbed, escaped, in_flight */
+void ora_get_state(const ora_grid *g, double *y, double *x, double *photons,
+                   double *nin, double *tallies);
+
+/* Replace y (neutral fraction) and O (photons, [N*K]) -- checkpoint restore.
+ * Either may be NULL. tallies (nullable, [5]) restores the counters. */
+void ora_set_state(ora_grid *g, const double *y, const double *photons,
+                   const double *tallies);
+
+/* Selection tables.  sel_nbr [N*K*max_per_bin] neighbour vertex ids (best
+ * first, -1 padding), sel_m [N*K], edge_bin [E] (bin of each directed edge
+ * in the caller's CSR order), dL [N], tau [N] (n_H sigma dL).  Nullable. */
+void ora_get_tables(const ora_grid *g, int32_t *sel_nbr, int32_t *sel_m,
+                    int32_t *edge_bin, double *dL, double *tau);
+
+void ora_free(ora_grid *g);
+
+/* One vertex, one radiative-transfer step of length dt: n_sub backward-Euler
+ * subcycles of the rate equation with a constant incoming photon flux
+ * n_in/dt.  nHV = n_H * V (atoms in the cell), tau = n_H sigma dL (optical
+ * depth of the fully neutral cell), b = alpha_B n_H.  Returns the new neutral
+ * fraction; *absorbed and *transmitted receive the photons absorbed and
+ * passed on. */
+double ora_chem_cell(double y, double n_in, double dt, double nHV, double tau,
+                     double b, int32_t n_sub, double *absorbed,
+                     double *transmitted);
+
+const char *ora_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,272 @@
+"""Pins of the CPU oracle: checks against what the paper and the mathematics
+fix, independent of the oracle's own code.  Each pin takes an optional
+oracle library path so the same checks can be run against a copy of the
+oracle with a planted mistake (tests/test_oracle_mutants.py)."""
+import math
+
+import numpy as np
+
+import analytic as A
+from paper_0912_4273_amd import gridgen as G
+from oracle import Oracle, chem_cell
+
+
+# ------------------------------------------------------------ chemistry ---
+
+def pin_recombination_closed_form(lib=None):
+    """No photons: the rate equation (Eq. rate_eq, n_e = n_HII) reduces to
+    dx/dt = -b x^2 with closed form x0/(1 + b x0 t).  Backward Euler must
+    converge to it at first order in the substep."""
+    b = G.ALPHA_B * 1e-3
+    t = 1.0 / b
+    for x0 in (1.0, 0.3):
+        exact = A.recombination_only(x0, b, t)
+        errs = []
+        for nsub in (10, 100, 1000):
+            y, absorbed, _ = chem_cell(1.0 - x0, 0.0, t, 1e60, 5.0, b, nsub, lib)
+            assert absorbed == 0.0
+            errs.append(abs((1.0 - y) - exact))
+        assert errs[2] < 1e-3 * abs(x0 - exact), errs
+        assert 7.0 < errs[0] / errs[1] < 13.0 and 7.0 < errs[1] / errs[2] < 13.0, errs
+
+
+def pin_equilibrium_fixed_point(lib=None):
+    """Constant incoming flux: the cell settles where photo-ionisations
+    a (1 - exp(-y tau)) balance recombinations b (1 - y)^2, and then absorbs
+    exactly the recombinations of a step."""
+    nHV = 1e60
+    dt = 3e14
+    b = G.ALPHA_B * 1e-3
+    for a_over_b, tau in ((40.0, 3.0), (2.0, 20.0), (1e4, 0.5)):
+        a = a_over_b * b
+        nin = a * dt * nHV
+        ystar = A.equilibrium_neutral_fraction(a, b, tau)
+        y = 1.0
+        for _ in range(400):
+            y, absorbed, trans = chem_cell(y, nin, dt, nHV, tau, b, 10, lib)
+        assert abs(y - ystar) <= 1e-10 * ystar, (y, ystar)
+        rec = b * (1.0 - ystar) ** 2 * nHV * dt
+        assert abs(absorbed - rec) <= 1e-8 * rec, (absorbed, rec)
+
+
+def pin_ode_convergence(lib=None):
+    """Backward-Euler subcycles converge to the rate equation with constant
+    flux (Eqs. rate_eq_subcycle, phot_ion_rate_subcycle) integrated by an
+    independent stiff solver."""
+    b = G.ALPHA_B * 1e-3
+    nHV = 1e60
+    for (y0, a, tau, dt) in ((0.9, 3e-15, 2.0, 4e14), (1.0, 1e-13, 15.0, 1e12),
+                             (0.2, 5e-16, 0.7, 2e15)):
+        ref = A.rate_ode_solution(y0, a, b, tau, dt)
+        errs = []
+        for nsub in (10, 100, 1000):
+            y, _, _ = chem_cell(y0, a * dt * nHV, dt, nHV, tau, b, nsub, lib)
+            errs.append(abs(y - ref))
+        assert errs[2] <= 2e-3 * abs(ref - y0) + 1e-12, (errs, ref, y0)
+        assert errs[2] <= errs[0] / 20.0 + 1e-14, errs
+
+
+def pin_photon_accounting(lib=None):
+    """Absorbed + passed-on photons = incoming photons; with no
+    recombination every absorbed photon ionises one atom."""
+    rng = np.random.default_rng(0)
+    nHV = 1e60
+    for _ in range(30):
+        y0 = rng.uniform(1e-4, 1.0)
+        tau = 10 ** rng.uniform(-2, 1.5)
+        dt = 10 ** rng.uniform(12, 15)
+        nin = 10 ** rng.uniform(-3, 1) * nHV
+        b = G.ALPHA_B * 1e-3 * rng.uniform(0.0, 1.0)
+        y, absorbed, trans = chem_cell(y0, nin, dt, nHV, tau, b, 10, lib)
+        assert 0.0 <= y <= 1.0
+        assert abs(absorbed + trans - nin) <= 1e-12 * nin
+        assert absorbed >= nHV * (y0 - y) * (1 - 1e-9)
+        y, absorbed, _ = chem_cell(y0, nin, dt, nHV, tau, 0.0, 10, lib)
+        assert abs(absorbed - nHV * (y0 - y)) <= 1e-9 * absorbed + 1e-300
+    # no gas opacity -> nothing absorbed, all passed on
+    y, absorbed, trans = chem_cell(1.0, 1e59, 1e13, nHV, 0.0, 2.6e-16, 10, lib)
+    assert absorbed == 0.0 and trans == 1e59 and y == 1.0
+
+
+# ------------------------------------------------------------ selection ---
+
+def _brute_tables(w):
+    """Full sort of every neighbour per (vertex, bin); argmax per edge."""
+    n, k = w.n, w.k
+    ptr, idx, pos, u = w.nbr_ptr, w.nbr_idx, w.pos, w.bin_dirs
+    sel = -np.ones((n, k, w.max_per_bin), np.int32)
+    m = np.zeros((n, k), np.int32)
+    eb = np.zeros(w.n_edges, np.int32)
+    for i in range(n):
+        nb = idx[ptr[i]:ptr[i + 1]]
+        if nb.size == 0:
+            continue
+        d = pos[nb] - pos[i]
+        ln = np.sqrt((d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2])
+        e = d / ln[:, None]
+        c = (e[:, 0:1] * u[None, :, 0] + e[:, 1:2] * u[None, :, 1]) + e[:, 2:3] * u[None, :, 2]
+        eb[ptr[i]:ptr[i + 1]] = np.argmax(c, axis=1)
+        for kk in range(k):
+            cand = sorted(((-c[s, kk], int(nb[s])) for s in range(nb.size) if c[s, kk] > w.cos_min))
+            top = [v for _, v in cand[: w.max_per_bin]]
+            m[i, kk] = len(top)
+            sel[i, kk, : len(top)] = top
+    return sel, m, eb
+
+
+def pin_selection_brute_force(lib=None):
+    """Direction-conserving routing (Sect. 2.2.3): each bin goes to the
+    (up to) three neighbours most aligned with it, cosine > 0, ties to the
+    lower id; each edge is filed in its closest bin (Sect. 2.2.4)."""
+    cases = [G.small_random(150, seed=1, n_bins=21),
+             G.small_random(120, seed=2, n_bins=84),
+             G.with_(G.small_random(100, seed=3, n_bins=42), max_per_bin=2),
+             G.with_(G.stromgren_test(200, seed=4, n_bins=42), max_per_bin=1)]
+    for w in cases:
+        t = Oracle(w, lib).tables()
+        sel, m, eb = _brute_tables(w)
+        assert np.array_equal(t["sel_m"], m), w.name
+        assert np.array_equal(t["sel_nbr"], sel), w.name
+        assert np.array_equal(t["edge_bin"], eb), w.name
+
+
+def pin_axis_star(lib=None):
+    """Centre with six axis neighbours, six axis bins: each bin of the
+    centre goes to exactly the neighbour along it; an outer vertex sends
+    only the bin pointing back at the centre; perpendicular neighbours
+    (cosine 0) are not eligible."""
+    w = G.star_graph()
+    t = Oracle(w, lib).tables()
+    opp = [1, 0, 3, 2, 5, 4]
+    for kk in range(6):
+        assert t["sel_m"][0, kk] == 1 and t["sel_nbr"][0, kk, 0] == kk + 1
+    for v in range(1, 7):
+        a = v - 1
+        for kk in range(6):
+            if kk == opp[a]:
+                assert t["sel_m"][v, kk] == 1 and t["sel_nbr"][v, kk, 0] == 0
+            else:
+                assert t["sel_m"][v, kk] == 0
+    # centre row lists vertices 1..6 along the six axes
+    assert list(t["edge_bin"][:6]) == [0, 1, 2, 3, 4, 5]
+    assert [t["edge_bin"][6 + a] for a in range(6)] == opp
+
+
+def pin_ties(lib=None):
+    """Exact ties: an edge halfway between two bins is filed in the lower
+    bin; two equally aligned neighbours are ranked by id."""
+    pos = np.array([[0, 0, 0], [1, 1, 0], [1, -1, 0]], float)
+    ptr = np.array([0, 2, 3, 4], np.int64)
+    idx = np.array([1, 2, 0, 0], np.int32)
+    w = G.Workload(name="ties", pos=pos, nbr_ptr=ptr, nbr_idx=idx,
+                   n_H=np.full(3, 1e-3), volume=np.ones(3),
+                   bin_dirs=G.axis_bins(), src_vertex=np.array([0], np.int32),
+                   src_rate=np.array([1.0]), dt=1.0, n_sweeps=1, max_per_bin=1)
+    t = Oracle(w, lib).tables()
+    # 0->1 is (+1,+1,0): tie of +x (bin 0) and +y (bin 2) -> 0
+    # 0->2 is (+1,-1,0): tie of +x (0) and -y (3) -> 0
+    # 1->0 is (-1,-1,0): tie of -x (1) and -y (3) -> 1
+    # 2->0 is (-1,+1,0): tie of -x (1) and +y (2) -> 1
+    assert list(t["edge_bin"]) == [0, 0, 1, 1]
+    # bin +x at vertex 0: neighbours 1 and 2 equally aligned -> the lower id
+    assert t["sel_m"][0, 0] == 1 and t["sel_nbr"][0, 0, 0] == 1
+
+
+# -------------------------------------------------------------- transport ---
+
+def pin_chain_hops(lib=None):
+    """A straight chain along +x with a weak source at one end: photons
+    advance exactly one edge per step in the +x bin and each vertex passes on
+    exp(-n_H sigma dL) of them (Eqs. photon_out, intensity_out); the far end
+    lets them escape."""
+    n = 10
+    sp = 3e21
+    rng = np.random.default_rng(1)
+    nH = 10 ** rng.uniform(-4, -2.5, n)
+    w = G.chain_graph(n, sp, 1e-3, sp ** 3)
+    w = G.with_(w, n_H=nH, src_rate=np.array([1e30]), dt=1e10)
+    o = Oracle(w, lib)
+    E = 1e30 * 1e10
+    tau = nH * G.SIGMA_H * sp
+    for s in range(1, n + 3):
+        o.run(1)
+        st = o.state()
+        nin = st["nin"]
+        assert nin[0] == 0.0
+        for j in range(1, n):
+            want = E * math.exp(-float(np.sum(tau[1:j]))) if j <= s else 0.0
+            assert abs(nin[j] - want) <= 1e-9 * want + 1e-300, (s, j, nin[j], want)
+    # steady state: per step, what leaves the last vertex escapes
+    t0 = o.state()["tallies"]["escaped"]
+    o.run(1)
+    t1 = o.state()["tallies"]["escaped"]
+    want = E * math.exp(-float(np.sum(tau[1:])))
+    assert abs((t1 - t0) - want) <= 1e-6 * want
+
+
+def pin_conservation(lib=None):
+    """Photon conservation at every step (Sect. 2.2.2, 4.5): emitted =
+    absorbed + escaped + still travelling, with isotropic and beam sources."""
+    w = G.small_random(600, seed=8, n_bins=42, box=3e21, n_H=1e-3, rate=1e48,
+                       n_src=3, dt=3e13)
+    sd = np.zeros((3, 3))
+    sd[1] = [0.0, 0.0, 1.0]
+    w = G.with_(w, src_dir=sd)
+    h = Oracle(w, lib).run(40, history=True)
+    res = h[:, 0] - (h[:, 1] + h[:, 2] + h[:, 3])
+    assert np.all(np.abs(res) <= 1e-12 * h[:, 0]), res / h[:, 0]
+    assert np.all(np.diff(h[:, 0]) > 0) and h[-1, 1] > 0 and h[-1, 3] > 0
+
+
+def pin_one_over_r2(lib=None):
+    """Optically thin medium: photons keep their direction (Sect. 2.2.3),
+    so the photons reaching a vertex fall off as 1/r^2 from the source
+    (shell average, steady state inside the light front)."""
+    w = G.stromgren_test(32768, seed=5, n_bins=42, n_H=1e-9, n_sweeps=30,
+                         t_end_myr=0.3)
+    o = Oracle(w, lib)
+    o.run(30)
+    nin = o.state()["nin"]
+    c = w.pos[w.src_vertex[0]]
+    r = np.linalg.norm(w.pos - c, axis=1)
+    sp = (w.box ** 3 / w.n) ** (1.0 / 3.0)
+    rs, vals = [], []
+    for a in np.arange(3.0, w.box / 2 / sp - 3.0, 1.0):
+        msk = (r >= a * sp) & (r < (a + 1) * sp)
+        rs.append((a + 0.5) * sp)
+        vals.append(nin[msk].mean())
+    rs, vals = np.array(rs), np.array(vals)
+    slope = np.polyfit(np.log(rs), np.log(vals), 1)[0]
+    assert abs(slope + 2.0) <= 0.1, slope
+    flat = vals * rs ** 2
+    assert np.all(np.abs(flat / flat.mean() - 1.0) <= 0.2), flat / flat.mean()
+
+
+def pin_front_law(lib=None, w=None, tol=0.08, t_min_myr=60.0):
+    """Isothermal H II region (Sect. 5.1): the ionised-volume radius follows
+    r_S (1 - exp(-t/t_rec))^(1/3) (Eq. IFront_pos); photons are conserved at
+    every step."""
+    w = w or G.config1()
+    nh, rate = w.meta["n_H"], w.meta["rate"]
+    r_s = A.stromgren_radius(rate, nh, w.alpha_B)
+    t_rec = A.recombination_time(nh, w.alpha_B)
+    o = Oracle(w, lib)
+    chunk = 10
+    worst = 0.0
+    for s in range(w.n_sweeps // chunk):
+        h = o.run(chunk, history=True)
+        res = h[:, 0] - (h[:, 1] + h[:, 2] + h[:, 3])
+        assert np.all(np.abs(res) <= 1e-12 * h[:, 0])
+        t = (s + 1) * chunk * w.dt
+        if t < t_min_myr * G.MYR_S:
+            continue
+        rv = A.ionised_volume_radius(w.volume, o.state()["x"])
+        worst = max(worst, abs(rv / A.front_radius(t, r_s, t_rec) - 1.0))
+    assert worst <= tol, worst
+    return worst
+
+
+FAST_PINS = [pin_recombination_closed_form, pin_equilibrium_fixed_point,
+             pin_ode_convergence, pin_photon_accounting,
+             pin_selection_brute_force, pin_axis_star, pin_ties,
+             pin_chain_hops, pin_conservation]

@@ -1,0 +1,56 @@
+"""Plant plausible mistakes in a copy of the oracle and check that the pins
+catch every one of them (CPU only).  Each mutant is the oracle source with
+one textual change; at least one fast pin must fail on it."""
+import os
+import shutil
+
+import pytest
+
+import oracle_pins as P
+from oracle.oracle import build_oracle
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                   "oracle", "sx_oracle.c")
+
+MUTANTS = {
+    "recombination_sign": ("+ hb * (x * x);", "- hb * (x * x);"),
+    "ionisation_uses_transmission": ("- ha * ion + hb", "- ha * (1.0 - ion) + hb"),
+    "rate_missing_dt": ("double a = n_in / (dt * nHV);", "double a = n_in / nHV;"),
+    "substep_length": ("double h = dt / (double)n_sub;", "double h = dt;"),
+    "transmission_ignores_ionisation": ("tr_sum += exp(-y * tau);", "tr_sum += exp(-tau);"),
+    "perpendicular_admitted": ("if (!(c > g->cos_min)) continue;", "if (!(c >= g->cos_min)) continue;"),
+    "tie_to_higher_id": ("(c == cb && g->nbr[b + s] < g->nbr[b + best])",
+                         "(c == cb && g->nbr[b + s] > g->nbr[b + best])"),
+    "edge_bin_tie_to_higher": ("if (c > cb) { cb = c; best = k; }", "if (c >= cb) { cb = c; best = k; }"),
+    "cosine_drops_z": ("return (a + b) + c;", "return (a + b);"),
+    "only_two_per_bin": ("for (int r = 0; r < g->mpb; r++) {", "for (int r = 0; r < g->mpb - 1; r++) {"),
+    "transport_wrong_bin": ("g->I[(int64_t)s[t] * K + k] += v;", "g->I[(int64_t)s[t] * K + (k + 1) % K] += v;"),
+    "transport_transposed_bins": ("double v = g->O[i * K + k];", "double v = g->O[i * K + (K - 1 - k)];"),
+    "no_split_over_neighbours": ("g->O[j * K + k] = out / (double)mm;", "g->O[j * K + k] = out;"),
+    "source_not_split": ("double share = E / (double)deg;", "double share = E;"),
+    "path_length_sum_not_mean": ("kappa * (sum / (double)deg)", "kappa * sum"),
+    "optical_depth_without_sigma": ("g->tau[i] = (g->nH[i] * sigma) * g->dL[i];",
+                                    "g->tau[i] = g->nH[i] * g->dL[i];"),
+    "escape_lost": ("g->escaped += out;", "g->escaped += 0.0 * out;"),
+    "nin_skips_first_bin": ("for (int64_t k = 0; k < K; k++) nin += g->I[j * K + k];",
+                            "for (int64_t k = 1; k < K; k++) nin += g->I[j * K + k];"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    txt = open(SRC).read()
+    assert txt.count(old) == 1, f"mutation site for {name} not unique/found"
+    src = tmp_path / "sx_oracle.c"
+    src.write_text(txt.replace(old, new))
+    shutil.copy(os.path.join(os.path.dirname(SRC), "sx_oracle.h"), tmp_path / "sx_oracle.h")
+    lib = build_oracle(force=True, src=str(src), out=str(tmp_path / f"lib_{name}.so"))
+    caught = []
+    for pin in P.FAST_PINS:
+        try:
+            pin(lib)
+        except Exception as e:  # noqa: BLE001 - any failure counts as caught
+            caught.append((pin.__name__, type(e).__name__))
+            break
+    assert caught, f"no pin caught mutant {name}"
