@@ -1,0 +1,221 @@
+/*
+ * sx.h -- C ABI of libsx: SimpleX2 direction-conserving photon transport
+ * fused with hydrogen photo-ionisation chemistry, on an AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Method: Paardekooper, Kruip & Icke (2010), "SimpleX2: radiative transfer on
+ * an unstructured, dynamic grid", A&A, arXiv:0912.4273.
+ *   - photons move along Delaunay edges, one edge per step, and interact at
+ *     the vertex they reach (Sects. 2.2, 4.6);
+ *   - direction-conserving transport (Sect. 2.2.3): each vertex keeps its
+ *     photons in K global direction bins and hands every bin to the (up to)
+ *     three neighbours most aligned with that bin's direction, never
+ *     backwards (cosine > 0);
+ *   - sources send their photons to all neighbours (Sects. 2.2, 4.3), filed
+ *     in the bin closest to each edge (Sect. 2.2.4);
+ *   - interaction exp(-n_HI sigma dL) (Eqs. optical_depth, intensity_absorbed,
+ *     intensity_out) with the rate equation subcycled at constant incoming
+ *     flux (Eqs. rate_eq, rate_eq_subcycle, phot_ion_rate_subcycle).
+ *
+ * Conventions
+ *   - CGS units.  Vertex ids, neighbour rows and bins are in the caller's
+ *     order on every call; the library may reorder internally but never
+ *     exposes that order.
+ *   - Every pointer argument is a HOST pointer unless stated otherwise.
+ *     The library copies what it needs during the call and never keeps a
+ *     caller pointer.
+ *   - Return value: SX_OK (0) or a negative SX_E* code.  sx_last_error()
+ *     gives a message for the most recent failure on that context.
+ *   - One context per host thread.  Work is enqueued on the context's HIP
+ *     stream; sx_step is asynchronous, every other call is synchronous.
+ */
+#ifndef SX_H
+#define SX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SX_ABI_VERSION 1
+
+/* ---- return codes ---------------------------------------------------- */
+#define SX_OK 0
+#define SX_EINVAL (-1)     /* malformed argument or grid                  */
+#define SX_ENOMEM (-2)     /* device memory budget or allocation exceeded */
+#define SX_EDEVICE (-3)    /* HIP runtime / kernel failure; ctx poisoned  */
+#define SX_ENOTFOUND (-4)  /* unknown grid id                             */
+#define SX_ENOTSUP (-5)    /* valid request outside the supported limits  */
+
+/* ---- precision ------------------------------------------------------- */
+#define SX_FP64 0            /* photons and chemistry in double            */
+#define SX_FP32_TRANSPORT 1  /* photons in float (scaled units, see below),
+                                neutral fraction, chemistry and tallies in
+                                double                                     */
+
+/* ---- limits ---------------------------------------------------------- */
+#define SX_MAX_BINS_FP32 96   /* K <= 96 in SX_FP32_TRANSPORT              */
+#define SX_MAX_BINS_FP64 96   /* K <= 96  in SX_FP64                       */
+#define SX_MAX_DEGREE 127     /* Delaunay degree of any vertex             */
+#define SX_MAX_PER_BIN 3      /* neighbours per bin (the paper's p = d = 3) */
+
+typedef struct sx_ctx sx_ctx;
+typedef int64_t sx_grid_id;
+
+/* Device-memory hooks: alloc(bytes, user) returns a device pointer or NULL;
+ * free(ptr, user).  Both NULL => hipMalloc / hipFree. */
+typedef void *(*sx_alloc_fn)(size_t bytes, void *user);
+typedef void (*sx_free_fn)(void *ptr, void *user);
+
+typedef struct sx_ctx_opts {
+    int32_t device;        /* HIP device ordinal                             */
+    int32_t reserved0;
+    uint64_t hbm_budget;   /* bytes the context may hold; 0 = 90% of free   */
+    void *stream;          /* hipStream_t to enqueue on; NULL = own stream  */
+    sx_alloc_fn alloc;     /* optional device allocator                      */
+    sx_free_fn free;
+    void *alloc_user;
+} sx_ctx_opts;
+
+/* One grid and one solve's physics.  All arrays are host pointers in the
+ * caller's vertex order and are only read during sx_grid_upload. */
+typedef struct sx_grid_desc {
+    int64_t n_vertices;          /* N >= 1                                   */
+    const double *pos;           /* [3N] vertex positions (cm)               */
+    const int64_t *nbr_ptr;      /* [N+1] CSR row offsets, nbr_ptr[0] = 0    */
+    const int32_t *nbr_idx;      /* [E] Delaunay neighbours: symmetric, no
+                                    self-loops, no duplicates, deg <= 127    */
+    const double *n_H;           /* [N] hydrogen number density (cm^-3)      */
+    const double *volume;        /* [N] cell volume (cm^3), > 0              */
+    const double *dL;            /* [N] path length through each cell, or
+                                    NULL: kappa * mean incident edge length  */
+    double kappa;                /* global path-length correction, Sect 2.2.3*/
+    const double *x_init;        /* [N] initial ionised fraction or NULL (0) */
+    int32_t n_bins;              /* K                                        */
+    int32_t max_per_bin;         /* neighbours per bin, 1..3 (paper: 3)      */
+    const double *bin_dirs;      /* [3K] unit vectors (|u| = 1 within 1e-12) */
+    double cos_min;              /* eligibility: cosine > cos_min (paper: 0) */
+    int32_t n_src;               /* number of sources                        */
+    int32_t n_subcycles;         /* chemistry substeps per step, >= 1        */
+    const int32_t *src_vertex;   /* [n_src] source vertex ids                */
+    const double *src_rate;      /* [n_src] ionising photons per second      */
+    const double *src_dir;       /* [3 n_src] or NULL.  A zero row means an
+                                    isotropic source (all neighbours); a unit
+                                    row makes a beam along that direction    */
+    double sigma;                /* photo-ionisation cross-section (cm^2)    */
+    double alpha_B;              /* case-B recombination coefficient         */
+    double dt;                   /* radiative-transfer time step (s)         */
+    int32_t precision;           /* SX_FP64 or SX_FP32_TRANSPORT             */
+    int32_t reserved1;
+} sx_grid_desc;
+
+/* Cumulative photon accounting of one grid (photons, double). */
+typedef struct sx_tally {
+    double sweeps;       /* steps done                                      */
+    double emitted;      /* photons sent out by the sources                  */
+    double absorbed;     /* photons absorbed (= photo-ionisations)           */
+    double escaped;      /* photons that left the domain                     */
+    double in_flight;    /* photons held in the outgoing field now           */
+} sx_tally;
+
+/* State read-back; every pointer is nullable (host memory, caller-owned).
+ *   x, y      [N]    ionised and neutral fraction
+ *   photons   [N*K]  double: O[i][k], the photons each selected neighbour of
+ *                    vertex i receives in bin k at the next step (row-major,
+ *                    caller's vertex order).  Bin k of vertex i holds
+ *                    m(i,k) * O[i][k] photons in total.
+ *   nin       [N]    photons that reached each vertex in the last step
+ *   tally     accounting above                                            */
+typedef struct sx_state_out {
+    double *x;
+    double *y;
+    double *photons;
+    double *nin;
+    sx_tally *tally;
+} sx_state_out;
+
+/* Checkpoint restore: nullable host arrays in the layout of sx_state_out. */
+typedef struct sx_state_in {
+    const double *y;
+    const double *photons;
+    const sx_tally *tally;
+} sx_state_in;
+
+/* Create a context on opts->device (NULL opts = device 0, defaults).
+ * Errors: SX_EINVAL (bad opts), SX_EDEVICE (no such device / HIP failure).*/
+int sx_init(sx_ctx **out, const sx_ctx_opts *opts);
+
+/* Release every grid and the context.  NULL is accepted. */
+int sx_finalize(sx_ctx *ctx);
+
+/* Device bytes a grid with this description would hold (no allocation).
+ * Used for admission control.  Errors: SX_EINVAL. */
+int sx_grid_bytes(const sx_grid_desc *d, uint64_t *bytes);
+
+/* Validate, reorder for locality, copy to the device, build the bin
+ * selection tables and the gather lists, and initialise the state.
+ * Errors: SX_EINVAL (asymmetric or malformed graph, non-finite values,
+ * non-unit bins, bad source ids), SX_ENOTSUP (K or degree over the
+ * limits), SX_ENOMEM (budget; nothing stays allocated), SX_EDEVICE. */
+int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out);
+
+/* Recompute the bin -> neighbour tables and gather lists on the device
+ * (direction-conserving transport recomputes them whenever the bins
+ * change, Sect. 2.2.3) and reset the state to the upload's initial one:
+ * y = 1 - x_init, no photons in flight, tallies zero.  Asynchronous. */
+int sx_grid_reset(sx_ctx *ctx, sx_grid_id id);
+
+/* Restore y, photons and tallies (checkpoint).  Synchronous. */
+int sx_grid_restore(sx_ctx *ctx, sx_grid_id id, const sx_state_in *in);
+
+/* Release one grid. */
+int sx_grid_free(sx_ctx *ctx, sx_grid_id id);
+
+/* Enqueue n_sweeps steps on each of the n grids (one batched launch per
+ * step when n > 1; grids must share the precision and the bin count's
+ * kernel class).  Asynchronous on the context stream.
+ * Errors: SX_ENOTFOUND, SX_EINVAL, SX_EDEVICE. */
+int sx_step(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, int32_t n_sweeps);
+
+/* Run grid ids[i] for n_sweeps[i] steps (grids finish independently and
+ * drop out of the batch), then wait for the device. */
+int sx_solve(sx_ctx *ctx, const sx_grid_id *ids, int32_t n,
+             const int32_t *n_sweeps);
+
+/* Wait for all work enqueued on the context. */
+int sx_sync(sx_ctx *ctx);
+
+/* Copy the state of one grid to host memory (synchronous). */
+int sx_read_state(sx_ctx *ctx, sx_grid_id id, const sx_state_out *out);
+
+/* Selection tables in the caller's order (synchronous), all nullable:
+ *   sel_nbr  [N*K*3] neighbour ids chosen for each (vertex, bin), best
+ *            first, -1 padding
+ *   sel_m    [N*K]   how many were chosen
+ *   edge_bin [E]     bin of each directed edge, caller's CSR order
+ *   dL, tau  [N]     path length and neutral optical depth n_H sigma dL */
+int sx_read_tables(sx_ctx *ctx, sx_grid_id id, int32_t *sel_nbr,
+                   int32_t *sel_m, int32_t *edge_bin, double *dL,
+                   double *tau);
+
+/* Grid facts: N, K, edges, precision, the photon unit S (photons per stored
+ * unit, a power of two), device bytes held. Any pointer nullable. */
+int sx_grid_info(sx_ctx *ctx, sx_grid_id id, int64_t *n, int32_t *k,
+                 int64_t *n_edges, int32_t *precision, double *photon_unit,
+                 uint64_t *bytes);
+
+/* Device bytes held by the context and its budget. */
+int sx_mem_info(sx_ctx *ctx, uint64_t *used, uint64_t *budget);
+
+/* The hipStream_t the context enqueues on. */
+void *sx_stream(sx_ctx *ctx);
+
+const char *sx_strerror(int code);
+const char *sx_last_error(const sx_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SX_H */

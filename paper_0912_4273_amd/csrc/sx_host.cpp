@@ -1,0 +1,1162 @@
+// sx_host.cpp -- host side of libsx: the C ABI declared in include/sx.h.
+//
+// Upload path (per grid, outside the per-step hot loop):
+//   validate -> Hilbert-curve reorder -> CSR rows sorted by original id ->
+//   unit edge vectors, path lengths, chemistry coefficients (fp64, no FMA
+//   contraction) -> device copies -> selection / edge-bin / gather-list
+//   kernels -> source emission lists -> initial state.
+// Step path: per-grid control words live in a device slot table; a step is
+//   one sweep launch per (precision, bin class) group plus one small
+//   advance launch, all on the context stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "sx.h"
+#include "sx_internal.h"
+
+using sx::GridDev;
+
+namespace {
+
+constexpr int kMaxSlots = 4096;
+
+struct DevBuf {
+  void *p = nullptr;
+  uint64_t bytes = 0;
+};
+
+struct Grid {
+  sx_grid_id id = 0;
+  int slot = -1;
+  GridDev hg{};
+  int kmax = 0;
+  int64_t n_em = 0;
+  std::vector<int32_t> perm;           // new -> original
+  std::vector<int32_t> inv;            // original -> new
+  std::vector<int32_t> orig_to_new_e;  // original CSR position -> new edge
+  std::vector<int32_t> row_ptr_h;      // new CSR, host copy
+  std::vector<int32_t> nbr_h;
+  std::vector<double> dL_h;            // new order
+  std::vector<double> tau_h;
+  std::vector<DevBuf> bufs;
+  uint64_t bytes = 0;
+  double *y_init = nullptr;
+  double e_sweep = 0.0;     // photons emitted per step
+  double esc_emit = 0.0;    // photons per step with no way out of a beam source
+  double base_sweeps = 0.0, base_emitted = 0.0, base_escaped = 0.0;
+};
+
+struct BatchCache {
+  std::vector<int32_t> key;
+  int2 *map = nullptr;
+  int32_t n_tiles = 0;
+};
+
+}  // namespace
+
+struct sx_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  uint64_t budget = 0;
+  uint64_t used = 0;
+  sx_alloc_fn alloc = nullptr;
+  sx_free_fn free_fn = nullptr;
+  void *user = nullptr;
+  GridDev *table = nullptr;
+  std::vector<int> free_slots;
+  std::map<sx_grid_id, Grid *> grids;
+  sx_grid_id next_id = 1;
+  std::string err;
+  bool poisoned = false;
+  std::vector<BatchCache> batches;
+};
+
+namespace {
+
+int fail(sx_ctx *ctx, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) {
+    ctx->err = buf;
+    if (code == SX_EDEVICE) ctx->poisoned = true;
+  }
+  return code;
+}
+
+#define HIP_TRY(ctx, call)                                                   \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return fail((ctx), SX_EDEVICE, "%s failed: %s", #call,                 \
+                  hipGetErrorString(e_));                                    \
+  } while (0)
+
+void *dev_alloc(sx_ctx *ctx, uint64_t bytes) {
+  if (bytes == 0) bytes = 16;
+  void *p = nullptr;
+  if (ctx->alloc) {
+    p = ctx->alloc((size_t)bytes, ctx->user);
+  } else {
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+  }
+  return p;
+}
+
+void dev_free(sx_ctx *ctx, void *p) {
+  if (!p) return;
+  if (ctx->free_fn)
+    ctx->free_fn(p, ctx->user);
+  else
+    (void)hipFree(p);
+}
+
+// Allocate for a grid, enforcing the context budget.
+template <typename T>
+int galloc(sx_ctx *ctx, Grid *g, T **out, uint64_t count) {
+  const uint64_t bytes = ((count * sizeof(T)) + 255) & ~uint64_t(255);
+  if (ctx->used + bytes > ctx->budget)
+    return fail(ctx, SX_ENOMEM, "device budget exceeded (%llu + %llu > %llu)",
+                (unsigned long long)ctx->used, (unsigned long long)bytes,
+                (unsigned long long)ctx->budget);
+  void *p = dev_alloc(ctx, bytes);
+  if (!p) return fail(ctx, SX_ENOMEM, "device allocation of %llu bytes failed",
+                      (unsigned long long)bytes);
+  g->bufs.push_back({p, bytes});
+  g->bytes += bytes;
+  ctx->used += bytes;
+  *out = (T *)p;
+  return SX_OK;
+}
+
+void grid_release(sx_ctx *ctx, Grid *g) {
+  for (auto &b : g->bufs) {
+    dev_free(ctx, b.p);
+    ctx->used -= b.bytes;
+  }
+  g->bufs.clear();
+  if (g->slot >= 0) ctx->free_slots.push_back(g->slot);
+  g->slot = -1;
+  delete g;
+}
+
+// ------------------------------------------------------------ Hilbert ---
+// Index of a point along a 3-D Hilbert curve with b bits per axis, from
+// J. Skilling, "Programming the Hilbert curve", AIP Conf. Proc. 707 (2004):
+// the axes are transformed in place into the curve's "transpose" form, whose
+// bits, interleaved from the top, are the index.
+uint64_t hilbert_key(uint32_t x0, uint32_t x1, uint32_t x2, int b) {
+  uint32_t X[3] = {x0, x1, x2};
+  const uint32_t M = 1u << (b - 1);
+  for (uint32_t Q = M; Q > 1; Q >>= 1) {
+    const uint32_t P = Q - 1;
+    for (int i = 0; i < 3; ++i) {
+      if (X[i] & Q) {
+        X[0] ^= P;
+      } else {
+        const uint32_t t = (X[0] ^ X[i]) & P;
+        X[0] ^= t;
+        X[i] ^= t;
+      }
+    }
+  }
+  for (int i = 1; i < 3; ++i) X[i] ^= X[i - 1];
+  uint32_t t = 0;
+  for (uint32_t Q = M; Q > 1; Q >>= 1)
+    if (X[2] & Q) t ^= Q - 1;
+  for (int i = 0; i < 3; ++i) X[i] ^= t;
+  uint64_t key = 0;
+  for (int q = b - 1; q >= 0; --q)
+    for (int i = 0; i < 3; ++i) key = (key << 1) | ((X[i] >> q) & 1u);
+  return key;
+}
+
+std::vector<int32_t> hilbert_order(const double *pos, int64_t n) {
+  double lo[3] = {INFINITY, INFINITY, INFINITY};
+  double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], pos[3 * i + a]);
+      hi[a] = std::max(hi[a], pos[3 * i + a]);
+    }
+  const int bits = 21;
+  const double scale = (double)((1u << bits) - 1);
+  std::vector<std::pair<uint64_t, int32_t>> kv((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    uint32_t q[3];
+    for (int a = 0; a < 3; ++a) {
+      const double w = hi[a] - lo[a];
+      const double f = w > 0 ? (pos[3 * i + a] - lo[a]) / w : 0.0;
+      double v = std::floor(f * scale);
+      v = std::min(std::max(v, 0.0), scale);
+      q[a] = (uint32_t)v;
+    }
+    kv[(size_t)i] = {hilbert_key(q[0], q[1], q[2], bits), (int32_t)i};
+  }
+  std::sort(kv.begin(), kv.end());
+  std::vector<int32_t> perm((size_t)n);
+  for (int64_t i = 0; i < n; ++i) perm[(size_t)i] = kv[(size_t)i].second;
+  return perm;
+}
+
+// -------------------------------------------------------- validation ---
+bool finite3(const double *p) {
+  return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]);
+}
+
+int validate(sx_ctx *ctx, const sx_grid_desc *d) {
+  if (!d) return fail(ctx, SX_EINVAL, "null descriptor");
+  const int64_t n = d->n_vertices;
+  if (n < 1) return fail(ctx, SX_EINVAL, "n_vertices must be >= 1");
+  if (n > (int64_t)1 << 30) return fail(ctx, SX_ENOTSUP, "n_vertices too large");
+  if (!d->pos || !d->nbr_ptr || !d->nbr_idx || !d->n_H || !d->volume ||
+      !d->bin_dirs)
+    return fail(ctx, SX_EINVAL, "required array is NULL");
+  if (d->precision != SX_FP64 && d->precision != SX_FP32_TRANSPORT)
+    return fail(ctx, SX_EINVAL, "precision must be SX_FP64 or SX_FP32_TRANSPORT");
+  const int K = d->n_bins;
+  if (K < 1) return fail(ctx, SX_EINVAL, "n_bins must be >= 1");
+  if (K > (d->precision == SX_FP64 ? SX_MAX_BINS_FP64 : SX_MAX_BINS_FP32))
+    return fail(ctx, SX_ENOTSUP, "n_bins %d over the limit for this precision",
+                K);
+  if (d->max_per_bin < 1 || d->max_per_bin > SX_MAX_PER_BIN)
+    return fail(ctx, SX_EINVAL, "max_per_bin must be 1..3");
+  if (d->n_subcycles < 1) return fail(ctx, SX_EINVAL, "n_subcycles must be >= 1");
+  if (!(d->dt > 0.0) || !std::isfinite(d->dt))
+    return fail(ctx, SX_EINVAL, "dt must be finite and > 0");
+  if (!(d->sigma >= 0.0) || !std::isfinite(d->sigma) ||
+      !(d->alpha_B >= 0.0) || !std::isfinite(d->alpha_B))
+    return fail(ctx, SX_EINVAL, "sigma and alpha_B must be finite and >= 0");
+  if (!std::isfinite(d->cos_min) || d->cos_min < -1.0 || d->cos_min >= 1.0)
+    return fail(ctx, SX_EINVAL, "cos_min must lie in [-1, 1)");
+  if (!d->dL && (!(d->kappa > 0.0) || !std::isfinite(d->kappa)))
+    return fail(ctx, SX_EINVAL, "kappa must be finite and > 0");
+  for (int k = 0; k < K; ++k) {
+    const double *u = d->bin_dirs + 3 * k;
+    if (!finite3(u)) return fail(ctx, SX_EINVAL, "bin %d not finite", k);
+    const double r = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (std::fabs(r - 1.0) > 1e-12)
+      return fail(ctx, SX_EINVAL, "bin %d is not a unit vector", k);
+  }
+  if (d->nbr_ptr[0] != 0) return fail(ctx, SX_EINVAL, "nbr_ptr[0] must be 0");
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t deg = d->nbr_ptr[i + 1] - d->nbr_ptr[i];
+    if (deg < 0) return fail(ctx, SX_EINVAL, "nbr_ptr decreases at %lld", (long long)i);
+    if (deg > SX_MAX_DEGREE)
+      return fail(ctx, SX_ENOTSUP, "vertex %lld has degree %lld > %d",
+                  (long long)i, (long long)deg, SX_MAX_DEGREE);
+    if (!finite3(d->pos + 3 * i))
+      return fail(ctx, SX_EINVAL, "position %lld not finite", (long long)i);
+    if (!(d->n_H[i] >= 0.0) || !std::isfinite(d->n_H[i]))
+      return fail(ctx, SX_EINVAL, "n_H[%lld] must be finite and >= 0", (long long)i);
+    if (!(d->volume[i] > 0.0) || !std::isfinite(d->volume[i]))
+      return fail(ctx, SX_EINVAL, "volume[%lld] must be finite and > 0", (long long)i);
+    if (d->dL && (!(d->dL[i] >= 0.0) || !std::isfinite(d->dL[i])))
+      return fail(ctx, SX_EINVAL, "dL[%lld] must be finite and >= 0", (long long)i);
+    if (d->x_init && !(d->x_init[i] >= 0.0 && d->x_init[i] <= 1.0))
+      return fail(ctx, SX_EINVAL, "x_init[%lld] outside [0,1]", (long long)i);
+  }
+  const int64_t E = d->nbr_ptr[n];
+  if (E >= ((int64_t)1 << 31) - 1) return fail(ctx, SX_ENOTSUP, "too many edges");
+  // rows: ids in range, no self loops, no duplicates; graph symmetric
+  std::vector<int32_t> sorted(d->nbr_idx, d->nbr_idx + E);
+  for (int64_t i = 0; i < n; ++i) {
+    auto b = sorted.begin() + d->nbr_ptr[i], e = sorted.begin() + d->nbr_ptr[i + 1];
+    std::sort(b, e);
+    for (auto it = b; it != e; ++it) {
+      if (*it < 0 || *it >= n)
+        return fail(ctx, SX_EINVAL, "neighbour id %d out of range", *it);
+      if (*it == i) return fail(ctx, SX_EINVAL, "self loop at vertex %lld", (long long)i);
+      if (it != b && *it == *(it - 1))
+        return fail(ctx, SX_EINVAL, "duplicate neighbour %d of vertex %lld", *it,
+                    (long long)i);
+    }
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t p = d->nbr_ptr[i]; p < d->nbr_ptr[i + 1]; ++p) {
+      const int32_t j = d->nbr_idx[p];
+      auto b = sorted.begin() + d->nbr_ptr[j], e = sorted.begin() + d->nbr_ptr[j + 1];
+      if (!std::binary_search(b, e, (int32_t)i))
+        return fail(ctx, SX_EINVAL, "graph not symmetric: %lld->%d has no reverse",
+                    (long long)i, j);
+    }
+  if (d->n_src < 0) return fail(ctx, SX_EINVAL, "n_src < 0");
+  if (d->n_src > 0 && (!d->src_vertex || !d->src_rate))
+    return fail(ctx, SX_EINVAL, "source arrays are NULL");
+  for (int s = 0; s < d->n_src; ++s) {
+    if (d->src_vertex[s] < 0 || d->src_vertex[s] >= n)
+      return fail(ctx, SX_EINVAL, "source %d vertex out of range", s);
+    if (!(d->src_rate[s] >= 0.0) || !std::isfinite(d->src_rate[s]))
+      return fail(ctx, SX_EINVAL, "source %d rate must be finite and >= 0", s);
+    if (d->src_dir) {
+      const double *u = d->src_dir + 3 * s;
+      if (!finite3(u)) return fail(ctx, SX_EINVAL, "source %d direction not finite", s);
+      const bool zero = u[0] == 0.0 && u[1] == 0.0 && u[2] == 0.0;
+      const double r = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      if (!zero && std::fabs(r - 1.0) > 1e-12)
+        return fail(ctx, SX_EINVAL, "source %d direction neither zero nor unit", s);
+    }
+  }
+  return SX_OK;
+}
+
+struct Sizes {
+  int64_t n, npad, ntiles, E, K, kw, sp;
+};
+
+Sizes sizes_of(const sx_grid_desc *d) {
+  Sizes s;
+  s.n = d->n_vertices;
+  s.npad = (s.n + sx::kTile - 1) / sx::kTile * sx::kTile;
+  s.ntiles = s.npad / sx::kTile;
+  s.E = d->nbr_ptr[s.n];
+  s.K = d->n_bins;
+  s.kw = (s.K + 15) / 16;
+  s.sp = d->precision == SX_FP64 ? 8 : 4;
+  return s;
+}
+
+uint64_t rnd(uint64_t b) { return (b + 255) & ~uint64_t(255); }
+
+uint64_t bytes_estimate(const Sizes &s, int64_t n_em, int64_t n_ovf) {
+  uint64_t b = 0;
+  b += rnd(4 * (s.npad + 1)) + rnd(4 * s.E) + rnd(s.E) + rnd(24 * s.E) + rnd(24 * s.K);
+  b += rnd(4 * s.npad * s.K) + rnd(s.E) + rnd(4 * s.npad * s.K) +
+       rnd(4 * s.npad * s.kw) + 2 * rnd(4 * (s.npad + 1)) + rnd(2 * n_ovf + 2);
+  b += rnd(4 * (s.npad + 1)) + rnd(4 * n_em + 4) + rnd(8 * n_em + 8);
+  b += 6 * rnd(8 * s.npad);
+  b += 2 * rnd((uint64_t)s.sp * s.K * s.npad);
+  b += rnd(24 * s.ntiles);
+  return b;
+}
+
+Grid *find(sx_ctx *ctx, sx_grid_id id) {
+  auto it = ctx->grids.find(id);
+  return it == ctx->grids.end() ? nullptr : it->second;
+}
+
+int write_slot(sx_ctx *ctx, Grid *g) {
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->table + g->slot, &g->hg, sizeof(GridDev),
+                              hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return SX_OK;
+}
+
+// (Re)build the selection products of a grid on the device; the overflow
+// pool must already be sized (ovf_cap).
+int build_tables(sx_ctx *ctx, Grid *g) {
+  GridDev *dg = ctx->table + g->slot;
+  HIP_TRY(ctx, sx::launch_select(dg, g->hg, ctx->stream));
+  HIP_TRY(ctx, sx::launch_edge_bins(dg, g->hg, ctx->stream));
+  HIP_TRY(ctx, sx::launch_inlist_count(dg, g->hg, ctx->stream));
+  HIP_TRY(ctx, sx::launch_scan(g->hg.ovf_cnt, g->hg.ovf_ptr, g->hg.npad, ctx->stream));
+  HIP_TRY(ctx, sx::launch_inlist_fill(dg, g->hg, ctx->stream));
+  return SX_OK;
+}
+
+}  // namespace
+
+// =================================================================== ABI ==
+extern "C" {
+
+const char *sx_strerror(int code) {
+  switch (code) {
+    case SX_OK: return "ok";
+    case SX_EINVAL: return "invalid argument";
+    case SX_ENOMEM: return "out of device memory budget";
+    case SX_EDEVICE: return "device error";
+    case SX_ENOTFOUND: return "unknown grid";
+    case SX_ENOTSUP: return "not supported";
+    default: return "unknown error";
+  }
+}
+
+const char *sx_last_error(const sx_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : "null context";
+}
+
+int sx_init(sx_ctx **out, const sx_ctx_opts *opts) {
+  if (!out) return SX_EINVAL;
+  *out = nullptr;
+  sx_ctx_opts o{};
+  if (opts) o = *opts;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return SX_EDEVICE;
+  }
+  if (o.device < 0 || o.device >= ndev) return SX_EINVAL;
+  if ((o.alloc == nullptr) != (o.free == nullptr)) return SX_EINVAL;
+  if (hipSetDevice(o.device) != hipSuccess) return SX_EDEVICE;
+  sx_ctx *ctx = new sx_ctx();
+  ctx->device = o.device;
+  ctx->alloc = o.alloc;
+  ctx->free_fn = o.free;
+  ctx->user = o.alloc_user;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    delete ctx;
+    return SX_EDEVICE;
+  }
+  ctx->budget = o.hbm_budget ? o.hbm_budget : (uint64_t)(0.9 * (double)fr);
+  if (o.stream) {
+    ctx->stream = (hipStream_t)o.stream;
+  } else {
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete ctx;
+      return SX_EDEVICE;
+    }
+    ctx->own_stream = true;
+  }
+  if (hipMalloc(&ctx->table, sizeof(GridDev) * kMaxSlots) != hipSuccess) {
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return SX_EDEVICE;
+  }
+  for (int s = kMaxSlots - 1; s >= 0; --s) ctx->free_slots.push_back(s);
+  *out = ctx;
+  return SX_OK;
+}
+
+int sx_finalize(sx_ctx *ctx) {
+  if (!ctx) return SX_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto &kv : ctx->grids) grid_release(ctx, kv.second);
+  ctx->grids.clear();
+  for (auto &b : ctx->batches) (void)hipFree(b.map);
+  (void)hipFree(ctx->table);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return SX_OK;
+}
+
+void *sx_stream(sx_ctx *ctx) { return ctx ? (void *)ctx->stream : nullptr; }
+
+int sx_mem_info(sx_ctx *ctx, uint64_t *used, uint64_t *budget) {
+  if (!ctx) return SX_EINVAL;
+  if (used) *used = ctx->used;
+  if (budget) *budget = ctx->budget;
+  return SX_OK;
+}
+
+int sx_grid_bytes(const sx_grid_desc *d, uint64_t *bytes) {
+  if (!d || !bytes || d->n_vertices < 1 || !d->nbr_ptr || d->n_bins < 1)
+    return SX_EINVAL;
+  const Sizes s = sizes_of(d);
+  // overflow entries: expect ~0.3 per (vertex, bin) on Poisson-Delaunay
+  // grids; the exact pool is allocated after the count pass
+  *bytes = bytes_estimate(s, s.E, (int64_t)(0.5 * (double)(s.npad * s.K)));
+  return SX_OK;
+}
+
+int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
+  if (!ctx || !out) return SX_EINVAL;
+  if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
+  int rc = validate(ctx, d);
+  if (rc) return rc;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (ctx->free_slots.empty()) return fail(ctx, SX_ENOMEM, "too many grids");
+  const Sizes S = sizes_of(d);
+  const int kmax = sx::kmax_bucket((int)S.K, d->precision);
+  if (!kmax) return fail(ctx, SX_ENOTSUP, "unsupported bin count");
+  {
+    uint64_t want = 0;
+    sx_grid_bytes(d, &want);
+    if (ctx->used + want > ctx->budget)
+      return fail(ctx, SX_ENOMEM, "grid needs ~%llu bytes, %llu of %llu free",
+                  (unsigned long long)want,
+                  (unsigned long long)(ctx->budget - ctx->used),
+                  (unsigned long long)ctx->budget);
+  }
+  const int64_t n = S.n, E = S.E, K = S.K, npad = S.npad;
+  Grid *g = new Grid();
+  g->kmax = kmax;
+
+  // ---- reorder along a Hilbert curve (locality of the gathers)
+  g->perm = hilbert_order(d->pos, n);
+  g->inv.assign((size_t)n, 0);
+  for (int64_t v = 0; v < n; ++v) g->inv[(size_t)g->perm[(size_t)v]] = (int32_t)v;
+
+  // ---- new CSR, rows sorted by ORIGINAL neighbour id, so that summing the
+  // in-list in slot order adds the senders in ascending original id
+  std::vector<int32_t> &rp = g->row_ptr_h;
+  rp.assign((size_t)npad + 1, 0);
+  for (int64_t v = 0; v < n; ++v) {
+    const int32_t i = g->perm[(size_t)v];
+    rp[(size_t)v + 1] = rp[(size_t)v] + (int32_t)(d->nbr_ptr[i + 1] - d->nbr_ptr[i]);
+  }
+  for (int64_t v = n; v < npad; ++v) rp[(size_t)v + 1] = rp[(size_t)v];
+  std::vector<int32_t> orig_nbr((size_t)E);   // original id of each new edge's target
+  g->nbr_h.assign((size_t)E, 0);
+  g->orig_to_new_e.assign((size_t)E, 0);
+  std::vector<double> edir((size_t)(3 * E));
+  std::vector<double> len_orig((size_t)E);     // per original CSR position
+  {
+    std::vector<std::pair<int32_t, int64_t>> row;
+    for (int64_t v = 0; v < n; ++v) {
+      const int32_t i = g->perm[(size_t)v];
+      row.clear();
+      for (int64_t p = d->nbr_ptr[i]; p < d->nbr_ptr[i + 1]; ++p)
+        row.push_back({d->nbr_idx[p], p});
+      std::sort(row.begin(), row.end());
+      for (size_t r = 0; r < row.size(); ++r) {
+        const int64_t e = rp[(size_t)v] + (int64_t)r;
+        const int32_t j = row[r].first;
+        orig_nbr[(size_t)e] = j;
+        g->nbr_h[(size_t)e] = g->inv[(size_t)j];
+        g->orig_to_new_e[(size_t)row[r].second] = (int32_t)e;
+      }
+    }
+  }
+  // ---- edge geometry in IEEE double with every operation rounded (the
+  // library is built without FMA contraction on the host): unit vector and
+  // length of each directed edge
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t p = d->nbr_ptr[i]; p < d->nbr_ptr[i + 1]; ++p) {
+      const int32_t j = d->nbr_idx[p];
+      const double dx = d->pos[3 * j + 0] - d->pos[3 * i + 0];
+      const double dy = d->pos[3 * j + 1] - d->pos[3 * i + 1];
+      const double dz = d->pos[3 * j + 2] - d->pos[3 * i + 2];
+      const double xx = dx * dx, yy = dy * dy, zz = dz * dz;
+      const double len = std::sqrt((xx + yy) + zz);
+      const int64_t e = g->orig_to_new_e[(size_t)p];
+      edir[(size_t)(3 * e + 0)] = dx / len;
+      edir[(size_t)(3 * e + 1)] = dy / len;
+      edir[(size_t)(3 * e + 2)] = dz / len;
+      len_orig[(size_t)p] = len;
+    }
+  }
+  // ---- reverse slots: position of the row's vertex in its neighbour's row
+  std::vector<uint8_t> rev((size_t)E);
+  for (int64_t v = 0; v < n; ++v) {
+    const int32_t vi = g->perm[(size_t)v];
+    for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) {
+      const int32_t w = g->nbr_h[(size_t)e];
+      auto b = orig_nbr.begin() + rp[(size_t)w], en = orig_nbr.begin() + rp[(size_t)w + 1];
+      auto it = std::lower_bound(b, en, vi);
+      rev[(size_t)e] = (uint8_t)(it - b);
+    }
+  }
+  // ---- per-vertex physics in new order
+  std::vector<double> tau((size_t)npad, 0.0), dtnhv((size_t)npad, 1.0),
+      bco((size_t)npad, 0.0), y0((size_t)npad, 1.0);
+  g->dL_h.assign((size_t)n, 0.0);
+  g->tau_h.assign((size_t)n, 0.0);
+  for (int64_t v = 0; v < n; ++v) {
+    const int32_t i = g->perm[(size_t)v];
+    double dl;
+    if (d->dL) {
+      dl = d->dL[i];
+    } else {
+      // mean incident edge length (in the caller's row order) times kappa
+      double sum = 0.0;
+      const int64_t deg = d->nbr_ptr[i + 1] - d->nbr_ptr[i];
+      for (int64_t p = d->nbr_ptr[i]; p < d->nbr_ptr[i + 1]; ++p) sum += len_orig[(size_t)p];
+      dl = deg > 0 ? d->kappa * (sum / (double)deg) : 0.0;
+    }
+    g->dL_h[(size_t)v] = dl;
+    tau[(size_t)v] = (d->n_H[i] * d->sigma) * dl;
+    g->tau_h[(size_t)v] = tau[(size_t)v];
+    dtnhv[(size_t)v] = d->dt * (d->n_H[i] * d->volume[i]);
+    bco[(size_t)v] = d->alpha_B * d->n_H[i];
+    y0[(size_t)v] = d->x_init ? 1.0 - d->x_init[i] : 1.0;
+  }
+  // ---- photon unit: the power of two nearest the photons emitted per step
+  double e_sweep = 0.0;
+  for (int s = 0; s < d->n_src; ++s) e_sweep += d->src_rate[s] * d->dt;
+  double unit = 1.0;
+  if (e_sweep > 0.0 && std::isfinite(e_sweep)) unit = std::ldexp(1.0, (int)std::lround(std::log2(e_sweep)));
+  g->e_sweep = e_sweep;
+
+  // ---- device allocations
+  GridDev &h = g->hg;
+  h.n = (int32_t)n;
+  h.npad = (int32_t)npad;
+  h.ntiles = (int32_t)S.ntiles;
+  h.k = (int32_t)K;
+  h.kw = (int32_t)S.kw;
+  h.n_sub = d->n_subcycles;
+  h.mpb = d->max_per_bin;
+  h.precision = d->precision;
+  h.parity = 0;
+  h.remaining = 0;
+  h.sweeps = 0;
+  h.unit = unit;
+  h.dt = d->dt;
+  h.cos_min = d->cos_min;
+  h.plane = npad;
+  h.n_edges = E;
+  int32_t *d_rp, *d_nbr, *d_ovf_cnt, *d_ovf_ptr;
+  uint8_t *d_rev, *d_ebin;
+  double *d_edir, *d_bins, *d_tau, *d_dtnhv, *d_b, *d_y, *d_nin, *d_y0, *d_tally;
+  uint32_t *d_fwd, *d_inw, *d_mb;
+  void *d_o0, *d_o1;
+#define GA(ptr, cnt)                                      \
+  do {                                                    \
+    int r_ = galloc(ctx, g, &ptr, (uint64_t)(cnt));       \
+    if (r_) { grid_release(ctx, g); return r_; }          \
+  } while (0)
+  GA(d_rp, npad + 1);
+  GA(d_nbr, E);
+  GA(d_rev, E);
+  GA(d_edir, 3 * E);
+  GA(d_bins, 3 * K);
+  GA(d_fwd, npad * K);
+  GA(d_ebin, E);
+  GA(d_inw, npad * K);
+  GA(d_mb, npad * S.kw);
+  GA(d_ovf_cnt, npad + 1);
+  GA(d_ovf_ptr, npad + 1);
+  GA(d_tau, npad);
+  GA(d_dtnhv, npad);
+  GA(d_b, npad);
+  GA(d_y, npad);
+  GA(d_nin, npad);
+  GA(d_y0, npad);
+  GA(d_tally, 3 * S.ntiles);
+  {
+    uint8_t *o0, *o1;
+    GA(o0, (uint64_t)S.sp * K * npad);
+    GA(o1, (uint64_t)S.sp * K * npad);
+    d_o0 = o0;
+    d_o1 = o1;
+  }
+  h.row_ptr = d_rp;
+  h.nbr = d_nbr;
+  h.rev = d_rev;
+  h.edir = d_edir;
+  h.bins = d_bins;
+  h.fwd = d_fwd;
+  h.ebin = d_ebin;
+  h.inword = d_inw;
+  h.mbits = d_mb;
+  h.ovf_cnt = d_ovf_cnt;
+  h.ovf_ptr = d_ovf_ptr;
+  h.ovf = nullptr;
+  h.ovf_cap = 0;
+  h.tau = d_tau;
+  h.dtnhv = d_dtnhv;
+  h.bcoef = d_b;
+  h.y = d_y;
+  h.nin = d_nin;
+  h.o[0] = d_o0;
+  h.o[1] = d_o1;
+  h.tally = d_tally;
+  g->y_init = d_y0;
+  g->slot = ctx->free_slots.back();
+  ctx->free_slots.pop_back();
+
+  hipStream_t st = ctx->stream;
+  auto H2D = [&](void *dst, const void *src, size_t bytes) {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+  };
+#define UP(dst, src, bytes)                                                   \
+  do {                                                                        \
+    hipError_t e_ = H2D(dst, src, bytes);                                     \
+    if (e_ != hipSuccess) {                                                   \
+      grid_release(ctx, g);                                                   \
+      return fail(ctx, SX_EDEVICE, "upload copy failed: %s", hipGetErrorString(e_)); \
+    }                                                                         \
+  } while (0)
+  UP(d_rp, rp.data(), 4 * (npad + 1));
+  UP(d_nbr, g->nbr_h.data(), 4 * E);
+  UP(d_rev, rev.data(), E);
+  UP(d_edir, edir.data(), 24 * E);
+  UP(d_bins, d->bin_dirs, 24 * K);
+  UP(d_tau, tau.data(), 8 * npad);
+  UP(d_dtnhv, dtnhv.data(), 8 * npad);
+  UP(d_b, bco.data(), 8 * npad);
+  UP(d_y0, y0.data(), 8 * npad);
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    grid_release(ctx, g);
+    return fail(ctx, SX_EDEVICE, "upload sync failed");
+  }
+  int r;
+  if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
+
+  // ---- selection tables and gather lists; size the overflow pool
+  GridDev *dg = ctx->table + g->slot;
+  auto kfail = [&](hipError_t e) {
+    grid_release(ctx, g);
+    return fail(ctx, SX_EDEVICE, "table kernels failed: %s", hipGetErrorString(e));
+  };
+  hipError_t he;
+  if ((he = sx::launch_select(dg, h, st)) != hipSuccess) return kfail(he);
+  if ((he = sx::launch_edge_bins(dg, h, st)) != hipSuccess) return kfail(he);
+  if ((he = sx::launch_inlist_count(dg, h, st)) != hipSuccess) return kfail(he);
+  if ((he = sx::launch_scan(h.ovf_cnt, h.ovf_ptr, h.npad, st)) != hipSuccess) return kfail(he);
+  int32_t n_ovf = 0;
+  if ((he = hipMemcpyAsync(&n_ovf, h.ovf_ptr + npad, 4, hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return kfail(he);
+  if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
+  {
+    uint16_t *d_ovf;
+    GA(d_ovf, (uint64_t)n_ovf + 1);
+    h.ovf = d_ovf;
+    h.ovf_cap = n_ovf;
+  }
+  if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
+  if ((he = sx::launch_inlist_fill(dg, h, st)) != hipSuccess) return kfail(he);
+
+  // ---- sources: per receiving vertex, in source order, the share of each
+  // source's photons and the bin of the edge it arrives along
+  std::vector<uint8_t> ebin((size_t)E);
+  if (E > 0) {
+    if ((he = hipMemcpyAsync(ebin.data(), d_ebin, E, hipMemcpyDeviceToHost, st)) != hipSuccess)
+      return kfail(he);
+    if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
+  }
+  struct Em {
+    int32_t recv;
+    int32_t k;
+    double amt;
+  };
+  std::vector<Em> em;
+  double esc_emit = 0.0;
+  for (int s = 0; s < d->n_src; ++s) {
+    const int32_t vi = d->src_vertex[s];
+    const int32_t v = g->inv[(size_t)vi];
+    const double Es = d->src_rate[s] * d->dt;
+    const double *u = d->src_dir ? d->src_dir + 3 * s : nullptr;
+    const bool iso = !u || (u[0] == 0.0 && u[1] == 0.0 && u[2] == 0.0);
+    const int64_t deg = d->nbr_ptr[vi + 1] - d->nbr_ptr[vi];
+    if (iso) {
+      if (deg == 0) { esc_emit += Es; continue; }
+      const double share = (Es / unit) / (double)deg;
+      for (int64_t p = d->nbr_ptr[vi]; p < d->nbr_ptr[vi + 1]; ++p) {
+        const int32_t e = g->orig_to_new_e[(size_t)p];
+        em.push_back({g->nbr_h[(size_t)e], (int32_t)ebin[(size_t)e], share});
+      }
+    } else {
+      // beam: the <= mpb neighbours most aligned with u, cosine > cos_min,
+      // ties to the lower original id (rows are in original-id order)
+      int32_t sl[3];
+      double cs[3];
+      int cnt = 0;
+      for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) {
+        const double *ed = &edir[(size_t)(3 * e)];
+        const double a = ed[0] * u[0], b = ed[1] * u[1], c3 = ed[2] * u[2];
+        const double c = (a + b) + c3;
+        if (!(c > d->cos_min)) continue;
+        int pos = cnt < d->max_per_bin ? cnt : d->max_per_bin;
+        while (pos > 0 && c > cs[pos - 1]) --pos;
+        if (pos >= d->max_per_bin) continue;
+        const int last = cnt < d->max_per_bin ? cnt : d->max_per_bin - 1;
+        for (int q = last; q > pos; --q) { cs[q] = cs[q - 1]; sl[q] = sl[q - 1]; }
+        cs[pos] = c;
+        sl[pos] = e;
+        if (cnt < d->max_per_bin) ++cnt;
+      }
+      if (cnt == 0) { esc_emit += Es; continue; }
+      const double share = (Es / unit) / (double)cnt;
+      for (int q = 0; q < cnt; ++q)
+        em.push_back({g->nbr_h[(size_t)sl[q]], (int32_t)ebin[(size_t)sl[q]], share});
+    }
+  }
+  g->esc_emit = esc_emit;
+  std::stable_sort(em.begin(), em.end(),
+                   [](const Em &a, const Em &b) { return a.recv < b.recv; });
+  std::vector<int32_t> em_ptr((size_t)npad + 1, 0), em_k(em.size());
+  std::vector<double> em_amt(em.size());
+  for (size_t q = 0; q < em.size(); ++q) {
+    em_ptr[(size_t)em[q].recv + 1]++;
+    em_k[q] = em[q].k;
+    em_amt[q] = em[q].amt;
+  }
+  for (int64_t v = 0; v < npad; ++v) em_ptr[(size_t)v + 1] += em_ptr[(size_t)v];
+  g->n_em = (int64_t)em.size();
+  {
+    int32_t *d_emp, *d_emk;
+    double *d_ema;
+    GA(d_emp, npad + 1);
+    GA(d_emk, g->n_em + 1);
+    GA(d_ema, g->n_em + 1);
+    UP(d_emp, em_ptr.data(), 4 * (npad + 1));
+    if (g->n_em) {
+      UP(d_emk, em_k.data(), 4 * g->n_em);
+      UP(d_ema, em_amt.data(), 8 * g->n_em);
+    }
+    h.em_ptr = d_emp;
+    h.em_k = d_emk;
+    h.em_amt = d_ema;
+  }
+#undef GA
+#undef UP
+  if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
+  if ((he = sx::launch_reset_state(dg, h, g->y_init, st)) != hipSuccess) return kfail(he);
+  if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
+  if ((he = hipGetLastError()) != hipSuccess) return kfail(he);
+  g->id = ctx->next_id++;
+  ctx->grids[g->id] = g;
+  *out = g->id;
+  return SX_OK;
+}
+
+int sx_grid_reset(sx_ctx *ctx, sx_grid_id id) {
+  if (!ctx) return SX_EINVAL;
+  if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
+  Grid *g = find(ctx, id);
+  if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  int r = build_tables(ctx, g);
+  if (r) return r;
+  HIP_TRY(ctx, sx::launch_reset_state(ctx->table + g->slot, g->hg, g->y_init, ctx->stream));
+  g->base_sweeps = g->base_emitted = g->base_escaped = 0.0;
+  return SX_OK;
+}
+
+int sx_grid_free(sx_ctx *ctx, sx_grid_id id) {
+  if (!ctx) return SX_EINVAL;
+  Grid *g = find(ctx, id);
+  if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  // cached batch maps may reference this grid's slot
+  for (auto &b : ctx->batches) (void)hipFree(b.map);
+  ctx->batches.clear();
+  ctx->grids.erase(id);
+  grid_release(ctx, g);
+  return SX_OK;
+}
+
+namespace {
+
+struct Group {
+  int precision, kmax;
+  std::vector<Grid *> gs;
+};
+
+int launch_steps(sx_ctx *ctx, std::vector<Grid *> &gs, int32_t n_launch) {
+  if (n_launch <= 0 || gs.empty()) return SX_OK;
+  std::vector<Group> groups;
+  for (Grid *g : gs) {
+    Group *hit = nullptr;
+    for (auto &gr : groups)
+      if (gr.precision == g->hg.precision && gr.kmax == g->kmax) hit = &gr;
+    if (!hit) {
+      groups.push_back({g->hg.precision, g->kmax, {}});
+      hit = &groups.back();
+    }
+    hit->gs.push_back(g);
+  }
+  struct Launch {
+    const GridDev *grids;
+    const int2 *map;
+    int32_t n_tiles;
+    int kmax, precision;
+  };
+  std::vector<Launch> launches;
+  for (auto &gr : groups) {
+    if (gr.gs.size() == 1) {
+      Grid *g = gr.gs[0];
+      launches.push_back({ctx->table + g->slot, nullptr, g->hg.ntiles, gr.kmax, gr.precision});
+      continue;
+    }
+    std::vector<int32_t> key;
+    for (Grid *g : gr.gs) key.push_back(g->slot);
+    BatchCache *bc = nullptr;
+    for (auto &b : ctx->batches)
+      if (b.key == key) bc = &b;
+    if (!bc) {
+      if (ctx->batches.size() >= 16) {
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        for (auto &b : ctx->batches) (void)hipFree(b.map);
+        ctx->batches.clear();
+      }
+      std::vector<int2> map;
+      for (Grid *g : gr.gs)
+        for (int32_t t = 0; t < g->hg.ntiles; ++t) map.push_back(make_int2(g->slot, t));
+      BatchCache nb;
+      nb.key = key;
+      nb.n_tiles = (int32_t)map.size();
+      HIP_TRY(ctx, hipMalloc(&nb.map, sizeof(int2) * map.size()));
+      HIP_TRY(ctx, hipMemcpyAsync(nb.map, map.data(), sizeof(int2) * map.size(),
+                                  hipMemcpyHostToDevice, ctx->stream));
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      ctx->batches.push_back(nb);
+      bc = &ctx->batches.back();
+    }
+    launches.push_back({ctx->table, bc->map, bc->n_tiles, gr.kmax, gr.precision});
+  }
+  std::vector<int32_t> slots;
+  for (Grid *g : gs) slots.push_back(g->slot);
+  for (int32_t s = 0; s < n_launch; ++s) {
+    for (auto &l : launches)
+      HIP_TRY(ctx, sx::launch_sweep(l.grids, l.map, l.n_tiles, l.kmax, l.precision,
+                                    ctx->stream));
+    HIP_TRY(ctx, sx::launch_advance(ctx->table, slots.data(), (int32_t)slots.size(),
+                                    ctx->stream));
+  }
+  return SX_OK;
+}
+
+int collect(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, std::vector<Grid *> &gs) {
+  if (n < 0 || (n > 0 && !ids)) return fail(ctx, SX_EINVAL, "bad id list");
+  for (int32_t i = 0; i < n; ++i) {
+    Grid *g = find(ctx, ids[i]);
+    if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)ids[i]);
+    for (Grid *o : gs)
+      if (o == g) return fail(ctx, SX_EINVAL, "grid %lld listed twice", (long long)ids[i]);
+    gs.push_back(g);
+  }
+  return SX_OK;
+}
+
+}  // namespace
+
+int sx_step(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, int32_t n_sweeps) {
+  if (!ctx) return SX_EINVAL;
+  if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
+  if (n_sweeps < 0) return fail(ctx, SX_EINVAL, "n_sweeps < 0");
+  std::vector<Grid *> gs;
+  int r = collect(ctx, ids, n, gs);
+  if (r) return r;
+  if (n_sweeps == 0 || gs.empty()) return SX_OK;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  std::vector<int32_t> slots, vals;
+  for (Grid *g : gs) {
+    slots.push_back(g->slot);
+    vals.push_back(n_sweeps);
+  }
+  HIP_TRY(ctx, sx::launch_set_remaining(ctx->table, slots.data(), vals.data(), n, 1,
+                                        ctx->stream));
+  return launch_steps(ctx, gs, n_sweeps);
+}
+
+int sx_solve(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, const int32_t *n_sweeps) {
+  if (!ctx) return SX_EINVAL;
+  if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
+  std::vector<Grid *> gs;
+  int r = collect(ctx, ids, n, gs);
+  if (r) return r;
+  if (gs.empty()) return SX_OK;
+  if (!n_sweeps) return fail(ctx, SX_EINVAL, "n_sweeps is NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  int32_t mx = 0;
+  std::vector<int32_t> slots, vals;
+  for (int32_t i = 0; i < n; ++i) {
+    if (n_sweeps[i] < 0) return fail(ctx, SX_EINVAL, "n_sweeps[%d] < 0", i);
+    mx = std::max(mx, n_sweeps[i]);
+    slots.push_back(gs[(size_t)i]->slot);
+    vals.push_back(n_sweeps[i]);
+  }
+  HIP_TRY(ctx, sx::launch_set_remaining(ctx->table, slots.data(), vals.data(), n, 0,
+                                        ctx->stream));
+  r = launch_steps(ctx, gs, mx);
+  if (r) return r;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  HIP_TRY(ctx, hipGetLastError());
+  return SX_OK;
+}
+
+int sx_sync(sx_ctx *ctx) {
+  if (!ctx) return SX_EINVAL;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return SX_OK;
+}
+
+int sx_read_state(sx_ctx *ctx, sx_grid_id id, const sx_state_out *out) {
+  if (!ctx || !out) return SX_EINVAL;
+  if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
+  Grid *g = find(ctx, id);
+  if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  const GridDev &h = g->hg;
+  const int64_t n = h.n, npad = h.npad, K = h.k;
+  GridDev cur;
+  HIP_TRY(ctx, hipMemcpyAsync(&cur, ctx->table + g->slot, sizeof cur,
+                              hipMemcpyDeviceToHost, st));
+  std::vector<double> buf;
+  if (out->x || out->y) {
+    buf.resize((size_t)npad);
+    HIP_TRY(ctx, hipMemcpyAsync(buf.data(), h.y, 8 * npad, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    for (int64_t i = 0; i < n; ++i) {
+      const double yv = buf[(size_t)g->inv[(size_t)i]];
+      if (out->y) out->y[i] = yv;
+      if (out->x) out->x[i] = 1.0 - yv;
+    }
+  }
+  if (out->nin) {
+    buf.resize((size_t)npad);
+    HIP_TRY(ctx, hipMemcpyAsync(buf.data(), h.nin, 8 * npad, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    for (int64_t i = 0; i < n; ++i) out->nin[i] = buf[(size_t)g->inv[(size_t)i]];
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  if (out->photons) {
+    const void *src = h.o[cur.parity];
+    if (h.precision == SX_FP64) {
+      std::vector<double> o((size_t)(K * npad));
+      HIP_TRY(ctx, hipMemcpyAsync(o.data(), src, 8 * K * npad, hipMemcpyDeviceToHost, st));
+      HIP_TRY(ctx, hipStreamSynchronize(st));
+      for (int64_t i = 0; i < n; ++i) {
+        const int64_t v = g->inv[(size_t)i];
+        for (int64_t k = 0; k < K; ++k) out->photons[i * K + k] = o[(size_t)(k * npad + v)] * h.unit;
+      }
+    } else {
+      std::vector<float> o((size_t)(K * npad));
+      HIP_TRY(ctx, hipMemcpyAsync(o.data(), src, 4 * K * npad, hipMemcpyDeviceToHost, st));
+      HIP_TRY(ctx, hipStreamSynchronize(st));
+      for (int64_t i = 0; i < n; ++i) {
+        const int64_t v = g->inv[(size_t)i];
+        for (int64_t k = 0; k < K; ++k)
+          out->photons[i * K + k] = (double)o[(size_t)(k * npad + v)] * h.unit;
+      }
+    }
+  }
+  if (out->tally) {
+    std::vector<double> t((size_t)(3 * h.ntiles));
+    HIP_TRY(ctx, hipMemcpyAsync(t.data(), h.tally, 8 * 3 * h.ntiles, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    double a = 0, e = 0, f = 0;
+    for (int64_t q = 0; q < h.ntiles; ++q) {
+      a += t[(size_t)(3 * q)];
+      e += t[(size_t)(3 * q + 1)];
+      f += t[(size_t)(3 * q + 2)];
+    }
+    const double sw = (double)cur.sweeps;
+    const double since = sw - g->base_sweeps;
+    out->tally->sweeps = sw;
+    out->tally->emitted = g->base_emitted + since * g->e_sweep;
+    out->tally->absorbed = a * h.unit;
+    out->tally->escaped = g->base_escaped + e * h.unit + since * g->esc_emit;
+    out->tally->in_flight = f * h.unit;
+  }
+  return SX_OK;
+}
+
+int sx_grid_restore(sx_ctx *ctx, sx_grid_id id, const sx_state_in *in) {
+  if (!ctx || !in) return SX_EINVAL;
+  if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
+  Grid *g = find(ctx, id);
+  if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  GridDev &h = g->hg;
+  const int64_t n = h.n, npad = h.npad, K = h.k;
+  GridDev cur;
+  HIP_TRY(ctx, hipMemcpy(&cur, ctx->table + g->slot, sizeof cur, hipMemcpyDeviceToHost));
+  if (in->y) {
+    std::vector<double> y((size_t)npad, 1.0);
+    for (int64_t i = 0; i < n; ++i) {
+      if (!(in->y[i] >= 0.0 && in->y[i] <= 1.0))
+        return fail(ctx, SX_EINVAL, "restored y[%lld] outside [0,1]", (long long)i);
+      y[(size_t)g->inv[(size_t)i]] = in->y[i];
+    }
+    HIP_TRY(ctx, hipMemcpy(h.y, y.data(), 8 * npad, hipMemcpyHostToDevice));
+  }
+  if (in->photons) {
+    for (int64_t q = 0; q < n * K; ++q)
+      if (!(in->photons[q] >= 0.0) || !std::isfinite(in->photons[q]))
+        return fail(ctx, SX_EINVAL, "restored photons must be finite and >= 0");
+    void *dst = h.o[cur.parity];
+    if (h.precision == SX_FP64) {
+      std::vector<double> o((size_t)(K * npad), 0.0);
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = 0; k < K; ++k)
+          o[(size_t)(k * npad + g->inv[(size_t)i])] = in->photons[i * K + k] / h.unit;
+      HIP_TRY(ctx, hipMemcpy(dst, o.data(), 8 * K * npad, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> o((size_t)(K * npad), 0.0f);
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = 0; k < K; ++k)
+          o[(size_t)(k * npad + g->inv[(size_t)i])] = (float)(in->photons[i * K + k] / h.unit);
+      HIP_TRY(ctx, hipMemcpy(dst, o.data(), 4 * K * npad, hipMemcpyHostToDevice));
+    }
+  }
+  if (in->tally) {
+    std::vector<double> t((size_t)(3 * h.ntiles), 0.0);
+    t[0] = in->tally->absorbed / h.unit;
+    t[2] = in->tally->in_flight / h.unit;
+    HIP_TRY(ctx, hipMemcpy(h.tally, t.data(), 8 * 3 * h.ntiles, hipMemcpyHostToDevice));
+    g->base_sweeps = in->tally->sweeps;
+    g->base_emitted = in->tally->emitted;
+    g->base_escaped = in->tally->escaped;
+    cur.sweeps = (int64_t)in->tally->sweeps;
+    HIP_TRY(ctx, hipMemcpy(&ctx->table[g->slot].sweeps, &cur.sweeps, sizeof(int64_t),
+                           hipMemcpyHostToDevice));
+  }
+  return SX_OK;
+}
+
+int sx_read_tables(sx_ctx *ctx, sx_grid_id id, int32_t *sel_nbr, int32_t *sel_m,
+                   int32_t *edge_bin, double *dL, double *tau) {
+  if (!ctx) return SX_EINVAL;
+  if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
+  Grid *g = find(ctx, id);
+  if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  const GridDev &h = g->hg;
+  const int64_t n = h.n, K = h.k, E = h.n_edges;
+  if (sel_nbr || sel_m) {
+    std::vector<uint32_t> f((size_t)(h.npad * K));
+    HIP_TRY(ctx, hipMemcpyAsync(f.data(), h.fwd, 4 * h.npad * K, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t v = g->inv[(size_t)i];
+      const int32_t rb = g->row_ptr_h[(size_t)v];
+      for (int64_t k = 0; k < K; ++k) {
+        const uint32_t w = f[(size_t)(v * K + k)];
+        const int32_t m = (int32_t)((w >> 21) & 3u);
+        if (sel_m) sel_m[i * K + k] = m;
+        if (sel_nbr)
+          for (int q = 0; q < 3; ++q) {
+            const uint32_t s = (w >> (7 * q)) & 127u;
+            sel_nbr[(i * K + k) * 3 + q] =
+                (q < m) ? g->perm[(size_t)g->nbr_h[(size_t)(rb + (int32_t)s)]] : -1;
+          }
+      }
+    }
+  }
+  if (edge_bin && E > 0) {
+    std::vector<uint8_t> eb((size_t)E);
+    HIP_TRY(ctx, hipMemcpyAsync(eb.data(), h.ebin, E, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    for (int64_t p = 0; p < E; ++p) edge_bin[p] = eb[(size_t)g->orig_to_new_e[(size_t)p]];
+  }
+  if (dL || tau)
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t v = g->inv[(size_t)i];
+      if (dL) dL[i] = g->dL_h[(size_t)v];
+      if (tau) tau[i] = g->tau_h[(size_t)v];
+    }
+  return SX_OK;
+}
+
+int sx_grid_info(sx_ctx *ctx, sx_grid_id id, int64_t *n, int32_t *k, int64_t *n_edges,
+                 int32_t *precision, double *photon_unit, uint64_t *bytes) {
+  if (!ctx) return SX_EINVAL;
+  Grid *g = find(ctx, id);
+  if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
+  if (n) *n = g->hg.n;
+  if (k) *k = g->hg.k;
+  if (n_edges) *n_edges = g->hg.n_edges;
+  if (precision) *precision = g->hg.precision;
+  if (photon_unit) *photon_unit = g->hg.unit;
+  if (bytes) *bytes = g->bytes;
+  return SX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// sx_internal.h -- device-side grid description shared by the host code and
+// the HIP kernels of libsx.  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sx {
+
+constexpr int kTile = 64;           // vertices per tile = one wavefront
+constexpr int kTilesPerBlock = 4;   // waves per workgroup of the sweep kernel
+constexpr int kEmptySlot = 127;     // unused slot marker in packed tables
+
+// In-word of a (vertex, bin) pair: which neighbours send this bin here.
+//   bits 0..2  : entries held in the word (0..4)
+//   bit  3     : more entries follow in the vertex's overflow list
+//   bits 4..31 : four 7-bit slots into the receiver's neighbour row,
+//                ascending (so the sum runs in ascending sender id)
+// Forward word of a (vertex, bin) pair (selection result):
+//   bits 0..20 : three 7-bit slots, best first (127 = none)
+//   bits 21..22: m, the number selected
+// Overflow entry (uint16): bin << 7 | slot.
+
+// Everything a kernel needs to know about one grid.  Lives in device memory
+// (an array of these for a batch); kernels read it through scalar loads.
+struct GridDev {
+  int32_t n;          // vertices
+  int32_t npad;       // vertices rounded up to kTile
+  int32_t ntiles;     // npad / kTile
+  int32_t k;          // bins
+  int32_t kw;         // ceil(k / 16): words of packed m per lane and tile
+  int32_t n_sub;      // chemistry substeps
+  int32_t mpb;        // max neighbours per bin
+  int32_t precision;  // 0 fp64, 1 fp32 transport
+  // mutable per-step control (advanced by sx_advance)
+  int32_t parity;     // O buffer holding the current field
+  int32_t remaining;  // steps still to run in the current request
+  int64_t sweeps;     // steps done
+  double unit;        // photons per stored unit (power of two)
+  double dt;
+  double cos_min;
+  int64_t plane;      // elements per bin plane of O (= npad)
+  int64_t n_edges;
+  // graph (reordered)
+  const int32_t *row_ptr;   // [npad+1]
+  const int32_t *nbr;       // [E] new ids, each row sorted by original id
+  const uint8_t *rev;       // [E] slot of the row's vertex in the neighbour's row
+  const double *edir;       // [3E] unit edge vectors
+  const double *bins;       // [3K]
+  // selection products
+  uint32_t *fwd;            // [npad*K]
+  uint8_t *ebin;            // [E]
+  uint32_t *inword;         // [ntiles][K][64]
+  uint32_t *mbits;          // [ntiles][kw][64]
+  int32_t *ovf_cnt;         // [npad+1] scratch: extras per vertex, then offsets
+  int32_t *ovf_ptr;         // [npad+1]
+  uint16_t *ovf;            // [n_ovf]
+  int64_t ovf_cap;
+  // sources (per receiving vertex)
+  const int32_t *em_ptr;    // [npad+1]
+  const int32_t *em_k;      // [n_em]
+  const double *em_amt;     // [n_em] photons / unit
+  // chemistry coefficients
+  const double *tau;        // [npad] n_H sigma dL
+  const double *dtnhv;      // [npad] dt * n_H * V
+  const double *bcoef;      // [npad] alpha_B * n_H
+  double *y;                // [npad] neutral fraction
+  double *nin;              // [npad] photons in, last step
+  void *o[2];               // [K*npad] fp32 or fp64 planes
+  double *tally;            // [ntiles*3] absorbed (cum), escaped (cum), in flight
+};
+
+// Kernel launchers (sx_kernels.hip).  All enqueue on `stream`, return the
+// HIP error of the launch.
+hipError_t launch_select(const GridDev *dg, const GridDev &hg, hipStream_t s);
+hipError_t launch_edge_bins(const GridDev *dg, const GridDev &hg, hipStream_t s);
+hipError_t launch_inlist_count(const GridDev *dg, const GridDev &hg, hipStream_t s);
+hipError_t launch_scan(int32_t *cnt, int32_t *ptr, int32_t n, hipStream_t s);
+hipError_t launch_inlist_fill(const GridDev *dg, const GridDev &hg, hipStream_t s);
+hipError_t launch_reset_state(GridDev *dg, const GridDev &hg, const double *y0,
+                              hipStream_t s);
+// One step for a batch: `grids` is the slot table (or one grid's entry when
+// tile_map is NULL); tile_map[t] = (slot, tile within that grid).
+hipError_t launch_sweep(const GridDev *grids, const int2 *tile_map,
+                        int32_t n_tiles, int32_t kmax_bucket, int32_t precision,
+                        hipStream_t s);
+// Slot-table updates: slots[i] indexes `table`.
+hipError_t launch_advance(GridDev *table, const int32_t *slots, int32_t n,
+                          hipStream_t s);
+hipError_t launch_set_remaining(GridDev *table, const int32_t *slots,
+                                const int32_t *values, int32_t n, int32_t add,
+                                hipStream_t s);
+
+int kmax_bucket(int k, int precision);   // 0 if unsupported
+
+}  // namespace sx

@@ -1,0 +1,361 @@
+"""Python binding of libsx (include/sx.h): argument marshalling only.
+
+Every function below has the name of the C entry point it calls.  All
+transport and chemistry run inside libsx's HIP kernels; this module only
+packs host arrays into the C structs and unpacks results.  PyTorch is used
+(optionally) for the HIP stream and as the device-memory allocator.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsx.so")
+
+SX_OK = 0
+SX_EINVAL = -1
+SX_ENOMEM = -2
+SX_EDEVICE = -3
+SX_ENOTFOUND = -4
+SX_ENOTSUP = -5
+SX_FP64 = 0
+SX_FP32_TRANSPORT = 1
+
+EXPORTED = [
+    "sx_init", "sx_finalize", "sx_grid_bytes", "sx_grid_upload",
+    "sx_grid_reset", "sx_grid_restore", "sx_grid_free", "sx_step",
+    "sx_solve", "sx_sync", "sx_read_state", "sx_read_tables",
+    "sx_grid_info", "sx_mem_info", "sx_stream", "sx_strerror",
+    "sx_last_error",
+]
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class SxCtxOpts(C.Structure):
+    _fields_ = [("device", C.c_int32), ("reserved0", C.c_int32),
+                ("hbm_budget", C.c_uint64), ("stream", C.c_void_p),
+                ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_user", C.c_void_p)]
+
+
+class SxGridDesc(C.Structure):
+    _fields_ = [
+        ("n_vertices", C.c_int64), ("pos", C.c_void_p),
+        ("nbr_ptr", C.c_void_p), ("nbr_idx", C.c_void_p),
+        ("n_H", C.c_void_p), ("volume", C.c_void_p), ("dL", C.c_void_p),
+        ("kappa", C.c_double), ("x_init", C.c_void_p),
+        ("n_bins", C.c_int32), ("max_per_bin", C.c_int32),
+        ("bin_dirs", C.c_void_p), ("cos_min", C.c_double),
+        ("n_src", C.c_int32), ("n_subcycles", C.c_int32),
+        ("src_vertex", C.c_void_p), ("src_rate", C.c_void_p),
+        ("src_dir", C.c_void_p), ("sigma", C.c_double),
+        ("alpha_B", C.c_double), ("dt", C.c_double),
+        ("precision", C.c_int32), ("reserved1", C.c_int32)]
+
+
+class SxTally(C.Structure):
+    _fields_ = [("sweeps", C.c_double), ("emitted", C.c_double),
+                ("absorbed", C.c_double), ("escaped", C.c_double),
+                ("in_flight", C.c_double)]
+
+
+class SxStateOut(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p),
+                ("photons", C.c_void_p), ("nin", C.c_void_p),
+                ("tally", C.POINTER(SxTally))]
+
+
+class SxStateIn(C.Structure):
+    _fields_ = [("y", C.c_void_p), ("photons", C.c_void_p),
+                ("tally", C.POINTER(SxTally))]
+
+
+class SxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: Optional[str] = None):
+    """Load libsx.so.  Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(
+            f"libsx.so not found at {p}; build it with "
+            "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = C.CDLL(p)
+    P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+    sig = {
+        "sx_init": (C.c_int, [C.POINTER(P), C.POINTER(SxCtxOpts)]),
+        "sx_finalize": (C.c_int, [P]),
+        "sx_grid_bytes": (C.c_int, [C.POINTER(SxGridDesc), C.POINTER(C.c_uint64)]),
+        "sx_grid_upload": (C.c_int, [P, C.POINTER(SxGridDesc), C.POINTER(I64)]),
+        "sx_grid_reset": (C.c_int, [P, I64]),
+        "sx_grid_restore": (C.c_int, [P, I64, C.POINTER(SxStateIn)]),
+        "sx_grid_free": (C.c_int, [P, I64]),
+        "sx_step": (C.c_int, [P, P, I32, I32]),
+        "sx_solve": (C.c_int, [P, P, I32, P]),
+        "sx_sync": (C.c_int, [P]),
+        "sx_read_state": (C.c_int, [P, I64, C.POINTER(SxStateOut)]),
+        "sx_read_tables": (C.c_int, [P, I64, P, P, P, P, P]),
+        "sx_grid_info": (C.c_int, [P, I64, P, P, P, P, P, P]),
+        "sx_mem_info": (C.c_int, [P, P, P]),
+        "sx_stream": (P, [P]),
+        "sx_strerror": (C.c_char_p, [C.c_int]),
+        "sx_last_error": (C.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _check(ctx, rc):
+    if rc != SX_OK:
+        lib = load()
+        msg = lib.sx_last_error(ctx).decode() if ctx else lib.sx_strerror(rc).decode()
+        raise SxError(rc, msg or lib.sx_strerror(rc).decode())
+
+
+# ------------------------------------------------------------- desc ----
+
+class _Desc:
+    """An SxGridDesc plus the numpy arrays its pointers refer to."""
+
+    def __init__(self, w):
+        f64 = lambda a: None if a is None else np.ascontiguousarray(a, np.float64)
+        self.arrays = dict(
+            pos=f64(w.pos), ptr=np.ascontiguousarray(w.nbr_ptr, np.int64),
+            idx=np.ascontiguousarray(w.nbr_idx, np.int32), nH=f64(w.n_H),
+            vol=f64(w.volume), dL=f64(w.dL), x0=f64(w.x_init),
+            bins=f64(w.bin_dirs), sv=np.ascontiguousarray(w.src_vertex, np.int32),
+            sr=f64(w.src_rate), sd=f64(w.src_dir))
+        a = self.arrays
+        self.c = SxGridDesc(
+            n_vertices=w.n, pos=_ptr(a["pos"]), nbr_ptr=_ptr(a["ptr"]),
+            nbr_idx=_ptr(a["idx"]), n_H=_ptr(a["nH"]), volume=_ptr(a["vol"]),
+            dL=_ptr(a["dL"]), kappa=float(w.kappa), x_init=_ptr(a["x0"]),
+            n_bins=w.k, max_per_bin=int(w.max_per_bin), bin_dirs=_ptr(a["bins"]),
+            cos_min=float(w.cos_min), n_src=int(a["sv"].shape[0]),
+            n_subcycles=int(w.n_subcycles), src_vertex=_ptr(a["sv"]),
+            src_rate=_ptr(a["sr"]), src_dir=_ptr(a["sd"]), sigma=float(w.sigma),
+            alpha_B=float(w.alpha_B), dt=float(w.dt), precision=int(w.precision),
+            reserved1=0)
+
+
+# ------------------------------------------------------ C entry points ----
+
+def sx_init(device: int = 0, hbm_budget: int = 0, stream: Optional[int] = None,
+            use_torch_allocator: bool = False):
+    """Create a context.  Returns (ctx_handle, keepalive)."""
+    lib = load()
+    keep = []
+    opts = SxCtxOpts(device=device, reserved0=0, hbm_budget=hbm_budget,
+                     stream=stream, alloc=ALLOC_FN(), free=FREE_FN(),
+                     alloc_user=None)
+    if use_torch_allocator:
+        import torch
+
+        def _alloc(nbytes, _user):
+            try:
+                s = torch.cuda.current_stream(device)
+                return int(torch.cuda.caching_allocator_alloc(int(nbytes), device, s))
+            except Exception:
+                return None
+
+        def _free(ptr, _user):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        fa, ff = ALLOC_FN(_alloc), FREE_FN(_free)
+        keep += [fa, ff]
+        opts.alloc, opts.free = fa, ff
+    h = C.c_void_p()
+    rc = lib.sx_init(C.byref(h), C.byref(opts))
+    _check(None, rc)
+    return h, keep
+
+
+def sx_finalize(ctx) -> None:
+    load().sx_finalize(ctx)
+
+
+def sx_grid_bytes(w) -> int:
+    d = _Desc(w)
+    b = C.c_uint64()
+    _check(None, load().sx_grid_bytes(C.byref(d.c), C.byref(b)))
+    return int(b.value)
+
+
+def sx_grid_upload(ctx, w) -> int:
+    d = _Desc(w)
+    gid = C.c_int64()
+    _check(ctx, load().sx_grid_upload(ctx, C.byref(d.c), C.byref(gid)))
+    return int(gid.value)
+
+
+def sx_grid_reset(ctx, gid: int) -> None:
+    _check(ctx, load().sx_grid_reset(ctx, gid))
+
+
+def sx_grid_free(ctx, gid: int) -> None:
+    _check(ctx, load().sx_grid_free(ctx, gid))
+
+
+def sx_step(ctx, ids: Sequence[int], n_sweeps: int) -> None:
+    a = np.ascontiguousarray(ids, np.int64)
+    _check(ctx, load().sx_step(ctx, _ptr(a), int(a.shape[0]), int(n_sweeps)))
+
+
+def sx_solve(ctx, ids: Sequence[int], n_sweeps) -> None:
+    a = np.ascontiguousarray(ids, np.int64)
+    s = np.broadcast_to(np.asarray(n_sweeps, np.int32), a.shape).copy()
+    _check(ctx, load().sx_solve(ctx, _ptr(a), int(a.shape[0]), _ptr(s)))
+
+
+def sx_sync(ctx) -> None:
+    _check(ctx, load().sx_sync(ctx))
+
+
+def sx_read_state(ctx, gid: int, n: int, k: int, photons: bool = False,
+                  nin: bool = True) -> dict:
+    y = np.zeros(n)
+    x = np.zeros(n)
+    ph = np.zeros((n, k)) if photons else None
+    ni = np.zeros(n) if nin else None
+    t = SxTally()
+    out = SxStateOut(x=_ptr(x), y=_ptr(y), photons=_ptr(ph), nin=_ptr(ni),
+                     tally=C.pointer(t))
+    _check(ctx, load().sx_read_state(ctx, gid, C.byref(out)))
+    return dict(x=x, y=y, photons=ph, nin=ni,
+                tallies=dict(sweeps=t.sweeps, emitted=t.emitted,
+                             absorbed=t.absorbed, escaped=t.escaped,
+                             in_flight=t.in_flight))
+
+
+def sx_grid_restore(ctx, gid: int, y=None, photons=None, tallies=None) -> None:
+    ya = None if y is None else np.ascontiguousarray(y, np.float64)
+    pa = None if photons is None else np.ascontiguousarray(photons, np.float64)
+    tp = None
+    if tallies is not None:
+        tp = C.pointer(SxTally(**{k: float(tallies[k]) for k in
+                                  ("sweeps", "emitted", "absorbed", "escaped", "in_flight")}))
+    si = SxStateIn(y=_ptr(ya), photons=_ptr(pa), tally=tp)
+    _check(ctx, load().sx_grid_restore(ctx, gid, C.byref(si)))
+
+
+def sx_read_tables(ctx, gid: int, n: int, k: int, n_edges: int) -> dict:
+    sel = np.zeros((n, k, 3), np.int32)
+    m = np.zeros((n, k), np.int32)
+    eb = np.zeros(n_edges, np.int32)
+    dL = np.zeros(n)
+    tau = np.zeros(n)
+    _check(ctx, load().sx_read_tables(ctx, gid, _ptr(sel), _ptr(m), _ptr(eb),
+                                      _ptr(dL), _ptr(tau)))
+    return dict(sel_nbr=sel, sel_m=m, edge_bin=eb, dL=dL, tau=tau)
+
+
+def sx_grid_info(ctx, gid: int) -> dict:
+    n = C.c_int64()
+    k = C.c_int32()
+    e = C.c_int64()
+    p = C.c_int32()
+    u = C.c_double()
+    b = C.c_uint64()
+    _check(ctx, load().sx_grid_info(ctx, gid, C.byref(n), C.byref(k), C.byref(e),
+                                    C.byref(p), C.byref(u), C.byref(b)))
+    return dict(n=n.value, k=k.value, n_edges=e.value, precision=p.value,
+                photon_unit=u.value, bytes=b.value)
+
+
+def sx_mem_info(ctx) -> tuple[int, int]:
+    u = C.c_uint64()
+    b = C.c_uint64()
+    _check(ctx, load().sx_mem_info(ctx, C.byref(u), C.byref(b)))
+    return int(u.value), int(b.value)
+
+
+def sx_stream(ctx) -> int:
+    return int(load().sx_stream(ctx) or 0)
+
+
+# ------------------------------------------------------ convenience ----
+
+class Context:
+    """RAII wrapper: a context plus uploaded grids keyed by id."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0,
+                 stream: Optional[int] = None, use_torch_allocator: bool = False):
+        self.h, self._keep = sx_init(device, hbm_budget, stream, use_torch_allocator)
+        self.shapes = {}
+
+    def upload(self, w) -> int:
+        gid = sx_grid_upload(self.h, w)
+        self.shapes[gid] = (w.n, w.k, w.n_edges)
+        return gid
+
+    def reset(self, gid):
+        sx_grid_reset(self.h, gid)
+
+    def step(self, ids, n_sweeps):
+        sx_step(self.h, ids, n_sweeps)
+
+    def solve(self, ids, n_sweeps):
+        sx_solve(self.h, ids, n_sweeps)
+
+    def sync(self):
+        sx_sync(self.h)
+
+    def state(self, gid, photons=False, nin=True):
+        n, k, _ = self.shapes[gid]
+        return sx_read_state(self.h, gid, n, k, photons=photons, nin=nin)
+
+    def restore(self, gid, **kw):
+        sx_grid_restore(self.h, gid, **kw)
+
+    def tables(self, gid):
+        n, k, e = self.shapes[gid]
+        return sx_read_tables(self.h, gid, n, k, e)
+
+    def info(self, gid):
+        return sx_grid_info(self.h, gid)
+
+    def free(self, gid):
+        sx_grid_free(self.h, gid)
+        self.shapes.pop(gid, None)
+
+    def mem_info(self):
+        return sx_mem_info(self.h)
+
+    @property
+    def stream(self) -> int:
+        return sx_stream(self.h)
+
+    def close(self):
+        if self.h:
+            sx_finalize(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

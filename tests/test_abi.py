@@ -1,0 +1,122 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/sx.h declares, the ctypes structs match the C
+layout, and the oracle and the library stay separate."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_0912_4273_amd import sx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sx.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(sx_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for must in ("sx_grid_upload", "sx_step", "sx_solve", "sx_read_state"):
+        assert must in names
+    assert set(names) == set(sx.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = sx.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", sx.LIB_PATH],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (sx_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_error_strings():
+    lib = sx.load()
+    assert lib.sx_strerror(sx.SX_EINVAL) == b"invalid argument"
+    assert lib.sx_strerror(sx.SX_ENOMEM).startswith(b"out of device memory")
+    assert lib.sx_last_error(None) == b"null context"
+
+
+def test_null_arguments_rejected_without_device():
+    lib = sx.load()
+    assert lib.sx_init(None, None) == sx.SX_EINVAL
+    assert lib.sx_step(None, None, 0, 1) == sx.SX_EINVAL
+    assert lib.sx_finalize(None) == sx.SX_OK
+    b = C.c_uint64()
+    assert lib.sx_grid_bytes(None, C.byref(b)) == sx.SX_EINVAL
+
+
+def _c_layout():
+    """offsetof/sizeof of the ABI structs as the C compiler sees them."""
+    src = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "sx.h"
+#define P(s, f) printf(#s "." #f " %zu\n", offsetof(s, f));
+int main(void) {
+  printf("sx_grid_desc %zu\n", sizeof(sx_grid_desc));
+  printf("sx_ctx_opts %zu\n", sizeof(sx_ctx_opts));
+  printf("sx_state_out %zu\n", sizeof(sx_state_out));
+  printf("sx_tally %zu\n", sizeof(sx_tally));
+  P(sx_grid_desc, kappa) P(sx_grid_desc, n_bins) P(sx_grid_desc, cos_min)
+  P(sx_grid_desc, src_dir) P(sx_grid_desc, dt) P(sx_grid_desc, precision)
+  P(sx_ctx_opts, stream) P(sx_ctx_opts, alloc_user)
+  return 0;
+}
+"""
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "l.c")
+        exe = os.path.join(d, "l")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    return dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
+
+
+def test_ctypes_struct_layout_matches_c():
+    lay = {k: int(v) for k, v in _c_layout().items()}
+    assert C.sizeof(sx.SxGridDesc) == lay["sx_grid_desc"]
+    assert C.sizeof(sx.SxCtxOpts) == lay["sx_ctx_opts"]
+    assert C.sizeof(sx.SxStateOut) == lay["sx_state_out"]
+    assert C.sizeof(sx.SxTally) == lay["sx_tally"]
+    for f in ("kappa", "n_bins", "cos_min", "src_dir", "dt", "precision"):
+        assert getattr(sx.SxGridDesc, f).offset == lay[f"sx_grid_desc.{f}"], f
+    for f in ("stream", "alloc_user"):
+        assert getattr(sx.SxCtxOpts, f).offset == lay[f"sx_ctx_opts.{f}"], f
+
+
+def test_oracle_and_library_share_no_code():
+    """The oracle is independent of the HIP path: neither includes or
+    imports the other."""
+    csrc = os.path.join(ROOT, "paper_0912_4273_amd", "csrc")
+    for f in os.listdir(csrc):
+        txt = open(os.path.join(csrc, f)).read()
+        assert "oracle" not in txt.lower(), f
+    for f in ("sx_oracle.c", "sx_oracle.h", "oracle.py"):
+        txt = open(os.path.join(ROOT, "oracle", f)).read()
+        assert "sx.h" not in txt and "sx_internal" not in txt
+        assert "paper_0912_4273_amd" not in txt
+    for f in os.listdir(os.path.join(ROOT, "paper_0912_4273_amd")):
+        if f.endswith(".py"):
+            txt = open(os.path.join(ROOT, "paper_0912_4273_amd", f)).read()
+            assert "import oracle" not in txt and "from oracle" not in txt, f
+
+
+def test_product_fails_loudly_without_library(tmp_path):
+    with pytest.raises(RuntimeError, match="libsx.so not found"):
+        sx.load(str(tmp_path / "libsx.so"))
+
+
+def test_gridgen_has_no_method_arithmetic():
+    """The shared input generator holds no transport or chemistry step."""
+    txt = open(os.path.join(ROOT, "paper_0912_4273_amd", "gridgen.py")).read()
+    for word in ("expm1", "exp(-", "argmax", "most_straightforward"):
+        assert word not in txt
