@@ -121,11 +121,16 @@ static double be_substep(double y0, double ha, double hb, double tau) {
         if (g == 0.0) return yn;
         if (g > 0.0) lo = yn; else hi = yn;
         double gp = -1.0 - ha * tau * exp(-yn * tau) - 2.0 * hb * x;
-        double yc = yn - g / gp;
+        double d = g / gp;
+        /* Newton has converged when its step is within rounding of y */
+        if (fabs(d) <= 4.0e-16 * yn) {
+            double yc = yn - d;
+            return yc < 0.0 ? 0.0 : (yc > 1.0 ? 1.0 : yc);
+        }
+        double yc = yn - d;
         if (!(yc > lo && yc < hi)) yc = 0.5 * (lo + hi);
-        double step = fabs(yc - yn);
         yn = yc;
-        if (step <= 4.0e-16 * yn || hi - lo <= 4.0e-16 * hi) break;
+        if (hi - lo <= 4.0e-16 * hi) break;
     }
     return yn;
 }
