@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Throughput of the SimpleX2 direction-conserving transport + hydrogen
+chemistry step on one MI355X, in vertex-direction updates per second.
+
+A step is one whole solve of the Stromgren problem on a resident grid:
+device-side re-selection of the bin tables and gather lists, state reset,
+`--sweeps` radiative-transfer steps (fused gather / chemistry / outgoing
+kernel each), and read-back of the ionised fraction and photon tallies.
+One update advances one (vertex, bin) pair by one sweep.
+
+Prints one JSON line (see the end of main()).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, GB/s
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_update(k: int, photon_bytes: int) -> float:
+    """What the method must move per vertex-direction update with perfect
+    reuse: read + write one photon word, ~2 B of routing (three 6-bit
+    slots), and ~110 B of per-vertex data (neutral fraction read + write,
+    transmission, three chemistry coefficients, one CSR row of ~15.5
+    neighbours) shared by the K bins."""
+    return 2.0 * photon_bytes + 2.0 + 110.0 / k
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_0912_4273_amd", "csrc", "sx_kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    e = d.get(workload)
+    if not e or e.get("kernel_sha") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(w, sweeps: int):
+    """The FP64 oracle (single thread) on the same grid, from the initial
+    state, for a bounded number of sweeps."""
+    from oracle import Oracle
+    o = Oracle(w)
+    t0 = time.perf_counter()
+    o.run(sweeps)
+    dt = time.perf_counter() - t0
+    return dict(value=w.n * w.k * sweeps / dt, unit="vertex·direction updates/s",
+                cores=1, kind="oracle",
+                sample=f"{sweeps} sweeps of the same {w.n}-vertex, {w.k}-bin grid "
+                       f"from the neutral initial state, FP64, one thread "
+                       f"({dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=262144)
+    ap.add_argument("--bins", type=int, default=84)
+    ap.add_argument("--sweeps", type=int, default=1000)
+    ap.add_argument("--cpu-sweeps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not "
+              "supported (independent grids shard across GPUs with no exchange, "
+              "see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_0912_4273_amd import gridgen as G
+    from paper_0912_4273_amd import sx
+
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.init()
+
+    t = time.perf_counter()
+    w = G.stromgren_test(args.n, seed=2, n_bins=args.bins, bins_seed=102,
+                         n_sweeps=args.sweeps, precision=G.SX_FP32_TRANSPORT,
+                         name=f"stromgren_{args.n}_k{args.bins}")
+    log(f"grid {w.n} vertices, {w.n_edges} directed edges, built in "
+        f"{time.perf_counter() - t:.1f} s")
+    workload = f"stromgren_{w.n}_k{w.k}_{args.sweeps}sweeps"
+
+    stream = torch.cuda.Stream(device=dev)
+    ctx = sx.Context(device=0, stream=stream.cuda_stream, use_torch_allocator=True)
+
+    def upload(wl):
+        t0 = time.perf_counter()
+        gid = ctx.upload(wl)
+        return gid, time.perf_counter() - t0
+
+    def one_step(gid):
+        ctx.reset(gid)
+        ctx.step([gid], args.sweeps)
+        return ctx.state(gid, nin=False)
+
+    def timed(gid, steps, warmup):
+        for _ in range(warmup):
+            one_step(gid)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read()
+        t0 = time.perf_counter()
+        st = None
+        for _ in range(steps):
+            st = one_step(gid)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        return el, prof, st
+
+    # ---- FP32 transport + FP64 chemistry (headline)
+    gid, up_s = upload(w)
+    log(f"uploaded fp32 grid in {up_s:.2f} s")
+    el, prof, st32 = timed(gid, args.steps, args.warmup)
+    ups = w.n * w.k * args.sweeps * args.steps / el
+    ms_step = 1e3 * el / args.steps
+    kern_ms = prof["total_ms"] / max(prof["launches"], 1)
+    log(f"fp32: {ms_step:.1f} ms/step, {ups:.3e} updates/s, sweep kernel "
+        f"{1e3 * kern_ms:.1f} us avg over {prof['launches']} launches")
+    t32 = st32["tallies"]
+    resid = abs(t32["emitted"] - (t32["absorbed"] + t32["escaped"] + t32["in_flight"])) \
+        / t32["emitted"]
+    ctx.free(gid)
+
+    # ---- plain single-grid FP64 on the same GPU
+    fp64 = None
+    if not args.no_fp64:
+        w64 = G.with_(w, precision=G.SX_FP64)
+        gid64, _ = upload(w64)
+        el64, prof64, st64 = timed(gid64, 1, 1)
+        ups64 = w.n * w.k * args.sweeps / el64
+        k64 = prof64["total_ms"] / max(prof64["launches"], 1)
+        fp64 = dict(value=ups64, ms_per_step=1e3 * el64, sweep_kernel_us=1e3 * k64)
+        ctx.free(gid64)
+
+    bpu = algorithmic_bytes_per_update(w.k, 4)
+    bytes_launch = bpu * w.n * w.k
+    achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=measured_traffic(workload))
+
+    # ---- physics / accuracy of the fp32 run
+    box = w.box
+    r_s = (3 * w.meta["rate"] / (4 * math.pi * w.alpha_B * w.meta["n_H"] ** 2)) ** (1 / 3)
+    t_rec = 1.0 / (w.alpha_B * w.meta["n_H"])
+    t_end = args.sweeps * w.dt
+    rv32 = (3 / (4 * math.pi) * float(np.sum(w.volume * st32["x"]))) ** (1 / 3)
+    acc = dict(front_radius_over_analytic=round(rv32 / (r_s * (1 - math.exp(-t_end / t_rec)) ** (1 / 3)), 4),
+               conservation_residual=resid)
+    if fp64 is not None:
+        rv64 = (3 / (4 * math.pi) * float(np.sum(w.volume * st64["x"]))) ** (1 / 3)
+        acc["fp32_vs_fp64_front_radius_rel"] = abs(rv32 / rv64 - 1)
+        acc["fp32_vs_fp64_max_abs_x"] = float(np.max(np.abs(st32["x"] - st64["x"])))
+
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: 3 x 1 GiB")
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"cpu oracle: {args.cpu_sweeps} sweeps")
+        cpu = cpu_baseline(G.with_(w, precision=G.SX_FP64), args.cpu_sweeps)
+
+    ctx.close()
+    out = {
+        "metric": "vertex·direction updates/s (batched FP32 vs plain FP64) + p50/p99 solve latency",
+        "value": ups,
+        "unit": "vertex·direction updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 transport, f64 chemistry",
+        "data": "synthetic",
+        "config": {"workload": workload, "vertices": w.n, "bins": w.k,
+                   "sweeps_per_step": args.sweeps, "precision": "fp32_transport",
+                   "physics": "Stromgren test: n_H 1e-3, 5e48 photons/s, 13.2 kpc box, 500 Myr"},
+        "fp64_plain": fp64,
+        "upload_s": up_s,
+        "sweep_kernel_us": 1e3 * kern_ms,
+        "roofline": roof,
+        "algorithmic_bytes_per_update": bpu,
+        "accuracy": acc,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -212,6 +212,15 @@ int sx_mem_info(sx_ctx *ctx, uint64_t *used, uint64_t *budget);
 /* The hipStream_t the context enqueues on. */
 void *sx_stream(sx_ctx *ctx);
 
+/* Kernel timing.  With enable != 0, every step-kernel launch (the fused
+ * sweep) is bracketed by a pair of HIP events on the context stream;
+ * sx_profile_read waits for them and returns the number of launches timed
+ * since the last read and the total, shortest and longest duration in
+ * milliseconds, then starts a new count.  Any out-pointer may be NULL. */
+int sx_profile(sx_ctx *ctx, int32_t enable);
+int sx_profile_read(sx_ctx *ctx, int64_t *launches, double *total_ms,
+                    double *min_ms, double *max_ms);
+
 const char *sx_strerror(int code);
 const char *sx_last_error(const sx_ctx *ctx);
 

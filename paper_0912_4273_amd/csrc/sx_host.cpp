@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -53,6 +54,7 @@ struct Grid {
   double e_sweep = 0.0;     // photons emitted per step
   double esc_emit = 0.0;    // photons per step with no way out of a beam source
   double base_sweeps = 0.0, base_emitted = 0.0, base_escaped = 0.0;
+  int64_t n_direct = 0;     // tiles whose halo is too large for LDS staging
 };
 
 struct BatchCache {
@@ -79,6 +81,9 @@ struct sx_ctx {
   std::string err;
   bool poisoned = false;
   std::vector<BatchCache> batches;
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;   // pool
+  size_t ev_used = 0;
 };
 
 namespace {
@@ -333,14 +338,15 @@ Sizes sizes_of(const sx_grid_desc *d) {
 
 uint64_t rnd(uint64_t b) { return (b + 255) & ~uint64_t(255); }
 
-uint64_t bytes_estimate(const Sizes &s, int64_t n_em, int64_t n_ovf) {
+uint64_t bytes_estimate(const Sizes &s, int64_t n_em, int64_t n_rec, int64_t n_halo) {
   uint64_t b = 0;
   b += rnd(4 * (s.npad + 1)) + rnd(4 * s.E) + rnd(s.E) + rnd(24 * s.E) + rnd(24 * s.K);
-  b += rnd(4 * s.npad * s.K) + rnd(s.E) + rnd(4 * s.npad * s.K) +
-       rnd(4 * s.npad * s.kw) + 2 * rnd(4 * (s.npad + 1)) + rnd(2 * n_ovf + 2);
+  b += rnd(4 * s.npad * s.K) + rnd(s.E) + rnd(8 * s.npad * s.K) +
+       rnd(4 * s.npad * s.kw) + 2 * rnd(4 * (s.ntiles * s.K + 1)) + rnd(2 * n_rec + 2);
+  b += rnd(4 * (s.ntiles + 1)) + rnd(4 * n_halo + 4) + rnd(2 * s.E) + rnd(s.ntiles);
   b += rnd(4 * (s.npad + 1)) + rnd(4 * n_em + 4) + rnd(8 * n_em + 8);
   b += 6 * rnd(8 * s.npad);
-  b += 2 * rnd((uint64_t)s.sp * s.K * s.npad);
+  b += 2 * rnd((uint64_t)s.sp * s.K * (s.npad + sx::kTile));
   b += rnd(24 * s.ntiles);
   return b;
 }
@@ -357,14 +363,16 @@ int write_slot(sx_ctx *ctx, Grid *g) {
   return SX_OK;
 }
 
-// (Re)build the selection products of a grid on the device; the overflow
-// pool must already be sized (ovf_cap).
+// (Re)build the selection products of a grid on the device; the record
+// pool must already be sized (rec_cap).
 int build_tables(sx_ctx *ctx, Grid *g) {
   GridDev *dg = ctx->table + g->slot;
+  const int32_t nrow = g->hg.ntiles * g->hg.k;
   HIP_TRY(ctx, sx::launch_select(dg, g->hg, ctx->stream));
   HIP_TRY(ctx, sx::launch_edge_bins(dg, g->hg, ctx->stream));
+  HIP_TRY(ctx, sx::launch_mbits(dg, g->hg, ctx->stream));
   HIP_TRY(ctx, sx::launch_inlist_count(dg, g->hg, ctx->stream));
-  HIP_TRY(ctx, sx::launch_scan(g->hg.ovf_cnt, g->hg.ovf_ptr, g->hg.npad, ctx->stream));
+  HIP_TRY(ctx, sx::launch_scan(g->hg.rec_cnt, g->hg.rec_ptr, nrow, ctx->stream));
   HIP_TRY(ctx, sx::launch_inlist_fill(dg, g->hg, ctx->stream));
   return SX_OK;
 }
@@ -440,6 +448,10 @@ int sx_finalize(sx_ctx *ctx) {
   for (auto &kv : ctx->grids) grid_release(ctx, kv.second);
   ctx->grids.clear();
   for (auto &b : ctx->batches) (void)hipFree(b.map);
+  for (auto &e : ctx->ev) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
   (void)hipFree(ctx->table);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -461,7 +473,9 @@ int sx_grid_bytes(const sx_grid_desc *d, uint64_t *bytes) {
   const Sizes s = sizes_of(d);
   // overflow entries: expect ~0.3 per (vertex, bin) on Poisson-Delaunay
   // grids; the exact pool is allocated after the count pass
-  *bytes = bytes_estimate(s, s.E, (int64_t)(0.5 * (double)(s.npad * s.K)));
+  // records: ~0.02 per (vertex, bin) on Poisson-Delaunay grids; halos
+  // ~4 vertices per tile vertex.  The exact pools are allocated at upload.
+  *bytes = bytes_estimate(s, s.E, (int64_t)(0.05 * (double)(s.npad * s.K)), 5 * s.npad);
   return SX_OK;
 }
 
@@ -553,6 +567,44 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
       rev[(size_t)e] = (uint8_t)(it - b);
     }
   }
+  // ---- tile halos: every neighbour of a tile's vertices, ascending; the
+  // index of each edge's target in its tile's halo.  Tiles with more than
+  // kHaloMax halo vertices gather directly (edge index = row slot).
+  const int64_t ntiles = S.ntiles;
+  std::vector<int32_t> halo_ptr((size_t)ntiles + 1, 0), halo_vid;
+  std::vector<uint16_t> edge_hidx((size_t)E, 0);
+  std::vector<uint8_t> tile_direct((size_t)ntiles, 0);
+  {
+    // SX_FORCE_DIRECT=1 makes every tile gather directly (a test knob for
+    // the path large-halo tiles take)
+    const char *fd = std::getenv("SX_FORCE_DIRECT");
+    const bool force_direct = fd && fd[0] == '1';
+    std::vector<int32_t> h;
+    for (int64_t t = 0; t < ntiles; ++t) {
+      const int64_t v0 = t * sx::kTile, v1 = std::min<int64_t>(v0 + sx::kTile, n);
+      h.clear();
+      for (int64_t v = v0; v < v1; ++v)
+        for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) h.push_back(g->nbr_h[(size_t)e]);
+      std::sort(h.begin(), h.end());
+      h.erase(std::unique(h.begin(), h.end()), h.end());
+      if ((int64_t)h.size() > sx::kHaloMax || force_direct) {
+        tile_direct[(size_t)t] = 1;
+        for (int64_t v = v0; v < v1; ++v)
+          for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e)
+            edge_hidx[(size_t)e] = (uint16_t)(e - rp[(size_t)v]);
+      } else {
+        for (int64_t v = v0; v < v1; ++v)
+          for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e)
+            edge_hidx[(size_t)e] = (uint16_t)(std::lower_bound(h.begin(), h.end(),
+                                                               g->nbr_h[(size_t)e]) - h.begin());
+        halo_vid.insert(halo_vid.end(), h.begin(), h.end());
+      }
+      halo_ptr[(size_t)t + 1] = (int32_t)halo_vid.size();
+    }
+  }
+  g->n_direct = 0;
+  for (auto d8 : tile_direct) g->n_direct += d8;
+
   // ---- per-vertex physics in new order
   std::vector<double> tau((size_t)npad, 0.0), dtnhv((size_t)npad, 1.0),
       bco((size_t)npad, 0.0), y0((size_t)npad, 1.0);
@@ -600,12 +652,14 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
   h.unit = unit;
   h.dt = d->dt;
   h.cos_min = d->cos_min;
-  h.plane = npad;
+  h.plane = npad + sx::kTile;   // the extra tile stays zero
   h.n_edges = E;
-  int32_t *d_rp, *d_nbr, *d_ovf_cnt, *d_ovf_ptr;
-  uint8_t *d_rev, *d_ebin;
+  int32_t *d_rp, *d_nbr, *d_rec_cnt, *d_rec_ptr, *d_hptr, *d_hvid;
+  uint8_t *d_rev, *d_ebin, *d_tdir;
+  uint16_t *d_ehidx;
   double *d_edir, *d_bins, *d_tau, *d_dtnhv, *d_b, *d_y, *d_nin, *d_y0, *d_tally;
-  uint32_t *d_fwd, *d_inw, *d_mb;
+  uint32_t *d_fwd, *d_mb;
+  uint64_t *d_inw;
   void *d_o0, *d_o1;
 #define GA(ptr, cnt)                                      \
   do {                                                    \
@@ -621,8 +675,12 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
   GA(d_ebin, E);
   GA(d_inw, npad * K);
   GA(d_mb, npad * S.kw);
-  GA(d_ovf_cnt, npad + 1);
-  GA(d_ovf_ptr, npad + 1);
+  GA(d_rec_cnt, ntiles * K + 1);
+  GA(d_rec_ptr, ntiles * K + 1);
+  GA(d_hptr, ntiles + 1);
+  GA(d_hvid, halo_vid.size() + 1);
+  GA(d_ehidx, E);
+  GA(d_tdir, ntiles);
   GA(d_tau, npad);
   GA(d_dtnhv, npad);
   GA(d_b, npad);
@@ -632,8 +690,8 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
   GA(d_tally, 3 * S.ntiles);
   {
     uint8_t *o0, *o1;
-    GA(o0, (uint64_t)S.sp * K * npad);
-    GA(o1, (uint64_t)S.sp * K * npad);
+    GA(o0, (uint64_t)S.sp * K * (npad + sx::kTile));
+    GA(o1, (uint64_t)S.sp * K * (npad + sx::kTile));
     d_o0 = o0;
     d_o1 = o1;
   }
@@ -644,12 +702,16 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
   h.bins = d_bins;
   h.fwd = d_fwd;
   h.ebin = d_ebin;
-  h.inword = d_inw;
+  h.inw = d_inw;
   h.mbits = d_mb;
-  h.ovf_cnt = d_ovf_cnt;
-  h.ovf_ptr = d_ovf_ptr;
-  h.ovf = nullptr;
-  h.ovf_cap = 0;
+  h.rec_cnt = d_rec_cnt;
+  h.rec_ptr = d_rec_ptr;
+  h.rec = nullptr;
+  h.rec_cap = 0;
+  h.halo_ptr = d_hptr;
+  h.halo_vid = d_hvid;
+  h.edge_hidx = d_ehidx;
+  h.tile_direct = d_tdir;
   h.tau = d_tau;
   h.dtnhv = d_dtnhv;
   h.bcoef = d_b;
@@ -684,6 +746,10 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
   UP(d_dtnhv, dtnhv.data(), 8 * npad);
   UP(d_b, bco.data(), 8 * npad);
   UP(d_y0, y0.data(), 8 * npad);
+  UP(d_hptr, halo_ptr.data(), 4 * (ntiles + 1));
+  UP(d_hvid, halo_vid.data(), 4 * halo_vid.size());
+  UP(d_ehidx, edge_hidx.data(), 2 * E);
+  UP(d_tdir, tile_direct.data(), ntiles);
   if (hipStreamSynchronize(st) != hipSuccess) {
     grid_release(ctx, g);
     return fail(ctx, SX_EDEVICE, "upload sync failed");
@@ -698,19 +764,21 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
     return fail(ctx, SX_EDEVICE, "table kernels failed: %s", hipGetErrorString(e));
   };
   hipError_t he;
+  const int32_t nrow = (int32_t)(ntiles * K);
   if ((he = sx::launch_select(dg, h, st)) != hipSuccess) return kfail(he);
   if ((he = sx::launch_edge_bins(dg, h, st)) != hipSuccess) return kfail(he);
+  if ((he = sx::launch_mbits(dg, h, st)) != hipSuccess) return kfail(he);
   if ((he = sx::launch_inlist_count(dg, h, st)) != hipSuccess) return kfail(he);
-  if ((he = sx::launch_scan(h.ovf_cnt, h.ovf_ptr, h.npad, st)) != hipSuccess) return kfail(he);
-  int32_t n_ovf = 0;
-  if ((he = hipMemcpyAsync(&n_ovf, h.ovf_ptr + npad, 4, hipMemcpyDeviceToHost, st)) != hipSuccess)
+  if ((he = sx::launch_scan(h.rec_cnt, h.rec_ptr, nrow, st)) != hipSuccess) return kfail(he);
+  int32_t n_rec = 0;
+  if ((he = hipMemcpyAsync(&n_rec, h.rec_ptr + nrow, 4, hipMemcpyDeviceToHost, st)) != hipSuccess)
     return kfail(he);
   if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
   {
-    uint16_t *d_ovf;
-    GA(d_ovf, (uint64_t)n_ovf + 1);
-    h.ovf = d_ovf;
-    h.ovf_cap = n_ovf;
+    uint16_t *d_rec;
+    GA(d_rec, (uint64_t)n_rec + 1);
+    h.rec = d_rec;
+    h.rec_cap = n_rec;
   }
   if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
   if ((he = sx::launch_inlist_fill(dg, h, st)) != hipSuccess) return kfail(he);
@@ -771,8 +839,10 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
     }
   }
   g->esc_emit = esc_emit;
-  std::stable_sort(em.begin(), em.end(),
-                   [](const Em &a, const Em &b) { return a.recv < b.recv; });
+  // per receiver, by bin; equal bins keep source order
+  std::stable_sort(em.begin(), em.end(), [](const Em &a, const Em &b) {
+    return a.recv != b.recv ? a.recv < b.recv : a.k < b.k;
+  });
   std::vector<int32_t> em_ptr((size_t)npad + 1, 0), em_k(em.size());
   std::vector<double> em_amt(em.size());
   for (size_t q = 0; q < em.size(); ++q) {
@@ -898,9 +968,22 @@ int launch_steps(sx_ctx *ctx, std::vector<Grid *> &gs, int32_t n_launch) {
   std::vector<int32_t> slots;
   for (Grid *g : gs) slots.push_back(g->slot);
   for (int32_t s = 0; s < n_launch; ++s) {
-    for (auto &l : launches)
+    for (auto &l : launches) {
+      std::pair<hipEvent_t, hipEvent_t> *ep = nullptr;
+      if (ctx->prof) {
+        if (ctx->ev_used == ctx->ev.size()) {
+          std::pair<hipEvent_t, hipEvent_t> e;
+          HIP_TRY(ctx, hipEventCreate(&e.first));
+          HIP_TRY(ctx, hipEventCreate(&e.second));
+          ctx->ev.push_back(e);
+        }
+        ep = &ctx->ev[ctx->ev_used++];
+        HIP_TRY(ctx, hipEventRecord(ep->first, ctx->stream));
+      }
       HIP_TRY(ctx, sx::launch_sweep(l.grids, l.map, l.n_tiles, l.kmax, l.precision,
                                     ctx->stream));
+      if (ep) HIP_TRY(ctx, hipEventRecord(ep->second, ctx->stream));
+    }
     HIP_TRY(ctx, sx::launch_advance(ctx->table, slots.data(), (int32_t)slots.size(),
                                     ctx->stream));
   }
@@ -966,6 +1049,33 @@ int sx_solve(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, const int32_t *n_swe
   return SX_OK;
 }
 
+int sx_profile(sx_ctx *ctx, int32_t enable) {
+  if (!ctx) return SX_EINVAL;
+  ctx->prof = enable != 0;
+  return SX_OK;
+}
+
+int sx_profile_read(sx_ctx *ctx, int64_t *launches, double *total_ms, double *min_ms,
+                    double *max_ms) {
+  if (!ctx) return SX_EINVAL;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  double tot = 0.0, mn = 0.0, mx = 0.0;
+  for (size_t i = 0; i < ctx->ev_used; ++i) {
+    float ms = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[i].first, ctx->ev[i].second));
+    tot += ms;
+    mn = i == 0 ? ms : std::min(mn, (double)ms);
+    mx = std::max(mx, (double)ms);
+  }
+  if (launches) *launches = (int64_t)ctx->ev_used;
+  if (total_ms) *total_ms = tot;
+  if (min_ms) *min_ms = mn;
+  if (max_ms) *max_ms = mx;
+  ctx->ev_used = 0;
+  return SX_OK;
+}
+
 int sx_sync(sx_ctx *ctx) {
   if (!ctx) return SX_EINVAL;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -1005,22 +1115,23 @@ int sx_read_state(sx_ctx *ctx, sx_grid_id id, const sx_state_out *out) {
   HIP_TRY(ctx, hipStreamSynchronize(st));
   if (out->photons) {
     const void *src = h.o[cur.parity];
+    const int64_t pl = h.plane;
     if (h.precision == SX_FP64) {
-      std::vector<double> o((size_t)(K * npad));
-      HIP_TRY(ctx, hipMemcpyAsync(o.data(), src, 8 * K * npad, hipMemcpyDeviceToHost, st));
+      std::vector<double> o((size_t)(K * pl));
+      HIP_TRY(ctx, hipMemcpyAsync(o.data(), src, 8 * K * pl, hipMemcpyDeviceToHost, st));
       HIP_TRY(ctx, hipStreamSynchronize(st));
       for (int64_t i = 0; i < n; ++i) {
         const int64_t v = g->inv[(size_t)i];
-        for (int64_t k = 0; k < K; ++k) out->photons[i * K + k] = o[(size_t)(k * npad + v)] * h.unit;
+        for (int64_t k = 0; k < K; ++k) out->photons[i * K + k] = o[(size_t)(k * pl + v)] * h.unit;
       }
     } else {
-      std::vector<float> o((size_t)(K * npad));
-      HIP_TRY(ctx, hipMemcpyAsync(o.data(), src, 4 * K * npad, hipMemcpyDeviceToHost, st));
+      std::vector<float> o((size_t)(K * pl));
+      HIP_TRY(ctx, hipMemcpyAsync(o.data(), src, 4 * K * pl, hipMemcpyDeviceToHost, st));
       HIP_TRY(ctx, hipStreamSynchronize(st));
       for (int64_t i = 0; i < n; ++i) {
         const int64_t v = g->inv[(size_t)i];
         for (int64_t k = 0; k < K; ++k)
-          out->photons[i * K + k] = (double)o[(size_t)(k * npad + v)] * h.unit;
+          out->photons[i * K + k] = (double)o[(size_t)(k * pl + v)] * h.unit;
       }
     }
   }
@@ -1071,18 +1182,19 @@ int sx_grid_restore(sx_ctx *ctx, sx_grid_id id, const sx_state_in *in) {
       if (!(in->photons[q] >= 0.0) || !std::isfinite(in->photons[q]))
         return fail(ctx, SX_EINVAL, "restored photons must be finite and >= 0");
     void *dst = h.o[cur.parity];
+    const int64_t pl = h.plane;
     if (h.precision == SX_FP64) {
-      std::vector<double> o((size_t)(K * npad), 0.0);
+      std::vector<double> o((size_t)(K * pl), 0.0);
       for (int64_t i = 0; i < n; ++i)
         for (int64_t k = 0; k < K; ++k)
-          o[(size_t)(k * npad + g->inv[(size_t)i])] = in->photons[i * K + k] / h.unit;
-      HIP_TRY(ctx, hipMemcpy(dst, o.data(), 8 * K * npad, hipMemcpyHostToDevice));
+          o[(size_t)(k * pl + g->inv[(size_t)i])] = in->photons[i * K + k] / h.unit;
+      HIP_TRY(ctx, hipMemcpy(dst, o.data(), 8 * K * pl, hipMemcpyHostToDevice));
     } else {
-      std::vector<float> o((size_t)(K * npad), 0.0f);
+      std::vector<float> o((size_t)(K * pl), 0.0f);
       for (int64_t i = 0; i < n; ++i)
         for (int64_t k = 0; k < K; ++k)
-          o[(size_t)(k * npad + g->inv[(size_t)i])] = (float)(in->photons[i * K + k] / h.unit);
-      HIP_TRY(ctx, hipMemcpy(dst, o.data(), 4 * K * npad, hipMemcpyHostToDevice));
+          o[(size_t)(k * pl + g->inv[(size_t)i])] = (float)(in->photons[i * K + k] / h.unit);
+      HIP_TRY(ctx, hipMemcpy(dst, o.data(), 4 * K * pl, hipMemcpyHostToDevice));
     }
   }
   if (in->tally) {

@@ -11,15 +11,27 @@ constexpr int kTile = 64;           // vertices per tile = one wavefront
 constexpr int kTilesPerBlock = 4;   // waves per workgroup of the sweep kernel
 constexpr int kEmptySlot = 127;     // unused slot marker in packed tables
 
-// In-word of a (vertex, bin) pair: which neighbours send this bin here.
-//   bits 0..2  : entries held in the word (0..4)
-//   bit  3     : more entries follow in the vertex's overflow list
-//   bits 4..31 : four 7-bit slots into the receiver's neighbour row,
-//                ascending (so the sum runs in ascending sender id)
+constexpr int kStageQ = 5;         // halo staging loads per lane and bin
+constexpr int kHaloMax = 64 * kStageQ;   // halo vertices a staged tile may have
+constexpr int kZeroSlot = 511;     // in-word index that reads 0
+constexpr int kWordEntries = 7;    // sender entries held by an in-word
+constexpr uint64_t kEmptyWord = 0x7FFFFFFFFFFFFFFFull;  // 7 x 511
+
+// Halo of a tile: the sorted list of every vertex that neighbours one of
+// the tile's 64 vertices.  Each bin's photons of the halo are staged in LDS
+// once per wave, and the gathers read LDS through 9-bit halo indices.  A
+// tile whose halo exceeds kHaloMax vertices is "direct": its entries are
+// slots into the receiver's neighbour row and the gathers go to global
+// memory.
+//
+// In-word of a (vertex, bin) pair (uint64): which neighbours send this bin
+// here.  Bits 9e..9e+8 (e = 0..6) hold the e-th sender, ascending sender
+// id, as a halo index (or row slot in a direct tile); 511 = none.  Senders
+// beyond the seventh are records (uint16: lane << 9 | index) grouped by
+// (tile, bin).
 // Forward word of a (vertex, bin) pair (selection result):
 //   bits 0..20 : three 7-bit slots, best first (127 = none)
 //   bits 21..22: m, the number selected
-// Overflow entry (uint16): bin << 7 | slot.
 
 // Everything a kernel needs to know about one grid.  Lives in device memory
 // (an array of these for a batch); kernels read it through scalar loads.
@@ -39,7 +51,7 @@ struct GridDev {
   double unit;        // photons per stored unit (power of two)
   double dt;
   double cos_min;
-  int64_t plane;      // elements per bin plane of O (= npad)
+  int64_t plane;      // elements per bin plane of O (npad + a zero tile)
   int64_t n_edges;
   // graph (reordered)
   const int32_t *row_ptr;   // [npad+1]
@@ -50,12 +62,16 @@ struct GridDev {
   // selection products
   uint32_t *fwd;            // [npad*K]
   uint8_t *ebin;            // [E]
-  uint32_t *inword;         // [ntiles][K][64]
+  uint64_t *inw;            // [ntiles][K][64]
   uint32_t *mbits;          // [ntiles][kw][64]
-  int32_t *ovf_cnt;         // [npad+1] scratch: extras per vertex, then offsets
-  int32_t *ovf_ptr;         // [npad+1]
-  uint16_t *ovf;            // [n_ovf]
-  int64_t ovf_cap;
+  int32_t *rec_cnt;         // [ntiles*K+1] scratch: records per (tile, bin)
+  int32_t *rec_ptr;         // [ntiles*K+1]
+  uint16_t *rec;            // [n_rec]
+  int64_t rec_cap;
+  const int32_t *halo_ptr;  // [ntiles+1]
+  const int32_t *halo_vid;  // [halo total] ascending new vertex ids
+  const uint16_t *edge_hidx;// [E] halo index of each edge's target (or slot)
+  const uint8_t *tile_direct; // [ntiles]
   // sources (per receiving vertex)
   const int32_t *em_ptr;    // [npad+1]
   const int32_t *em_k;      // [n_em]
@@ -77,6 +93,7 @@ hipError_t launch_edge_bins(const GridDev *dg, const GridDev &hg, hipStream_t s)
 hipError_t launch_inlist_count(const GridDev *dg, const GridDev &hg, hipStream_t s);
 hipError_t launch_scan(int32_t *cnt, int32_t *ptr, int32_t n, hipStream_t s);
 hipError_t launch_inlist_fill(const GridDev *dg, const GridDev &hg, hipStream_t s);
+hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s);
 hipError_t launch_reset_state(GridDev *dg, const GridDev &hg, const double *y0,
                               hipStream_t s);
 // One step for a batch: `grids` is the slot table (or one grid's entry when

@@ -11,9 +11,36 @@
 //   and the in-word / m-bit loads are fully coalesced, and the gathers of a
 //   wave hit the few cache lines of the tile's Hilbert neighbourhood;
 //   gather lists per (vertex, bin) as 32-bit in-words [tile][K][64].
+#include <utility>
+
 #include "sx_internal.h"
 
 namespace sx {
+
+// Pointers read from a GridDev are generic to the compiler; casting them to
+// the global address space makes it emit global (not flat) loads and stores,
+// which do not share the LDS wait counter.
+#define SX_G __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const SX_G T *gld(const T *p) {
+  return (const SX_G T *)p;
+}
+template <typename T>
+__device__ __forceinline__ SX_G T *gst(T *p) {
+  return (SX_G T *)p;
+}
+
+// Compile-time loop: f(std::integral_constant<int, i>) for i = 0..N-1, so
+// per-bin register arrays are indexed by constants (never spilled).
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F &&f,
+                                                std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 // --------------------------------------------------------------- helpers --
 
@@ -107,56 +134,75 @@ __global__ void k_edge_bins(const GridDev *__restrict__ gp) {
 
 // ------------------------------------------------------- gather lists ---
 // The receiver side of the selection: neighbour t of j sends bin k to j iff
-// j is among the selected slots of (nbr_t, k).  Entries are kept in
-// ascending slot order.  Pass 1 counts, per vertex, the entries beyond the
-// four an in-word holds; pass 2 (after a scan) writes in-words, packed m
-// and the overflow entries.
+// j is among the selected slots of (nbr_t, k).  One thread per (tile, bin)
+// walks the tile's 64 receivers in lane order, so that the in-words of a
+// (tile, bin) and its records are produced together and the records come
+// out grouped by (tile, bin).  Pass 1 counts the records, pass 2 (after a
+// scan) writes in-words and records.
+__device__ __forceinline__ int sender_index(const GridDev &g, bool direct,
+                                            int e, int rb) {
+  return direct ? e - rb : (int)g.edge_hidx[e];
+}
+
 __global__ void k_inlist_count(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= g.npad) return;
-  int extras = 0;
-  if (j < g.n) {
-    const int rb = g.row_ptr[j], re = g.row_ptr[j + 1];
-    const int K = g.k;
-    for (int k = 0; k < K; ++k) {
-      int c = 0;
-      for (int e = rb; e < re; ++e)
-        c += fwd_selects(g.fwd[(int64_t)g.nbr[e] * K + k], g.rev[e]) ? 1 : 0;
-      extras += c > 4 ? c - 4 : 0;
-    }
+  const int K = g.k;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)g.ntiles * K) return;
+  const int tile = (int)(t / K), k = (int)(t - (int64_t)tile * K);
+  int recs = 0;
+  for (int lane = 0; lane < kTile; ++lane) {
+    const int j = tile * kTile + lane;
+    if (j >= g.n) break;
+    int c = 0;
+    for (int e = g.row_ptr[j]; e < g.row_ptr[j + 1]; ++e)
+      c += fwd_selects(g.fwd[(int64_t)g.nbr[e] * K + k], g.rev[e]) ? 1 : 0;
+    recs += c > kWordEntries ? c - kWordEntries : 0;
   }
-  g.ovf_cnt[j] = extras;
+  g.rec_cnt[t] = recs;
 }
 
 __global__ void k_inlist_fill(const GridDev *__restrict__ gp) {
+  const GridDev &g = *gp;
+  const int K = g.k;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)g.ntiles * K) return;
+  const int tile = (int)(t / K), k = (int)(t - (int64_t)tile * K);
+  const bool direct = g.tile_direct[tile] != 0;
+  int64_t rp = g.rec_ptr[t];
+  uint64_t *out = g.inw + t * kTile;
+  for (int lane = 0; lane < kTile; ++lane) {
+    const int j = tile * kTile + lane;
+    uint64_t w = kEmptyWord;
+    if (j < g.n) {
+      const int rb = g.row_ptr[j], re = g.row_ptr[j + 1];
+      int c = 0;
+      for (int e = rb; e < re; ++e) {
+        if (!fwd_selects(g.fwd[(int64_t)g.nbr[e] * K + k], g.rev[e])) continue;
+        const uint64_t idx = (uint64_t)sender_index(g, direct, e, rb);
+        if (c < kWordEntries) {
+          w = (w & ~(511ull << (9 * c))) | (idx << (9 * c));
+        } else if (rp < g.rec_cap) {
+          g.rec[rp] = (uint16_t)(((uint32_t)lane << 9) | (uint32_t)idx);
+          ++rp;
+        }
+        ++c;
+      }
+    }
+    out[lane] = w;
+  }
+}
+
+// Packed m(j, k), 2 bits per bin, 16 bins per word.  One lane per vertex.
+__global__ void k_mbits(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= g.npad) return;
   const int tile = j >> 6, lane = j & 63;
   const int K = g.k;
-  const bool valid = j < g.n;
-  const int rb = g.row_ptr[j], re = g.row_ptr[j + 1];
-  int64_t op = g.ovf_ptr[j];
   uint32_t mword = 0;
   for (int k = 0; k < K; ++k) {
-    uint32_t w = 0, c = 0, m = 0;
-    if (valid) {
-      for (int e = rb; e < re; ++e) {
-        if (!fwd_selects(g.fwd[(int64_t)g.nbr[e] * K + k], g.rev[e])) continue;
-        const uint32_t t = (uint32_t)(e - rb);
-        if (c < 4) {
-          w |= t << (4 + 7 * c);
-        } else if (op < g.ovf_cap) {
-          g.ovf[op] = (uint16_t)(((uint32_t)k << 7) | t);
-          ++op;
-        }
-        ++c;
-      }
-      w |= (c < 4 ? c : 4u) | (c > 4 ? 8u : 0u);
-      m = (g.fwd[(int64_t)j * K + k] >> 21) & 3u;
-    }
-    g.inword[((int64_t)tile * K + k) * 64 + lane] = w;
+    const uint32_t m = j < g.n ? (g.fwd[(int64_t)j * K + k] >> 21) & 3u : 0u;
     mword |= m << (2 * (k & 15));
     if ((k & 15) == 15 || k == K - 1) {
       g.mbits[((int64_t)tile * g.kw + (k >> 4)) * 64 + lane] = mword;
@@ -207,11 +253,16 @@ __device__ __forceinline__ double be_substep(double y0, double ha, double hb,
     if (g == 0.0) break;
     if (g > 0.0) lo = yn; else hi = yn;
     const double gp = -1.0 - ha * tau * (1.0 - ion) - 2.0 * hb * x;
-    double yc = yn - g / gp;
+    const double d = g / gp;
+    if (fabs(d) <= 4.0e-16 * yn) {   // Newton step within rounding of y
+      const double yc = yn - d;
+      yn = yc < 0.0 ? 0.0 : (yc > 1.0 ? 1.0 : yc);
+      break;
+    }
+    double yc = yn - d;
     if (!(yc > lo && yc < hi)) yc = 0.5 * (lo + hi);
-    const double step = fabs(yc - yn);
     yn = yc;
-    if (step <= 4.0e-16 * yn || hi - lo <= 4.0e-16 * hi) break;
+    if (hi - lo <= 4.0e-16 * hi) break;
   }
   return yn;
 }
@@ -237,113 +288,185 @@ __device__ __forceinline__ double chem_step(double y, double nin, double dt,
 }
 
 // -------------------------------------------------------------- sweep ---
-// One radiative-transfer step of every active grid in the batch (Sect. 4.6:
-// photons move one edge, interact once).  Lane = vertex of a 64-vertex tile:
-//   1. gather: I[k] = sum over the in-word (+ overflow) entries of the
-//      senders' O[k]; plus this vertex's share of source emission;
+// Gather of one tile (lane = receiver j): I[k] = photons arriving at j in
+// bin k, summed over its senders in ascending sender id.
+//
+// Staged tiles: per bin, the wave stages the bin's photons of the whole tile
+// halo into LDS (kStageQ coalesced loads per lane), then each lane reads its
+// seven in-word senders from LDS; slot kZeroSlot holds 0, so every read is
+// unconditional.  Loads of bin k + PD (staging values, in-word, records) are
+// issued before bin k is summed.
+// Senders beyond the seventh ("records", lane << 9 | index, grouped by bin
+// and sorted by lane) are handled lane-parallel: record r goes to lane r,
+// a segmented scan sums the records of each receiver, and the last record
+// of each receiver hands its sum over through LDS.
+template <typename P, int KMAX, bool DIRECT>
+__device__ __forceinline__ void gather_tile(const GridDev *__restrict__ G, int tile,
+                                            int lane, P *__restrict__ hl,
+                                            P *__restrict__ xchg, P (&I)[KMAX]) {
+  constexpr int PD = sizeof(P) == 8 ? 1 : 2;
+  constexpr int NQ = DIRECT ? 0 : kStageQ;
+  const int K = G->k;
+  const uint32_t plane = (uint32_t)G->plane;
+  const int j = tile * kTile + lane;
+  const SX_G P *__restrict__ oin = gld((const P *)G->o[G->parity]);
+  const SX_G int32_t *__restrict__ nbr = gld(G->nbr);
+  const int rb = gld(G->row_ptr)[j];
+  const SX_G uint64_t *__restrict__ iw = gld(G->inw) + (int64_t)tile * K * kTile + lane;
+  const SX_G int32_t *__restrict__ rptr = gld(G->rec_ptr) + (int64_t)tile * K;
+  const SX_G uint16_t *__restrict__ rec = gld(G->rec);
+
+  uint32_t hv[NQ > 0 ? NQ : 1];
+  if constexpr (!DIRECT) {
+    const SX_G int32_t *__restrict__ hptr = gld(G->halo_ptr);
+    const int hp = hptr[tile];
+    const int hlen = hptr[tile + 1] - hp;
+    const SX_G int32_t *__restrict__ hvid = gld(G->halo_vid);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int idx = 64 * q + lane;
+      hv[q] = (uint32_t)(idx < hlen ? hvid[hp + idx] : G->npad);
+    }
+    if (lane == 63) hl[kZeroSlot] = P(0);
+  }
+
+  P st[PD + 1][NQ > 0 ? NQ : 1];
+  uint64_t wq[PD + 1];
+  uint32_t rq[PD + 1];     // this lane's record of the bin (or 0xffffffff)
+  int rn[PD + 1];          // records of the bin
+  int rs[PD + 1];          // first record of the bin
+  auto issue = [&](int k, int slot) {
+    if constexpr (!DIRECT) {
+      const SX_G P *__restrict__ pk = oin + (uint32_t)k * plane;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) st[slot][q] = pk[hv[q]];
+    }
+    wq[slot] = iw[(int64_t)k * kTile];
+    const int r0 = rptr[k], r1 = rptr[k + 1];
+    rn[slot] = r1 - r0;
+    rs[slot] = r0;
+    rq[slot] = (lane < r1 - r0) ? (uint32_t)rec[r0 + lane] : 0xffffffffu;
+  };
+  static_for<PD>([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    if (p < K) issue(p, p);
+  });
+
+  // Sources: this vertex's shares of the neighbouring sources' photons,
+  // sorted by bin (then source order); added after the transported photons
+  // of the bin.
+  const SX_G int32_t *__restrict__ emk = gld(G->em_k);
+  const SX_G double *__restrict__ ema = gld(G->em_amt);
+  int ep = gld(G->em_ptr)[j];
+  const int ee = gld(G->em_ptr)[j + 1];
+  int ek = ep < ee ? emk[ep] : -1;
+
+  static_for<KMAX>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    P acc = P(0);
+    if (k < K) {
+      constexpr int slot = k % (PD + 1);
+      if (k + PD < K) issue(k + PD, (k + PD) % (PD + 1));
+      const uint64_t w = wq[slot];
+      const SX_G P *__restrict__ pk = oin + (uint32_t)k * plane;
+      if constexpr (!DIRECT) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) hl[64 * q + lane] = st[slot][q];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int e = 0; e < kWordEntries; ++e) acc += hl[(uint32_t)(w >> (9 * e)) & 511u];
+      } else {
+#pragma unroll
+        for (int e = 0; e < kWordEntries; ++e) {
+          const uint32_t idx = (uint32_t)(w >> (9 * e)) & 511u;
+          if (idx != 511u) acc += pk[(uint32_t)nbr[rb + idx]];
+        }
+      }
+      const int nrec = __builtin_amdgcn_readfirstlane(rn[slot]);
+      // lanes hold consecutive records (sorted by receiver), 64 at a time
+      for (int c0 = 0; c0 < nrec; c0 += 64) {
+        const uint32_t r = c0 == 0 ? rq[slot]
+                                   : (lane < nrec - c0 ? (uint32_t)rec[rs[slot] + c0 + lane]
+                                                       : 0xffffffffu);
+        const int tgt = r == 0xffffffffu ? -1 - lane : (int)(r >> 9);
+        P v = P(0);
+        if (r != 0xffffffffu) {
+          const uint32_t idx = r & 511u;
+          if constexpr (!DIRECT) v = hl[idx];
+          else v = pk[(uint32_t)nbr[gld(G->row_ptr)[tile * kTile + tgt] + idx]];
+        }
+        // segmented inclusive scan over runs of equal receivers
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const P vo = __shfl_up(v, off);
+          const int to = __shfl_up(tgt, off);
+          if (lane >= off && to == tgt) v += vo;
+        }
+        const int tnext = __shfl_down(tgt, 1);
+        xchg[lane] = P(0);
+        __builtin_amdgcn_wave_barrier();
+        if (tgt >= 0 && (lane == 63 || tnext != tgt)) xchg[tgt] = v;
+        __builtin_amdgcn_wave_barrier();
+        acc += xchg[lane];
+        __builtin_amdgcn_wave_barrier();
+      }
+      while (ek == k) {
+        acc += (P)ema[ep];
+        ++ep;
+        ek = ep < ee ? emk[ep] : -1;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    I[k] = acc;
+  });
+}
+
+// One radiative-transfer step of one tile (Sect. 4.6: photons move one
+// edge, interact once).  Lane = vertex of the 64-vertex tile:
+//   1. gather (above) plus this vertex's share of source emission;
 //   2. N_in = sum_k I[k];
 //   3. chemistry in fp64 -> y, absorbed A, transmitted fraction T;
 //   4. O'[k] = I[k] T / m(j,k), or escape when m = 0;
 //   5. per-tile photon accounting in fp64, fixed-order wave reduction.
-template <typename P, int KMAX>
-__global__ __launch_bounds__(256) void k_sweep(
-    const GridDev *__restrict__ grids, const int2 *__restrict__ tile_map,
-    int32_t n_tiles) {
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // Workgroups are dealt round-robin to the 8 XCDs; renumber them so each
-  // XCD runs a contiguous range of tiles and its L2 sees the neighbourhood.
-  const uint32_t nb = gridDim.x;   // a multiple of 8
-  const uint32_t b = blockIdx.x;
-  const uint32_t lb = (b & 7u) * (nb >> 3) + (b >> 3);
-  const int gt = (int)lb * kTilesPerBlock + wave;
-  if (gt >= n_tiles) return;
-  int gi = 0, tile = gt;
-  if (tile_map) {
-    const int2 tm = tile_map[gt];
-    gi = __builtin_amdgcn_readfirstlane(tm.x);
-    tile = __builtin_amdgcn_readfirstlane(tm.y);
-  }
-  const GridDev *__restrict__ G = grids + gi;
-  if (G->remaining <= 0) return;
-
+template <typename P, int KMAX, bool DIRECT>
+__device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int tile,
+                                           int lane, P *__restrict__ hl,
+                                           P *__restrict__ xchg) {
   const int K = G->k;
   const int64_t plane = G->plane;
   const int j = tile * kTile + lane;
   const bool valid = j < G->n;
-  const int par = G->parity;
-  const P *__restrict__ oin = (const P *)G->o[par];
-  P *__restrict__ oout = (P *)G->o[par ^ 1];
-  const int32_t *__restrict__ nbr = G->nbr;
-  const int rb = G->row_ptr[j];
-  const uint32_t *__restrict__ iw = G->inword + (int64_t)tile * K * 64 + lane;
-  const uint16_t *__restrict__ ovf = G->ovf;
-  int op = G->ovf_ptr[j];
-  const int oe = G->ovf_ptr[j + 1];
-
+  SX_G P *__restrict__ oout = gst((P *)G->o[G->parity ^ 1]);
   P I[KMAX];
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    P acc = P(0);
-    if (k < K) {
-      const uint32_t w = iw[(int64_t)k * 64];
-      const uint32_t nm = w & 7u;
-      const P *__restrict__ pk = oin + (int64_t)k * plane;
-      if (nm > 0) acc += pk[nbr[rb + ((w >> 4) & 127u)]];
-      if (nm > 1) acc += pk[nbr[rb + ((w >> 11) & 127u)]];
-      if (nm > 2) acc += pk[nbr[rb + ((w >> 18) & 127u)]];
-      if (nm > 3) acc += pk[nbr[rb + ((w >> 25) & 127u)]];
-      if (w & 8u) {
-        while (op < oe) {
-          const uint32_t v = ovf[op];
-          if ((int)(v >> 7) != k) break;
-          acc += pk[nbr[rb + (v & 127u)]];
-          ++op;
-        }
-      }
-    }
-    I[k] = acc;
-  }
-
-  // Sources: this vertex's share of each neighbouring source's photons,
-  // in source order, filed in the bin of the edge they come along.
-  {
-    int ep = G->em_ptr[j];
-    const int ee = G->em_ptr[j + 1];
-    for (; ep < ee; ++ep) {
-      const int kk = G->em_k[ep];
-      const P amt = (P)G->em_amt[ep];
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k)
-        if (k == kk) I[k] += amt;
-    }
-  }
+  gather_tile<P, KMAX, DIRECT>(G, tile, lane, hl, xchg, I);
 
   P sum = P(0);
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k)
+  static_for<KMAX>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
     if (k < K) sum += I[k];
+  });
 
   double A = 0.0, T = 1.0;
   if (valid) {
     const double nin = (double)sum * G->unit;
-    const double y0 = G->y[j];
+    SX_G double *__restrict__ yv = gst(G->y);
+    const double y0 = yv[j];
     if (!(nin == 0.0 && y0 == 1.0)) {
-      const double yn = chem_step(y0, nin, G->dt, G->dtnhv[j], G->tau[j],
-                                  G->bcoef[j], G->n_sub, A, T);
-      G->y[j] = yn;
+      const double yn = chem_step(y0, nin, G->dt, gld(G->dtnhv)[j], gld(G->tau)[j],
+                                  gld(G->bcoef)[j], G->n_sub, A, T);
+      yv[j] = yn;
     }
-    G->nin[j] = nin;
+    gst(G->nin)[j] = nin;
   }
   A /= G->unit;   // tallies in stored units; scaled back on read
 
   const double t2 = T * 0.5;
   const double t3 = T / 3.0;
   double esc = 0.0, fly = 0.0;
-  const uint32_t *__restrict__ mb = G->mbits + (int64_t)tile * G->kw * 64 + lane;
+  const SX_G uint32_t *__restrict__ mb = gld(G->mbits) + (int64_t)tile * G->kw * 64 + lane;
   uint32_t mw = 0;
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
+  static_for<KMAX>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
     if (k < K) {
       if ((k & 15) == 0) mw = mb[(int64_t)(k >> 4) * 64];
       const uint32_t m = (mw >> (2 * (k & 15))) & 3u;
@@ -365,7 +488,7 @@ __global__ __launch_bounds__(256) void k_sweep(
       fly += (double)os * (double)m;
       if (valid) oout[(int64_t)k * plane + j] = os;
     }
-  }
+  });
 
   // Fixed butterfly: every lane ends with the same, order-determined sum.
 #pragma unroll
@@ -375,11 +498,40 @@ __global__ __launch_bounds__(256) void k_sweep(
     fly += __shfl_xor(fly, off);
   }
   if (lane == 0) {
-    double *t = G->tally + (int64_t)tile * 3;
+    SX_G double *t = gst(G->tally) + (int64_t)tile * 3;
     t[0] += A;
     t[1] += esc;
     t[2] = fly;
   }
+}
+
+template <typename P, int KMAX>
+__global__ __launch_bounds__(256) void k_sweep(
+    const GridDev *__restrict__ grids, const int2 *__restrict__ tile_map,
+    int32_t n_tiles) {
+  __shared__ P hbuf[kTilesPerBlock][kZeroSlot + 1];
+  __shared__ P xbuf[kTilesPerBlock][kTile];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // Workgroups are dealt round-robin to the 8 XCDs; renumber them so each
+  // XCD runs a contiguous range of tiles and its L2 sees the neighbourhood.
+  const uint32_t nb = gridDim.x;   // a multiple of 8
+  const uint32_t b = blockIdx.x;
+  const uint32_t lb = (b & 7u) * (nb >> 3) + (b >> 3);
+  const int gt = (int)lb * kTilesPerBlock + wave;
+  if (gt >= n_tiles) return;
+  int gi = 0, tile = gt;
+  if (tile_map) {
+    const int2 tm = tile_map[gt];
+    gi = __builtin_amdgcn_readfirstlane(tm.x);
+    tile = __builtin_amdgcn_readfirstlane(tm.y);
+  }
+  const GridDev *__restrict__ G = grids + gi;
+  if (G->remaining <= 0) return;
+  if (gld(G->tile_direct)[tile] != 0)
+    sweep_tile<P, KMAX, true>(G, tile, lane, hbuf[wave], xbuf[wave]);
+  else
+    sweep_tile<P, KMAX, false>(G, tile, lane, hbuf[wave], xbuf[wave]);
 }
 
 struct SlotVals {
@@ -442,8 +594,13 @@ hipError_t launch_edge_bins(const GridDev *dg, const GridDev &hg,
 
 hipError_t launch_inlist_count(const GridDev *dg, const GridDev &hg,
                                hipStream_t s) {
-  hipLaunchKernelGGL(k_inlist_count, dim3(blocks_for(hg.npad, 256)), dim3(256),
-                     0, s, dg);
+  hipLaunchKernelGGL(k_inlist_count, dim3(blocks_for((int64_t)hg.ntiles * hg.k, 64)),
+                     dim3(64), 0, s, dg);
+  return hipGetLastError();
+}
+
+hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s) {
+  hipLaunchKernelGGL(k_mbits, dim3(blocks_for(hg.npad, 256)), dim3(256), 0, s, dg);
   return hipGetLastError();
 }
 
@@ -454,15 +611,15 @@ hipError_t launch_scan(int32_t *cnt, int32_t *ptr, int32_t n, hipStream_t s) {
 
 hipError_t launch_inlist_fill(const GridDev *dg, const GridDev &hg,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_inlist_fill, dim3(blocks_for(hg.npad, 256)), dim3(256),
-                     0, s, dg);
+  hipLaunchKernelGGL(k_inlist_fill, dim3(blocks_for((int64_t)hg.ntiles * hg.k, 64)),
+                     dim3(64), 0, s, dg);
   return hipGetLastError();
 }
 
 hipError_t launch_reset_state(GridDev *dg, const GridDev &hg, const double *y0,
                               hipStream_t s) {
   hipError_t e;
-  const int64_t nk = (int64_t)hg.k * hg.plane;
+  const int64_t nk = (int64_t)hg.k * hg.plane;   // includes the zero tiles
   for (int b = 0; b < 2; ++b) {
     if (hg.precision == 0)
       e = fill<double>((double *)hg.o[b], 0.0, nk, s);

@@ -29,8 +29,8 @@ EXPORTED = [
     "sx_init", "sx_finalize", "sx_grid_bytes", "sx_grid_upload",
     "sx_grid_reset", "sx_grid_restore", "sx_grid_free", "sx_step",
     "sx_solve", "sx_sync", "sx_read_state", "sx_read_tables",
-    "sx_grid_info", "sx_mem_info", "sx_stream", "sx_strerror",
-    "sx_last_error",
+    "sx_grid_info", "sx_mem_info", "sx_stream", "sx_profile",
+    "sx_profile_read", "sx_strerror", "sx_last_error",
 ]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -113,6 +113,8 @@ def load(path: Optional[str] = None):
         "sx_grid_info": (C.c_int, [P, I64, P, P, P, P, P, P]),
         "sx_mem_info": (C.c_int, [P, P, P]),
         "sx_stream": (P, [P]),
+        "sx_profile": (C.c_int, [P, I32]),
+        "sx_profile_read": (C.c_int, [P, P, P, P, P]),
         "sx_strerror": (C.c_char_p, [C.c_int]),
         "sx_last_error": (C.c_char_p, [P]),
     }
@@ -297,6 +299,20 @@ def sx_stream(ctx) -> int:
     return int(load().sx_stream(ctx) or 0)
 
 
+def sx_profile(ctx, enable: bool) -> None:
+    _check(ctx, load().sx_profile(ctx, 1 if enable else 0))
+
+
+def sx_profile_read(ctx) -> dict:
+    n = C.c_int64()
+    t = C.c_double()
+    lo = C.c_double()
+    hi = C.c_double()
+    _check(ctx, load().sx_profile_read(ctx, C.byref(n), C.byref(t), C.byref(lo),
+                                       C.byref(hi)))
+    return dict(launches=n.value, total_ms=t.value, min_ms=lo.value, max_ms=hi.value)
+
+
 # ------------------------------------------------------ convenience ----
 
 class Context:
@@ -344,6 +360,12 @@ class Context:
 
     def mem_info(self):
         return sx_mem_info(self.h)
+
+    def profile(self, enable: bool = True):
+        sx_profile(self.h, enable)
+
+    def profile_read(self) -> dict:
+        return sx_profile_read(self.h)
 
     @property
     def stream(self) -> int:

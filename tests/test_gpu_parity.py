@@ -242,3 +242,24 @@ def test_budget_enomem():
         assert ctx.mem_info()[0] == 0
     finally:
         ctx.close()
+
+
+def test_direct_gather_path_matches(sxctx, monkeypatch):
+    """Tiles whose halo is too large for LDS staging gather straight from
+    global memory; forcing every tile onto that path gives the oracle's
+    result, and the same bits as the staged path."""
+    w = G.small_random(1500, seed=51, n_bins=42, box=3e21, rate=1e48, n_src=3)
+    staged = _both(sxctx, w, 20)
+    monkeypatch.setenv("SX_FORCE_DIRECT", "1")
+    got, ref, tab, ot, unit = _both(sxctx, w, 20)
+    assert_state_close(got, ref, 0, unit, "direct")
+    assert np.array_equal(got["y"], staged[0]["y"])
+    assert np.array_equal(got["photons"], staged[0]["photons"])
+
+
+def test_many_records_per_bin(sxctx):
+    """A coarse grid where hull vertices receive a bin from many senders:
+    more than 64 senders-beyond-the-seventh in one (tile, bin)."""
+    w = G.small_random(400, seed=61, n_bins=84, box=3e21, rate=1e48, n_src=4)
+    got, ref, tab, ot, unit = _both(sxctx, w, 15)
+    assert_state_close(got, ref, 0, unit, "records")
