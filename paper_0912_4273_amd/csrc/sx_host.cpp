@@ -342,11 +342,12 @@ uint64_t bytes_estimate(const Sizes &s, int64_t n_em, int64_t n_rec, int64_t n_h
   uint64_t b = 0;
   b += rnd(4 * (s.npad + 1)) + rnd(4 * s.E) + rnd(s.E) + rnd(24 * s.E) + rnd(24 * s.K);
   b += rnd(4 * s.npad * s.K) + rnd(s.E) + rnd(8 * s.npad * s.K) +
-       rnd(4 * s.npad * s.kw) + 2 * rnd(4 * (s.ntiles * s.K + 1)) + rnd(2 * n_rec + 2);
+       rnd(4 * s.npad * s.kw) + 2 * rnd(4 * (s.ntiles * s.K + 1)) + rnd(4 * n_rec + 4);
   b += rnd(4 * (s.ntiles + 1)) + rnd(4 * n_halo + 4) + rnd(2 * s.E) + rnd(s.ntiles);
   b += rnd(4 * (s.npad + 1)) + rnd(4 * n_em + 4) + rnd(8 * n_em + 8);
   b += 6 * rnd(8 * s.npad);
   b += 2 * rnd((uint64_t)s.sp * s.K * (s.npad + sx::kTile));
+  b += 2 * rnd((uint64_t)s.sp * (s.npad + sx::kTile));
   b += rnd(24 * s.ntiles);
   return b;
 }
@@ -688,12 +689,17 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
   GA(d_nin, npad);
   GA(d_y0, npad);
   GA(d_tally, 3 * S.ntiles);
+  void *d_t0, *d_t1;
   {
-    uint8_t *o0, *o1;
+    uint8_t *o0, *o1, *t0, *t1;
     GA(o0, (uint64_t)S.sp * K * (npad + sx::kTile));
     GA(o1, (uint64_t)S.sp * K * (npad + sx::kTile));
+    GA(t0, (uint64_t)S.sp * (npad + sx::kTile));
+    GA(t1, (uint64_t)S.sp * (npad + sx::kTile));
     d_o0 = o0;
     d_o1 = o1;
+    d_t0 = t0;
+    d_t1 = t1;
   }
   h.row_ptr = d_rp;
   h.nbr = d_nbr;
@@ -719,6 +725,8 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
   h.nin = d_nin;
   h.o[0] = d_o0;
   h.o[1] = d_o1;
+  h.t[0] = d_t0;
+  h.t[1] = d_t1;
   h.tally = d_tally;
   g->y_init = d_y0;
   g->slot = ctx->free_slots.back();
@@ -757,7 +765,8 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
   int r;
   if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
 
-  // ---- selection tables and gather lists; size the overflow pool
+  // ---- selection tables, source lists, gather lists (records sized by a
+  // count pass)
   GridDev *dg = ctx->table + g->slot;
   auto kfail = [&](hipError_t e) {
     grid_release(ctx, g);
@@ -767,22 +776,6 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
   const int32_t nrow = (int32_t)(ntiles * K);
   if ((he = sx::launch_select(dg, h, st)) != hipSuccess) return kfail(he);
   if ((he = sx::launch_edge_bins(dg, h, st)) != hipSuccess) return kfail(he);
-  if ((he = sx::launch_mbits(dg, h, st)) != hipSuccess) return kfail(he);
-  if ((he = sx::launch_inlist_count(dg, h, st)) != hipSuccess) return kfail(he);
-  if ((he = sx::launch_scan(h.rec_cnt, h.rec_ptr, nrow, st)) != hipSuccess) return kfail(he);
-  int32_t n_rec = 0;
-  if ((he = hipMemcpyAsync(&n_rec, h.rec_ptr + nrow, 4, hipMemcpyDeviceToHost, st)) != hipSuccess)
-    return kfail(he);
-  if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
-  {
-    uint16_t *d_rec;
-    GA(d_rec, (uint64_t)n_rec + 1);
-    h.rec = d_rec;
-    h.rec_cap = n_rec;
-  }
-  if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
-  if ((he = sx::launch_inlist_fill(dg, h, st)) != hipSuccess) return kfail(he);
-
   // ---- sources: per receiving vertex, in source order, the share of each
   // source's photons and the bin of the edge it arrives along
   std::vector<uint8_t> ebin((size_t)E);
@@ -867,6 +860,23 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
     h.em_k = d_emk;
     h.em_amt = d_ema;
   }
+  if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
+  if ((he = sx::launch_mbits(dg, h, st)) != hipSuccess) return kfail(he);
+  if ((he = sx::launch_inlist_count(dg, h, st)) != hipSuccess) return kfail(he);
+  if ((he = sx::launch_scan(h.rec_cnt, h.rec_ptr, nrow, st)) != hipSuccess) return kfail(he);
+  int32_t n_rec = 0;
+  if ((he = hipMemcpyAsync(&n_rec, h.rec_ptr + nrow, 4, hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return kfail(he);
+  if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
+  {
+    uint32_t *d_rec;
+    GA(d_rec, (uint64_t)n_rec + 1);
+    h.rec = d_rec;
+    h.rec_cap = n_rec;
+  }
+  if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
+  if ((he = sx::launch_inlist_fill(dg, h, st)) != hipSuccess) return kfail(he);
+
 #undef GA
 #undef UP
   if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
@@ -1114,24 +1124,31 @@ int sx_read_state(sx_ctx *ctx, sx_grid_id id, const sx_state_out *out) {
   }
   HIP_TRY(ctx, hipStreamSynchronize(st));
   if (out->photons) {
+    // O = Ipre * T in the stored precision, as the next step would form it
     const void *src = h.o[cur.parity];
+    const void *tsrc = h.t[cur.parity];
     const int64_t pl = h.plane;
     if (h.precision == SX_FP64) {
-      std::vector<double> o((size_t)(K * pl));
+      std::vector<double> o((size_t)(K * pl)), t((size_t)pl);
       HIP_TRY(ctx, hipMemcpyAsync(o.data(), src, 8 * K * pl, hipMemcpyDeviceToHost, st));
-      HIP_TRY(ctx, hipStreamSynchronize(st));
-      for (int64_t i = 0; i < n; ++i) {
-        const int64_t v = g->inv[(size_t)i];
-        for (int64_t k = 0; k < K; ++k) out->photons[i * K + k] = o[(size_t)(k * pl + v)] * h.unit;
-      }
-    } else {
-      std::vector<float> o((size_t)(K * pl));
-      HIP_TRY(ctx, hipMemcpyAsync(o.data(), src, 4 * K * pl, hipMemcpyDeviceToHost, st));
+      HIP_TRY(ctx, hipMemcpyAsync(t.data(), tsrc, 8 * pl, hipMemcpyDeviceToHost, st));
       HIP_TRY(ctx, hipStreamSynchronize(st));
       for (int64_t i = 0; i < n; ++i) {
         const int64_t v = g->inv[(size_t)i];
         for (int64_t k = 0; k < K; ++k)
-          out->photons[i * K + k] = (double)o[(size_t)(k * pl + v)] * h.unit;
+          out->photons[i * K + k] = (o[(size_t)(k * pl + v)] * t[(size_t)v]) * h.unit;
+      }
+    } else {
+      std::vector<float> o((size_t)(K * pl)), t((size_t)pl);
+      HIP_TRY(ctx, hipMemcpyAsync(o.data(), src, 4 * K * pl, hipMemcpyDeviceToHost, st));
+      HIP_TRY(ctx, hipMemcpyAsync(t.data(), tsrc, 4 * pl, hipMemcpyDeviceToHost, st));
+      HIP_TRY(ctx, hipStreamSynchronize(st));
+      for (int64_t i = 0; i < n; ++i) {
+        const int64_t v = g->inv[(size_t)i];
+        for (int64_t k = 0; k < K; ++k) {
+          const float ov = o[(size_t)(k * pl + v)] * t[(size_t)v];
+          out->photons[i * K + k] = (double)ov * h.unit;
+        }
       }
     }
   }
@@ -1181,20 +1198,24 @@ int sx_grid_restore(sx_ctx *ctx, sx_grid_id id, const sx_state_in *in) {
     for (int64_t q = 0; q < n * K; ++q)
       if (!(in->photons[q] >= 0.0) || !std::isfinite(in->photons[q]))
         return fail(ctx, SX_EINVAL, "restored photons must be finite and >= 0");
+    // the restored field is the outgoing share itself: Ipre = O, T = 1
     void *dst = h.o[cur.parity];
+    void *tdst = h.t[cur.parity];
     const int64_t pl = h.plane;
     if (h.precision == SX_FP64) {
-      std::vector<double> o((size_t)(K * pl), 0.0);
+      std::vector<double> o((size_t)(K * pl), 0.0), t((size_t)pl, 1.0);
       for (int64_t i = 0; i < n; ++i)
         for (int64_t k = 0; k < K; ++k)
           o[(size_t)(k * pl + g->inv[(size_t)i])] = in->photons[i * K + k] / h.unit;
       HIP_TRY(ctx, hipMemcpy(dst, o.data(), 8 * K * pl, hipMemcpyHostToDevice));
+      HIP_TRY(ctx, hipMemcpy(tdst, t.data(), 8 * pl, hipMemcpyHostToDevice));
     } else {
-      std::vector<float> o((size_t)(K * pl), 0.0f);
+      std::vector<float> o((size_t)(K * pl), 0.0f), t((size_t)pl, 1.0f);
       for (int64_t i = 0; i < n; ++i)
         for (int64_t k = 0; k < K; ++k)
           o[(size_t)(k * pl + g->inv[(size_t)i])] = (float)(in->photons[i * K + k] / h.unit);
       HIP_TRY(ctx, hipMemcpy(dst, o.data(), 4 * K * pl, hipMemcpyHostToDevice));
+      HIP_TRY(ctx, hipMemcpy(tdst, t.data(), 4 * pl, hipMemcpyHostToDevice));
     }
   }
   if (in->tally) {

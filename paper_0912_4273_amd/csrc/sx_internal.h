@@ -26,9 +26,11 @@ constexpr uint64_t kEmptyWord = 0x7FFFFFFFFFFFFFFFull;  // 7 x 511
 //
 // In-word of a (vertex, bin) pair (uint64): which neighbours send this bin
 // here.  Bits 9e..9e+8 (e = 0..6) hold the e-th sender, ascending sender
-// id, as a halo index (or row slot in a direct tile); 511 = none.  Senders
-// beyond the seventh are records (uint16: lane << 9 | index) grouped by
-// (tile, bin).
+// id, as a halo index (or row slot in a direct tile); 511 = none.
+// Records (uint32, grouped by (tile, bin), sorted by lane) carry what does
+// not fit: senders beyond the seventh, then the vertex's shares of source
+// emission for the bin.  Record = lane << 26 | kind << 25 | index, kind 0 =
+// sender (halo index or row slot), kind 1 = emission amount index.
 // Forward word of a (vertex, bin) pair (selection result):
 //   bits 0..20 : three 7-bit slots, best first (127 = none)
 //   bits 21..22: m, the number selected
@@ -66,13 +68,13 @@ struct GridDev {
   uint32_t *mbits;          // [ntiles][kw][64]
   int32_t *rec_cnt;         // [ntiles*K+1] scratch: records per (tile, bin)
   int32_t *rec_ptr;         // [ntiles*K+1]
-  uint16_t *rec;            // [n_rec]
+  uint32_t *rec;            // [n_rec]
   int64_t rec_cap;
   const int32_t *halo_ptr;  // [ntiles+1]
   const int32_t *halo_vid;  // [halo total] ascending new vertex ids
   const uint16_t *edge_hidx;// [E] halo index of each edge's target (or slot)
   const uint8_t *tile_direct; // [ntiles]
-  // sources (per receiving vertex)
+  // sources (per receiving vertex, by bin, then source order)
   const int32_t *em_ptr;    // [npad+1]
   const int32_t *em_k;      // [n_em]
   const double *em_amt;     // [n_em] photons / unit
@@ -82,7 +84,10 @@ struct GridDev {
   const double *bcoef;      // [npad] alpha_B * n_H
   double *y;                // [npad] neutral fraction
   double *nin;              // [npad] photons in, last step
-  void *o[2];               // [K*npad] fp32 or fp64 planes
+  void *o[2];               // [K*plane] photons per selected neighbour before
+                            // attenuation, I/m (fp32 or fp64), double buffered
+  void *t[2];               // [plane] transmitted fraction T of each vertex
+                            // in the step that wrote o[] (fp32 or fp64)
   double *tally;            // [ntiles*3] absorbed (cum), escaped (cum), in flight
 };
 

@@ -57,6 +57,14 @@ __device__ __forceinline__ double cosine3(const double *e, const double *u) {
   return ab + c;
 }
 
+// A product that is rounded on its own (never fused into a following add),
+// so that staged and direct gathers round a sender's outgoing photons alike.
+template <typename P>
+__device__ __forceinline__ P mul_rn(P a, P b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+
 __device__ __forceinline__ bool fwd_selects(uint32_t f, uint32_t slot) {
   return ((f & 127u) == slot) | (((f >> 7) & 127u) == slot) |
          (((f >> 14) & 127u) == slot);
@@ -144,6 +152,8 @@ __device__ __forceinline__ int sender_index(const GridDev &g, bool direct,
   return direct ? e - rb : (int)g.edge_hidx[e];
 }
 
+constexpr uint32_t kRecEmission = 1u << 25;
+
 __global__ void k_inlist_count(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
   const int K = g.k;
@@ -158,6 +168,7 @@ __global__ void k_inlist_count(const GridDev *__restrict__ gp) {
     for (int e = g.row_ptr[j]; e < g.row_ptr[j + 1]; ++e)
       c += fwd_selects(g.fwd[(int64_t)g.nbr[e] * K + k], g.rev[e]) ? 1 : 0;
     recs += c > kWordEntries ? c - kWordEntries : 0;
+    for (int q = g.em_ptr[j]; q < g.em_ptr[j + 1]; ++q) recs += g.em_k[q] == k ? 1 : 0;
   }
   g.rec_cnt[t] = recs;
 }
@@ -176,18 +187,21 @@ __global__ void k_inlist_fill(const GridDev *__restrict__ gp) {
     uint64_t w = kEmptyWord;
     if (j < g.n) {
       const int rb = g.row_ptr[j], re = g.row_ptr[j + 1];
+      const uint32_t lbits = (uint32_t)lane << 26;
       int c = 0;
       for (int e = rb; e < re; ++e) {
         if (!fwd_selects(g.fwd[(int64_t)g.nbr[e] * K + k], g.rev[e])) continue;
-        const uint64_t idx = (uint64_t)sender_index(g, direct, e, rb);
+        const uint32_t idx = (uint32_t)sender_index(g, direct, e, rb);
         if (c < kWordEntries) {
-          w = (w & ~(511ull << (9 * c))) | (idx << (9 * c));
+          w = (w & ~(511ull << (9 * c))) | ((uint64_t)idx << (9 * c));
         } else if (rp < g.rec_cap) {
-          g.rec[rp] = (uint16_t)(((uint32_t)lane << 9) | (uint32_t)idx);
-          ++rp;
+          g.rec[rp++] = lbits | idx;
         }
         ++c;
       }
+      // source shares come after the transported photons of the bin
+      for (int q = g.em_ptr[j]; q < g.em_ptr[j + 1]; ++q)
+        if (g.em_k[q] == k && rp < g.rec_cap) g.rec[rp++] = lbits | kRecEmission | (uint32_t)q;
     }
     out[lane] = w;
   }
@@ -288,53 +302,81 @@ __device__ __forceinline__ double chem_step(double y, double nin, double dt,
 }
 
 // -------------------------------------------------------------- sweep ---
-// Gather of one tile (lane = receiver j): I[k] = photons arriving at j in
-// bin k, summed over its senders in ascending sender id.
+// State between steps: for every vertex i and bin k, Ipre[k][i] = I/m, the
+// photons that entered i in bin k divided over its m selected neighbours,
+// and per vertex the fraction T_i it passed on.  A neighbour receives
+// Ipre * T_i from i, which is the outgoing share I T / m of the method.
+// Keeping T apart lets a step write each bin the moment it is gathered.
 //
-// Staged tiles: per bin, the wave stages the bin's photons of the whole tile
-// halo into LDS (kStageQ coalesced loads per lane), then each lane reads its
-// seven in-word senders from LDS; slot kZeroSlot holds 0, so every read is
-// unconditional.  Loads of bin k + PD (staging values, in-word, records) are
-// issued before bin k is summed.
-// Senders beyond the seventh ("records", lane << 9 | index, grouped by bin
-// and sorted by lane) are handled lane-parallel: record r goes to lane r,
-// a segmented scan sums the records of each receiver, and the last record
-// of each receiver hands its sum over through LDS.
-template <typename P, int KMAX, bool DIRECT>
-__device__ __forceinline__ void gather_tile(const GridDev *__restrict__ G, int tile,
-                                            int lane, P *__restrict__ hl,
-                                            P *__restrict__ xchg, P (&I)[KMAX]) {
-  constexpr int PD = sizeof(P) == 8 ? 1 : 2;
-  constexpr int NQ = DIRECT ? 0 : kStageQ;
+// One radiative-transfer step of one tile (Sect. 4.6: photons move one edge
+// and interact once).  Lane = receiver j of the 64-vertex tile.
+// 1. Per bin k: I = photons arriving at j in bin k, summed over its senders
+//    in ascending sender id, then its source shares.  A staged tile copies
+//    the bin's Ipre * T of its whole halo into LDS (kStageQ coalesced loads
+//    per lane); each lane then reads its seven in-word senders from LDS
+//    (slot kZeroSlot holds 0, so every read is unconditional).  Loads for
+//    bin k + 2 are in flight while bin k is summed.  Records (senders beyond
+//    the seventh, source shares) go lane-parallel: record r to lane r, runs
+//    of records for one receiver summed by a segmented scan (only when a
+//    receiver has two), sums handed over through LDS.
+//    Ipre'[k][j] = I / m(j,k) is stored at once; N_in and the photons of
+//    bins with no forward neighbour (m = 0, they leave the domain) add up.
+// 2. Chemistry in fp64 -> y, absorbed A, transmitted fraction T' of j.
+// 3. Per-tile photon accounting in fp64, fixed-order wave reduction.
+template <typename P, bool DIRECT>
+__device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int tile,
+                                           int lane, volatile P *hl,
+                                           volatile P *xchg) {
+  // hl and xchg carry data between lanes of this wave through LDS.  The
+  // accesses are volatile so that the compiler keeps every store and load in
+  // program order (it may not forward a lane's own store past another
+  // lane's); LDS executes a wave's operations in issue order.
+  constexpr int NQ = DIRECT ? 1 : kStageQ;
   const int K = G->k;
   const uint32_t plane = (uint32_t)G->plane;
   const int j = tile * kTile + lane;
-  const SX_G P *__restrict__ oin = gld((const P *)G->o[G->parity]);
+  const bool valid = j < G->n;
+  const int par = G->parity;
+  const SX_G P *__restrict__ oin = gld((const P *)G->o[par]);
+  const SX_G P *__restrict__ tin = gld((const P *)G->t[par]);
+  SX_G P *__restrict__ oout = gst((P *)G->o[par ^ 1]);
   const SX_G int32_t *__restrict__ nbr = gld(G->nbr);
-  const int rb = gld(G->row_ptr)[j];
+  const SX_G int32_t *__restrict__ rowp = gld(G->row_ptr);
+  const int rb = rowp[j];
   const SX_G uint64_t *__restrict__ iw = gld(G->inw) + (int64_t)tile * K * kTile + lane;
   const SX_G int32_t *__restrict__ rptr = gld(G->rec_ptr) + (int64_t)tile * K;
-  const SX_G uint16_t *__restrict__ rec = gld(G->rec);
+  const SX_G uint32_t *__restrict__ rec = gld(G->rec);
+  const SX_G double *__restrict__ ema = gld(G->em_amt);
 
-  uint32_t hv[NQ > 0 ? NQ : 1];
+  // halo of the tile and its senders' T (once per step)
+  uint32_t hv[NQ];
+  P th[NQ];
   if constexpr (!DIRECT) {
     const SX_G int32_t *__restrict__ hptr = gld(G->halo_ptr);
     const int hp = hptr[tile];
     const int hlen = hptr[tile + 1] - hp;
     const SX_G int32_t *__restrict__ hvid = gld(G->halo_vid);
+    const uint32_t zero = (uint32_t)G->npad;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int idx = 64 * q + lane;
-      hv[q] = (uint32_t)(idx < hlen ? hvid[hp + idx] : G->npad);
+      hv[q] = idx < hlen ? (uint32_t)hvid[hp + idx] : zero;
+      th[q] = tin[hv[q]];
     }
     if (lane == 63) hl[kZeroSlot] = P(0);
   }
+  // packed m(j, k), 16 bins per word, consumed 2 bits at a time
+  const SX_G uint32_t *__restrict__ mbp = gld(G->mbits) + (int64_t)tile * G->kw * 64 + lane;
+  uint32_t mwv[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) mwv[q] = q < G->kw ? mbp[q * 64] : 0u;
 
-  P st[PD + 1][NQ > 0 ? NQ : 1];
-  uint64_t wq[PD + 1];
-  uint32_t rq[PD + 1];     // this lane's record of the bin (or 0xffffffff)
-  int rn[PD + 1];          // records of the bin
-  int rs[PD + 1];          // first record of the bin
+  // ring of loads in flight, slot = k mod 3
+  P st[3][NQ];
+  uint64_t wq[3];
+  uint32_t rq[3];   // this lane's first record of the bin, or ~0
+  int rn[3];        // records of the bin
+  int rs[3];        // index of the bin's first record
   auto issue = [&](int k, int slot) {
     if constexpr (!DIRECT) {
       const SX_G P *__restrict__ pk = oin + (uint32_t)k * plane;
@@ -345,150 +387,112 @@ __device__ __forceinline__ void gather_tile(const GridDev *__restrict__ G, int t
     const int r0 = rptr[k], r1 = rptr[k + 1];
     rn[slot] = r1 - r0;
     rs[slot] = r0;
-    rq[slot] = (lane < r1 - r0) ? (uint32_t)rec[r0 + lane] : 0xffffffffu;
+    rq[slot] = lane < r1 - r0 ? rec[r0 + lane] : ~0u;
   };
-  static_for<PD>([&](auto pc) {
-    constexpr int p = decltype(pc)::value;
-    if (p < K) issue(p, p);
-  });
 
-  // Sources: this vertex's shares of the neighbouring sources' photons,
-  // sorted by bin (then source order); added after the transported photons
-  // of the bin.
-  const SX_G int32_t *__restrict__ emk = gld(G->em_k);
-  const SX_G double *__restrict__ ema = gld(G->em_amt);
-  int ep = gld(G->em_ptr)[j];
-  const int ee = gld(G->em_ptr)[j + 1];
-  int ek = ep < ee ? emk[ep] : -1;
-
-  static_for<KMAX>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
+  P nin_p = P(0);    // sum over bins of I, in bin order
+  P esc_p = P(0);    // sum of I over bins that leave the domain
+  auto bin = [&](int k, int slot) {
+    if (k + 2 < K) issue(k + 2, (slot + 2) % 3);
+    const uint64_t w = wq[slot];
     P acc = P(0);
-    if (k < K) {
-      constexpr int slot = k % (PD + 1);
-      if (k + PD < K) issue(k + PD, (k + PD) % (PD + 1));
-      const uint64_t w = wq[slot];
+    if constexpr (!DIRECT) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) hl[64 * q + lane] = mul_rn(st[slot][q], th[q]);
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int e = 0; e < kWordEntries; ++e) acc += hl[(uint32_t)(w >> (9 * e)) & 511u];
+    } else {
       const SX_G P *__restrict__ pk = oin + (uint32_t)k * plane;
-      if constexpr (!DIRECT) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) hl[64 * q + lane] = st[slot][q];
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int e = 0; e < kWordEntries; ++e) acc += hl[(uint32_t)(w >> (9 * e)) & 511u];
-      } else {
-#pragma unroll
-        for (int e = 0; e < kWordEntries; ++e) {
-          const uint32_t idx = (uint32_t)(w >> (9 * e)) & 511u;
-          if (idx != 511u) acc += pk[(uint32_t)nbr[rb + idx]];
+      for (int e = 0; e < kWordEntries; ++e) {
+        const uint32_t idx = (uint32_t)(w >> (9 * e)) & 511u;
+        if (idx != 511u) {
+          const uint32_t src = (uint32_t)nbr[rb + idx];
+          acc += mul_rn(pk[src], tin[src]);
         }
       }
-      const int nrec = __builtin_amdgcn_readfirstlane(rn[slot]);
-      // lanes hold consecutive records (sorted by receiver), 64 at a time
-      for (int c0 = 0; c0 < nrec; c0 += 64) {
-        const uint32_t r = c0 == 0 ? rq[slot]
-                                   : (lane < nrec - c0 ? (uint32_t)rec[rs[slot] + c0 + lane]
-                                                       : 0xffffffffu);
-        const int tgt = r == 0xffffffffu ? -1 - lane : (int)(r >> 9);
-        P v = P(0);
-        if (r != 0xffffffffu) {
-          const uint32_t idx = r & 511u;
-          if constexpr (!DIRECT) v = hl[idx];
-          else v = pk[(uint32_t)nbr[gld(G->row_ptr)[tile * kTile + tgt] + idx]];
+    }
+    const int nrec = __builtin_amdgcn_readfirstlane(rn[slot]);
+    for (int c0 = 0; c0 < nrec; c0 += 64) {
+      const uint32_t r = c0 == 0 ? rq[slot]
+                                 : (lane < nrec - c0 ? rec[rs[slot] + c0 + lane] : ~0u);
+      const bool has = r != ~0u;
+      const int tgt = has ? (int)(r >> 26) : -1 - lane;
+      const uint32_t idx = r & 0x1ffffffu;
+      P v = P(0);
+      if (has) {
+        if (r & kRecEmission) {
+          v = (P)ema[idx];
+        } else if constexpr (!DIRECT) {
+          v = hl[idx];
+        } else {
+          const uint32_t src = (uint32_t)nbr[rowp[tile * kTile + tgt] + idx];
+          v = mul_rn(oin[(uint32_t)k * plane + src], tin[src]);
         }
-        // segmented inclusive scan over runs of equal receivers
+      }
+      const int tnext = __shfl_down(tgt, 1);
+      if (__ballot(has && lane < 63 && tnext == tgt)) {
+        // a receiver with several records: segmented inclusive scan
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
           const P vo = __shfl_up(v, off);
           const int to = __shfl_up(tgt, off);
           if (lane >= off && to == tgt) v += vo;
         }
-        const int tnext = __shfl_down(tgt, 1);
-        xchg[lane] = P(0);
-        __builtin_amdgcn_wave_barrier();
-        if (tgt >= 0 && (lane == 63 || tnext != tgt)) xchg[tgt] = v;
-        __builtin_amdgcn_wave_barrier();
-        acc += xchg[lane];
-        __builtin_amdgcn_wave_barrier();
       }
-      while (ek == k) {
-        acc += (P)ema[ep];
-        ++ep;
-        ek = ep < ee ? emk[ep] : -1;
-      }
+      xchg[lane] = P(0);
+      __builtin_amdgcn_wave_barrier();
+      if (has && (lane == 63 || tnext != tgt)) xchg[tgt] = v;
+      __builtin_amdgcn_wave_barrier();
+      acc += xchg[lane];
       __builtin_amdgcn_wave_barrier();
     }
-    I[k] = acc;
-  });
-}
+    __builtin_amdgcn_wave_barrier();
+    // m(j, k) and the stored share
+    const uint32_t m = mwv[0] & 3u;
+    mwv[0] >>= 2;
+    if ((k & 15) == 15) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) mwv[q] = mwv[q + 1];
+    }
+    nin_p += acc;
+    esc_p += m == 0u ? acc : P(0);
+    P ipre;
+    if constexpr (sizeof(P) == 8) {
+      ipre = m == 0u ? 0.0 : (m == 1u ? acc : (m == 2u ? acc * 0.5 : acc / 3.0));
+    } else {
+      // 1/m for m = 1, 2, 3 as (m^2 - 6m + 11) / 6 (no table lookup)
+      const float fm = (float)(int)(m * m - 6u * m + 11u) * (1.0f / 6.0f);
+      ipre = m == 0u ? 0.0f : acc * fm;
+    }
+    if (valid) oout[(uint32_t)k * plane + j] = ipre;
+  };
 
-// One radiative-transfer step of one tile (Sect. 4.6: photons move one
-// edge, interact once).  Lane = vertex of the 64-vertex tile:
-//   1. gather (above) plus this vertex's share of source emission;
-//   2. N_in = sum_k I[k];
-//   3. chemistry in fp64 -> y, absorbed A, transmitted fraction T;
-//   4. O'[k] = I[k] T / m(j,k), or escape when m = 0;
-//   5. per-tile photon accounting in fp64, fixed-order wave reduction.
-template <typename P, int KMAX, bool DIRECT>
-__device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int tile,
-                                           int lane, P *__restrict__ hl,
-                                           P *__restrict__ xchg) {
-  const int K = G->k;
-  const int64_t plane = G->plane;
-  const int j = tile * kTile + lane;
-  const bool valid = j < G->n;
-  SX_G P *__restrict__ oout = gst((P *)G->o[G->parity ^ 1]);
-  P I[KMAX];
-  gather_tile<P, KMAX, DIRECT>(G, tile, lane, hl, xchg, I);
-
-  P sum = P(0);
-  static_for<KMAX>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    if (k < K) sum += I[k];
-  });
+  if (0 < K) issue(0, 0);
+  if (1 < K) issue(1, 1);
+  for (int k0 = 0; k0 < K; k0 += 3) {
+    bin(k0, 0);
+    if (k0 + 1 < K) bin(k0 + 1, 1);
+    if (k0 + 2 < K) bin(k0 + 2, 2);
+  }
 
   double A = 0.0, T = 1.0;
+  const double nin = (double)nin_p;
   if (valid) {
-    const double nin = (double)sum * G->unit;
     SX_G double *__restrict__ yv = gst(G->y);
     const double y0 = yv[j];
     if (!(nin == 0.0 && y0 == 1.0)) {
-      const double yn = chem_step(y0, nin, G->dt, gld(G->dtnhv)[j], gld(G->tau)[j],
-                                  gld(G->bcoef)[j], G->n_sub, A, T);
+      const double yn = chem_step(y0, nin * G->unit, G->dt, gld(G->dtnhv)[j],
+                                  gld(G->tau)[j], gld(G->bcoef)[j], G->n_sub, A, T);
       yv[j] = yn;
     }
-    gst(G->nin)[j] = nin;
+    gst(G->nin)[j] = nin * G->unit;
+    gst((P *)G->t[par ^ 1])[j] = (P)T;
   }
   A /= G->unit;   // tallies in stored units; scaled back on read
-
-  const double t2 = T * 0.5;
-  const double t3 = T / 3.0;
-  double esc = 0.0, fly = 0.0;
-  const SX_G uint32_t *__restrict__ mb = gld(G->mbits) + (int64_t)tile * G->kw * 64 + lane;
-  uint32_t mw = 0;
-  static_for<KMAX>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    if (k < K) {
-      if ((k & 15) == 0) mw = mb[(int64_t)(k >> 4) * 64];
-      const uint32_t m = (mw >> (2 * (k & 15))) & 3u;
-      const double it = (double)I[k] * T;
-      double o;
-      if (m == 0u) {
-        esc += it;
-        o = 0.0;
-      } else if (m == 1u) {
-        o = it;
-      } else if (m == 2u) {
-        o = (double)I[k] * t2;
-      } else if constexpr (sizeof(P) == 8) {
-        o = it / 3.0;   // same rounding as (I T) / 3 on the host
-      } else {
-        o = (double)I[k] * t3;
-      }
-      const P os = (P)o;
-      fly += (double)os * (double)m;
-      if (valid) oout[(int64_t)k * plane + j] = os;
-    }
-  });
+  double esc = (double)esc_p * T;
+  double fly = (nin - (double)esc_p) * T;
 
   // Fixed butterfly: every lane ends with the same, order-determined sum.
 #pragma unroll
@@ -505,7 +509,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
   }
 }
 
-template <typename P, int KMAX>
+template <typename P>
 __global__ __launch_bounds__(256) void k_sweep(
     const GridDev *__restrict__ grids, const int2 *__restrict__ tile_map,
     int32_t n_tiles) {
@@ -529,9 +533,9 @@ __global__ __launch_bounds__(256) void k_sweep(
   const GridDev *__restrict__ G = grids + gi;
   if (G->remaining <= 0) return;
   if (gld(G->tile_direct)[tile] != 0)
-    sweep_tile<P, KMAX, true>(G, tile, lane, hbuf[wave], xbuf[wave]);
+    sweep_tile<P, true>(G, tile, lane, hbuf[wave], xbuf[wave]);
   else
-    sweep_tile<P, KMAX, false>(G, tile, lane, hbuf[wave], xbuf[wave]);
+    sweep_tile<P, false>(G, tile, lane, hbuf[wave], xbuf[wave]);
 }
 
 struct SlotVals {
@@ -621,10 +625,13 @@ hipError_t launch_reset_state(GridDev *dg, const GridDev &hg, const double *y0,
   hipError_t e;
   const int64_t nk = (int64_t)hg.k * hg.plane;   // includes the zero tiles
   for (int b = 0; b < 2; ++b) {
-    if (hg.precision == 0)
+    if (hg.precision == 0) {
       e = fill<double>((double *)hg.o[b], 0.0, nk, s);
-    else
+      if (e == hipSuccess) e = fill<double>((double *)hg.t[b], 1.0, hg.plane, s);
+    } else {
       e = fill<float>((float *)hg.o[b], 0.0f, nk, s);
+      if (e == hipSuccess) e = fill<float>((float *)hg.t[b], 1.0f, hg.plane, s);
+    }
     if (e != hipSuccess) return e;
   }
   e = fill<double>(hg.tally, 0.0, (int64_t)hg.ntiles * 3, s);
@@ -644,39 +651,19 @@ int kmax_bucket(int k, int precision) {
   return 0;
 }
 
-template <typename P>
-static hipError_t sweep_p(const GridDev *grids, const int2 *tile_map,
-                          int32_t n_tiles, int kmax, hipStream_t s) {
-  unsigned nb = blocks_for(n_tiles, kTilesPerBlock);
-  nb = (nb + 7u) & ~7u;
-  dim3 g(nb), t(64 * kTilesPerBlock);
-  switch (kmax) {
-#define SX_CASE(KM)                                                         \
-  case KM:                                                                  \
-    hipLaunchKernelGGL((k_sweep<P, KM>), g, t, 0, s, grids, tile_map,       \
-                       n_tiles);                                            \
-    break;
-    SX_CASE(8)
-    SX_CASE(16)
-    SX_CASE(32)
-    SX_CASE(42)
-    SX_CASE(48)
-    SX_CASE(64)
-    SX_CASE(84)
-    SX_CASE(96)
-#undef SX_CASE
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
 hipError_t launch_sweep(const GridDev *grids, const int2 *tile_map,
                         int32_t n_tiles, int32_t kmax, int32_t precision,
                         hipStream_t s) {
+  (void)kmax;
   if (n_tiles <= 0) return hipSuccess;
-  if (precision == 0) return sweep_p<double>(grids, tile_map, n_tiles, kmax, s);
-  return sweep_p<float>(grids, tile_map, n_tiles, kmax, s);
+  unsigned nb = blocks_for(n_tiles, kTilesPerBlock);
+  nb = (nb + 7u) & ~7u;
+  dim3 g(nb), t(64 * kTilesPerBlock);
+  if (precision == 0)
+    hipLaunchKernelGGL(k_sweep<double>, g, t, 0, s, grids, tile_map, n_tiles);
+  else
+    hipLaunchKernelGGL(k_sweep<float>, g, t, 0, s, grids, tile_map, n_tiles);
+  return hipGetLastError();
 }
 
 hipError_t launch_advance(GridDev *table, const int32_t *slots, int32_t n,
