@@ -321,7 +321,7 @@ int validate(sx_ctx *ctx, const sx_grid_desc *d) {
 }
 
 struct Sizes {
-  int64_t n, npad, ntiles, E, K, kw, sp;
+  int64_t n, npad, ntiles, E, K, kw, sp, bb, kb;
 };
 
 Sizes sizes_of(const sx_grid_desc *d) {
@@ -333,6 +333,8 @@ Sizes sizes_of(const sx_grid_desc *d) {
   s.K = d->n_bins;
   s.kw = (s.K + 15) / 16;
   s.sp = d->precision == SX_FP64 ? 8 : 4;
+  s.bb = sx::kBlockBytes / s.sp;
+  s.kb = (s.K + s.bb - 1) / s.bb;
   return s;
 }
 
@@ -341,12 +343,12 @@ uint64_t rnd(uint64_t b) { return (b + 255) & ~uint64_t(255); }
 uint64_t bytes_estimate(const Sizes &s, int64_t n_em, int64_t n_rec, int64_t n_halo) {
   uint64_t b = 0;
   b += rnd(4 * (s.npad + 1)) + rnd(4 * s.E) + rnd(s.E) + rnd(24 * s.E) + rnd(24 * s.K);
-  b += rnd(4 * s.npad * s.K) + rnd(s.E) + rnd(8 * s.npad * s.K) +
+  b += rnd(4 * s.npad * s.K) + rnd(s.E) + rnd(8 * s.npad * s.kb * s.bb) +
        rnd(4 * s.npad * s.kw) + 2 * rnd(4 * (s.ntiles * s.K + 1)) + rnd(4 * n_rec + 4);
   b += rnd(4 * (s.ntiles + 1)) + rnd(4 * n_halo + 4) + rnd(2 * s.E) + rnd(s.ntiles);
   b += rnd(4 * (s.npad + 1)) + rnd(4 * n_em + 4) + rnd(8 * n_em + 8);
   b += 6 * rnd(8 * s.npad);
-  b += 2 * rnd((uint64_t)s.sp * s.K * (s.npad + sx::kTile));
+  b += 2 * rnd((uint64_t)sx::kBlockBytes * s.kb * (s.npad + sx::kTile));
   b += 2 * rnd((uint64_t)s.sp * (s.npad + sx::kTile));
   b += rnd(24 * s.ntiles);
   return b;
@@ -372,6 +374,7 @@ int build_tables(sx_ctx *ctx, Grid *g) {
   HIP_TRY(ctx, sx::launch_select(dg, g->hg, ctx->stream));
   HIP_TRY(ctx, sx::launch_edge_bins(dg, g->hg, ctx->stream));
   HIP_TRY(ctx, sx::launch_mbits(dg, g->hg, ctx->stream));
+  HIP_TRY(ctx, sx::launch_clear_inw(g->hg, ctx->stream));
   HIP_TRY(ctx, sx::launch_inlist_count(dg, g->hg, ctx->stream));
   HIP_TRY(ctx, sx::launch_scan(g->hg.rec_cnt, g->hg.rec_ptr, nrow, ctx->stream));
   HIP_TRY(ctx, sx::launch_inlist_fill(dg, g->hg, ctx->stream));
@@ -644,6 +647,8 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
   h.ntiles = (int32_t)S.ntiles;
   h.k = (int32_t)K;
   h.kw = (int32_t)S.kw;
+  h.bb = (int32_t)S.bb;
+  h.kb = (int32_t)S.kb;
   h.n_sub = d->n_subcycles;
   h.mpb = d->max_per_bin;
   h.precision = d->precision;
@@ -674,7 +679,7 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
   GA(d_bins, 3 * K);
   GA(d_fwd, npad * K);
   GA(d_ebin, E);
-  GA(d_inw, npad * K);
+  GA(d_inw, npad * S.kb * S.bb);
   GA(d_mb, npad * S.kw);
   GA(d_rec_cnt, ntiles * K + 1);
   GA(d_rec_ptr, ntiles * K + 1);
@@ -692,8 +697,8 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
   void *d_t0, *d_t1;
   {
     uint8_t *o0, *o1, *t0, *t1;
-    GA(o0, (uint64_t)S.sp * K * (npad + sx::kTile));
-    GA(o1, (uint64_t)S.sp * K * (npad + sx::kTile));
+    GA(o0, (uint64_t)sx::kBlockBytes * S.kb * (npad + sx::kTile));
+    GA(o1, (uint64_t)sx::kBlockBytes * S.kb * (npad + sx::kTile));
     GA(t0, (uint64_t)S.sp * (npad + sx::kTile));
     GA(t1, (uint64_t)S.sp * (npad + sx::kTile));
     d_o0 = o0;
@@ -832,6 +837,10 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
     }
   }
   g->esc_emit = esc_emit;
+  if ((int64_t)em.size() >= ((int64_t)1 << sx::kRecIdxBits)) {
+    grid_release(ctx, g);
+    return fail(ctx, SX_ENOTSUP, "too many source-neighbour pairs (%zu)", em.size());
+  }
   // per receiver, by bin; equal bins keep source order
   std::stable_sort(em.begin(), em.end(), [](const Em &a, const Em &b) {
     return a.recv != b.recv ? a.recv < b.recv : a.k < b.k;
@@ -862,6 +871,7 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
   }
   if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
   if ((he = sx::launch_mbits(dg, h, st)) != hipSuccess) return kfail(he);
+  if ((he = sx::launch_clear_inw(h, st)) != hipSuccess) return kfail(he);
   if ((he = sx::launch_inlist_count(dg, h, st)) != hipSuccess) return kfail(he);
   if ((he = sx::launch_scan(h.rec_cnt, h.rec_ptr, nrow, st)) != hipSuccess) return kfail(he);
   int32_t n_rec = 0;
@@ -1125,28 +1135,32 @@ int sx_read_state(sx_ctx *ctx, sx_grid_id id, const sx_state_out *out) {
   HIP_TRY(ctx, hipStreamSynchronize(st));
   if (out->photons) {
     // O = Ipre * T in the stored precision, as the next step would form it
+    const int64_t words = (h.ntiles + 1) * (int64_t)h.kb * sx::kTile * h.bb;
+    auto at = [&](int64_t v, int64_t k) {
+      return (((v >> 6) * h.kb + k / h.bb) * sx::kTile + (v & 63)) * h.bb + k % h.bb;
+    };
     const void *src = h.o[cur.parity];
     const void *tsrc = h.t[cur.parity];
     const int64_t pl = h.plane;
     if (h.precision == SX_FP64) {
-      std::vector<double> o((size_t)(K * pl)), t((size_t)pl);
-      HIP_TRY(ctx, hipMemcpyAsync(o.data(), src, 8 * K * pl, hipMemcpyDeviceToHost, st));
+      std::vector<double> o((size_t)words), t((size_t)pl);
+      HIP_TRY(ctx, hipMemcpyAsync(o.data(), src, 8 * words, hipMemcpyDeviceToHost, st));
       HIP_TRY(ctx, hipMemcpyAsync(t.data(), tsrc, 8 * pl, hipMemcpyDeviceToHost, st));
       HIP_TRY(ctx, hipStreamSynchronize(st));
       for (int64_t i = 0; i < n; ++i) {
         const int64_t v = g->inv[(size_t)i];
         for (int64_t k = 0; k < K; ++k)
-          out->photons[i * K + k] = (o[(size_t)(k * pl + v)] * t[(size_t)v]) * h.unit;
+          out->photons[i * K + k] = (o[(size_t)at(v, k)] * t[(size_t)v]) * h.unit;
       }
     } else {
-      std::vector<float> o((size_t)(K * pl)), t((size_t)pl);
-      HIP_TRY(ctx, hipMemcpyAsync(o.data(), src, 4 * K * pl, hipMemcpyDeviceToHost, st));
+      std::vector<float> o((size_t)words), t((size_t)pl);
+      HIP_TRY(ctx, hipMemcpyAsync(o.data(), src, 4 * words, hipMemcpyDeviceToHost, st));
       HIP_TRY(ctx, hipMemcpyAsync(t.data(), tsrc, 4 * pl, hipMemcpyDeviceToHost, st));
       HIP_TRY(ctx, hipStreamSynchronize(st));
       for (int64_t i = 0; i < n; ++i) {
         const int64_t v = g->inv[(size_t)i];
         for (int64_t k = 0; k < K; ++k) {
-          const float ov = o[(size_t)(k * pl + v)] * t[(size_t)v];
+          const float ov = o[(size_t)at(v, k)] * t[(size_t)v];
           out->photons[i * K + k] = (double)ov * h.unit;
         }
       }
@@ -1199,22 +1213,26 @@ int sx_grid_restore(sx_ctx *ctx, sx_grid_id id, const sx_state_in *in) {
       if (!(in->photons[q] >= 0.0) || !std::isfinite(in->photons[q]))
         return fail(ctx, SX_EINVAL, "restored photons must be finite and >= 0");
     // the restored field is the outgoing share itself: Ipre = O, T = 1
+    const int64_t words = (h.ntiles + 1) * (int64_t)h.kb * sx::kTile * h.bb;
+    auto at = [&](int64_t v, int64_t k) {
+      return (((v >> 6) * h.kb + k / h.bb) * sx::kTile + (v & 63)) * h.bb + k % h.bb;
+    };
     void *dst = h.o[cur.parity];
     void *tdst = h.t[cur.parity];
     const int64_t pl = h.plane;
     if (h.precision == SX_FP64) {
-      std::vector<double> o((size_t)(K * pl), 0.0), t((size_t)pl, 1.0);
+      std::vector<double> o((size_t)words, 0.0), t((size_t)pl, 1.0);
       for (int64_t i = 0; i < n; ++i)
         for (int64_t k = 0; k < K; ++k)
-          o[(size_t)(k * pl + g->inv[(size_t)i])] = in->photons[i * K + k] / h.unit;
-      HIP_TRY(ctx, hipMemcpy(dst, o.data(), 8 * K * pl, hipMemcpyHostToDevice));
+          o[(size_t)at(g->inv[(size_t)i], k)] = in->photons[i * K + k] / h.unit;
+      HIP_TRY(ctx, hipMemcpy(dst, o.data(), 8 * words, hipMemcpyHostToDevice));
       HIP_TRY(ctx, hipMemcpy(tdst, t.data(), 8 * pl, hipMemcpyHostToDevice));
     } else {
-      std::vector<float> o((size_t)(K * pl), 0.0f), t((size_t)pl, 1.0f);
+      std::vector<float> o((size_t)words, 0.0f), t((size_t)pl, 1.0f);
       for (int64_t i = 0; i < n; ++i)
         for (int64_t k = 0; k < K; ++k)
-          o[(size_t)(k * pl + g->inv[(size_t)i])] = (float)(in->photons[i * K + k] / h.unit);
-      HIP_TRY(ctx, hipMemcpy(dst, o.data(), 4 * K * pl, hipMemcpyHostToDevice));
+          o[(size_t)at(g->inv[(size_t)i], k)] = (float)(in->photons[i * K + k] / h.unit);
+      HIP_TRY(ctx, hipMemcpy(dst, o.data(), 4 * words, hipMemcpyHostToDevice));
       HIP_TRY(ctx, hipMemcpy(tdst, t.data(), 4 * pl, hipMemcpyHostToDevice));
     }
   }

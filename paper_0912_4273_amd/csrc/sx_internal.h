@@ -27,10 +27,19 @@ constexpr uint64_t kEmptyWord = 0x7FFFFFFFFFFFFFFFull;  // 7 x 511
 // In-word of a (vertex, bin) pair (uint64): which neighbours send this bin
 // here.  Bits 9e..9e+8 (e = 0..6) hold the e-th sender, ascending sender
 // id, as a halo index (or row slot in a direct tile); 511 = none.
-// Records (uint32, grouped by (tile, bin), sorted by lane) carry what does
-// not fit: senders beyond the seventh, then the vertex's shares of source
-// emission for the bin.  Record = lane << 26 | kind << 25 | index, kind 0 =
-// sender (halo index or row slot), kind 1 = emission amount index.
+// Records (uint32, grouped by (tile, bin), sorted by bin then lane) carry
+// what does not fit: senders beyond the seventh, then the vertex's shares of
+// source emission for the bin.  Record = lane << 26 | (bin mod BB) << 24 |
+// kind << 23 | index; kind 0 = sender (halo index or row slot), kind 1 =
+// emission amount index.
+//
+// Photon field layout: 16-byte blocks of BB = 16 / sizeof(photon) bins per
+// vertex (4 fp32 or 2 fp64), element (v, k) at block
+// ((v / 64) * KB + k / BB) * 64 + v % 64, component k % BB, KB = ceil(K/BB).
+// One extra tile past the last holds zeros.  In-words use the same block
+// order with BB 64-bit words per block.
+constexpr int kBlockBytes = 16;
+constexpr int kRecIdxBits = 23;
 // Forward word of a (vertex, bin) pair (selection result):
 //   bits 0..20 : three 7-bit slots, best first (127 = none)
 //   bits 21..22: m, the number selected
@@ -43,6 +52,8 @@ struct GridDev {
   int32_t ntiles;     // npad / kTile
   int32_t k;          // bins
   int32_t kw;         // ceil(k / 16): words of packed m per lane and tile
+  int32_t bb;         // bins per 16-byte block (4 fp32, 2 fp64)
+  int32_t kb;         // blocks per vertex, ceil(k / bb)
   int32_t n_sub;      // chemistry substeps
   int32_t mpb;        // max neighbours per bin
   int32_t precision;  // 0 fp64, 1 fp32 transport
@@ -53,7 +64,7 @@ struct GridDev {
   double unit;        // photons per stored unit (power of two)
   double dt;
   double cos_min;
-  int64_t plane;      // elements per bin plane of O (npad + a zero tile)
+  int64_t plane;      // entries of the per-vertex arrays t[] (npad + a zero tile)
   int64_t n_edges;
   // graph (reordered)
   const int32_t *row_ptr;   // [npad+1]
@@ -64,7 +75,7 @@ struct GridDev {
   // selection products
   uint32_t *fwd;            // [npad*K]
   uint8_t *ebin;            // [E]
-  uint64_t *inw;            // [ntiles][K][64]
+  uint64_t *inw;            // [ntiles][kb][64][bb]
   uint32_t *mbits;          // [ntiles][kw][64]
   int32_t *rec_cnt;         // [ntiles*K+1] scratch: records per (tile, bin)
   int32_t *rec_ptr;         // [ntiles*K+1]
@@ -84,8 +95,8 @@ struct GridDev {
   const double *bcoef;      // [npad] alpha_B * n_H
   double *y;                // [npad] neutral fraction
   double *nin;              // [npad] photons in, last step
-  void *o[2];               // [K*plane] photons per selected neighbour before
-                            // attenuation, I/m (fp32 or fp64), double buffered
+  void *o[2];               // [(ntiles+1)*kb*64] blocks: photons per selected
+                            // neighbour before attenuation, I/m, double buffered
   void *t[2];               // [plane] transmitted fraction T of each vertex
                             // in the step that wrote o[] (fp32 or fp64)
   double *tally;            // [ntiles*3] absorbed (cum), escaped (cum), in flight
@@ -99,6 +110,7 @@ hipError_t launch_inlist_count(const GridDev *dg, const GridDev &hg, hipStream_t
 hipError_t launch_scan(int32_t *cnt, int32_t *ptr, int32_t n, hipStream_t s);
 hipError_t launch_inlist_fill(const GridDev *dg, const GridDev &hg, hipStream_t s);
 hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s);
+hipError_t launch_clear_inw(const GridDev &hg, hipStream_t s);
 hipError_t launch_reset_state(GridDev *dg, const GridDev &hg, const double *y0,
                               hipStream_t s);
 // One step for a batch: `grids` is the slot table (or one grid's entry when

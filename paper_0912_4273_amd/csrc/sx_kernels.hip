@@ -152,7 +152,8 @@ __device__ __forceinline__ int sender_index(const GridDev &g, bool direct,
   return direct ? e - rb : (int)g.edge_hidx[e];
 }
 
-constexpr uint32_t kRecEmission = 1u << 25;
+constexpr uint32_t kRecEmission = 1u << kRecIdxBits;
+constexpr uint32_t kRecIdxMask = (1u << kRecIdxBits) - 1u;
 
 __global__ void k_inlist_count(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
@@ -181,13 +182,14 @@ __global__ void k_inlist_fill(const GridDev *__restrict__ gp) {
   const int tile = (int)(t / K), k = (int)(t - (int64_t)tile * K);
   const bool direct = g.tile_direct[tile] != 0;
   int64_t rp = g.rec_ptr[t];
-  uint64_t *out = g.inw + t * kTile;
+  const int kb = k / g.bb, b = k - kb * g.bb;
+  uint64_t *out = g.inw + (((int64_t)tile * g.kb + kb) * kTile) * g.bb + b;
   for (int lane = 0; lane < kTile; ++lane) {
     const int j = tile * kTile + lane;
     uint64_t w = kEmptyWord;
     if (j < g.n) {
       const int rb = g.row_ptr[j], re = g.row_ptr[j + 1];
-      const uint32_t lbits = (uint32_t)lane << 26;
+      const uint32_t lbits = ((uint32_t)lane << 26) | ((uint32_t)b << 24);
       int c = 0;
       for (int e = rb; e < re; ++e) {
         if (!fwd_selects(g.fwd[(int64_t)g.nbr[e] * K + k], g.rev[e])) continue;
@@ -203,7 +205,7 @@ __global__ void k_inlist_fill(const GridDev *__restrict__ gp) {
       for (int q = g.em_ptr[j]; q < g.em_ptr[j + 1]; ++q)
         if (g.em_k[q] == k && rp < g.rec_cap) g.rec[rp++] = lbits | kRecEmission | (uint32_t)q;
     }
-    out[lane] = w;
+    out[(int64_t)lane * g.bb] = w;
   }
 }
 
@@ -331,22 +333,30 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
   // accesses are volatile so that the compiler keeps every store and load in
   // program order (it may not forward a lane's own store past another
   // lane's); LDS executes a wave's operations in issue order.
+  constexpr int BB = kBlockBytes / sizeof(P);
+  typedef P V __attribute__((ext_vector_type(BB)));
+  typedef uint64_t W2 __attribute__((ext_vector_type(2)));
   constexpr int NQ = DIRECT ? 1 : kStageQ;
   const int K = G->k;
-  const uint32_t plane = (uint32_t)G->plane;
+  const int KB = G->kb;
   const int j = tile * kTile + lane;
   const bool valid = j < G->n;
   const int par = G->parity;
-  const SX_G P *__restrict__ oin = gld((const P *)G->o[par]);
+  const SX_G V *__restrict__ oin = gld((const V *)G->o[par]);
   const SX_G P *__restrict__ tin = gld((const P *)G->t[par]);
-  SX_G P *__restrict__ oout = gst((P *)G->o[par ^ 1]);
+  SX_G V *__restrict__ oout = gst((V *)G->o[par ^ 1]);
   const SX_G int32_t *__restrict__ nbr = gld(G->nbr);
   const SX_G int32_t *__restrict__ rowp = gld(G->row_ptr);
   const int rb = rowp[j];
-  const SX_G uint64_t *__restrict__ iw = gld(G->inw) + (int64_t)tile * K * kTile + lane;
+  const SX_G W2 *__restrict__ iw =
+      gld((const W2 *)(G->inw + ((int64_t)tile * KB * kTile + lane) * BB));
   const SX_G int32_t *__restrict__ rptr = gld(G->rec_ptr) + (int64_t)tile * K;
   const SX_G uint32_t *__restrict__ rec = gld(G->rec);
   const SX_G double *__restrict__ ema = gld(G->em_amt);
+  // block of (vertex v, block kb)
+  auto blk = [&](uint32_t v, int kb) -> uint32_t {
+    return ((v >> 6) * (uint32_t)KB + (uint32_t)kb) * 64u + (v & 63u);
+  };
 
   // halo of the tile and its senders' T (once per step)
   uint32_t hv[NQ];
@@ -363,7 +373,10 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
       hv[q] = idx < hlen ? (uint32_t)hvid[hp + idx] : zero;
       th[q] = tin[hv[q]];
     }
-    if (lane == 63) hl[kZeroSlot] = P(0);
+    if (lane == 63) {
+#pragma unroll
+      for (int b = 0; b < BB; ++b) hl[kZeroSlot * BB + b] = P(0);
+    }
   }
   // packed m(j, k), 16 bins per word, consumed 2 bits at a time
   const SX_G uint32_t *__restrict__ mbp = gld(G->mbits) + (int64_t)tile * G->kw * 64 + lane;
@@ -371,20 +384,26 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
 #pragma unroll
   for (int q = 0; q < 6; ++q) mwv[q] = q < G->kw ? mbp[q * 64] : 0u;
 
-  // ring of loads in flight, slot = k mod 3
-  P st[3][NQ];
-  uint64_t wq[3];
-  uint32_t rq[3];   // this lane's first record of the bin, or ~0
-  int rn[3];        // records of the bin
-  int rs[3];        // index of the bin's first record
-  auto issue = [&](int k, int slot) {
+  // ring of loads in flight, slot = block mod 2
+  V st[2][NQ];
+  uint64_t wq[2][BB];
+  uint32_t rq[2];   // this lane's first record of the block, or ~0
+  int rn[2];        // records of the block
+  int rs[2];        // index of the block's first record
+  auto issue = [&](int kb, int slot) {
     if constexpr (!DIRECT) {
-      const SX_G P *__restrict__ pk = oin + (uint32_t)k * plane;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) st[slot][q] = pk[hv[q]];
+      for (int q = 0; q < NQ; ++q) st[slot][q] = oin[blk(hv[q], kb)];
     }
-    wq[slot] = iw[(int64_t)k * kTile];
-    const int r0 = rptr[k], r1 = rptr[k + 1];
+#pragma unroll
+    for (int h = 0; h < BB / 2; ++h) {
+      const W2 w2 = iw[(int64_t)kb * kTile * (BB / 2) + h];
+      wq[slot][2 * h] = w2.x;
+      wq[slot][2 * h + 1] = w2.y;
+    }
+    const int k0 = kb * BB;
+    const int k1 = k0 + BB < K ? k0 + BB : K;
+    const int r0 = rptr[k0], r1 = rptr[k1];
     rn[slot] = r1 - r0;
     rs[slot] = r0;
     rq[slot] = lane < r1 - r0 ? rec[r0 + lane] : ~0u;
@@ -392,25 +411,43 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
 
   P nin_p = P(0);    // sum over bins of I, in bin order
   P esc_p = P(0);    // sum of I over bins that leave the domain
-  auto bin = [&](int k, int slot) {
-    if (k + 2 < K) issue(k + 2, (slot + 2) % 3);
-    const uint64_t w = wq[slot];
-    P acc = P(0);
+  auto block = [&](int kb, int slot) {
+    if (kb + 1 < KB) issue(kb + 1, slot ^ 1);
+    P acc[BB];
     if constexpr (!DIRECT) {
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) hl[64 * q + lane] = mul_rn(st[slot][q], th[q]);
+      for (int q = 0; q < NQ; ++q) {
+        const V v = st[slot][q];
+        V pr;
+#pragma unroll
+        for (int b = 0; b < BB; ++b) pr[b] = mul_rn(v[b], th[q]);
+        *(volatile V *)(hl + (64 * q + lane) * BB) = pr;
+      }
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
-      for (int e = 0; e < kWordEntries; ++e) acc += hl[(uint32_t)(w >> (9 * e)) & 511u];
-    } else {
-      const SX_G P *__restrict__ pk = oin + (uint32_t)k * plane;
+      for (int b = 0; b < BB; ++b) {
+        const uint64_t w = wq[slot][b];
+        P a = P(0);
 #pragma unroll
-      for (int e = 0; e < kWordEntries; ++e) {
-        const uint32_t idx = (uint32_t)(w >> (9 * e)) & 511u;
-        if (idx != 511u) {
-          const uint32_t src = (uint32_t)nbr[rb + idx];
-          acc += mul_rn(pk[src], tin[src]);
+        for (int e = 0; e < kWordEntries; ++e)
+          a += hl[((uint32_t)(w >> (9 * e)) & 511u) * BB + b];
+        acc[b] = a;
+      }
+    } else {
+      const SX_G P *__restrict__ oin_p = (const SX_G P *)oin;
+#pragma unroll
+      for (int b = 0; b < BB; ++b) {
+        const uint64_t w = wq[slot][b];
+        P a = P(0);
+#pragma unroll
+        for (int e = 0; e < kWordEntries; ++e) {
+          const uint32_t idx = (uint32_t)(w >> (9 * e)) & 511u;
+          if (idx != 511u) {
+            const uint32_t src = (uint32_t)nbr[rb + idx];
+            a += mul_rn(oin_p[blk(src, kb) * BB + b], tin[src]);
+          }
         }
+        acc[b] = a;
       }
     }
     const int nrec = __builtin_amdgcn_readfirstlane(rn[slot]);
@@ -418,63 +455,74 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
       const uint32_t r = c0 == 0 ? rq[slot]
                                  : (lane < nrec - c0 ? rec[rs[slot] + c0 + lane] : ~0u);
       const bool has = r != ~0u;
-      const int tgt = has ? (int)(r >> 26) : -1 - lane;
-      const uint32_t idx = r & 0x1ffffffu;
+      // key = bin-in-block * 64 + receiver lane; records are sorted by key
+      const int key = has ? (int)(((r >> 24) & 3u) * 64u + (r >> 26)) : -1 - lane;
+      const uint32_t idx = r & kRecIdxMask;
+      const int rb_ = (int)((r >> 24) & 3u);
       P v = P(0);
       if (has) {
         if (r & kRecEmission) {
           v = (P)ema[idx];
         } else if constexpr (!DIRECT) {
-          v = hl[idx];
+          v = hl[idx * BB + rb_];
         } else {
-          const uint32_t src = (uint32_t)nbr[rowp[tile * kTile + tgt] + idx];
-          v = mul_rn(oin[(uint32_t)k * plane + src], tin[src]);
+          const uint32_t src = (uint32_t)nbr[rowp[tile * kTile + (int)(r >> 26)] + idx];
+          v = mul_rn(((const SX_G P *)oin)[blk(src, kb) * BB + rb_], tin[src]);
         }
       }
-      const int tnext = __shfl_down(tgt, 1);
-      if (__ballot(has && lane < 63 && tnext == tgt)) {
-        // a receiver with several records: segmented inclusive scan
+      const int knext = __shfl_down(key, 1);
+      if (__ballot(has && lane < 63 && knext == key)) {
+        // a receiver with several records in one bin: segmented scan
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
           const P vo = __shfl_up(v, off);
-          const int to = __shfl_up(tgt, off);
-          if (lane >= off && to == tgt) v += vo;
+          const int ko = __shfl_up(key, off);
+          if (lane >= off && ko == key) v += vo;
         }
       }
-      xchg[lane] = P(0);
+      // hand-over slot of (receiver lane, bin in block): lane * BB + bin
+      *(volatile V *)(xchg + lane * BB) = V(0);
       __builtin_amdgcn_wave_barrier();
-      if (has && (lane == 63 || tnext != tgt)) xchg[tgt] = v;
+      if (has && (lane == 63 || knext != key))
+        xchg[(int)(r >> 26) * BB + rb_] = v;
       __builtin_amdgcn_wave_barrier();
-      acc += xchg[lane];
+      const V got = *(volatile V *)(xchg + lane * BB);
+#pragma unroll
+      for (int b = 0; b < BB; ++b) acc[b] += got[b];
       __builtin_amdgcn_wave_barrier();
     }
     __builtin_amdgcn_wave_barrier();
-    // m(j, k) and the stored share
-    const uint32_t m = mwv[0] & 3u;
-    mwv[0] >>= 2;
-    if ((k & 15) == 15) {
+    V out;
 #pragma unroll
-      for (int q = 0; q < 5; ++q) mwv[q] = mwv[q + 1];
+    for (int b = 0; b < BB; ++b) {
+      const int k = kb * BB + b;
+      P ipre = P(0);
+      if (k < K) {
+        const uint32_t m = mwv[0] & 3u;
+        mwv[0] >>= 2;
+        if ((k & 15) == 15) {
+#pragma unroll
+          for (int q = 0; q < 5; ++q) mwv[q] = mwv[q + 1];
+        }
+        nin_p += acc[b];
+        esc_p += m == 0u ? acc[b] : P(0);
+        if constexpr (sizeof(P) == 8) {
+          ipre = m == 0u ? 0.0 : (m == 1u ? acc[b] : (m == 2u ? acc[b] * 0.5 : acc[b] / 3.0));
+        } else {
+          // 1/m for m = 1, 2, 3 as (m^2 - 6m + 11) / 6 (no table lookup)
+          const float fm = (float)(int)(m * m - 6u * m + 11u) * (1.0f / 6.0f);
+          ipre = m == 0u ? 0.0f : acc[b] * fm;
+        }
+      }
+      out[b] = ipre;
     }
-    nin_p += acc;
-    esc_p += m == 0u ? acc : P(0);
-    P ipre;
-    if constexpr (sizeof(P) == 8) {
-      ipre = m == 0u ? 0.0 : (m == 1u ? acc : (m == 2u ? acc * 0.5 : acc / 3.0));
-    } else {
-      // 1/m for m = 1, 2, 3 as (m^2 - 6m + 11) / 6 (no table lookup)
-      const float fm = (float)(int)(m * m - 6u * m + 11u) * (1.0f / 6.0f);
-      ipre = m == 0u ? 0.0f : acc * fm;
-    }
-    if (valid) oout[(uint32_t)k * plane + j] = ipre;
+    if (valid) oout[blk((uint32_t)j, kb)] = out;
   };
 
-  if (0 < K) issue(0, 0);
-  if (1 < K) issue(1, 1);
-  for (int k0 = 0; k0 < K; k0 += 3) {
-    bin(k0, 0);
-    if (k0 + 1 < K) bin(k0 + 1, 1);
-    if (k0 + 2 < K) bin(k0 + 2, 2);
+  if (0 < KB) issue(0, 0);
+  for (int kb = 0; kb < KB; kb += 2) {
+    block(kb, 0);
+    if (kb + 1 < KB) block(kb + 1, 1);
   }
 
   double A = 0.0, T = 1.0;
@@ -513,8 +561,9 @@ template <typename P>
 __global__ __launch_bounds__(256) void k_sweep(
     const GridDev *__restrict__ grids, const int2 *__restrict__ tile_map,
     int32_t n_tiles) {
-  __shared__ P hbuf[kTilesPerBlock][kZeroSlot + 1];
-  __shared__ P xbuf[kTilesPerBlock][kTile];
+  constexpr int BB = kBlockBytes / sizeof(P);
+  __shared__ P hbuf[kTilesPerBlock][(kZeroSlot + 1) * BB];
+  __shared__ P xbuf[kTilesPerBlock][kTile * BB];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // Workgroups are dealt round-robin to the 8 XCDs; renumber them so each
@@ -603,6 +652,10 @@ hipError_t launch_inlist_count(const GridDev *dg, const GridDev &hg,
   return hipGetLastError();
 }
 
+hipError_t launch_clear_inw(const GridDev &hg, hipStream_t s) {
+  return fill<uint64_t>(hg.inw, kEmptyWord, (int64_t)hg.ntiles * hg.kb * kTile * hg.bb, s);
+}
+
 hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s) {
   hipLaunchKernelGGL(k_mbits, dim3(blocks_for(hg.npad, 256)), dim3(256), 0, s, dg);
   return hipGetLastError();
@@ -623,7 +676,8 @@ hipError_t launch_inlist_fill(const GridDev *dg, const GridDev &hg,
 hipError_t launch_reset_state(GridDev *dg, const GridDev &hg, const double *y0,
                               hipStream_t s) {
   hipError_t e;
-  const int64_t nk = (int64_t)hg.k * hg.plane;   // includes the zero tiles
+  // photon blocks of all tiles plus the zero tile, in photon words
+  const int64_t nk = ((int64_t)hg.ntiles + 1) * hg.kb * kTile * hg.bb;
   for (int b = 0; b < 2; ++b) {
     if (hg.precision == 0) {
       e = fill<double>((double *)hg.o[b], 0.0, nk, s);
