@@ -21,6 +21,9 @@ namespace sx {
 // the global address space makes it emit global (not flat) loads and stores,
 // which do not share the LDS wait counter.
 #define SX_G __attribute__((address_space(1)))
+// LDS pointers carry their address space explicitly: volatile accesses
+// through a generic pointer would be emitted as FLAT instructions.
+#define SX_L __attribute__((address_space(3)))
 template <typename T>
 __device__ __forceinline__ const SX_G T *gld(const T *p) {
   return (const SX_G T *)p;
@@ -327,8 +330,8 @@ __device__ __forceinline__ double chem_step(double y, double nin, double dt,
 // 3. Per-tile photon accounting in fp64, fixed-order wave reduction.
 template <typename P, bool DIRECT>
 __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int tile,
-                                           int lane, volatile P *hl,
-                                           volatile P *xchg) {
+                                           int lane, volatile SX_L P *hl,
+                                           volatile SX_L P *xchg) {
   // hl and xchg carry data between lanes of this wave through LDS.  The
   // accesses are volatile so that the compiler keeps every store and load in
   // program order (it may not forward a lane's own store past another
@@ -421,7 +424,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
         V pr;
 #pragma unroll
         for (int b = 0; b < BB; ++b) pr[b] = mul_rn(v[b], th[q]);
-        *(volatile V *)(hl + (64 * q + lane) * BB) = pr;
+        *(volatile SX_L V *)(hl + (64 * q + lane) * BB) = pr;
       }
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -481,12 +484,12 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
         }
       }
       // hand-over slot of (receiver lane, bin in block): lane * BB + bin
-      *(volatile V *)(xchg + lane * BB) = V(0);
+      *(volatile SX_L V *)(xchg + lane * BB) = V(0);
       __builtin_amdgcn_wave_barrier();
       if (has && (lane == 63 || knext != key))
         xchg[(int)(r >> 26) * BB + rb_] = v;
       __builtin_amdgcn_wave_barrier();
-      const V got = *(volatile V *)(xchg + lane * BB);
+      const V got = *(volatile SX_L V *)(xchg + lane * BB);
 #pragma unroll
       for (int b = 0; b < BB; ++b) acc[b] += got[b];
       __builtin_amdgcn_wave_barrier();
@@ -581,10 +584,12 @@ __global__ __launch_bounds__(256) void k_sweep(
   }
   const GridDev *__restrict__ G = grids + gi;
   if (G->remaining <= 0) return;
+  volatile SX_L P *hl = (volatile SX_L P *)hbuf[wave];
+  volatile SX_L P *xc = (volatile SX_L P *)xbuf[wave];
   if (gld(G->tile_direct)[tile] != 0)
-    sweep_tile<P, true>(G, tile, lane, hbuf[wave], xbuf[wave]);
+    sweep_tile<P, true>(G, tile, lane, hl, xc);
   else
-    sweep_tile<P, false>(G, tile, lane, hbuf[wave], xbuf[wave]);
+    sweep_tile<P, false>(G, tile, lane, hl, xc);
 }
 
 struct SlotVals {
