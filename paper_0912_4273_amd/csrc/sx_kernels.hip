@@ -328,6 +328,8 @@ __device__ __forceinline__ double chem_step(double y, double nin, double dt,
 //    bins with no forward neighbour (m = 0, they leave the domain) add up.
 // 2. Chemistry in fp64 -> y, absorbed A, transmitted fraction T' of j.
 // 3. Per-tile photon accounting in fp64, fixed-order wave reduction.
+constexpr int kHaloPlane = kZeroSlot + 1;   // LDS words per staged bin
+
 template <typename P, bool DIRECT>
 __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int tile,
                                            int lane, volatile SX_L P *hl,
@@ -355,6 +357,9 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
       gld((const W2 *)(G->inw + ((int64_t)tile * KB * kTile + lane) * BB));
   const SX_G int32_t *__restrict__ rptr = gld(G->rec_ptr) + (int64_t)tile * K;
   const SX_G uint32_t *__restrict__ rec = gld(G->rec);
+  // first record of every block of the tile, lane kb holding block kb's
+  // (KB < 64), so that no load inside the block loop waits on another
+  const int rpl = lane <= KB ? rptr[lane * BB < K ? lane * BB : K] : 0;
   const SX_G double *__restrict__ ema = gld(G->em_amt);
   // block of (vertex v, block kb)
   auto blk = [&](uint32_t v, int kb) -> uint32_t {
@@ -378,7 +383,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
     }
     if (lane == 63) {
 #pragma unroll
-      for (int b = 0; b < BB; ++b) hl[kZeroSlot * BB + b] = P(0);
+      for (int b = 0; b < BB; ++b) hl[b * kHaloPlane + kZeroSlot] = P(0);
     }
   }
   // packed m(j, k), 16 bins per word, consumed 2 bits at a time
@@ -390,7 +395,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
   // ring of loads in flight, slot = block mod 2
   V st[2][NQ];
   uint64_t wq[2][BB];
-  uint32_t rq[2];   // this lane's first record of the block, or ~0
+  uint32_t rq[2];   // this lane's first record of the block (if lane < rn)
   int rn[2];        // records of the block
   int rs[2];        // index of the block's first record
   auto issue = [&](int kb, int slot) {
@@ -404,27 +409,31 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
       wq[slot][2 * h] = w2.x;
       wq[slot][2 * h + 1] = w2.y;
     }
-    const int k0 = kb * BB;
-    const int k1 = k0 + BB < K ? k0 + BB : K;
-    const int r0 = rptr[k0], r1 = rptr[k1];
-    rn[slot] = r1 - r0;
+    const int r0 = __builtin_amdgcn_readlane(rpl, kb);
+    const int nr = __builtin_amdgcn_readlane(rpl, kb + 1) - r0;
+    rn[slot] = nr;
     rs[slot] = r0;
-    rq[slot] = lane < r1 - r0 ? rec[r0 + lane] : ~0u;
+    // unconditional and in bounds (the pool holds one spare entry); lanes
+    // past the block's records are masked where the value is used
+    rq[slot] = rec[r0 + (lane < nr ? lane : (nr > 0 ? nr - 1 : 0))];
   };
 
   P nin_p = P(0);    // sum over bins of I, in bin order
   P esc_p = P(0);    // sum of I over bins that leave the domain
   auto block = [&](int kb, int slot) {
-    if (kb + 1 < KB) issue(kb + 1, slot ^ 1);
+    // always issued (the last block re-reads itself from L2): a load that
+    // is skipped on some path leaves the wait counts conservative, and the
+    // wave would stall on the loads it has just issued
+    issue(kb + 1 < KB ? kb + 1 : kb, slot ^ 1);
     P acc[BB];
     if constexpr (!DIRECT) {
+      // one LDS plane per bin of the block: a bin's reads spread over all
+      // 64 banks
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const V v = st[slot][q];
-        V pr;
 #pragma unroll
-        for (int b = 0; b < BB; ++b) pr[b] = mul_rn(v[b], th[q]);
-        *(volatile SX_L V *)(hl + (64 * q + lane) * BB) = pr;
+        for (int b = 0; b < BB; ++b) hl[b * kHaloPlane + 64 * q + lane] = mul_rn(v[b], th[q]);
       }
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -433,7 +442,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
         P a = P(0);
 #pragma unroll
         for (int e = 0; e < kWordEntries; ++e)
-          a += hl[((uint32_t)(w >> (9 * e)) & 511u) * BB + b];
+          a += hl[b * kHaloPlane + ((uint32_t)(w >> (9 * e)) & 511u)];
         acc[b] = a;
       }
     } else {
@@ -455,8 +464,8 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
     }
     const int nrec = __builtin_amdgcn_readfirstlane(rn[slot]);
     for (int c0 = 0; c0 < nrec; c0 += 64) {
-      const uint32_t r = c0 == 0 ? rq[slot]
-                                 : (lane < nrec - c0 ? rec[rs[slot] + c0 + lane] : ~0u);
+      const uint32_t r = lane >= nrec - c0 ? ~0u
+                         : (c0 == 0 ? rq[slot] : rec[rs[slot] + c0 + lane]);
       const bool has = r != ~0u;
       // key = bin-in-block * 64 + receiver lane; records are sorted by key
       const int key = has ? (int)(((r >> 24) & 3u) * 64u + (r >> 26)) : -1 - lane;
@@ -467,7 +476,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
         if (r & kRecEmission) {
           v = (P)ema[idx];
         } else if constexpr (!DIRECT) {
-          v = hl[idx * BB + rb_];
+          v = hl[rb_ * kHaloPlane + idx];
         } else {
           const uint32_t src = (uint32_t)nbr[rowp[tile * kTile + (int)(r >> 26)] + idx];
           v = mul_rn(((const SX_G P *)oin)[blk(src, kb) * BB + rb_], tin[src]);
@@ -565,7 +574,7 @@ __global__ __launch_bounds__(256) void k_sweep(
     const GridDev *__restrict__ grids, const int2 *__restrict__ tile_map,
     int32_t n_tiles) {
   constexpr int BB = kBlockBytes / sizeof(P);
-  __shared__ P hbuf[kTilesPerBlock][(kZeroSlot + 1) * BB];
+  __shared__ P hbuf[kTilesPerBlock][kHaloPlane * BB];
   __shared__ P xbuf[kTilesPerBlock][kTile * BB];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
