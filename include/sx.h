@@ -212,14 +212,65 @@ int sx_mem_info(sx_ctx *ctx, uint64_t *used, uint64_t *budget);
 /* The hipStream_t the context enqueues on. */
 void *sx_stream(sx_ctx *ctx);
 
-/* Kernel timing.  With enable != 0, every step-kernel launch (the fused
- * sweep) is bracketed by a pair of HIP events on the context stream;
- * sx_profile_read waits for them and returns the number of launches timed
- * since the last read and the total, shortest and longest duration in
- * milliseconds, then starts a new count.  Any out-pointer may be NULL. */
+/* Kernel timing.  With enable != 0, every sweep-kernel launch made singly,
+ * and every graph replay (graph_sweeps sweeps back to back), is bracketed by
+ * a pair of HIP events on the context stream; sx_profile_read waits for them
+ * and returns the number of sweep launches timed since the last read, their
+ * total time, and the shortest and longest time per launch (a replay counts
+ * as its launches, each at the replay's average, which includes the gaps
+ * between its kernels) in milliseconds, then starts a new count.  Any
+ * out-pointer may be NULL. */
 int sx_profile(sx_ctx *ctx, int32_t enable);
 int sx_profile_read(sx_ctx *ctx, int64_t *launches, double *total_ms,
                     double *min_ms, double *max_ms);
+
+/* ---- sweep schedule --------------------------------------------------
+ * How the sweeps of a step are launched.  A schedule only changes the order
+ * in which independent 64-vertex tiles run (each tile's arithmetic and every
+ * sum order are fixed), so results are bitwise the same under every
+ * schedule.
+ *   tiles_per_group  tiles per workgroup: 1, 2 or 4
+ *   order            SX_ORDER_GRID: grid by grid, each in its internal
+ *                    (Hilbert) order; SX_ORDER_DIRECT_FIRST: tiles too large
+ *                    for LDS staging first, then the rest
+ *   xcd_contiguous   1: each of the 8 XCDs runs a contiguous eighth of the
+ *                    tile list (its L2 sees one neighbourhood); 0: the
+ *                    hardware's round-robin
+ *   graph_sweeps     > 0: sweeps are launched as replays of one HIP graph of
+ *                    that many sweeps (the rest singly); 0: one launch per
+ *                    sweep and precision
+ * Default {4, SX_ORDER_GRID, 1, 50}. */
+#define SX_ORDER_GRID 0
+#define SX_ORDER_DIRECT_FIRST 1
+#define SX_MAX_GRAPH_SWEEPS 4096
+typedef struct sx_schedule {
+    int32_t tiles_per_group;
+    int32_t order;
+    int32_t xcd_contiguous;
+    int32_t graph_sweeps;
+} sx_schedule;
+
+/* Schedule for steps over exactly this list of grids, in this order (n = 0:
+ * the default for every list without its own).  Synchronous.  Errors:
+ * SX_EINVAL (invalid schedule), SX_ENOTFOUND. */
+int sx_set_schedule(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, const sx_schedule *s);
+
+/* The schedule a step over this list uses (n = 0: the default), and the
+ * autotuner's time per sweep in microseconds for it (0 if not tuned);
+ * us_per_sweep may be NULL. */
+int sx_get_schedule(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, sx_schedule *out,
+                    double *us_per_sweep);
+
+/* trials > 0 turns the autotuner on: the first sx_step / sx_solve over a grid
+ * list that has no schedule of its own, if it asks for at least 4 x trials x
+ * (number of candidates) sweeps, runs `trials` of those sweeps under each
+ * candidate schedule (tiles per group 1, 2, 4; XCD-contiguous or not; direct
+ * tiles first or not when the list has any), timed with HIP events, and
+ * keeps the fastest for that list (graph_sweeps is kept from the default).
+ * The sweeps count toward the step; the step synchronises the stream while
+ * tuning.  trials = 0 turns it off.  Errors: SX_EINVAL (trials outside
+ * [0, 64]). */
+int sx_autotune(sx_ctx *ctx, int32_t trials);
 
 const char *sx_strerror(int code);
 const char *sx_last_error(const sx_ctx *ctx);

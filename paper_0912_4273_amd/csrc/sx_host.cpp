@@ -39,7 +39,6 @@ struct Grid {
   sx_grid_id id = 0;
   int slot = -1;
   GridDev hg{};
-  int kmax = 0;
   int64_t n_em = 0;
   std::vector<int32_t> perm;           // new -> original
   std::vector<int32_t> inv;            // original -> new
@@ -55,12 +54,27 @@ struct Grid {
   double esc_emit = 0.0;    // photons per step with no way out of a beam source
   double base_sweeps = 0.0, base_emitted = 0.0, base_escaped = 0.0;
   int64_t n_direct = 0;     // tiles whose halo is too large for LDS staging
+  std::vector<uint8_t> tile_direct;
 };
 
-struct BatchCache {
-  std::vector<int32_t> key;
-  int2 *map = nullptr;
-  int32_t n_tiles = 0;
+// How the sweeps of one list of grids are launched: one kernel launch per
+// precision present, the tile lists and advance lists they read, and a HIP
+// graph of graph_sweeps consecutive sweeps, replayed.
+struct Plan {
+  std::vector<int32_t> key;   // slots, in the caller's order
+  sx_schedule sched{};
+  bool fixed = false;         // set by the caller or by the autotuner
+  bool built = false;
+  std::vector<sx::SweepLaunch> launches;
+  std::vector<void *> dev;    // tile maps and advance lists
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  double tuned_us = 0.0;      // autotuner's best time per sweep
+};
+
+struct ProfEv {
+  hipEvent_t a = nullptr, b = nullptr;
+  int32_t launches = 0;
 };
 
 }  // namespace
@@ -80,13 +94,18 @@ struct sx_ctx {
   sx_grid_id next_id = 1;
   std::string err;
   bool poisoned = false;
-  std::vector<BatchCache> batches;
+  std::vector<Plan *> plans;
+  sx_schedule dflt{4, SX_ORDER_GRID, 1, 50};
+  int32_t autotune = 0;
+  uint32_t *done = nullptr;   // completion counter of the sweep launches
   bool prof = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;   // pool
+  std::vector<ProfEv> ev;     // pool
   size_t ev_used = 0;
 };
 
 namespace {
+
+void drop_plans(sx_ctx *ctx, int slot);
 
 int fail(sx_ctx *ctx, int code, const char *fmt, ...) {
   char buf[512];
@@ -440,6 +459,14 @@ int sx_init(sx_ctx **out, const sx_ctx_opts *opts) {
     delete ctx;
     return SX_EDEVICE;
   }
+  if (hipMalloc(&ctx->done, 256) != hipSuccess || hipMemset(ctx->done, 0, 256) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(ctx->table);
+    if (ctx->done) (void)hipFree(ctx->done);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return SX_EDEVICE;
+  }
   for (int s = kMaxSlots - 1; s >= 0; --s) ctx->free_slots.push_back(s);
   *out = ctx;
   return SX_OK;
@@ -451,11 +478,12 @@ int sx_finalize(sx_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (auto &kv : ctx->grids) grid_release(ctx, kv.second);
   ctx->grids.clear();
-  for (auto &b : ctx->batches) (void)hipFree(b.map);
+  drop_plans(ctx, -1);
   for (auto &e : ctx->ev) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
   }
+  (void)hipFree(ctx->done);
   (void)hipFree(ctx->table);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -491,8 +519,6 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   if (ctx->free_slots.empty()) return fail(ctx, SX_ENOMEM, "too many grids");
   const Sizes S = sizes_of(d);
-  const int kmax = sx::kmax_bucket((int)S.K, d->precision);
-  if (!kmax) return fail(ctx, SX_ENOTSUP, "unsupported bin count");
   {
     uint64_t want = 0;
     sx_grid_bytes(d, &want);
@@ -504,7 +530,6 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
   }
   const int64_t n = S.n, E = S.E, K = S.K, npad = S.npad;
   Grid *g = new Grid();
-  g->kmax = kmax;
 
   // ---- reorder along a Hilbert curve (locality of the gathers)
   g->perm = hilbert_order(d->pos, n);
@@ -608,6 +633,7 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
   }
   g->n_direct = 0;
   for (auto d8 : tile_direct) g->n_direct += d8;
+  g->tile_direct = tile_direct;
 
   // ---- per-vertex physics in new order
   std::vector<double> tau((size_t)npad, 0.0), dtnhv((size_t)npad, 1.0),
@@ -918,9 +944,8 @@ int sx_grid_free(sx_ctx *ctx, sx_grid_id id) {
   if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  // cached batch maps may reference this grid's slot
-  for (auto &b : ctx->batches) (void)hipFree(b.map);
-  ctx->batches.clear();
+  // launch plans that reference this grid's slot
+  drop_plans(ctx, g->slot);
   ctx->grids.erase(id);
   grid_release(ctx, g);
   return SX_OK;
@@ -928,86 +953,243 @@ int sx_grid_free(sx_ctx *ctx, sx_grid_id id) {
 
 namespace {
 
-struct Group {
-  int precision, kmax;
-  std::vector<Grid *> gs;
-};
+bool valid_schedule(const sx_schedule &s) {
+  return (s.tiles_per_group == 1 || s.tiles_per_group == 2 || s.tiles_per_group == 4) &&
+         (s.order == SX_ORDER_GRID || s.order == SX_ORDER_DIRECT_FIRST) &&
+         (s.xcd_contiguous == 0 || s.xcd_contiguous == 1) && s.graph_sweeps >= 0 &&
+         s.graph_sweeps <= SX_MAX_GRAPH_SWEEPS;
+}
+
+void plan_unbuild(Plan *p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+  for (void *d : p->dev) (void)hipFree(d);
+  p->dev.clear();
+  p->launches.clear();
+  p->built = false;
+}
+
+// Lay out the launches of one sweep for `gs` under p->sched: one launch per
+// precision present (grids in the caller's order), tiles grid by grid in
+// each grid's (Hilbert) order, or the directly gathering tiles first.
+int plan_build(sx_ctx *ctx, Plan *p, const std::vector<Grid *> &gs) {
+  plan_unbuild(p);
+  for (int prec : {SX_FP64, SX_FP32_TRANSPORT}) {
+    std::vector<Grid *> grp;
+    for (Grid *g : gs)
+      if (g->hg.precision == prec) grp.push_back(g);
+    if (grp.empty()) continue;
+    sx::SweepLaunch l{};
+    l.done = ctx->done;
+    l.tpb = p->sched.tiles_per_group;
+    l.xcd_remap = p->sched.xcd_contiguous;
+    l.precision = prec;
+    const bool any_direct = std::any_of(grp.begin(), grp.end(),
+                                        [](Grid *g) { return g->n_direct > 0; });
+    const bool reorder = p->sched.order == SX_ORDER_DIRECT_FIRST && any_direct;
+    if (grp.size() == 1 && !reorder) {
+      l.grids = ctx->table + grp[0]->slot;
+      l.map = nullptr;
+      l.n_tiles = grp[0]->hg.ntiles;
+      l.adv = nullptr;
+      l.n_adv = 1;
+    } else {
+      std::vector<int2> map;
+      for (int pass = reorder ? 0 : 1; pass < 2; ++pass)
+        for (Grid *g : grp)
+          for (int32_t t = 0; t < g->hg.ntiles; ++t)
+            if (!reorder || (g->tile_direct[(size_t)t] != 0) == (pass == 0))
+              map.push_back(make_int2(g->slot, t));
+      std::vector<int32_t> adv;
+      for (Grid *g : grp) adv.push_back(g->slot);
+      int2 *dmap = nullptr;
+      int32_t *dadv = nullptr;
+      HIP_TRY(ctx, hipMalloc(&dmap, sizeof(int2) * map.size()));
+      p->dev.push_back(dmap);
+      HIP_TRY(ctx, hipMalloc(&dadv, sizeof(int32_t) * adv.size()));
+      p->dev.push_back(dadv);
+      HIP_TRY(ctx, hipMemcpyAsync(dmap, map.data(), sizeof(int2) * map.size(),
+                                  hipMemcpyHostToDevice, ctx->stream));
+      HIP_TRY(ctx, hipMemcpyAsync(dadv, adv.data(), sizeof(int32_t) * adv.size(),
+                                  hipMemcpyHostToDevice, ctx->stream));
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      l.grids = ctx->table;
+      l.map = dmap;
+      l.n_tiles = (int32_t)map.size();
+      l.adv = dadv;
+      l.n_adv = (int32_t)adv.size();
+    }
+    p->launches.push_back(l);
+  }
+  if (p->sched.graph_sweeps > 0) {
+    HIP_TRY(ctx, hipGraphCreate(&p->graph, 0));
+    hipGraphNode_t prev = nullptr;
+    for (int32_t s = 0; s < p->sched.graph_sweeps; ++s)
+      for (auto &l : p->launches) HIP_TRY(ctx, sx::add_sweep_node(p->graph, l, &prev));
+    HIP_TRY(ctx, hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+  }
+  p->built = true;
+  return SX_OK;
+}
+
+// Plans that hold `slot` (all plans for slot < 0), after the stream drains.
+void drop_plans(sx_ctx *ctx, int slot) {
+  (void)hipStreamSynchronize(ctx->stream);
+  std::vector<Plan *> keep;
+  for (Plan *p : ctx->plans) {
+    if (slot < 0 || std::find(p->key.begin(), p->key.end(), slot) != p->key.end()) {
+      plan_unbuild(p);
+      delete p;
+    } else {
+      keep.push_back(p);
+    }
+  }
+  ctx->plans.swap(keep);
+}
+
+Plan *get_plan(sx_ctx *ctx, const std::vector<Grid *> &gs) {
+  std::vector<int32_t> key;
+  for (Grid *g : gs) key.push_back(g->slot);
+  for (Plan *p : ctx->plans)
+    if (p->key == key) return p;
+  if (ctx->plans.size() >= 64) {
+    // forget the oldest plan without a caller-set schedule
+    (void)hipStreamSynchronize(ctx->stream);
+    for (size_t i = 0; i < ctx->plans.size(); ++i) {
+      Plan *o = ctx->plans[i];
+      plan_unbuild(o);
+      delete o;
+      ctx->plans.erase(ctx->plans.begin() + (long)i);
+      break;
+    }
+  }
+  Plan *p = new Plan();
+  p->key = key;
+  p->sched = ctx->dflt;
+  ctx->plans.push_back(p);
+  return p;
+}
+
+ProfEv *prof_begin(sx_ctx *ctx, int32_t launches, hipError_t *err) {
+  *err = hipSuccess;
+  if (!ctx->prof) return nullptr;
+  if (ctx->ev_used == ctx->ev.size()) {
+    ProfEv e;
+    if ((*err = hipEventCreate(&e.a)) != hipSuccess) return nullptr;
+    if ((*err = hipEventCreate(&e.b)) != hipSuccess) return nullptr;
+    ctx->ev.push_back(e);
+  }
+  ProfEv *e = &ctx->ev[ctx->ev_used++];
+  e->launches = launches;
+  *err = hipEventRecord(e->a, ctx->stream);
+  return e;
+}
+
+// n sweeps of a built plan: whole graph replays, then single launches.
+int run_plan(sx_ctx *ctx, Plan *p, int32_t n) {
+  hipError_t pe;
+  const int32_t per = (int32_t)p->launches.size();
+  int32_t s = 0;
+  if (p->exec)
+    for (; s + p->sched.graph_sweeps <= n; s += p->sched.graph_sweeps) {
+      ProfEv *e = prof_begin(ctx, p->sched.graph_sweeps * per, &pe);
+      HIP_TRY(ctx, pe);
+      HIP_TRY(ctx, hipGraphLaunch(p->exec, ctx->stream));
+      if (e) HIP_TRY(ctx, hipEventRecord(e->b, ctx->stream));
+    }
+  for (; s < n; ++s)
+    for (auto &l : p->launches) {
+      ProfEv *e = prof_begin(ctx, 1, &pe);
+      HIP_TRY(ctx, pe);
+      HIP_TRY(ctx, sx::launch_sweep(l, ctx->stream));
+      if (e) HIP_TRY(ctx, hipEventRecord(e->b, ctx->stream));
+    }
+  return SX_OK;
+}
+
+// Time each candidate schedule on `trials` of the grids' own sweeps (the
+// schedule only reorders independent tiles, so results do not change) and
+// keep the fastest.  Returns the sweeps used in *used.
+int autotune(sx_ctx *ctx, Plan *p, const std::vector<Grid *> &gs, int32_t trials,
+             int32_t n_launch, int32_t *used) {
+  *used = 0;
+  bool any_direct = false;
+  for (Grid *g : gs) any_direct = any_direct || g->n_direct > 0;
+  std::vector<sx_schedule> cand;
+  for (int tpb : {4, 2, 1})
+    for (int xcd : {1, 0})
+      for (int order : {SX_ORDER_GRID, SX_ORDER_DIRECT_FIRST}) {
+        if (order == SX_ORDER_DIRECT_FIRST && !any_direct) continue;
+        cand.push_back({tpb, order, xcd, 0});
+      }
+  // only when tuning takes at most a quarter of the sweeps asked for
+  if ((int64_t)n_launch < 4 * (int64_t)trials * (int64_t)cand.size()) return SX_OK;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev((size_t)trials);
+  for (auto &e : ev) {
+    HIP_TRY(ctx, hipEventCreate(&e.first));
+    HIP_TRY(ctx, hipEventCreate(&e.second));
+  }
+  const int32_t graph_sweeps = p->sched.graph_sweeps;
+  double best = 1e300;
+  sx_schedule best_s = p->sched;
+  int rc = SX_OK;
+  for (const sx_schedule &c : cand) {
+    p->sched = c;
+    if ((rc = plan_build(ctx, p, gs))) break;
+    std::vector<double> t;
+    for (int32_t i = 0; i < trials && rc == SX_OK; ++i) {
+      if (hipEventRecord(ev[(size_t)i].first, ctx->stream) != hipSuccess ||
+          run_plan(ctx, p, 1) != SX_OK ||
+          hipEventRecord(ev[(size_t)i].second, ctx->stream) != hipSuccess)
+        rc = fail(ctx, SX_EDEVICE, "autotune launch failed");
+    }
+    if (rc) break;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      rc = fail(ctx, SX_EDEVICE, "autotune sync failed");
+      break;
+    }
+    for (int32_t i = 0; i < trials; ++i) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, ev[(size_t)i].first, ev[(size_t)i].second) == hipSuccess)
+        t.push_back(ms);
+    }
+    *used += trials;
+    // the first trial of a schedule also pays for its first launch
+    std::sort(t.begin() + (t.size() > 1 ? 1 : 0), t.end());
+    const double v = t.size() > 1 ? t[1] : (t.empty() ? 1e300 : t[0]);
+    if (v < best) {
+      best = v;
+      best_s = c;
+    }
+  }
+  for (auto &e : ev) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  if (rc) return rc;
+  best_s.graph_sweeps = graph_sweeps;
+  p->sched = best_s;
+  p->fixed = true;
+  p->tuned_us = 1e3 * best;
+  return plan_build(ctx, p, gs);
+}
 
 int launch_steps(sx_ctx *ctx, std::vector<Grid *> &gs, int32_t n_launch) {
   if (n_launch <= 0 || gs.empty()) return SX_OK;
-  std::vector<Group> groups;
-  for (Grid *g : gs) {
-    Group *hit = nullptr;
-    for (auto &gr : groups)
-      if (gr.precision == g->hg.precision && gr.kmax == g->kmax) hit = &gr;
-    if (!hit) {
-      groups.push_back({g->hg.precision, g->kmax, {}});
-      hit = &groups.back();
-    }
-    hit->gs.push_back(g);
+  Plan *p = get_plan(ctx, gs);
+  if (ctx->autotune > 0 && !p->fixed) {
+    int32_t used = 0;
+    int r = autotune(ctx, p, gs, ctx->autotune, n_launch, &used);
+    if (r) return r;
+    n_launch -= used;
   }
-  struct Launch {
-    const GridDev *grids;
-    const int2 *map;
-    int32_t n_tiles;
-    int kmax, precision;
-  };
-  std::vector<Launch> launches;
-  for (auto &gr : groups) {
-    if (gr.gs.size() == 1) {
-      Grid *g = gr.gs[0];
-      launches.push_back({ctx->table + g->slot, nullptr, g->hg.ntiles, gr.kmax, gr.precision});
-      continue;
-    }
-    std::vector<int32_t> key;
-    for (Grid *g : gr.gs) key.push_back(g->slot);
-    BatchCache *bc = nullptr;
-    for (auto &b : ctx->batches)
-      if (b.key == key) bc = &b;
-    if (!bc) {
-      if (ctx->batches.size() >= 16) {
-        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-        for (auto &b : ctx->batches) (void)hipFree(b.map);
-        ctx->batches.clear();
-      }
-      std::vector<int2> map;
-      for (Grid *g : gr.gs)
-        for (int32_t t = 0; t < g->hg.ntiles; ++t) map.push_back(make_int2(g->slot, t));
-      BatchCache nb;
-      nb.key = key;
-      nb.n_tiles = (int32_t)map.size();
-      HIP_TRY(ctx, hipMalloc(&nb.map, sizeof(int2) * map.size()));
-      HIP_TRY(ctx, hipMemcpyAsync(nb.map, map.data(), sizeof(int2) * map.size(),
-                                  hipMemcpyHostToDevice, ctx->stream));
-      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-      ctx->batches.push_back(nb);
-      bc = &ctx->batches.back();
-    }
-    launches.push_back({ctx->table, bc->map, bc->n_tiles, gr.kmax, gr.precision});
+  if (!p->built) {
+    int r = plan_build(ctx, p, gs);
+    if (r) return r;
   }
-  std::vector<int32_t> slots;
-  for (Grid *g : gs) slots.push_back(g->slot);
-  for (int32_t s = 0; s < n_launch; ++s) {
-    for (auto &l : launches) {
-      std::pair<hipEvent_t, hipEvent_t> *ep = nullptr;
-      if (ctx->prof) {
-        if (ctx->ev_used == ctx->ev.size()) {
-          std::pair<hipEvent_t, hipEvent_t> e;
-          HIP_TRY(ctx, hipEventCreate(&e.first));
-          HIP_TRY(ctx, hipEventCreate(&e.second));
-          ctx->ev.push_back(e);
-        }
-        ep = &ctx->ev[ctx->ev_used++];
-        HIP_TRY(ctx, hipEventRecord(ep->first, ctx->stream));
-      }
-      HIP_TRY(ctx, sx::launch_sweep(l.grids, l.map, l.n_tiles, l.kmax, l.precision,
-                                    ctx->stream));
-      if (ep) HIP_TRY(ctx, hipEventRecord(ep->second, ctx->stream));
-    }
-    HIP_TRY(ctx, sx::launch_advance(ctx->table, slots.data(), (int32_t)slots.size(),
-                                    ctx->stream));
-  }
-  return SX_OK;
+  return run_plan(ctx, p, n_launch);
 }
 
 int collect(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, std::vector<Grid *> &gs) {
@@ -1081,18 +1263,75 @@ int sx_profile_read(sx_ctx *ctx, int64_t *launches, double *total_ms, double *mi
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   double tot = 0.0, mn = 0.0, mx = 0.0;
+  int64_t nl = 0;
   for (size_t i = 0; i < ctx->ev_used; ++i) {
     float ms = 0.0f;
-    HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[i].first, ctx->ev[i].second));
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[i].a, ctx->ev[i].b));
+    const int32_t k = std::max(ctx->ev[i].launches, 1);
+    const double per = (double)ms / k;
     tot += ms;
-    mn = i == 0 ? ms : std::min(mn, (double)ms);
-    mx = std::max(mx, (double)ms);
+    nl += k;
+    mn = i == 0 ? per : std::min(mn, per);
+    mx = std::max(mx, per);
   }
-  if (launches) *launches = (int64_t)ctx->ev_used;
+  if (launches) *launches = nl;
   if (total_ms) *total_ms = tot;
   if (min_ms) *min_ms = mn;
   if (max_ms) *max_ms = mx;
   ctx->ev_used = 0;
+  return SX_OK;
+}
+
+int sx_set_schedule(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, const sx_schedule *s) {
+  if (!ctx) return SX_EINVAL;
+  if (!s || !valid_schedule(*s)) return fail(ctx, SX_EINVAL, "invalid schedule");
+  if (n == 0) {
+    ctx->dflt = *s;
+    // plans that follow the default are rebuilt on their next step
+    (void)hipStreamSynchronize(ctx->stream);
+    for (Plan *p : ctx->plans)
+      if (!p->fixed) {
+        plan_unbuild(p);
+        p->sched = *s;
+      }
+    return SX_OK;
+  }
+  std::vector<Grid *> gs;
+  int r = collect(ctx, ids, n, gs);
+  if (r) return r;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  Plan *p = get_plan(ctx, gs);
+  plan_unbuild(p);
+  p->sched = *s;
+  p->fixed = true;
+  p->tuned_us = 0.0;
+  return SX_OK;
+}
+
+int sx_get_schedule(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, sx_schedule *out,
+                    double *us_per_sweep) {
+  if (!ctx || !out) return SX_EINVAL;
+  *out = ctx->dflt;
+  if (us_per_sweep) *us_per_sweep = 0.0;
+  if (n == 0) return SX_OK;
+  std::vector<Grid *> gs;
+  int r = collect(ctx, ids, n, gs);
+  if (r) return r;
+  std::vector<int32_t> key;
+  for (Grid *g : gs) key.push_back(g->slot);
+  for (Plan *p : ctx->plans)
+    if (p->key == key) {
+      *out = p->sched;
+      if (us_per_sweep) *us_per_sweep = p->tuned_us;
+    }
+  return SX_OK;
+}
+
+int sx_autotune(sx_ctx *ctx, int32_t trials) {
+  if (!ctx) return SX_EINVAL;
+  if (trials < 0 || trials > 64) return fail(ctx, SX_EINVAL, "trials must be in [0, 64]");
+  ctx->autotune = trials;
   return SX_OK;
 }
 

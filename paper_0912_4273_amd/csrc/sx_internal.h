@@ -8,7 +8,6 @@
 namespace sx {
 
 constexpr int kTile = 64;           // vertices per tile = one wavefront
-constexpr int kTilesPerBlock = 4;   // waves per workgroup of the sweep kernel
 constexpr int kEmptySlot = 127;     // unused slot marker in packed tables
 
 constexpr int kStageQ = 5;         // halo staging loads per lane and bin
@@ -113,18 +112,26 @@ hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s);
 hipError_t launch_clear_inw(const GridDev &hg, hipStream_t s);
 hipError_t launch_reset_state(GridDev *dg, const GridDev &hg, const double *y0,
                               hipStream_t s);
-// One step for a batch: `grids` is the slot table (or one grid's entry when
-// tile_map is NULL); tile_map[t] = (slot, tile within that grid).
-hipError_t launch_sweep(const GridDev *grids, const int2 *tile_map,
-                        int32_t n_tiles, int32_t kmax_bucket, int32_t precision,
-                        hipStream_t s);
-// Slot-table updates: slots[i] indexes `table`.
-hipError_t launch_advance(GridDev *table, const int32_t *slots, int32_t n,
-                          hipStream_t s);
+// One sweep launch: a tile list over grids[] (tile_map null: one grid, tile
+// t = t), tpb (1, 2 or 4) waves per workgroup, XCD-contiguous workgroup
+// numbering or not, and the grids to advance when the launch completes (adv
+// null: grids[0 .. n_adv)).  done: a zeroed device counter that no other
+// launch uses concurrently.
+struct SweepLaunch {
+  GridDev *grids;
+  const int2 *map;
+  int32_t n_tiles;
+  const int32_t *adv;
+  int32_t n_adv;
+  uint32_t *done;
+  int32_t xcd_remap;
+  int32_t tpb, precision;
+};
+hipError_t launch_sweep(const SweepLaunch &l, hipStream_t s);
+hipError_t add_sweep_node(hipGraph_t graph, const SweepLaunch &l, hipGraphNode_t *prev);
 hipError_t launch_set_remaining(GridDev *table, const int32_t *slots,
                                 const int32_t *values, int32_t n, int32_t add,
                                 hipStream_t s);
 
-int kmax_bucket(int k, int precision);   // 0 if unsupported
 
 }  // namespace sx

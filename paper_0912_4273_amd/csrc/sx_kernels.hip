@@ -569,54 +569,66 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
   }
 }
 
-template <typename P>
-__global__ __launch_bounds__(256) void k_sweep(
-    const GridDev *__restrict__ grids, const int2 *__restrict__ tile_map,
-    int32_t n_tiles) {
+// One sweep over a list of tiles (a batch of grids, or one grid when
+// tile_map is null): workgroups of TPB waves, one tile per wave.  With
+// xcd_remap, workgroup numbers are rearranged so that each XCD (workgroups
+// are dealt to the 8 XCDs round-robin) runs a contiguous eighth of the tile
+// list and its L2 sees one neighbourhood.  The workgroup that finishes last
+// flips the buffers of the listed grids and clears the completion counter,
+// so consecutive launches are identical and need no kernel between them.
+template <typename P, int TPB>
+__global__ __launch_bounds__(64 * TPB, 4) void k_sweep(
+    GridDev *__restrict__ grids, const int2 *__restrict__ tile_map,
+    int32_t n_tiles, const int32_t *__restrict__ adv, int32_t n_adv,
+    uint32_t *__restrict__ done, int32_t xcd_remap) {
   constexpr int BB = kBlockBytes / sizeof(P);
-  __shared__ P hbuf[kTilesPerBlock][kHaloPlane * BB];
-  __shared__ P xbuf[kTilesPerBlock][kTile * BB];
+  __shared__ P hbuf[TPB][kHaloPlane * BB];
+  __shared__ P xbuf[TPB][kTile * BB];
+  __shared__ int last;
   const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // Workgroups are dealt round-robin to the 8 XCDs; renumber them so each
-  // XCD runs a contiguous range of tiles and its L2 sees the neighbourhood.
+  const int wave = TPB == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t nb = gridDim.x;   // a multiple of 8
   const uint32_t b = blockIdx.x;
-  const uint32_t lb = (b & 7u) * (nb >> 3) + (b >> 3);
-  const int gt = (int)lb * kTilesPerBlock + wave;
-  if (gt >= n_tiles) return;
-  int gi = 0, tile = gt;
-  if (tile_map) {
-    const int2 tm = tile_map[gt];
-    gi = __builtin_amdgcn_readfirstlane(tm.x);
-    tile = __builtin_amdgcn_readfirstlane(tm.y);
+  const uint32_t grp = xcd_remap ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
+  const int gt = (int)grp * TPB + wave;
+  if (gt < n_tiles) {
+    int gi = 0, tile = gt;
+    if (tile_map) {
+      const int2 tm = tile_map[gt];
+      gi = __builtin_amdgcn_readfirstlane(tm.x);
+      tile = __builtin_amdgcn_readfirstlane(tm.y);
+    }
+    const GridDev *__restrict__ G = grids + gi;
+    if (G->remaining > 0) {
+      volatile SX_L P *hl = (volatile SX_L P *)hbuf[wave];
+      volatile SX_L P *xc = (volatile SX_L P *)xbuf[wave];
+      if (gld(G->tile_direct)[tile] != 0)
+        sweep_tile<P, true>(G, tile, lane, hl, xc);
+      else
+        sweep_tile<P, false>(G, tile, lane, hl, xc);
+    }
   }
-  const GridDev *__restrict__ G = grids + gi;
-  if (G->remaining <= 0) return;
-  volatile SX_L P *hl = (volatile SX_L P *)hbuf[wave];
-  volatile SX_L P *xc = (volatile SX_L P *)xbuf[wave];
-  if (gld(G->tile_direct)[tile] != 0)
-    sweep_tile<P, true>(G, tile, lane, hl, xc);
-  else
-    sweep_tile<P, false>(G, tile, lane, hl, xc);
+  // completion count; the last workgroup advances the grids
+  __syncthreads();
+  if (threadIdx.x == 0)
+    last = atomicAdd(done, 1u) == nb - 1u;
+  __syncthreads();
+  if (!last) return;
+  for (int i = threadIdx.x; i < n_adv; i += 64 * TPB) {
+    GridDev &g = grids[adv ? adv[i] : i];
+    if (g.remaining > 0) {
+      g.parity ^= 1;
+      g.remaining -= 1;
+      g.sweeps += 1;
+    }
+  }
+  if (threadIdx.x == 0) atomicExch(done, 0u);
 }
 
 struct SlotVals {
   int32_t slot[120];
   int32_t v[120];
 };
-
-// After a step: every listed grid that ran flips its buffers.
-__global__ void k_advance(GridDev *table, SlotVals sv, int32_t n) {
-  const int i = threadIdx.x;
-  if (i >= n) return;
-  GridDev &g = table[sv.slot[i]];
-  if (g.remaining > 0) {
-    g.parity ^= 1;
-    g.remaining -= 1;
-    g.sweeps += 1;
-  }
-}
 
 __global__ void k_set_remaining(GridDev *table, SlotVals sv, int32_t n,
                                 int32_t add) {
@@ -711,41 +723,58 @@ hipError_t launch_reset_state(GridDev *dg, const GridDev &hg, const double *y0,
   return hipGetLastError();
 }
 
-int kmax_bucket(int k, int precision) {
-  (void)precision;
-  static const int b[] = {8, 16, 32, 42, 48, 64, 84, 96};
-  for (int v : b)
-    if (k <= v) return v;
-  return 0;
-}
-
-hipError_t launch_sweep(const GridDev *grids, const int2 *tile_map,
-                        int32_t n_tiles, int32_t kmax, int32_t precision,
-                        hipStream_t s) {
-  (void)kmax;
-  if (n_tiles <= 0) return hipSuccess;
-  unsigned nb = blocks_for(n_tiles, kTilesPerBlock);
-  nb = (nb + 7u) & ~7u;
-  dim3 g(nb), t(64 * kTilesPerBlock);
-  if (precision == 0)
-    hipLaunchKernelGGL(k_sweep<double>, g, t, 0, s, grids, tile_map, n_tiles);
-  else
-    hipLaunchKernelGGL(k_sweep<float>, g, t, 0, s, grids, tile_map, n_tiles);
-  return hipGetLastError();
-}
-
-hipError_t launch_advance(GridDev *table, const int32_t *slots, int32_t n,
-                          hipStream_t s) {
-  for (int32_t base = 0; base < n; base += 120) {
-    SlotVals v;
-    const int32_t m = n - base < 120 ? n - base : 120;
-    for (int32_t i = 0; i < m; ++i) { v.slot[i] = slots[base + i]; v.v[i] = 0; }
-    hipLaunchKernelGGL(k_advance, dim3(1), dim3(128), 0, s, table, v, m);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+template <typename P>
+static const void *sweep_fn(int tpb) {
+  switch (tpb) {
+    case 1: return (const void *)k_sweep<P, 1>;
+    case 2: return (const void *)k_sweep<P, 2>;
+    case 4: return (const void *)k_sweep<P, 4>;
   }
+  return nullptr;
+}
+
+static hipError_t sweep_shape(const SweepLaunch &l, const void **fn, dim3 *grid,
+                              dim3 *block) {
+  const void *f = l.precision == 0 ? sweep_fn<double>(l.tpb) : sweep_fn<float>(l.tpb);
+  if (!f || l.n_tiles <= 0 || !l.done) return hipErrorInvalidValue;
+  *fn = f;
+  // one workgroup per tpb tiles, rounded up to a multiple of 8
+  *grid = dim3((((unsigned)l.n_tiles + l.tpb - 1) / l.tpb + 7u) & ~7u);
+  *block = dim3(64u * (unsigned)l.tpb);
   return hipSuccess;
 }
+
+hipError_t launch_sweep(const SweepLaunch &l, hipStream_t s) {
+  const void *fn;
+  dim3 g, t;
+  hipError_t e = sweep_shape(l, &fn, &g, &t);
+  if (e != hipSuccess) return e;
+  SweepLaunch a = l;
+  void *args[] = {&a.grids, &a.map, &a.n_tiles, &a.adv, &a.n_adv, &a.done, &a.xcd_remap};
+  return hipLaunchKernel(fn, g, t, args, 0, s);
+}
+
+hipError_t add_sweep_node(hipGraph_t graph, const SweepLaunch &l,
+                          hipGraphNode_t *prev) {
+  const void *fn;
+  dim3 g, t;
+  hipError_t e = sweep_shape(l, &fn, &g, &t);
+  if (e != hipSuccess) return e;
+  SweepLaunch a = l;
+  void *args[] = {&a.grids, &a.map, &a.n_tiles, &a.adv, &a.n_adv, &a.done, &a.xcd_remap};
+  hipKernelNodeParams kp = {};
+  kp.func = const_cast<void *>(fn);
+  kp.gridDim = g;
+  kp.blockDim = t;
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  hipGraphNode_t node;
+  e = hipGraphAddKernelNode(&node, graph, *prev ? prev : nullptr, *prev ? 1 : 0, &kp);
+  if (e == hipSuccess) *prev = node;
+  return e;
+}
+
 
 hipError_t launch_set_remaining(GridDev *table, const int32_t *slots,
                                 const int32_t *values, int32_t n, int32_t add,

@@ -24,13 +24,17 @@ SX_ENOTFOUND = -4
 SX_ENOTSUP = -5
 SX_FP64 = 0
 SX_FP32_TRANSPORT = 1
+SX_ORDER_GRID = 0
+SX_ORDER_DIRECT_FIRST = 1
+SX_MAX_GRAPH_SWEEPS = 4096
 
 EXPORTED = [
     "sx_init", "sx_finalize", "sx_grid_bytes", "sx_grid_upload",
     "sx_grid_reset", "sx_grid_restore", "sx_grid_free", "sx_step",
     "sx_solve", "sx_sync", "sx_read_state", "sx_read_tables",
     "sx_grid_info", "sx_mem_info", "sx_stream", "sx_profile",
-    "sx_profile_read", "sx_strerror", "sx_last_error",
+    "sx_profile_read", "sx_set_schedule", "sx_get_schedule", "sx_autotune",
+    "sx_strerror", "sx_last_error",
 ]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -76,6 +80,11 @@ class SxStateIn(C.Structure):
                 ("tally", C.POINTER(SxTally))]
 
 
+class SxSchedule(C.Structure):
+    _fields_ = [("tiles_per_group", C.c_int32), ("order", C.c_int32),
+                ("xcd_contiguous", C.c_int32), ("graph_sweeps", C.c_int32)]
+
+
 class SxError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{msg} (code {code})")
@@ -115,6 +124,9 @@ def load(path: Optional[str] = None):
         "sx_stream": (P, [P]),
         "sx_profile": (C.c_int, [P, I32]),
         "sx_profile_read": (C.c_int, [P, P, P, P, P]),
+        "sx_set_schedule": (C.c_int, [P, P, I32, C.POINTER(SxSchedule)]),
+        "sx_get_schedule": (C.c_int, [P, P, I32, C.POINTER(SxSchedule), P]),
+        "sx_autotune": (C.c_int, [P, I32]),
         "sx_strerror": (C.c_char_p, [C.c_int]),
         "sx_last_error": (C.c_char_p, [P]),
     }
@@ -313,6 +325,32 @@ def sx_profile_read(ctx) -> dict:
     return dict(launches=n.value, total_ms=t.value, min_ms=lo.value, max_ms=hi.value)
 
 
+def _ids(ids):
+    a = np.ascontiguousarray(np.asarray(ids, dtype=np.int64).reshape(-1))
+    return a, (_ptr(a) if a.size else None), int(a.size)
+
+
+def sx_set_schedule(ctx, ids, tiles_per_group=4, order=SX_ORDER_GRID,
+                    xcd_contiguous=1, graph_sweeps=50) -> None:
+    a, p, n = _ids(ids)
+    s = SxSchedule(tiles_per_group, order, xcd_contiguous, graph_sweeps)
+    _check(ctx, load().sx_set_schedule(ctx, p, n, C.byref(s)))
+
+
+def sx_get_schedule(ctx, ids) -> dict:
+    a, p, n = _ids(ids)
+    s = SxSchedule()
+    us = C.c_double()
+    _check(ctx, load().sx_get_schedule(ctx, p, n, C.byref(s), C.byref(us)))
+    return dict(tiles_per_group=s.tiles_per_group, order=s.order,
+                xcd_contiguous=s.xcd_contiguous, graph_sweeps=s.graph_sweeps,
+                us_per_sweep=us.value)
+
+
+def sx_autotune(ctx, trials: int) -> None:
+    _check(ctx, load().sx_autotune(ctx, int(trials)))
+
+
 # ------------------------------------------------------ convenience ----
 
 class Context:
@@ -366,6 +404,15 @@ class Context:
 
     def profile_read(self) -> dict:
         return sx_profile_read(self.h)
+
+    def set_schedule(self, ids, **kw):
+        sx_set_schedule(self.h, ids, **kw)
+
+    def get_schedule(self, ids) -> dict:
+        return sx_get_schedule(self.h, ids)
+
+    def autotune(self, trials: int):
+        sx_autotune(self.h, trials)
 
     @property
     def stream(self) -> int:

@@ -48,6 +48,9 @@ def test_null_arguments_rejected_without_device():
     lib = sx.load()
     assert lib.sx_init(None, None) == sx.SX_EINVAL
     assert lib.sx_step(None, None, 0, 1) == sx.SX_EINVAL
+    assert lib.sx_autotune(None, 1) == sx.SX_EINVAL
+    assert lib.sx_set_schedule(None, None, 0, None) == sx.SX_EINVAL
+    assert lib.sx_get_schedule(None, None, 0, None, None) == sx.SX_EINVAL
     assert lib.sx_finalize(None) == sx.SX_OK
     b = C.c_uint64()
     assert lib.sx_grid_bytes(None, C.byref(b)) == sx.SX_EINVAL
@@ -65,6 +68,8 @@ int main(void) {
   printf("sx_ctx_opts %zu\n", sizeof(sx_ctx_opts));
   printf("sx_state_out %zu\n", sizeof(sx_state_out));
   printf("sx_tally %zu\n", sizeof(sx_tally));
+  printf("sx_schedule %zu\n", sizeof(sx_schedule));
+  P(sx_schedule, order) P(sx_schedule, graph_sweeps)
   P(sx_grid_desc, kappa) P(sx_grid_desc, n_bins) P(sx_grid_desc, cos_min)
   P(sx_grid_desc, src_dir) P(sx_grid_desc, dt) P(sx_grid_desc, precision)
   P(sx_ctx_opts, stream) P(sx_ctx_opts, alloc_user)
@@ -87,6 +92,9 @@ def test_ctypes_struct_layout_matches_c():
     assert C.sizeof(sx.SxCtxOpts) == lay["sx_ctx_opts"]
     assert C.sizeof(sx.SxStateOut) == lay["sx_state_out"]
     assert C.sizeof(sx.SxTally) == lay["sx_tally"]
+    assert C.sizeof(sx.SxSchedule) == lay["sx_schedule"]
+    for f in ("order", "graph_sweeps"):
+        assert getattr(sx.SxSchedule, f).offset == lay[f"sx_schedule.{f}"], f
     for f in ("kappa", "n_bins", "cos_min", "src_dir", "dt", "precision"):
         assert getattr(sx.SxGridDesc, f).offset == lay[f"sx_grid_desc.{f}"], f
     for f in ("stream", "alloc_user"):
