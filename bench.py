@@ -60,6 +60,20 @@ def measured_traffic(workload: str):
     return e.get("bytes_per_launch")
 
 
+def _batch_member(g):
+    from paper_0912_4273_amd import gridgen as G
+    return G.batch_member(g)
+
+
+def build_batch(n_grids: int):
+    """The 64-grid batch, built on the host cores before the GPU is touched
+    (worker processes are forked)."""
+    import multiprocessing as mp
+    workers = max(1, min(16, os.cpu_count() or 1, n_grids))
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_batch_member, range(n_grids), chunksize=1), workers
+
+
 def cpu_baseline(w, sweeps: int):
     """The FP64 oracle (single thread) on the same grid, from the initial
     state, for a bounded number of sweeps."""
@@ -83,9 +97,15 @@ def main():
     ap.add_argument("--n", type=int, default=262144)
     ap.add_argument("--bins", type=int, default=84)
     ap.add_argument("--sweeps", type=int, default=1000)
-    ap.add_argument("--cpu-sweeps", type=int, default=3)
+    ap.add_argument("--cpu-sweeps", type=int, default=25)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--batch-grids", type=int, default=64,
+                    help="grids in the batched leg (0 = skip it)")
+    ap.add_argument("--batch-sweeps", type=int, default=200)
+    ap.add_argument("--autotune-trials", type=int, default=2)
+    ap.add_argument("--graph-sweeps", type=int, default=50,
+                    help="sweeps per replayed HIP graph (0: one launch per sweep)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -97,8 +117,24 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
     from paper_0912_4273_amd import gridgen as G
+
+    # host-side grid construction first: the batch is built by forked
+    # workers, which must not inherit an initialised GPU runtime
+    batch = []
+    if args.batch_grids > 0:
+        t = time.perf_counter()
+        batch, nw = build_batch(args.batch_grids)
+        log(f"batch: {len(batch)} grids, {sum(b.n for b in batch)} vertices, built "
+            f"in {time.perf_counter() - t:.1f} s on {nw} processes")
+    t = time.perf_counter()
+    w = G.stromgren_test(args.n, seed=2, n_bins=args.bins, bins_seed=102,
+                         n_sweeps=args.sweeps, precision=G.SX_FP32_TRANSPORT,
+                         name=f"stromgren_{args.n}_k{args.bins}")
+    log(f"grid {w.n} vertices, {w.n_edges} directed edges, built in "
+        f"{time.perf_counter() - t:.1f} s")
+
+    import torch
     from paper_0912_4273_amd import sx
 
     if not torch.cuda.is_available():
@@ -106,17 +142,11 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     torch.cuda.init()
-
-    t = time.perf_counter()
-    w = G.stromgren_test(args.n, seed=2, n_bins=args.bins, bins_seed=102,
-                         n_sweeps=args.sweeps, precision=G.SX_FP32_TRANSPORT,
-                         name=f"stromgren_{args.n}_k{args.bins}")
-    log(f"grid {w.n} vertices, {w.n_edges} directed edges, built in "
-        f"{time.perf_counter() - t:.1f} s")
     workload = f"stromgren_{w.n}_k{w.k}_{args.sweeps}sweeps"
 
     stream = torch.cuda.Stream(device=dev)
     ctx = sx.Context(device=0, stream=stream.cuda_stream, use_torch_allocator=True)
+    ctx.set_schedule([], graph_sweeps=args.graph_sweeps)
 
     def upload(wl):
         t0 = time.perf_counter()
@@ -169,6 +199,60 @@ def main():
         fp64 = dict(value=ups64, ms_per_step=1e3 * el64, sweep_kernel_us=1e3 * k64)
         ctx.free(gid64)
 
+    # ---- batched: many uneven grids in one launch per sweep, autotuned
+    batched = None
+    if batch:
+        t0 = time.perf_counter()
+        ids = [ctx.upload(b) for b in batch]
+        up_b = time.perf_counter() - t0
+        nsw = [args.batch_sweeps] * len(ids)
+        ctx.autotune(args.autotune_trials)
+        ctx.solve(ids, nsw)            # tunes the schedule on its first sweeps
+        ctx.autotune(0)
+        sched = ctx.get_schedule(ids)
+        for gid in ids:
+            ctx.reset(gid)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read()
+        t0 = time.perf_counter()
+        ctx.solve(ids, nsw)
+        sts = [ctx.state(gid, nin=False) for gid in ids]
+        el_b = time.perf_counter() - t0
+        pb = ctx.profile_read()
+        ctx.profile(False)
+        upd_b = sum(b.n * b.k for b in batch) * args.batch_sweeps
+        kb = pb["total_ms"] / max(pb["launches"], 1)
+        # front radius against the analytic law, per grid (4 t_rec: 0.9937 r_S)
+        ratios = []
+        for b, st in zip(batch, sts):
+            rv = (3 / (4 * math.pi) * float(np.sum(b.volume * st["x"]))) ** (1 / 3)
+            ratios.append(rv / (b.meta["r_s"] * (1 - math.exp(-4.0)) ** (1 / 3)))
+        # FP32 against all-FP64 on a few members, alone
+        dx = []
+        for b, st in list(zip(batch, sts))[:4]:
+            g64 = ctx.upload(G.with_(b, precision=G.SX_FP64))
+            ctx.solve([g64], args.batch_sweeps)
+            dx.append(float(np.max(np.abs(ctx.state(g64, nin=False)["x"] - st["x"]))))
+            ctx.free(g64)
+        for gid in ids:
+            ctx.free(gid)
+        bpu_b = algorithmic_bytes_per_update(42, 4)
+        batched = dict(
+            value=upd_b / el_b, unit="vertex·direction updates/s",
+            ms_per_step=1e3 * el_b, grids=len(batch),
+            vertices=int(sum(b.n for b in batch)), bins=42, sweeps=args.batch_sweeps,
+            upload_s=up_b, sweep_kernel_us=1e3 * kb,
+            algorithmic_hbm_frac=round(bpu_b * upd_b / args.batch_sweeps
+                                       / (kb * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            schedule=sched,
+            front_radius_over_analytic=dict(min=round(min(ratios), 4),
+                                            median=round(float(np.median(ratios)), 4),
+                                            max=round(max(ratios), 4)),
+            fp32_vs_fp64_max_abs_x_4_grids=max(dx))
+        log(f"batched: {batched['value']:.3e} updates/s, {1e3 * el_b:.1f} ms/solve, "
+            f"sweep launch {1e3 * kb:.1f} us, schedule {sched}")
+
     bpu = algorithmic_bytes_per_update(w.k, 4)
     bytes_launch = bpu * w.n * w.k
     achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
@@ -220,6 +304,7 @@ def main():
                    "sweeps_per_step": args.sweeps, "precision": "fp32_transport",
                    "physics": "Stromgren test: n_H 1e-3, 5e48 photons/s, 13.2 kpc box, 500 Myr"},
         "fp64_plain": fp64,
+        "batched": batched,
         "upload_s": up_s,
         "sweep_kernel_us": 1e3 * kern_ms,
         "roofline": roof,
