@@ -56,7 +56,7 @@ struct GridDev {
   int32_t n_sub;      // chemistry substeps
   int32_t mpb;        // max neighbours per bin
   int32_t precision;  // 0 fp64, 1 fp32 transport
-  // mutable per-step control (advanced by sx_advance)
+  // mutable per-sweep control, advanced by the last workgroup of each sweep launch
   int32_t parity;     // O buffer holding the current field
   int32_t remaining;  // steps still to run in the current request
   int64_t sweeps;     // steps done
