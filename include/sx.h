@@ -48,6 +48,7 @@ extern "C" {
 #define SX_EDEVICE (-3)    /* HIP runtime / kernel failure; ctx poisoned  */
 #define SX_ENOTFOUND (-4)  /* unknown grid id                             */
 #define SX_ENOTSUP (-5)    /* valid request outside the supported limits  */
+#define SX_EAGAIN (-6)     /* nothing finished within the wait (serving)  */
 
 /* ---- precision ------------------------------------------------------- */
 #define SX_FP64 0            /* photons and chemistry in double            */
@@ -224,6 +225,31 @@ int sx_profile(sx_ctx *ctx, int32_t enable);
 int sx_profile_read(sx_ctx *ctx, int64_t *launches, double *total_ms,
                     double *min_ms, double *max_ms);
 
+/* ---- upload in two parts ---------------------------------------------
+ * sx_grid_upload = sx_grid_prepare + sx_grid_commit.  The host part (all
+ * validation, the Hilbert reorder, neighbour rows, edge geometry, tile
+ * halos, per-vertex coefficients, source lists) needs no context and no
+ * device and may run on any thread, concurrently; the device part runs on
+ * the context's thread.  A request loop prepares on worker threads while the
+ * GPU sweeps. */
+typedef struct sx_prepared sx_prepared;
+
+/* Prepare a grid on the host.  On failure returns the SX_E* code of
+ * sx_grid_upload and, if err is not NULL, a message in err[0..err_len). */
+int sx_grid_prepare(const sx_grid_desc *d, sx_prepared **out, char *err, size_t err_len);
+
+/* Device bytes the prepared grid is expected to take (admission control). */
+int sx_prepared_bytes(const sx_prepared *p, uint64_t *bytes);
+
+/* Upload a prepared grid.  p is consumed on success (it may then only be
+ * freed).  When the budget check refuses it (SX_ENOMEM, nothing allocated)
+ * it stays usable and may be committed later; sx_prepared_bytes tells
+ * (SX_EINVAL once p is consumed).  Errors: as sx_grid_upload. */
+int sx_grid_commit(sx_ctx *ctx, sx_prepared *p, sx_grid_id *out);
+
+/* Release a prepared grid (committed or not).  NULL is accepted. */
+int sx_prepared_free(sx_prepared *p);
+
 /* ---- sweep schedule --------------------------------------------------
  * How the sweeps of a step are launched.  A schedule only changes the order
  * in which independent 64-vertex tiles run (each tile's arithmetic and every
@@ -271,6 +297,68 @@ int sx_get_schedule(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, sx_schedule *
  * tuning.  trials = 0 turns it off.  Errors: SX_EINVAL (trials outside
  * [0, 64]). */
 int sx_autotune(sx_ctx *ctx, int32_t trials);
+
+/* ---- serving ----------------------------------------------------------
+ * A request loop with continuous batching over one context.  Requests
+ * (sx_serve_submit, any thread) are copied, prepared on prep_threads host
+ * threads, and admitted in arrival order between rounds as the HBM budget
+ * (hbm_budget, 0 = the context's) and max_active allow.  A round runs up to
+ * round_sweeps sweeps over every resident grid as one batch (each grid only
+ * the sweeps it still needs, under the context's schedule); grids that are
+ * done are read back into the server and freed, making room for the next
+ * admissions.  Each result equals the result of solving that grid alone.
+ * While serving, the context belongs to the server's thread: the caller must
+ * not use it until sx_serve_stop returns. */
+typedef struct sx_server sx_server;
+
+typedef struct sx_serve_opts {
+    int32_t round_sweeps;   /* sweeps per round; 0 = 50                       */
+    int32_t max_active;     /* grids resident at once; 0 = 64 (<= 1024)        */
+    int32_t prep_threads;   /* host threads preparing uploads; 0 = 4 (<= 64)   */
+    int32_t reserved;
+    uint64_t hbm_budget;    /* admission limit in bytes; 0 = context budget    */
+} sx_serve_opts;
+
+typedef struct sx_serve_result {
+    int64_t ticket;
+    int32_t status;         /* SX_OK or the request's error                   */
+    int32_t n_bins;
+    int64_t n_vertices;
+    int32_t n_sweeps;
+    int32_t reserved;
+    double t_submit, t_prepared, t_admit, t_done;  /* s since sx_serve_start */
+    sx_tally tally;
+} sx_serve_result;
+
+typedef struct sx_serve_stats {
+    int64_t finished, failed, rounds;
+    int32_t peak_active, reserved;
+    double updates;         /* vertex-direction updates of finished requests  */
+    double span_s;          /* first admission to last completion             */
+    double round_s;         /* time inside rounds (GPU sweeps + their sync)   */
+    double latency_p50_s, latency_p99_s, latency_max_s;  /* submit -> done   */
+} sx_serve_stats;
+
+/* Start the loop on ctx.  Errors: SX_EINVAL. */
+int sx_serve_start(sx_ctx *ctx, const sx_serve_opts *opts, sx_server **out);
+
+/* Queue a request: the description is copied during the call.  *ticket
+ * identifies it.  Errors: SX_EINVAL (malformed, or the server is
+ * stopping).  Validation errors of the grid itself come back as the
+ * result's status. */
+int sx_serve_submit(sx_server *s, const sx_grid_desc *d, int32_t n_sweeps, int64_t *ticket);
+
+/* Wait up to timeout_s seconds for the next finished request (in completion
+ * order) and describe it in *res.  Returns SX_OK or SX_EAGAIN. */
+int sx_serve_poll(sx_server *s, double timeout_s, sx_serve_result *res);
+
+/* Copy a polled request's x and y [N] (caller order; either may be NULL)
+ * and release them.  Errors: SX_ENOTFOUND (not polled, or already taken). */
+int sx_serve_take(sx_server *s, int64_t ticket, double *x, double *y);
+
+/* Finish every queued request, stop the threads, fill *st (nullable), and
+ * release the server; results not taken are dropped.  NULL is accepted. */
+int sx_serve_stop(sx_server *s, sx_serve_stats *st);
 
 const char *sx_strerror(int code);
 const char *sx_last_error(const sx_ctx *ctx);

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsx.so")
 
-SOURCES = ["sx_host.cpp", "sx_kernels.hip"]
+SOURCES = ["sx_host.cpp", "sx_serve.cpp", "sx_kernels.hip"]
 ARCH = os.environ.get("SX_OFFLOAD_ARCH", "gfx950")
 
 
@@ -32,6 +32,7 @@ def flags() -> list[str]:
         # host arithmetic rounded operation by operation (edge geometry)
         "-Xarch_host", "-ffp-contract=off",
         "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument",
+        "-pthread",
     ]
 
 
@@ -40,15 +41,19 @@ def build_library(verbose: bool = False) -> str:
     objs = []
     build_dir = os.path.join(PKG, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    for src in SOURCES:
+    procs = []
+    for src in SOURCES:   # compiled in parallel
         obj = os.path.join(build_dir, src.replace(".", "_") + ".o")
         cmd = [hipcc()] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        procs.append((subprocess.Popen(cmd), cmd))
         objs.append(obj)
+    for p, cmd in procs:
+        if p.wait() != 0:
+            raise subprocess.CalledProcessError(p.returncode, cmd)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -402,6 +402,487 @@ int build_tables(sx_ctx *ctx, Grid *g) {
 
 }  // namespace
 
+// Host-side product of sx_grid_prepare: a Grid with its host tables filled,
+// and everything the device part uploads.
+struct sx_prepared {
+  Grid *g = nullptr;
+  Sizes S{};
+  int32_t n_sub = 0, mpb = 0, precision = 0;
+  double dt = 0.0, cos_min = 0.0, unit = 1.0;
+  std::vector<double> bins;
+  std::vector<uint8_t> rev;
+  std::vector<double> edir;
+  std::vector<int32_t> halo_ptr, halo_vid;
+  std::vector<uint16_t> edge_hidx;
+  std::vector<double> tau, dtnhv, bco, y0;
+  std::vector<int32_t> em_ptr, em_k;
+  std::vector<double> em_amt;
+  ~sx_prepared() { delete g; }
+};
+
+namespace {
+
+// The host part of an upload: validation, Hilbert reorder, CSR, edge
+// geometry, halos, per-vertex coefficients, photon unit and source lists.
+// No device work; `ctx` only collects the error message.
+int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
+  int rc = validate(ctx, d);
+  if (rc) return rc;
+  const Sizes S = sizes_of(d);
+  P->S = S;
+  P->n_sub = d->n_subcycles;
+  P->mpb = d->max_per_bin;
+  P->precision = d->precision;
+  P->dt = d->dt;
+  P->cos_min = d->cos_min;
+  P->bins.assign(d->bin_dirs, d->bin_dirs + 3 * S.K);
+  const int64_t n = S.n, E = S.E, K = S.K, npad = S.npad;
+  (void)K;
+  Grid *g = new Grid();
+  P->g = g;
+
+  // ---- reorder along a Hilbert curve (locality of the gathers)
+  g->perm = hilbert_order(d->pos, n);
+  g->inv.assign((size_t)n, 0);
+  for (int64_t v = 0; v < n; ++v) g->inv[(size_t)g->perm[(size_t)v]] = (int32_t)v;
+
+  // ---- new CSR, rows sorted by ORIGINAL neighbour id, so that summing the
+  // in-list in slot order adds the senders in ascending original id
+  std::vector<int32_t> &rp = g->row_ptr_h;
+  rp.assign((size_t)npad + 1, 0);
+  for (int64_t v = 0; v < n; ++v) {
+    const int32_t i = g->perm[(size_t)v];
+    rp[(size_t)v + 1] = rp[(size_t)v] + (int32_t)(d->nbr_ptr[i + 1] - d->nbr_ptr[i]);
+  }
+  for (int64_t v = n; v < npad; ++v) rp[(size_t)v + 1] = rp[(size_t)v];
+  std::vector<int32_t> orig_nbr((size_t)E);   // original id of each new edge's target
+  g->nbr_h.assign((size_t)E, 0);
+  g->orig_to_new_e.assign((size_t)E, 0);
+  std::vector<double> &edir = P->edir;
+  edir.assign((size_t)(3 * E), 0.0);
+  std::vector<double> len_orig((size_t)E);     // per original CSR position
+  {
+    std::vector<std::pair<int32_t, int64_t>> row;
+    for (int64_t v = 0; v < n; ++v) {
+      const int32_t i = g->perm[(size_t)v];
+      row.clear();
+      for (int64_t p = d->nbr_ptr[i]; p < d->nbr_ptr[i + 1]; ++p)
+        row.push_back({d->nbr_idx[p], p});
+      std::sort(row.begin(), row.end());
+      for (size_t r = 0; r < row.size(); ++r) {
+        const int64_t e = rp[(size_t)v] + (int64_t)r;
+        const int32_t j = row[r].first;
+        orig_nbr[(size_t)e] = j;
+        g->nbr_h[(size_t)e] = g->inv[(size_t)j];
+        g->orig_to_new_e[(size_t)row[r].second] = (int32_t)e;
+      }
+    }
+  }
+  // ---- edge geometry in IEEE double with every operation rounded (the
+  // library is built without FMA contraction on the host): unit vector and
+  // length of each directed edge
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t p = d->nbr_ptr[i]; p < d->nbr_ptr[i + 1]; ++p) {
+      const int32_t j = d->nbr_idx[p];
+      const double dx = d->pos[3 * j + 0] - d->pos[3 * i + 0];
+      const double dy = d->pos[3 * j + 1] - d->pos[3 * i + 1];
+      const double dz = d->pos[3 * j + 2] - d->pos[3 * i + 2];
+      const double xx = dx * dx, yy = dy * dy, zz = dz * dz;
+      const double len = std::sqrt((xx + yy) + zz);
+      const int64_t e = g->orig_to_new_e[(size_t)p];
+      edir[(size_t)(3 * e + 0)] = dx / len;
+      edir[(size_t)(3 * e + 1)] = dy / len;
+      edir[(size_t)(3 * e + 2)] = dz / len;
+      len_orig[(size_t)p] = len;
+    }
+  }
+  // ---- reverse slots: position of the row's vertex in its neighbour's row
+  std::vector<uint8_t> &rev = P->rev;
+  rev.assign((size_t)E, 0);
+  for (int64_t v = 0; v < n; ++v) {
+    const int32_t vi = g->perm[(size_t)v];
+    for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) {
+      const int32_t w = g->nbr_h[(size_t)e];
+      auto b = orig_nbr.begin() + rp[(size_t)w], en = orig_nbr.begin() + rp[(size_t)w + 1];
+      auto it = std::lower_bound(b, en, vi);
+      rev[(size_t)e] = (uint8_t)(it - b);
+    }
+  }
+  // ---- tile halos: every neighbour of a tile's vertices, ascending; the
+  // index of each edge's target in its tile's halo.  Tiles with more than
+  // kHaloMax halo vertices gather directly (edge index = row slot).
+  const int64_t ntiles = S.ntiles;
+  std::vector<int32_t> &halo_ptr = P->halo_ptr, &halo_vid = P->halo_vid;
+  halo_ptr.assign((size_t)ntiles + 1, 0);
+  std::vector<uint16_t> &edge_hidx = P->edge_hidx;
+  edge_hidx.assign((size_t)E, 0);
+  std::vector<uint8_t> tile_direct((size_t)ntiles, 0);
+  {
+    // SX_FORCE_DIRECT=1 makes every tile gather directly (a test knob for
+    // the path large-halo tiles take)
+    const char *fd = std::getenv("SX_FORCE_DIRECT");
+    const bool force_direct = fd && fd[0] == '1';
+    std::vector<int32_t> h;
+    for (int64_t t = 0; t < ntiles; ++t) {
+      const int64_t v0 = t * sx::kTile, v1 = std::min<int64_t>(v0 + sx::kTile, n);
+      h.clear();
+      for (int64_t v = v0; v < v1; ++v)
+        for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) h.push_back(g->nbr_h[(size_t)e]);
+      std::sort(h.begin(), h.end());
+      h.erase(std::unique(h.begin(), h.end()), h.end());
+      if ((int64_t)h.size() > sx::kHaloMax || force_direct) {
+        tile_direct[(size_t)t] = 1;
+        for (int64_t v = v0; v < v1; ++v)
+          for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e)
+            edge_hidx[(size_t)e] = (uint16_t)(e - rp[(size_t)v]);
+      } else {
+        for (int64_t v = v0; v < v1; ++v)
+          for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e)
+            edge_hidx[(size_t)e] = (uint16_t)(std::lower_bound(h.begin(), h.end(),
+                                                               g->nbr_h[(size_t)e]) - h.begin());
+        halo_vid.insert(halo_vid.end(), h.begin(), h.end());
+      }
+      halo_ptr[(size_t)t + 1] = (int32_t)halo_vid.size();
+    }
+  }
+  g->n_direct = 0;
+  for (auto d8 : tile_direct) g->n_direct += d8;
+  g->tile_direct = tile_direct;
+
+  // ---- per-vertex physics in new order
+  std::vector<double> &tau = P->tau, &dtnhv = P->dtnhv, &bco = P->bco, &y0 = P->y0;
+  tau.assign((size_t)npad, 0.0);
+  dtnhv.assign((size_t)npad, 1.0);
+  bco.assign((size_t)npad, 0.0);
+  y0.assign((size_t)npad, 1.0);
+  g->dL_h.assign((size_t)n, 0.0);
+  g->tau_h.assign((size_t)n, 0.0);
+  for (int64_t v = 0; v < n; ++v) {
+    const int32_t i = g->perm[(size_t)v];
+    double dl;
+    if (d->dL) {
+      dl = d->dL[i];
+    } else {
+      // mean incident edge length (in the caller's row order) times kappa
+      double sum = 0.0;
+      const int64_t deg = d->nbr_ptr[i + 1] - d->nbr_ptr[i];
+      for (int64_t p = d->nbr_ptr[i]; p < d->nbr_ptr[i + 1]; ++p) sum += len_orig[(size_t)p];
+      dl = deg > 0 ? d->kappa * (sum / (double)deg) : 0.0;
+    }
+    g->dL_h[(size_t)v] = dl;
+    tau[(size_t)v] = (d->n_H[i] * d->sigma) * dl;
+    g->tau_h[(size_t)v] = tau[(size_t)v];
+    dtnhv[(size_t)v] = d->dt * (d->n_H[i] * d->volume[i]);
+    bco[(size_t)v] = d->alpha_B * d->n_H[i];
+    y0[(size_t)v] = d->x_init ? 1.0 - d->x_init[i] : 1.0;
+  }
+  // ---- photon unit: the power of two nearest the photons emitted per step
+  double e_sweep = 0.0;
+  for (int s = 0; s < d->n_src; ++s) e_sweep += d->src_rate[s] * d->dt;
+  double unit = 1.0;
+  if (e_sweep > 0.0 && std::isfinite(e_sweep)) unit = std::ldexp(1.0, (int)std::lround(std::log2(e_sweep)));
+  g->e_sweep = e_sweep;
+
+  P->unit = unit;
+
+  // ---- sources: per receiving vertex, in source order, the share of each
+  // source's photons and the bin of the edge it arrives along.  The edge bin
+  // is the device's rule (largest cosine, ties to the lower bin) evaluated
+  // the same way, so both sides agree bit for bit.
+  auto edge_bin = [&](int64_t e) -> int32_t {
+    const double *ed = &edir[(size_t)(3 * e)];
+    int32_t best = 0;
+    double cb = 0.0;
+    for (int32_t k = 0; k < (int32_t)S.K; ++k) {
+      const double *u = &P->bins[(size_t)(3 * k)];
+      const double a = ed[0] * u[0], b = ed[1] * u[1], c3 = ed[2] * u[2];
+      const double c = (a + b) + c3;
+      if (k == 0 || c > cb) { cb = c; best = k; }
+    }
+    return best;
+  };
+  struct Em {
+    int32_t recv;
+    int32_t k;
+    double amt;
+  };
+  std::vector<Em> em;
+  double esc_emit = 0.0;
+  for (int s = 0; s < d->n_src; ++s) {
+    const int32_t vi = d->src_vertex[s];
+    const int32_t v = g->inv[(size_t)vi];
+    const double Es = d->src_rate[s] * d->dt;
+    const double *u = d->src_dir ? d->src_dir + 3 * s : nullptr;
+    const bool iso = !u || (u[0] == 0.0 && u[1] == 0.0 && u[2] == 0.0);
+    const int64_t deg = d->nbr_ptr[vi + 1] - d->nbr_ptr[vi];
+    if (iso) {
+      if (deg == 0) { esc_emit += Es; continue; }
+      const double share = (Es / unit) / (double)deg;
+      for (int64_t p = d->nbr_ptr[vi]; p < d->nbr_ptr[vi + 1]; ++p) {
+        const int32_t e = g->orig_to_new_e[(size_t)p];
+        em.push_back({g->nbr_h[(size_t)e], edge_bin(e), share});
+      }
+    } else {
+      // beam: the <= mpb neighbours most aligned with u, cosine > cos_min,
+      // ties to the lower original id (rows are in original-id order)
+      int32_t sl[3];
+      double cs[3];
+      int cnt = 0;
+      for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) {
+        const double *ed = &edir[(size_t)(3 * e)];
+        const double a = ed[0] * u[0], b = ed[1] * u[1], c3 = ed[2] * u[2];
+        const double c = (a + b) + c3;
+        if (!(c > d->cos_min)) continue;
+        int pos = cnt < d->max_per_bin ? cnt : d->max_per_bin;
+        while (pos > 0 && c > cs[pos - 1]) --pos;
+        if (pos >= d->max_per_bin) continue;
+        const int last = cnt < d->max_per_bin ? cnt : d->max_per_bin - 1;
+        for (int q = last; q > pos; --q) { cs[q] = cs[q - 1]; sl[q] = sl[q - 1]; }
+        cs[pos] = c;
+        sl[pos] = e;
+        if (cnt < d->max_per_bin) ++cnt;
+      }
+      if (cnt == 0) { esc_emit += Es; continue; }
+      const double share = (Es / unit) / (double)cnt;
+      for (int q = 0; q < cnt; ++q)
+        em.push_back({g->nbr_h[(size_t)sl[q]], edge_bin(sl[q]), share});
+    }
+  }
+  g->esc_emit = esc_emit;
+  if ((int64_t)em.size() >= ((int64_t)1 << sx::kRecIdxBits))
+    return fail(ctx, SX_ENOTSUP, "too many source-neighbour pairs (%zu)", em.size());
+  // per receiver, by bin; equal bins keep source order
+  std::stable_sort(em.begin(), em.end(), [](const Em &a, const Em &b) {
+    return a.recv != b.recv ? a.recv < b.recv : a.k < b.k;
+  });
+  std::vector<int32_t> &em_ptr = P->em_ptr, &em_k = P->em_k;
+  std::vector<double> &em_amt = P->em_amt;
+  em_ptr.assign((size_t)npad + 1, 0);
+  em_k.assign(em.size(), 0);
+  em_amt.assign(em.size(), 0.0);
+  for (size_t q = 0; q < em.size(); ++q) {
+    em_ptr[(size_t)em[q].recv + 1]++;
+    em_k[q] = em[q].k;
+    em_amt[q] = em[q].amt;
+  }
+  for (int64_t v = 0; v < npad; ++v) em_ptr[(size_t)v + 1] += em_ptr[(size_t)v];
+  g->n_em = (int64_t)em.size();
+  return SX_OK;
+}
+
+// The device part of an upload: budget, slot, allocations, copies, the
+// selection tables and gather lists built on the GPU, initial state.
+int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
+  const Sizes S = P->S;
+  const int64_t n = S.n, E = S.E, K = S.K, npad = S.npad, ntiles = S.ntiles;
+  (void)n;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (ctx->free_slots.empty()) return fail(ctx, SX_ENOMEM, "too many grids");
+  {
+    const uint64_t want = bytes_estimate(S, (int64_t)P->em_k.size(),
+                                         (int64_t)(0.05 * (double)(S.npad * S.K)),
+                                         (int64_t)P->halo_vid.size());
+    if (ctx->used + want > ctx->budget)
+      return fail(ctx, SX_ENOMEM, "grid needs ~%llu bytes, %llu of %llu free",
+                  (unsigned long long)want,
+                  (unsigned long long)(ctx->budget - ctx->used),
+                  (unsigned long long)ctx->budget);
+  }
+  Grid *g = P->g;
+  P->g = nullptr;   // owned here from now on
+  std::vector<int32_t> &rp = g->row_ptr_h;
+  std::vector<int32_t> &halo_vid = P->halo_vid;
+  const double unit = P->unit;
+
+  // ---- device allocations
+  GridDev &h = g->hg;
+  h.n = (int32_t)n;
+  h.npad = (int32_t)npad;
+  h.ntiles = (int32_t)S.ntiles;
+  h.k = (int32_t)K;
+  h.kw = (int32_t)S.kw;
+  h.bb = (int32_t)S.bb;
+  h.kb = (int32_t)S.kb;
+  h.n_sub = P->n_sub;
+  h.mpb = P->mpb;
+  h.precision = P->precision;
+  h.parity = 0;
+  h.remaining = 0;
+  h.sweeps = 0;
+  h.unit = unit;
+  h.dt = P->dt;
+  h.cos_min = P->cos_min;
+  h.plane = npad + sx::kTile;   // the extra tile stays zero
+  h.n_edges = E;
+  int32_t *d_rp, *d_nbr, *d_rec_cnt, *d_rec_ptr, *d_hptr, *d_hvid;
+  uint8_t *d_rev, *d_ebin, *d_tdir;
+  uint16_t *d_ehidx;
+  double *d_edir, *d_bins, *d_tau, *d_dtnhv, *d_b, *d_y, *d_nin, *d_y0, *d_tally;
+  uint32_t *d_fwd, *d_mb;
+  uint64_t *d_inw;
+  void *d_o0, *d_o1;
+#define GA(ptr, cnt)                                      \
+  do {                                                    \
+    int r_ = galloc(ctx, g, &ptr, (uint64_t)(cnt));       \
+    if (r_) { grid_release(ctx, g); return r_; }          \
+  } while (0)
+  GA(d_rp, npad + 1);
+  GA(d_nbr, E);
+  GA(d_rev, E);
+  GA(d_edir, 3 * E);
+  GA(d_bins, 3 * K);
+  GA(d_fwd, npad * K);
+  GA(d_ebin, E);
+  GA(d_inw, npad * S.kb * S.bb);
+  GA(d_mb, npad * S.kw);
+  GA(d_rec_cnt, ntiles * K + 1);
+  GA(d_rec_ptr, ntiles * K + 1);
+  GA(d_hptr, ntiles + 1);
+  GA(d_hvid, halo_vid.size() + 1);
+  GA(d_ehidx, E);
+  GA(d_tdir, ntiles);
+  GA(d_tau, npad);
+  GA(d_dtnhv, npad);
+  GA(d_b, npad);
+  GA(d_y, npad);
+  GA(d_nin, npad);
+  GA(d_y0, npad);
+  GA(d_tally, 3 * S.ntiles);
+  void *d_t0, *d_t1;
+  {
+    uint8_t *o0, *o1, *t0, *t1;
+    GA(o0, (uint64_t)sx::kBlockBytes * S.kb * (npad + sx::kTile));
+    GA(o1, (uint64_t)sx::kBlockBytes * S.kb * (npad + sx::kTile));
+    GA(t0, (uint64_t)S.sp * (npad + sx::kTile));
+    GA(t1, (uint64_t)S.sp * (npad + sx::kTile));
+    d_o0 = o0;
+    d_o1 = o1;
+    d_t0 = t0;
+    d_t1 = t1;
+  }
+  h.row_ptr = d_rp;
+  h.nbr = d_nbr;
+  h.rev = d_rev;
+  h.edir = d_edir;
+  h.bins = d_bins;
+  h.fwd = d_fwd;
+  h.ebin = d_ebin;
+  h.inw = d_inw;
+  h.mbits = d_mb;
+  h.rec_cnt = d_rec_cnt;
+  h.rec_ptr = d_rec_ptr;
+  h.rec = nullptr;
+  h.rec_cap = 0;
+  h.halo_ptr = d_hptr;
+  h.halo_vid = d_hvid;
+  h.edge_hidx = d_ehidx;
+  h.tile_direct = d_tdir;
+  h.tau = d_tau;
+  h.dtnhv = d_dtnhv;
+  h.bcoef = d_b;
+  h.y = d_y;
+  h.nin = d_nin;
+  h.o[0] = d_o0;
+  h.o[1] = d_o1;
+  h.t[0] = d_t0;
+  h.t[1] = d_t1;
+  h.tally = d_tally;
+  g->y_init = d_y0;
+  g->slot = ctx->free_slots.back();
+  ctx->free_slots.pop_back();
+
+  hipStream_t st = ctx->stream;
+  auto H2D = [&](void *dst, const void *src, size_t bytes) {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+  };
+#define UP(dst, src, bytes)                                                   \
+  do {                                                                        \
+    hipError_t e_ = H2D(dst, src, bytes);                                     \
+    if (e_ != hipSuccess) {                                                   \
+      grid_release(ctx, g);                                                   \
+      return fail(ctx, SX_EDEVICE, "upload copy failed: %s", hipGetErrorString(e_)); \
+    }                                                                         \
+  } while (0)
+  UP(d_rp, rp.data(), 4 * (npad + 1));
+  UP(d_nbr, g->nbr_h.data(), 4 * E);
+  UP(d_rev, P->rev.data(), E);
+  UP(d_edir, P->edir.data(), 24 * E);
+  UP(d_bins, P->bins.data(), 24 * K);
+  UP(d_tau, P->tau.data(), 8 * npad);
+  UP(d_dtnhv, P->dtnhv.data(), 8 * npad);
+  UP(d_b, P->bco.data(), 8 * npad);
+  UP(d_y0, P->y0.data(), 8 * npad);
+  UP(d_hptr, P->halo_ptr.data(), 4 * (ntiles + 1));
+  UP(d_hvid, halo_vid.data(), 4 * halo_vid.size());
+  UP(d_ehidx, P->edge_hidx.data(), 2 * E);
+  UP(d_tdir, g->tile_direct.data(), ntiles);
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    grid_release(ctx, g);
+    return fail(ctx, SX_EDEVICE, "upload sync failed");
+  }
+  int r;
+  if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
+
+  // ---- selection tables, source lists, gather lists (records sized by a
+  // count pass)
+  GridDev *dg = ctx->table + g->slot;
+  auto kfail = [&](hipError_t e) {
+    grid_release(ctx, g);
+    return fail(ctx, SX_EDEVICE, "table kernels failed: %s", hipGetErrorString(e));
+  };
+  hipError_t he;
+  const int32_t nrow = (int32_t)(ntiles * K);
+  if ((he = sx::launch_select(dg, h, st)) != hipSuccess) return kfail(he);
+  if ((he = sx::launch_edge_bins(dg, h, st)) != hipSuccess) return kfail(he);
+  g->n_em = (int64_t)P->em_k.size();
+  {
+    int32_t *d_emp, *d_emk;
+    double *d_ema;
+    GA(d_emp, npad + 1);
+    GA(d_emk, g->n_em + 1);
+    GA(d_ema, g->n_em + 1);
+    UP(d_emp, P->em_ptr.data(), 4 * (npad + 1));
+    if (g->n_em) {
+      UP(d_emk, P->em_k.data(), 4 * g->n_em);
+      UP(d_ema, P->em_amt.data(), 8 * g->n_em);
+    }
+    h.em_ptr = d_emp;
+    h.em_k = d_emk;
+    h.em_amt = d_ema;
+  }
+  if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
+  if ((he = sx::launch_mbits(dg, h, st)) != hipSuccess) return kfail(he);
+  if ((he = sx::launch_clear_inw(h, st)) != hipSuccess) return kfail(he);
+  if ((he = sx::launch_inlist_count(dg, h, st)) != hipSuccess) return kfail(he);
+  if ((he = sx::launch_scan(h.rec_cnt, h.rec_ptr, nrow, st)) != hipSuccess) return kfail(he);
+  int32_t n_rec = 0;
+  if ((he = hipMemcpyAsync(&n_rec, h.rec_ptr + nrow, 4, hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return kfail(he);
+  if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
+  {
+    uint32_t *d_rec;
+    GA(d_rec, (uint64_t)n_rec + 1);
+    h.rec = d_rec;
+    h.rec_cap = n_rec;
+  }
+  if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
+  if ((he = sx::launch_inlist_fill(dg, h, st)) != hipSuccess) return kfail(he);
+
+#undef GA
+#undef UP
+  if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
+  if ((he = sx::launch_reset_state(dg, h, g->y_init, st)) != hipSuccess) return kfail(he);
+  if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
+  if ((he = hipGetLastError()) != hipSuccess) return kfail(he);
+  g->id = ctx->next_id++;
+  ctx->grids[g->id] = g;
+  *out = g->id;
+  return SX_OK;
+}
+
+}  // namespace
+
 // =================================================================== ABI ==
 extern "C" {
 
@@ -511,418 +992,48 @@ int sx_grid_bytes(const sx_grid_desc *d, uint64_t *bytes) {
   return SX_OK;
 }
 
+int sx_grid_prepare(const sx_grid_desc *d, sx_prepared **out, char *err, size_t err_len) {
+  if (!out) return SX_EINVAL;
+  *out = nullptr;
+  sx_ctx sink;   // collects the message only
+  sx_prepared *P = new sx_prepared();
+  int r = prepare(&sink, d, P);
+  if (r) {
+    delete P;
+    if (err && err_len) snprintf(err, err_len, "%s", sink.err.c_str());
+    return r;
+  }
+  *out = P;
+  return SX_OK;
+}
+
+int sx_grid_commit(sx_ctx *ctx, sx_prepared *p, sx_grid_id *out) {
+  if (!ctx || !p || !out) return SX_EINVAL;
+  if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
+  if (!p->g) return fail(ctx, SX_EINVAL, "prepared grid already committed");
+  return commit(ctx, p, out);
+}
+
+int sx_prepared_free(sx_prepared *p) {
+  delete p;
+  return SX_OK;
+}
+
+int sx_prepared_bytes(const sx_prepared *p, uint64_t *bytes) {
+  if (!p || !bytes || !p->g) return SX_EINVAL;
+  *bytes = bytes_estimate(p->S, (int64_t)p->em_k.size(),
+                          (int64_t)(0.05 * (double)(p->S.npad * p->S.K)),
+                          (int64_t)p->halo_vid.size());
+  return SX_OK;
+}
+
 int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out) {
   if (!ctx || !out) return SX_EINVAL;
   if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
-  int rc = validate(ctx, d);
-  if (rc) return rc;
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
-  if (ctx->free_slots.empty()) return fail(ctx, SX_ENOMEM, "too many grids");
-  const Sizes S = sizes_of(d);
-  {
-    uint64_t want = 0;
-    sx_grid_bytes(d, &want);
-    if (ctx->used + want > ctx->budget)
-      return fail(ctx, SX_ENOMEM, "grid needs ~%llu bytes, %llu of %llu free",
-                  (unsigned long long)want,
-                  (unsigned long long)(ctx->budget - ctx->used),
-                  (unsigned long long)ctx->budget);
-  }
-  const int64_t n = S.n, E = S.E, K = S.K, npad = S.npad;
-  Grid *g = new Grid();
-
-  // ---- reorder along a Hilbert curve (locality of the gathers)
-  g->perm = hilbert_order(d->pos, n);
-  g->inv.assign((size_t)n, 0);
-  for (int64_t v = 0; v < n; ++v) g->inv[(size_t)g->perm[(size_t)v]] = (int32_t)v;
-
-  // ---- new CSR, rows sorted by ORIGINAL neighbour id, so that summing the
-  // in-list in slot order adds the senders in ascending original id
-  std::vector<int32_t> &rp = g->row_ptr_h;
-  rp.assign((size_t)npad + 1, 0);
-  for (int64_t v = 0; v < n; ++v) {
-    const int32_t i = g->perm[(size_t)v];
-    rp[(size_t)v + 1] = rp[(size_t)v] + (int32_t)(d->nbr_ptr[i + 1] - d->nbr_ptr[i]);
-  }
-  for (int64_t v = n; v < npad; ++v) rp[(size_t)v + 1] = rp[(size_t)v];
-  std::vector<int32_t> orig_nbr((size_t)E);   // original id of each new edge's target
-  g->nbr_h.assign((size_t)E, 0);
-  g->orig_to_new_e.assign((size_t)E, 0);
-  std::vector<double> edir((size_t)(3 * E));
-  std::vector<double> len_orig((size_t)E);     // per original CSR position
-  {
-    std::vector<std::pair<int32_t, int64_t>> row;
-    for (int64_t v = 0; v < n; ++v) {
-      const int32_t i = g->perm[(size_t)v];
-      row.clear();
-      for (int64_t p = d->nbr_ptr[i]; p < d->nbr_ptr[i + 1]; ++p)
-        row.push_back({d->nbr_idx[p], p});
-      std::sort(row.begin(), row.end());
-      for (size_t r = 0; r < row.size(); ++r) {
-        const int64_t e = rp[(size_t)v] + (int64_t)r;
-        const int32_t j = row[r].first;
-        orig_nbr[(size_t)e] = j;
-        g->nbr_h[(size_t)e] = g->inv[(size_t)j];
-        g->orig_to_new_e[(size_t)row[r].second] = (int32_t)e;
-      }
-    }
-  }
-  // ---- edge geometry in IEEE double with every operation rounded (the
-  // library is built without FMA contraction on the host): unit vector and
-  // length of each directed edge
-  for (int64_t i = 0; i < n; ++i) {
-    for (int64_t p = d->nbr_ptr[i]; p < d->nbr_ptr[i + 1]; ++p) {
-      const int32_t j = d->nbr_idx[p];
-      const double dx = d->pos[3 * j + 0] - d->pos[3 * i + 0];
-      const double dy = d->pos[3 * j + 1] - d->pos[3 * i + 1];
-      const double dz = d->pos[3 * j + 2] - d->pos[3 * i + 2];
-      const double xx = dx * dx, yy = dy * dy, zz = dz * dz;
-      const double len = std::sqrt((xx + yy) + zz);
-      const int64_t e = g->orig_to_new_e[(size_t)p];
-      edir[(size_t)(3 * e + 0)] = dx / len;
-      edir[(size_t)(3 * e + 1)] = dy / len;
-      edir[(size_t)(3 * e + 2)] = dz / len;
-      len_orig[(size_t)p] = len;
-    }
-  }
-  // ---- reverse slots: position of the row's vertex in its neighbour's row
-  std::vector<uint8_t> rev((size_t)E);
-  for (int64_t v = 0; v < n; ++v) {
-    const int32_t vi = g->perm[(size_t)v];
-    for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) {
-      const int32_t w = g->nbr_h[(size_t)e];
-      auto b = orig_nbr.begin() + rp[(size_t)w], en = orig_nbr.begin() + rp[(size_t)w + 1];
-      auto it = std::lower_bound(b, en, vi);
-      rev[(size_t)e] = (uint8_t)(it - b);
-    }
-  }
-  // ---- tile halos: every neighbour of a tile's vertices, ascending; the
-  // index of each edge's target in its tile's halo.  Tiles with more than
-  // kHaloMax halo vertices gather directly (edge index = row slot).
-  const int64_t ntiles = S.ntiles;
-  std::vector<int32_t> halo_ptr((size_t)ntiles + 1, 0), halo_vid;
-  std::vector<uint16_t> edge_hidx((size_t)E, 0);
-  std::vector<uint8_t> tile_direct((size_t)ntiles, 0);
-  {
-    // SX_FORCE_DIRECT=1 makes every tile gather directly (a test knob for
-    // the path large-halo tiles take)
-    const char *fd = std::getenv("SX_FORCE_DIRECT");
-    const bool force_direct = fd && fd[0] == '1';
-    std::vector<int32_t> h;
-    for (int64_t t = 0; t < ntiles; ++t) {
-      const int64_t v0 = t * sx::kTile, v1 = std::min<int64_t>(v0 + sx::kTile, n);
-      h.clear();
-      for (int64_t v = v0; v < v1; ++v)
-        for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) h.push_back(g->nbr_h[(size_t)e]);
-      std::sort(h.begin(), h.end());
-      h.erase(std::unique(h.begin(), h.end()), h.end());
-      if ((int64_t)h.size() > sx::kHaloMax || force_direct) {
-        tile_direct[(size_t)t] = 1;
-        for (int64_t v = v0; v < v1; ++v)
-          for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e)
-            edge_hidx[(size_t)e] = (uint16_t)(e - rp[(size_t)v]);
-      } else {
-        for (int64_t v = v0; v < v1; ++v)
-          for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e)
-            edge_hidx[(size_t)e] = (uint16_t)(std::lower_bound(h.begin(), h.end(),
-                                                               g->nbr_h[(size_t)e]) - h.begin());
-        halo_vid.insert(halo_vid.end(), h.begin(), h.end());
-      }
-      halo_ptr[(size_t)t + 1] = (int32_t)halo_vid.size();
-    }
-  }
-  g->n_direct = 0;
-  for (auto d8 : tile_direct) g->n_direct += d8;
-  g->tile_direct = tile_direct;
-
-  // ---- per-vertex physics in new order
-  std::vector<double> tau((size_t)npad, 0.0), dtnhv((size_t)npad, 1.0),
-      bco((size_t)npad, 0.0), y0((size_t)npad, 1.0);
-  g->dL_h.assign((size_t)n, 0.0);
-  g->tau_h.assign((size_t)n, 0.0);
-  for (int64_t v = 0; v < n; ++v) {
-    const int32_t i = g->perm[(size_t)v];
-    double dl;
-    if (d->dL) {
-      dl = d->dL[i];
-    } else {
-      // mean incident edge length (in the caller's row order) times kappa
-      double sum = 0.0;
-      const int64_t deg = d->nbr_ptr[i + 1] - d->nbr_ptr[i];
-      for (int64_t p = d->nbr_ptr[i]; p < d->nbr_ptr[i + 1]; ++p) sum += len_orig[(size_t)p];
-      dl = deg > 0 ? d->kappa * (sum / (double)deg) : 0.0;
-    }
-    g->dL_h[(size_t)v] = dl;
-    tau[(size_t)v] = (d->n_H[i] * d->sigma) * dl;
-    g->tau_h[(size_t)v] = tau[(size_t)v];
-    dtnhv[(size_t)v] = d->dt * (d->n_H[i] * d->volume[i]);
-    bco[(size_t)v] = d->alpha_B * d->n_H[i];
-    y0[(size_t)v] = d->x_init ? 1.0 - d->x_init[i] : 1.0;
-  }
-  // ---- photon unit: the power of two nearest the photons emitted per step
-  double e_sweep = 0.0;
-  for (int s = 0; s < d->n_src; ++s) e_sweep += d->src_rate[s] * d->dt;
-  double unit = 1.0;
-  if (e_sweep > 0.0 && std::isfinite(e_sweep)) unit = std::ldexp(1.0, (int)std::lround(std::log2(e_sweep)));
-  g->e_sweep = e_sweep;
-
-  // ---- device allocations
-  GridDev &h = g->hg;
-  h.n = (int32_t)n;
-  h.npad = (int32_t)npad;
-  h.ntiles = (int32_t)S.ntiles;
-  h.k = (int32_t)K;
-  h.kw = (int32_t)S.kw;
-  h.bb = (int32_t)S.bb;
-  h.kb = (int32_t)S.kb;
-  h.n_sub = d->n_subcycles;
-  h.mpb = d->max_per_bin;
-  h.precision = d->precision;
-  h.parity = 0;
-  h.remaining = 0;
-  h.sweeps = 0;
-  h.unit = unit;
-  h.dt = d->dt;
-  h.cos_min = d->cos_min;
-  h.plane = npad + sx::kTile;   // the extra tile stays zero
-  h.n_edges = E;
-  int32_t *d_rp, *d_nbr, *d_rec_cnt, *d_rec_ptr, *d_hptr, *d_hvid;
-  uint8_t *d_rev, *d_ebin, *d_tdir;
-  uint16_t *d_ehidx;
-  double *d_edir, *d_bins, *d_tau, *d_dtnhv, *d_b, *d_y, *d_nin, *d_y0, *d_tally;
-  uint32_t *d_fwd, *d_mb;
-  uint64_t *d_inw;
-  void *d_o0, *d_o1;
-#define GA(ptr, cnt)                                      \
-  do {                                                    \
-    int r_ = galloc(ctx, g, &ptr, (uint64_t)(cnt));       \
-    if (r_) { grid_release(ctx, g); return r_; }          \
-  } while (0)
-  GA(d_rp, npad + 1);
-  GA(d_nbr, E);
-  GA(d_rev, E);
-  GA(d_edir, 3 * E);
-  GA(d_bins, 3 * K);
-  GA(d_fwd, npad * K);
-  GA(d_ebin, E);
-  GA(d_inw, npad * S.kb * S.bb);
-  GA(d_mb, npad * S.kw);
-  GA(d_rec_cnt, ntiles * K + 1);
-  GA(d_rec_ptr, ntiles * K + 1);
-  GA(d_hptr, ntiles + 1);
-  GA(d_hvid, halo_vid.size() + 1);
-  GA(d_ehidx, E);
-  GA(d_tdir, ntiles);
-  GA(d_tau, npad);
-  GA(d_dtnhv, npad);
-  GA(d_b, npad);
-  GA(d_y, npad);
-  GA(d_nin, npad);
-  GA(d_y0, npad);
-  GA(d_tally, 3 * S.ntiles);
-  void *d_t0, *d_t1;
-  {
-    uint8_t *o0, *o1, *t0, *t1;
-    GA(o0, (uint64_t)sx::kBlockBytes * S.kb * (npad + sx::kTile));
-    GA(o1, (uint64_t)sx::kBlockBytes * S.kb * (npad + sx::kTile));
-    GA(t0, (uint64_t)S.sp * (npad + sx::kTile));
-    GA(t1, (uint64_t)S.sp * (npad + sx::kTile));
-    d_o0 = o0;
-    d_o1 = o1;
-    d_t0 = t0;
-    d_t1 = t1;
-  }
-  h.row_ptr = d_rp;
-  h.nbr = d_nbr;
-  h.rev = d_rev;
-  h.edir = d_edir;
-  h.bins = d_bins;
-  h.fwd = d_fwd;
-  h.ebin = d_ebin;
-  h.inw = d_inw;
-  h.mbits = d_mb;
-  h.rec_cnt = d_rec_cnt;
-  h.rec_ptr = d_rec_ptr;
-  h.rec = nullptr;
-  h.rec_cap = 0;
-  h.halo_ptr = d_hptr;
-  h.halo_vid = d_hvid;
-  h.edge_hidx = d_ehidx;
-  h.tile_direct = d_tdir;
-  h.tau = d_tau;
-  h.dtnhv = d_dtnhv;
-  h.bcoef = d_b;
-  h.y = d_y;
-  h.nin = d_nin;
-  h.o[0] = d_o0;
-  h.o[1] = d_o1;
-  h.t[0] = d_t0;
-  h.t[1] = d_t1;
-  h.tally = d_tally;
-  g->y_init = d_y0;
-  g->slot = ctx->free_slots.back();
-  ctx->free_slots.pop_back();
-
-  hipStream_t st = ctx->stream;
-  auto H2D = [&](void *dst, const void *src, size_t bytes) {
-    if (bytes == 0) return hipSuccess;
-    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
-  };
-#define UP(dst, src, bytes)                                                   \
-  do {                                                                        \
-    hipError_t e_ = H2D(dst, src, bytes);                                     \
-    if (e_ != hipSuccess) {                                                   \
-      grid_release(ctx, g);                                                   \
-      return fail(ctx, SX_EDEVICE, "upload copy failed: %s", hipGetErrorString(e_)); \
-    }                                                                         \
-  } while (0)
-  UP(d_rp, rp.data(), 4 * (npad + 1));
-  UP(d_nbr, g->nbr_h.data(), 4 * E);
-  UP(d_rev, rev.data(), E);
-  UP(d_edir, edir.data(), 24 * E);
-  UP(d_bins, d->bin_dirs, 24 * K);
-  UP(d_tau, tau.data(), 8 * npad);
-  UP(d_dtnhv, dtnhv.data(), 8 * npad);
-  UP(d_b, bco.data(), 8 * npad);
-  UP(d_y0, y0.data(), 8 * npad);
-  UP(d_hptr, halo_ptr.data(), 4 * (ntiles + 1));
-  UP(d_hvid, halo_vid.data(), 4 * halo_vid.size());
-  UP(d_ehidx, edge_hidx.data(), 2 * E);
-  UP(d_tdir, tile_direct.data(), ntiles);
-  if (hipStreamSynchronize(st) != hipSuccess) {
-    grid_release(ctx, g);
-    return fail(ctx, SX_EDEVICE, "upload sync failed");
-  }
-  int r;
-  if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
-
-  // ---- selection tables, source lists, gather lists (records sized by a
-  // count pass)
-  GridDev *dg = ctx->table + g->slot;
-  auto kfail = [&](hipError_t e) {
-    grid_release(ctx, g);
-    return fail(ctx, SX_EDEVICE, "table kernels failed: %s", hipGetErrorString(e));
-  };
-  hipError_t he;
-  const int32_t nrow = (int32_t)(ntiles * K);
-  if ((he = sx::launch_select(dg, h, st)) != hipSuccess) return kfail(he);
-  if ((he = sx::launch_edge_bins(dg, h, st)) != hipSuccess) return kfail(he);
-  // ---- sources: per receiving vertex, in source order, the share of each
-  // source's photons and the bin of the edge it arrives along
-  std::vector<uint8_t> ebin((size_t)E);
-  if (E > 0) {
-    if ((he = hipMemcpyAsync(ebin.data(), d_ebin, E, hipMemcpyDeviceToHost, st)) != hipSuccess)
-      return kfail(he);
-    if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
-  }
-  struct Em {
-    int32_t recv;
-    int32_t k;
-    double amt;
-  };
-  std::vector<Em> em;
-  double esc_emit = 0.0;
-  for (int s = 0; s < d->n_src; ++s) {
-    const int32_t vi = d->src_vertex[s];
-    const int32_t v = g->inv[(size_t)vi];
-    const double Es = d->src_rate[s] * d->dt;
-    const double *u = d->src_dir ? d->src_dir + 3 * s : nullptr;
-    const bool iso = !u || (u[0] == 0.0 && u[1] == 0.0 && u[2] == 0.0);
-    const int64_t deg = d->nbr_ptr[vi + 1] - d->nbr_ptr[vi];
-    if (iso) {
-      if (deg == 0) { esc_emit += Es; continue; }
-      const double share = (Es / unit) / (double)deg;
-      for (int64_t p = d->nbr_ptr[vi]; p < d->nbr_ptr[vi + 1]; ++p) {
-        const int32_t e = g->orig_to_new_e[(size_t)p];
-        em.push_back({g->nbr_h[(size_t)e], (int32_t)ebin[(size_t)e], share});
-      }
-    } else {
-      // beam: the <= mpb neighbours most aligned with u, cosine > cos_min,
-      // ties to the lower original id (rows are in original-id order)
-      int32_t sl[3];
-      double cs[3];
-      int cnt = 0;
-      for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) {
-        const double *ed = &edir[(size_t)(3 * e)];
-        const double a = ed[0] * u[0], b = ed[1] * u[1], c3 = ed[2] * u[2];
-        const double c = (a + b) + c3;
-        if (!(c > d->cos_min)) continue;
-        int pos = cnt < d->max_per_bin ? cnt : d->max_per_bin;
-        while (pos > 0 && c > cs[pos - 1]) --pos;
-        if (pos >= d->max_per_bin) continue;
-        const int last = cnt < d->max_per_bin ? cnt : d->max_per_bin - 1;
-        for (int q = last; q > pos; --q) { cs[q] = cs[q - 1]; sl[q] = sl[q - 1]; }
-        cs[pos] = c;
-        sl[pos] = e;
-        if (cnt < d->max_per_bin) ++cnt;
-      }
-      if (cnt == 0) { esc_emit += Es; continue; }
-      const double share = (Es / unit) / (double)cnt;
-      for (int q = 0; q < cnt; ++q)
-        em.push_back({g->nbr_h[(size_t)sl[q]], (int32_t)ebin[(size_t)sl[q]], share});
-    }
-  }
-  g->esc_emit = esc_emit;
-  if ((int64_t)em.size() >= ((int64_t)1 << sx::kRecIdxBits)) {
-    grid_release(ctx, g);
-    return fail(ctx, SX_ENOTSUP, "too many source-neighbour pairs (%zu)", em.size());
-  }
-  // per receiver, by bin; equal bins keep source order
-  std::stable_sort(em.begin(), em.end(), [](const Em &a, const Em &b) {
-    return a.recv != b.recv ? a.recv < b.recv : a.k < b.k;
-  });
-  std::vector<int32_t> em_ptr((size_t)npad + 1, 0), em_k(em.size());
-  std::vector<double> em_amt(em.size());
-  for (size_t q = 0; q < em.size(); ++q) {
-    em_ptr[(size_t)em[q].recv + 1]++;
-    em_k[q] = em[q].k;
-    em_amt[q] = em[q].amt;
-  }
-  for (int64_t v = 0; v < npad; ++v) em_ptr[(size_t)v + 1] += em_ptr[(size_t)v];
-  g->n_em = (int64_t)em.size();
-  {
-    int32_t *d_emp, *d_emk;
-    double *d_ema;
-    GA(d_emp, npad + 1);
-    GA(d_emk, g->n_em + 1);
-    GA(d_ema, g->n_em + 1);
-    UP(d_emp, em_ptr.data(), 4 * (npad + 1));
-    if (g->n_em) {
-      UP(d_emk, em_k.data(), 4 * g->n_em);
-      UP(d_ema, em_amt.data(), 8 * g->n_em);
-    }
-    h.em_ptr = d_emp;
-    h.em_k = d_emk;
-    h.em_amt = d_ema;
-  }
-  if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
-  if ((he = sx::launch_mbits(dg, h, st)) != hipSuccess) return kfail(he);
-  if ((he = sx::launch_clear_inw(h, st)) != hipSuccess) return kfail(he);
-  if ((he = sx::launch_inlist_count(dg, h, st)) != hipSuccess) return kfail(he);
-  if ((he = sx::launch_scan(h.rec_cnt, h.rec_ptr, nrow, st)) != hipSuccess) return kfail(he);
-  int32_t n_rec = 0;
-  if ((he = hipMemcpyAsync(&n_rec, h.rec_ptr + nrow, 4, hipMemcpyDeviceToHost, st)) != hipSuccess)
-    return kfail(he);
-  if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
-  {
-    uint32_t *d_rec;
-    GA(d_rec, (uint64_t)n_rec + 1);
-    h.rec = d_rec;
-    h.rec_cap = n_rec;
-  }
-  if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
-  if ((he = sx::launch_inlist_fill(dg, h, st)) != hipSuccess) return kfail(he);
-
-#undef GA
-#undef UP
-  if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
-  if ((he = sx::launch_reset_state(dg, h, g->y_init, st)) != hipSuccess) return kfail(he);
-  if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
-  if ((he = hipGetLastError()) != hipSuccess) return kfail(he);
-  g->id = ctx->next_id++;
-  ctx->grids[g->id] = g;
-  *out = g->id;
-  return SX_OK;
+  sx_prepared P;
+  int r = prepare(ctx, d, &P);
+  if (r) return r;
+  return commit(ctx, &P, out);
 }
 
 int sx_grid_reset(sx_ctx *ctx, sx_grid_id id) {

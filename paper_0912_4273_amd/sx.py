@@ -22,6 +22,7 @@ SX_ENOMEM = -2
 SX_EDEVICE = -3
 SX_ENOTFOUND = -4
 SX_ENOTSUP = -5
+SX_EAGAIN = -6
 SX_FP64 = 0
 SX_FP32_TRANSPORT = 1
 SX_ORDER_GRID = 0
@@ -34,7 +35,9 @@ EXPORTED = [
     "sx_solve", "sx_sync", "sx_read_state", "sx_read_tables",
     "sx_grid_info", "sx_mem_info", "sx_stream", "sx_profile",
     "sx_profile_read", "sx_set_schedule", "sx_get_schedule", "sx_autotune",
-    "sx_strerror", "sx_last_error",
+    "sx_grid_prepare", "sx_prepared_bytes", "sx_grid_commit", "sx_prepared_free",
+    "sx_serve_start", "sx_serve_submit", "sx_serve_poll", "sx_serve_take",
+    "sx_serve_stop", "sx_strerror", "sx_last_error",
 ]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -85,6 +88,27 @@ class SxSchedule(C.Structure):
                 ("xcd_contiguous", C.c_int32), ("graph_sweeps", C.c_int32)]
 
 
+class SxServeOpts(C.Structure):
+    _fields_ = [("round_sweeps", C.c_int32), ("max_active", C.c_int32),
+                ("prep_threads", C.c_int32), ("reserved", C.c_int32),
+                ("hbm_budget", C.c_uint64)]
+
+
+class SxServeResult(C.Structure):
+    _fields_ = [("ticket", C.c_int64), ("status", C.c_int32), ("n_bins", C.c_int32),
+                ("n_vertices", C.c_int64), ("n_sweeps", C.c_int32), ("reserved", C.c_int32),
+                ("t_submit", C.c_double), ("t_prepared", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double), ("tally", SxTally)]
+
+
+class SxServeStats(C.Structure):
+    _fields_ = [("finished", C.c_int64), ("failed", C.c_int64), ("rounds", C.c_int64),
+                ("peak_active", C.c_int32), ("reserved", C.c_int32),
+                ("updates", C.c_double), ("span_s", C.c_double), ("round_s", C.c_double),
+                ("latency_p50_s", C.c_double), ("latency_p99_s", C.c_double),
+                ("latency_max_s", C.c_double)]
+
+
 class SxError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{msg} (code {code})")
@@ -127,6 +151,16 @@ def load(path: Optional[str] = None):
         "sx_set_schedule": (C.c_int, [P, P, I32, C.POINTER(SxSchedule)]),
         "sx_get_schedule": (C.c_int, [P, P, I32, C.POINTER(SxSchedule), P]),
         "sx_autotune": (C.c_int, [P, I32]),
+        "sx_grid_prepare": (C.c_int, [C.POINTER(SxGridDesc), C.POINTER(P), C.c_char_p,
+                                      C.c_size_t]),
+        "sx_prepared_bytes": (C.c_int, [P, C.POINTER(C.c_uint64)]),
+        "sx_grid_commit": (C.c_int, [P, P, C.POINTER(I64)]),
+        "sx_prepared_free": (C.c_int, [P]),
+        "sx_serve_start": (C.c_int, [P, C.POINTER(SxServeOpts), C.POINTER(P)]),
+        "sx_serve_submit": (C.c_int, [P, C.POINTER(SxGridDesc), I32, C.POINTER(I64)]),
+        "sx_serve_poll": (C.c_int, [P, C.c_double, C.POINTER(SxServeResult)]),
+        "sx_serve_take": (C.c_int, [P, I64, P, P]),
+        "sx_serve_stop": (C.c_int, [P, C.POINTER(SxServeStats)]),
         "sx_strerror": (C.c_char_p, [C.c_int]),
         "sx_last_error": (C.c_char_p, [P]),
     }
@@ -224,6 +258,35 @@ def sx_grid_upload(ctx, w) -> int:
     gid = C.c_int64()
     _check(ctx, load().sx_grid_upload(ctx, C.byref(d.c), C.byref(gid)))
     return int(gid.value)
+
+
+def sx_grid_prepare(w):
+    """Host part of an upload (no context); returns an opaque handle."""
+    d = _Desc(w)
+    h = C.c_void_p()
+    err = C.create_string_buffer(256)
+    rc = load().sx_grid_prepare(C.byref(d.c), C.byref(h), err, 256)
+    if rc != SX_OK:
+        raise SxError(rc, err.value.decode() or load().sx_strerror(rc).decode())
+    return h
+
+
+def sx_prepared_bytes(p) -> int:
+    b = C.c_uint64()
+    rc = load().sx_prepared_bytes(p, C.byref(b))
+    if rc != SX_OK:
+        raise SxError(rc, load().sx_strerror(rc).decode())
+    return int(b.value)
+
+
+def sx_grid_commit(ctx, p) -> int:
+    gid = C.c_int64()
+    _check(ctx, load().sx_grid_commit(ctx, p, C.byref(gid)))
+    return int(gid.value)
+
+
+def sx_prepared_free(p) -> None:
+    load().sx_prepared_free(p)
 
 
 def sx_grid_reset(ctx, gid: int) -> None:
@@ -349,6 +412,60 @@ def sx_get_schedule(ctx, ids) -> dict:
 
 def sx_autotune(ctx, trials: int) -> None:
     _check(ctx, load().sx_autotune(ctx, int(trials)))
+
+
+class Server:
+    """The library's request loop (continuous batching) over a Context.
+    While it runs, the context belongs to the server."""
+
+    def __init__(self, ctx: "Context", round_sweeps: int = 50, max_active: int = 64,
+                 prep_threads: int = 4, hbm_budget: int = 0):
+        o = SxServeOpts(round_sweeps, max_active, prep_threads, 0, hbm_budget)
+        h = C.c_void_p()
+        rc = load().sx_serve_start(ctx.h, C.byref(o), C.byref(h))
+        if rc != SX_OK:
+            raise SxError(rc, load().sx_strerror(rc).decode())
+        self.h = h
+        self.n = {}
+
+    def submit(self, w, n_sweeps: int) -> int:
+        d = _Desc(w)
+        t = C.c_int64()
+        rc = load().sx_serve_submit(self.h, C.byref(d.c), int(n_sweeps), C.byref(t))
+        if rc != SX_OK:
+            raise SxError(rc, load().sx_strerror(rc).decode())
+        self.n[int(t.value)] = w.n
+        return int(t.value)
+
+    def poll(self, timeout: float = 1.0):
+        r = SxServeResult()
+        rc = load().sx_serve_poll(self.h, float(timeout), C.byref(r))
+        if rc == SX_EAGAIN:
+            return None
+        if rc != SX_OK:
+            raise SxError(rc, load().sx_strerror(rc).decode())
+        t = r.tally
+        return dict(ticket=r.ticket, status=r.status, n_vertices=r.n_vertices,
+                    n_bins=r.n_bins, n_sweeps=r.n_sweeps, t_submit=r.t_submit,
+                    t_prepared=r.t_prepared, t_admit=r.t_admit, t_done=r.t_done,
+                    tallies=dict(sweeps=t.sweeps, emitted=t.emitted, absorbed=t.absorbed,
+                                 escaped=t.escaped, in_flight=t.in_flight))
+
+    def take(self, ticket: int):
+        n = self.n.pop(ticket)
+        x = np.empty(n)
+        y = np.empty(n)
+        rc = load().sx_serve_take(self.h, int(ticket), _ptr(x), _ptr(y))
+        if rc != SX_OK:
+            raise SxError(rc, load().sx_strerror(rc).decode())
+        return x, y
+
+    def stop(self) -> dict:
+        st = SxServeStats()
+        if self.h:
+            load().sx_serve_stop(self.h, C.byref(st))
+            self.h = None
+        return {f: getattr(st, f) for f, _ in SxServeStats._fields_ if f != "reserved"}
 
 
 # ------------------------------------------------------ convenience ----

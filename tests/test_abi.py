@@ -49,6 +49,10 @@ def test_null_arguments_rejected_without_device():
     assert lib.sx_init(None, None) == sx.SX_EINVAL
     assert lib.sx_step(None, None, 0, 1) == sx.SX_EINVAL
     assert lib.sx_autotune(None, 1) == sx.SX_EINVAL
+    assert lib.sx_serve_start(None, None, None) == sx.SX_EINVAL
+    assert lib.sx_serve_stop(None, None) == sx.SX_OK
+    assert lib.sx_prepared_free(None) == sx.SX_OK
+    assert lib.sx_grid_commit(None, None, None) == sx.SX_EINVAL
     assert lib.sx_set_schedule(None, None, 0, None) == sx.SX_EINVAL
     assert lib.sx_get_schedule(None, None, 0, None, None) == sx.SX_EINVAL
     assert lib.sx_finalize(None) == sx.SX_OK
@@ -70,6 +74,11 @@ int main(void) {
   printf("sx_tally %zu\n", sizeof(sx_tally));
   printf("sx_schedule %zu\n", sizeof(sx_schedule));
   P(sx_schedule, order) P(sx_schedule, graph_sweeps)
+  printf("sx_serve_opts %zu\n", sizeof(sx_serve_opts));
+  printf("sx_serve_result %zu\n", sizeof(sx_serve_result));
+  printf("sx_serve_stats %zu\n", sizeof(sx_serve_stats));
+  P(sx_serve_opts, hbm_budget) P(sx_serve_result, n_vertices) P(sx_serve_result, t_submit)
+  P(sx_serve_result, tally) P(sx_serve_stats, updates) P(sx_serve_stats, latency_max_s)
   P(sx_grid_desc, kappa) P(sx_grid_desc, n_bins) P(sx_grid_desc, cos_min)
   P(sx_grid_desc, src_dir) P(sx_grid_desc, dt) P(sx_grid_desc, precision)
   P(sx_ctx_opts, stream) P(sx_ctx_opts, alloc_user)
@@ -95,6 +104,13 @@ def test_ctypes_struct_layout_matches_c():
     assert C.sizeof(sx.SxSchedule) == lay["sx_schedule"]
     for f in ("order", "graph_sweeps"):
         assert getattr(sx.SxSchedule, f).offset == lay[f"sx_schedule.{f}"], f
+    for name, cls, fields in (
+            ("sx_serve_opts", sx.SxServeOpts, ("hbm_budget",)),
+            ("sx_serve_result", sx.SxServeResult, ("n_vertices", "t_submit", "tally")),
+            ("sx_serve_stats", sx.SxServeStats, ("updates", "latency_max_s"))):
+        assert C.sizeof(cls) == lay[name], name
+        for f in fields:
+            assert getattr(cls, f).offset == lay[f"{name}.{f}"], (name, f)
     for f in ("kappa", "n_bins", "cos_min", "src_dir", "dt", "precision"):
         assert getattr(sx.SxGridDesc, f).offset == lay[f"sx_grid_desc.{f}"], f
     for f in ("stream", "alloc_user"):
@@ -128,3 +144,20 @@ def test_gridgen_has_no_method_arithmetic():
     txt = open(os.path.join(ROOT, "paper_0912_4273_amd", "gridgen.py")).read()
     for word in ("expm1", "exp(-", "argmax", "most_straightforward"):
         assert word not in txt
+
+
+def test_prepare_is_host_only():
+    """sx_grid_prepare (the host half of an upload) needs no device: it
+    accepts a valid grid, rejects a malformed one with a message, and its
+    handle reports a positive byte estimate."""
+    from paper_0912_4273_amd import gridgen as G
+    w = G.small_random(300, seed=5, n_bins=21)
+    h = sx.sx_grid_prepare(w)
+    try:
+        assert sx.sx_prepared_bytes(h) > 0
+    finally:
+        sx.sx_prepared_free(h)
+    bad = G.with_(w, nbr_idx=np.where(w.nbr_idx == 0, 1, w.nbr_idx).astype(np.int32))
+    with pytest.raises(sx.SxError) as e:
+        sx.sx_grid_prepare(bad)
+    assert e.value.code == sx.SX_EINVAL
