@@ -60,18 +60,83 @@ def measured_traffic(workload: str):
     return e.get("bytes_per_launch")
 
 
-def _batch_member(g):
+def _build(task):
     from paper_0912_4273_amd import gridgen as G
-    return G.batch_member(g)
+    if task[0] == "batch":
+        return G.batch_member(task[1])
+    return G.serve_pool_grid(task[1], task[2])
 
 
-def build_batch(n_grids: int):
-    """The 64-grid batch, built on the host cores before the GPU is touched
-    (worker processes are forked)."""
+def build_grids(n_batch: int, pool_sizes):
+    """The batch members and the serving pool, built on the host cores
+    before the GPU is touched (worker processes are forked); largest first."""
     import multiprocessing as mp
-    workers = max(1, min(16, os.cpu_count() or 1, n_grids))
+    tasks = [("pool", i, n) for i, n in enumerate(pool_sizes)][::-1]
+    tasks += [("batch", g) for g in range(n_batch)]
+    if not tasks:
+        return [], [], 0
+    workers = max(1, min(16, os.cpu_count() or 1, len(tasks)))
     with mp.get_context("fork").Pool(workers) as pool:
-        return pool.map(_batch_member, range(n_grids), chunksize=1), workers
+        out = pool.map(_build, tasks, chunksize=1)
+    pool_grids = sorted(out[:len(pool_sizes)], key=lambda w: w.n)
+    return out[len(pool_sizes):], pool_grids, workers
+
+
+def serve_leg(ctx, pool, args, log):
+    """Poisson arrivals of solve requests into the library's request loop;
+    throughput and submit-to-result latency."""
+    import threading
+    import numpy as np
+    from paper_0912_4273_amd import gridgen as G
+    from paper_0912_4273_amd import sx
+    arr = G.serve_arrivals(args.serve_rate, args.serve_seconds)
+    n_max = max(w.n for w in pool)
+    ctx.set_schedule([], graph_sweeps=0)   # the batch changes every round
+    srv = sx.Server(ctx, round_sweeps=args.serve_round, max_active=64,
+                    prep_threads=args.serve_prep_threads)
+    results, errors = [], []
+
+    def poller():
+        while len(results) + len(errors) < len(arr):
+            r = srv.poll(timeout=5.0)
+            if r is None:
+                continue
+            srv.take(r["ticket"])
+            (results if r["status"] == sx.SX_OK else errors).append(r)
+
+    th = threading.Thread(target=poller, daemon=True)
+    th.start()
+    offered = 0.0
+    t0 = time.perf_counter()
+    for r, ta in enumerate(arr):
+        dt = t0 + ta - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        w = G.serve_request(pool, r, 1e4, n_max)
+        offered += w.n * w.k * w.n_sweeps
+        srv.submit(w, w.n_sweeps)
+        if (r + 1) % 100 == 0:
+            log(f"serve: {r + 1}/{len(arr)} submitted, {len(results)} done")
+    th.join(timeout=max(600.0, 4 * args.serve_seconds))
+    wall = time.perf_counter() - t0
+    st = srv.stop()
+    ctx.set_schedule([], graph_sweeps=args.graph_sweeps)
+    lat = np.array([r["t_done"] - r["t_submit"] for r in results])
+    q = (lambda f: float(np.quantile(lat, f))) if len(lat) else (lambda f: None)
+    return dict(
+        value=st["updates"] / st["span_s"] if st["span_s"] > 0 else None,
+        unit="vertex·direction updates/s",
+        requests=len(arr), finished=int(st["finished"]), failed=int(st["failed"]),
+        arrivals=f"Poisson {args.serve_rate}/s for {args.serve_seconds} s (seed 5)",
+        vertices=f"log-uniform [1e4, {n_max}] served from a pool of {len(pool)} grids",
+        offered_updates_per_s=offered / args.serve_seconds,
+        latency_p50_s=q(0.5), latency_p99_s=q(0.99),
+        latency_max_s=float(lat.max()) if len(lat) else None,
+        queue_wait_p50_s=float(np.median([r["t_admit"] - r["t_submit"] for r in results]))
+        if results else None,
+        rounds=int(st["rounds"]), peak_active=int(st["peak_active"]),
+        gpu_round_frac=st["round_s"] / st["span_s"] if st["span_s"] > 0 else None,
+        wall_s=wall, round_sweeps=args.serve_round, prep_threads=args.serve_prep_threads)
 
 
 def cpu_baseline(w, sweeps: int):
@@ -104,6 +169,17 @@ def main():
                     help="grids in the batched leg (0 = skip it)")
     ap.add_argument("--batch-sweeps", type=int, default=200)
     ap.add_argument("--autotune-trials", type=int, default=2)
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="arrival window of the serving leg (0 = skip it)")
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-max-n", type=int, default=524288,
+                    help="largest pool grid (the full request range goes to 2e6)")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="pool up to 2e6 vertices (building it takes minutes)")
+    ap.add_argument("--serve-round", type=int, default=50)
+    ap.add_argument("--serve-prep-threads", type=int, default=12)
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving leg")
     ap.add_argument("--graph-sweeps", type=int, default=50,
                     help="sweeps per replayed HIP graph (0: one launch per sweep)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -121,12 +197,18 @@ def main():
 
     # host-side grid construction first: the batch is built by forked
     # workers, which must not inherit an initialised GPU runtime
-    batch = []
-    if args.batch_grids > 0:
-        t = time.perf_counter()
-        batch, nw = build_batch(args.batch_grids)
-        log(f"batch: {len(batch)} grids, {sum(b.n for b in batch)} vertices, built "
-            f"in {time.perf_counter() - t:.1f} s on {nw} processes")
+    if args.serve_only:
+        args.batch_grids = 0
+    if args.serve_full:
+        args.serve_max_n = 2000000
+    pool_sizes = (G.serve_pool_sizes(1e4, args.serve_max_n, 8)
+                  if args.serve_seconds > 0 else [])
+    t = time.perf_counter()
+    batch, pool, nw = build_grids(max(args.batch_grids, 0), pool_sizes)
+    if batch or pool:
+        log(f"built {len(batch)} batch grids ({sum(b.n for b in batch)} vertices) and "
+            f"{len(pool)} pool grids (up to {max([0] + [w.n for w in pool])} vertices) in "
+            f"{time.perf_counter() - t:.1f} s on {nw} processes")
     t = time.perf_counter()
     w = G.stromgren_test(args.n, seed=2, n_bins=args.bins, bins_seed=102,
                          n_sweeps=args.sweeps, precision=G.SX_FP32_TRANSPORT,
@@ -173,6 +255,13 @@ def main():
         prof = ctx.profile_read()
         ctx.profile(False)
         return el, prof, st
+
+    served = None
+    if args.serve_only:
+        served = serve_leg(ctx, pool, args, log)
+        print(json.dumps({"served": served}), flush=True)
+        ctx.close()
+        return
 
     # ---- FP32 transport + FP64 chemistry (headline)
     gid, up_s = upload(w)
@@ -253,6 +342,12 @@ def main():
         log(f"batched: {batched['value']:.3e} updates/s, {1e3 * el_b:.1f} ms/solve, "
             f"sweep launch {1e3 * kb:.1f} us, schedule {sched}")
 
+    if pool:
+        served = serve_leg(ctx, pool, args, log)
+        log(f"served: {served['finished']}/{served['requests']} requests, "
+            f"{served['value']:.3e} updates/s, p50 {served['latency_p50_s']:.2f} s, "
+            f"p99 {served['latency_p99_s']:.2f} s")
+
     bpu = algorithmic_bytes_per_update(w.k, 4)
     bytes_launch = bpu * w.n * w.k
     achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
@@ -305,6 +400,7 @@ def main():
                    "physics": "Stromgren test: n_H 1e-3, 5e48 photons/s, 13.2 kpc box, 500 Myr"},
         "fp64_plain": fp64,
         "batched": batched,
+        "served": served,
         "upload_s": up_s,
         "sweep_kernel_us": 1e3 * kern_ms,
         "roofline": roof,

@@ -347,3 +347,69 @@ def with_(w: Workload, **kw) -> Workload:
     d = dict(w.__dict__)
     d.update(kw)
     return Workload(**d)
+
+
+# ---------------------------------------------------------------- serving
+# Solve requests for the request loop: each request takes a grid from a
+# pool built once (live triangulation of up to 2e6 points per request would
+# take minutes), and draws its own sources, density field, bin set and
+# sweep count.
+
+def serve_pool_sizes(n_min: float = 1e4, n_max: float = 2e6, count: int = 8) -> list:
+    """Pool grid sizes, log-spaced over [n_min, n_max]."""
+    return [int(round(v)) for v in np.exp(np.linspace(math.log(n_min), math.log(n_max), count))]
+
+
+def serve_pool_grid(i: int, n: int, box_kpc: float = 13.2) -> Workload:
+    """Pool grid i: n Poisson points (seed 6000 + i) in the 13.2 kpc box,
+    Delaunay graph and dual volumes; physics is filled in per request."""
+    box = box_kpc * KPC_CM
+    rng = np.random.default_rng(6000 + i)
+    pts = poisson_points(n, box, rng)
+    ptr, idx, simp = delaunay(pts)
+    vol = dual_volumes(pts, simp)
+    return Workload(
+        name=f"pool{i}_n{n}", pos=pts, nbr_ptr=ptr, nbr_idx=idx,
+        n_H=np.full(n, 1e-3), volume=vol, bin_dirs=icosahedral_bins_42(),
+        src_vertex=np.zeros(1, np.int32), src_rate=np.ones(1),
+        dt=MYR_S, n_sweeps=1, precision=SX_FP32_TRANSPORT, box=box,
+        meta=dict(pool=i))
+
+
+def serve_arrivals(rate_per_s: float, seconds: float, seed: int = 5) -> np.ndarray:
+    """Poisson arrival times in [0, seconds)."""
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate_per_s)
+        if t >= seconds:
+            return np.array(out)
+        out.append(t)
+
+
+def serve_request(pool: list, r: int, n_min: float = 1e4, n_max: float = 2e6,
+                  t_end_myr: float = 500.0) -> Workload:
+    """Request r (seed 5,000,000 + r): N log-uniform in [n_min, n_max]
+    (served by the pool grid nearest in log N), 1-32 point sources with rates
+    log-uniform in [1e47, 1e50] s^-1, uniform n_H = 1e-3 cm^-3 or a 100x
+    clump (a sphere of radius 0.1 box at a random centre), 42 or 84 bins,
+    200-1000 sweeps over 500 Myr, FP32 transport."""
+    rng = np.random.default_rng(5_000_000 + r)
+    n_want = math.exp(rng.uniform(math.log(n_min), math.log(n_max)))
+    g = min(pool, key=lambda w: abs(math.log(w.n) - math.log(n_want)))
+    n_src = int(rng.integers(1, 33))
+    src = rng.choice(g.n, size=n_src, replace=False).astype(np.int32)
+    rates = 10.0 ** rng.uniform(47.0, 50.0, size=n_src)
+    n_H = np.full(g.n, 1e-3)
+    clump = bool(rng.integers(0, 2))
+    if clump:
+        c = rng.uniform(0.0, g.box, size=3)
+        inside = np.sum((g.pos - c) ** 2, axis=1) < (0.1 * g.box) ** 2
+        n_H[inside] *= 100.0
+    k = 42 if rng.integers(0, 2) == 0 else 84
+    bins = icosahedral_bins_42() if k == 42 else random_bins(84, 102)
+    sweeps = int(rng.integers(200, 1001))
+    return with_(g, name=f"req{r}_{g.name}_k{k}", n_H=n_H, bin_dirs=bins,
+                 src_vertex=src, src_rate=rates, dt=t_end_myr * MYR_S / sweeps,
+                 n_sweeps=sweeps, precision=SX_FP32_TRANSPORT,
+                 meta=dict(request=r, pool=g.meta["pool"], n_want=n_want, clump=clump))
