@@ -64,22 +64,79 @@ def _build(task):
     from paper_0912_4273_amd import gridgen as G
     if task[0] == "batch":
         return G.batch_member(task[1])
+    if task[0] == "shadow":
+        return G.shadow_test(n=task[1], n_sweeps=task[2])
     return G.serve_pool_grid(task[1], task[2])
 
 
-def build_grids(n_batch: int, pool_sizes):
-    """The batch members and the serving pool, built on the host cores
-    before the GPU is touched (worker processes are forked); largest first."""
+def build_grids(n_batch: int, pool_sizes, shadow_n: int = 0, shadow_sweeps: int = 1500):
+    """The shadowing grid, the batch members and the serving pool, built on
+    the host cores before the GPU is touched (worker processes are forked);
+    largest first."""
     import multiprocessing as mp
-    tasks = [("pool", i, n) for i, n in enumerate(pool_sizes)][::-1]
+    tasks = [("shadow", shadow_n, shadow_sweeps)] if shadow_n > 0 else []
+    tasks += [("pool", i, n) for i, n in enumerate(pool_sizes)][::-1]
     tasks += [("batch", g) for g in range(n_batch)]
     if not tasks:
-        return [], [], 0
+        return [], [], None, 0
     workers = max(1, min(16, os.cpu_count() or 1, len(tasks)))
     with mp.get_context("fork").Pool(workers) as pool:
         out = pool.map(_build, tasks, chunksize=1)
+    shadow = out.pop(0) if shadow_n > 0 else None
     pool_grids = sorted(out[:len(pool_sizes)], key=lambda w: w.n)
-    return out[len(pool_sizes):], pool_grids, workers
+    return out[len(pool_sizes):], pool_grids, shadow, workers
+
+
+def shadow_leg(ctx, w, log, profile):
+    """The 1M-vertex shadowing problem in FP32: throughput of the whole
+    solve, and the plane-parallel diagnostics (front crossing, ionised depth
+    into the clump on its axis against the 1-D Stromgren length, ionisation
+    behind the clump against off the shadow)."""
+    import numpy as np
+    from paper_0912_4273_amd import gridgen as G
+    kpc = G.KPC_CM
+    t0 = time.perf_counter()
+    gid = ctx.upload(w)
+    up = time.perf_counter() - t0
+    profile(True)
+    t0 = time.perf_counter()
+    ctx.solve([gid], w.n_sweeps)
+    st = ctx.state(gid, nin=False)
+    el = time.perf_counter() - t0
+    pr = profile(False)
+    info = ctx.info(gid)
+    ctx.free(gid)
+    m = w.meta
+    p = w.pos / kpc
+    cy = m["clump_c_kpc"][1]
+    rperp = np.hypot(p[:, 1] - cy, p[:, 2] - m["clump_c_kpc"][2])
+    inclump = np.sum((p - np.array(m["clump_c_kpc"])) ** 2, axis=1) < m["clump_r_kpc"] ** 2
+    x = st["x"]
+    lit = m["clump_c_kpc"][0] - m["clump_r_kpc"]
+    ax = inclump & (rperp < 0.25) & (x > 0.5)
+    depth = float(p[ax, 0].max() - lit) if ax.any() else None
+    back = m["clump_c_kpc"][0] + m["clump_r_kpc"] + 0.2
+    behind = (p[:, 0] > back) & (rperp < 0.4)
+    off = (p[:, 0] > back) & (rperp > 1.5)
+    n_c = m["n_H"] * m["contrast"]
+    l_s = m["flux"] / (G.ALPHA_B * n_c * n_c) / kpc
+    tl = st["tallies"]
+    kern = pr["total_ms"] / max(pr["launches"], 1)
+    upd = w.n * w.k * w.n_sweeps
+    res = dict(
+        value=upd / el, unit="vertex·direction updates/s", vertices=w.n, bins=w.k,
+        sweeps=w.n_sweeps, ms_per_solve=1e3 * el, upload_s=up, sweep_kernel_us=1e3 * kern,
+        algorithmic_hbm_frac=round(algorithmic_bytes_per_update(w.k, 4) * w.n * w.k
+                                   / (kern * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        device_bytes=info["bytes"],
+        clump_axis_depth_kpc=depth, stromgren_length_1d_kpc=l_s,
+        x_behind_clump=float(x[behind].mean()), x_off_shadow=float(x[off].mean()),
+        conservation_residual=abs(tl["emitted"] - tl["absorbed"] - tl["escaped"]
+                                  - tl["in_flight"]) / tl["emitted"])
+    log(f"shadow: {res['value']:.3e} updates/s, sweep {1e3 * kern:.1f} us, depth "
+        f"{depth} kpc (1-D {l_s:.3f}), behind {res['x_behind_clump']:.3f} off "
+        f"{res['x_off_shadow']:.3f}")
+    return res
 
 
 def serve_leg(ctx, pool, args, log):
@@ -180,6 +237,9 @@ def main():
     ap.add_argument("--serve-prep-threads", type=int, default=12)
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving leg")
+    ap.add_argument("--shadow-n", type=int, default=1048576,
+                    help="vertices of the shadowing leg (0 = skip it)")
+    ap.add_argument("--shadow-sweeps", type=int, default=1500)
     ap.add_argument("--graph-sweeps", type=int, default=50,
                     help="sweeps per replayed HIP graph (0: one launch per sweep)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -199,12 +259,14 @@ def main():
     # workers, which must not inherit an initialised GPU runtime
     if args.serve_only:
         args.batch_grids = 0
+        args.shadow_n = 0
     if args.serve_full:
         args.serve_max_n = 2000000
     pool_sizes = (G.serve_pool_sizes(1e4, args.serve_max_n, 8)
                   if args.serve_seconds > 0 else [])
     t = time.perf_counter()
-    batch, pool, nw = build_grids(max(args.batch_grids, 0), pool_sizes)
+    batch, pool, shadow, nw = build_grids(max(args.batch_grids, 0), pool_sizes,
+                                          max(args.shadow_n, 0), args.shadow_sweeps)
     if batch or pool:
         log(f"built {len(batch)} batch grids ({sum(b.n for b in batch)} vertices) and "
             f"{len(pool)} pool grids (up to {max([0] + [w.n for w in pool])} vertices) in "
@@ -342,6 +404,18 @@ def main():
         log(f"batched: {batched['value']:.3e} updates/s, {1e3 * el_b:.1f} ms/solve, "
             f"sweep launch {1e3 * kb:.1f} us, schedule {sched}")
 
+    shadowed = None
+    if shadow is not None:
+        def prof(on):
+            if on:
+                ctx.profile(True)
+                ctx.profile_read()
+                return None
+            r = ctx.profile_read()
+            ctx.profile(False)
+            return r
+        shadowed = shadow_leg(ctx, shadow, log, prof)
+
     if pool:
         served = serve_leg(ctx, pool, args, log)
         log(f"served: {served['finished']}/{served['requests']} requests, "
@@ -401,6 +475,7 @@ def main():
         "fp64_plain": fp64,
         "batched": batched,
         "served": served,
+        "shadow": shadowed,
         "upload_s": up_s,
         "sweep_kernel_us": 1e3 * kern_ms,
         "roofline": roof,
