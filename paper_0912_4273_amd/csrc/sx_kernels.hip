@@ -262,27 +262,33 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt,
 // (Eqs. rate_eq, rate_eq_subcycle, phot_ion_rate_subcycle; on the spot,
 // n_e = n_HII):  y' = y - ha (1 - exp(-y' tau)) + hb (1 - y')^2, solved by
 // safeguarded Newton inside the bracket [0, 1].
+// Also returns 1 - exp(-y tau) at the root (from the last Newton
+// evaluation when the final step is within rounding of y).
 __device__ __forceinline__ double be_substep(double y0, double ha, double hb,
-                                             double tau) {
+                                             double tau, double &ion_root) {
   double lo = 0.0, hi = 1.0, yn = y0;
   for (int it = 0; it < 200; ++it) {
     const double ion = -expm1(-yn * tau);
     const double x = 1.0 - yn;
     const double g = (y0 - yn) - ha * ion + hb * (x * x);
-    if (g == 0.0) break;
+    if (g == 0.0) {
+      ion_root = ion;
+      return yn;
+    }
     if (g > 0.0) lo = yn; else hi = yn;
     const double gp = -1.0 - ha * tau * (1.0 - ion) - 2.0 * hb * x;
     const double d = g / gp;
     if (fabs(d) <= 4.0e-16 * yn) {   // Newton step within rounding of y
       const double yc = yn - d;
-      yn = yc < 0.0 ? 0.0 : (yc > 1.0 ? 1.0 : yc);
-      break;
+      ion_root = ion;
+      return yc < 0.0 ? 0.0 : (yc > 1.0 ? 1.0 : yc);
     }
     double yc = yn - d;
     if (!(yc > lo && yc < hi)) yc = 0.5 * (lo + hi);
     yn = yc;
     if (hi - lo <= 4.0e-16 * hi) break;
   }
+  ion_root = -expm1(-yn * tau);
   return yn;
 }
 
@@ -297,9 +303,10 @@ __device__ __forceinline__ double chem_step(double y, double nin, double dt,
   const double share = nin / (double)n_sub;
   double abs_sum = 0.0, tr_sum = 0.0;
   for (int s = 0; s < n_sub; ++s) {
-    y = be_substep(y, ha, hb, tau);
-    abs_sum += share * (-expm1(-y * tau));
-    tr_sum += exp(-y * tau);
+    double ion;
+    y = be_substep(y, ha, hb, tau, ion);
+    abs_sum += share * ion;
+    tr_sum += 1.0 - ion;   // exp(-y tau)
   }
   A = abs_sum;
   T = nin > 0.0 ? tr_sum / (double)n_sub : 1.0;
