@@ -55,6 +55,8 @@ def _load(path=None):
         lib.ora_set_state.argtypes = [P, P, P, P]
         lib.ora_get_tables.restype = None
         lib.ora_get_tables.argtypes = [P, P, P, P, P, P]
+        lib.ora_rotate.restype = C.c_int
+        lib.ora_rotate.argtypes = [P, P]
         lib.ora_free.restype = None
         lib.ora_free.argtypes = [P]
         lib.ora_chem_cell.restype = C.c_double
@@ -141,6 +143,11 @@ class Oracle:
                           tallies["absorbed"], tallies["escaped"],
                           tallies["in_flight"]], np.float64)
         self._lib.ora_set_state(self._h, _p(y), _p(ph), _p(t))
+
+    def rotate(self, R):
+        """Rotate the direction bins to R u_k (Sect. 2.2.3)."""
+        r = np.ascontiguousarray(np.asarray(R, np.float64).reshape(9))
+        self._lib.ora_rotate(self._h, _p(r))
 
     def tables(self):
         n, k, m = self.n, self.k, self.mpb

@@ -31,7 +31,8 @@ struct ora_grid {
     int32_t *nbr;        /* [E]   */
     double *edir;        /* [E*3] unit edge vectors (Sect. 2.2) */
     double *elen;        /* [E]   edge lengths */
-    double *bins;        /* [K*3] */
+    double *bins;        /* [K*3] current bin directions */
+    double *bins0;       /* [K*3] bin directions given at creation */
     double *nH, *vol, *dL, *tau; /* [N] */
     int32_t *sel;        /* [N*K*mpb] selected neighbour ids, best first */
     int32_t *m;          /* [N*K] number selected */
@@ -167,6 +168,40 @@ double ora_chem_cell(double y, double n_in, double dt, double nHV, double tau,
 }
 
 /* ---------------------------------------------------------------------- */
+/* The routing of direction-conserving transport for the current bins:
+ * which neighbours each bin of each vertex goes to, and the bin of every
+ * directed edge. */
+static void build_routing(ora_grid *g) {
+    int64_t n = g->n, K = g->K, E = g->n_edges;
+    int max_per_bin = g->mpb;
+    /* Direction-bin -> neighbour selection of direction-conserving transport
+     * (Sect. 2.2.3): every bin goes to the mpb (= dimension d = 3) most
+     * straightforward neighbours w.r.t. the bin's own direction. */
+    for (int64_t i = 0; i < n; i++) {
+        for (int64_t k = 0; k < K; k++) {
+            int32_t slots[16];
+            int c = select_slots(g, i, &g->bins[3 * k], slots);
+            int32_t *dst = &g->sel[(i * K + k) * max_per_bin];
+            for (int r = 0; r < max_per_bin; r++)
+                dst[r] = r < c ? g->nbr[g->ptr[i] + slots[r]] : -1;
+            g->m[i * K + k] = c;
+        }
+    }
+
+    /* Bin of each directed edge: photons sent along an edge are filed in
+     * the solid angle whose direction is closest to the edge (Sect. 2.2.4);
+     * ties go to the lower bin. */
+    for (int64_t e = 0; e < E; e++) {
+        int32_t best = 0;
+        double cb = cosine(&g->edir[3 * e], &g->bins[0]);
+        for (int32_t k = 1; k < K; k++) {
+            double c = cosine(&g->edir[3 * e], &g->bins[3 * k]);
+            if (c > cb) { cb = c; best = k; }
+        }
+        g->ebin[e] = best;
+    }
+}
+
 ora_grid *ora_create(int64_t n, const double *pos, const int64_t *nbr_ptr,
                      const int32_t *nbr_idx, const double *n_H,
                      const double *volume, const double *dL, double kappa,
@@ -199,6 +234,8 @@ ora_grid *ora_create(int64_t n, const double *pos, const int64_t *nbr_ptr,
     memcpy(g->nbr, nbr_idx, E * sizeof(int32_t));
     g->bins = (double *)xcalloc(K * 3, sizeof(double));
     memcpy(g->bins, bin_dirs, K * 3 * sizeof(double));
+    g->bins0 = (double *)xcalloc(K * 3, sizeof(double));
+    memcpy(g->bins0, bin_dirs, K * 3 * sizeof(double));
     g->nH = (double *)xcalloc(n, sizeof(double));
     g->vol = (double *)xcalloc(n, sizeof(double));
     memcpy(g->nH, n_H, n * sizeof(double));
@@ -254,32 +291,7 @@ ora_grid *ora_create(int64_t n, const double *pos, const int64_t *nbr_ptr,
         g->y[i] = x_init ? 1.0 - x_init[i] : 1.0;
     }
 
-    /* Direction-bin -> neighbour selection of direction-conserving transport
-     * (Sect. 2.2.3): every bin goes to the mpb (= dimension d = 3) most
-     * straightforward neighbours w.r.t. the bin's own direction. */
-    for (int64_t i = 0; i < n; i++) {
-        for (int64_t k = 0; k < K; k++) {
-            int32_t slots[16];
-            int c = select_slots(g, i, &g->bins[3 * k], slots);
-            int32_t *dst = &g->sel[(i * K + k) * max_per_bin];
-            for (int r = 0; r < max_per_bin; r++)
-                dst[r] = r < c ? g->nbr[g->ptr[i] + slots[r]] : -1;
-            g->m[i * K + k] = c;
-        }
-    }
-
-    /* Bin of each directed edge: photons sent along an edge are filed in
-     * the solid angle whose direction is closest to the edge (Sect. 2.2.4);
-     * ties go to the lower bin. */
-    for (int64_t e = 0; e < E; e++) {
-        int32_t best = 0;
-        double cb = cosine(&g->edir[3 * e], &g->bins[0]);
-        for (int32_t k = 1; k < K; k++) {
-            double c = cosine(&g->edir[3 * e], &g->bins[3 * k]);
-            if (c > cb) { cb = c; best = k; }
-        }
-        g->ebin[e] = best;
-    }
+    build_routing(g);
     return g;
 }
 
@@ -406,6 +418,42 @@ void ora_set_state(ora_grid *g, const double *y, const double *photons,
     }
 }
 
+/* Random rotation of the direction bins between transport steps, against
+ * preferential directions (Sect. 2.2.3): the bins become R u_k of the bins
+ * given at creation (R row-major, applied as ((R_r0 u_x + R_r1 u_y) +
+ * R_r2 u_z) with no fused multiply-add) and the routing is recomputed.
+ * Reading of what happens to photons in flight (the paper does not say):
+ * the photons a vertex holds in a bin, O m, keep their bin and are split over
+ * the neighbours selected for the bin's new direction; where none is
+ * selected they leave the domain. */
+int ora_rotate(ora_grid *g, const double *R) {
+    int64_t n = g->n, K = g->K;
+    int32_t *m_old = (int32_t *)xcalloc(n * K, sizeof(int32_t));
+    memcpy(m_old, g->m, (size_t)(n * K) * sizeof(int32_t));
+    for (int64_t k = 0; k < K; k++) {
+        const double *u = &g->bins0[3 * k];
+        for (int r = 0; r < 3; r++) {
+            double a = R[3 * r + 0] * u[0];
+            double b = R[3 * r + 1] * u[1];
+            double c = R[3 * r + 2] * u[2];
+            g->bins[3 * k + r] = (a + b) + c;
+        }
+    }
+    build_routing(g);
+    for (int64_t i = 0; i < n * K; i++) {
+        double held = g->O[i] * (double)m_old[i];
+        if (g->m[i] == 0) {
+            g->escaped += held;
+            g->in_flight -= held;
+            g->O[i] = 0.0;
+        } else {
+            g->O[i] = held / (double)g->m[i];
+        }
+    }
+    free(m_old);
+    return 0;
+}
+
 void ora_get_tables(const ora_grid *g, int32_t *sel_nbr, int32_t *sel_m,
                     int32_t *edge_bin, double *dL, double *tau) {
     int64_t n = g->n, K = g->K;
@@ -418,7 +466,7 @@ void ora_get_tables(const ora_grid *g, int32_t *sel_nbr, int32_t *sel_m,
 
 void ora_free(ora_grid *g) {
     if (!g) return;
-    free(g->ptr); free(g->nbr); free(g->edir); free(g->elen); free(g->bins);
+    free(g->ptr); free(g->nbr); free(g->edir); free(g->elen); free(g->bins); free(g->bins0);
     free(g->nH); free(g->vol); free(g->dL); free(g->tau); free(g->sel);
     free(g->m); free(g->ebin); free(g->src_v); free(g->src_rate);
     free(g->src_dir); free(g->y); free(g->O); free(g->I); free(g->nin);

@@ -413,3 +413,32 @@ def serve_request(pool: list, r: int, n_min: float = 1e4, n_max: float = 2e6,
                  src_vertex=src, src_rate=rates, dt=t_end_myr * MYR_S / sweeps,
                  n_sweeps=sweeps, precision=SX_FP32_TRANSPORT,
                  meta=dict(request=r, pool=g.meta["pool"], n_want=n_want, clump=clump))
+
+
+# --------------------------------------------------------------- rotations
+# Random orientations of the direction bins (the method rotates them between
+# steps against preferential directions).  They are inputs: the caller draws
+# them and hands the same matrices to every implementation.
+
+def random_rotations(n: int, seed: int) -> np.ndarray:
+    """n rotation matrices [n, 3, 3], uniform on SO(3): normalised Gaussian
+    quaternions (seed)."""
+    q = np.random.default_rng(seed).normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1)[:, None]
+    w, x, y, z = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
+    R = np.empty((n, 3, 3))
+    R[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    R[:, 0, 1] = 2 * (x * y - z * w)
+    R[:, 0, 2] = 2 * (x * z + y * w)
+    R[:, 1, 0] = 2 * (x * y + z * w)
+    R[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    R[:, 1, 2] = 2 * (y * z - x * w)
+    R[:, 2, 0] = 2 * (x * z - y * w)
+    R[:, 2, 1] = 2 * (y * z + x * w)
+    R[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+def quarter_turn_z() -> np.ndarray:
+    """Rotation by 90 degrees about z (exact entries)."""
+    return np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
