@@ -225,6 +225,19 @@ int sx_profile(sx_ctx *ctx, int32_t enable);
 int sx_profile_read(sx_ctx *ctx, int64_t *launches, double *total_ms,
                     double *min_ms, double *max_ms);
 
+/* Rotate the direction bins of a grid to R u_k, u_k the bins given at
+ * upload (R: row-major 3x3, orthonormal within 1e-9, determinant +1).  The
+ * method rotates its bins over random angles between transport steps
+ * against preferential directions (Sect. 2.2.3); the caller draws the
+ * rotations.  The routing (selection, edge bins, bins of the source shares,
+ * gather lists) is rebuilt on the device.  Photons in flight keep their bin:
+ * what a vertex holds in a bin is split over the neighbours selected for
+ * the bin's new direction (unchanged where their number is the same), and
+ * escapes where none is selected (tallied as escaped).  sx_grid_reset
+ * restores the given bins.  Synchronous.  Errors: SX_EINVAL (not a
+ * rotation), SX_ENOTFOUND, SX_ENOMEM, SX_EDEVICE. */
+int sx_rotate_bins(sx_ctx *ctx, sx_grid_id id, const double *R);
+
 /* ---- upload in two parts ---------------------------------------------
  * sx_grid_upload = sx_grid_prepare + sx_grid_commit.  The host part (all
  * validation, the Hilbert reorder, neighbour rows, edge geometry, tile

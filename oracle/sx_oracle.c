@@ -424,8 +424,9 @@ void ora_set_state(ora_grid *g, const double *y, const double *photons,
  * R_r2 u_z) with no fused multiply-add) and the routing is recomputed.
  * Reading of what happens to photons in flight (the paper does not say):
  * the photons a vertex holds in a bin, O m, keep their bin and are split over
- * the neighbours selected for the bin's new direction; where none is
- * selected they leave the domain. */
+ * the neighbours selected for the bin's new direction (unchanged where the
+ * number selected is the same); where none is selected they leave the
+ * domain. */
 int ora_rotate(ora_grid *g, const double *R) {
     int64_t n = g->n, K = g->K;
     int32_t *m_old = (int32_t *)xcalloc(n * K, sizeof(int32_t));
@@ -441,6 +442,7 @@ int ora_rotate(ora_grid *g, const double *R) {
     }
     build_routing(g);
     for (int64_t i = 0; i < n * K; i++) {
+        if (g->m[i] == m_old[i]) continue;   /* same share per neighbour */
         double held = g->O[i] * (double)m_old[i];
         if (g->m[i] == 0) {
             g->escaped += held;

@@ -54,6 +54,8 @@ struct Grid {
   double esc_emit = 0.0;    // photons per step with no way out of a beam source
   double base_sweeps = 0.0, base_emitted = 0.0, base_escaped = 0.0;
   int64_t n_direct = 0;     // tiles whose halo is too large for LDS staging
+  std::vector<double> bins0;   // [3K] bin directions given at upload
+  bool rotated = false;
   std::vector<uint8_t> tile_direct;
 };
 
@@ -385,18 +387,57 @@ int write_slot(sx_ctx *ctx, Grid *g) {
   return SX_OK;
 }
 
-// (Re)build the selection products of a grid on the device; the record
-// pool must already be sized (rec_cap).
-int build_tables(sx_ctx *ctx, Grid *g) {
+// Release one of a grid's device buffers.
+void gfree(sx_ctx *ctx, Grid *g, void *p) {
+  for (size_t i = 0; i < g->bufs.size(); ++i)
+    if (g->bufs[i].p == p) {
+      dev_free(ctx, p);
+      ctx->used -= g->bufs[i].bytes;
+      g->bytes -= g->bufs[i].bytes;
+      g->bufs.erase(g->bufs.begin() + (long)i);
+      return;
+    }
+}
+
+// Rebuild a grid's routing on the device for bin directions `bins` [3K]:
+// selection, (with rescale) the photons in flight re-split over the new
+// selection, edge bins, source-share bins, m, gather lists; the overflow
+// record pool grows when the new routing needs more.  Synchronous.
+int rebuild_routing(sx_ctx *ctx, Grid *g, const double *bins, bool rescale) {
+  GridDev &h = g->hg;
   GridDev *dg = ctx->table + g->slot;
-  const int32_t nrow = g->hg.ntiles * g->hg.k;
-  HIP_TRY(ctx, sx::launch_select(dg, g->hg, ctx->stream));
-  HIP_TRY(ctx, sx::launch_edge_bins(dg, g->hg, ctx->stream));
-  HIP_TRY(ctx, sx::launch_mbits(dg, g->hg, ctx->stream));
-  HIP_TRY(ctx, sx::launch_clear_inw(g->hg, ctx->stream));
-  HIP_TRY(ctx, sx::launch_inlist_count(dg, g->hg, ctx->stream));
-  HIP_TRY(ctx, sx::launch_scan(g->hg.rec_cnt, g->hg.rec_ptr, nrow, ctx->stream));
-  HIP_TRY(ctx, sx::launch_inlist_fill(dg, g->hg, ctx->stream));
+  hipStream_t st = ctx->stream;
+  const int32_t nrow = h.ntiles * h.k;
+  HIP_TRY(ctx, hipMemcpyAsync(const_cast<double *>(h.bins), bins, sizeof(double) * 3 * h.k,
+                              hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, sx::launch_select(dg, h, st));
+  if (rescale) HIP_TRY(ctx, sx::launch_rot_rescale(dg, h, st));
+  HIP_TRY(ctx, sx::launch_edge_bins(dg, h, st));
+  HIP_TRY(ctx, sx::launch_em_bins(dg, h, g->n_em, st));
+  HIP_TRY(ctx, sx::launch_mbits(dg, h, st));
+  HIP_TRY(ctx, sx::launch_clear_inw(h, st));
+  HIP_TRY(ctx, sx::launch_inlist_count(dg, h, st));
+  HIP_TRY(ctx, sx::launch_scan(h.rec_cnt, h.rec_ptr, nrow, st));
+  int32_t n_rec = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(&n_rec, h.rec_ptr + nrow, 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  if (n_rec > h.rec_cap) {
+    gfree(ctx, g, h.rec);
+    uint32_t *d_rec = nullptr;
+    int r = galloc(ctx, g, &d_rec, (uint64_t)n_rec + 1);
+    if (r) {
+      h.rec = nullptr;
+      h.rec_cap = 0;
+      (void)write_slot(ctx, g);
+      return fail(ctx, SX_EDEVICE, "overflow record pool could not grow to %d entries", n_rec);
+    }
+    h.rec = d_rec;
+    h.rec_cap = n_rec;
+    int w = write_slot(ctx, g);
+    if (w) return w;
+  }
+  HIP_TRY(ctx, sx::launch_inlist_fill(dg, h, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
   return SX_OK;
 }
 
@@ -415,7 +456,7 @@ struct sx_prepared {
   std::vector<int32_t> halo_ptr, halo_vid;
   std::vector<uint16_t> edge_hidx;
   std::vector<double> tau, dtnhv, bco, y0;
-  std::vector<int32_t> em_ptr, em_k;
+  std::vector<int32_t> em_ptr, em_k, em_edge;
   std::vector<double> em_amt;
   ~sx_prepared() { delete g; }
 };
@@ -605,6 +646,7 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
     int32_t recv;
     int32_t k;
     double amt;
+    int32_t edge;   // the source's edge it travels along (new edge id)
   };
   std::vector<Em> em;
   double esc_emit = 0.0;
@@ -620,7 +662,7 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
       const double share = (Es / unit) / (double)deg;
       for (int64_t p = d->nbr_ptr[vi]; p < d->nbr_ptr[vi + 1]; ++p) {
         const int32_t e = g->orig_to_new_e[(size_t)p];
-        em.push_back({g->nbr_h[(size_t)e], edge_bin(e), share});
+        em.push_back({g->nbr_h[(size_t)e], edge_bin(e), share, e});
       }
     } else {
       // beam: the <= mpb neighbours most aligned with u, cosine > cos_min,
@@ -645,24 +687,25 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
       if (cnt == 0) { esc_emit += Es; continue; }
       const double share = (Es / unit) / (double)cnt;
       for (int q = 0; q < cnt; ++q)
-        em.push_back({g->nbr_h[(size_t)sl[q]], edge_bin(sl[q]), share});
+        em.push_back({g->nbr_h[(size_t)sl[q]], edge_bin(sl[q]), share, sl[q]});
     }
   }
   g->esc_emit = esc_emit;
   if ((int64_t)em.size() >= ((int64_t)1 << sx::kRecIdxBits))
     return fail(ctx, SX_ENOTSUP, "too many source-neighbour pairs (%zu)", em.size());
-  // per receiver, by bin; equal bins keep source order
-  std::stable_sort(em.begin(), em.end(), [](const Em &a, const Em &b) {
-    return a.recv != b.recv ? a.recv < b.recv : a.k < b.k;
-  });
-  std::vector<int32_t> &em_ptr = P->em_ptr, &em_k = P->em_k;
+  // per receiver, in source order (a bin's shares then add in source order
+  // whatever the bins' orientation)
+  std::stable_sort(em.begin(), em.end(), [](const Em &a, const Em &b) { return a.recv < b.recv; });
+  std::vector<int32_t> &em_ptr = P->em_ptr, &em_k = P->em_k, &em_edge = P->em_edge;
   std::vector<double> &em_amt = P->em_amt;
   em_ptr.assign((size_t)npad + 1, 0);
   em_k.assign(em.size(), 0);
+  em_edge.assign(em.size(), 0);
   em_amt.assign(em.size(), 0.0);
   for (size_t q = 0; q < em.size(); ++q) {
     em_ptr[(size_t)em[q].recv + 1]++;
     em_k[q] = em[q].k;
+    em_edge[q] = em[q].edge;
     em_amt[q] = em[q].amt;
   }
   for (int64_t v = 0; v < npad; ++v) em_ptr[(size_t)v + 1] += em_ptr[(size_t)v];
@@ -837,20 +880,24 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   if ((he = sx::launch_edge_bins(dg, h, st)) != hipSuccess) return kfail(he);
   g->n_em = (int64_t)P->em_k.size();
   {
-    int32_t *d_emp, *d_emk;
+    int32_t *d_emp, *d_emk, *d_eme;
     double *d_ema;
     GA(d_emp, npad + 1);
     GA(d_emk, g->n_em + 1);
+    GA(d_eme, g->n_em + 1);
     GA(d_ema, g->n_em + 1);
     UP(d_emp, P->em_ptr.data(), 4 * (npad + 1));
     if (g->n_em) {
       UP(d_emk, P->em_k.data(), 4 * g->n_em);
+      UP(d_eme, P->em_edge.data(), 4 * g->n_em);
       UP(d_ema, P->em_amt.data(), 8 * g->n_em);
     }
     h.em_ptr = d_emp;
     h.em_k = d_emk;
+    h.em_edge = d_eme;
     h.em_amt = d_ema;
   }
+  g->bins0 = P->bins;
   if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
   if ((he = sx::launch_mbits(dg, h, st)) != hipSuccess) return kfail(he);
   if ((he = sx::launch_clear_inw(h, st)) != hipSuccess) return kfail(he);
@@ -1042,10 +1089,45 @@ int sx_grid_reset(sx_ctx *ctx, sx_grid_id id) {
   Grid *g = find(ctx, id);
   if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  int r = build_tables(ctx, g);
+  int r = rebuild_routing(ctx, g, g->bins0.data(), false);
   if (r) return r;
+  g->rotated = false;
   HIP_TRY(ctx, sx::launch_reset_state(ctx->table + g->slot, g->hg, g->y_init, ctx->stream));
   g->base_sweeps = g->base_emitted = g->base_escaped = 0.0;
+  return SX_OK;
+}
+
+int sx_rotate_bins(sx_ctx *ctx, sx_grid_id id, const double *R) {
+  if (!ctx) return SX_EINVAL;
+  if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
+  Grid *g = find(ctx, id);
+  if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
+  if (!R) return fail(ctx, SX_EINVAL, "null rotation");
+  // a rotation: orthonormal rows, determinant +1
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(R[i])) return fail(ctx, SX_EINVAL, "rotation has a non-finite entry");
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      const double d = R[3 * a] * R[3 * b] + R[3 * a + 1] * R[3 * b + 1] + R[3 * a + 2] * R[3 * b + 2];
+      if (std::fabs(d - (a == b ? 1.0 : 0.0)) > 1e-9)
+        return fail(ctx, SX_EINVAL, "rotation rows are not orthonormal");
+    }
+  const double det = R[0] * (R[4] * R[8] - R[5] * R[7]) - R[1] * (R[3] * R[8] - R[5] * R[6]) +
+                     R[2] * (R[3] * R[7] - R[4] * R[6]);
+  if (!(det > 0.0)) return fail(ctx, SX_EINVAL, "rotation has determinant %g", det);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const int64_t K = g->hg.k;
+  std::vector<double> b((size_t)(3 * K));
+  for (int64_t k = 0; k < K; ++k) {
+    const double *u = &g->bins0[(size_t)(3 * k)];
+    for (int r = 0; r < 3; ++r) {
+      const double p0 = R[3 * r] * u[0], p1 = R[3 * r + 1] * u[1], p2 = R[3 * r + 2] * u[2];
+      b[(size_t)(3 * k + r)] = (p0 + p1) + p2;
+    }
+  }
+  int r = rebuild_routing(ctx, g, b.data(), true);
+  if (r) return r;
+  g->rotated = true;
   return SX_OK;
 }
 

@@ -86,7 +86,8 @@ struct GridDev {
   const uint8_t *tile_direct; // [ntiles]
   // sources (per receiving vertex, by bin, then source order)
   const int32_t *em_ptr;    // [npad+1]
-  const int32_t *em_k;      // [n_em]
+  int32_t *em_k;            // [n_em] bin of each share (from its edge)
+  const int32_t *em_edge;   // [n_em] the source's edge the share travels along
   const double *em_amt;     // [n_em] photons / unit
   // chemistry coefficients
   const double *tau;        // [npad] n_H sigma dL
@@ -108,6 +109,12 @@ hipError_t launch_edge_bins(const GridDev *dg, const GridDev &hg, hipStream_t s)
 hipError_t launch_inlist_count(const GridDev *dg, const GridDev &hg, hipStream_t s);
 hipError_t launch_scan(int32_t *cnt, int32_t *ptr, int32_t n, hipStream_t s);
 hipError_t launch_inlist_fill(const GridDev *dg, const GridDev &hg, hipStream_t s);
+// After a rotation of the bins: the photons each (vertex, bin) holds are
+// re-split over the new selection (from fwd; the old one is still in
+// mbits); those with no forward neighbour left move to the escape tally.
+hipError_t launch_rot_rescale(GridDev *dg, const GridDev &hg, hipStream_t s);
+// Bin of each source share from its edge's bin.
+hipError_t launch_em_bins(GridDev *dg, const GridDev &hg, int64_t n_em, hipStream_t s);
 hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s);
 hipError_t launch_clear_inw(const GridDev &hg, hipStream_t s);
 hipError_t launch_reset_state(GridDev *dg, const GridDev &hg, const double *y0,

@@ -212,6 +212,57 @@ __global__ void k_inlist_fill(const GridDev *__restrict__ gp) {
   }
 }
 
+// Re-split after a rotation of the bins, one wave per tile, lane = vertex.
+// Each (vertex, bin) holds m_old * Ipre * T photons (T of the step that
+// wrote them); they now go to m_new neighbours, Ipre' = Ipre m_old / m_new
+// (unchanged if m_new = m_old), or escape if m_new = 0.  The escaping
+// photons move from the tile's in-flight tally to its escape tally.
+template <typename P>
+__device__ __forceinline__ void rot_rescale(GridDev &g, int tile, int lane) {
+  constexpr int BB = kBlockBytes / sizeof(P);
+  const int K = g.k;
+  const int j = tile * kTile + lane;
+  const int par = g.parity;
+  P *o = (P *)g.o[par];
+  const double T = (double)((const P *)g.t[par])[j];
+  const uint32_t *mb = g.mbits + (int64_t)tile * g.kw * 64 + lane;
+  double esc = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const uint32_t mo = (mb[(k >> 4) * 64] >> (2 * (k & 15))) & 3u;
+    const uint32_t mn = (g.fwd[(int64_t)j * K + k] >> 21) & 3u;
+    if (mn == mo) continue;
+    const int kb = k / BB, b = k - kb * BB;
+    P &v = o[(((int64_t)tile * g.kb + kb) * 64 + lane) * BB + b];
+    if (mn == 0u) {
+      esc += (double)v * (double)mo * T;
+      v = P(0);
+    } else {
+      v = (P)((double)v * (double)mo / (double)mn);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) esc += __shfl_xor(esc, off);
+  if (lane == 0) {
+    g.tally[(int64_t)tile * 3 + 1] += esc;
+    g.tally[(int64_t)tile * 3 + 2] -= esc;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_rot_rescale(GridDev *__restrict__ gp) {
+  GridDev &g = *gp;
+  if (g.precision == 0)
+    rot_rescale<double>(g, blockIdx.x, threadIdx.x);
+  else
+    rot_rescale<float>(g, blockIdx.x, threadIdx.x);
+}
+
+__global__ void k_em_bins(GridDev *__restrict__ gp, int64_t n_em) {
+  GridDev &g = *gp;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_em) return;
+  g.em_k[q] = g.ebin[g.em_edge[q]];
+}
+
 // Packed m(j, k), 2 bits per bin, 16 bins per word.  One lane per vertex.
 __global__ void k_mbits(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
@@ -691,6 +742,18 @@ hipError_t launch_clear_inw(const GridDev &hg, hipStream_t s) {
 
 hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s) {
   hipLaunchKernelGGL(k_mbits, dim3(blocks_for(hg.npad, 256)), dim3(256), 0, s, dg);
+  return hipGetLastError();
+}
+
+hipError_t launch_rot_rescale(GridDev *dg, const GridDev &hg, hipStream_t s) {
+  hipLaunchKernelGGL(k_rot_rescale, dim3((unsigned)hg.ntiles), dim3(64), 0, s, dg);
+  return hipGetLastError();
+}
+
+hipError_t launch_em_bins(GridDev *dg, const GridDev &hg, int64_t n_em, hipStream_t s) {
+  (void)hg;
+  if (n_em <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_em_bins, dim3(blocks_for(n_em, 256)), dim3(256), 0, s, dg, n_em);
   return hipGetLastError();
 }
 

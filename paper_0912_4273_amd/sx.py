@@ -35,7 +35,7 @@ EXPORTED = [
     "sx_solve", "sx_sync", "sx_read_state", "sx_read_tables",
     "sx_grid_info", "sx_mem_info", "sx_stream", "sx_profile",
     "sx_profile_read", "sx_set_schedule", "sx_get_schedule", "sx_autotune",
-    "sx_grid_prepare", "sx_prepared_bytes", "sx_grid_commit", "sx_prepared_free",
+    "sx_rotate_bins", "sx_grid_prepare", "sx_prepared_bytes", "sx_grid_commit", "sx_prepared_free",
     "sx_serve_start", "sx_serve_submit", "sx_serve_poll", "sx_serve_take",
     "sx_serve_stop", "sx_strerror", "sx_last_error",
 ]
@@ -151,6 +151,7 @@ def load(path: Optional[str] = None):
         "sx_set_schedule": (C.c_int, [P, P, I32, C.POINTER(SxSchedule)]),
         "sx_get_schedule": (C.c_int, [P, P, I32, C.POINTER(SxSchedule), P]),
         "sx_autotune": (C.c_int, [P, I32]),
+        "sx_rotate_bins": (C.c_int, [P, I64, P]),
         "sx_grid_prepare": (C.c_int, [C.POINTER(SxGridDesc), C.POINTER(P), C.c_char_p,
                                       C.c_size_t]),
         "sx_prepared_bytes": (C.c_int, [P, C.POINTER(C.c_uint64)]),
@@ -287,6 +288,11 @@ def sx_grid_commit(ctx, p) -> int:
 
 def sx_prepared_free(p) -> None:
     load().sx_prepared_free(p)
+
+
+def sx_rotate_bins(ctx, gid: int, R) -> None:
+    r = np.ascontiguousarray(np.asarray(R, np.float64).reshape(9))
+    _check(ctx, load().sx_rotate_bins(ctx, gid, _ptr(r)))
 
 
 def sx_grid_reset(ctx, gid: int) -> None:
@@ -485,6 +491,9 @@ class Context:
 
     def reset(self, gid):
         sx_grid_reset(self.h, gid)
+
+    def rotate(self, gid, R):
+        sx_rotate_bins(self.h, gid, R)
 
     def step(self, ids, n_sweeps):
         sx_step(self.h, ids, n_sweeps)
