@@ -196,6 +196,46 @@ def serve_leg(ctx, pool, args, log):
         wall_s=wall, round_sweeps=args.serve_round, prep_threads=args.serve_prep_threads)
 
 
+def rotation_leg(ctx, w, every: int, log):
+    """The same Stromgren solve with the direction bins rotated at random
+    every `every` sweeps (seeded rotations): throughput including the
+    rebuilds of the routing, their cost, and the ionised-volume radius
+    against the analytic front law."""
+    import numpy as np
+    from paper_0912_4273_amd import gridgen as G
+    gid = ctx.upload(w)
+    n_rot = (w.n_sweeps + every - 1) // every
+    Rs = G.random_rotations(n_rot, seed=2024)
+    t_rot = 0.0
+    t0 = time.perf_counter()
+    done = 0
+    for i in range(n_rot):
+        n = min(every, w.n_sweeps - done)
+        ctx.step([gid], n)
+        done += n
+        t1 = time.perf_counter()
+        ctx.rotate(gid, Rs[i])
+        t_rot += time.perf_counter() - t1
+    st = ctx.state(gid, nin=False)
+    el = time.perf_counter() - t0
+    ctx.free(gid)
+    r_s = (3 * w.meta["rate"] / (4 * math.pi * w.alpha_B * w.meta["n_H"] ** 2)) ** (1 / 3)
+    t_rec = 1.0 / (w.alpha_B * w.meta["n_H"])
+    rv = (3 / (4 * math.pi) * float(np.sum(w.volume * st["x"]))) ** (1 / 3)
+    tl = st["tallies"]
+    res = dict(value=w.n * w.k * w.n_sweeps / el, unit="vertex·direction updates/s",
+               rotate_every=every, rotations=n_rot, ms_per_solve=1e3 * el,
+               ms_per_rotation=1e3 * t_rot / n_rot,
+               front_radius_over_analytic=round(
+                   rv / (r_s * (1 - math.exp(-w.n_sweeps * w.dt / t_rec)) ** (1 / 3)), 4),
+               conservation_residual=abs(tl["emitted"] - tl["absorbed"] - tl["escaped"]
+                                         - tl["in_flight"]) / tl["emitted"])
+    log(f"rotating every {every}: {res['value']:.3e} updates/s, "
+        f"{res['ms_per_rotation']:.2f} ms per rotation, front/analytic "
+        f"{res['front_radius_over_analytic']}")
+    return res
+
+
 def cpu_baseline(w, sweeps: int):
     """The FP64 oracle (single thread) on the same grid, from the initial
     state, for a bounded number of sweeps."""
@@ -240,6 +280,9 @@ def main():
     ap.add_argument("--shadow-n", type=int, default=1048576,
                     help="vertices of the shadowing leg (0 = skip it)")
     ap.add_argument("--shadow-sweeps", type=int, default=1500)
+    ap.add_argument("--rotate-every", type=int, default=1,
+                    help="sweeps between random rotations of the bins in the rotation leg "
+                         "(0 = skip the leg)")
     ap.add_argument("--graph-sweeps", type=int, default=50,
                     help="sweeps per replayed HIP graph (0: one launch per sweep)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -404,6 +447,10 @@ def main():
         log(f"batched: {batched['value']:.3e} updates/s, {1e3 * el_b:.1f} ms/solve, "
             f"sweep launch {1e3 * kb:.1f} us, schedule {sched}")
 
+    rotated = None
+    if args.rotate_every > 0:
+        rotated = rotation_leg(ctx, w, args.rotate_every, log)
+
     shadowed = None
     if shadow is not None:
         def prof(on):
@@ -476,6 +523,7 @@ def main():
         "batched": batched,
         "served": served,
         "shadow": shadowed,
+        "rotated": rotated,
         "upload_s": up_s,
         "sweep_kernel_us": 1e3 * kern_ms,
         "roofline": roof,
