@@ -56,6 +56,7 @@ struct Grid {
   int64_t n_direct = 0;     // tiles whose halo is too large for LDS staging
   std::vector<double> bins0;   // [3K] bin directions given at upload
   bool rotated = false;
+  bool ebin_stale = false;
   std::vector<uint8_t> tile_direct;
 };
 
@@ -365,7 +366,7 @@ uint64_t bytes_estimate(const Sizes &s, int64_t n_em, int64_t n_rec, int64_t n_h
   uint64_t b = 0;
   b += rnd(4 * (s.npad + 1)) + rnd(4 * s.E) + rnd(s.E) + rnd(24 * s.E) + rnd(24 * s.K);
   b += rnd(4 * s.npad * s.K) + rnd(s.E) + rnd(8 * s.npad * s.kb * s.bb) +
-       rnd(4 * s.npad * s.kw) + 2 * rnd(4 * (s.ntiles * s.K + 1)) + rnd(4 * n_rec + 4);
+       rnd(4 * s.npad * s.kw) + 2 * rnd(4 * (s.ntiles * s.K * sx::kRecGroups + 1)) + rnd(4 * n_rec + 4);
   b += rnd(4 * (s.ntiles + 1)) + rnd(4 * n_halo + 4) + rnd(2 * s.E) + rnd(s.ntiles);
   b += rnd(4 * (s.npad + 1)) + rnd(4 * n_em + 4) + rnd(8 * n_em + 8);
   b += 6 * rnd(8 * s.npad);
@@ -407,17 +408,17 @@ int rebuild_routing(sx_ctx *ctx, Grid *g, const double *bins, bool rescale) {
   GridDev &h = g->hg;
   GridDev *dg = ctx->table + g->slot;
   hipStream_t st = ctx->stream;
-  const int32_t nrow = h.ntiles * h.k;
+  const int32_t nrow = h.ntiles * h.k * sx::kRecGroups;
   HIP_TRY(ctx, hipMemcpyAsync(const_cast<double *>(h.bins), bins, sizeof(double) * 3 * h.k,
                               hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, sx::launch_select(dg, h, st));
   if (rescale) HIP_TRY(ctx, sx::launch_rot_rescale(dg, h, st));
-  HIP_TRY(ctx, sx::launch_edge_bins(dg, h, st));
   HIP_TRY(ctx, sx::launch_em_bins(dg, h, g->n_em, st));
+  g->ebin_stale = true;   // the full edge-bin table is rebuilt when read
   HIP_TRY(ctx, sx::launch_mbits(dg, h, st));
   HIP_TRY(ctx, sx::launch_clear_inw(h, st));
   HIP_TRY(ctx, sx::launch_inlist_count(dg, h, st));
-  HIP_TRY(ctx, sx::launch_scan(h.rec_cnt, h.rec_ptr, nrow, st));
+  HIP_TRY(ctx, sx::launch_scan(h.rec_cnt, h.rec_ptr, h.scan_part, nrow, st));
   int32_t n_rec = 0;
   HIP_TRY(ctx, hipMemcpyAsync(&n_rec, h.rec_ptr + nrow, 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(ctx, hipStreamSynchronize(st));
@@ -778,8 +779,10 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   GA(d_ebin, E);
   GA(d_inw, npad * S.kb * S.bb);
   GA(d_mb, npad * S.kw);
-  GA(d_rec_cnt, ntiles * K + 1);
-  GA(d_rec_ptr, ntiles * K + 1);
+  GA(d_rec_cnt, ntiles * K * sx::kRecGroups + 1);
+  GA(d_rec_ptr, ntiles * K * sx::kRecGroups + 1);
+  int64_t *d_part;
+  GA(d_part, ntiles * K * sx::kRecGroups / 1024 + 2);
   GA(d_hptr, ntiles + 1);
   GA(d_hvid, halo_vid.size() + 1);
   GA(d_ehidx, E);
@@ -814,6 +817,7 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   h.mbits = d_mb;
   h.rec_cnt = d_rec_cnt;
   h.rec_ptr = d_rec_ptr;
+  h.scan_part = d_part;
   h.rec = nullptr;
   h.rec_cap = 0;
   h.halo_ptr = d_hptr;
@@ -875,7 +879,7 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
     return fail(ctx, SX_EDEVICE, "table kernels failed: %s", hipGetErrorString(e));
   };
   hipError_t he;
-  const int32_t nrow = (int32_t)(ntiles * K);
+  const int32_t nrow = (int32_t)(ntiles * K * sx::kRecGroups);
   if ((he = sx::launch_select(dg, h, st)) != hipSuccess) return kfail(he);
   if ((he = sx::launch_edge_bins(dg, h, st)) != hipSuccess) return kfail(he);
   g->n_em = (int64_t)P->em_k.size();
@@ -902,7 +906,7 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   if ((he = sx::launch_mbits(dg, h, st)) != hipSuccess) return kfail(he);
   if ((he = sx::launch_clear_inw(h, st)) != hipSuccess) return kfail(he);
   if ((he = sx::launch_inlist_count(dg, h, st)) != hipSuccess) return kfail(he);
-  if ((he = sx::launch_scan(h.rec_cnt, h.rec_ptr, nrow, st)) != hipSuccess) return kfail(he);
+  if ((he = sx::launch_scan(h.rec_cnt, h.rec_ptr, h.scan_part, nrow, st)) != hipSuccess) return kfail(he);
   int32_t n_rec = 0;
   if ((he = hipMemcpyAsync(&n_rec, h.rec_ptr + nrow, 4, hipMemcpyDeviceToHost, st)) != hipSuccess)
     return kfail(he);
@@ -1693,6 +1697,10 @@ int sx_read_tables(sx_ctx *ctx, sx_grid_id id, int32_t *sel_nbr, int32_t *sel_m,
   hipStream_t st = ctx->stream;
   const GridDev &h = g->hg;
   const int64_t n = h.n, K = h.k, E = h.n_edges;
+  if (edge_bin && g->ebin_stale) {
+    HIP_TRY(ctx, sx::launch_edge_bins(ctx->table + g->slot, h, st));
+    g->ebin_stale = false;
+  }
   if (sel_nbr || sel_m) {
     std::vector<uint32_t> f((size_t)(h.npad * K));
     HIP_TRY(ctx, hipMemcpyAsync(f.data(), h.fwd, 4 * h.npad * K, hipMemcpyDeviceToHost, st));

@@ -38,6 +38,9 @@ constexpr uint64_t kEmptyWord = 0x7FFFFFFFFFFFFFFFull;  // 7 x 511
 // One extra tile past the last holds zeros.  In-words use the same block
 // order with BB 64-bit words per block.
 constexpr int kBlockBytes = 16;
+// Record counts and offsets per (tile, bin, group of kRecGroupLanes lanes).
+constexpr int kRecGroups = 8;
+constexpr int kRecGroupLanes = kTile / kRecGroups;
 constexpr int kRecIdxBits = 23;
 // Forward word of a (vertex, bin) pair (selection result):
 //   bits 0..20 : three 7-bit slots, best first (127 = none)
@@ -76,8 +79,9 @@ struct GridDev {
   uint8_t *ebin;            // [E]
   uint64_t *inw;            // [ntiles][kb][64][bb]
   uint32_t *mbits;          // [ntiles][kw][64]
-  int32_t *rec_cnt;         // [ntiles*K+1] scratch: records per (tile, bin)
-  int32_t *rec_ptr;         // [ntiles*K+1]
+  int32_t *rec_cnt;         // [ntiles*K*kRecGroups+1] scratch: records per (tile, bin, group)
+  int32_t *rec_ptr;         // [ntiles*K*kRecGroups+1] first record of each
+  int64_t *scan_part;       // [ntiles*K*kRecGroups/1024 + 2] scratch of the record scan
   uint32_t *rec;            // [n_rec]
   int64_t rec_cap;
   const int32_t *halo_ptr;  // [ntiles+1]
@@ -107,7 +111,7 @@ struct GridDev {
 hipError_t launch_select(const GridDev *dg, const GridDev &hg, hipStream_t s);
 hipError_t launch_edge_bins(const GridDev *dg, const GridDev &hg, hipStream_t s);
 hipError_t launch_inlist_count(const GridDev *dg, const GridDev &hg, hipStream_t s);
-hipError_t launch_scan(int32_t *cnt, int32_t *ptr, int32_t n, hipStream_t s);
+hipError_t launch_scan(int32_t *cnt, int32_t *ptr, int64_t *part, int32_t n, hipStream_t s);
 hipError_t launch_inlist_fill(const GridDev *dg, const GridDev &hg, hipStream_t s);
 // After a rotation of the bins: the photons each (vertex, bin) holds are
 // re-split over the new selection (from fwd; the old one is still in

@@ -158,14 +158,23 @@ __device__ __forceinline__ int sender_index(const GridDev &g, bool direct,
 constexpr uint32_t kRecEmission = 1u << kRecIdxBits;
 constexpr uint32_t kRecIdxMask = (1u << kRecIdxBits) - 1u;
 
+// Thread (tile, bin, group) walks the kRecGroupLanes receivers of its
+// group in lane order; threads of neighbouring bins are neighbours, so their
+// selection-table reads are contiguous.  Record counts and offsets are kept
+// per (tile, bin, group), groups in lane order, so the records of a
+// (tile, bin) come out sorted by lane.
 __global__ void k_inlist_count(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
   const int K = g.k;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)g.ntiles * K) return;
-  const int tile = (int)(t / K), k = (int)(t - (int64_t)tile * K);
+  const int64_t nt = (int64_t)g.ntiles * K * kRecGroups;
+  if (t >= nt) return;
+  // t = (tile * kRecGroups + group) * K + k
+  const int k = (int)(t % K);
+  const int64_t tg = t / K;
+  const int tile = (int)(tg / kRecGroups), grp = (int)(tg % kRecGroups);
   int recs = 0;
-  for (int lane = 0; lane < kTile; ++lane) {
+  for (int lane = grp * kRecGroupLanes; lane < (grp + 1) * kRecGroupLanes; ++lane) {
     const int j = tile * kTile + lane;
     if (j >= g.n) break;
     int c = 0;
@@ -174,20 +183,23 @@ __global__ void k_inlist_count(const GridDev *__restrict__ gp) {
     recs += c > kWordEntries ? c - kWordEntries : 0;
     for (int q = g.em_ptr[j]; q < g.em_ptr[j + 1]; ++q) recs += g.em_k[q] == k ? 1 : 0;
   }
-  g.rec_cnt[t] = recs;
+  g.rec_cnt[((int64_t)tile * K + k) * kRecGroups + grp] = recs;
 }
 
 __global__ void k_inlist_fill(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
   const int K = g.k;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)g.ntiles * K) return;
-  const int tile = (int)(t / K), k = (int)(t - (int64_t)tile * K);
+  const int64_t nt = (int64_t)g.ntiles * K * kRecGroups;
+  if (t >= nt) return;
+  const int k = (int)(t % K);
+  const int64_t tg = t / K;
+  const int tile = (int)(tg / kRecGroups), grp = (int)(tg % kRecGroups);
   const bool direct = g.tile_direct[tile] != 0;
-  int64_t rp = g.rec_ptr[t];
+  int64_t rp = g.rec_ptr[((int64_t)tile * K + k) * kRecGroups + grp];
   const int kb = k / g.bb, b = k - kb * g.bb;
   uint64_t *out = g.inw + (((int64_t)tile * g.kb + kb) * kTile) * g.bb + b;
-  for (int lane = 0; lane < kTile; ++lane) {
+  for (int lane = grp * kRecGroupLanes; lane < (grp + 1) * kRecGroupLanes; ++lane) {
     const int j = tile * kTile + lane;
     uint64_t w = kEmptyWord;
     if (j < g.n) {
@@ -256,11 +268,19 @@ __global__ __launch_bounds__(64) void k_rot_rescale(GridDev *__restrict__ gp) {
     rot_rescale<float>(g, blockIdx.x, threadIdx.x);
 }
 
+// Bin of each source share: the bin closest to its edge (the edge-bin rule).
 __global__ void k_em_bins(GridDev *__restrict__ gp, int64_t n_em) {
   GridDev &g = *gp;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n_em) return;
-  g.em_k[q] = g.ebin[g.em_edge[q]];
+  const double *ed = &g.edir[3 * (int64_t)g.em_edge[q]];
+  int best = 0;
+  double cb = cosine3(ed, &g.bins[0]);
+  for (int k = 1; k < g.k; ++k) {
+    const double c = cosine3(ed, &g.bins[3 * k]);
+    if (c > cb) { cb = c; best = k; }
+  }
+  g.em_k[q] = best;
 }
 
 // Packed m(j, k), 2 bits per bin, 16 bins per word.  One lane per vertex.
@@ -281,31 +301,71 @@ __global__ void k_mbits(const GridDev *__restrict__ gp) {
   }
 }
 
-// Exclusive scan of n counts into ptr[0..n] by one workgroup.
-__global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt,
-                                               int32_t *__restrict__ ptr,
-                                               int32_t n) {
-  __shared__ int64_t part[1024];
+// Exclusive scan of n counts into ptr[0..n] (ptr[n] = total) in three
+// passes: each workgroup of 1024 scans its part and leaves its total in
+// part[], one workgroup scans the totals, each part adds its offset.
+__global__ __launch_bounds__(1024) void k_scan_part(const int32_t *__restrict__ cnt,
+                                                    int32_t *__restrict__ ptr,
+                                                    int64_t *__restrict__ part, int32_t n) {
+  __shared__ int64_t ws[16];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 1024 + t;
+  const int64_t v = i < n ? cnt[i] : 0;
+  int64_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) ws[wave] = x;
+  __syncthreads();
+  if (wave == 0) {
+    int64_t z = lane < 16 ? ws[lane] : 0;
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      const int64_t y = __shfl_up(z, off);
+      if (lane >= off) z += y;
+    }
+    if (lane < 16) ws[lane] = z;
+  }
+  __syncthreads();
+  if (i < n) ptr[i] = (int32_t)(x - v + (wave > 0 ? ws[wave - 1] : 0));
+  if (t == 0) part[blockIdx.x] = ws[15];
+}
+
+// Exclusive scan of the nb part totals in place (part[nb] = total), one
+// workgroup, any nb.
+__global__ __launch_bounds__(1024) void k_scan_top(int64_t *__restrict__ part, int32_t nb) {
+  __shared__ int64_t acc[1024];
   const int t = threadIdx.x;
-  const int64_t chunk = ((int64_t)n + 1023) / 1024;
+  const int64_t chunk = ((int64_t)nb + 1023) / 1024;
   const int64_t b = t * chunk;
-  const int64_t e = b + chunk < n ? b + chunk : n;
+  const int64_t e = b + chunk < nb ? b + chunk : nb;
   int64_t s = 0;
-  for (int64_t i = b; i < e; ++i) s += cnt[i];
-  part[t] = s;
+  for (int64_t i = b; i < e; ++i) s += part[i];
+  acc[t] = s;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
-    int64_t v = t >= off ? part[t - off] : 0;
+    const int64_t v = t >= off ? acc[t - off] : 0;
     __syncthreads();
-    part[t] += v;
+    acc[t] += v;
     __syncthreads();
   }
-  int64_t run = part[t] - s;
+  int64_t run = acc[t] - s;
   for (int64_t i = b; i < e; ++i) {
-    ptr[i] = (int32_t)run;
-    run += cnt[i];
+    const int64_t c = part[i];
+    part[i] = run;
+    run += c;
   }
-  if (t == 1023) ptr[n] = (int32_t)part[1023];
+  if (t == 1023) part[nb] = acc[1023];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_add(int32_t *__restrict__ ptr,
+                                                   const int64_t *__restrict__ part,
+                                                   int32_t n, int32_t nb) {
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  if (i < n) ptr[i] += (int32_t)part[blockIdx.x];
+  if (i == 0) ptr[n] = (int32_t)part[nb];
 }
 
 // ---------------------------------------------------------- chemistry ---
@@ -413,11 +473,11 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
   const int rb = rowp[j];
   const SX_G W2 *__restrict__ iw =
       gld((const W2 *)(G->inw + ((int64_t)tile * KB * kTile + lane) * BB));
-  const SX_G int32_t *__restrict__ rptr = gld(G->rec_ptr) + (int64_t)tile * K;
+  const SX_G int32_t *__restrict__ rptr = gld(G->rec_ptr) + (int64_t)tile * K * kRecGroups;
   const SX_G uint32_t *__restrict__ rec = gld(G->rec);
   // first record of every block of the tile, lane kb holding block kb's
   // (KB < 64), so that no load inside the block loop waits on another
-  const int rpl = lane <= KB ? rptr[lane * BB < K ? lane * BB : K] : 0;
+  const int rpl = lane <= KB ? rptr[(lane * BB < K ? lane * BB : K) * kRecGroups] : 0;
   const SX_G double *__restrict__ ema = gld(G->em_amt);
   // block of (vertex v, block kb)
   auto blk = [&](uint32_t v, int kb) -> uint32_t {
@@ -731,8 +791,9 @@ hipError_t launch_edge_bins(const GridDev *dg, const GridDev &hg,
 
 hipError_t launch_inlist_count(const GridDev *dg, const GridDev &hg,
                                hipStream_t s) {
-  hipLaunchKernelGGL(k_inlist_count, dim3(blocks_for((int64_t)hg.ntiles * hg.k, 64)),
-                     dim3(64), 0, s, dg);
+  hipLaunchKernelGGL(k_inlist_count,
+                     dim3(blocks_for((int64_t)hg.ntiles * hg.k * kRecGroups, 256)), dim3(256),
+                     0, s, dg);
   return hipGetLastError();
 }
 
@@ -757,15 +818,22 @@ hipError_t launch_em_bins(GridDev *dg, const GridDev &hg, int64_t n_em, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_scan(int32_t *cnt, int32_t *ptr, int32_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, cnt, ptr, n);
+hipError_t launch_scan(int32_t *cnt, int32_t *ptr, int64_t *part, int32_t n,
+                       hipStream_t s) {
+  const unsigned nb = blocks_for(n, 1024);
+  if (nb > 0)
+    hipLaunchKernelGGL(k_scan_part, dim3(nb), dim3(1024), 0, s, cnt, ptr, part, n);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, part, (int32_t)nb);
+  hipLaunchKernelGGL(k_scan_add, dim3(nb > 0 ? nb : 1), dim3(1024), 0, s, ptr, part, n,
+                     (int32_t)nb);
   return hipGetLastError();
 }
 
 hipError_t launch_inlist_fill(const GridDev *dg, const GridDev &hg,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_inlist_fill, dim3(blocks_for((int64_t)hg.ntiles * hg.k, 64)),
-                     dim3(64), 0, s, dg);
+  hipLaunchKernelGGL(k_inlist_fill,
+                     dim3(blocks_for((int64_t)hg.ntiles * hg.k * kRecGroups, 256)), dim3(256),
+                     0, s, dg);
   return hipGetLastError();
 }
 
