@@ -28,6 +28,8 @@ SX_FP32_TRANSPORT = 1
 SX_ORDER_GRID = 0
 SX_ORDER_DIRECT_FIRST = 1
 SX_MAX_GRAPH_SWEEPS = 4096
+SX_MAX_BINS = 96
+SX_MAX_DEGREE = 127
 
 EXPORTED = [
     "sx_init", "sx_finalize", "sx_grid_bytes", "sx_grid_upload",

@@ -37,6 +37,17 @@ def test_library_exports_every_declared_symbol():
     assert set(declared_functions()) <= exported
 
 
+def test_binding_constants_match_header():
+    txt = open(HEADER).read()
+    defs = dict(re.findall(r"^#define (SX_\w+)\s+\(?(-?\d+)\)?", txt, re.M))
+    for name in ("SX_OK", "SX_EINVAL", "SX_ENOMEM", "SX_EDEVICE", "SX_ENOTFOUND",
+                 "SX_ENOTSUP", "SX_EAGAIN", "SX_FP64", "SX_FP32_TRANSPORT",
+                 "SX_ORDER_GRID", "SX_ORDER_DIRECT_FIRST", "SX_MAX_GRAPH_SWEEPS",
+                 "SX_MAX_DEGREE"):
+        assert int(defs[name]) == getattr(sx, name), name
+    assert sx.SX_MAX_BINS == int(defs["SX_MAX_BINS_FP32"]) == int(defs["SX_MAX_BINS_FP64"])
+
+
 def test_error_strings():
     lib = sx.load()
     assert lib.sx_strerror(sx.SX_EINVAL) == b"invalid argument"
