@@ -57,6 +57,14 @@ def _load(path=None):
         lib.ora_get_tables.argtypes = [P, P, P, P, P, P]
         lib.ora_rotate.restype = C.c_int
         lib.ora_rotate.argtypes = [P, P]
+        lib.ora_set_transport.restype = C.c_int
+        lib.ora_set_transport.argtypes = [P, C.c_int32, C.c_double]
+        lib.ora_get_edge_state.restype = None
+        lib.ora_get_edge_state.argtypes = [P, P, P]
+        lib.ora_set_edge_state.restype = None
+        lib.ora_set_edge_state.argtypes = [P, P, P]
+        lib.ora_get_ballistic.restype = None
+        lib.ora_get_ballistic.argtypes = [P, P, P]
         lib.ora_free.restype = None
         lib.ora_free.argtypes = [P]
         lib.ora_chem_cell.restype = C.c_double
@@ -116,6 +124,9 @@ class Oracle:
         if not h:
             raise ValueError("oracle: " + lib.ora_last_error().decode())
         self._h = h
+        self.combined = int(getattr(w, "transport", 0)) == 1
+        if self.combined:
+            lib.ora_set_transport(h, 1, float(w.tau_switch))
 
     def run(self, n_sweeps: int, history: bool = False):
         hist = np.zeros((n_sweeps, 4)) if history else None
@@ -143,6 +154,26 @@ class Oracle:
                           tallies["absorbed"], tallies["escaped"],
                           tallies["in_flight"]], np.float64)
         self._lib.ora_set_state(self._h, _p(y), _p(ph), _p(t))
+
+    def edge_state(self):
+        """Combined transport: photons per edge slot [E] and the layout of
+        every vertex [N] (0 bins, 1 edges)."""
+        pe = np.zeros(self.w.n_edges)
+        lay = np.zeros(self.n, np.int8)
+        self._lib.ora_get_edge_state(self._h, _p(pe), _p(lay))
+        return dict(photons_e=pe, layout=lay)
+
+    def set_edge_state(self, photons_e=None, layout=None):
+        pe = None if photons_e is None else np.ascontiguousarray(photons_e, np.float64)
+        lay = None if layout is None else np.ascontiguousarray(layout, np.int8)
+        self._lib.ora_set_edge_state(self._h, _p(pe), _p(lay))
+
+    def ballistic(self):
+        """Ballistic tables: chosen neighbours [E, mpb] (-1 padding), counts [E]."""
+        sel = np.zeros((self.w.n_edges, self.mpb), np.int32)
+        cnt = np.zeros(self.w.n_edges, np.int32)
+        self._lib.ora_get_ballistic(self._h, _p(sel), _p(cnt))
+        return dict(bsel=sel, bm=cnt)
 
     def rotate(self, R):
         """Rotate the direction bins to R u_k (Sect. 2.2.3)."""

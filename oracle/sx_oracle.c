@@ -46,6 +46,18 @@ struct ora_grid {
     double *I;           /* [N*K] scratch: incoming photons */
     double *nin;         /* [N] last sweep's incoming photons */
     double sweeps, emitted, absorbed, escaped, in_flight;
+    /* Combined transport (Sect. 2.2.4); unused while combined == 0. */
+    int32_t combined;
+    double tau_switch;   /* ballistic where y tau >= tau_switch */
+    int32_t *rev;        /* [E] slot of i in the row of j, for edge i -> j */
+    int32_t *bsel;       /* [E*mpb] ballistic choice for the packet that came
+                            into the row's vertex along the slot's edge */
+    int32_t *bm;         /* [E] number chosen */
+    double *Oe;          /* [E] outgoing photons per chosen neighbour of each
+                            incoming packet of a ballistic vertex */
+    double *Ie;          /* [E] scratch: photons in, per incoming edge */
+    int8_t *layout;      /* [N] 0: vertex holds bins (O), 1: edges (Oe) */
+    int8_t *mode;        /* [N] scratch: this sweep's mode */
 };
 
 static void *xcalloc(size_t n, size_t s) {
@@ -375,9 +387,201 @@ static void sweep(ora_grid *g) {
     g->sweeps += 1.0;
 }
 
+/* ---------------------------------------------------------------------- */
+/* Combined transport (Sects. 2.2.2-2.2.4, 5.1.3).
+ *
+ * Ballistic transport: photons that came into vertex j along the edge from
+ * i keep travelling in the direction of that edge, i -> j; they are split
+ * equally over the mpb (= d = 3) neighbours of j most aligned with it,
+ * excluding any outside the forward 90 degree cone, with the selection rule
+ * of the bins.  These tables depend on the grid alone.
+ *
+ * Mode of a vertex: ballistic where its optical depth y tau (Eq.
+ * optical_depth with the neutral fraction at the start of the step) is at
+ * least tau_switch, direction-conserving elsewhere.  A ballistic vertex
+ * holds its photons per incoming edge, a direction-conserving one per bin.
+ * Conversion at the receiver: photons that reach a ballistic vertex are
+ * filed under the edge they came along (whatever bin they were in); photons
+ * sent by a ballistic vertex (and photons of sources) that reach a
+ * direction-conserving vertex are filed in the bin of the edge they came
+ * along. */
+
+/* Index of the directed edge i -> j in the row of i. */
+static int64_t edge_index(const ora_grid *g, int64_t i, int32_t j) {
+    for (int64_t e = g->ptr[i]; e < g->ptr[i + 1]; e++)
+        if (g->nbr[e] == j) return e;
+    return -1;
+}
+
+static void build_ballistic(ora_grid *g) {
+    int64_t n = g->n;
+    int mpb = g->mpb;
+    for (int64_t j = 0; j < n; j++) {
+        for (int64_t e = g->ptr[j]; e < g->ptr[j + 1]; e++) {
+            /* the packet arrived along nbr[e] -> j: the direction opposite
+             * to the unit vector of the edge j -> nbr[e] */
+            double u[3] = {-g->edir[3 * e + 0], -g->edir[3 * e + 1],
+                           -g->edir[3 * e + 2]};
+            int32_t slots[16];
+            int c = select_slots(g, j, u, slots);
+            for (int r = 0; r < mpb; r++)
+                g->bsel[e * mpb + r] = r < c ? g->nbr[g->ptr[j] + slots[r]] : -1;
+            g->bm[e] = c;
+            /* the edge j -> nbr[e] is the incoming edge nbr[e] -> j seen
+             * from the other end: its slot in the row of nbr[e] */
+            int64_t back = edge_index(g, g->nbr[e], (int32_t)j);
+            g->rev[e] = (int32_t)(back - g->ptr[g->nbr[e]]);
+        }
+    }
+}
+
+/* Photons v travel along the edge e (i -> j) carrying bin b; file them at j
+ * by j's mode in this step. */
+static void deliver(ora_grid *g, int64_t e, int32_t b, double v) {
+    int32_t j = g->nbr[e];
+    if (g->mode[j] == 0)
+        g->I[(int64_t)j * g->K + b] += v;
+    else
+        g->Ie[g->ptr[j] + g->rev[e]] += v;
+}
+
+static void sweep_combined(ora_grid *g) {
+    int64_t n = g->n, K = g->K, E = g->n_edges;
+    int mpb = g->mpb;
+    for (int64_t j = 0; j < n; j++)
+        g->mode[j] = (g->y[j] * g->tau[j] >= g->tau_switch) ? 1 : 0;
+    memset(g->I, 0, (size_t)(n * K) * sizeof(double));
+    memset(g->Ie, 0, (size_t)E * sizeof(double));
+
+    /* Transport from what every vertex held after the previous step. */
+    for (int64_t i = 0; i < n; i++) {
+        if (g->layout[i] == 0) {
+            for (int64_t k = 0; k < K; k++) {
+                int32_t mm = g->m[i * K + k];
+                double v = g->O[i * K + k];
+                const int32_t *s = &g->sel[(i * K + k) * mpb];
+                for (int t = 0; t < mm; t++)
+                    deliver(g, edge_index(g, i, s[t]), (int32_t)k, v);
+            }
+        } else {
+            for (int64_t ein = g->ptr[i]; ein < g->ptr[i + 1]; ein++) {
+                double v = g->Oe[ein];
+                for (int t = 0; t < g->bm[ein]; t++) {
+                    int64_t e = edge_index(g, i, g->bsel[ein * mpb + t]);
+                    deliver(g, e, g->ebin[e], v);
+                }
+            }
+        }
+    }
+
+    /* Sources, as in direction-conserving transport, filed by the mode of
+     * each receiver. */
+    for (int32_t s = 0; s < g->n_src; s++) {
+        int64_t v = g->src_v[s];
+        double En = g->src_rate[s] * g->dt;
+        g->emitted += En;
+        const double *d = &g->src_dir[3 * s];
+        int64_t b = g->ptr[v], deg = g->ptr[v + 1] - g->ptr[v];
+        if (d[0] == 0.0 && d[1] == 0.0 && d[2] == 0.0) {
+            if (deg == 0) { g->escaped += En; continue; }
+            double share = En / (double)deg;
+            for (int64_t e = b; e < b + deg; e++) deliver(g, e, g->ebin[e], share);
+        } else {
+            int32_t slots[16];
+            int c = select_slots(g, v, d, slots);
+            if (c == 0) { g->escaped += En; continue; }
+            double share = En / (double)c;
+            for (int t = 0; t < c; t++) {
+                int64_t e = b + slots[t];
+                deliver(g, e, g->ebin[e], share);
+            }
+        }
+    }
+
+    /* Interaction, then the outgoing photons in the vertex's mode. */
+    for (int64_t j = 0; j < n; j++) {
+        double nin = 0.0;
+        if (g->mode[j] == 0)
+            for (int64_t k = 0; k < K; k++) nin += g->I[j * K + k];
+        else
+            for (int64_t e = g->ptr[j]; e < g->ptr[j + 1]; e++) nin += g->Ie[e];
+        g->nin[j] = nin;
+        double A, T;
+        g->y[j] = chem(g->y[j], nin, g->dt, g->nH[j] * g->vol[j], g->tau[j],
+                       g->alpha_B * g->nH[j], g->n_sub, &A, &T);
+        g->absorbed += A;
+        for (int64_t k = 0; k < K; k++) g->O[j * K + k] = 0.0;
+        for (int64_t e = g->ptr[j]; e < g->ptr[j + 1]; e++) g->Oe[e] = 0.0;
+        if (g->mode[j] == 0) {
+            for (int64_t k = 0; k < K; k++) {
+                double out = g->I[j * K + k] * T;
+                int32_t mm = g->m[j * K + k];
+                if (mm > 0) g->O[j * K + k] = out / (double)mm;
+                else g->escaped += out;
+            }
+        } else {
+            for (int64_t e = g->ptr[j]; e < g->ptr[j + 1]; e++) {
+                double out = g->Ie[e] * T;
+                if (g->bm[e] > 0) g->Oe[e] = out / (double)g->bm[e];
+                else g->escaped += out;
+            }
+        }
+        g->layout[j] = g->mode[j];
+    }
+
+    double f = 0.0;
+    for (int64_t j = 0; j < n; j++)
+        for (int64_t k = 0; k < K; k++)
+            f += g->O[j * K + k] * (double)g->m[j * K + k];
+    for (int64_t e = 0; e < E; e++) f += g->Oe[e] * (double)g->bm[e];
+    g->in_flight = f;
+    g->sweeps += 1.0;
+}
+
+int ora_set_transport(ora_grid *g, int32_t combined, double tau_switch) {
+    g_err[0] = 0;
+    if (combined != 0 && combined != 1) {
+        snprintf(g_err, sizeof g_err, "bad transport");
+        return -1;
+    }
+    g->combined = combined;
+    g->tau_switch = tau_switch;
+    if (combined && !g->bsel) {
+        int64_t E = g->n_edges;
+        g->rev = (int32_t *)xcalloc(E, sizeof(int32_t));
+        g->bsel = (int32_t *)xcalloc(E * g->mpb, sizeof(int32_t));
+        g->bm = (int32_t *)xcalloc(E, sizeof(int32_t));
+        g->Oe = (double *)xcalloc(E, sizeof(double));
+        g->Ie = (double *)xcalloc(E, sizeof(double));
+        g->layout = (int8_t *)xcalloc(g->n, sizeof(int8_t));
+        g->mode = (int8_t *)xcalloc(g->n, sizeof(int8_t));
+        build_ballistic(g);
+    }
+    return 0;
+}
+
+void ora_get_edge_state(const ora_grid *g, double *photons_e, int8_t *layout) {
+    if (!g->combined) return;
+    if (photons_e) memcpy(photons_e, g->Oe, (size_t)g->n_edges * sizeof(double));
+    if (layout) memcpy(layout, g->layout, (size_t)g->n * sizeof(int8_t));
+}
+
+void ora_set_edge_state(ora_grid *g, const double *photons_e, const int8_t *layout) {
+    if (!g->combined) return;
+    if (photons_e) memcpy(g->Oe, photons_e, (size_t)g->n_edges * sizeof(double));
+    if (layout) memcpy(g->layout, layout, (size_t)g->n * sizeof(int8_t));
+}
+
+void ora_get_ballistic(const ora_grid *g, int32_t *bsel, int32_t *bm) {
+    if (!g->combined) return;
+    if (bsel) memcpy(bsel, g->bsel, (size_t)(g->n_edges * g->mpb) * sizeof(int32_t));
+    if (bm) memcpy(bm, g->bm, (size_t)g->n_edges * sizeof(int32_t));
+}
+
 int ora_run(ora_grid *g, int32_t n_sweeps, double *history) {
     for (int32_t s = 0; s < n_sweeps; s++) {
-        sweep(g);
+        if (g->combined) sweep_combined(g);
+        else sweep(g);
         if (history) {
             history[4 * s + 0] = g->emitted;
             history[4 * s + 1] = g->absorbed;
@@ -472,5 +676,7 @@ void ora_free(ora_grid *g) {
     free(g->nH); free(g->vol); free(g->dL); free(g->tau); free(g->sel);
     free(g->m); free(g->ebin); free(g->src_v); free(g->src_rate);
     free(g->src_dir); free(g->y); free(g->O); free(g->I); free(g->nin);
+    free(g->rev); free(g->bsel); free(g->bm); free(g->Oe); free(g->Ie);
+    free(g->layout); free(g->mode);
     free(g);
 }

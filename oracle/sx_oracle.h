@@ -68,6 +68,28 @@ int ora_rotate(ora_grid *g, const double *R);
 void ora_get_tables(const ora_grid *g, int32_t *sel_nbr, int32_t *sel_m,
                     int32_t *edge_bin, double *dL, double *tau);
 
+/* Combined transport (Sects. 2.2.2-2.2.4).  combined = 1: from the next
+ * sweep on, every vertex whose optical depth y tau is at least tau_switch at
+ * the start of a sweep uses ballistic transport (photons held per incoming
+ * edge, sent on to the <= max_per_bin neighbours most aligned with that
+ * edge), the others direction-conserving transport; tau_switch <= 0 makes
+ * every vertex ballistic.  combined = 0: direction-conserving everywhere.
+ * Returns 0, or -1 for a bad argument. */
+int ora_set_transport(ora_grid *g, int32_t combined, double tau_switch);
+
+/* Per-edge state of combined transport (nothing happens while combined is
+ * 0).  photons_e [E]: for edge slot e of vertex j (caller's CSR order), the
+ * photons each chosen neighbour of j receives next step from the packet that
+ * came into j along that edge; layout [N]: 0 = the vertex holds bins
+ * (photons of ora_get_state), 1 = edges. */
+void ora_get_edge_state(const ora_grid *g, double *photons_e, int8_t *layout);
+void ora_set_edge_state(ora_grid *g, const double *photons_e, const int8_t *layout);
+
+/* Ballistic tables: bsel [E*max_per_bin] the neighbour ids chosen for the
+ * packet arriving along each edge slot (best first, -1 padding), bm [E] how
+ * many. */
+void ora_get_ballistic(const ora_grid *g, int32_t *bsel, int32_t *bm);
+
 void ora_free(ora_grid *g);
 
 /* One vertex, one radiative-transfer step of length dt: n_sub backward-Euler

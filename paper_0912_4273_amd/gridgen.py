@@ -29,6 +29,9 @@ ALPHA_B = 2.59e-13          # cm^3 s^-1, case B at 1e4 K
 SX_FP64 = 0
 SX_FP32_TRANSPORT = 1
 
+SX_TRANSPORT_DCT = 0        # direction-conserving transport everywhere
+SX_TRANSPORT_COMBINED = 1   # ballistic where y tau >= tau_switch (Sect. 2.2.4)
+
 
 @dataclass
 class Workload:
@@ -54,6 +57,8 @@ class Workload:
     max_per_bin: int = 3
     cos_min: float = 0.0
     precision: int = SX_FP64
+    transport: int = SX_TRANSPORT_DCT
+    tau_switch: float = 1.0
     box: float = 0.0
     meta: dict = field(default_factory=dict)
 
@@ -307,6 +312,33 @@ def chain_graph(n: int, spacing: float, n_H: float, volume: float,
         bin_dirs=axis_bins() if bins is None else bins,
         src_vertex=np.array([0], np.int32), src_rate=np.array([1e40]),
         dt=1e10, n_sweeps=n, box=n * spacing)
+
+
+def lattice_graph(L: int, spacing: float = 1.0) -> Workload:
+    """An L x L x L cubic lattice, vertex (ix, iy, iz) at index
+    (ix * L + iy) * L + iz and position spacing * (ix, iy, iz), each linked
+    to its (up to) six axis neighbours.  Six axis bins, one source at the
+    centre; unit density and volume (callers override the physics)."""
+    ids = np.arange(L ** 3).reshape(L, L, L)
+    ix, iy, iz = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+    pos = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], 1).astype(np.float64) * spacing
+    rows = []
+    for a, b, c in zip(ix.ravel(), iy.ravel(), iz.ravel()):
+        r = []
+        for d in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+            p2 = (a + d[0], b + d[1], c + d[2])
+            if all(0 <= q < L for q in p2):
+                r.append(int(ids[p2]))
+        rows.append(sorted(r))
+    ptr = np.zeros(L ** 3 + 1, np.int64)
+    ptr[1:] = np.cumsum([len(r) for r in rows])
+    idx = np.array([j for r in rows for j in r], np.int32)
+    n = L ** 3
+    return Workload(
+        name=f"lattice{L}", pos=pos, nbr_ptr=ptr, nbr_idx=idx,
+        n_H=np.ones(n), volume=np.full(n, spacing ** 3), bin_dirs=axis_bins(),
+        src_vertex=np.array([int(ids[L // 2, L // 2, L // 2])], np.int32),
+        src_rate=np.array([1.0]), dt=1.0, n_sweeps=L, box=L * spacing)
 
 
 def star_graph(spacing: float = 1.0) -> Workload:

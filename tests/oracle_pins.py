@@ -266,7 +266,165 @@ def pin_front_law(lib=None, w=None, tol=0.08, t_min_myr=60.0):
     return worst
 
 
+# ------------------------------------------------------ combined transport ---
+
+def pin_combined_off_is_dct(lib=None):
+    """Combined transport with a switch no vertex reaches is
+    direction-conserving transport everywhere, to the last bit."""
+    w = G.small_random(300, seed=11, n_bins=21, box=3e21, rate=1e48, n_src=2, dt=3e13)
+    a = Oracle(w, lib)
+    a.run(12)
+    sa = a.state()
+    for ts in (math.inf, 1e300):
+        b = Oracle(G.with_(w, transport=G.SX_TRANSPORT_COMBINED, tau_switch=ts), lib)
+        b.run(12)
+        sb = b.state()
+        assert np.array_equal(sa["y"], sb["y"]) and np.array_equal(sa["photons"], sb["photons"])
+        assert sa["tallies"] == sb["tallies"]
+        assert not b.edge_state()["layout"].any()
+
+
+def _brute_ballistic(w):
+    """For every edge slot (j, s): the packet came from i = nbr[s] and keeps
+    the direction i -> j; sort j's neighbours by cosine with it, keep the
+    best max_per_bin with cosine > cos_min, ties to the lower id."""
+    ptr, idx, pos = w.nbr_ptr, w.nbr_idx, w.pos
+    sel = -np.ones((w.n_edges, w.max_per_bin), np.int32)
+    cnt = np.zeros(w.n_edges, np.int32)
+    for j in range(w.n):
+        nb = idx[ptr[j]:ptr[j + 1]]
+        if nb.size == 0:
+            continue
+        d = pos[nb] - pos[j]
+        ln = np.sqrt((d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2])
+        e = d / ln[:, None]
+        for s in range(nb.size):
+            u = -e[s]
+            c = (e[:, 0] * u[0] + e[:, 1] * u[1]) + e[:, 2] * u[2]
+            cand = sorted((-c[q], int(nb[q])) for q in range(nb.size) if c[q] > w.cos_min)
+            top = [v for _, v in cand[: w.max_per_bin]]
+            cnt[ptr[j] + s] = len(top)
+            sel[ptr[j] + s, : len(top)] = top
+    return sel, cnt
+
+
+def pin_ballistic_brute_force(lib=None):
+    """Ballistic transport (Sect. 2.2.2): the packet that came in along an
+    edge goes to the (up to) three neighbours most aligned with that edge,
+    never outside the forward 90 degree cone."""
+    for w in (G.small_random(150, seed=12, n_bins=21),
+              G.with_(G.small_random(120, seed=13, n_bins=21), max_per_bin=2)):
+        o = Oracle(G.with_(w, transport=G.SX_TRANSPORT_COMBINED, tau_switch=0.0), lib)
+        t = o.ballistic()
+        sel, cnt = _brute_ballistic(w)
+        assert np.array_equal(t["bm"], cnt), w.name
+        assert np.array_equal(t["bsel"], sel), w.name
+        # a straight packet never turns back towards where it came from
+        for j in range(w.n):
+            for e in range(w.nbr_ptr[j], w.nbr_ptr[j + 1]):
+                assert w.nbr_idx[e] not in t["bsel"][e], (j, e)
+
+
+def lattice_two_regions(L=9, sweeps=6):
+    """Cubic lattice, six axis bins, no absorption to rounding (sigma 1e-40,
+    no recombination).  Vertices with ix < L//2 are ionised (y = 0, so
+    optical depth 0: direction-conserving), the rest neutral (optical depth
+    1e-40 >= switch 1e-41: ballistic).  Sources of 6 photons per step (one
+    per axis edge) at ix = 1 (conserving side), ix = L//2 and ix = L//2 + 2
+    (ballistic side), all at iy = iz = L//2."""
+    w = G.lattice_graph(L)
+    c = L // 2
+    ids = np.arange(L ** 3).reshape(L, L, L)
+    x0 = np.zeros(L ** 3)
+    x0[ids[:c].ravel()] = 1.0
+    src = np.array([ids[1, c, c], ids[c, c, c], ids[c + 2, c, c]], np.int32)
+    return G.with_(w, x_init=x0, sigma=1e-40, alpha_B=0.0, dt=1.0, n_sweeps=sweeps,
+                   src_vertex=src, src_rate=np.full(3, 6.0), dL=np.ones(L ** 3),
+                   transport=G.SX_TRANSPORT_COMBINED, tau_switch=1e-41)
+
+
+def lattice_expected(w):
+    """Straight lines: the packet a source sends along axis a in step t is
+    one photon at distance S - t + 1 after S steps, held by that vertex in
+    the bin of a (conserving side) or under the edge it came along
+    (ballistic side); it leaves the domain when it reaches the face the axis
+    points at."""
+    L = round(w.n ** (1 / 3))
+    S = w.n_sweeps
+    c = L // 2
+    ids = np.arange(L ** 3).reshape(L, L, L)
+    axes = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+    O = np.zeros((w.n, 6))
+    Oe = np.zeros(w.n_edges)
+    escaped = 0.0
+    for v in w.src_vertex:
+        p0 = np.array(np.unravel_index(int(v), (L, L, L)))
+        for a, d in enumerate(axes):
+            for dist in range(1, S + 1):
+                p = p0 + dist * np.array(d)
+                if not np.all((p >= 0) & (p < L)):
+                    break
+                nxt = p + np.array(d)
+                if not np.all((nxt >= 0) & (nxt < L)):
+                    # arrived at the face and left: this packet and every
+                    # one sent before it along this axis
+                    escaped += float(S - dist + 1)
+                    break
+                j = int(ids[tuple(p)])
+                if p[0] < c:
+                    O[j, a] += 1.0
+                else:
+                    prev = int(ids[tuple(p - np.array(d))])
+                    row = w.nbr_idx[w.nbr_ptr[j]:w.nbr_ptr[j + 1]]
+                    Oe[w.nbr_ptr[j] + int(np.nonzero(row == prev)[0][0])] += 1.0
+    layout = (np.arange(w.n) // (L * L) >= c).astype(np.int8)
+    return O, Oe, layout, escaped
+
+
+def pin_combined_lattice(lib=None):
+    """Both conversions of combined transport (Sect. 2.2.4) on a lattice
+    where every path is a straight line: photons crossing into the
+    ballistic side are filed under their edge, photons sent from the
+    ballistic side into the conserving side in the bin of their edge."""
+    w = lattice_two_regions()
+    o = Oracle(w, lib)
+    o.run(w.n_sweeps)
+    st, es = o.state(), o.edge_state()
+    O, Oe, layout, escaped = lattice_expected(w)
+    assert np.array_equal(es["layout"], layout)
+    assert np.array_equal(st["photons"], O)
+    assert np.array_equal(es["photons_e"], Oe)
+    t = st["tallies"]
+    assert t["emitted"] == 18.0 * w.n_sweeps
+    assert t["escaped"] == escaped
+    assert t["in_flight"] == O.sum() + Oe.sum()
+    assert 0.0 <= t["absorbed"] <= 1e-30
+
+
+def pin_combined_conservation(lib=None):
+    """Photon conservation at every step with both modes in use and
+    vertices changing mode as they are ionised."""
+    w = G.small_random(500, seed=14, n_bins=42, box=3e21, n_H=1e-3, rate=1e46,
+                       n_src=3, dt=3e13)
+    sd = np.zeros((3, 3))
+    sd[2] = [0.0, 1.0, 0.0]
+    w = G.with_(w, src_dir=sd, transport=G.SX_TRANSPORT_COMBINED, tau_switch=1.0)
+    o = Oracle(w, lib)
+    lay0 = None
+    for _ in range(4):
+        h = o.run(10, history=True)
+        res = h[:, 0] - (h[:, 1] + h[:, 2] + h[:, 3])
+        assert np.all(np.abs(res) <= 1e-12 * h[:, 0]), res / h[:, 0]
+        lay = o.edge_state()["layout"]
+        if lay0 is None:
+            lay0 = lay
+    assert lay0.any() and (lay0 == 0).any()        # both modes in use
+    assert np.count_nonzero(lay0 == 1) > np.count_nonzero(lay == 1)   # fronts switch vertices
+
+
 FAST_PINS = [pin_recombination_closed_form, pin_equilibrium_fixed_point,
              pin_ode_convergence, pin_photon_accounting,
              pin_selection_brute_force, pin_axis_star, pin_ties,
-             pin_chain_hops, pin_conservation]
+             pin_chain_hops, pin_conservation, pin_combined_off_is_dct,
+             pin_ballistic_brute_force, pin_combined_lattice,
+             pin_combined_conservation]

@@ -32,6 +32,17 @@ MUTANTS = {
     "optical_depth_without_sigma": ("g->tau[i] = (g->nH[i] * sigma) * g->dL[i];",
                                     "g->tau[i] = g->nH[i] * g->dL[i];"),
     "escape_lost": ("g->escaped += out;", "g->escaped += 0.0 * out;"),
+    "ballistic_not_reversed": ("double u[3] = {-g->edir[3 * e + 0], -g->edir[3 * e + 1],",
+                               "double u[3] = {g->edir[3 * e + 0], g->edir[3 * e + 1],"),
+    "mode_ignores_neutral_fraction": ("(g->y[j] * g->tau[j] >= g->tau_switch)",
+                                      "(g->tau[j] >= g->tau_switch)"),
+    "mode_from_previous_layout": ("    if (g->mode[j] == 0)\n        g->I[",
+                                  "    if (g->layout[j] == 0)\n        g->I["),
+    "ballistic_conversion_first_bin": ("deliver(g, e, g->ebin[e], v);", "deliver(g, e, 0, v);"),
+    "ballistic_not_split": ("if (g->bm[e] > 0) g->Oe[e] = out / (double)g->bm[e];",
+                            "if (g->bm[e] > 0) g->Oe[e] = out;"),
+    "filed_at_sender_slot": ("g->Ie[g->ptr[j] + g->rev[e]] += v;", "g->Ie[e] += v;"),
+    "in_flight_skips_edges": ("f += g->Oe[e] * (double)g->bm[e];", "f += 0.0 * g->Oe[e];"),
     "nin_skips_first_bin": ("for (int64_t k = 0; k < K; k++) nin += g->I[j * K + k];",
                             "for (int64_t k = 1; k < K; k++) nin += g->I[j * K + k];"),
 }

@@ -39,6 +39,15 @@ def test_front_law_config1():
     assert worst < 0.08
 
 
+@pytest.mark.parametrize("tau_switch", [1.0, 0.0])
+def test_front_law_combined(tau_switch):
+    """Combined transport with the paper's switch (optical depth 1) and pure
+    ballistic transport (switch 0) both follow the front law of Test 1."""
+    w = G.with_(G.config1(), transport=G.SX_TRANSPORT_COMBINED, tau_switch=tau_switch)
+    worst = P.pin_front_law(w=w)
+    assert worst < 0.08
+
+
 def test_one_over_r2():
     P.pin_one_over_r2()
 
