@@ -25,13 +25,16 @@ MUTANTS = {
     "cosine_drops_z": ("return (a + b) + c;", "return (a + b);"),
     "only_two_per_bin": ("for (int r = 0; r < g->mpb; r++) {", "for (int r = 0; r < g->mpb - 1; r++) {"),
     "transport_wrong_bin": ("g->I[(int64_t)s[t] * K + k] += v;", "g->I[(int64_t)s[t] * K + (k + 1) % K] += v;"),
-    "transport_transposed_bins": ("double v = g->O[i * K + k];", "double v = g->O[i * K + (K - 1 - k)];"),
-    "no_split_over_neighbours": ("g->O[j * K + k] = out / (double)mm;", "g->O[j * K + k] = out;"),
+    "transport_transposed_bins": ("\n            double v = g->O[i * K + k];",
+                                  "\n            double v = g->O[i * K + (K - 1 - k)];"),
+    "no_split_over_neighbours": ("{\n                g->O[j * K + k] = out / (double)mm;",
+                                 "{\n                g->O[j * K + k] = out;"),
     "source_not_split": ("double share = E / (double)deg;", "double share = E;"),
     "path_length_sum_not_mean": ("kappa * (sum / (double)deg)", "kappa * sum"),
     "optical_depth_without_sigma": ("g->tau[i] = (g->nH[i] * sigma) * g->dL[i];",
                                     "g->tau[i] = g->nH[i] * g->dL[i];"),
-    "escape_lost": ("g->escaped += out;", "g->escaped += 0.0 * out;"),
+    "escape_lost": ("g->escaped += out;\n                g->O[j * K + k] = 0.0;",
+                    "g->escaped += 0.0 * out;\n                g->O[j * K + k] = 0.0;"),
     "ballistic_not_reversed": ("double u[3] = {-g->edir[3 * e + 0], -g->edir[3 * e + 1],",
                                "double u[3] = {g->edir[3 * e + 0], g->edir[3 * e + 1],"),
     "mode_ignores_neutral_fraction": ("(g->y[j] * g->tau[j] >= g->tau_switch)",
@@ -41,10 +44,12 @@ MUTANTS = {
     "ballistic_conversion_first_bin": ("deliver(g, e, g->ebin[e], v);", "deliver(g, e, 0, v);"),
     "ballistic_not_split": ("if (g->bm[e] > 0) g->Oe[e] = out / (double)g->bm[e];",
                             "if (g->bm[e] > 0) g->Oe[e] = out;"),
+    "ballistic_escape_lost": ("g->Oe[e] = out / (double)g->bm[e];\n                else g->escaped += out;",
+                              "g->Oe[e] = out / (double)g->bm[e];\n                else g->escaped += 0.0 * out;"),
     "filed_at_sender_slot": ("g->Ie[g->ptr[j] + g->rev[e]] += v;", "g->Ie[e] += v;"),
     "in_flight_skips_edges": ("f += g->Oe[e] * (double)g->bm[e];", "f += 0.0 * g->Oe[e];"),
-    "nin_skips_first_bin": ("for (int64_t k = 0; k < K; k++) nin += g->I[j * K + k];",
-                            "for (int64_t k = 1; k < K; k++) nin += g->I[j * K + k];"),
+    "nin_skips_first_bin": ("\n        for (int64_t k = 0; k < K; k++) nin += g->I[j * K + k];",
+                            "\n        for (int64_t k = 1; k < K; k++) nin += g->I[j * K + k];"),
 }
 
 
