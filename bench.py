@@ -236,6 +236,48 @@ def rotation_leg(ctx, w, every: int, log):
     return res
 
 
+def combined_leg(ctx, w, tau_switch: float, log, prof):
+    """The same Stromgren solve with combined transport: ballistic where the
+    optical depth is at least tau_switch, direction-conserving elsewhere.
+    Throughput in the headline's units (N K per step, the same problem),
+    the combined sweep kernel's average time, the share of vertices left
+    ballistic, the front radius against the analytic law."""
+    import numpy as np
+    from paper_0912_4273_amd import gridgen as G
+    wc = G.with_(w, transport=G.SX_TRANSPORT_COMBINED, tau_switch=tau_switch)
+    t0 = time.perf_counter()
+    gid = ctx.upload(wc)
+    up = time.perf_counter() - t0
+    ctx.solve([gid], 20)           # warm-up: plan, graph, caches
+    ctx.reset(gid)
+    ctx.sync()
+    prof(True)
+    t0 = time.perf_counter()
+    ctx.step([gid], w.n_sweeps)
+    st = ctx.state(gid, nin=False)
+    el = time.perf_counter() - t0
+    pr = prof(False)
+    lay = ctx.edge_state(gid)["layout"]
+    ctx.free(gid)
+    r_s = (3 * w.meta["rate"] / (4 * math.pi * w.alpha_B * w.meta["n_H"] ** 2)) ** (1 / 3)
+    t_rec = 1.0 / (w.alpha_B * w.meta["n_H"])
+    rv = (3 / (4 * math.pi) * float(np.sum(w.volume * st["x"]))) ** (1 / 3)
+    tl = st["tallies"]
+    res = dict(value=w.n * w.k * w.n_sweeps / el, unit="vertex·direction updates/s",
+               tau_switch=tau_switch, ms_per_solve=1e3 * el, upload_s=round(up, 2),
+               sweep_kernel_us=1e3 * pr["total_ms"] / max(pr["launches"], 1),
+               ballistic_fraction_end=round(float(lay.mean()), 4),
+               front_radius_over_analytic=round(
+                   rv / (r_s * (1 - math.exp(-w.n_sweeps * w.dt / t_rec)) ** (1 / 3)), 4),
+               conservation_residual=abs(tl["emitted"] - tl["absorbed"] - tl["escaped"]
+                                         - tl["in_flight"]) / tl["emitted"])
+    log(f"combined transport (switch {tau_switch}): {res['value']:.3e} updates/s, "
+        f"{res['ms_per_solve']:.1f} ms/solve, sweep {res['sweep_kernel_us']:.1f} us, "
+        f"ballistic at end {res['ballistic_fraction_end']}, front/analytic "
+        f"{res['front_radius_over_analytic']}")
+    return res
+
+
 def cpu_baseline(w, sweeps: int):
     """The FP64 oracle (single thread) on the same grid, from the initial
     state, for a bounded number of sweeps."""
@@ -283,6 +325,8 @@ def main():
     ap.add_argument("--rotate-every", type=int, default=1,
                     help="sweeps between random rotations of the bins in the rotation leg "
                          "(0 = skip the leg)")
+    ap.add_argument("--combined-tau", type=float, default=1.0,
+                    help="switch of the combined-transport leg (negative: skip the leg)")
     ap.add_argument("--graph-sweeps", type=int, default=50,
                     help="sweeps per replayed HIP graph (0: one launch per sweep)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -451,16 +495,21 @@ def main():
     if args.rotate_every > 0:
         rotated = rotation_leg(ctx, w, args.rotate_every, log)
 
+    def prof(on):
+        if on:
+            ctx.profile(True)
+            ctx.profile_read()
+            return None
+        r = ctx.profile_read()
+        ctx.profile(False)
+        return r
+
+    combined = None
+    if args.combined_tau >= 0:
+        combined = combined_leg(ctx, w, args.combined_tau, log, prof)
+
     shadowed = None
     if shadow is not None:
-        def prof(on):
-            if on:
-                ctx.profile(True)
-                ctx.profile_read()
-                return None
-            r = ctx.profile_read()
-            ctx.profile(False)
-            return r
         shadowed = shadow_leg(ctx, shadow, log, prof)
 
     if pool:
@@ -524,6 +573,7 @@ def main():
         "served": served,
         "shadow": shadowed,
         "rotated": rotated,
+        "combined": combined,
         "upload_s": up_s,
         "sweep_kernel_us": 1e3 * kern_ms,
         "roofline": roof,

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define SX_ABI_VERSION 1
+#define SX_ABI_VERSION 2
 
 /* ---- return codes ---------------------------------------------------- */
 #define SX_OK 0
@@ -61,6 +61,22 @@ extern "C" {
 #define SX_MAX_BINS_FP64 96   /* K <= 96  in SX_FP64                       */
 #define SX_MAX_DEGREE 127     /* Delaunay degree of any vertex             */
 #define SX_MAX_PER_BIN 3      /* neighbours per bin (the paper's p = d = 3) */
+
+/* Transport modes (Sect. 2.2).  SX_TRANSPORT_DCT: direction-conserving
+ * transport everywhere (Sect. 2.2.3).  SX_TRANSPORT_COMBINED: combined
+ * transport (Sect. 2.2.4): at the start of every step each vertex whose
+ * optical depth y tau (tau = n_H sigma dL, y its neutral fraction then) is
+ * at least tau_switch uses ballistic transport (Sect. 2.2.2): it holds the
+ * photons it received per incoming edge and sends each packet on, split
+ * equally, to the <= max_per_bin neighbours most aligned with the edge it
+ * came along (cosine > cos_min, ties to the lower id, like the bins).  The
+ * other vertices use direction-conserving transport.  Photons reaching a
+ * ballistic vertex are filed under the edge they came along; photons sent by
+ * a ballistic vertex or a source to a direction-conserving one are filed in
+ * the bin of the edge.  tau_switch <= 0 makes every vertex ballistic; the
+ * paper uses 1. */
+#define SX_TRANSPORT_DCT 0
+#define SX_TRANSPORT_COMBINED 1
 
 typedef struct sx_ctx sx_ctx;
 typedef int64_t sx_grid_id;
@@ -109,7 +125,10 @@ typedef struct sx_grid_desc {
     double alpha_B;              /* case-B recombination coefficient         */
     double dt;                   /* radiative-transfer time step (s)         */
     int32_t precision;           /* SX_FP64 or SX_FP32_TRANSPORT             */
-    int32_t reserved1;
+    int32_t transport;           /* SX_TRANSPORT_DCT (0) or _COMBINED        */
+    double tau_switch;           /* combined transport: ballistic where
+                                    y tau >= tau_switch (not NaN; +inf =
+                                    never)                                   */
 } sx_grid_desc;
 
 /* Cumulative photon accounting of one grid (photons, double). */
@@ -235,8 +254,36 @@ int sx_profile_read(sx_ctx *ctx, int64_t *launches, double *total_ms,
  * the bin's new direction (unchanged where their number is the same), and
  * escapes where none is selected (tallied as escaped).  sx_grid_reset
  * restores the given bins.  Synchronous.  Errors: SX_EINVAL (not a
- * rotation), SX_ENOTFOUND, SX_ENOMEM, SX_EDEVICE. */
+ * rotation), SX_ENOTSUP (a combined-transport grid), SX_ENOTFOUND,
+ * SX_ENOMEM, SX_EDEVICE. */
 int sx_rotate_bins(sx_ctx *ctx, sx_grid_id id, const double *R);
+
+/* ---- combined transport -------------------------------------------------
+ * Per-edge state of a grid uploaded with SX_TRANSPORT_COMBINED (host
+ * memory, caller-owned, nullable):
+ *   photons_e [E] for edge slot p of vertex j (caller's CSR order, the edge
+ *             j -> nbr_idx[p]): photons each chosen neighbour of j receives
+ *             at the next step from the packet that came into j along that
+ *             edge (ballistic vertices; 0 elsewhere)
+ *   layout    [N] 1 where the vertex holds its photons per incoming edge
+ *             (it was ballistic in the last step), 0 where it holds bins;
+ *             sx_read_state reports 0 photons in the bins of layout-1
+ *             vertices.
+ * Synchronous.  Errors: SX_ENOTFOUND, SX_EINVAL (not a combined grid). */
+int sx_read_edge_state(sx_ctx *ctx, sx_grid_id id, double *photons_e,
+                       uint8_t *layout);
+
+/* Checkpoint restore of the per-edge state in the layout above (after
+ * sx_grid_restore, which restores y, bins and tallies and leaves every
+ * vertex holding bins).  Synchronous.  Errors: SX_EINVAL (not a combined
+ * grid, negative or non-finite photons, layout not 0/1), SX_ENOTFOUND. */
+int sx_grid_restore_edges(sx_ctx *ctx, sx_grid_id id, const double *photons_e,
+                          const uint8_t *layout);
+
+/* Ballistic tables in the caller's order (nullable): bsel [E*3] the
+ * neighbour ids chosen for the packet that arrives along each edge slot
+ * (best first, -1 padding), bm [E] how many.  Errors as above. */
+int sx_read_ballistic(sx_ctx *ctx, sx_grid_id id, int32_t *bsel, int32_t *bm);
 
 /* ---- upload in two parts ---------------------------------------------
  * sx_grid_upload = sx_grid_prepare + sx_grid_commit.  The host part (all

@@ -58,6 +58,8 @@ struct Grid {
   bool rotated = false;
   bool ebin_stale = false;
   std::vector<uint8_t> tile_direct;
+  std::vector<int32_t> bsel_h;   // combined transport: [3E] chosen out-edges per in-edge, -1 pad
+  std::vector<uint8_t> bm_h;     // [E]
 };
 
 // How the sweeps of one list of grids are launched: one kernel launch per
@@ -256,6 +258,10 @@ int validate(sx_ctx *ctx, const sx_grid_desc *d) {
     return fail(ctx, SX_EINVAL, "required array is NULL");
   if (d->precision != SX_FP64 && d->precision != SX_FP32_TRANSPORT)
     return fail(ctx, SX_EINVAL, "precision must be SX_FP64 or SX_FP32_TRANSPORT");
+  if (d->transport != SX_TRANSPORT_DCT && d->transport != SX_TRANSPORT_COMBINED)
+    return fail(ctx, SX_EINVAL, "transport must be SX_TRANSPORT_DCT or SX_TRANSPORT_COMBINED");
+  if (d->transport == SX_TRANSPORT_COMBINED && std::isnan(d->tau_switch))
+    return fail(ctx, SX_EINVAL, "tau_switch is NaN");
   const int K = d->n_bins;
   if (K < 1) return fail(ctx, SX_EINVAL, "n_bins must be >= 1");
   if (K > (d->precision == SX_FP64 ? SX_MAX_BINS_FP64 : SX_MAX_BINS_FP32))
@@ -344,6 +350,7 @@ int validate(sx_ctx *ctx, const sx_grid_desc *d) {
 
 struct Sizes {
   int64_t n, npad, ntiles, E, K, kw, sp, bb, kb;
+  int32_t transport, mpb;
 };
 
 Sizes sizes_of(const sx_grid_desc *d) {
@@ -357,6 +364,8 @@ Sizes sizes_of(const sx_grid_desc *d) {
   s.sp = d->precision == SX_FP64 ? 8 : 4;
   s.bb = sx::kBlockBytes / s.sp;
   s.kb = (s.K + s.bb - 1) / s.bb;
+  s.transport = d->transport;
+  s.mpb = d->max_per_bin;
   return s;
 }
 
@@ -373,6 +382,13 @@ uint64_t bytes_estimate(const Sizes &s, int64_t n_em, int64_t n_rec, int64_t n_h
   b += 2 * rnd((uint64_t)sx::kBlockBytes * s.kb * (s.npad + sx::kTile));
   b += 2 * rnd((uint64_t)s.sp * (s.npad + sx::kTile));
   b += rnd(24 * s.ntiles);
+  if (s.transport == SX_TRANSPORT_COMBINED) {
+    // bin lists (at most mpb entries per (vertex, bin)), ballistic lists
+    // (at most mpb per edge), counts, per-edge photons, layouts
+    b += 2 * rnd(4 * (s.E + 1)) + rnd((uint64_t)s.mpb * s.npad * s.K) +
+         rnd((uint64_t)s.mpb * s.E) + rnd(s.E) + 2 * rnd((uint64_t)s.sp * s.E) +
+         2 * rnd(s.npad);
+  }
   return b;
 }
 
@@ -459,6 +475,10 @@ struct sx_prepared {
   std::vector<double> tau, dtnhv, bco, y0;
   std::vector<int32_t> em_ptr, em_k, em_edge;
   std::vector<double> em_amt;
+  int32_t transport = 0;
+  double tau_switch = 0.0;
+  std::vector<int32_t> bl_ptr;   // combined transport: ballistic lists by in-edge
+  std::vector<uint8_t> bl;
   ~sx_prepared() { delete g; }
 };
 
@@ -643,6 +663,28 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
     }
     return best;
   };
+  // The <= mpb edges of v's row most aligned with direction u, cosine >
+  // cos_min, ties to the lower original id (rows are in original-id order):
+  // the rule of the bins, used for beams and for ballistic transport.
+  auto pick = [&](int64_t v, const double *u, int32_t *sl) -> int {
+    double cs[3];
+    int cnt = 0;
+    for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) {
+      const double *ed = &edir[(size_t)(3 * e)];
+      const double a = ed[0] * u[0], b = ed[1] * u[1], c3 = ed[2] * u[2];
+      const double c = (a + b) + c3;
+      if (!(c > d->cos_min)) continue;
+      int pos = cnt < d->max_per_bin ? cnt : d->max_per_bin;
+      while (pos > 0 && c > cs[pos - 1]) --pos;
+      if (pos >= d->max_per_bin) continue;
+      const int last = cnt < d->max_per_bin ? cnt : d->max_per_bin - 1;
+      for (int q = last; q > pos; --q) { cs[q] = cs[q - 1]; sl[q] = sl[q - 1]; }
+      cs[pos] = c;
+      sl[pos] = e;
+      if (cnt < d->max_per_bin) ++cnt;
+    }
+    return cnt;
+  };
   struct Em {
     int32_t recv;
     int32_t k;
@@ -666,25 +708,9 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
         em.push_back({g->nbr_h[(size_t)e], edge_bin(e), share, e});
       }
     } else {
-      // beam: the <= mpb neighbours most aligned with u, cosine > cos_min,
-      // ties to the lower original id (rows are in original-id order)
+      // beam: the <= mpb neighbours most aligned with u
       int32_t sl[3];
-      double cs[3];
-      int cnt = 0;
-      for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) {
-        const double *ed = &edir[(size_t)(3 * e)];
-        const double a = ed[0] * u[0], b = ed[1] * u[1], c3 = ed[2] * u[2];
-        const double c = (a + b) + c3;
-        if (!(c > d->cos_min)) continue;
-        int pos = cnt < d->max_per_bin ? cnt : d->max_per_bin;
-        while (pos > 0 && c > cs[pos - 1]) --pos;
-        if (pos >= d->max_per_bin) continue;
-        const int last = cnt < d->max_per_bin ? cnt : d->max_per_bin - 1;
-        for (int q = last; q > pos; --q) { cs[q] = cs[q - 1]; sl[q] = sl[q - 1]; }
-        cs[pos] = c;
-        sl[pos] = e;
-        if (cnt < d->max_per_bin) ++cnt;
-      }
+      const int cnt = pick(v, u, sl);
       if (cnt == 0) { esc_emit += Es; continue; }
       const double share = (Es / unit) / (double)cnt;
       for (int q = 0; q < cnt; ++q)
@@ -711,6 +737,45 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
   }
   for (int64_t v = 0; v < npad; ++v) em_ptr[(size_t)v + 1] += em_ptr[(size_t)v];
   g->n_em = (int64_t)em.size();
+
+  // ---- combined transport: ballistic choice for the packet that entered v
+  // along each of its edges (it keeps the direction nbr -> v, the opposite
+  // of the edge's unit vector), and per receiving in-edge the list of the
+  // sender's edges whose packets it gets, ascending
+  P->transport = d->transport;
+  P->tau_switch = d->tau_switch;
+  if (d->transport == SX_TRANSPORT_COMBINED) {
+    g->bsel_h.assign((size_t)(3 * E), -1);
+    g->bm_h.assign((size_t)E, 0);
+    std::vector<int32_t> &blp = P->bl_ptr;
+    blp.assign((size_t)E + 1, 0);
+    for (int64_t v = 0; v < n; ++v)
+      for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) {
+        const double u[3] = {-edir[(size_t)(3 * e)], -edir[(size_t)(3 * e + 1)],
+                             -edir[(size_t)(3 * e + 2)]};
+        int32_t sl[3];
+        const int cnt = pick(v, u, sl);
+        g->bm_h[(size_t)e] = (uint8_t)cnt;
+        for (int q = 0; q < cnt; ++q) {
+          g->bsel_h[(size_t)(3 * e + q)] = sl[q];
+          const int32_t l = g->nbr_h[(size_t)sl[q]];
+          blp[(size_t)(rp[(size_t)l] + rev[(size_t)sl[q]]) + 1]++;
+        }
+      }
+    int64_t tot = 0;
+    for (int64_t e = 0; e < E; ++e) tot += blp[(size_t)e + 1];
+    if (tot >= INT32_MAX) return fail(ctx, SX_ENOTSUP, "too many ballistic routes");
+    for (int64_t e = 0; e < E; ++e) blp[(size_t)e + 1] += blp[(size_t)e];
+    std::vector<int32_t> fillp(blp.begin(), blp.end() - 1);
+    P->bl.assign((size_t)blp[(size_t)E], 0);
+    for (int64_t v = 0; v < n; ++v)
+      for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e)
+        for (int q = 0; q < g->bm_h[(size_t)e]; ++q) {
+          const int32_t f = g->bsel_h[(size_t)(3 * e + q)];
+          const int32_t in = rp[(size_t)g->nbr_h[(size_t)f]] + rev[(size_t)f];
+          P->bl[(size_t)fillp[(size_t)in]++] = (uint8_t)(e - rp[(size_t)v]);
+        }
+  }
   return SX_OK;
 }
 
@@ -758,6 +823,8 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   h.cos_min = P->cos_min;
   h.plane = npad + sx::kTile;   // the extra tile stays zero
   h.n_edges = E;
+  h.transport = P->transport;
+  h.tau_switch = P->transport == SX_TRANSPORT_COMBINED ? P->tau_switch : 0.0;
   int32_t *d_rp, *d_nbr, *d_rec_cnt, *d_rec_ptr, *d_hptr, *d_hvid;
   uint8_t *d_rev, *d_ebin, *d_tdir;
   uint16_t *d_ehidx;
@@ -920,6 +987,69 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
   if ((he = sx::launch_inlist_fill(dg, h, st)) != hipSuccess) return kfail(he);
 
+  if (P->transport == SX_TRANSPORT_COMBINED) {
+    // per receiving in-edge, the sender's bins whose selection holds the
+    // receiver (from the device selection), ascending
+    std::vector<uint32_t> f((size_t)(npad * K));
+    if ((he = hipMemcpyAsync(f.data(), h.fwd, 4 * npad * K, hipMemcpyDeviceToHost, st)) != hipSuccess)
+      return kfail(he);
+    if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
+    std::vector<int32_t> klp((size_t)E + 1, 0);
+    const std::vector<int32_t> &nb = g->nbr_h;
+    for (int64_t v = 0; v < n; ++v)
+      for (int64_t k = 0; k < K; ++k) {
+        const uint32_t w = f[(size_t)(v * K + k)];
+        for (uint32_t q = 0; q < ((w >> 21) & 3u); ++q) {
+          const int32_t eo = rp[(size_t)v] + (int32_t)((w >> (7 * q)) & 127u);
+          klp[(size_t)(rp[(size_t)nb[(size_t)eo]] + P->rev[(size_t)eo]) + 1]++;
+        }
+      }
+    int64_t tot = 0;
+    for (int64_t e = 0; e < E; ++e) tot += klp[(size_t)e + 1];
+    if (tot >= INT32_MAX) {
+      grid_release(ctx, g);
+      return fail(ctx, SX_ENOTSUP, "too many (vertex, bin) routes for combined transport");
+    }
+    for (int64_t e = 0; e < E; ++e) klp[(size_t)e + 1] += klp[(size_t)e];
+    std::vector<int32_t> fillp(klp.begin(), klp.end() - 1);
+    std::vector<uint8_t> kl((size_t)klp[(size_t)E]);
+    for (int64_t v = 0; v < n; ++v)
+      for (int64_t k = 0; k < K; ++k) {
+        const uint32_t w = f[(size_t)(v * K + k)];
+        for (uint32_t q = 0; q < ((w >> 21) & 3u); ++q) {
+          const int32_t eo = rp[(size_t)v] + (int32_t)((w >> (7 * q)) & 127u);
+          const int32_t in = rp[(size_t)nb[(size_t)eo]] + P->rev[(size_t)eo];
+          kl[(size_t)fillp[(size_t)in]++] = (uint8_t)k;
+        }
+      }
+    int32_t *d_klp, *d_blp;
+    uint8_t *d_kl, *d_bl, *d_bm, *d_l0, *d_l1, *d_e0, *d_e1;
+    GA(d_klp, E + 1);
+    GA(d_kl, kl.size() + 1);
+    GA(d_blp, E + 1);
+    GA(d_bl, P->bl.size() + 1);
+    GA(d_bm, E + 1);
+    GA(d_e0, (uint64_t)S.sp * (E + 1));
+    GA(d_e1, (uint64_t)S.sp * (E + 1));
+    GA(d_l0, npad);
+    GA(d_l1, npad);
+    UP(d_klp, klp.data(), 4 * (E + 1));
+    UP(d_kl, kl.data(), kl.size());
+    UP(d_blp, P->bl_ptr.data(), 4 * (E + 1));
+    UP(d_bl, P->bl.data(), P->bl.size());
+    UP(d_bm, g->bm_h.data(), E);
+    if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
+    h.kl_ptr = d_klp;
+    h.kl = d_kl;
+    h.bl_ptr = d_blp;
+    h.bl = d_bl;
+    h.bm = d_bm;
+    h.oe[0] = d_e0;
+    h.oe[1] = d_e1;
+    h.lay[0] = d_l0;
+    h.lay[1] = d_l1;
+  }
+
 #undef GA
 #undef UP
   if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
@@ -933,6 +1063,25 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
 }
 
 }  // namespace
+
+// Combined-transport grid by id, or an error code.
+static int combined_grid(sx_ctx *ctx, sx_grid_id id, Grid **out) {
+  if (!ctx) return SX_EINVAL;
+  if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
+  Grid *g = find(ctx, id);
+  if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
+  if (g->hg.transport != SX_TRANSPORT_COMBINED)
+    return fail(ctx, SX_EINVAL, "grid %lld does not use combined transport", (long long)id);
+  *out = g;
+  return SX_OK;
+}
+
+// new edge -> caller's CSR position
+static std::vector<int32_t> new_to_orig_edges(const Grid *g) {
+  std::vector<int32_t> m(g->orig_to_new_e.size());
+  for (size_t p = 0; p < m.size(); ++p) m[(size_t)g->orig_to_new_e[p]] = (int32_t)p;
+  return m;
+}
 
 // =================================================================== ABI ==
 extern "C" {
@@ -1106,6 +1255,8 @@ int sx_rotate_bins(sx_ctx *ctx, sx_grid_id id, const double *R) {
   if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
   Grid *g = find(ctx, id);
   if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
+  if (g->hg.transport != SX_TRANSPORT_DCT)
+    return fail(ctx, SX_ENOTSUP, "rotating the bins of a combined-transport grid");
   if (!R) return fail(ctx, SX_EINVAL, "null rotation");
   // a rotation: orthonormal rows, determinant +1
   for (int i = 0; i < 9; ++i)
@@ -1169,20 +1320,23 @@ void plan_unbuild(Plan *p) {
 }
 
 // Lay out the launches of one sweep for `gs` under p->sched: one launch per
-// precision present (grids in the caller's order), tiles grid by grid in
+// precision and transport mode present (grids in the caller's order), tiles grid by grid in
 // each grid's (Hilbert) order, or the directly gathering tiles first.
 int plan_build(sx_ctx *ctx, Plan *p, const std::vector<Grid *> &gs) {
   plan_unbuild(p);
-  for (int prec : {SX_FP64, SX_FP32_TRANSPORT}) {
+  for (int cls = 0; cls < 4; ++cls) {
+    const int prec = cls & 1 ? SX_FP32_TRANSPORT : SX_FP64;
+    const int tr = cls >> 1;
     std::vector<Grid *> grp;
     for (Grid *g : gs)
-      if (g->hg.precision == prec) grp.push_back(g);
+      if (g->hg.precision == prec && g->hg.transport == tr) grp.push_back(g);
     if (grp.empty()) continue;
     sx::SweepLaunch l{};
     l.done = ctx->done;
-    l.tpb = p->sched.tiles_per_group;
+    l.tpb = tr ? 1 : p->sched.tiles_per_group;
     l.xcd_remap = p->sched.xcd_contiguous;
     l.precision = prec;
+    l.transport = tr;
     const bool any_direct = std::any_of(grp.begin(), grp.end(),
                                         [](Grid *g) { return g->n_direct > 0; });
     const bool reorder = p->sched.order == SX_ORDER_DIRECT_FIRST && any_direct;
@@ -1578,6 +1732,13 @@ int sx_read_state(sx_ctx *ctx, sx_grid_id id, const sx_state_out *out) {
     const void *src = h.o[cur.parity];
     const void *tsrc = h.t[cur.parity];
     const int64_t pl = h.plane;
+    // combined transport: vertices holding edges have no photons in bins
+    std::vector<uint8_t> lay;
+    if (h.transport != SX_TRANSPORT_DCT) {
+      lay.resize((size_t)npad);
+      HIP_TRY(ctx, hipMemcpyAsync(lay.data(), h.lay[cur.parity], npad, hipMemcpyDeviceToHost, st));
+    }
+    auto held = [&](int64_t v) { return lay.empty() || lay[(size_t)v] == 0; };
     if (h.precision == SX_FP64) {
       std::vector<double> o((size_t)words), t((size_t)pl);
       HIP_TRY(ctx, hipMemcpyAsync(o.data(), src, 8 * words, hipMemcpyDeviceToHost, st));
@@ -1586,7 +1747,7 @@ int sx_read_state(sx_ctx *ctx, sx_grid_id id, const sx_state_out *out) {
       for (int64_t i = 0; i < n; ++i) {
         const int64_t v = g->inv[(size_t)i];
         for (int64_t k = 0; k < K; ++k)
-          out->photons[i * K + k] = (o[(size_t)at(v, k)] * t[(size_t)v]) * h.unit;
+          out->photons[i * K + k] = held(v) ? (o[(size_t)at(v, k)] * t[(size_t)v]) * h.unit : 0.0;
       }
     } else {
       std::vector<float> o((size_t)words), t((size_t)pl);
@@ -1597,7 +1758,7 @@ int sx_read_state(sx_ctx *ctx, sx_grid_id id, const sx_state_out *out) {
         const int64_t v = g->inv[(size_t)i];
         for (int64_t k = 0; k < K; ++k) {
           const float ov = o[(size_t)at(v, k)] * t[(size_t)v];
-          out->photons[i * K + k] = (double)ov * h.unit;
+          out->photons[i * K + k] = held(v) ? (double)ov * h.unit : 0.0;
         }
       }
     }
@@ -1671,6 +1832,10 @@ int sx_grid_restore(sx_ctx *ctx, sx_grid_id id, const sx_state_in *in) {
       HIP_TRY(ctx, hipMemcpy(dst, o.data(), 4 * words, hipMemcpyHostToDevice));
       HIP_TRY(ctx, hipMemcpy(tdst, t.data(), 4 * pl, hipMemcpyHostToDevice));
     }
+    if (h.transport != SX_TRANSPORT_DCT) {
+      HIP_TRY(ctx, hipMemset(h.lay[cur.parity], 0, npad));
+      HIP_TRY(ctx, hipMemset(h.oe[cur.parity], 0, (size_t)(h.precision == SX_FP64 ? 8 : 4) * h.n_edges));
+    }
   }
   if (in->tally) {
     std::vector<double> t((size_t)(3 * h.ntiles), 0.0);
@@ -1733,6 +1898,112 @@ int sx_read_tables(sx_ctx *ctx, sx_grid_id id, int32_t *sel_nbr, int32_t *sel_m,
       if (dL) dL[i] = g->dL_h[(size_t)v];
       if (tau) tau[i] = g->tau_h[(size_t)v];
     }
+  return SX_OK;
+}
+
+int sx_read_edge_state(sx_ctx *ctx, sx_grid_id id, double *photons_e, uint8_t *layout) {
+  Grid *g = nullptr;
+  int r = combined_grid(ctx, id, &g);
+  if (r) return r;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  const GridDev &h = g->hg;
+  const int64_t n = h.n, npad = h.npad, E = h.n_edges;
+  GridDev cur;
+  HIP_TRY(ctx, hipMemcpyAsync(&cur, ctx->table + g->slot, sizeof cur, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  std::vector<uint8_t> lay((size_t)npad);
+  HIP_TRY(ctx, hipMemcpyAsync(lay.data(), h.lay[cur.parity], npad, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  if (layout)
+    for (int64_t i = 0; i < n; ++i) layout[i] = lay[(size_t)g->inv[(size_t)i]];
+  if (photons_e && E > 0) {
+    // O_e = Ipre_e * T of the holder, in the stored precision
+    const std::vector<int32_t> to_orig = new_to_orig_edges(g);
+    const std::vector<int32_t> &rp = g->row_ptr_h;
+    if (h.precision == SX_FP64) {
+      std::vector<double> o((size_t)E), t((size_t)h.plane);
+      HIP_TRY(ctx, hipMemcpyAsync(o.data(), h.oe[cur.parity], 8 * E, hipMemcpyDeviceToHost, st));
+      HIP_TRY(ctx, hipMemcpyAsync(t.data(), h.t[cur.parity], 8 * h.plane, hipMemcpyDeviceToHost, st));
+      HIP_TRY(ctx, hipStreamSynchronize(st));
+      for (int64_t v = 0; v < n; ++v)
+        for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e)
+          photons_e[to_orig[(size_t)e]] =
+              lay[(size_t)v] ? (o[(size_t)e] * t[(size_t)v]) * h.unit : 0.0;
+    } else {
+      std::vector<float> o((size_t)E), t((size_t)h.plane);
+      HIP_TRY(ctx, hipMemcpyAsync(o.data(), h.oe[cur.parity], 4 * E, hipMemcpyDeviceToHost, st));
+      HIP_TRY(ctx, hipMemcpyAsync(t.data(), h.t[cur.parity], 4 * h.plane, hipMemcpyDeviceToHost, st));
+      HIP_TRY(ctx, hipStreamSynchronize(st));
+      for (int64_t v = 0; v < n; ++v)
+        for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) {
+          const float ov = o[(size_t)e] * t[(size_t)v];
+          photons_e[to_orig[(size_t)e]] = lay[(size_t)v] ? (double)ov * h.unit : 0.0;
+        }
+    }
+  }
+  return SX_OK;
+}
+
+int sx_grid_restore_edges(sx_ctx *ctx, sx_grid_id id, const double *photons_e,
+                          const uint8_t *layout) {
+  Grid *g = nullptr;
+  int r = combined_grid(ctx, id, &g);
+  if (r) return r;
+  if (!layout) return fail(ctx, SX_EINVAL, "layout is NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  const GridDev &h = g->hg;
+  const int64_t n = h.n, npad = h.npad, E = h.n_edges;
+  for (int64_t i = 0; i < n; ++i)
+    if (layout[i] > 1) return fail(ctx, SX_EINVAL, "layout[%lld] is not 0 or 1", (long long)i);
+  if (photons_e)
+    for (int64_t p = 0; p < E; ++p)
+      if (!(photons_e[p] >= 0.0) || !std::isfinite(photons_e[p]))
+        return fail(ctx, SX_EINVAL, "restored photons must be finite and >= 0");
+  GridDev cur;
+  HIP_TRY(ctx, hipMemcpy(&cur, ctx->table + g->slot, sizeof cur, hipMemcpyDeviceToHost));
+  const int par = cur.parity;
+  std::vector<uint8_t> lay((size_t)npad, 0);
+  for (int64_t i = 0; i < n; ++i) lay[(size_t)g->inv[(size_t)i]] = layout[i];
+  const std::vector<int32_t> to_orig = new_to_orig_edges(g);
+  const std::vector<int32_t> &rp = g->row_ptr_h;
+  // the restored packets are the outgoing share itself: Ipre_e = O_e and
+  // T = 1 for the vertices that hold edges (their bins are not read)
+  auto put = [&](auto zero) -> int {
+    using T = decltype(zero);
+    std::vector<T> o((size_t)E, zero), t((size_t)h.plane);
+    HIP_TRY(ctx, hipMemcpy(t.data(), h.t[par], sizeof(T) * h.plane, hipMemcpyDeviceToHost));
+    for (int64_t v = 0; v < n; ++v) {
+      if (!lay[(size_t)v]) continue;
+      t[(size_t)v] = (T)1;
+      for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e)
+        o[(size_t)e] = photons_e ? (T)(photons_e[to_orig[(size_t)e]] / h.unit) : zero;
+    }
+    HIP_TRY(ctx, hipMemcpy(h.oe[par], o.data(), sizeof(T) * E, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(h.t[par], t.data(), sizeof(T) * h.plane, hipMemcpyHostToDevice));
+    return SX_OK;
+  };
+  r = h.precision == SX_FP64 ? put(0.0) : put(0.0f);
+  if (r) return r;
+  HIP_TRY(ctx, hipMemcpy(h.lay[par], lay.data(), npad, hipMemcpyHostToDevice));
+  return SX_OK;
+}
+
+int sx_read_ballistic(sx_ctx *ctx, sx_grid_id id, int32_t *bsel, int32_t *bm) {
+  Grid *g = nullptr;
+  int r = combined_grid(ctx, id, &g);
+  if (r) return r;
+  const int64_t E = g->hg.n_edges;
+  for (int64_t p = 0; p < E; ++p) {
+    const int32_t e = g->orig_to_new_e[(size_t)p];
+    const int m = g->bm_h[(size_t)e];
+    if (bm) bm[p] = m;
+    if (bsel)
+      for (int q = 0; q < 3; ++q)
+        bsel[3 * p + q] = q < m ? g->perm[(size_t)g->nbr_h[(size_t)g->bsel_h[(size_t)(3 * e + q)]]] : -1;
+  }
   return SX_OK;
 }
 

@@ -104,6 +104,18 @@ struct GridDev {
   void *t[2];               // [plane] transmitted fraction T of each vertex
                             // in the step that wrote o[] (fp32 or fp64)
   double *tally;            // [ntiles*3] absorbed (cum), escaped (cum), in flight
+  // combined transport (transport == 1; null otherwise).  Lists are indexed
+  // by the incoming edge e = (row of j, slot s), the sender i = nbr[e]:
+  int32_t transport;        // 0 direction-conserving, 1 combined
+  int32_t pad0;
+  double tau_switch;        // ballistic where y tau >= tau_switch
+  const int32_t *kl_ptr;    // [E+1]
+  const uint8_t *kl;        // bins of i whose selection holds j, ascending
+  const int32_t *bl_ptr;    // [E+1]
+  const uint8_t *bl;        // slots of i whose ballistic packets go to j, ascending
+  const uint8_t *bm;        // [E] neighbours chosen for the packet entering j along e
+  void *oe[2];              // [E] ballistic photons I/bm per incoming edge (fp32 or fp64)
+  uint8_t *lay[2];          // [npad] 1: the vertex held edges in the step that wrote it
 };
 
 // Kernel launchers (sx_kernels.hip).  All enqueue on `stream`, return the
@@ -137,6 +149,7 @@ struct SweepLaunch {
   uint32_t *done;
   int32_t xcd_remap;
   int32_t tpb, precision;
+  int32_t transport;
 };
 hipError_t launch_sweep(const SweepLaunch &l, hipStream_t s);
 hipError_t add_sweep_node(hipGraph_t graph, const SweepLaunch &l, hipGraphNode_t *prev);

@@ -743,6 +743,205 @@ __global__ __launch_bounds__(64 * TPB, 4) void k_sweep(
   if (threadIdx.x == 0) atomicExch(done, 0u);
 }
 
+// ------------------------------------------------- combined transport ---
+// One step of combined transport (Sects. 2.2.2-2.2.4) for one tile; lane =
+// receiver j.  j is ballistic in this step when its optical depth y tau at
+// the start of the step is at least tau_switch.  Each sender i holds what it
+// received in the previous step either per bin (layout 0: Ipre = I/m in
+// o[], as in direction-conserving transport) or per incoming edge (layout 1:
+// Ipre = I/bm in oe[]), and passes on Ipre * T_i.  j walks its incoming
+// edges once, in ascending original sender id:
+//  - a sender holding bins sends the bins whose selection holds j (kl), each
+//    in its own bin;
+//  - a sender holding edges sends the packets whose ballistic choice holds j
+//    (bl), in the bin of the edge i -> j;
+//  - source shares arrive along the edge from the source, in that edge's bin.
+// A ballistic j adds up what came along each edge and stores I / bm for
+// that edge at once; a direction-conserving j adds into its bins (an LDS
+// column per lane) and stores I / m per bin after the walk.  Chemistry and
+// accounting as in direction-conserving transport.
+constexpr int kMaxBinsCt = 96;
+
+template <typename P>
+__device__ __forceinline__ P div_m(P v, uint32_t m) {
+  if constexpr (sizeof(P) == 8) {
+    return m == 0u ? 0.0 : (m == 1u ? v : (m == 2u ? v * 0.5 : v / 3.0));
+  } else {
+    const float fm = (float)(int)(m * m - 6u * m + 11u) * (1.0f / 6.0f);
+    return m == 0u ? 0.0f : v * fm;
+  }
+}
+
+template <typename P>
+__device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int tile,
+                                              int lane, SX_L P *acc) {
+  constexpr int BB = kBlockBytes / sizeof(P);
+  typedef P V __attribute__((ext_vector_type(BB)));
+  const int K = G->k;
+  const int KB = G->kb;
+  const int j = tile * kTile + lane;
+  const bool valid = j < G->n;
+  const int par = G->parity;
+  const SX_G P *__restrict__ oin = gld((const P *)G->o[par]);
+  SX_G V *__restrict__ oout = gst((V *)G->o[par ^ 1]);
+  const SX_G P *__restrict__ tin = gld((const P *)G->t[par]);
+  const SX_G P *__restrict__ ein = gld((const P *)G->oe[par]);
+  SX_G P *__restrict__ eout = gst((P *)G->oe[par ^ 1]);
+  const SX_G uint8_t *__restrict__ lin = gld((const uint8_t *)G->lay[par]);
+  const SX_G int32_t *__restrict__ rowp = gld(G->row_ptr);
+  const SX_G int32_t *__restrict__ nbr = gld(G->nbr);
+  const SX_G uint8_t *__restrict__ rev = gld(G->rev);
+  const SX_G uint8_t *__restrict__ ebin = gld((const uint8_t *)G->ebin);
+  const SX_G int32_t *__restrict__ klp = gld(G->kl_ptr);
+  const SX_G uint8_t *__restrict__ kl = gld(G->kl);
+  const SX_G int32_t *__restrict__ blp = gld(G->bl_ptr);
+  const SX_G uint8_t *__restrict__ bl = gld(G->bl);
+  const SX_G uint8_t *__restrict__ bmv = gld(G->bm);
+  const SX_G int32_t *__restrict__ emp = gld(G->em_ptr);
+  const SX_G double *__restrict__ ema = gld(G->em_amt);
+  const SX_G int32_t *__restrict__ eme = gld(G->em_edge);
+  const SX_G int32_t *__restrict__ emk = gld((const int32_t *)G->em_k);
+  // element (v, k) of the bin field
+  auto at = [&](uint32_t v, int k) -> uint32_t {
+    return (((v >> 6) * (uint32_t)KB + (uint32_t)(k / BB)) * 64u + (v & 63u)) * BB +
+           (uint32_t)(k % BB);
+  };
+
+  double y0 = 1.0;
+  bool bal = false;
+  if (valid) {
+    y0 = gld(G->y)[j];
+    bal = y0 * gld(G->tau)[j] >= G->tau_switch;
+  }
+  P nin_p = P(0), esc_p = P(0);
+  if (valid) {
+    if (!bal)
+      for (int k = 0; k < K; ++k) acc[k * kTile + lane] = P(0);
+    const int rb = rowp[j], re = rowp[j + 1];
+    const int e0 = emp[j], e1 = emp[j + 1];
+    for (int e = rb; e < re; ++e) {
+      const int i = nbr[e];
+      const P ti = tin[i];
+      P ve = P(0);
+      if (lin[i] == 0) {
+        const int q1 = klp[e + 1];
+        for (int q = klp[e]; q < q1; ++q) {
+          const int k = kl[q];
+          const P v = mul_rn(oin[at((uint32_t)i, k)], ti);
+          if (bal) ve += v;
+          else acc[k * kTile + lane] += v;
+        }
+      } else {
+        const int ib = rowp[i];
+        const int kb = ebin[ib + rev[e]];
+        const int q1 = blp[e + 1];
+        for (int q = blp[e]; q < q1; ++q) {
+          const P v = mul_rn(ein[ib + bl[q]], ti);
+          if (bal) ve += v;
+          else acc[kb * kTile + lane] += v;
+        }
+      }
+      if (bal) {
+        for (int q = e0; q < e1; ++q)
+          if (rb + (int)rev[eme[q]] == e) ve += (P)ema[q];
+        const uint32_t m = bmv[e];
+        eout[e] = div_m(ve, m);
+        nin_p += ve;
+        esc_p += m == 0u ? ve : P(0);
+      }
+    }
+    if (!bal) {
+      for (int q = e0; q < e1; ++q) acc[emk[q] * kTile + lane] += (P)ema[q];
+      const SX_G uint32_t *__restrict__ mbp =
+          gld(G->mbits) + (int64_t)tile * G->kw * 64 + lane;
+      for (int kb = 0; kb < KB; ++kb) {
+        V out;
+#pragma unroll
+        for (int b = 0; b < BB; ++b) {
+          const int k = kb * BB + b;
+          P ipre = P(0);
+          if (k < K) {
+            const uint32_t m = (mbp[(k >> 4) * 64] >> (2 * (k & 15))) & 3u;
+            const P I = acc[k * kTile + lane];
+            nin_p += I;
+            esc_p += m == 0u ? I : P(0);
+            ipre = div_m(I, m);
+          }
+          out[b] = ipre;
+        }
+        oout[((uint32_t)tile * (uint32_t)KB + (uint32_t)kb) * 64u + (uint32_t)lane] = out;
+      }
+    }
+  }
+
+  double A = 0.0, T = 1.0;
+  const double nin = (double)nin_p;
+  if (valid) {
+    if (!(nin == 0.0 && y0 == 1.0)) {
+      const double yn = chem_step(y0, nin * G->unit, G->dt, gld(G->dtnhv)[j],
+                                  gld(G->tau)[j], gld(G->bcoef)[j], G->n_sub, A, T);
+      gst(G->y)[j] = yn;
+    }
+    gst(G->nin)[j] = nin * G->unit;
+    gst((P *)G->t[par ^ 1])[j] = (P)T;
+    gst(G->lay[par ^ 1])[j] = bal ? 1 : 0;
+  }
+  A /= G->unit;
+  double esc = (double)esc_p * T;
+  double fly = (nin - (double)esc_p) * T;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    A += __shfl_xor(A, off);
+    esc += __shfl_xor(esc, off);
+    fly += __shfl_xor(fly, off);
+  }
+  if (lane == 0) {
+    SX_G double *t = gst(G->tally) + (int64_t)tile * 3;
+    t[0] += A;
+    t[1] += esc;
+    t[2] = fly;
+  }
+}
+
+// One combined-transport step over a tile list: one tile per workgroup of
+// one wave, the same tile lists, XCD numbering and completion as k_sweep.
+template <typename P>
+__global__ __launch_bounds__(64) void k_sweep_ct(
+    GridDev *__restrict__ grids, const int2 *__restrict__ tile_map,
+    int32_t n_tiles, const int32_t *__restrict__ adv, int32_t n_adv,
+    uint32_t *__restrict__ done, int32_t xcd_remap) {
+  __shared__ P acc[kMaxBinsCt * kTile];
+  __shared__ int last;
+  const int lane = threadIdx.x & 63;
+  const uint32_t nb = gridDim.x;   // a multiple of 8
+  const uint32_t b = blockIdx.x;
+  const uint32_t gt = xcd_remap ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
+  if ((int)gt < n_tiles) {
+    int gi = 0, tile = (int)gt;
+    if (tile_map) {
+      const int2 tm = tile_map[gt];
+      gi = __builtin_amdgcn_readfirstlane(tm.x);
+      tile = __builtin_amdgcn_readfirstlane(tm.y);
+    }
+    const GridDev *__restrict__ G = grids + gi;
+    if (G->remaining > 0) sweep_tile_ct<P>(G, tile, lane, (SX_L P *)acc);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    last = atomicAdd(done, 1u) == nb - 1u;
+  __syncthreads();
+  if (!last) return;
+  for (int i = threadIdx.x; i < n_adv; i += 64) {
+    GridDev &g = grids[adv ? adv[i] : i];
+    if (g.remaining > 0) {
+      g.parity ^= 1;
+      g.remaining -= 1;
+      g.sweeps += 1;
+    }
+  }
+  if (threadIdx.x == 0) atomicExch(done, 0u);
+}
+
 struct SlotVals {
   int32_t slot[120];
   int32_t v[120];
@@ -854,6 +1053,14 @@ hipError_t launch_reset_state(GridDev *dg, const GridDev &hg, const double *y0,
   }
   e = fill<double>(hg.tally, 0.0, (int64_t)hg.ntiles * 3, s);
   if (e != hipSuccess) return e;
+  if (hg.transport != 0) {
+    for (int b = 0; b < 2; ++b) {
+      if (hg.precision == 0) e = fill<double>((double *)hg.oe[b], 0.0, hg.n_edges, s);
+      else e = fill<float>((float *)hg.oe[b], 0.0f, hg.n_edges, s);
+      if (e == hipSuccess) e = fill<uint8_t>(hg.lay[b], (uint8_t)0, hg.npad, s);
+      if (e != hipSuccess) return e;
+    }
+  }
   hipLaunchKernelGGL(k_reset, dim3(blocks_for(hg.npad, 256)), dim3(256), 0, s,
                      dg, y0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -873,6 +1080,13 @@ static const void *sweep_fn(int tpb) {
 
 static hipError_t sweep_shape(const SweepLaunch &l, const void **fn, dim3 *grid,
                               dim3 *block) {
+  if (l.transport != 0) {
+    if (l.n_tiles <= 0 || !l.done) return hipErrorInvalidValue;
+    *fn = l.precision == 0 ? (const void *)k_sweep_ct<double> : (const void *)k_sweep_ct<float>;
+    *grid = dim3(((unsigned)l.n_tiles + 7u) & ~7u);
+    *block = dim3(64u);
+    return hipSuccess;
+  }
   const void *f = l.precision == 0 ? sweep_fn<double>(l.tpb) : sweep_fn<float>(l.tpb);
   if (!f || l.n_tiles <= 0 || !l.done) return hipErrorInvalidValue;
   *fn = f;

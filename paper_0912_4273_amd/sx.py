@@ -30,6 +30,8 @@ SX_ORDER_DIRECT_FIRST = 1
 SX_MAX_GRAPH_SWEEPS = 4096
 SX_MAX_BINS = 96
 SX_MAX_DEGREE = 127
+SX_TRANSPORT_DCT = 0
+SX_TRANSPORT_COMBINED = 1
 
 EXPORTED = [
     "sx_init", "sx_finalize", "sx_grid_bytes", "sx_grid_upload",
@@ -37,7 +39,8 @@ EXPORTED = [
     "sx_solve", "sx_sync", "sx_read_state", "sx_read_tables",
     "sx_grid_info", "sx_mem_info", "sx_stream", "sx_profile",
     "sx_profile_read", "sx_set_schedule", "sx_get_schedule", "sx_autotune",
-    "sx_rotate_bins", "sx_grid_prepare", "sx_prepared_bytes", "sx_grid_commit", "sx_prepared_free",
+    "sx_rotate_bins", "sx_read_edge_state", "sx_grid_restore_edges", "sx_read_ballistic",
+    "sx_grid_prepare", "sx_prepared_bytes", "sx_grid_commit", "sx_prepared_free",
     "sx_serve_start", "sx_serve_submit", "sx_serve_poll", "sx_serve_take",
     "sx_serve_stop", "sx_strerror", "sx_last_error",
 ]
@@ -65,7 +68,8 @@ class SxGridDesc(C.Structure):
         ("src_vertex", C.c_void_p), ("src_rate", C.c_void_p),
         ("src_dir", C.c_void_p), ("sigma", C.c_double),
         ("alpha_B", C.c_double), ("dt", C.c_double),
-        ("precision", C.c_int32), ("reserved1", C.c_int32)]
+        ("precision", C.c_int32), ("transport", C.c_int32),
+        ("tau_switch", C.c_double)]
 
 
 class SxTally(C.Structure):
@@ -154,6 +158,9 @@ def load(path: Optional[str] = None):
         "sx_get_schedule": (C.c_int, [P, P, I32, C.POINTER(SxSchedule), P]),
         "sx_autotune": (C.c_int, [P, I32]),
         "sx_rotate_bins": (C.c_int, [P, I64, P]),
+        "sx_read_edge_state": (C.c_int, [P, I64, P, P]),
+        "sx_grid_restore_edges": (C.c_int, [P, I64, P, P]),
+        "sx_read_ballistic": (C.c_int, [P, I64, P, P]),
         "sx_grid_prepare": (C.c_int, [C.POINTER(SxGridDesc), C.POINTER(P), C.c_char_p,
                                       C.c_size_t]),
         "sx_prepared_bytes": (C.c_int, [P, C.POINTER(C.c_uint64)]),
@@ -210,7 +217,8 @@ class _Desc:
             n_subcycles=int(w.n_subcycles), src_vertex=_ptr(a["sv"]),
             src_rate=_ptr(a["sr"]), src_dir=_ptr(a["sd"]), sigma=float(w.sigma),
             alpha_B=float(w.alpha_B), dt=float(w.dt), precision=int(w.precision),
-            reserved1=0)
+            transport=int(getattr(w, "transport", SX_TRANSPORT_DCT)),
+            tau_switch=float(getattr(w, "tau_switch", 1.0)))
 
 
 # ------------------------------------------------------ C entry points ----
@@ -295,6 +303,28 @@ def sx_prepared_free(p) -> None:
 def sx_rotate_bins(ctx, gid: int, R) -> None:
     r = np.ascontiguousarray(np.asarray(R, np.float64).reshape(9))
     _check(ctx, load().sx_rotate_bins(ctx, gid, _ptr(r)))
+
+
+def sx_read_edge_state(ctx, gid: int, n: int, n_edges: int) -> dict:
+    """Combined transport: photons per edge slot [E] (caller's CSR order) and
+    the layout of every vertex [N] (1: it holds edges)."""
+    pe = np.zeros(n_edges)
+    lay = np.zeros(n, np.uint8)
+    _check(ctx, load().sx_read_edge_state(ctx, gid, _ptr(pe), _ptr(lay)))
+    return dict(photons_e=pe, layout=lay)
+
+
+def sx_grid_restore_edges(ctx, gid: int, photons_e, layout) -> None:
+    pe = None if photons_e is None else np.ascontiguousarray(photons_e, np.float64)
+    lay = np.ascontiguousarray(layout, np.uint8)
+    _check(ctx, load().sx_grid_restore_edges(ctx, gid, _ptr(pe), _ptr(lay)))
+
+
+def sx_read_ballistic(ctx, gid: int, n_edges: int) -> dict:
+    sel = np.zeros((n_edges, 3), np.int32)
+    cnt = np.zeros(n_edges, np.int32)
+    _check(ctx, load().sx_read_ballistic(ctx, gid, _ptr(sel), _ptr(cnt)))
+    return dict(bsel=sel, bm=cnt)
 
 
 def sx_grid_reset(ctx, gid: int) -> None:
@@ -512,6 +542,17 @@ class Context:
 
     def restore(self, gid, **kw):
         sx_grid_restore(self.h, gid, **kw)
+
+    def edge_state(self, gid) -> dict:
+        n, _, e = self.shapes[gid]
+        return sx_read_edge_state(self.h, gid, n, e)
+
+    def restore_edges(self, gid, photons_e, layout):
+        sx_grid_restore_edges(self.h, gid, photons_e, layout)
+
+    def ballistic(self, gid) -> dict:
+        _, _, e = self.shapes[gid]
+        return sx_read_ballistic(self.h, gid, e)
 
     def tables(self, gid):
         n, k, e = self.shapes[gid]

@@ -38,3 +38,15 @@ def assert_state_close(got, ref, precision, unit, what=""):
         assert abs(a - b) <= t["tally"] * abs(b) + 1e-12 * scale, \
             f"{what} tally {key}: gpu {a!r} oracle {b!r}"
     assert got["tallies"]["sweeps"] == ref["tallies"]["sweeps"]
+
+
+def assert_edges_close(got, ref, precision, unit, what=""):
+    """Combined transport: every vertex holds the same layout on both sides,
+    and the photons per edge slot agree within the photon tolerance."""
+    lg = np.asarray(got["layout"]).astype(np.int64)
+    lr = np.asarray(ref["layout"]).astype(np.int64)
+    nbad = int(np.count_nonzero(lg != lr))
+    assert nbad == 0, f"{what} layout: {nbad} vertices differ"
+    rt, at = TOL[precision]["ph"]
+    ok, nbad, worst = close(got["photons_e"], ref["photons_e"], rt, at * unit)
+    assert ok, f"{what} photons_e: {nbad} elements off, worst rel {worst:.3e}"

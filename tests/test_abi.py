@@ -43,7 +43,7 @@ def test_binding_constants_match_header():
     for name in ("SX_OK", "SX_EINVAL", "SX_ENOMEM", "SX_EDEVICE", "SX_ENOTFOUND",
                  "SX_ENOTSUP", "SX_EAGAIN", "SX_FP64", "SX_FP32_TRANSPORT",
                  "SX_ORDER_GRID", "SX_ORDER_DIRECT_FIRST", "SX_MAX_GRAPH_SWEEPS",
-                 "SX_MAX_DEGREE"):
+                 "SX_MAX_DEGREE", "SX_TRANSPORT_DCT", "SX_TRANSPORT_COMBINED"):
         assert int(defs[name]) == getattr(sx, name), name
     assert sx.SX_MAX_BINS == int(defs["SX_MAX_BINS_FP32"]) == int(defs["SX_MAX_BINS_FP64"])
 
@@ -67,6 +67,9 @@ def test_null_arguments_rejected_without_device():
     assert lib.sx_set_schedule(None, None, 0, None) == sx.SX_EINVAL
     assert lib.sx_get_schedule(None, None, 0, None, None) == sx.SX_EINVAL
     assert lib.sx_finalize(None) == sx.SX_OK
+    assert lib.sx_read_edge_state(None, 1, None, None) == sx.SX_EINVAL
+    assert lib.sx_grid_restore_edges(None, 1, None, None) == sx.SX_EINVAL
+    assert lib.sx_read_ballistic(None, 1, None, None) == sx.SX_EINVAL
     b = C.c_uint64()
     assert lib.sx_grid_bytes(None, C.byref(b)) == sx.SX_EINVAL
 
@@ -92,6 +95,7 @@ int main(void) {
   P(sx_serve_result, tally) P(sx_serve_stats, updates) P(sx_serve_stats, latency_max_s)
   P(sx_grid_desc, kappa) P(sx_grid_desc, n_bins) P(sx_grid_desc, cos_min)
   P(sx_grid_desc, src_dir) P(sx_grid_desc, dt) P(sx_grid_desc, precision)
+  P(sx_grid_desc, transport) P(sx_grid_desc, tau_switch)
   P(sx_ctx_opts, stream) P(sx_ctx_opts, alloc_user)
   return 0;
 }
@@ -122,7 +126,8 @@ def test_ctypes_struct_layout_matches_c():
         assert C.sizeof(cls) == lay[name], name
         for f in fields:
             assert getattr(cls, f).offset == lay[f"{name}.{f}"], (name, f)
-    for f in ("kappa", "n_bins", "cos_min", "src_dir", "dt", "precision"):
+    for f in ("kappa", "n_bins", "cos_min", "src_dir", "dt", "precision", "transport",
+              "tau_switch"):
         assert getattr(sx.SxGridDesc, f).offset == lay[f"sx_grid_desc.{f}"], f
     for f in ("stream", "alloc_user"):
         assert getattr(sx.SxCtxOpts, f).offset == lay[f"sx_ctx_opts.{f}"], f
@@ -172,3 +177,24 @@ def test_prepare_is_host_only():
     with pytest.raises(sx.SxError) as e:
         sx.sx_grid_prepare(bad)
     assert e.value.code == sx.SX_EINVAL
+
+
+def test_prepare_combined_transport_host_only():
+    """Combined transport is prepared on the host: a valid request gets a
+    larger byte estimate (per-edge state and lists); an unknown mode or a NaN
+    switch is rejected."""
+    from paper_0912_4273_amd import gridgen as G
+    w = G.small_random(300, seed=6, n_bins=21)
+    sizes = []
+    for ww in (w, G.with_(w, transport=G.SX_TRANSPORT_COMBINED, tau_switch=1.0)):
+        h = sx.sx_grid_prepare(ww)
+        try:
+            sizes.append(sx.sx_prepared_bytes(h))
+        finally:
+            sx.sx_prepared_free(h)
+    assert sizes[1] > sizes[0]
+    for bad in (G.with_(w, transport=2),
+                G.with_(w, transport=G.SX_TRANSPORT_COMBINED, tau_switch=float("nan"))):
+        with pytest.raises(sx.SxError) as e:
+            sx.sx_grid_prepare(bad)
+        assert e.value.code == sx.SX_EINVAL

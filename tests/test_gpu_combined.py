@@ -1,0 +1,205 @@
+"""Combined ballistic / direction-conserving transport on the GPU against
+the oracle: the ballistic tables bit for bit, whole solves where the mode
+decisions cannot differ, one step from a shared state at the benchmark's
+size, the exact straight-line lattice, batches that mix transport modes,
+checkpoint restore and the refused rotation."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle_pins as P
+from paper_0912_4273_amd import gridgen as G
+from paper_0912_4273_amd import sx
+from oracle import Oracle
+from parity import assert_edges_close, assert_state_close
+
+pytestmark = pytest.mark.gpu
+
+CT = G.SX_TRANSPORT_COMBINED
+
+
+def _work(n=2000, seed=61, k=42, prec=G.SX_FP64, tau_switch=1.0, rate=3e45):
+    w = G.small_random(n, seed=seed, n_bins=k, box=3e21, rate=rate, n_src=3, dt=3e13,
+                       precision=prec)
+    sd = np.zeros((3, 3))
+    sd[1] = [0.0, 0.6, 0.8]   # one beam source
+    return G.with_(w, src_dir=sd, transport=CT, tau_switch=tau_switch)
+
+
+def _gpu_run(ctx, w, sweeps):
+    gid = ctx.upload(w)
+    try:
+        ctx.solve([gid], sweeps)
+        st = ctx.state(gid, photons=True)
+        es = ctx.edge_state(gid)
+        unit = ctx.info(gid)["photon_unit"]
+    finally:
+        ctx.free(gid)
+    return st, es, unit
+
+
+def _oracle_run(w, sweeps):
+    o = Oracle(w)
+    o.run(sweeps)
+    st, es = o.state(), o.edge_state()
+    o.close()
+    return st, es
+
+
+def test_ballistic_tables_bit_exact(sxctx):
+    for w in (_work(800, seed=62), G.with_(_work(600, seed=63), max_per_bin=2)):
+        print(f"[case] ballistic tables n={w.n} mpb={w.max_per_bin}", flush=True)
+        gid = sxctx.upload(w)
+        try:
+            got = sxctx.ballistic(gid)
+            tab = sxctx.tables(gid)
+        finally:
+            sxctx.free(gid)
+        o = Oracle(w)
+        ref = o.ballistic()
+        ot = o.tables()
+        o.close()
+        assert np.array_equal(got["bm"], ref["bm"])
+        assert np.array_equal(got["bsel"][:, :w.max_per_bin], ref["bsel"])
+        assert np.array_equal(tab["sel_m"], ot["sel_m"])
+
+
+@pytest.mark.parametrize("prec", [G.SX_FP64, G.SX_FP32_TRANSPORT])
+def test_all_ballistic_solve(sxctx, prec):
+    """Switch 0: every vertex ballistic in every step (no decision can differ
+    between the two sides), whole solve compared."""
+    w = _work(prec=prec, tau_switch=0.0)
+    print(f"[case] all ballistic prec={prec}", flush=True)
+    st, es, unit = _gpu_run(sxctx, w, 40)
+    rs, re_ = _oracle_run(w, 40)
+    assert es["layout"].all()
+    assert_state_close(st, rs, prec, unit, "all ballistic")
+    assert_edges_close(es, re_, prec, unit, "all ballistic")
+
+
+def test_combined_solve_fp64(sxctx):
+    """The paper's switch (optical depth 1): ionised vertices turn
+    direction-conserving as the fronts pass; fp64 on both sides."""
+    w = _work(tau_switch=1.0)
+    print("[case] combined fp64, switch 1", flush=True)
+    st, es, unit = _gpu_run(sxctx, w, 60)
+    rs, re_ = _oracle_run(w, 60)
+    lay = es["layout"]
+    assert lay.any() and (lay == 0).any(), "both modes in use"
+    assert_state_close(st, rs, G.SX_FP64, unit, "combined fp64")
+    assert_edges_close(es, re_, G.SX_FP64, unit, "combined fp64")
+
+
+@pytest.mark.parametrize("prec", [G.SX_FP64, G.SX_FP32_TRANSPORT])
+def test_combined_one_step_from_shared_state(sxctx, prec):
+    """Mixed modes in both precisions: the GPU's state after 50 steps is
+    handed to the oracle and one more step is compared (both sides take the
+    mode decisions from the same neutral fractions)."""
+    w = _work(3000, seed=64, prec=prec, tau_switch=1.0)
+    print(f"[case] combined one step prec={prec}", flush=True)
+    gid = sxctx.upload(w)
+    try:
+        sxctx.solve([gid], 50)
+        s1, e1 = sxctx.state(gid, photons=True), sxctx.edge_state(gid)
+        sxctx.solve([gid], 1)
+        s2, e2 = sxctx.state(gid, photons=True), sxctx.edge_state(gid)
+        unit = sxctx.info(gid)["photon_unit"]
+    finally:
+        sxctx.free(gid)
+    assert e1["layout"].any() and (e1["layout"] == 0).any()
+    o = Oracle(w)
+    o.set_state(y=s1["y"], photons=s1["photons"], tallies=s1["tallies"])
+    o.set_edge_state(photons_e=e1["photons_e"], layout=e1["layout"].astype(np.int8))
+    o.run(1)
+    rs, re_ = o.state(), o.edge_state()
+    o.close()
+    assert_state_close(s2, rs, prec, unit, f"one step prec {prec}")
+    assert_edges_close(e2, re_, prec, unit, f"one step prec {prec}")
+
+
+@pytest.mark.parametrize("prec", [G.SX_FP64, G.SX_FP32_TRANSPORT])
+def test_lattice_straight_lines_exact(sxctx, prec):
+    """Both conversions on the lattice where every path is straight: exact
+    photon counts, layouts and escapes."""
+    w = G.with_(P.lattice_two_regions(), precision=prec)
+    print(f"[case] lattice prec={prec}", flush=True)
+    st, es, unit = _gpu_run(sxctx, w, w.n_sweeps)
+    O, Oe, layout, escaped = P.lattice_expected(w)
+    assert np.array_equal(es["layout"].astype(np.int8), layout)
+    assert np.array_equal(st["photons"], O)
+    assert np.array_equal(es["photons_e"], Oe)
+    t = st["tallies"]
+    assert t["emitted"] == 18.0 * w.n_sweeps
+    assert t["escaped"] == escaped
+    assert t["in_flight"] == O.sum() + Oe.sum()
+
+
+def test_batches_mix_transport_modes():
+    """DCT and combined grids of both precisions solved in one batch give
+    each grid's result alone, bit for bit."""
+    ws = [_work(900, seed=65, tau_switch=1.0),
+          G.small_random(700, seed=66, n_bins=21, box=3e21, rate=1e47, n_src=2, dt=3e13),
+          _work(1100, seed=67, prec=G.SX_FP32_TRANSPORT, tau_switch=0.5),
+          G.small_random(500, seed=68, n_bins=42, box=3e21, rate=1e47, n_src=1, dt=3e13,
+                         precision=G.SX_FP32_TRANSPORT)]
+    sweeps = [30, 25, 40, 20]
+    print("[case] mixed batch of 4 grids", flush=True)
+    with sx.Context(0) as ctx:
+        alone = []
+        for w, s in zip(ws, sweeps):
+            gid = ctx.upload(w)
+            ctx.solve([gid], s)
+            alone.append(ctx.state(gid, photons=True))
+            ctx.free(gid)
+        gids = [ctx.upload(w) for w in ws]
+        ctx.solve(gids, sweeps)
+        for a, gid, w in zip(alone, gids, ws):
+            b = ctx.state(gid, photons=True)
+            assert np.array_equal(a["y"], b["y"]), w.name
+            assert np.array_equal(a["photons"], b["photons"]), w.name
+            assert a["tallies"] == b["tallies"], w.name
+
+
+def test_checkpoint_restore_edges(sxctx):
+    """State and per-edge state read back, restored into a fresh grid, and
+    both continued: the same evolution to the photon tolerance."""
+    w = _work(1500, seed=69, tau_switch=1.0)
+    print("[case] restore with edges", flush=True)
+    a = sxctx.upload(w)
+    b = sxctx.upload(w)
+    try:
+        sxctx.solve([a], 30)
+        st, es = sxctx.state(a, photons=True), sxctx.edge_state(a)
+        sxctx.restore(b, y=st["y"], photons=st["photons"], tallies=st["tallies"])
+        sxctx.restore_edges(b, es["photons_e"], es["layout"])
+        e2 = sxctx.edge_state(b)
+        assert np.array_equal(e2["layout"], es["layout"])
+        sxctx.solve([a], 10)
+        sxctx.solve([b], 10)
+        sa, sb = sxctx.state(a, photons=True), sxctx.state(b, photons=True)
+        unit = sxctx.info(a)["photon_unit"]
+        assert_state_close(sb, sa, G.SX_FP64, unit, "restored")
+        assert_edges_close(sxctx.edge_state(b), sxctx.edge_state(a), G.SX_FP64, unit,
+                           "restored")
+    finally:
+        sxctx.free(a)
+        sxctx.free(b)
+
+
+def test_combined_limits(sxctx):
+    w = _work(300, seed=70)
+    gid = sxctx.upload(w)
+    try:
+        with pytest.raises(sx.SxError) as e:
+            sxctx.rotate(gid, np.eye(3))
+        assert e.value.code == sx.SX_ENOTSUP
+    finally:
+        sxctx.free(gid)
+    d = sxctx.upload(G.small_random(300, seed=71, n_bins=21))
+    try:
+        with pytest.raises(sx.SxError) as e:
+            sxctx.edge_state(d)
+        assert e.value.code == sx.SX_EINVAL
+    finally:
+        sxctx.free(d)
