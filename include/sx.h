@@ -78,6 +78,16 @@ extern "C" {
 #define SX_TRANSPORT_DCT 0
 #define SX_TRANSPORT_COMBINED 1
 
+/* Reference direction of the bin selection of direction-conserving
+ * transport.  SX_DCT_REF_BIN: the bin's own direction u_k (Sect. 2.2.3).
+ * SX_DCT_REF_EDGE: the reading of the caption of the paper's figure of the
+ * three transport modes: the bin is first tied to the vertex's Delaunay edge
+ * closest to u_k (largest cosine, > cos_min, ties to the lower id; none:
+ * the bin has no neighbour), and goes to the <= max_per_bin neighbours most
+ * aligned with that edge. */
+#define SX_DCT_REF_BIN 0
+#define SX_DCT_REF_EDGE 1
+
 typedef struct sx_ctx sx_ctx;
 typedef int64_t sx_grid_id;
 
@@ -126,6 +136,7 @@ typedef struct sx_grid_desc {
     double dt;                   /* radiative-transfer time step (s)         */
     int32_t precision;           /* SX_FP64 or SX_FP32_TRANSPORT             */
     int32_t transport;           /* SX_TRANSPORT_DCT (0) or _COMBINED        */
+    int32_t dct_reference;       /* SX_DCT_REF_BIN (0) or SX_DCT_REF_EDGE    */
     double tau_switch;           /* combined transport: ballistic where
                                     y tau >= tau_switch (not NaN; +inf =
                                     never)                                   */

@@ -57,6 +57,8 @@ def _load(path=None):
         lib.ora_get_tables.argtypes = [P, P, P, P, P, P]
         lib.ora_rotate.restype = C.c_int
         lib.ora_rotate.argtypes = [P, P]
+        lib.ora_set_dct_reference.restype = C.c_int
+        lib.ora_set_dct_reference.argtypes = [P, C.c_int32]
         lib.ora_set_transport.restype = C.c_int
         lib.ora_set_transport.argtypes = [P, C.c_int32, C.c_double]
         lib.ora_get_edge_state.restype = None
@@ -124,6 +126,8 @@ class Oracle:
         if not h:
             raise ValueError("oracle: " + lib.ora_last_error().decode())
         self._h = h
+        if int(getattr(w, "dct_reference", 0)) == 1:
+            lib.ora_set_dct_reference(h, 1)
         self.combined = int(getattr(w, "transport", 0)) == 1
         if self.combined:
             lib.ora_set_transport(h, 1, float(w.tau_switch))
@@ -154,6 +158,11 @@ class Oracle:
                           tallies["absorbed"], tallies["escaped"],
                           tallies["in_flight"]], np.float64)
         self._lib.ora_set_state(self._h, _p(y), _p(ph), _p(t))
+
+    def set_transport(self, combined: bool, tau_switch: float = 1.0):
+        """Switch between direction-conserving and combined transport."""
+        self._lib.ora_set_transport(self._h, 1 if combined else 0, float(tau_switch))
+        self.combined = bool(combined)
 
     def edge_state(self):
         """Combined transport: photons per edge slot [E] and the layout of

@@ -58,6 +58,8 @@ struct ora_grid {
     double *Ie;          /* [E] scratch: photons in, per incoming edge */
     int8_t *layout;      /* [N] 0: vertex holds bins (O), 1: edges (Oe) */
     int8_t *mode;        /* [N] scratch: this sweep's mode */
+    int32_t dct_ref;     /* 0: bins go by their own direction; 1: by the
+                            vertex's edge closest to the bin */
 };
 
 static void *xcalloc(size_t n, size_t s) {
@@ -188,11 +190,30 @@ static void build_routing(ora_grid *g) {
     int max_per_bin = g->mpb;
     /* Direction-bin -> neighbour selection of direction-conserving transport
      * (Sect. 2.2.3): every bin goes to the mpb (= dimension d = 3) most
-     * straightforward neighbours w.r.t. the bin's own direction. */
+     * straightforward neighbours w.r.t. the bin's own direction, or (the
+     * reading of the caption of the figure of the three transport modes)
+     * w.r.t. the vertex's Delaunay edge closest to the bin: the edge with
+     * the largest cosine to u_k, which must exceed cos_min, ties to the
+     * lower neighbour id. */
     for (int64_t i = 0; i < n; i++) {
         for (int64_t k = 0; k < K; k++) {
             int32_t slots[16];
-            int c = select_slots(g, i, &g->bins[3 * k], slots);
+            const double *ref = &g->bins[3 * k];
+            int c = 0;
+            if (g->dct_ref) {
+                int64_t b = g->ptr[i], best = -1;
+                double cb = g->cos_min;
+                for (int64_t s = 0; s < g->ptr[i + 1] - b; s++) {
+                    double cs = cosine(&g->edir[3 * (b + s)], ref);
+                    if (cs > cb || (best >= 0 && cs == cb && g->nbr[b + s] < g->nbr[b + best])) {
+                        cb = cs;
+                        best = s;
+                    }
+                }
+                if (best >= 0) c = select_slots(g, i, &g->edir[3 * (b + best)], slots);
+            } else {
+                c = select_slots(g, i, ref, slots);
+            }
             int32_t *dst = &g->sel[(i * K + k) * max_per_bin];
             for (int r = 0; r < max_per_bin; r++)
                 dst[r] = r < c ? g->nbr[g->ptr[i] + slots[r]] : -1;
@@ -536,6 +557,17 @@ static void sweep_combined(ora_grid *g) {
     for (int64_t e = 0; e < E; e++) f += g->Oe[e] * (double)g->bm[e];
     g->in_flight = f;
     g->sweeps += 1.0;
+}
+
+int ora_set_dct_reference(ora_grid *g, int32_t edge) {
+    g_err[0] = 0;
+    if (edge != 0 && edge != 1) {
+        snprintf(g_err, sizeof g_err, "bad reference");
+        return -1;
+    }
+    g->dct_ref = edge;
+    build_routing(g);
+    return 0;
 }
 
 int ora_set_transport(ora_grid *g, int32_t combined, double tau_switch) {

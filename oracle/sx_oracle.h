@@ -68,6 +68,13 @@ int ora_rotate(ora_grid *g, const double *R);
 void ora_get_tables(const ora_grid *g, int32_t *sel_nbr, int32_t *sel_m,
                     int32_t *edge_bin, double *dL, double *tau);
 
+/* Reference direction of the bin selection: edge = 0 (default) the bin's
+ * own direction u_k; edge = 1 the vertex's Delaunay edge closest to u_k
+ * (largest cosine, > cos_min, ties to the lower id): the bin then goes to
+ * the neighbours most aligned with that edge.  Rebuilds the routing; call
+ * before the first sweep.  Returns 0, or -1 for a bad argument. */
+int ora_set_dct_reference(ora_grid *g, int32_t edge);
+
 /* Combined transport (Sects. 2.2.2-2.2.4).  combined = 1: from the next
  * sweep on, every vertex whose optical depth y tau is at least tau_switch at
  * the start of a sweep uses ballistic transport (photons held per incoming

@@ -262,6 +262,8 @@ int validate(sx_ctx *ctx, const sx_grid_desc *d) {
     return fail(ctx, SX_EINVAL, "transport must be SX_TRANSPORT_DCT or SX_TRANSPORT_COMBINED");
   if (d->transport == SX_TRANSPORT_COMBINED && std::isnan(d->tau_switch))
     return fail(ctx, SX_EINVAL, "tau_switch is NaN");
+  if (d->dct_reference != SX_DCT_REF_BIN && d->dct_reference != SX_DCT_REF_EDGE)
+    return fail(ctx, SX_EINVAL, "dct_reference must be SX_DCT_REF_BIN or SX_DCT_REF_EDGE");
   const int K = d->n_bins;
   if (K < 1) return fail(ctx, SX_EINVAL, "n_bins must be >= 1");
   if (K > (d->precision == SX_FP64 ? SX_MAX_BINS_FP64 : SX_MAX_BINS_FP32))
@@ -475,7 +477,7 @@ struct sx_prepared {
   std::vector<double> tau, dtnhv, bco, y0;
   std::vector<int32_t> em_ptr, em_k, em_edge;
   std::vector<double> em_amt;
-  int32_t transport = 0;
+  int32_t transport = 0, dct_ref = 0;
   double tau_switch = 0.0;
   std::vector<int32_t> bl_ptr;   // combined transport: ballistic lists by in-edge
   std::vector<uint8_t> bl;
@@ -744,6 +746,7 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
   // sender's edges whose packets it gets, ascending
   P->transport = d->transport;
   P->tau_switch = d->tau_switch;
+  P->dct_ref = d->dct_reference;
   if (d->transport == SX_TRANSPORT_COMBINED) {
     g->bsel_h.assign((size_t)(3 * E), -1);
     g->bm_h.assign((size_t)E, 0);
@@ -824,6 +827,7 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   h.plane = npad + sx::kTile;   // the extra tile stays zero
   h.n_edges = E;
   h.transport = P->transport;
+  h.dct_ref = P->dct_ref;
   h.tau_switch = P->transport == SX_TRANSPORT_COMBINED ? P->tau_switch : 0.0;
   int32_t *d_rp, *d_nbr, *d_rec_cnt, *d_rec_ptr, *d_hptr, *d_hvid;
   uint8_t *d_rev, *d_ebin, *d_tdir;

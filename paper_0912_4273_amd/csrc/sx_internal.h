@@ -107,7 +107,7 @@ struct GridDev {
   // combined transport (transport == 1; null otherwise).  Lists are indexed
   // by the incoming edge e = (row of j, slot s), the sender i = nbr[e]:
   int32_t transport;        // 0 direction-conserving, 1 combined
-  int32_t pad0;
+  int32_t dct_ref;          // bin selection w.r.t. 0: the bin, 1: its closest edge
   double tau_switch;        // ballistic where y tau >= tau_switch
   const int32_t *kl_ptr;    // [E+1]
   const uint8_t *kl;        // bins of i whose selection holds j, ascending

@@ -94,7 +94,9 @@ static hipError_t fill(T *p, T v, int64_t n, hipStream_t s) {
 // For every (vertex, bin): the <= mpb neighbours with the largest cosine
 // between edge and bin direction, cosine > cos_min (photons never go
 // backwards), ties to the lower original neighbour id.  Rows are sorted by
-// original id, so "lower slot" is "lower id".  One lane per pair.
+// original id, so "lower slot" is "lower id".  With dct_ref the reference
+// direction is the vertex's edge closest to the bin (largest cosine over
+// cos_min, ties to the lower id) in place of the bin.  One lane per pair.
 __global__ void k_select(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -104,8 +106,24 @@ __global__ void k_select(const GridDev *__restrict__ gp) {
   const int k = (int)(p - (int64_t)i * K);
   uint32_t s0 = kEmptySlot, s1 = kEmptySlot, s2 = kEmptySlot, cnt = 0;
   if (i < g.n) {
-    const double u[3] = {g.bins[3 * k], g.bins[3 * k + 1], g.bins[3 * k + 2]};
-    const int rb = g.row_ptr[i], re = g.row_ptr[i + 1];
+    double u[3] = {g.bins[3 * k], g.bins[3 * k + 1], g.bins[3 * k + 2]};
+    const int rb = g.row_ptr[i];
+    int re = g.row_ptr[i + 1];
+    if (g.dct_ref) {
+      int best = -1;
+      double cb = g.cos_min;
+      for (int e = rb; e < re; ++e) {
+        const double c = cosine3(&g.edir[3 * (int64_t)e], u);
+        if (c > cb) { cb = c; best = e; }
+      }
+      if (best >= 0) {
+        u[0] = g.edir[3 * (int64_t)best];
+        u[1] = g.edir[3 * (int64_t)best + 1];
+        u[2] = g.edir[3 * (int64_t)best + 2];
+      } else {
+        re = rb;   // no edge in the bin's forward cone: nothing selected
+      }
+    }
     double c0 = -3.0, c1 = -3.0, c2 = -3.0;
     for (int e = rb; e < re; ++e) {
       const double c = cosine3(&g.edir[3 * (int64_t)e], u);

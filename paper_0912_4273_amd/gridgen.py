@@ -31,6 +31,8 @@ SX_FP32_TRANSPORT = 1
 
 SX_TRANSPORT_DCT = 0        # direction-conserving transport everywhere
 SX_TRANSPORT_COMBINED = 1   # ballistic where y tau >= tau_switch (Sect. 2.2.4)
+SX_DCT_REF_BIN = 0          # bins go by their own direction
+SX_DCT_REF_EDGE = 1         # bins go by the vertex's edge closest to them
 
 
 @dataclass
@@ -59,6 +61,7 @@ class Workload:
     precision: int = SX_FP64
     transport: int = SX_TRANSPORT_DCT
     tau_switch: float = 1.0
+    dct_reference: int = SX_DCT_REF_BIN
     box: float = 0.0
     meta: dict = field(default_factory=dict)
 

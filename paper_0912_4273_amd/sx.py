@@ -32,6 +32,8 @@ SX_MAX_BINS = 96
 SX_MAX_DEGREE = 127
 SX_TRANSPORT_DCT = 0
 SX_TRANSPORT_COMBINED = 1
+SX_DCT_REF_BIN = 0
+SX_DCT_REF_EDGE = 1
 
 EXPORTED = [
     "sx_init", "sx_finalize", "sx_grid_bytes", "sx_grid_upload",
@@ -69,7 +71,7 @@ class SxGridDesc(C.Structure):
         ("src_dir", C.c_void_p), ("sigma", C.c_double),
         ("alpha_B", C.c_double), ("dt", C.c_double),
         ("precision", C.c_int32), ("transport", C.c_int32),
-        ("tau_switch", C.c_double)]
+        ("dct_reference", C.c_int32), ("tau_switch", C.c_double)]
 
 
 class SxTally(C.Structure):
@@ -218,6 +220,7 @@ class _Desc:
             src_rate=_ptr(a["sr"]), src_dir=_ptr(a["sd"]), sigma=float(w.sigma),
             alpha_B=float(w.alpha_B), dt=float(w.dt), precision=int(w.precision),
             transport=int(getattr(w, "transport", SX_TRANSPORT_DCT)),
+            dct_reference=int(getattr(w, "dct_reference", SX_DCT_REF_BIN)),
             tau_switch=float(getattr(w, "tau_switch", 1.0)))
 
 

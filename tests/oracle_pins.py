@@ -266,6 +266,46 @@ def pin_front_law(lib=None, w=None, tol=0.08, t_min_myr=60.0):
     return worst
 
 
+def _brute_tables_edge_ref(w):
+    """Bin selection with the edge reference: each bin is first mapped to
+    the vertex's edge closest to it (cosine > cos_min, ties to the lower id),
+    then goes to the neighbours most aligned with that edge."""
+    n, k = w.n, w.k
+    ptr, idx, pos, u = w.nbr_ptr, w.nbr_idx, w.pos, w.bin_dirs
+    sel = -np.ones((n, k, w.max_per_bin), np.int32)
+    m = np.zeros((n, k), np.int32)
+    for i in range(n):
+        nb = idx[ptr[i]:ptr[i + 1]]
+        if nb.size == 0:
+            continue
+        d = pos[nb] - pos[i]
+        ln = np.sqrt((d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2])
+        e = d / ln[:, None]
+        for kk in range(k):
+            c = (e[:, 0] * u[kk, 0] + e[:, 1] * u[kk, 1]) + e[:, 2] * u[kk, 2]
+            ok = [(-c[s], int(nb[s]), s) for s in range(nb.size) if c[s] > w.cos_min]
+            if not ok:
+                continue
+            ref = e[min(ok)[2]]
+            c2 = (e[:, 0] * ref[0] + e[:, 1] * ref[1]) + e[:, 2] * ref[2]
+            cand = sorted((-c2[s], int(nb[s])) for s in range(nb.size) if c2[s] > w.cos_min)
+            top = [v for _, v in cand[: w.max_per_bin]]
+            m[i, kk] = len(top)
+            sel[i, kk, : len(top)] = top
+    return sel, m
+
+
+def pin_edge_reference_brute_force(lib=None):
+    """The alternative reading of the bin selection (the bin is mapped to
+    its closest Delaunay edge, whose neighbour is then chosen first)."""
+    for w in (G.small_random(150, seed=15, n_bins=21),
+              G.with_(G.small_random(120, seed=16, n_bins=42), max_per_bin=2)):
+        t = Oracle(G.with_(w, dct_reference=G.SX_DCT_REF_EDGE), lib).tables()
+        sel, m = _brute_tables_edge_ref(w)
+        assert np.array_equal(t["sel_m"], m), w.name
+        assert np.array_equal(t["sel_nbr"], sel), w.name
+
+
 # ------------------------------------------------------ combined transport ---
 
 def pin_combined_off_is_dct(lib=None):
@@ -427,4 +467,4 @@ FAST_PINS = [pin_recombination_closed_form, pin_equilibrium_fixed_point,
              pin_selection_brute_force, pin_axis_star, pin_ties,
              pin_chain_hops, pin_conservation, pin_combined_off_is_dct,
              pin_ballistic_brute_force, pin_combined_lattice,
-             pin_combined_conservation]
+             pin_combined_conservation, pin_edge_reference_brute_force]

@@ -43,7 +43,8 @@ def test_binding_constants_match_header():
     for name in ("SX_OK", "SX_EINVAL", "SX_ENOMEM", "SX_EDEVICE", "SX_ENOTFOUND",
                  "SX_ENOTSUP", "SX_EAGAIN", "SX_FP64", "SX_FP32_TRANSPORT",
                  "SX_ORDER_GRID", "SX_ORDER_DIRECT_FIRST", "SX_MAX_GRAPH_SWEEPS",
-                 "SX_MAX_DEGREE", "SX_TRANSPORT_DCT", "SX_TRANSPORT_COMBINED"):
+                 "SX_MAX_DEGREE", "SX_TRANSPORT_DCT", "SX_TRANSPORT_COMBINED",
+                 "SX_DCT_REF_BIN", "SX_DCT_REF_EDGE"):
         assert int(defs[name]) == getattr(sx, name), name
     assert sx.SX_MAX_BINS == int(defs["SX_MAX_BINS_FP32"]) == int(defs["SX_MAX_BINS_FP64"])
 
@@ -95,7 +96,7 @@ int main(void) {
   P(sx_serve_result, tally) P(sx_serve_stats, updates) P(sx_serve_stats, latency_max_s)
   P(sx_grid_desc, kappa) P(sx_grid_desc, n_bins) P(sx_grid_desc, cos_min)
   P(sx_grid_desc, src_dir) P(sx_grid_desc, dt) P(sx_grid_desc, precision)
-  P(sx_grid_desc, transport) P(sx_grid_desc, tau_switch)
+  P(sx_grid_desc, transport) P(sx_grid_desc, dct_reference) P(sx_grid_desc, tau_switch)
   P(sx_ctx_opts, stream) P(sx_ctx_opts, alloc_user)
   return 0;
 }
@@ -127,7 +128,7 @@ def test_ctypes_struct_layout_matches_c():
         for f in fields:
             assert getattr(cls, f).offset == lay[f"{name}.{f}"], (name, f)
     for f in ("kappa", "n_bins", "cos_min", "src_dir", "dt", "precision", "transport",
-              "tau_switch"):
+              "dct_reference", "tau_switch"):
         assert getattr(sx.SxGridDesc, f).offset == lay[f"sx_grid_desc.{f}"], f
     for f in ("stream", "alloc_user"):
         assert getattr(sx.SxCtxOpts, f).offset == lay[f"sx_ctx_opts.{f}"], f

@@ -203,3 +203,73 @@ def test_combined_limits(sxctx):
         assert e.value.code == sx.SX_EINVAL
     finally:
         sxctx.free(d)
+
+
+# ------------------------------------------- edge reference of the bins ---
+
+def _edge_ref(n=1500, seed=72, prec=G.SX_FP64, k=42):
+    w = G.small_random(n, seed=seed, n_bins=k, box=3e21, rate=3e45, n_src=3, dt=3e13,
+                       precision=prec)
+    return G.with_(w, dct_reference=G.SX_DCT_REF_EDGE)
+
+
+@pytest.mark.parametrize("prec", [G.SX_FP64, G.SX_FP32_TRANSPORT])
+def test_edge_reference_tables_and_solve(sxctx, prec):
+    """Bins tied to their closest edge: selection bit for bit, whole solve."""
+    w = _edge_ref(prec=prec)
+    print(f"[case] edge reference prec={prec}", flush=True)
+    gid = sxctx.upload(w)
+    try:
+        tab = sxctx.tables(gid)
+        sxctx.solve([gid], 40)
+        st = sxctx.state(gid, photons=True)
+        unit = sxctx.info(gid)["photon_unit"]
+    finally:
+        sxctx.free(gid)
+    o = Oracle(w)
+    ot = o.tables()
+    o.run(40)
+    ref = o.state()
+    o.close()
+    assert np.array_equal(tab["sel_m"], ot["sel_m"])
+    assert np.array_equal(tab["sel_nbr"][:, :, :w.max_per_bin], ot["sel_nbr"])
+    assert_state_close(st, ref, prec, unit, f"edge reference prec {prec}")
+
+
+def test_edge_reference_rotated(sxctx):
+    """The edge reference after a rotation of the bins (rebuilt on the
+    device) against the oracle's rotation."""
+    w = _edge_ref(1200, seed=73)
+    R = G.random_rotations(1, seed=7)[0]
+    print("[case] edge reference rotated", flush=True)
+    gid = sxctx.upload(w)
+    try:
+        sxctx.solve([gid], 10)
+        sxctx.rotate(gid, R)
+        tab = sxctx.tables(gid)
+        sxctx.solve([gid], 10)
+        st = sxctx.state(gid, photons=True)
+        unit = sxctx.info(gid)["photon_unit"]
+    finally:
+        sxctx.free(gid)
+    o = Oracle(w)
+    o.run(10)
+    o.rotate(R)
+    ot = o.tables()
+    o.run(10)
+    ref = o.state()
+    o.close()
+    assert np.array_equal(tab["sel_m"], ot["sel_m"])
+    assert np.array_equal(tab["sel_nbr"], ot["sel_nbr"])
+    assert_state_close(st, ref, G.SX_FP64, unit, "edge reference rotated")
+
+
+def test_edge_reference_combined(sxctx):
+    """Combined transport with the edge reference for its
+    direction-conserving part."""
+    w = G.with_(_work(1500, seed=74, tau_switch=1.0), dct_reference=G.SX_DCT_REF_EDGE)
+    print("[case] edge reference + combined", flush=True)
+    st, es, unit = _gpu_run(sxctx, w, 50)
+    rs, re_ = _oracle_run(w, 50)
+    assert_state_close(st, rs, G.SX_FP64, unit, "edge reference combined")
+    assert_edges_close(es, re_, G.SX_FP64, unit, "edge reference combined")

@@ -12,7 +12,7 @@ import pytest
 from paper_0912_4273_amd import gridgen as G
 from paper_0912_4273_amd import sx
 from oracle import Oracle
-from parity import assert_state_close
+from parity import assert_edges_close, assert_state_close
 
 pytestmark = pytest.mark.gpu
 
@@ -48,6 +48,37 @@ def test_full_size_one_sweep(full_grid, prec):
     assert_state_close(s2, ref, prec, unit, f"full size one sweep, prec {prec}")
     # the front has moved well into the grid: the comparison covers lit cells
     assert np.count_nonzero(s2["x"] > 0.5) > 1000
+
+
+@pytest.mark.parametrize("prec", [G.SX_FP32_TRANSPORT, G.SX_FP64])
+def test_full_size_one_sweep_combined(full_grid, prec):
+    """Combined transport (switch at optical depth 1) at the benchmark's size
+    and launch configuration: 300 steps on the GPU, then one step on each
+    side from the GPU's state, bins and per-edge packets."""
+    w0, ora = full_grid
+    w = G.with_(w0, precision=prec, transport=G.SX_TRANSPORT_COMBINED, tau_switch=1.0)
+    with sx.Context(0) as ctx:
+        ctx.set_schedule([], graph_sweeps=50)
+        gid = ctx.upload(w)
+        print(f"[case] full size combined prec={prec}: 300 sweeps on the GPU", flush=True)
+        ctx.solve([gid], 300)
+        s1, e1 = ctx.state(gid, photons=True), ctx.edge_state(gid)
+        ctx.solve([gid], 1)
+        s2, e2 = ctx.state(gid, photons=True), ctx.edge_state(gid)
+        unit = ctx.info(gid)["photon_unit"]
+    lay = e1["layout"]
+    assert np.count_nonzero(lay == 0) > 1000 and np.count_nonzero(lay == 1) > 1000
+    print(f"[case] full size combined prec={prec}: one oracle sweep", flush=True)
+    ora.set_transport(True, 1.0)
+    try:
+        ora.set_state(y=s1["y"], photons=s1["photons"], tallies=s1["tallies"])
+        ora.set_edge_state(photons_e=e1["photons_e"], layout=lay.astype(np.int8))
+        ora.run(1)
+        ref, ref_e = ora.state(), ora.edge_state()
+    finally:
+        ora.set_transport(False)
+    assert_state_close(s2, ref, prec, unit, f"full size combined, prec {prec}")
+    assert_edges_close(e2, ref_e, prec, unit, f"full size combined, prec {prec}")
 
 
 @pytest.mark.parametrize("prec", [G.SX_FP64, G.SX_FP32_TRANSPORT])

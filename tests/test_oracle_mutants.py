@@ -48,6 +48,10 @@ MUTANTS = {
                               "g->Oe[e] = out / (double)g->bm[e];\n                else g->escaped += 0.0 * out;"),
     "filed_at_sender_slot": ("g->Ie[g->ptr[j] + g->rev[e]] += v;", "g->Ie[e] += v;"),
     "in_flight_skips_edges": ("f += g->Oe[e] * (double)g->bm[e];", "f += 0.0 * g->Oe[e];"),
+    "edge_reference_unused": ("if (best >= 0) c = select_slots(g, i, &g->edir[3 * (b + best)], slots);",
+                              "if (best >= 0) c = select_slots(g, i, ref, slots);"),
+    "edge_reference_admits_backward": ("double cb = g->cos_min;\n                for (int64_t s = 0;",
+                                       "double cb = -2.0;\n                for (int64_t s = 0;"),
     "nin_skips_first_bin": ("\n        for (int64_t k = 0; k < K; k++) nin += g->I[j * K + k];",
                             "\n        for (int64_t k = 1; k < K; k++) nin += g->I[j * K + k];"),
 }
