@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -441,19 +442,29 @@ int rebuild_routing(sx_ctx *ctx, Grid *g, const double *bins, bool rescale) {
   HIP_TRY(ctx, hipMemcpyAsync(&n_rec, h.rec_ptr + nrow, 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(ctx, hipStreamSynchronize(st));
   if (n_rec > h.rec_cap) {
+    // Only the pool pointer and capacity change in the device table: the
+    // per-sweep control there (parity, steps done) is the device's own and
+    // newer than the host copy, so the whole slot is not rewritten.
+    static_assert(offsetof(GridDev, rec_cap) == offsetof(GridDev, rec) + sizeof(h.rec),
+                  "rec and rec_cap adjacent");
+    auto put_pool = [&]() {
+      return hipMemcpyAsync(&dg->rec, &h.rec, sizeof(h.rec) + sizeof(h.rec_cap),
+                            hipMemcpyHostToDevice, st);
+    };
     gfree(ctx, g, h.rec);
     uint32_t *d_rec = nullptr;
     int r = galloc(ctx, g, &d_rec, (uint64_t)n_rec + 1);
     if (r) {
       h.rec = nullptr;
       h.rec_cap = 0;
-      (void)write_slot(ctx, g);
+      (void)put_pool();
+      (void)hipStreamSynchronize(st);
       return fail(ctx, SX_EDEVICE, "overflow record pool could not grow to %d entries", n_rec);
     }
     h.rec = d_rec;
     h.rec_cap = n_rec;
-    int w = write_slot(ctx, g);
-    if (w) return w;
+    HIP_TRY(ctx, put_pool());
+    HIP_TRY(ctx, hipStreamSynchronize(st));
   }
   HIP_TRY(ctx, sx::launch_inlist_fill(dg, h, st));
   HIP_TRY(ctx, hipStreamSynchronize(st));

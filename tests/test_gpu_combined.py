@@ -238,27 +238,30 @@ def test_edge_reference_tables_and_solve(sxctx, prec):
 
 def test_edge_reference_rotated(sxctx):
     """The edge reference after a rotation of the bins (rebuilt on the
-    device) against the oracle's rotation."""
+    device) against the oracle's rotation.  The rotation comes after an odd
+    number of steps and needs a larger overflow pool than the upload: the
+    step count and buffer parity on the device survive the rebuild."""
     w = _edge_ref(1200, seed=73)
     R = G.random_rotations(1, seed=7)[0]
     print("[case] edge reference rotated", flush=True)
     gid = sxctx.upload(w)
     try:
-        sxctx.solve([gid], 10)
+        sxctx.solve([gid], 11)
         sxctx.rotate(gid, R)
         tab = sxctx.tables(gid)
-        sxctx.solve([gid], 10)
+        sxctx.solve([gid], 9)
         st = sxctx.state(gid, photons=True)
         unit = sxctx.info(gid)["photon_unit"]
     finally:
         sxctx.free(gid)
     o = Oracle(w)
-    o.run(10)
+    o.run(11)
     o.rotate(R)
     ot = o.tables()
-    o.run(10)
+    o.run(9)
     ref = o.state()
     o.close()
+    assert st["tallies"]["sweeps"] == 20
     assert np.array_equal(tab["sel_m"], ot["sel_m"])
     assert np.array_equal(tab["sel_nbr"], ot["sel_nbr"])
     assert_state_close(st, ref, G.SX_FP64, unit, "edge reference rotated")
