@@ -389,7 +389,8 @@ uint64_t bytes_estimate(const Sizes &s, int64_t n_em, int64_t n_rec, int64_t n_h
     // bin lists (at most mpb entries per (vertex, bin)), ballistic lists
     // (at most mpb per edge), counts, per-edge photons, layouts
     b += 2 * rnd(4 * (s.E + 1)) + rnd((uint64_t)s.mpb * s.npad * s.K) +
-         rnd((uint64_t)s.mpb * s.E) + rnd(s.E) + 2 * rnd((uint64_t)s.sp * s.E) +
+         rnd((uint64_t)4 * s.mpb * s.E) + 3 * rnd(s.E) + 2 * rnd((uint64_t)s.sp * s.E) +
+         rnd((uint64_t)sx::kBlockBytes * s.kb * (s.npad + sx::kTile)) +
          2 * rnd(s.npad);
   }
   return b;
@@ -491,7 +492,8 @@ struct sx_prepared {
   int32_t transport = 0, dct_ref = 0;
   double tau_switch = 0.0;
   std::vector<int32_t> bl_ptr;   // combined transport: ballistic lists by in-edge
-  std::vector<uint8_t> bl;
+  std::vector<int32_t> bl;
+  std::vector<uint8_t> elane, ebin_in;
   ~sx_prepared() { delete g; }
 };
 
@@ -782,12 +784,20 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
     for (int64_t e = 0; e < E; ++e) blp[(size_t)e + 1] += blp[(size_t)e];
     std::vector<int32_t> fillp(blp.begin(), blp.end() - 1);
     P->bl.assign((size_t)blp[(size_t)E], 0);
+    P->elane.assign((size_t)E, 0);
+    P->ebin_in.assign((size_t)E, 0);
+    for (int64_t v = 0; v < n; ++v)
+      for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) {
+        P->elane[(size_t)e] = (uint8_t)(v & 63);
+        // bin of the edge nbr -> v (its id in the row of nbr)
+        P->ebin_in[(size_t)e] = (uint8_t)edge_bin(rp[(size_t)g->nbr_h[(size_t)e]] + rev[(size_t)e]);
+      }
     for (int64_t v = 0; v < n; ++v)
       for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e)
         for (int q = 0; q < g->bm_h[(size_t)e]; ++q) {
           const int32_t f = g->bsel_h[(size_t)(3 * e + q)];
           const int32_t in = rp[(size_t)g->nbr_h[(size_t)f]] + rev[(size_t)f];
-          P->bl[(size_t)fillp[(size_t)in]++] = (uint8_t)(e - rp[(size_t)v]);
+          P->bl[(size_t)fillp[(size_t)in]++] = e;
         }
   }
   return SX_OK;
@@ -1037,13 +1047,16 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
           kl[(size_t)fillp[(size_t)in]++] = (uint8_t)k;
         }
       }
-    int32_t *d_klp, *d_blp;
-    uint8_t *d_kl, *d_bl, *d_bm, *d_l0, *d_l1, *d_e0, *d_e1;
+    int32_t *d_klp, *d_blp, *d_bl;
+    uint8_t *d_kl, *d_bm, *d_el, *d_eb, *d_l0, *d_l1, *d_e0, *d_e1, *d_x;
     GA(d_klp, E + 1);
     GA(d_kl, kl.size() + 1);
     GA(d_blp, E + 1);
     GA(d_bl, P->bl.size() + 1);
     GA(d_bm, E + 1);
+    GA(d_el, E + 1);
+    GA(d_eb, E + 1);
+    GA(d_x, (uint64_t)sx::kBlockBytes * S.kb * (npad + sx::kTile));
     GA(d_e0, (uint64_t)S.sp * (E + 1));
     GA(d_e1, (uint64_t)S.sp * (E + 1));
     GA(d_l0, npad);
@@ -1051,13 +1064,18 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
     UP(d_klp, klp.data(), 4 * (E + 1));
     UP(d_kl, kl.data(), kl.size());
     UP(d_blp, P->bl_ptr.data(), 4 * (E + 1));
-    UP(d_bl, P->bl.data(), P->bl.size());
+    UP(d_bl, P->bl.data(), 4 * P->bl.size());
     UP(d_bm, g->bm_h.data(), E);
+    UP(d_el, P->elane.data(), E);
+    UP(d_eb, P->ebin_in.data(), E);
     if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
     h.kl_ptr = d_klp;
     h.kl = d_kl;
     h.bl_ptr = d_blp;
     h.bl = d_bl;
+    h.elane = d_el;
+    h.ebin_in = d_eb;
+    h.xin = d_x;
     h.bm = d_bm;
     h.oe[0] = d_e0;
     h.oe[1] = d_e1;
@@ -1986,18 +2004,24 @@ int sx_grid_restore_edges(sx_ctx *ctx, sx_grid_id id, const double *photons_e,
   const std::vector<int32_t> &rp = g->row_ptr_h;
   // the restored packets are the outgoing share itself: Ipre_e = O_e and
   // T = 1 for the vertices that hold edges (their bins are not read)
+  // vertices that hold edges keep zeros in their bins
+  const int64_t words = (h.ntiles + 1) * (int64_t)h.kb * sx::kTile * h.bb;
   auto put = [&](auto zero) -> int {
     using T = decltype(zero);
-    std::vector<T> o((size_t)E, zero), t((size_t)h.plane);
+    std::vector<T> o((size_t)E, zero), t((size_t)h.plane), bins((size_t)words);
     HIP_TRY(ctx, hipMemcpy(t.data(), h.t[par], sizeof(T) * h.plane, hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(bins.data(), h.o[par], sizeof(T) * words, hipMemcpyDeviceToHost));
     for (int64_t v = 0; v < n; ++v) {
       if (!lay[(size_t)v]) continue;
       t[(size_t)v] = (T)1;
       for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e)
         o[(size_t)e] = photons_e ? (T)(photons_e[to_orig[(size_t)e]] / h.unit) : zero;
+      for (int64_t k = 0; k < h.k; ++k)
+        bins[(size_t)((((v >> 6) * h.kb + k / h.bb) * sx::kTile + (v & 63)) * h.bb + k % h.bb)] = zero;
     }
     HIP_TRY(ctx, hipMemcpy(h.oe[par], o.data(), sizeof(T) * E, hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipMemcpy(h.t[par], t.data(), sizeof(T) * h.plane, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(h.o[par], bins.data(), sizeof(T) * words, hipMemcpyHostToDevice));
     return SX_OK;
   };
   r = h.precision == SX_FP64 ? put(0.0) : put(0.0f);

@@ -112,7 +112,13 @@ struct GridDev {
   const int32_t *kl_ptr;    // [E+1]
   const uint8_t *kl;        // bins of i whose selection holds j, ascending
   const int32_t *bl_ptr;    // [E+1]
-  const uint8_t *bl;        // slots of i whose ballistic packets go to j, ascending
+  const int32_t *bl;        // edges of i (global ids, ascending) whose ballistic
+                            // packets go to j
+  const uint8_t *elane;     // [E] lane (vertex mod 64) of each edge's row
+  const uint8_t *ebin_in;   // [E] bin of the edge i -> j, for the in-edge (j, slot of i)
+  void *xin;                // bin field (layout of o[]): photons from ballistic
+                            // senders waiting for their receiver's bin code; zero
+                            // between steps
   const uint8_t *bm;        // [E] neighbours chosen for the packet entering j along e
   void *oe[2];              // [E] ballistic photons I/bm per incoming edge (fp32 or fp64)
   uint8_t *lay[2];          // [npad] 1: the vertex held edges in the step that wrote it

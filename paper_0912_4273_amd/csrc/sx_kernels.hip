@@ -466,10 +466,25 @@ __device__ __forceinline__ double chem_step(double y, double nin, double dt,
 // 3. Per-tile photon accounting in fp64, fixed-order wave reduction.
 constexpr int kHaloPlane = kZeroSlot + 1;   // LDS words per staged bin
 
-template <typename P, bool DIRECT>
+// What a combined-transport step hands the tile code (CT = true): whether
+// this lane's vertex is ballistic (then its bins are written as zeros and
+// its N_in and escapes come from the per-edge sums), and for a
+// direction-conserving vertex the bins that receive photons from ballistic
+// senders: their sums wait in xin (element (j, k) in the layout of o[]),
+// flagged per block in xmask, and are added and cleared there.
+template <typename P>
+struct CtIn {
+  bool bal = false;
+  P nin_b = P(0), esc_b = P(0);
+  uint64_t xmask = 0;   // one bit per 16-byte block (up to 48)
+  P *xin = nullptr;
+};
+
+template <typename P, bool DIRECT, bool CT = false>
 __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int tile,
                                            int lane, volatile SX_L P *hl,
-                                           volatile SX_L P *xchg) {
+                                           volatile SX_L P *xchg,
+                                           const CtIn<P> &ci = CtIn<P>()) {
   // hl and xchg carry data between lanes of this wave through LDS.  The
   // accesses are volatile so that the compiler keeps every store and load in
   // program order (it may not forward a lane's own store past another
@@ -640,6 +655,15 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
       __builtin_amdgcn_wave_barrier();
     }
     __builtin_amdgcn_wave_barrier();
+    if constexpr (CT) {
+      if ((ci.xmask >> kb) & 1ull) {
+        SX_G V *xp = (SX_G V *)ci.xin + blk((uint32_t)j, kb);
+        const V xv = *xp;
+#pragma unroll
+        for (int b = 0; b < BB; ++b) acc[b] += xv[b];
+        *xp = V(0);
+      }
+    }
     V out;
 #pragma unroll
     for (int b = 0; b < BB; ++b) {
@@ -664,6 +688,9 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
       }
       out[b] = ipre;
     }
+    if constexpr (CT) {
+      if (ci.bal) out = V(0);
+    }
     if (valid) oout[blk((uint32_t)j, kb)] = out;
   };
 
@@ -673,6 +700,12 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
     if (kb + 1 < KB) block(kb + 1, 1);
   }
 
+  if constexpr (CT) {
+    if (ci.bal) {
+      nin_p = ci.nin_b;
+      esc_p = ci.esc_b;
+    }
+  }
   double A = 0.0, T = 1.0;
   const double nin = (double)nin_p;
   if (valid) {
@@ -767,18 +800,35 @@ __global__ __launch_bounds__(64 * TPB, 4) void k_sweep(
 // the start of the step is at least tau_switch.  Each sender i holds what it
 // received in the previous step either per bin (layout 0: Ipre = I/m in
 // o[], as in direction-conserving transport) or per incoming edge (layout 1:
-// Ipre = I/bm in oe[]), and passes on Ipre * T_i.  j walks its incoming
-// edges once, in ascending original sender id:
-//  - a sender holding bins sends the bins whose selection holds j (kl), each
+// Ipre = I/bm in oe[]), and passes on Ipre * T_i.  What arrives along the
+// edge i -> j:
+//  - from a sender holding bins: the bins whose selection holds j (kl), each
 //    in its own bin;
-//  - a sender holding edges sends the packets whose ballistic choice holds j
+//  - from a sender holding edges: the packets whose ballistic choice holds j
 //    (bl), in the bin of the edge i -> j;
-//  - source shares arrive along the edge from the source, in that edge's bin.
-// A ballistic j adds up what came along each edge and stores I / bm for
-// that edge at once; a direction-conserving j adds into its bins (an LDS
-// column per lane) and stores I / m per bin after the walk.  Chemistry and
-// accounting as in direction-conserving transport.
-constexpr int kMaxBinsCt = 96;
+//  - source shares, in the bin of the edge from the source.
+// A ballistic j stores I / bm per incoming edge; a direction-conserving j
+// stores I / m per bin.  Chemistry and accounting as in direction-conserving
+// transport.
+//
+// A vertex holding edges keeps zeros in its bins (it clears them in the two
+// steps after it turns ballistic, and writes zeros while it is in a tile
+// that runs the bin code), so the bin gathers of the direction-conserving
+// tile code read 0 from it, and only what it sends along edges is added
+// apart.  Per tile:
+//  1. every receiver direction-conserving and every halo sender holding
+//     bins (the ionised interior): the tile code of k_sweep as it is;
+//  2. otherwise the tile's incoming edges are summed one edge per lane,
+//     rounds of 64 over the tile's CSR range (the static per-edge data read
+//     coalesced): for a ballistic receiver everything that arrives along the
+//     edge (stored at once as I / bm), for a direction-conserving one what a
+//     ballistic sender sends; the sums wait in LDS.  Each receiver then adds
+//     its row in order: a ballistic one its N_in and escapes, a
+//     direction-conserving one files the ballistic senders' photons in xin
+//     under the bin of the edge;
+//  3. a tile of ballistic receivers only ends there (chemistry, tallies);
+//     any other runs the tile code with those hand-overs.
+constexpr int kVeCap = 1536;   // incoming edges of a tile summed through LDS
 
 template <typename P>
 __device__ __forceinline__ P div_m(P v, uint32_t m) {
@@ -792,38 +842,40 @@ __device__ __forceinline__ P div_m(P v, uint32_t m) {
 
 template <typename P>
 __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int tile,
-                                              int lane, SX_L P *acc) {
+                                              int lane, SX_L P *veb,
+                                              volatile SX_L P *hl, volatile SX_L P *xc) {
   constexpr int BB = kBlockBytes / sizeof(P);
   typedef P V __attribute__((ext_vector_type(BB)));
-  const int K = G->k;
   const int KB = G->kb;
   const int j = tile * kTile + lane;
   const bool valid = j < G->n;
   const int par = G->parity;
   const SX_G P *__restrict__ oin = gld((const P *)G->o[par]);
-  SX_G V *__restrict__ oout = gst((V *)G->o[par ^ 1]);
   const SX_G P *__restrict__ tin = gld((const P *)G->t[par]);
   const SX_G P *__restrict__ ein = gld((const P *)G->oe[par]);
   SX_G P *__restrict__ eout = gst((P *)G->oe[par ^ 1]);
   const SX_G uint8_t *__restrict__ lin = gld((const uint8_t *)G->lay[par]);
+  SX_G uint8_t *__restrict__ lout = gst(G->lay[par ^ 1]);
   const SX_G int32_t *__restrict__ rowp = gld(G->row_ptr);
   const SX_G int32_t *__restrict__ nbr = gld(G->nbr);
   const SX_G uint8_t *__restrict__ rev = gld(G->rev);
-  const SX_G uint8_t *__restrict__ ebin = gld((const uint8_t *)G->ebin);
+  const SX_G uint8_t *__restrict__ ebin_in = gld(G->ebin_in);
   const SX_G int32_t *__restrict__ klp = gld(G->kl_ptr);
   const SX_G uint8_t *__restrict__ kl = gld(G->kl);
   const SX_G int32_t *__restrict__ blp = gld(G->bl_ptr);
-  const SX_G uint8_t *__restrict__ bl = gld(G->bl);
+  const SX_G int32_t *__restrict__ bl = gld(G->bl);
   const SX_G uint8_t *__restrict__ bmv = gld(G->bm);
+  const SX_G uint8_t *__restrict__ elane = gld(G->elane);
   const SX_G int32_t *__restrict__ emp = gld(G->em_ptr);
   const SX_G double *__restrict__ ema = gld(G->em_amt);
   const SX_G int32_t *__restrict__ eme = gld(G->em_edge);
-  const SX_G int32_t *__restrict__ emk = gld((const int32_t *)G->em_k);
+  SX_G P *__restrict__ xin = gst((P *)G->xin);
   // element (v, k) of the bin field
   auto at = [&](uint32_t v, int k) -> uint32_t {
     return (((v >> 6) * (uint32_t)KB + (uint32_t)(k / BB)) * 64u + (v & 63u)) * BB +
            (uint32_t)(k % BB);
   };
+  const bool direct = gld(G->tile_direct)[tile] != 0;
 
   double y0 = 1.0;
   bool bal = false;
@@ -831,95 +883,148 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
     y0 = gld(G->y)[j];
     bal = y0 * gld(G->tau)[j] >= G->tau_switch;
   }
-  P nin_p = P(0), esc_p = P(0);
-  if (valid) {
-    if (!bal)
-      for (int k = 0; k < K; ++k) acc[k * kTile + lane] = P(0);
-    const int rb = rowp[j], re = rowp[j + 1];
-    const int e0 = emp[j], e1 = emp[j + 1];
-    for (int e = rb; e < re; ++e) {
-      const int i = nbr[e];
-      const P ti = tin[i];
-      P ve = P(0);
-      if (lin[i] == 0) {
-        const int q1 = klp[e + 1];
-        for (int q = klp[e]; q < q1; ++q) {
-          const int k = kl[q];
-          const P v = mul_rn(oin[at((uint32_t)i, k)], ti);
-          if (bal) ve += v;
-          else acc[k * kTile + lane] += v;
-        }
-      } else {
-        const int ib = rowp[i];
-        const int kb = ebin[ib + rev[e]];
-        const int q1 = blp[e + 1];
-        for (int q = blp[e]; q < q1; ++q) {
-          const P v = mul_rn(ein[ib + bl[q]], ti);
-          if (bal) ve += v;
-          else acc[kb * kTile + lane] += v;
-        }
-      }
-      if (bal) {
-        for (int q = e0; q < e1; ++q)
-          if (rb + (int)rev[eme[q]] == e) ve += (P)ema[q];
-        const uint32_t m = bmv[e];
-        eout[e] = div_m(ve, m);
-        nin_p += ve;
-        esc_p += m == 0u ? ve : P(0);
-      }
-    }
-    if (!bal) {
-      for (int q = e0; q < e1; ++q) acc[emk[q] * kTile + lane] += (P)ema[q];
-      const SX_G uint32_t *__restrict__ mbp =
-          gld(G->mbits) + (int64_t)tile * G->kw * 64 + lane;
-      for (int kb = 0; kb < KB; ++kb) {
-        V out;
+  const uint64_t balmask = __ballot(bal);
+  const uint64_t validmask = __ballot(valid);
+
+  // 1. direction-conserving transport proper
+  if (balmask == 0 && !direct) {
+    const SX_G int32_t *__restrict__ hptr = gld(G->halo_ptr);
+    const int hp = hptr[tile];
+    const int hlen = hptr[tile + 1] - hp;
+    const SX_G int32_t *__restrict__ hvid = gld(G->halo_vid);
+    bool edges = false;
 #pragma unroll
-        for (int b = 0; b < BB; ++b) {
-          const int k = kb * BB + b;
-          P ipre = P(0);
-          if (k < K) {
-            const uint32_t m = (mbp[(k >> 4) * 64] >> (2 * (k & 15))) & 3u;
-            const P I = acc[k * kTile + lane];
-            nin_p += I;
-            esc_p += m == 0u ? I : P(0);
-            ipre = div_m(I, m);
-          }
-          out[b] = ipre;
-        }
-        oout[((uint32_t)tile * (uint32_t)KB + (uint32_t)kb) * 64u + (uint32_t)lane] = out;
+    for (int q = 0; q < kStageQ; ++q) {
+      const int idx = 64 * q + lane;
+      if (idx < hlen && lin[hvid[hp + idx]] != 0) edges = true;
+    }
+    if (__ballot(edges) == 0) {
+      sweep_tile<P, false>(G, tile, lane, hl, xc);
+      if (valid) lout[j] = 0;
+      return;
+    }
+  }
+
+  // 2. per incoming edge e (receiver lane r): everything that arrives at a
+  // ballistic receiver (stored as I / bm), or what a ballistic sender sends
+  // a direction-conserving one
+  auto edge_in = [&](int e, int r, bool rbal) -> P {
+    const int i = nbr[e];
+    const bool iedges = lin[i] != 0;
+    P ve = P(0);
+    if (!rbal && !iedges) return ve;
+    const P ti = tin[i];
+    if (!iedges) {
+      const int q1 = klp[e + 1];
+      for (int q = klp[e]; q < q1; ++q) ve += mul_rn(oin[at((uint32_t)i, kl[q])], ti);
+    } else {
+      const int q1 = blp[e + 1];
+      for (int q = blp[e]; q < q1; ++q) ve += mul_rn(ein[bl[q]], ti);
+    }
+    if (rbal) {
+      const int jr = tile * kTile + r;
+      const int e0 = emp[jr], e1 = emp[jr + 1];
+      if (e0 < e1) {
+        const int rbj = rowp[jr];
+        for (int q = e0; q < e1; ++q)
+          if (rbj + (int)rev[eme[q]] == e) ve += (P)ema[q];
+      }
+      eout[e] = div_m(ve, (uint32_t)bmv[e]);
+    }
+    return ve;
+  };
+  const int E0 = rowp[tile * kTile];
+  const int ne = rowp[tile * kTile + kTile] - E0;
+  const bool edge_par = ne <= kVeCap;
+  if (edge_par) {
+    for (int base = 0; base < ne; base += 2 * kTile) {
+      const int l0 = base + lane, l1 = base + kTile + lane;
+      P v0 = P(0), v1 = P(0);
+      if (l0 < ne) {
+        const int r = elane[E0 + l0];
+        v0 = edge_in(E0 + l0, r, (balmask >> r) & 1ull);
+      }
+      if (l1 < ne) {
+        const int r = elane[E0 + l1];
+        v1 = edge_in(E0 + l1, r, (balmask >> r) & 1ull);
+      }
+      if (l0 < ne) veb[l0] = v0;
+      if (l1 < ne) veb[l1] = v1;
+    }
+    __syncthreads();
+  }
+  CtIn<P> ci;
+  ci.bal = bal;
+  ci.xin = (P *)G->xin;
+  if (valid) {
+    const int rb = rowp[j], re = rowp[j + 1];
+    for (int e = rb; e < re; ++e) {
+      const P ve = edge_par ? veb[e - E0] : edge_in(e, lane, bal);
+      if (bal) {
+        ci.nin_b += ve;
+        ci.esc_b += bmv[e] == 0 ? ve : P(0);
+      } else if (ve != P(0)) {
+        const int k = ebin_in[e];
+        xin[at((uint32_t)j, k)] += ve;
+        ci.xmask |= 1ull << (k / BB);
       }
     }
   }
 
-  double A = 0.0, T = 1.0;
-  const double nin = (double)nin_p;
-  if (valid) {
-    if (!(nin == 0.0 && y0 == 1.0)) {
-      const double yn = chem_step(y0, nin * G->unit, G->dt, gld(G->dtnhv)[j],
-                                  gld(G->tau)[j], gld(G->bcoef)[j], G->n_sub, A, T);
-      gst(G->y)[j] = yn;
+  // 3. ballistic receivers only: no bins to gather
+  if (balmask == validmask) {
+    if (valid && lout[j] == 0) {
+      // the buffer about to be written still holds the bins of two steps
+      // ago: clear them
+      SX_G V *__restrict__ oout = gst((V *)G->o[par ^ 1]);
+      for (int kb = 0; kb < KB; ++kb)
+        oout[((uint32_t)tile * (uint32_t)KB + (uint32_t)kb) * 64u + (uint32_t)lane] = V(0);
     }
-    gst(G->nin)[j] = nin * G->unit;
-    gst((P *)G->t[par ^ 1])[j] = (P)T;
-    gst(G->lay[par ^ 1])[j] = bal ? 1 : 0;
-  }
-  A /= G->unit;
-  double esc = (double)esc_p * T;
-  double fly = (nin - (double)esc_p) * T;
+    double A = 0.0, T = 1.0;
+    const double nin = (double)ci.nin_b;
+    if (valid) {
+      if (!(nin == 0.0 && y0 == 1.0)) {
+        const double yn = chem_step(y0, nin * G->unit, G->dt, gld(G->dtnhv)[j],
+                                    gld(G->tau)[j], gld(G->bcoef)[j], G->n_sub, A, T);
+        gst(G->y)[j] = yn;
+      }
+      gst(G->nin)[j] = nin * G->unit;
+      gst((P *)G->t[par ^ 1])[j] = (P)T;
+      lout[j] = 1;
+    }
+    A /= G->unit;
+    double esc = (double)ci.esc_b * T;
+    double fly = (nin - (double)ci.esc_b) * T;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    A += __shfl_xor(A, off);
-    esc += __shfl_xor(esc, off);
-    fly += __shfl_xor(fly, off);
+    for (int off = 32; off > 0; off >>= 1) {
+      A += __shfl_xor(A, off);
+      esc += __shfl_xor(esc, off);
+      fly += __shfl_xor(fly, off);
+    }
+    if (lane == 0) {
+      SX_G double *t = gst(G->tally) + (int64_t)tile * 3;
+      t[0] += A;
+      t[1] += esc;
+      t[2] = fly;
+    }
+    return;
   }
-  if (lane == 0) {
-    SX_G double *t = gst(G->tally) + (int64_t)tile * 3;
-    t[0] += A;
-    t[1] += esc;
-    t[2] = fly;
-  }
+  if (direct)
+    sweep_tile<P, true, true>(G, tile, lane, hl, xc, ci);
+  else
+    sweep_tile<P, false, true>(G, tile, lane, hl, xc, ci);
+  if (valid) lout[j] = bal ? 1 : 0;
 }
+
+// LDS of one combined-transport workgroup: the tile code's halo plane and
+// hand-over slots, and the per-edge sums.
+template <typename P>
+struct CtLds {
+  static constexpr int BB = kBlockBytes / sizeof(P);
+  P h[kHaloPlane * BB];
+  P x[kTile * BB];
+  P ve[kVeCap];
+};
 
 // One combined-transport step over a tile list: one tile per workgroup of
 // one wave, the same tile lists, XCD numbering and completion as k_sweep.
@@ -928,7 +1033,7 @@ __global__ __launch_bounds__(64) void k_sweep_ct(
     GridDev *__restrict__ grids, const int2 *__restrict__ tile_map,
     int32_t n_tiles, const int32_t *__restrict__ adv, int32_t n_adv,
     uint32_t *__restrict__ done, int32_t xcd_remap) {
-  __shared__ P acc[kMaxBinsCt * kTile];
+  __shared__ CtLds<P> lds;
   __shared__ int last;
   const int lane = threadIdx.x & 63;
   const uint32_t nb = gridDim.x;   // a multiple of 8
@@ -942,7 +1047,9 @@ __global__ __launch_bounds__(64) void k_sweep_ct(
       tile = __builtin_amdgcn_readfirstlane(tm.y);
     }
     const GridDev *__restrict__ G = grids + gi;
-    if (G->remaining > 0) sweep_tile_ct<P>(G, tile, lane, (SX_L P *)acc);
+    if (G->remaining > 0)
+      sweep_tile_ct<P>(G, tile, lane, (SX_L P *)lds.ve, (volatile SX_L P *)lds.h,
+                       (volatile SX_L P *)lds.x);
   }
   __syncthreads();
   if (threadIdx.x == 0)
@@ -1078,6 +1185,9 @@ hipError_t launch_reset_state(GridDev *dg, const GridDev &hg, const double *y0,
       if (e == hipSuccess) e = fill<uint8_t>(hg.lay[b], (uint8_t)0, hg.npad, s);
       if (e != hipSuccess) return e;
     }
+    if (hg.precision == 0) e = fill<double>((double *)hg.xin, 0.0, nk, s);
+    else e = fill<float>((float *)hg.xin, 0.0f, nk, s);
+    if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_reset, dim3(blocks_for(hg.npad, 256)), dim3(256), 0, s,
                      dg, y0);
