@@ -39,6 +39,20 @@ def algorithmic_bytes_per_update(k: int, photon_bytes: int) -> float:
     return 2.0 * photon_bytes + 2.0 + 110.0 / k
 
 
+def combined_bytes_per_step(w, layout, photon_bytes: int) -> float:
+    """Algorithmic bytes of one combined-transport step for a given mode
+    mix: a direction-conserving vertex moves what it moves in
+    direction-conserving transport (K updates); a ballistic vertex reads one
+    packet and writes one per incoming edge, with ~1 B of routing per edge,
+    plus the same ~110 B of per-vertex data."""
+    import numpy as np
+    deg = np.diff(w.nbr_ptr)
+    lay = np.asarray(layout) != 0
+    dct = float(np.count_nonzero(~lay)) * w.k * algorithmic_bytes_per_update(w.k, photon_bytes)
+    bal = float(np.sum(deg[lay])) * (2.0 * photon_bytes + 1.0) + 110.0 * float(np.count_nonzero(lay))
+    return dct + bal
+
+
 def kernel_source_hash() -> str:
     p = os.path.join(ROOT, "paper_0912_4273_amd", "csrc", "sx_kernels.hip")
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
@@ -263,9 +277,13 @@ def combined_leg(ctx, w, tau_switch: float, log, prof):
     t_rec = 1.0 / (w.alpha_B * w.meta["n_H"])
     rv = (3 / (4 * math.pi) * float(np.sum(w.volume * st["x"]))) ** (1 / 3)
     tl = st["tallies"]
+    kus = 1e3 * pr["total_ms"] / max(pr["launches"], 1)
+    bytes_end = combined_bytes_per_step(w, lay, 4)
     res = dict(value=w.n * w.k * w.n_sweeps / el, unit="vertex·direction updates/s",
                tau_switch=tau_switch, ms_per_solve=1e3 * el, upload_s=round(up, 2),
-               sweep_kernel_us=1e3 * pr["total_ms"] / max(pr["launches"], 1),
+               sweep_kernel_us=kus,
+               algorithmic_bytes_per_step_at_end=round(bytes_end),
+               hbm_frac_at_end_mix=round(bytes_end / (kus * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                ballistic_fraction_end=round(float(lay.mean()), 4),
                front_radius_over_analytic=round(
                    rv / (r_s * (1 - math.exp(-w.n_sweeps * w.dt / t_rec)) ** (1 / 3)), 4),
