@@ -57,6 +57,12 @@ def _load(path=None):
         lib.ora_get_tables.argtypes = [P, P, P, P, P, P]
         lib.ora_rotate.restype = C.c_int
         lib.ora_rotate.argtypes = [P, P]
+        lib.ora_set_diffuse.restype = C.c_int
+        lib.ora_set_diffuse.argtypes = [P, C.c_double]
+        lib.ora_get_diffuse.restype = None
+        lib.ora_get_diffuse.argtypes = [P, P]
+        lib.ora_set_diffuse_pending.restype = None
+        lib.ora_set_diffuse_pending.argtypes = [P, P]
         lib.ora_set_dct_reference.restype = C.c_int
         lib.ora_set_dct_reference.argtypes = [P, C.c_int32]
         lib.ora_set_transport.restype = C.c_int
@@ -126,6 +132,9 @@ class Oracle:
         if not h:
             raise ValueError("oracle: " + lib.ora_last_error().decode())
         self._h = h
+        if float(getattr(w, "alpha_A", 0.0)) > 0.0:
+            if lib.ora_set_diffuse(h, float(w.alpha_A)) != 0:
+                raise ValueError("oracle: " + lib.ora_last_error().decode())
         if int(getattr(w, "dct_reference", 0)) == 1:
             lib.ora_set_dct_reference(h, 1)
         self.combined = int(getattr(w, "transport", 0)) == 1
@@ -158,6 +167,15 @@ class Oracle:
                           tallies["absorbed"], tallies["escaped"],
                           tallies["in_flight"]], np.float64)
         self._lib.ora_set_state(self._h, _p(y), _p(ph), _p(t))
+
+    def diffuse_pending(self):
+        """Recombination photons each vertex sends at the next sweep [N]."""
+        d = np.zeros(self.n)
+        self._lib.ora_get_diffuse(self._h, _p(d))
+        return d
+
+    def set_diffuse_pending(self, pending):
+        self._lib.ora_set_diffuse_pending(self._h, _p(np.ascontiguousarray(pending, np.float64)))
 
     def set_transport(self, combined: bool, tau_switch: float = 1.0):
         """Switch between direction-conserving and combined transport."""

@@ -60,6 +60,10 @@ struct ora_grid {
     int8_t *mode;        /* [N] scratch: this sweep's mode */
     int32_t dct_ref;     /* 0: bins go by their own direction; 1: by the
                             vertex's edge closest to the bin */
+    /* Diffuse recombination radiation (Sects. 2.2.1, 4.2); off while
+     * alpha_A == 0 (on the spot). */
+    double alpha_A;
+    double *D;           /* [N] recombination photons to send next sweep */
 };
 
 static void *xcalloc(size_t n, size_t s) {
@@ -155,19 +159,24 @@ static double be_substep(double y0, double ha, double hb, double tau) {
  * the substeps of exp(-y' tau) (Eqs. intensity_absorbed, intensity_out, with
  * the optical depth of Eq. optical_depth re-evaluated every substep). */
 static double chem(double y, double n_in, double dt, double nHV, double tau,
-                   double b, int n_sub, double *A, double *T) {
+                   double b, int n_sub, double *A, double *T, double *Rsum) {
     double h = dt / (double)n_sub;
     double a = n_in / (dt * nHV);
     double ha = h * a, hb = h * b;
-    double abs_sum = 0.0, tr_sum = 0.0;
+    double abs_sum = 0.0, tr_sum = 0.0, rec_sum = 0.0;
     double share = n_in / (double)n_sub;
     for (int s = 0; s < n_sub; s++) {
         y = be_substep(y, ha, hb, tau);
         abs_sum += share * (-expm1(-y * tau));
         tr_sum += exp(-y * tau);
+        /* recombinations per atom in the substep, the b term of the
+         * backward-Euler update */
+        double x = 1.0 - y;
+        rec_sum += hb * (x * x);
     }
     *A = abs_sum;
     *T = (n_in > 0.0) ? tr_sum / (double)n_sub : 1.0;
+    if (Rsum) *Rsum = rec_sum;
     return y;
 }
 
@@ -175,7 +184,7 @@ double ora_chem_cell(double y, double n_in, double dt, double nHV, double tau,
                      double b, int32_t n_sub, double *absorbed,
                      double *transmitted) {
     double A, T;
-    double yn = chem(y, n_in, dt, nHV, tau, b, n_sub, &A, &T);
+    double yn = chem(y, n_in, dt, nHV, tau, b, n_sub, &A, &T, NULL);
     if (absorbed) *absorbed = A;
     if (transmitted) *transmitted = n_in * T;
     return yn;
@@ -329,6 +338,53 @@ ora_grid *ora_create(int64_t n, const double *pos, const int64_t *nbr_ptr,
 }
 
 /* ---------------------------------------------------------------------- */
+/* Diffuse recombination radiation (Sects. 2.2.1, 4.2).  Off the spot, the
+ * rate equation recombines with alpha_A (all levels); the recombinations
+ * straight to the ground level, the share (alpha_A - alpha_B) / alpha_A of
+ * them, emit ionising photons.  A vertex's such photons of one step leave it
+ * in the next step, split equally over all its neighbours (isotropic
+ * re-emission), and are filed by the receivers like those of a source.  They
+ * count as emitted when produced and as in flight until sent. */
+static double recomb_coeff(const ora_grid *g) {
+    return g->alpha_A > 0.0 ? g->alpha_A : g->alpha_B;
+}
+
+/* Photons produced by the recombinations of vertex j in this sweep (Rsum:
+ * recombinations per atom). */
+static void diffuse_made(ora_grid *g, int64_t j, double Rsum) {
+    if (g->alpha_A <= 0.0) return;
+    double Dj = (g->nH[j] * g->vol[j]) * Rsum * ((g->alpha_A - g->alpha_B) / g->alpha_A);
+    g->D[j] = Dj;
+    g->emitted += Dj;
+}
+
+static void deliver(ora_grid *g, int64_t e, int32_t b, double v);
+
+/* Send last sweep's recombination photons: each vertex to all neighbours. */
+static void diffuse_send(ora_grid *g) {
+    if (g->alpha_A <= 0.0) return;
+    for (int64_t i = 0; i < g->n; i++) {
+        double Di = g->D[i];
+        if (Di == 0.0) continue;
+        g->D[i] = 0.0;
+        int64_t b = g->ptr[i], deg = g->ptr[i + 1] - g->ptr[i];
+        if (deg == 0) { g->escaped += Di; continue; }
+        double share = Di / (double)deg;
+        for (int64_t e = b; e < b + deg; e++) {
+            if (g->combined) deliver(g, e, g->ebin[e], share);
+            else g->I[(int64_t)g->nbr[e] * g->K + g->ebin[e]] += share;
+        }
+    }
+}
+
+static double pending_diffuse(const ora_grid *g) {
+    double f = 0.0;
+    if (g->alpha_A > 0.0)
+        for (int64_t j = 0; j < g->n; j++) f += g->D[j];
+    return f;
+}
+
+/* ---------------------------------------------------------------------- */
 /* One radiative-transfer time step: photons move one Delaunay edge and
  * interact once, at the vertex they arrive at (Sect. 4.6). */
 static void sweep(ora_grid *g) {
@@ -375,6 +431,7 @@ static void sweep(ora_grid *g) {
             }
         }
     }
+    diffuse_send(g);
 
     /* Interaction and chemistry at every vertex, then the outgoing photons
      * of every bin are split equally over its selected neighbours; a bin
@@ -383,10 +440,11 @@ static void sweep(ora_grid *g) {
         double nin = 0.0;
         for (int64_t k = 0; k < K; k++) nin += g->I[j * K + k];
         g->nin[j] = nin;
-        double A, T;
+        double A, T, R;
         g->y[j] = chem(g->y[j], nin, g->dt, g->nH[j] * g->vol[j], g->tau[j],
-                       g->alpha_B * g->nH[j], g->n_sub, &A, &T);
+                       recomb_coeff(g) * g->nH[j], g->n_sub, &A, &T, &R);
         g->absorbed += A;
+        diffuse_made(g, j, R);
         for (int64_t k = 0; k < K; k++) {
             double out = g->I[j * K + k] * T;
             int32_t mm = g->m[j * K + k];
@@ -404,7 +462,7 @@ static void sweep(ora_grid *g) {
     for (int64_t j = 0; j < n; j++)
         for (int64_t k = 0; k < K; k++)
             f += g->O[j * K + k] * (double)g->m[j * K + k];
-    g->in_flight = f;
+    g->in_flight = f + pending_diffuse(g);
     g->sweeps += 1.0;
 }
 
@@ -518,6 +576,7 @@ static void sweep_combined(ora_grid *g) {
             }
         }
     }
+    diffuse_send(g);
 
     /* Interaction, then the outgoing photons in the vertex's mode. */
     for (int64_t j = 0; j < n; j++) {
@@ -527,10 +586,11 @@ static void sweep_combined(ora_grid *g) {
         else
             for (int64_t e = g->ptr[j]; e < g->ptr[j + 1]; e++) nin += g->Ie[e];
         g->nin[j] = nin;
-        double A, T;
+        double A, T, R;
         g->y[j] = chem(g->y[j], nin, g->dt, g->nH[j] * g->vol[j], g->tau[j],
-                       g->alpha_B * g->nH[j], g->n_sub, &A, &T);
+                       recomb_coeff(g) * g->nH[j], g->n_sub, &A, &T, &R);
         g->absorbed += A;
+        diffuse_made(g, j, R);
         for (int64_t k = 0; k < K; k++) g->O[j * K + k] = 0.0;
         for (int64_t e = g->ptr[j]; e < g->ptr[j + 1]; e++) g->Oe[e] = 0.0;
         if (g->mode[j] == 0) {
@@ -555,8 +615,29 @@ static void sweep_combined(ora_grid *g) {
         for (int64_t k = 0; k < K; k++)
             f += g->O[j * K + k] * (double)g->m[j * K + k];
     for (int64_t e = 0; e < E; e++) f += g->Oe[e] * (double)g->bm[e];
-    g->in_flight = f;
+    g->in_flight = f + pending_diffuse(g);
     g->sweeps += 1.0;
+}
+
+int ora_set_diffuse(ora_grid *g, double alpha_A) {
+    g_err[0] = 0;
+    if (!(alpha_A == 0.0 || alpha_A >= g->alpha_B)) {
+        snprintf(g_err, sizeof g_err, "alpha_A must be 0 or >= alpha_B");
+        return -1;
+    }
+    g->alpha_A = alpha_A;
+    if (alpha_A > 0.0 && !g->D) g->D = (double *)xcalloc(g->n, sizeof(double));
+    return 0;
+}
+
+void ora_get_diffuse(const ora_grid *g, double *pending) {
+    if (!pending) return;
+    for (int64_t j = 0; j < g->n; j++) pending[j] = g->D ? g->D[j] : 0.0;
+}
+
+void ora_set_diffuse_pending(ora_grid *g, const double *pending) {
+    if (!g->D || !pending) return;
+    memcpy(g->D, pending, (size_t)g->n * sizeof(double));
 }
 
 int ora_set_dct_reference(ora_grid *g, int32_t edge) {
@@ -709,6 +790,6 @@ void ora_free(ora_grid *g) {
     free(g->m); free(g->ebin); free(g->src_v); free(g->src_rate);
     free(g->src_dir); free(g->y); free(g->O); free(g->I); free(g->nin);
     free(g->rev); free(g->bsel); free(g->bm); free(g->Oe); free(g->Ie);
-    free(g->layout); free(g->mode);
+    free(g->layout); free(g->mode); free(g->D);
     free(g);
 }

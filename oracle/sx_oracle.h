@@ -68,6 +68,20 @@ int ora_rotate(ora_grid *g, const double *R);
 void ora_get_tables(const ora_grid *g, int32_t *sel_nbr, int32_t *sel_m,
                     int32_t *edge_bin, double *dL, double *tau);
 
+/* Diffuse recombination radiation (Sects. 2.2.1, 4.2).  alpha_A > 0
+ * (>= alpha_B): the rate equation recombines with alpha_A, and each sweep's
+ * recombinations straight to the ground level, (alpha_A - alpha_B)/alpha_A
+ * of all, become photons that the vertex sends at the next sweep, equally
+ * to all its neighbours (filed like those of a source).  They count as
+ * emitted when produced and in flight until sent.  alpha_A = 0: on the spot
+ * (alpha_B, no diffuse photons).  Returns 0, or -1 for a bad argument. */
+int ora_set_diffuse(ora_grid *g, double alpha_A);
+
+/* Recombination photons produced in the last sweep, to be sent in the next
+ * one [N] (zeros while off); and their restore. */
+void ora_get_diffuse(const ora_grid *g, double *pending);
+void ora_set_diffuse_pending(ora_grid *g, const double *pending);
+
 /* Reference direction of the bin selection: edge = 0 (default) the bin's
  * own direction u_k; edge = 1 the vertex's Delaunay edge closest to u_k
  * (largest cosine, > cos_min, ties to the lower id): the bin then goes to

@@ -25,6 +25,7 @@ MYR_S = 3.15576e13          # 1 Myr (Julian years) in s
 # 13.6 eV photons, T = 1e4 K, case-B recombination.
 SIGMA_H = 6.3e-18           # cm^2, Eq. (cross_section) at the Lyman limit
 ALPHA_B = 2.59e-13          # cm^3 s^-1, case B at 1e4 K
+ALPHA_A = 4.18e-13          # cm^3 s^-1, case A (all levels) at 1e4 K
 
 SX_FP64 = 0
 SX_FP32_TRANSPORT = 1
@@ -62,6 +63,7 @@ class Workload:
     transport: int = SX_TRANSPORT_DCT
     tau_switch: float = 1.0
     dct_reference: int = SX_DCT_REF_BIN
+    alpha_A: float = 0.0             # > 0: diffuse recombination radiation
     box: float = 0.0
     meta: dict = field(default_factory=dict)
 

@@ -306,6 +306,104 @@ def pin_edge_reference_brute_force(lib=None):
         assert np.array_equal(t["sel_nbr"], sel), w.name
 
 
+# ------------------------------------------------------- diffuse radiation ---
+
+def pin_diffuse_off_is_on_the_spot(lib=None):
+    """alpha_A = alpha_B: no ground-level recombination photons, the run is
+    the on-the-spot run to the last bit."""
+    w = G.small_random(300, seed=17, n_bins=21, box=3e21, rate=1e46, n_src=2, dt=3e13)
+    a = Oracle(w, lib)
+    a.run(10)
+    b = Oracle(G.with_(w, alpha_A=w.alpha_B), lib)
+    b.run(10)
+    sa, sb = a.state(), b.state()
+    assert np.array_equal(sa["y"], sb["y"]) and np.array_equal(sa["photons"], sb["photons"])
+    assert sa["tallies"] == sb["tallies"]
+
+
+def pin_diffuse_recombination_budget(lib=None):
+    """No sources and no absorption (sigma = 0), fully ionised start: each
+    step's recombination photons are the ground-level share of the atoms
+    that recombined, sum_j n_H V dy (alpha_A - alpha_B) / alpha_A, and the
+    neutral fraction follows the case-A recombination law."""
+    w = G.small_random(200, seed=18, n_bins=21, box=3e21, n_H=1e-3, rate=1e46, n_src=1,
+                       dt=3e14)
+    w = G.with_(w, src_vertex=np.zeros(0, np.int32), src_rate=np.zeros(0), sigma=0.0,
+                x_init=np.ones(w.n), alpha_A=G.ALPHA_A, n_subcycles=50)
+    o = Oracle(w, lib)
+    nhv = w.n_H * w.volume
+    frac = (G.ALPHA_A - G.ALPHA_B) / G.ALPHA_A
+    y_prev = o.state()["y"]
+    em_prev = 0.0
+    for step in range(1, 6):
+        o.run(1)
+        st = o.state()
+        made = st["tallies"]["emitted"] - em_prev
+        want = float(np.sum(nhv * (st["y"] - y_prev))) * frac
+        assert abs(made - want) <= 1e-10 * want, (step, made, want)
+        y_prev, em_prev = st["y"], st["tallies"]["emitted"]
+    x_law = A.recombination_only(1.0, G.ALPHA_A * w.n_H, 5 * w.dt)
+    assert np.all(np.abs((1.0 - st["y"]) - x_law) <= 2e-3 * x_law)
+
+
+def pin_diffuse_lattice(lib=None):
+    """One ionised vertex at the centre of a lattice with six axis bins, no
+    absorption: its recombination photons of the first step leave in the
+    second, one sixth along each axis, filed in that axis's bin."""
+    w = G.lattice_graph(7)
+    c = int(w.src_vertex[0])
+    x0 = np.zeros(w.n)
+    x0[c] = 1.0
+    w = G.with_(w, src_vertex=np.zeros(0, np.int32), src_rate=np.zeros(0), sigma=0.0,
+                x_init=x0, alpha_A=G.ALPHA_A, n_H=np.full(w.n, 1e3), dt=1e9)
+    o = Oracle(w, lib)
+    o.run(1)
+    d1 = o.state()["tallies"]["emitted"]
+    assert d1 > 0 and np.array_equal(o.state()["photons"], np.zeros((w.n, 6)))
+    o.run(1)
+    ph = o.state()["photons"]
+    L = 7
+    for a, d in enumerate([(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]):
+        p = np.array(np.unravel_index(c, (L, L, L))) + np.array(d)
+        nb = int(np.ravel_multi_index(p, (L, L, L)))
+        assert ph[nb, a] == d1 / 6.0, (a, ph[nb, a], d1 / 6.0)
+        assert np.count_nonzero(ph[nb]) == 1
+    assert np.count_nonzero(ph) == 6
+
+
+def pin_diffuse_conservation(lib=None):
+    """Sources plus recombination photons: emitted (both) = absorbed +
+    escaped + in flight at every step, in both transport modes."""
+    w = G.small_random(500, seed=19, n_bins=42, box=3e21, n_H=1e-3, rate=1e46, n_src=3,
+                       dt=3e13)
+    for ww in (G.with_(w, alpha_A=G.ALPHA_A),
+               G.with_(w, alpha_A=G.ALPHA_A, transport=G.SX_TRANSPORT_COMBINED, tau_switch=1.0)):
+        h = Oracle(ww, lib).run(30, history=True)
+        res = h[:, 0] - (h[:, 1] + h[:, 2] + h[:, 3])
+        assert np.all(np.abs(res) <= 1e-12 * h[:, 0]), res / h[:, 0]
+        assert h[-1, 0] > 1.001 * 30 * 3 * 1e46 * 3e13    # recombination photons add
+
+
+def pin_diffuse_front_follows_case_b(lib=None):
+    """With the ground-level photons transported, the ionised region grows
+    like the on-the-spot (case B) law, not like case A without them
+    (Sect. 4.2: on the spot stands in for this diffuse transport)."""
+    w = G.config1()
+    nh, rate = w.meta["n_H"], w.meta["rate"]
+    r_b = A.stromgren_radius(rate, nh, G.ALPHA_B)
+    t_b = A.recombination_time(nh, G.ALPHA_B)
+    out = {}
+    for name, ww in (("diffuse", G.with_(w, alpha_A=G.ALPHA_A)),
+                     ("case_a", G.with_(w, alpha_B=G.ALPHA_A))):
+        o = Oracle(ww, lib)
+        o.run(w.n_sweeps)
+        out[name] = A.ionised_volume_radius(w.volume, o.state()["x"]) / \
+            A.front_radius(w.n_sweeps * w.dt, r_b, t_b)
+    assert abs(out["diffuse"] - 1.0) <= 0.08, out
+    assert out["diffuse"] > out["case_a"] + 0.1, out
+    return out
+
+
 # ------------------------------------------------------ combined transport ---
 
 def pin_combined_off_is_dct(lib=None):
@@ -467,4 +565,6 @@ FAST_PINS = [pin_recombination_closed_form, pin_equilibrium_fixed_point,
              pin_selection_brute_force, pin_axis_star, pin_ties,
              pin_chain_hops, pin_conservation, pin_combined_off_is_dct,
              pin_ballistic_brute_force, pin_combined_lattice,
-             pin_combined_conservation, pin_edge_reference_brute_force]
+             pin_combined_conservation, pin_edge_reference_brute_force,
+             pin_diffuse_off_is_on_the_spot, pin_diffuse_recombination_budget,
+             pin_diffuse_lattice, pin_diffuse_conservation]

@@ -52,6 +52,13 @@ MUTANTS = {
                               "if (best >= 0) c = select_slots(g, i, ref, slots);"),
     "edge_reference_admits_backward": ("double cb = g->cos_min;\n                for (int64_t s = 0;",
                                        "double cb = -2.0;\n                for (int64_t s = 0;"),
+    "diffuse_not_split": ("double share = Di / (double)deg;", "double share = Di;"),
+    "diffuse_chemistry_case_b": ("return g->alpha_A > 0.0 ? g->alpha_A : g->alpha_B;",
+                                 "return g->alpha_B;"),
+    "diffuse_all_recombinations": ("* ((g->alpha_A - g->alpha_B) / g->alpha_A);", "* 1.0;"),
+    "diffuse_not_counted": ("    g->emitted += Dj;\n", "\n"),
+    "diffuse_sent_late": ("    diffuse_send(g);\n\n    /* Interaction and chemistry at every vertex",
+                          "\n    /* Interaction and chemistry at every vertex"),
     "nin_skips_first_bin": ("\n        for (int64_t k = 0; k < K; k++) nin += g->I[j * K + k];",
                             "\n        for (int64_t k = 1; k < K; k++) nin += g->I[j * K + k];"),
 }

@@ -48,6 +48,10 @@ def test_front_law_combined(tau_switch):
     assert worst < 0.08
 
 
+def test_diffuse_front_follows_case_b():
+    P.pin_diffuse_front_follows_case_b()
+
+
 def test_one_over_r2():
     P.pin_one_over_r2()
 
