@@ -296,6 +296,45 @@ def combined_leg(ctx, w, tau_switch: float, log, prof):
     return res
 
 
+def diffuse_leg(ctx, w, log, prof):
+    """The same Stromgren solve off the spot: case-A chemistry and the
+    ground-level recombination photons transported (direction-conserving
+    transport).  Throughput in the headline's units, the kernel's average
+    time, the share of recombination photons among those emitted, and the
+    front radius against the on-the-spot (case-B) law it should follow."""
+    import numpy as np
+    from paper_0912_4273_amd import gridgen as G
+    wd = G.with_(w, alpha_A=G.ALPHA_A)
+    gid = ctx.upload(wd)
+    ctx.solve([gid], 20)
+    ctx.reset(gid)
+    ctx.sync()
+    prof(True)
+    t0 = time.perf_counter()
+    ctx.step([gid], w.n_sweeps)
+    st = ctx.state(gid, nin=False)
+    el = time.perf_counter() - t0
+    pr = prof(False)
+    ctx.free(gid)
+    r_s = (3 * w.meta["rate"] / (4 * math.pi * w.alpha_B * w.meta["n_H"] ** 2)) ** (1 / 3)
+    t_rec = 1.0 / (w.alpha_B * w.meta["n_H"])
+    rv = (3 / (4 * math.pi) * float(np.sum(w.volume * st["x"]))) ** (1 / 3)
+    tl = st["tallies"]
+    src = w.meta["rate"] * w.dt * w.n_sweeps
+    res = dict(value=w.n * w.k * w.n_sweeps / el, unit="vertex·direction updates/s",
+               alpha_A=G.ALPHA_A, ms_per_solve=1e3 * el,
+               sweep_kernel_us=1e3 * pr["total_ms"] / max(pr["launches"], 1),
+               recombination_photon_share=round((tl["emitted"] - src) / tl["emitted"], 4),
+               front_radius_over_case_b_law=round(
+                   rv / (r_s * (1 - math.exp(-w.n_sweeps * w.dt / t_rec)) ** (1 / 3)), 4),
+               conservation_residual=abs(tl["emitted"] - tl["absorbed"] - tl["escaped"]
+                                         - tl["in_flight"]) / tl["emitted"])
+    log(f"diffuse radiation: {res['value']:.3e} updates/s, sweep {res['sweep_kernel_us']:.1f} us, "
+        f"recombination photons {res['recombination_photon_share']}, front/case-B "
+        f"{res['front_radius_over_case_b_law']}")
+    return res
+
+
 def cpu_baseline(w, sweeps: int):
     """The FP64 oracle (single thread) on the same grid, from the initial
     state, for a bounded number of sweeps."""
@@ -345,6 +384,8 @@ def main():
                          "(0 = skip the leg)")
     ap.add_argument("--combined-tau", type=float, default=1.0,
                     help="switch of the combined-transport leg (negative: skip the leg)")
+    ap.add_argument("--no-diffuse", action="store_true",
+                    help="skip the diffuse-recombination-radiation leg")
     ap.add_argument("--graph-sweeps", type=int, default=50,
                     help="sweeps per replayed HIP graph (0: one launch per sweep)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -526,6 +567,10 @@ def main():
     if args.combined_tau >= 0:
         combined = combined_leg(ctx, w, args.combined_tau, log, prof)
 
+    diffused = None
+    if not args.no_diffuse:
+        diffused = diffuse_leg(ctx, w, log, prof)
+
     shadowed = None
     if shadow is not None:
         shadowed = shadow_leg(ctx, shadow, log, prof)
@@ -592,6 +637,7 @@ def main():
         "shadow": shadowed,
         "rotated": rotated,
         "combined": combined,
+        "diffuse": diffused,
         "upload_s": up_s,
         "sweep_kernel_us": 1e3 * kern_ms,
         "roofline": roof,

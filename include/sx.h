@@ -140,6 +140,17 @@ typedef struct sx_grid_desc {
     double tau_switch;           /* combined transport: ballistic where
                                     y tau >= tau_switch (not NaN; +inf =
                                     never)                                   */
+    double alpha_A;              /* 0: on the spot (alpha_B).  > 0 (>=
+                                    alpha_B): diffuse recombination
+                                    radiation, Sects. 2.2.1, 4.2: the rate
+                                    equation recombines with alpha_A, and a
+                                    vertex's recombinations straight to the
+                                    ground level in a step, (alpha_A -
+                                    alpha_B) / alpha_A of all, become photons
+                                    it sends at the next step, equally to
+                                    all its neighbours, filed like those of
+                                    a source.  They count as emitted when
+                                    made and in flight until sent            */
 } sx_grid_desc;
 
 /* Cumulative photon accounting of one grid (photons, double). */
@@ -290,6 +301,11 @@ int sx_read_edge_state(sx_ctx *ctx, sx_grid_id id, double *photons_e,
  * grid, negative or non-finite photons, layout not 0/1), SX_ENOTFOUND. */
 int sx_grid_restore_edges(sx_ctx *ctx, sx_grid_id id, const double *photons_e,
                           const uint8_t *layout);
+
+/* Diffuse recombination radiation: the photons each vertex made in the last
+ * step and sends at the next one [N] (caller's order; zeros without diffuse
+ * radiation).  sx_grid_restore clears them.  Synchronous. */
+int sx_read_diffuse(sx_ctx *ctx, sx_grid_id id, double *pending);
 
 /* Ballistic tables in the caller's order (nullable): bsel [E*3] the
  * neighbour ids chosen for the packet that arrives along each edge slot

@@ -59,6 +59,7 @@ struct Grid {
   bool rotated = false;
   bool ebin_stale = false;
   std::vector<uint8_t> tile_direct;
+  int32_t transport = SX_TRANSPORT_DCT;   // as uploaded (the kernel class may differ)
   std::vector<int32_t> bsel_h;   // combined transport: [3E] chosen out-edges per in-edge, -1 pad
   std::vector<uint8_t> bm_h;     // [E]
 };
@@ -263,6 +264,8 @@ int validate(sx_ctx *ctx, const sx_grid_desc *d) {
     return fail(ctx, SX_EINVAL, "transport must be SX_TRANSPORT_DCT or SX_TRANSPORT_COMBINED");
   if (d->transport == SX_TRANSPORT_COMBINED && std::isnan(d->tau_switch))
     return fail(ctx, SX_EINVAL, "tau_switch is NaN");
+  if (!(d->alpha_A == 0.0 || (std::isfinite(d->alpha_A) && d->alpha_A >= d->alpha_B)))
+    return fail(ctx, SX_EINVAL, "alpha_A must be 0 or finite and >= alpha_B");
   if (d->dct_reference != SX_DCT_REF_BIN && d->dct_reference != SX_DCT_REF_EDGE)
     return fail(ctx, SX_EINVAL, "dct_reference must be SX_DCT_REF_BIN or SX_DCT_REF_EDGE");
   const int K = d->n_bins;
@@ -353,7 +356,8 @@ int validate(sx_ctx *ctx, const sx_grid_desc *d) {
 
 struct Sizes {
   int64_t n, npad, ntiles, E, K, kw, sp, bb, kb;
-  int32_t transport, mpb;
+  int32_t transport, mpb;   // transport: the kernel class (1 also for diffuse radiation)
+  bool diffuse;
 };
 
 Sizes sizes_of(const sx_grid_desc *d) {
@@ -367,7 +371,9 @@ Sizes sizes_of(const sx_grid_desc *d) {
   s.sp = d->precision == SX_FP64 ? 8 : 4;
   s.bb = sx::kBlockBytes / s.sp;
   s.kb = (s.K + s.bb - 1) / s.bb;
-  s.transport = d->transport;
+  s.diffuse = d->alpha_A > 0.0;
+  s.transport = (d->transport == SX_TRANSPORT_COMBINED || s.diffuse) ? SX_TRANSPORT_COMBINED
+                                                                     : SX_TRANSPORT_DCT;
   s.mpb = d->max_per_bin;
   return s;
 }
@@ -393,6 +399,8 @@ uint64_t bytes_estimate(const Sizes &s, int64_t n_em, int64_t n_rec, int64_t n_h
          rnd((uint64_t)sx::kBlockBytes * s.kb * (s.npad + sx::kTile)) +
          2 * rnd(s.npad);
   }
+  if (s.diffuse) b += rnd(8 * s.npad) + 2 * rnd((uint64_t)s.sp * (s.npad + sx::kTile)) +
+                     rnd(8 * s.ntiles);
   return b;
 }
 
@@ -489,8 +497,9 @@ struct sx_prepared {
   std::vector<double> tau, dtnhv, bco, y0;
   std::vector<int32_t> em_ptr, em_k, em_edge;
   std::vector<double> em_amt;
-  int32_t transport = 0, dct_ref = 0;
-  double tau_switch = 0.0;
+  int32_t transport = 0, dct_ref = 0;   // transport: the kernel class
+  double tau_switch = 0.0, alpha_A = 0.0, alpha_B = 0.0;
+  std::vector<double> nhv;
   std::vector<int32_t> bl_ptr;   // combined transport: ballistic lists by in-edge
   std::vector<int32_t> bl;
   std::vector<uint8_t> elane, ebin_in;
@@ -650,7 +659,7 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
     tau[(size_t)v] = (d->n_H[i] * d->sigma) * dl;
     g->tau_h[(size_t)v] = tau[(size_t)v];
     dtnhv[(size_t)v] = d->dt * (d->n_H[i] * d->volume[i]);
-    bco[(size_t)v] = d->alpha_B * d->n_H[i];
+    bco[(size_t)v] = (d->alpha_A > 0.0 ? d->alpha_A : d->alpha_B) * d->n_H[i];
     y0[(size_t)v] = d->x_init ? 1.0 - d->x_init[i] : 1.0;
   }
   // ---- photon unit: the power of two nearest the photons emitted per step
@@ -757,10 +766,22 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
   // along each of its edges (it keeps the direction nbr -> v, the opposite
   // of the edge's unit vector), and per receiving in-edge the list of the
   // sender's edges whose packets it gets, ascending
-  P->transport = d->transport;
-  P->tau_switch = d->tau_switch;
+  P->transport = S.transport;
+  g->transport = d->transport;
+  // diffuse radiation runs in the combined-transport kernel; without
+  // combined transport no vertex turns ballistic
+  P->tau_switch = d->transport == SX_TRANSPORT_COMBINED ? d->tau_switch : INFINITY;
   P->dct_ref = d->dct_reference;
-  if (d->transport == SX_TRANSPORT_COMBINED) {
+  P->alpha_A = d->alpha_A;
+  P->alpha_B = d->alpha_B;
+  if (d->alpha_A > 0.0) {
+    P->nhv.assign((size_t)npad, 0.0);
+    for (int64_t v = 0; v < n; ++v) {
+      const int32_t i = g->perm[(size_t)v];
+      P->nhv[(size_t)v] = d->n_H[i] * d->volume[i];
+    }
+  }
+  if (S.transport == SX_TRANSPORT_COMBINED) {
     g->bsel_h.assign((size_t)(3 * E), -1);
     g->bm_h.assign((size_t)E, 0);
     std::vector<int32_t> &blp = P->bl_ptr;
@@ -849,6 +870,8 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   h.n_edges = E;
   h.transport = P->transport;
   h.dct_ref = P->dct_ref;
+  h.diffuse = P->alpha_A > 0.0 ? 1 : 0;
+  h.dfrac = P->alpha_A > 0.0 ? (P->alpha_A - P->alpha_B) / P->alpha_A : 0.0;
   h.tau_switch = P->transport == SX_TRANSPORT_COMBINED ? P->tau_switch : 0.0;
   int32_t *d_rp, *d_nbr, *d_rec_cnt, *d_rec_ptr, *d_hptr, *d_hvid;
   uint8_t *d_rev, *d_ebin, *d_tdir;
@@ -1082,6 +1105,20 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
     h.lay[0] = d_l0;
     h.lay[1] = d_l1;
   }
+  if (h.diffuse) {
+    double *d_nhv, *d_dt;
+    uint8_t *d_s0, *d_s1;
+    GA(d_nhv, npad);
+    GA(d_dt, ntiles);
+    GA(d_s0, (uint64_t)S.sp * (npad + sx::kTile));
+    GA(d_s1, (uint64_t)S.sp * (npad + sx::kTile));
+    UP(d_nhv, P->nhv.data(), 8 * npad);
+    if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
+    h.nhv = d_nhv;
+    h.dtally = d_dt;
+    h.dsh[0] = d_s0;
+    h.dsh[1] = d_s1;
+  }
 
 #undef GA
 #undef UP
@@ -1103,7 +1140,7 @@ static int combined_grid(sx_ctx *ctx, sx_grid_id id, Grid **out) {
   if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
   Grid *g = find(ctx, id);
   if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
-  if (g->hg.transport != SX_TRANSPORT_COMBINED)
+  if (g->transport != SX_TRANSPORT_COMBINED)
     return fail(ctx, SX_EINVAL, "grid %lld does not use combined transport", (long long)id);
   *out = g;
   return SX_OK;
@@ -1289,7 +1326,7 @@ int sx_rotate_bins(sx_ctx *ctx, sx_grid_id id, const double *R) {
   Grid *g = find(ctx, id);
   if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
   if (g->hg.transport != SX_TRANSPORT_DCT)
-    return fail(ctx, SX_ENOTSUP, "rotating the bins of a combined-transport grid");
+    return fail(ctx, SX_ENOTSUP, "rotating the bins of a combined-transport or diffuse grid");
   if (!R) return fail(ctx, SX_EINVAL, "null rotation");
   // a rotation: orthonormal rows, determinant +1
   for (int i = 0; i < 9; ++i)
@@ -1809,7 +1846,14 @@ int sx_read_state(sx_ctx *ctx, sx_grid_id id, const sx_state_out *out) {
     const double sw = (double)cur.sweeps;
     const double since = sw - g->base_sweeps;
     out->tally->sweeps = sw;
-    out->tally->emitted = g->base_emitted + since * g->e_sweep;
+    double made = 0.0;
+    if (h.diffuse) {
+      std::vector<double> dt((size_t)h.ntiles);
+      HIP_TRY(ctx, hipMemcpyAsync(dt.data(), h.dtally, 8 * h.ntiles, hipMemcpyDeviceToHost, st));
+      HIP_TRY(ctx, hipStreamSynchronize(st));
+      for (double v : dt) made += v;
+    }
+    out->tally->emitted = g->base_emitted + since * g->e_sweep + made * h.unit;
     out->tally->absorbed = a * h.unit;
     out->tally->escaped = g->base_escaped + e * h.unit + since * g->esc_emit;
     out->tally->in_flight = f * h.unit;
@@ -1878,6 +1922,10 @@ int sx_grid_restore(sx_ctx *ctx, sx_grid_id id, const sx_state_in *in) {
     g->base_sweeps = in->tally->sweeps;
     g->base_emitted = in->tally->emitted;
     g->base_escaped = in->tally->escaped;
+    if (h.diffuse) {
+      HIP_TRY(ctx, hipMemset(h.dtally, 0, 8 * h.ntiles));
+      HIP_TRY(ctx, hipMemset(h.dsh[cur.parity], 0, (size_t)(h.precision == SX_FP64 ? 8 : 4) * h.plane));
+    }
     cur.sweeps = (int64_t)in->tally->sweeps;
     HIP_TRY(ctx, hipMemcpy(&ctx->table[g->slot].sweeps, &cur.sweeps, sizeof(int64_t),
                            hipMemcpyHostToDevice));
@@ -2028,6 +2076,39 @@ int sx_grid_restore_edges(sx_ctx *ctx, sx_grid_id id, const double *photons_e,
   if (r) return r;
   HIP_TRY(ctx, hipMemcpy(h.lay[par], lay.data(), npad, hipMemcpyHostToDevice));
   return SX_OK;
+}
+
+int sx_read_diffuse(sx_ctx *ctx, sx_grid_id id, double *pending) {
+  if (!ctx || !pending) return SX_EINVAL;
+  if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
+  Grid *g = find(ctx, id);
+  if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
+  const GridDev &h = g->hg;
+  const int64_t n = h.n;
+  if (!h.diffuse) {
+    for (int64_t i = 0; i < n; ++i) pending[i] = 0.0;
+    return SX_OK;
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  GridDev cur;
+  HIP_TRY(ctx, hipMemcpyAsync(&cur, ctx->table + g->slot, sizeof cur, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  const std::vector<int32_t> &rp = g->row_ptr_h;
+  auto get = [&](auto zero) -> int {
+    using T = decltype(zero);
+    std::vector<T> d((size_t)h.plane);
+    HIP_TRY(ctx, hipMemcpyAsync(d.data(), h.dsh[cur.parity], sizeof(T) * h.plane,
+                                hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t v = g->inv[(size_t)i];
+      const int deg = rp[(size_t)v + 1] - rp[(size_t)v];
+      pending[i] = (double)d[(size_t)v] * (deg > 0 ? (double)deg : 1.0) * h.unit;
+    }
+    return SX_OK;
+  };
+  return h.precision == SX_FP64 ? get(0.0) : get(0.0f);
 }
 
 int sx_read_ballistic(sx_ctx *ctx, sx_grid_id id, int32_t *bsel, int32_t *bm) {

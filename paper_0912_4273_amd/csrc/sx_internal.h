@@ -116,6 +116,14 @@ struct GridDev {
                             // packets go to j
   const uint8_t *elane;     // [E] lane (vertex mod 64) of each edge's row
   const uint8_t *ebin_in;   // [E] bin of the edge i -> j, for the in-edge (j, slot of i)
+  int32_t diffuse;          // recombination photons re-emitted (alpha_A > 0)
+  int32_t pad1;
+  double dfrac;             // (alpha_A - alpha_B) / alpha_A
+  const double *nhv;        // [npad] n_H V
+  void *dsh[2];             // [plane] photons / unit each neighbour gets next
+                            // step from the vertex's recombinations (the whole
+                            // amount for a vertex with no neighbour)
+  double *dtally;           // [ntiles] recombination photons made (cum), / unit
   void *xin;                // bin field (layout of o[]): photons from ballistic
                             // senders waiting for their receiver's bin code; zero
                             // between steps

@@ -442,6 +442,31 @@ __device__ __forceinline__ double chem_step(double y, double nin, double dt,
   return y;
 }
 
+// The same with the recombinations per atom of the step, R = sum over the
+// substeps of h b (1 - y')^2 (the b term of each backward-Euler update).
+__device__ __forceinline__ double chem_step_r(double y, double nin, double dt,
+                                              double dtnhv, double tau, double b,
+                                              int n_sub, double &A, double &T,
+                                              double &R) {
+  const double h = dt / (double)n_sub;
+  const double a = nin / dtnhv;
+  const double ha = h * a, hb = h * b;
+  const double share = nin / (double)n_sub;
+  double abs_sum = 0.0, tr_sum = 0.0, rec_sum = 0.0;
+  for (int s = 0; s < n_sub; ++s) {
+    double ion;
+    y = be_substep(y, ha, hb, tau, ion);
+    abs_sum += share * ion;
+    tr_sum += 1.0 - ion;
+    const double x = 1.0 - y;
+    rec_sum += hb * (x * x);
+  }
+  A = abs_sum;
+  T = nin > 0.0 ? tr_sum / (double)n_sub : 1.0;
+  R = rec_sum;
+  return y;
+}
+
 // -------------------------------------------------------------- sweep ---
 // State between steps: for every vertex i and bin k, Ipre[k][i] = I/m, the
 // photons that entered i in bin k divided over its m selected neighbours,
@@ -475,10 +500,61 @@ constexpr int kHaloPlane = kZeroSlot + 1;   // LDS words per staged bin
 template <typename P>
 struct CtIn {
   bool bal = false;
+  double y0 = 1.0;
   P nin_b = P(0), esc_b = P(0);
   uint64_t xmask = 0;   // one bit per 16-byte block (up to 48)
   P *xin = nullptr;
 };
+
+// End of a combined-transport (or diffuse) step for one lane: chemistry,
+// the recombination photons it sends next step, the tile's accounting.
+template <typename P>
+__device__ __forceinline__ void ct_finish(const GridDev *__restrict__ G, int tile, int lane,
+                                          bool valid, double y0, P nin_p, P esc_p) {
+  const int j = tile * kTile + lane;
+  const int par = G->parity;
+  double A = 0.0, T = 1.0, R = 0.0;
+  const double nin = (double)nin_p;
+  double made = 0.0, lost = 0.0;   // recombination photons / unit
+  if (valid) {
+    if (!(nin == 0.0 && y0 == 1.0)) {
+      double yn;
+      if (G->diffuse)
+        yn = chem_step_r(y0, nin * G->unit, G->dt, gld(G->dtnhv)[j], gld(G->tau)[j],
+                         gld(G->bcoef)[j], G->n_sub, A, T, R);
+      else
+        yn = chem_step(y0, nin * G->unit, G->dt, gld(G->dtnhv)[j], gld(G->tau)[j],
+                       gld(G->bcoef)[j], G->n_sub, A, T);
+      gst(G->y)[j] = yn;
+    }
+    gst(G->nin)[j] = nin * G->unit;
+    gst((P *)G->t[par ^ 1])[j] = (P)T;
+    if (G->diffuse) {
+      made = ((gld(G->nhv)[j] * R) * G->dfrac) / G->unit;
+      const int deg = gld(G->row_ptr)[j + 1] - gld(G->row_ptr)[j];
+      // a vertex with no neighbour: what it made last step leaves now
+      if (deg == 0) lost = (double)gld((const P *)G->dsh[par])[j];
+      gst((P *)G->dsh[par ^ 1])[j] = deg > 0 ? (P)(made / (double)deg) : (P)made;
+    }
+  }
+  A /= G->unit;
+  double esc = (double)esc_p * T + lost;
+  double fly = (nin - (double)esc_p) * T + made;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    A += __shfl_xor(A, off);
+    esc += __shfl_xor(esc, off);
+    fly += __shfl_xor(fly, off);
+    made += __shfl_xor(made, off);
+  }
+  if (lane == 0) {
+    SX_G double *t = gst(G->tally) + (int64_t)tile * 3;
+    t[0] += A;
+    t[1] += esc;
+    t[2] = fly;
+    if (G->diffuse) gst(G->dtally)[tile] += made;
+  }
+}
 
 template <typename P, bool DIRECT, bool CT = false>
 __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int tile,
@@ -705,6 +781,8 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
       nin_p = ci.nin_b;
       esc_p = ci.esc_b;
     }
+    ct_finish<P>(G, tile, lane, valid, ci.y0, nin_p, esc_p);
+    return;
   }
   double A = 0.0, T = 1.0;
   const double nin = (double)nin_p;
@@ -870,6 +948,8 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
   const SX_G double *__restrict__ ema = gld(G->em_amt);
   const SX_G int32_t *__restrict__ eme = gld(G->em_edge);
   SX_G P *__restrict__ xin = gst((P *)G->xin);
+  const SX_G P *__restrict__ dshin = gld((const P *)G->dsh[par]);
+  const bool diffuse = G->diffuse != 0;
   // element (v, k) of the bin field
   auto at = [&](uint32_t v, int k) -> uint32_t {
     return (((v >> 6) * (uint32_t)KB + (uint32_t)(k / BB)) * 64u + (v & 63u)) * BB +
@@ -887,7 +967,7 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
   const uint64_t validmask = __ballot(valid);
 
   // 1. direction-conserving transport proper
-  if (balmask == 0 && !direct) {
+  if (balmask == 0 && !direct && !diffuse) {
     const SX_G int32_t *__restrict__ hptr = gld(G->halo_ptr);
     const int hp = hptr[tile];
     const int hlen = hptr[tile + 1] - hp;
@@ -911,7 +991,8 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
   auto edge_in = [&](int e, int r, bool rbal) -> P {
     const int i = nbr[e];
     const bool iedges = lin[i] != 0;
-    P ve = P(0);
+    // the sender's recombination photons of last step, its share per edge
+    P ve = diffuse ? dshin[i] : P(0);
     if (!rbal && !iedges) return ve;
     const P ti = tin[i];
     if (!iedges) {
@@ -955,6 +1036,7 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
   }
   CtIn<P> ci;
   ci.bal = bal;
+  ci.y0 = y0;
   ci.xin = (P *)G->xin;
   if (valid) {
     const int rb = rowp[j], re = rowp[j + 1];
@@ -980,33 +1062,8 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
       for (int kb = 0; kb < KB; ++kb)
         oout[((uint32_t)tile * (uint32_t)KB + (uint32_t)kb) * 64u + (uint32_t)lane] = V(0);
     }
-    double A = 0.0, T = 1.0;
-    const double nin = (double)ci.nin_b;
-    if (valid) {
-      if (!(nin == 0.0 && y0 == 1.0)) {
-        const double yn = chem_step(y0, nin * G->unit, G->dt, gld(G->dtnhv)[j],
-                                    gld(G->tau)[j], gld(G->bcoef)[j], G->n_sub, A, T);
-        gst(G->y)[j] = yn;
-      }
-      gst(G->nin)[j] = nin * G->unit;
-      gst((P *)G->t[par ^ 1])[j] = (P)T;
-      lout[j] = 1;
-    }
-    A /= G->unit;
-    double esc = (double)ci.esc_b * T;
-    double fly = (nin - (double)ci.esc_b) * T;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      A += __shfl_xor(A, off);
-      esc += __shfl_xor(esc, off);
-      fly += __shfl_xor(fly, off);
-    }
-    if (lane == 0) {
-      SX_G double *t = gst(G->tally) + (int64_t)tile * 3;
-      t[0] += A;
-      t[1] += esc;
-      t[2] = fly;
-    }
+    ct_finish<P>(G, tile, lane, valid, y0, ci.nin_b, ci.esc_b);
+    if (valid) lout[j] = 1;
     return;
   }
   if (direct)
@@ -1187,6 +1244,15 @@ hipError_t launch_reset_state(GridDev *dg, const GridDev &hg, const double *y0,
     }
     if (hg.precision == 0) e = fill<double>((double *)hg.xin, 0.0, nk, s);
     else e = fill<float>((float *)hg.xin, 0.0f, nk, s);
+    if (e != hipSuccess) return e;
+  }
+  if (hg.diffuse != 0) {
+    for (int b = 0; b < 2; ++b) {
+      if (hg.precision == 0) e = fill<double>((double *)hg.dsh[b], 0.0, hg.plane, s);
+      else e = fill<float>((float *)hg.dsh[b], 0.0f, hg.plane, s);
+      if (e != hipSuccess) return e;
+    }
+    e = fill<double>(hg.dtally, 0.0, (int64_t)hg.ntiles, s);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_reset, dim3(blocks_for(hg.npad, 256)), dim3(256), 0, s,

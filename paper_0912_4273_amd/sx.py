@@ -42,6 +42,7 @@ EXPORTED = [
     "sx_grid_info", "sx_mem_info", "sx_stream", "sx_profile",
     "sx_profile_read", "sx_set_schedule", "sx_get_schedule", "sx_autotune",
     "sx_rotate_bins", "sx_read_edge_state", "sx_grid_restore_edges", "sx_read_ballistic",
+    "sx_read_diffuse",
     "sx_grid_prepare", "sx_prepared_bytes", "sx_grid_commit", "sx_prepared_free",
     "sx_serve_start", "sx_serve_submit", "sx_serve_poll", "sx_serve_take",
     "sx_serve_stop", "sx_strerror", "sx_last_error",
@@ -71,7 +72,8 @@ class SxGridDesc(C.Structure):
         ("src_dir", C.c_void_p), ("sigma", C.c_double),
         ("alpha_B", C.c_double), ("dt", C.c_double),
         ("precision", C.c_int32), ("transport", C.c_int32),
-        ("dct_reference", C.c_int32), ("tau_switch", C.c_double)]
+        ("dct_reference", C.c_int32), ("tau_switch", C.c_double),
+        ("alpha_A", C.c_double)]
 
 
 class SxTally(C.Structure):
@@ -163,6 +165,7 @@ def load(path: Optional[str] = None):
         "sx_read_edge_state": (C.c_int, [P, I64, P, P]),
         "sx_grid_restore_edges": (C.c_int, [P, I64, P, P]),
         "sx_read_ballistic": (C.c_int, [P, I64, P, P]),
+        "sx_read_diffuse": (C.c_int, [P, I64, P]),
         "sx_grid_prepare": (C.c_int, [C.POINTER(SxGridDesc), C.POINTER(P), C.c_char_p,
                                       C.c_size_t]),
         "sx_prepared_bytes": (C.c_int, [P, C.POINTER(C.c_uint64)]),
@@ -221,7 +224,8 @@ class _Desc:
             alpha_B=float(w.alpha_B), dt=float(w.dt), precision=int(w.precision),
             transport=int(getattr(w, "transport", SX_TRANSPORT_DCT)),
             dct_reference=int(getattr(w, "dct_reference", SX_DCT_REF_BIN)),
-            tau_switch=float(getattr(w, "tau_switch", 1.0)))
+            tau_switch=float(getattr(w, "tau_switch", 1.0)),
+            alpha_A=float(getattr(w, "alpha_A", 0.0)))
 
 
 # ------------------------------------------------------ C entry points ----
@@ -552,6 +556,13 @@ class Context:
 
     def restore_edges(self, gid, photons_e, layout):
         sx_grid_restore_edges(self.h, gid, photons_e, layout)
+
+    def diffuse_pending(self, gid):
+        """Recombination photons each vertex sends at the next step [N]."""
+        n, _, _ = self.shapes[gid]
+        d = np.zeros(n)
+        _check(self.h, load().sx_read_diffuse(self.h, gid, _ptr(d)))
+        return d
 
     def ballistic(self, gid) -> dict:
         _, _, e = self.shapes[gid]

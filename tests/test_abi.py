@@ -71,6 +71,7 @@ def test_null_arguments_rejected_without_device():
     assert lib.sx_read_edge_state(None, 1, None, None) == sx.SX_EINVAL
     assert lib.sx_grid_restore_edges(None, 1, None, None) == sx.SX_EINVAL
     assert lib.sx_read_ballistic(None, 1, None, None) == sx.SX_EINVAL
+    assert lib.sx_read_diffuse(None, 1, None) == sx.SX_EINVAL
     b = C.c_uint64()
     assert lib.sx_grid_bytes(None, C.byref(b)) == sx.SX_EINVAL
 
@@ -97,6 +98,7 @@ int main(void) {
   P(sx_grid_desc, kappa) P(sx_grid_desc, n_bins) P(sx_grid_desc, cos_min)
   P(sx_grid_desc, src_dir) P(sx_grid_desc, dt) P(sx_grid_desc, precision)
   P(sx_grid_desc, transport) P(sx_grid_desc, dct_reference) P(sx_grid_desc, tau_switch)
+  P(sx_grid_desc, alpha_A)
   P(sx_ctx_opts, stream) P(sx_ctx_opts, alloc_user)
   return 0;
 }
@@ -128,7 +130,7 @@ def test_ctypes_struct_layout_matches_c():
         for f in fields:
             assert getattr(cls, f).offset == lay[f"{name}.{f}"], (name, f)
     for f in ("kappa", "n_bins", "cos_min", "src_dir", "dt", "precision", "transport",
-              "dct_reference", "tau_switch"):
+              "dct_reference", "tau_switch", "alpha_A"):
         assert getattr(sx.SxGridDesc, f).offset == lay[f"sx_grid_desc.{f}"], f
     for f in ("stream", "alloc_user"):
         assert getattr(sx.SxCtxOpts, f).offset == lay[f"sx_ctx_opts.{f}"], f

@@ -1,0 +1,135 @@
+"""Diffuse recombination radiation on the GPU against the oracle: whole
+solves in both precisions and both transport modes, one step from a shared
+state (with the photons waiting to be re-emitted), the lattice delivery, and
+the limits."""
+import numpy as np
+import pytest
+
+from paper_0912_4273_amd import gridgen as G
+from paper_0912_4273_amd import sx
+from oracle import Oracle
+from parity import TOL, assert_edges_close, assert_state_close, close
+
+pytestmark = pytest.mark.gpu
+
+
+def _work(n=1500, seed=81, prec=G.SX_FP64, **kw):
+    w = G.small_random(n, seed=seed, n_bins=42, box=3e21, rate=3e45, n_src=3, dt=3e13,
+                       precision=prec)
+    return G.with_(w, alpha_A=G.ALPHA_A, **kw)
+
+
+def _check_pending(got, ref, prec, unit, what):
+    rt, at = TOL[prec]["ph"]
+    ok, nbad, worst = close(got, ref, rt, at * unit)
+    assert ok, f"{what} pending: {nbad} off, worst rel {worst:.3e}"
+
+
+@pytest.mark.parametrize("prec", [G.SX_FP64, G.SX_FP32_TRANSPORT])
+def test_diffuse_solve(sxctx, prec):
+    w = _work(prec=prec)
+    print(f"[case] diffuse, direction-conserving, prec={prec}", flush=True)
+    gid = sxctx.upload(w)
+    try:
+        sxctx.solve([gid], 40)
+        st = sxctx.state(gid, photons=True)
+        pend = sxctx.diffuse_pending(gid)
+        unit = sxctx.info(gid)["photon_unit"]
+    finally:
+        sxctx.free(gid)
+    o = Oracle(w)
+    o.run(40)
+    ref = o.state()
+    rp = o.diffuse_pending()
+    o.close()
+    assert ref["tallies"]["emitted"] > 40 * 3 * 3e45 * 3e13   # recombination photons counted
+    assert_state_close(st, ref, prec, unit, f"diffuse prec {prec}")
+    _check_pending(pend, rp, prec, unit, f"diffuse prec {prec}")
+
+
+def test_diffuse_combined_fp64(sxctx):
+    w = _work(seed=82, transport=G.SX_TRANSPORT_COMBINED, tau_switch=1.0)
+    print("[case] diffuse + combined fp64", flush=True)
+    gid = sxctx.upload(w)
+    try:
+        sxctx.solve([gid], 50)
+        st, es = sxctx.state(gid, photons=True), sxctx.edge_state(gid)
+        pend = sxctx.diffuse_pending(gid)
+        unit = sxctx.info(gid)["photon_unit"]
+    finally:
+        sxctx.free(gid)
+    o = Oracle(w)
+    o.run(50)
+    ref, ref_e, rp = o.state(), o.edge_state(), o.diffuse_pending()
+    o.close()
+    assert es["layout"].any() and (es["layout"] == 0).any()
+    assert_state_close(st, ref, G.SX_FP64, unit, "diffuse combined")
+    assert_edges_close(es, ref_e, G.SX_FP64, unit, "diffuse combined")
+    _check_pending(pend, rp, G.SX_FP64, unit, "diffuse combined")
+
+
+@pytest.mark.parametrize("prec", [G.SX_FP64, G.SX_FP32_TRANSPORT])
+def test_diffuse_one_step_from_shared_state(sxctx, prec):
+    w = _work(2500, seed=83, prec=prec, transport=G.SX_TRANSPORT_COMBINED, tau_switch=1.0)
+    print(f"[case] diffuse one step prec={prec}", flush=True)
+    gid = sxctx.upload(w)
+    try:
+        sxctx.solve([gid], 40)
+        s1, e1, p1 = sxctx.state(gid, photons=True), sxctx.edge_state(gid), sxctx.diffuse_pending(gid)
+        sxctx.solve([gid], 1)
+        s2, e2, p2 = sxctx.state(gid, photons=True), sxctx.edge_state(gid), sxctx.diffuse_pending(gid)
+        unit = sxctx.info(gid)["photon_unit"]
+    finally:
+        sxctx.free(gid)
+    o = Oracle(w)
+    o.set_state(y=s1["y"], photons=s1["photons"], tallies=s1["tallies"])
+    o.set_edge_state(photons_e=e1["photons_e"], layout=e1["layout"].astype(np.int8))
+    o.set_diffuse_pending(p1)
+    o.run(1)
+    ref, ref_e, rp = o.state(), o.edge_state(), o.diffuse_pending()
+    o.close()
+    assert_state_close(s2, ref, prec, unit, f"diffuse one step prec {prec}")
+    assert_edges_close(e2, ref_e, prec, unit, f"diffuse one step prec {prec}")
+    _check_pending(p2, rp, prec, unit, f"diffuse one step prec {prec}")
+
+
+def test_diffuse_lattice_delivery(sxctx):
+    """One ionised vertex, no absorption, six axis bins: what it made in the
+    first step arrives in the second, a sixth along each axis, in that
+    axis's bin."""
+    w = G.lattice_graph(7)
+    c = int(w.src_vertex[0])
+    x0 = np.zeros(w.n)
+    x0[c] = 1.0
+    w = G.with_(w, src_vertex=np.zeros(0, np.int32), src_rate=np.zeros(0), sigma=0.0,
+                x_init=x0, alpha_A=G.ALPHA_A, n_H=np.full(w.n, 1e3), dt=1e9)
+    print("[case] diffuse lattice", flush=True)
+    gid = sxctx.upload(w)
+    try:
+        sxctx.solve([gid], 1)
+        d1 = sxctx.state(gid)["tallies"]["emitted"]
+        sxctx.solve([gid], 1)
+        ph = sxctx.state(gid, photons=True)["photons"]
+    finally:
+        sxctx.free(gid)
+    assert d1 > 0
+    L = 7
+    for a, d in enumerate([(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]):
+        p = np.array(np.unravel_index(c, (L, L, L))) + np.array(d)
+        nb = int(np.ravel_multi_index(p, (L, L, L)))
+        assert abs(ph[nb, a] - d1 / 6.0) <= 1e-14 * d1, (a, ph[nb, a], d1 / 6.0)
+    assert np.count_nonzero(ph) == 6
+
+
+def test_diffuse_limits(sxctx):
+    w = _work(300, seed=84)
+    gid = sxctx.upload(w)
+    try:
+        with pytest.raises(sx.SxError) as e:
+            sxctx.rotate(gid, np.eye(3))
+        assert e.value.code == sx.SX_ENOTSUP
+    finally:
+        sxctx.free(gid)
+    with pytest.raises(sx.SxError) as e:
+        sxctx.upload(G.with_(w, alpha_A=0.5 * w.alpha_B))
+    assert e.value.code == sx.SX_EINVAL
