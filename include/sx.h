@@ -302,6 +302,35 @@ int sx_read_edge_state(sx_ctx *ctx, sx_grid_id id, double *photons_e,
 int sx_grid_restore_edges(sx_ctx *ctx, sx_grid_id id, const double *photons_e,
                           const uint8_t *layout);
 
+/* ---- dynamic grid (Sect. 2.1.4) --------------------------------------------
+ * Between solves a caller may thin the grid where the optical depth has
+ * dropped: choose the vertices to remove, triangulate the rest (on the
+ * host), upload the new grid with the same bins and move the state over.
+ *
+ * sx_grid_select_removal: vertex i is a candidate when its optical depth
+ * y tau (neutral fraction now, tau = n_H sigma dL) is below tau_remove,
+ * its path length dL is below min_spacing (the grid there is finer than the
+ * minimum resolution) and it holds no source.  Candidates are taken in
+ * ascending optical depth (ties: lower id) and kept out when a neighbour
+ * has already been taken, so no two removed vertices are neighbours.
+ * remove [N] (caller's order) receives 1 for removed vertices; n_removed
+ * (nullable) their number.  Synchronous.  Errors: SX_EINVAL (NaN
+ * thresholds), SX_ENOTFOUND. */
+int sx_grid_select_removal(sx_ctx *ctx, sx_grid_id id, double tau_remove,
+                           double min_spacing, uint8_t *remove, int64_t *n_removed);
+
+/* Move the state of grid `from` onto grid `to` (both direction-conserving,
+ * on the spot, the same unrotated bins): new_of_old [N_from] gives each old
+ * vertex's index in `to`, or -1 for a removed one; every vertex of `to`
+ * must be hit once.  Kept vertices keep y.  What a vertex holds in a bin,
+ * m O, stays in that bin with the vertex it maps to (a removed vertex's
+ * goes to its nearest kept former neighbour, ties to the lower id) and is
+ * split over that vertex's selection on the new grid; where none is
+ * selected (or a removed vertex has no kept neighbour) it is counted as
+ * escaped.  Tallies carry over.  Synchronous.  Errors: SX_EINVAL,
+ * SX_ENOTSUP (combined transport or diffuse radiation), SX_ENOTFOUND. */
+int sx_grid_remap(sx_ctx *ctx, sx_grid_id from, sx_grid_id to, const int32_t *new_of_old);
+
 /* Diffuse recombination radiation: the photons each vertex made in the last
  * step and sends at the next one [N] (caller's order; zeros without diffuse
  * radiation).  sx_grid_restore clears them.  Synchronous. */

@@ -48,6 +48,8 @@ struct Grid {
   std::vector<int32_t> nbr_h;
   std::vector<double> dL_h;            // new order
   std::vector<double> tau_h;
+  std::vector<double> elen_h;          // [E] edge lengths, new order
+  std::vector<uint8_t> is_src_h;       // [N] new order: vertex holds a source
   std::vector<DevBuf> bufs;
   uint64_t bytes = 0;
   double *y_init = nullptr;
@@ -547,6 +549,7 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
   std::vector<double> &edir = P->edir;
   edir.assign((size_t)(3 * E), 0.0);
   std::vector<double> len_orig((size_t)E);     // per original CSR position
+  g->elen_h.assign((size_t)E, 0.0);
   {
     std::vector<std::pair<int32_t, int64_t>> row;
     for (int64_t v = 0; v < n; ++v) {
@@ -580,6 +583,7 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
       edir[(size_t)(3 * e + 1)] = dy / len;
       edir[(size_t)(3 * e + 2)] = dz / len;
       len_orig[(size_t)p] = len;
+      g->elen_h[(size_t)e] = len;
     }
   }
   // ---- reverse slots: position of the row's vertex in its neighbour's row
@@ -719,6 +723,8 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
   double esc_emit = 0.0;
   for (int s = 0; s < d->n_src; ++s) {
     const int32_t vi = d->src_vertex[s];
+    if (g->is_src_h.empty()) g->is_src_h.assign((size_t)n, 0);
+    g->is_src_h[(size_t)g->inv[(size_t)vi]] = 1;
     const int32_t v = g->inv[(size_t)vi];
     const double Es = d->src_rate[s] * d->dt;
     const double *u = d->src_dir ? d->src_dir + 3 * s : nullptr;
@@ -2125,6 +2131,125 @@ int sx_read_ballistic(sx_ctx *ctx, sx_grid_id id, int32_t *bsel, int32_t *bm) {
         bsel[3 * p + q] = q < m ? g->perm[(size_t)g->nbr_h[(size_t)g->bsel_h[(size_t)(3 * e + q)]]] : -1;
   }
   return SX_OK;
+}
+
+int sx_grid_select_removal(sx_ctx *ctx, sx_grid_id id, double tau_remove,
+                           double min_spacing, uint8_t *remove, int64_t *n_removed) {
+  if (!ctx || !remove) return SX_EINVAL;
+  if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
+  Grid *g = find(ctx, id);
+  if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
+  if (std::isnan(tau_remove) || std::isnan(min_spacing))
+    return fail(ctx, SX_EINVAL, "tau_remove and min_spacing must not be NaN");
+  const GridDev &h = g->hg;
+  const int64_t n = h.n;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  std::vector<double> y((size_t)h.npad);
+  HIP_TRY(ctx, hipMemcpyAsync(y.data(), h.y, 8 * h.npad, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  // candidates: optically thin, finer than the minimum resolution, no source
+  struct Cand {
+    double od;
+    int32_t orig, v;
+  };
+  std::vector<Cand> c;
+  for (int64_t v = 0; v < n; ++v) {
+    const double od = y[(size_t)v] * g->tau_h[(size_t)v];
+    const bool src = !g->is_src_h.empty() && g->is_src_h[(size_t)v];
+    if (od < tau_remove && g->dL_h[(size_t)v] < min_spacing && !src)
+      c.push_back({od, g->perm[(size_t)v], (int32_t)v});
+  }
+  std::sort(c.begin(), c.end(), [](const Cand &a, const Cand &b) {
+    return a.od < b.od || (a.od == b.od && a.orig < b.orig);
+  });
+  // greedy independent set: no two removed vertices are neighbours
+  std::vector<uint8_t> blocked((size_t)n, 0), rm((size_t)n, 0);
+  int64_t cnt = 0;
+  for (const Cand &q : c) {
+    if (blocked[(size_t)q.v]) continue;
+    rm[(size_t)q.v] = 1;
+    ++cnt;
+    for (int32_t e = g->row_ptr_h[(size_t)q.v]; e < g->row_ptr_h[(size_t)q.v + 1]; ++e)
+      blocked[(size_t)g->nbr_h[(size_t)e]] = 1;
+  }
+  for (int64_t i = 0; i < n; ++i) remove[i] = rm[(size_t)g->inv[(size_t)i]];
+  if (n_removed) *n_removed = cnt;
+  return SX_OK;
+}
+
+int sx_grid_remap(sx_ctx *ctx, sx_grid_id from, sx_grid_id to, const int32_t *new_of_old) {
+  if (!ctx || !new_of_old) return SX_EINVAL;
+  if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
+  Grid *a = find(ctx, from), *b = find(ctx, to);
+  if (!a || !b) return fail(ctx, SX_ENOTFOUND, "grid not found");
+  if (a->hg.transport != SX_TRANSPORT_DCT || b->hg.transport != SX_TRANSPORT_DCT)
+    return fail(ctx, SX_ENOTSUP, "remap needs direction-conserving, on-the-spot grids");
+  const int64_t na = a->hg.n, nb = b->hg.n, K = a->hg.k;
+  if (b->hg.k != K || a->bins0 != b->bins0 || a->rotated || b->rotated)
+    return fail(ctx, SX_EINVAL, "remap needs the same unrotated bins on both grids");
+  std::vector<uint8_t> hit((size_t)nb, 0);
+  for (int64_t i = 0; i < na; ++i) {
+    const int32_t j = new_of_old[i];
+    if (j < -1 || j >= nb) return fail(ctx, SX_EINVAL, "new_of_old[%lld] out of range", (long long)i);
+    if (j >= 0) {
+      if (hit[(size_t)j]) return fail(ctx, SX_EINVAL, "vertex %d of the new grid mapped twice", j);
+      hit[(size_t)j] = 1;
+    }
+  }
+  for (int64_t j = 0; j < nb; ++j)
+    if (!hit[(size_t)j]) return fail(ctx, SX_EINVAL, "vertex %lld of the new grid has no old vertex", (long long)j);
+  std::vector<double> ya((size_t)na), oa((size_t)(na * K));
+  std::vector<int32_t> ma((size_t)(na * K)), mb((size_t)(nb * K));
+  sx_tally t{};
+  sx_state_out so{nullptr, ya.data(), oa.data(), nullptr, &t};
+  int r = sx_read_state(ctx, from, &so);
+  if (!r) r = sx_read_tables(ctx, from, nullptr, ma.data(), nullptr, nullptr, nullptr);
+  if (!r) r = sx_read_tables(ctx, to, nullptr, mb.data(), nullptr, nullptr, nullptr);
+  if (r) return r;
+  // what each vertex holds per bin, m O, moves with it; a removed vertex's
+  // goes to its nearest kept former neighbour (ties: lower id), in the same
+  // bin, added in ascending old id
+  std::vector<double> held((size_t)(nb * K), 0.0), yb((size_t)nb, 1.0);
+  double lost = 0.0;
+  for (int64_t i = 0; i < na; ++i) {
+    int32_t j = new_of_old[i];
+    if (j >= 0) {
+      yb[(size_t)j] = ya[(size_t)i];
+    } else {
+      const int64_t v = a->inv[(size_t)i];
+      double best = 0.0;
+      int32_t bo = -1;
+      for (int32_t e = a->row_ptr_h[(size_t)v]; e < a->row_ptr_h[(size_t)v + 1]; ++e) {
+        const int32_t o = a->perm[(size_t)a->nbr_h[(size_t)e]];
+        if (new_of_old[o] < 0) continue;
+        const double len = a->elen_h[(size_t)e];
+        if (bo < 0 || len < best || (len == best && o < bo)) { best = len; bo = o; }
+      }
+      j = bo >= 0 ? new_of_old[bo] : -1;
+    }
+    for (int64_t k = 0; k < K; ++k) {
+      const double hk = oa[(size_t)(i * K + k)] * (double)ma[(size_t)(i * K + k)];
+      if (j >= 0) held[(size_t)(j * K + k)] += hk;
+      else lost += hk;
+    }
+  }
+  std::vector<double> ob((size_t)(nb * K), 0.0);
+  double fly = 0.0;
+  for (int64_t q = 0; q < nb * K; ++q) {
+    const int32_t m = mb[(size_t)q];
+    if (m > 0) {
+      ob[(size_t)q] = held[(size_t)q] / (double)m;
+      fly += held[(size_t)q];
+    } else {
+      lost += held[(size_t)q];
+    }
+  }
+  sx_tally tb = t;
+  tb.escaped = t.escaped + lost;
+  tb.in_flight = fly;
+  sx_state_in si{yb.data(), ob.data(), &tb};
+  return sx_grid_restore(ctx, to, &si);
 }
 
 int sx_grid_info(sx_ctx *ctx, sx_grid_id id, int64_t *n, int32_t *k, int64_t *n_edges,

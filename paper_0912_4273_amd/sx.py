@@ -42,7 +42,7 @@ EXPORTED = [
     "sx_grid_info", "sx_mem_info", "sx_stream", "sx_profile",
     "sx_profile_read", "sx_set_schedule", "sx_get_schedule", "sx_autotune",
     "sx_rotate_bins", "sx_read_edge_state", "sx_grid_restore_edges", "sx_read_ballistic",
-    "sx_read_diffuse",
+    "sx_read_diffuse", "sx_grid_select_removal", "sx_grid_remap",
     "sx_grid_prepare", "sx_prepared_bytes", "sx_grid_commit", "sx_prepared_free",
     "sx_serve_start", "sx_serve_submit", "sx_serve_poll", "sx_serve_take",
     "sx_serve_stop", "sx_strerror", "sx_last_error",
@@ -166,6 +166,8 @@ def load(path: Optional[str] = None):
         "sx_grid_restore_edges": (C.c_int, [P, I64, P, P]),
         "sx_read_ballistic": (C.c_int, [P, I64, P, P]),
         "sx_read_diffuse": (C.c_int, [P, I64, P]),
+        "sx_grid_select_removal": (C.c_int, [P, I64, C.c_double, C.c_double, P, P]),
+        "sx_grid_remap": (C.c_int, [P, I64, I64, P]),
         "sx_grid_prepare": (C.c_int, [C.POINTER(SxGridDesc), C.POINTER(P), C.c_char_p,
                                       C.c_size_t]),
         "sx_prepared_bytes": (C.c_int, [P, C.POINTER(C.c_uint64)]),
@@ -563,6 +565,21 @@ class Context:
         d = np.zeros(n)
         _check(self.h, load().sx_read_diffuse(self.h, gid, _ptr(d)))
         return d
+
+    def select_removal(self, gid, tau_remove: float, min_spacing: float):
+        """Vertices to remove between solves [N] bool (Sect. 2.1.4)."""
+        n, _, _ = self.shapes[gid]
+        rm = np.zeros(n, np.uint8)
+        cnt = C.c_int64()
+        _check(self.h, load().sx_grid_select_removal(self.h, gid, float(tau_remove),
+                                                     float(min_spacing), _ptr(rm),
+                                                     C.byref(cnt)))
+        return rm.astype(bool)
+
+    def remap(self, src, dst, new_of_old):
+        """Move the state of grid src onto grid dst (new_of_old: -1 removed)."""
+        a = np.ascontiguousarray(new_of_old, np.int32)
+        _check(self.h, load().sx_grid_remap(self.h, src, dst, _ptr(a)))
 
     def ballistic(self, gid) -> dict:
         _, _, e = self.shapes[gid]
