@@ -335,6 +335,67 @@ def diffuse_leg(ctx, w, log, prof):
     return res
 
 
+def regrid_leg(ctx, w, passes: int, n_min: int, tau_remove: float, log, prof):
+    """Dynamic grid (Sect. 2.1.4): half the Stromgren solve, then `passes`
+    thinning passes (vertices with optical depth below tau_remove, down to a
+    minimum resolution of n_min^3 over the box), then the second half on the
+    thinned grid.  Cost of a pass by part, vertices left, step time before
+    and after, front radius against the analytic law at the end."""
+    import numpy as np
+    from paper_0912_4273_amd import regrid as RG
+    half = w.n_sweeps // 2
+    spacing = RG.min_spacing_for(w.box, n_min)
+    gid = ctx.upload(w)
+    prof(True)
+    ctx.solve([gid], half)
+    k0 = prof(False)
+    wc, gc = w, gid
+    parts = dict(select_s=0.0, triangulate_s=0.0, upload_s=0.0, remap_s=0.0)
+    removed = []
+    for _ in range(passes):
+        t0 = time.perf_counter()
+        rm = ctx.select_removal(gc, tau_remove, spacing)
+        t1 = time.perf_counter()
+        if not rm.any():
+            break
+        st = ctx.state(gc, nin=False)
+        wn, new_of_old = RG.thinned_workload(wc, ~rm, st["x"])
+        t2 = time.perf_counter()
+        gn = ctx.upload(wn)
+        t3 = time.perf_counter()
+        ctx.remap(gc, gn, new_of_old)
+        t4 = time.perf_counter()
+        ctx.free(gc)
+        parts["select_s"] += t1 - t0
+        parts["triangulate_s"] += t2 - t1
+        parts["upload_s"] += t3 - t2
+        parts["remap_s"] += t4 - t3
+        removed.append(int(rm.sum()))
+        wc, gc = wn, gn
+    prof(True)
+    ctx.solve([gc], w.n_sweeps - half)
+    k1 = prof(False)
+    st = ctx.state(gc, nin=False)
+    ctx.free(gc)
+    r_s = (3 * w.meta["rate"] / (4 * math.pi * w.alpha_B * w.meta["n_H"] ** 2)) ** (1 / 3)
+    t_rec = 1.0 / (w.alpha_B * w.meta["n_H"])
+    rv = (3 / (4 * math.pi) * float(np.sum(wc.volume * st["x"]))) ** (1 / 3)
+    tl = st["tallies"]
+    res = dict(passes=len(removed), removed_per_pass=removed, vertices_after=wc.n,
+               min_resolution=n_min, tau_remove=tau_remove,
+               seconds_per_pass={k: round(v / max(len(removed), 1), 3) for k, v in parts.items()},
+               sweep_kernel_us_before=1e3 * k0["total_ms"] / max(k0["launches"], 1),
+               sweep_kernel_us_after=1e3 * k1["total_ms"] / max(k1["launches"], 1),
+               front_radius_over_analytic=round(
+                   rv / (r_s * (1 - math.exp(-w.n_sweeps * w.dt / t_rec)) ** (1 / 3)), 4),
+               conservation_residual=abs(tl["emitted"] - tl["absorbed"] - tl["escaped"]
+                                         - tl["in_flight"]) / tl["emitted"])
+    log(f"dynamic grid: removed {removed} of {w.n}, sweep {res['sweep_kernel_us_before']:.1f} -> "
+        f"{res['sweep_kernel_us_after']:.1f} us, per pass {res['seconds_per_pass']}, front/analytic "
+        f"{res['front_radius_over_analytic']}")
+    return res
+
+
 def cpu_baseline(w, sweeps: int):
     """The FP64 oracle (single thread) on the same grid, from the initial
     state, for a bounded number of sweeps."""
@@ -386,6 +447,9 @@ def main():
                     help="switch of the combined-transport leg (negative: skip the leg)")
     ap.add_argument("--no-diffuse", action="store_true",
                     help="skip the diffuse-recombination-radiation leg")
+    ap.add_argument("--regrid-passes", type=int, default=2,
+                    help="thinning passes of the dynamic-grid leg (0: skip the leg)")
+    ap.add_argument("--regrid-min-res", type=int, default=32)
     ap.add_argument("--graph-sweeps", type=int, default=50,
                     help="sweeps per replayed HIP graph (0: one launch per sweep)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -567,6 +631,10 @@ def main():
     if args.combined_tau >= 0:
         combined = combined_leg(ctx, w, args.combined_tau, log, prof)
 
+    regridded = None
+    if args.regrid_passes > 0:
+        regridded = regrid_leg(ctx, w, args.regrid_passes, args.regrid_min_res, 0.5, log, prof)
+
     diffused = None
     if not args.no_diffuse:
         diffused = diffuse_leg(ctx, w, log, prof)
@@ -638,6 +706,7 @@ def main():
         "rotated": rotated,
         "combined": combined,
         "diffuse": diffused,
+        "dynamic_grid": regridded,
         "upload_s": up_s,
         "sweep_kernel_us": 1e3 * kern_ms,
         "roofline": roof,
