@@ -435,7 +435,9 @@ __device__ __forceinline__ double chem_step(double y, double nin, double dt,
     double ion;
     y = be_substep(y, ha, hb, tau, ion);
     abs_sum += share * ion;
-    tr_sum += 1.0 - ion;   // exp(-y tau)
+    // exp(-y tau): 1 - ion where that loses nothing; in a thick cell ion
+    // rounds towards 1 and the difference would cancel to 0
+    tr_sum += ion < 0.5 ? 1.0 - ion : exp(-y * tau);
   }
   A = abs_sum;
   T = nin > 0.0 ? tr_sum / (double)n_sub : 1.0;
@@ -457,7 +459,7 @@ __device__ __forceinline__ double chem_step_r(double y, double nin, double dt,
     double ion;
     y = be_substep(y, ha, hb, tau, ion);
     abs_sum += share * ion;
-    tr_sum += 1.0 - ion;
+    tr_sum += ion < 0.5 ? 1.0 - ion : exp(-y * tau);
     const double x = 1.0 - y;
     rec_sum += hb * (x * x);
   }

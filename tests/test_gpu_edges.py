@@ -94,3 +94,28 @@ def test_limits_just_past_supported(sxctx):
         sxctx.upload(G.with_(G.small_random(300, seed=95), max_per_bin=4))
     assert e.value.code == sx.SX_EINVAL
 
+
+
+@pytest.mark.parametrize("prec", [G.SX_FP64, G.SX_FP32_TRANSPORT])
+def test_thick_cells_pass_their_tiny_share(sxctx, prec):
+    """Cells of optical depth ~40: what they pass on (~e^-40 of what comes
+    in) is kept, not rounded away, so the escaped tally agrees with the
+    oracle relative to its own size."""
+    w = G.with_(G.stromgren_test(512, seed=11, n_bins=21, bins_seed=5, n_sweeps=20,
+                                 t_end_myr=50.0, name="thick"), precision=prec)
+    gid = sxctx.upload(w)
+    try:
+        sxctx.solve([gid], w.n_sweeps)
+        got = sxctx.state(gid)["tallies"]
+    finally:
+        sxctx.free(gid)
+    o = Oracle(w)
+    tau = o.tables()["tau"]
+    o.run(w.n_sweeps)
+    ref = o.state()["tallies"]
+    o.close()
+    assert np.median(tau) > 20
+    assert ref["escaped"] > 0
+    rel = 1e-9 if prec == G.SX_FP64 else 1e-3
+    for key in ("emitted", "absorbed", "escaped", "in_flight"):
+        assert abs(got[key] - ref[key]) <= rel * abs(ref[key]), (key, got[key], ref[key])
