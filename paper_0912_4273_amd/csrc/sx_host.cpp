@@ -398,6 +398,7 @@ uint64_t bytes_estimate(const Sizes &s, int64_t n_em, int64_t n_rec, int64_t n_h
     // (at most mpb per edge), counts, per-edge photons, layouts
     b += 2 * rnd(4 * (s.E + 1)) + rnd((uint64_t)s.mpb * s.npad * s.K) +
          rnd((uint64_t)4 * s.mpb * s.E) + 3 * rnd(s.E) + 2 * rnd((uint64_t)s.sp * s.E) +
+         rnd((uint64_t)16 * (s.E + 1)) +
          rnd((uint64_t)sx::kBlockBytes * s.kb * (s.npad + sx::kTile)) +
          2 * rnd(s.npad);
   }
@@ -504,6 +505,7 @@ struct sx_prepared {
   std::vector<double> nhv;
   std::vector<int32_t> bl_ptr;   // combined transport: ballistic lists by in-edge
   std::vector<int32_t> bl;
+  std::vector<int32_t> bl4;      // [4E] first four entries of each ballistic list, -1 padding
   std::vector<uint8_t> elane, ebin_in;
   ~sx_prepared() { delete g; }
 };
@@ -826,6 +828,10 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
           const int32_t in = rp[(size_t)g->nbr_h[(size_t)f]] + rev[(size_t)f];
           P->bl[(size_t)fillp[(size_t)in]++] = e;
         }
+    P->bl4.assign((size_t)(4 * E), -1);
+    for (int64_t e = 0; e < E; ++e)
+      for (int32_t q = blp[(size_t)e]; q < blp[(size_t)e + 1] && q < blp[(size_t)e] + 4; ++q)
+        P->bl4[(size_t)(4 * e + (q - blp[(size_t)e]))] = P->bl[(size_t)q];
   }
   return SX_OK;
 }
@@ -1084,6 +1090,8 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
     GA(d_bl, P->bl.size() + 1);
     GA(d_bm, E + 1);
     GA(d_el, E + 1);
+    int4 *d_b4;
+    GA(d_b4, E + 1);
     GA(d_eb, E + 1);
     GA(d_x, (uint64_t)sx::kBlockBytes * S.kb * (npad + sx::kTile));
     GA(d_e0, (uint64_t)S.sp * (E + 1));
@@ -1096,6 +1104,7 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
     UP(d_bl, P->bl.data(), 4 * P->bl.size());
     UP(d_bm, g->bm_h.data(), E);
     UP(d_el, P->elane.data(), E);
+    UP(d_b4, P->bl4.data(), 16 * E);
     UP(d_eb, P->ebin_in.data(), E);
     if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
     h.kl_ptr = d_klp;
@@ -1103,6 +1112,7 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
     h.bl_ptr = d_blp;
     h.bl = d_bl;
     h.elane = d_el;
+    h.bl4 = d_b4;
     h.ebin_in = d_eb;
     h.xin = d_x;
     h.bm = d_bm;

@@ -114,6 +114,7 @@ struct GridDev {
   const int32_t *bl_ptr;    // [E+1]
   const int32_t *bl;        // edges of i (global ids, ascending) whose ballistic
                             // packets go to j
+  const int4 *bl4;          // [E] the first four entries of each bl list, -1 padding
   const uint8_t *elane;     // [E] lane (vertex mod 64) of each edge's row
   const uint8_t *ebin_in;   // [E] bin of the edge i -> j, for the in-edge (j, slot of i)
   int32_t diffuse;          // recombination photons re-emitted (alpha_A > 0)

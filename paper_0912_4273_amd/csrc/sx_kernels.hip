@@ -946,6 +946,8 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
   const SX_G int32_t *__restrict__ bl = gld(G->bl);
   const SX_G uint8_t *__restrict__ bmv = gld(G->bm);
   const SX_G uint8_t *__restrict__ elane = gld(G->elane);
+  typedef int I4 __attribute__((ext_vector_type(4)));
+  const SX_G I4 *__restrict__ bl4 = (const SX_G I4 *)G->bl4;
   const SX_G int32_t *__restrict__ emp = gld(G->em_ptr);
   const SX_G double *__restrict__ ema = gld(G->em_amt);
   const SX_G int32_t *__restrict__ eme = gld(G->em_edge);
@@ -990,8 +992,15 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
   // 2. per incoming edge e (receiver lane r): everything that arrives at a
   // ballistic receiver (stored as I / bm), or what a ballistic sender sends
   // a direction-conserving one
+  // which lanes receive source shares (so the others skip the search)
+  const uint64_t emmask = __ballot(valid && emp[j] < emp[j + 1]);
   auto edge_in = [&](int e, int r, bool rbal) -> P {
     const int i = nbr[e];
+    // the first four packets of a ballistic sender, read before its layout
+    // is known (the indices are valid edges either way; padding reads edge 0)
+    const I4 b4 = bl4[e];
+    const P p0 = ein[b4.x < 0 ? 0 : b4.x], p1 = ein[b4.y < 0 ? 0 : b4.y];
+    const P p2 = ein[b4.z < 0 ? 0 : b4.z], p3 = ein[b4.w < 0 ? 0 : b4.w];
     const bool iedges = lin[i] != 0;
     // the sender's recombination photons of last step, its share per edge
     P ve = diffuse ? dshin[i] : P(0);
@@ -1001,13 +1010,19 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
       const int q1 = klp[e + 1];
       for (int q = klp[e]; q < q1; ++q) ve += mul_rn(oin[at((uint32_t)i, kl[q])], ti);
     } else {
-      const int q1 = blp[e + 1];
-      for (int q = blp[e]; q < q1; ++q) ve += mul_rn(ein[bl[q]], ti);
+      if (b4.x >= 0) ve += mul_rn(p0, ti);
+      if (b4.y >= 0) ve += mul_rn(p1, ti);
+      if (b4.z >= 0) ve += mul_rn(p2, ti);
+      if (b4.w >= 0) {
+        ve += mul_rn(p3, ti);
+        const int q1 = blp[e + 1];
+        for (int q = blp[e] + 4; q < q1; ++q) ve += mul_rn(ein[bl[q]], ti);
+      }
     }
     if (rbal) {
-      const int jr = tile * kTile + r;
-      const int e0 = emp[jr], e1 = emp[jr + 1];
-      if (e0 < e1) {
+      if ((emmask >> r) & 1ull) {
+        const int jr = tile * kTile + r;
+        const int e0 = emp[jr], e1 = emp[jr + 1];
         const int rbj = rowp[jr];
         for (int q = e0; q < e1; ++q)
           if (rbj + (int)rev[eme[q]] == e) ve += (P)ema[q];
