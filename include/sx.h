@@ -275,9 +275,11 @@ int sx_profile_read(sx_ctx *ctx, int64_t *launches, double *total_ms,
  * what a vertex holds in a bin is split over the neighbours selected for
  * the bin's new direction (unchanged where their number is the same), and
  * escapes where none is selected (tallied as escaped).  sx_grid_reset
- * restores the given bins.  Synchronous.  Errors: SX_EINVAL (not a
- * rotation), SX_ENOTSUP (a combined-transport grid), SX_ENOTFOUND,
- * SX_ENOMEM, SX_EDEVICE. */
+ * restores the given bins.  With combined transport or diffuse radiation
+ * the bin of each incoming edge and the per-edge bin lists are rebuilt too
+ * (ballistic routing does not depend on the bins; what ballistic vertices
+ * hold is untouched).  Synchronous.  Errors: SX_EINVAL (not a rotation),
+ * SX_ENOTFOUND, SX_ENOMEM, SX_EDEVICE. */
 int sx_rotate_bins(sx_ctx *ctx, sx_grid_id id, const double *R);
 
 /* ---- combined transport -------------------------------------------------

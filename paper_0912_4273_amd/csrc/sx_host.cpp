@@ -268,6 +268,9 @@ int validate(sx_ctx *ctx, const sx_grid_desc *d) {
     return fail(ctx, SX_EINVAL, "tau_switch is NaN");
   if (!(d->alpha_A == 0.0 || (std::isfinite(d->alpha_A) && d->alpha_A >= d->alpha_B)))
     return fail(ctx, SX_EINVAL, "alpha_A must be 0 or finite and >= alpha_B");
+  if ((d->transport == SX_TRANSPORT_COMBINED || d->alpha_A > 0.0) &&
+      (double)n * (double)d->n_bins * (double)d->max_per_bin >= 2147483647.0)
+    return fail(ctx, SX_ENOTSUP, "grid too large for the per-edge lists of combined transport");
   if (d->dct_reference != SX_DCT_REF_BIN && d->dct_reference != SX_DCT_REF_EDGE)
     return fail(ctx, SX_EINVAL, "dct_reference must be SX_DCT_REF_BIN or SX_DCT_REF_EDGE");
   const int K = d->n_bins;
@@ -396,7 +399,7 @@ uint64_t bytes_estimate(const Sizes &s, int64_t n_em, int64_t n_rec, int64_t n_h
   if (s.transport == SX_TRANSPORT_COMBINED) {
     // bin lists (at most mpb entries per (vertex, bin)), ballistic lists
     // (at most mpb per edge), counts, per-edge photons, layouts
-    b += 2 * rnd(4 * (s.E + 1)) + rnd((uint64_t)s.mpb * s.npad * s.K) +
+    b += 3 * rnd(4 * (s.E + 1)) + rnd(8 * (s.E / 1024 + 2)) + rnd((uint64_t)s.mpb * s.npad * s.K) +
          rnd((uint64_t)4 * s.mpb * s.E) + 3 * rnd(s.E) + 2 * rnd((uint64_t)s.sp * s.E) +
          rnd((uint64_t)16 * (s.E + 1)) +
          rnd((uint64_t)sx::kBlockBytes * s.kb * (s.npad + sx::kTile)) +
@@ -429,6 +432,36 @@ void gfree(sx_ctx *ctx, Grid *g, void *p) {
       g->bufs.erase(g->bufs.begin() + (long)i);
       return;
     }
+}
+
+// Combined transport (and diffuse radiation): the bin of each in-edge and
+// the per-in-edge bin lists from the current selection and edge bins, on
+// the device; the list pool grows when needed.  Only the pool pointer and
+// capacity are written to the device table.  Synchronous.
+int build_ct_tables(sx_ctx *ctx, Grid *g) {
+  GridDev &h = g->hg;
+  GridDev *dg = ctx->table + g->slot;
+  hipStream_t st = ctx->stream;
+  HIP_TRY(ctx, sx::launch_ebin_in(dg, h, st));
+  HIP_TRY(ctx, sx::launch_kl_count(dg, h, st));
+  HIP_TRY(ctx, sx::launch_scan(h.kl_cnt, h.kl_ptr, h.kl_part, (int32_t)h.n_edges, st));
+  int32_t total = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(&total, h.kl_ptr + h.n_edges, 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  if (!h.kl || total > h.kl_cap) {
+    if (h.kl) gfree(ctx, g, h.kl);
+    uint8_t *d = nullptr;
+    const int r = galloc(ctx, g, &d, (uint64_t)total + 1);
+    h.kl = r ? nullptr : d;
+    h.kl_cap = r ? 0 : total;
+    HIP_TRY(ctx, hipMemcpyAsync(&dg->kl, &h.kl, sizeof(h.kl), hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, hipMemcpyAsync(&dg->kl_cap, &h.kl_cap, sizeof(h.kl_cap), hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    if (r) return fail(ctx, SX_ENOMEM, "bin lists of combined transport: %d entries", total);
+  }
+  HIP_TRY(ctx, sx::launch_kl_fill(dg, h, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  return SX_OK;
 }
 
 // Rebuild a grid's routing on the device for bin directions `bins` [3K]:
@@ -480,6 +513,12 @@ int rebuild_routing(sx_ctx *ctx, Grid *g, const double *bins, bool rescale) {
   }
   HIP_TRY(ctx, sx::launch_inlist_fill(dg, h, st));
   HIP_TRY(ctx, hipStreamSynchronize(st));
+  if (h.transport == SX_TRANSPORT_COMBINED) {
+    // the in-edge bins need the full edge-bin table
+    HIP_TRY(ctx, sx::launch_edge_bins(dg, h, st));
+    g->ebin_stale = false;
+    return build_ct_tables(ctx, g);
+  }
   return SX_OK;
 }
 
@@ -506,7 +545,7 @@ struct sx_prepared {
   std::vector<int32_t> bl_ptr;   // combined transport: ballistic lists by in-edge
   std::vector<int32_t> bl;
   std::vector<int32_t> bl4;      // [4E] first four entries of each ballistic list, -1 padding
-  std::vector<uint8_t> elane, ebin_in;
+  std::vector<uint8_t> elane;
   ~sx_prepared() { delete g; }
 };
 
@@ -814,13 +853,8 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
     std::vector<int32_t> fillp(blp.begin(), blp.end() - 1);
     P->bl.assign((size_t)blp[(size_t)E], 0);
     P->elane.assign((size_t)E, 0);
-    P->ebin_in.assign((size_t)E, 0);
     for (int64_t v = 0; v < n; ++v)
-      for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) {
-        P->elane[(size_t)e] = (uint8_t)(v & 63);
-        // bin of the edge nbr -> v (its id in the row of nbr)
-        P->ebin_in[(size_t)e] = (uint8_t)edge_bin(rp[(size_t)g->nbr_h[(size_t)e]] + rev[(size_t)e]);
-      }
+      for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) P->elane[(size_t)e] = (uint8_t)(v & 63);
     for (int64_t v = 0; v < n; ++v)
       for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e)
         for (int q = 0; q < g->bm_h[(size_t)e]; ++q) {
@@ -1048,44 +1082,12 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   if ((he = sx::launch_inlist_fill(dg, h, st)) != hipSuccess) return kfail(he);
 
   if (P->transport == SX_TRANSPORT_COMBINED) {
-    // per receiving in-edge, the sender's bins whose selection holds the
-    // receiver (from the device selection), ascending
-    std::vector<uint32_t> f((size_t)(npad * K));
-    if ((he = hipMemcpyAsync(f.data(), h.fwd, 4 * npad * K, hipMemcpyDeviceToHost, st)) != hipSuccess)
-      return kfail(he);
-    if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
-    std::vector<int32_t> klp((size_t)E + 1, 0);
-    const std::vector<int32_t> &nb = g->nbr_h;
-    for (int64_t v = 0; v < n; ++v)
-      for (int64_t k = 0; k < K; ++k) {
-        const uint32_t w = f[(size_t)(v * K + k)];
-        for (uint32_t q = 0; q < ((w >> 21) & 3u); ++q) {
-          const int32_t eo = rp[(size_t)v] + (int32_t)((w >> (7 * q)) & 127u);
-          klp[(size_t)(rp[(size_t)nb[(size_t)eo]] + P->rev[(size_t)eo]) + 1]++;
-        }
-      }
-    int64_t tot = 0;
-    for (int64_t e = 0; e < E; ++e) tot += klp[(size_t)e + 1];
-    if (tot >= INT32_MAX) {
-      grid_release(ctx, g);
-      return fail(ctx, SX_ENOTSUP, "too many (vertex, bin) routes for combined transport");
-    }
-    for (int64_t e = 0; e < E; ++e) klp[(size_t)e + 1] += klp[(size_t)e];
-    std::vector<int32_t> fillp(klp.begin(), klp.end() - 1);
-    std::vector<uint8_t> kl((size_t)klp[(size_t)E]);
-    for (int64_t v = 0; v < n; ++v)
-      for (int64_t k = 0; k < K; ++k) {
-        const uint32_t w = f[(size_t)(v * K + k)];
-        for (uint32_t q = 0; q < ((w >> 21) & 3u); ++q) {
-          const int32_t eo = rp[(size_t)v] + (int32_t)((w >> (7 * q)) & 127u);
-          const int32_t in = rp[(size_t)nb[(size_t)eo]] + P->rev[(size_t)eo];
-          kl[(size_t)fillp[(size_t)in]++] = (uint8_t)k;
-        }
-      }
-    int32_t *d_klp, *d_blp, *d_bl;
-    uint8_t *d_kl, *d_bm, *d_el, *d_eb, *d_l0, *d_l1, *d_e0, *d_e1, *d_x;
+    int32_t *d_klp, *d_klc, *d_blp, *d_bl;
+    int64_t *d_klpart;
+    uint8_t *d_bm, *d_el, *d_eb, *d_l0, *d_l1, *d_e0, *d_e1, *d_x;
     GA(d_klp, E + 1);
-    GA(d_kl, kl.size() + 1);
+    GA(d_klc, E + 1);
+    GA(d_klpart, E / 1024 + 2);
     GA(d_blp, E + 1);
     GA(d_bl, P->bl.size() + 1);
     GA(d_bm, E + 1);
@@ -1098,17 +1100,17 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
     GA(d_e1, (uint64_t)S.sp * (E + 1));
     GA(d_l0, npad);
     GA(d_l1, npad);
-    UP(d_klp, klp.data(), 4 * (E + 1));
-    UP(d_kl, kl.data(), kl.size());
     UP(d_blp, P->bl_ptr.data(), 4 * (E + 1));
     UP(d_bl, P->bl.data(), 4 * P->bl.size());
     UP(d_bm, g->bm_h.data(), E);
     UP(d_el, P->elane.data(), E);
     UP(d_b4, P->bl4.data(), 16 * E);
-    UP(d_eb, P->ebin_in.data(), E);
     if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
     h.kl_ptr = d_klp;
-    h.kl = d_kl;
+    h.kl_cnt = d_klc;
+    h.kl_part = d_klpart;
+    h.kl = nullptr;
+    h.kl_cap = 0;
     h.bl_ptr = d_blp;
     h.bl = d_bl;
     h.elane = d_el;
@@ -1120,6 +1122,9 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
     h.oe[1] = d_e1;
     h.lay[0] = d_l0;
     h.lay[1] = d_l1;
+    // the bin of each in-edge and the per-in-edge bin lists, on the device
+    if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
+    if ((r = build_ct_tables(ctx, g))) { grid_release(ctx, g); return r; }
   }
   if (h.diffuse) {
     double *d_nhv, *d_dt;
@@ -1341,8 +1346,6 @@ int sx_rotate_bins(sx_ctx *ctx, sx_grid_id id, const double *R) {
   if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
   Grid *g = find(ctx, id);
   if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
-  if (g->hg.transport != SX_TRANSPORT_DCT)
-    return fail(ctx, SX_ENOTSUP, "rotating the bins of a combined-transport or diffuse grid");
   if (!R) return fail(ctx, SX_EINVAL, "null rotation");
   // a rotation: orthonormal rows, determinant +1
   for (int i = 0; i < 9; ++i)

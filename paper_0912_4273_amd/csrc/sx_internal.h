@@ -109,14 +109,17 @@ struct GridDev {
   int32_t transport;        // 0 direction-conserving, 1 combined
   int32_t dct_ref;          // bin selection w.r.t. 0: the bin, 1: its closest edge
   double tau_switch;        // ballistic where y tau >= tau_switch
-  const int32_t *kl_ptr;    // [E+1]
-  const uint8_t *kl;        // bins of i whose selection holds j, ascending
+  int32_t *kl_ptr;          // [E+1]
+  uint8_t *kl;              // bins of i whose selection holds j, ascending
+  int64_t kl_cap;           // entries kl holds
+  int32_t *kl_cnt;          // [E+1] scratch: entries per in-edge
+  int64_t *kl_part;         // [E/1024 + 2] scratch of their scan
   const int32_t *bl_ptr;    // [E+1]
   const int32_t *bl;        // edges of i (global ids, ascending) whose ballistic
                             // packets go to j
   const int4 *bl4;          // [E] the first four entries of each bl list, -1 padding
   const uint8_t *elane;     // [E] lane (vertex mod 64) of each edge's row
-  const uint8_t *ebin_in;   // [E] bin of the edge i -> j, for the in-edge (j, slot of i)
+  uint8_t *ebin_in;         // [E] bin of the edge i -> j, for the in-edge (j, slot of i)
   int32_t diffuse;          // recombination photons re-emitted (alpha_A > 0)
   int32_t pad1;
   double dfrac;             // (alpha_A - alpha_B) / alpha_A
@@ -147,6 +150,12 @@ hipError_t launch_rot_rescale(GridDev *dg, const GridDev &hg, hipStream_t s);
 // Bin of each source share from its edge's bin.
 hipError_t launch_em_bins(GridDev *dg, const GridDev &hg, int64_t n_em, hipStream_t s);
 hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s);
+// Combined transport, from the selection and the edge bins: the bin of each
+// in-edge, and per in-edge the sender's bins that hold the receiver (count,
+// then fill after a scan of the counts into kl_ptr).
+hipError_t launch_ebin_in(const GridDev *dg, const GridDev &hg, hipStream_t s);
+hipError_t launch_kl_count(const GridDev *dg, const GridDev &hg, hipStream_t s);
+hipError_t launch_kl_fill(const GridDev *dg, const GridDev &hg, hipStream_t s);
 hipError_t launch_clear_inw(const GridDev &hg, hipStream_t s);
 hipError_t launch_reset_state(GridDev *dg, const GridDev &hg, const double *y0,
                               hipStream_t s);

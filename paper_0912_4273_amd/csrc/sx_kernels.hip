@@ -286,6 +286,47 @@ __global__ __launch_bounds__(64) void k_rot_rescale(GridDev *__restrict__ gp) {
     rot_rescale<float>(g, blockIdx.x, threadIdx.x);
 }
 
+// Combined transport: the bin of each in-edge (j, slot of i), which is the
+// bin of the edge i -> j.  One lane per in-edge.
+__global__ void k_ebin_in(const GridDev *__restrict__ gp) {
+  const GridDev &g = *gp;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.n_edges) return;
+  const int i = g.nbr[e];
+  g.ebin_in[e] = g.ebin[g.row_ptr[i] + g.rev[e]];
+}
+
+// Combined transport: how many bins of the sender i select the receiver j
+// of in-edge e (j sits in slot rev[e] of i's row), then the bins in
+// ascending order.  One lane per in-edge.
+__global__ void k_kl_count(const GridDev *__restrict__ gp) {
+  const GridDev &g = *gp;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e > g.n_edges) return;
+  if (e == g.n_edges) {   // the scan's total slot
+    g.kl_cnt[e] = 0;
+    return;
+  }
+  const int64_t i = g.nbr[e];
+  const uint32_t t = g.rev[e];
+  const uint32_t *f = g.fwd + i * g.k;
+  int c = 0;
+  for (int k = 0; k < g.k; ++k) c += fwd_selects(f[k], t) && ((f[k] >> 21) & 3u) > 0 ? 1 : 0;
+  g.kl_cnt[e] = c;
+}
+
+__global__ void k_kl_fill(const GridDev *__restrict__ gp) {
+  const GridDev &g = *gp;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.n_edges) return;
+  const int64_t i = g.nbr[e];
+  const uint32_t t = g.rev[e];
+  const uint32_t *f = g.fwd + i * g.k;
+  int64_t p = g.kl_ptr[e];
+  for (int k = 0; k < g.k; ++k)
+    if (fwd_selects(f[k], t) && ((f[k] >> 21) & 3u) > 0) g.kl[p++] = (uint8_t)k;
+}
+
 // Bin of each source share: the bin closest to its edge (the edge-bin rule).
 __global__ void k_em_bins(GridDev *__restrict__ gp, int64_t n_em) {
   GridDev &g = *gp;
@@ -1213,6 +1254,23 @@ hipError_t launch_em_bins(GridDev *dg, const GridDev &hg, int64_t n_em, hipStrea
   (void)hg;
   if (n_em <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_em_bins, dim3(blocks_for(n_em, 256)), dim3(256), 0, s, dg, n_em);
+  return hipGetLastError();
+}
+
+hipError_t launch_ebin_in(const GridDev *dg, const GridDev &hg, hipStream_t s) {
+  if (hg.n_edges == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ebin_in, dim3(blocks_for(hg.n_edges, 256)), dim3(256), 0, s, dg);
+  return hipGetLastError();
+}
+
+hipError_t launch_kl_count(const GridDev *dg, const GridDev &hg, hipStream_t s) {
+  hipLaunchKernelGGL(k_kl_count, dim3(blocks_for(hg.n_edges + 1, 256)), dim3(256), 0, s, dg);
+  return hipGetLastError();
+}
+
+hipError_t launch_kl_fill(const GridDev *dg, const GridDev &hg, hipStream_t s) {
+  if (hg.n_edges == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kl_fill, dim3(blocks_for(hg.n_edges, 256)), dim3(256), 0, s, dg);
   return hipGetLastError();
 }
 

@@ -187,15 +187,48 @@ def test_checkpoint_restore_edges(sxctx):
         sxctx.free(b)
 
 
-def test_combined_limits(sxctx):
-    w = _work(300, seed=70)
+@pytest.mark.parametrize("prec", [G.SX_FP64, G.SX_FP32_TRANSPORT])
+def test_combined_rotated(sxctx, prec):
+    """Combined transport with the bins rotated between steps (as the
+    paper does for its direction-conserving part): the bin selection, the
+    edge bins and the per-edge lists are rebuilt on the device.  fp64: whole
+    solve; fp32: one step from the GPU's state after the rotations."""
+    w = _work(2000, seed=75, prec=prec, tau_switch=1.0)
+    Rs = G.random_rotations(3, seed=11)
+    print(f"[case] combined rotated prec={prec}", flush=True)
     gid = sxctx.upload(w)
+    o = Oracle(w)
     try:
-        with pytest.raises(sx.SxError) as e:
-            sxctx.rotate(gid, np.eye(3))
-        assert e.value.code == sx.SX_ENOTSUP
+        for R in Rs:
+            sxctx.solve([gid], 15)
+            sxctx.rotate(gid, R)
+            o.run(15)
+            o.rotate(R)
+        tab = sxctx.tables(gid)
+        ot = o.tables()
+        assert np.array_equal(tab["sel_m"], ot["sel_m"])
+        assert np.array_equal(tab["edge_bin"], ot["edge_bin"])
+        if prec == G.SX_FP32_TRANSPORT:
+            s1, e1 = sxctx.state(gid, photons=True), sxctx.edge_state(gid)
+            o.set_state(y=s1["y"], photons=s1["photons"], tallies=s1["tallies"])
+            o.set_edge_state(photons_e=e1["photons_e"], layout=e1["layout"].astype(np.int8))
+            sxctx.solve([gid], 1)
+            o.run(1)
+        else:
+            sxctx.solve([gid], 15)
+            o.run(15)
+        st, es = sxctx.state(gid, photons=True), sxctx.edge_state(gid)
+        unit = sxctx.info(gid)["photon_unit"]
+        ref, ref_e = o.state(), o.edge_state()
     finally:
         sxctx.free(gid)
+        o.close()
+    assert es["layout"].any() and (es["layout"] == 0).any()
+    assert_state_close(st, ref, prec, unit, f"combined rotated prec {prec}")
+    assert_edges_close(es, ref_e, prec, unit, f"combined rotated prec {prec}")
+
+
+def test_combined_limits(sxctx):
     d = sxctx.upload(G.small_random(300, seed=71, n_bins=21))
     try:
         with pytest.raises(sx.SxError) as e:

@@ -121,15 +121,34 @@ def test_diffuse_lattice_delivery(sxctx):
     assert np.count_nonzero(ph) == 6
 
 
-def test_diffuse_limits(sxctx):
-    w = _work(300, seed=84)
+def test_diffuse_rotated(sxctx):
+    """Diffuse radiation with the bins rotated between steps."""
+    w = _work(1500, seed=85)
+    Rs = G.random_rotations(2, seed=12)
+    print("[case] diffuse rotated", flush=True)
     gid = sxctx.upload(w)
+    o = Oracle(w)
     try:
-        with pytest.raises(sx.SxError) as e:
-            sxctx.rotate(gid, np.eye(3))
-        assert e.value.code == sx.SX_ENOTSUP
+        for R in Rs:
+            sxctx.solve([gid], 15)
+            sxctx.rotate(gid, R)
+            o.run(15)
+            o.rotate(R)
+        sxctx.solve([gid], 15)
+        o.run(15)
+        st = sxctx.state(gid, photons=True)
+        pend = sxctx.diffuse_pending(gid)
+        unit = sxctx.info(gid)["photon_unit"]
+        ref, rp = o.state(), o.diffuse_pending()
     finally:
         sxctx.free(gid)
+        o.close()
+    assert_state_close(st, ref, G.SX_FP64, unit, "diffuse rotated")
+    _check_pending(pend, rp, G.SX_FP64, unit, "diffuse rotated")
+
+
+def test_diffuse_limits(sxctx):
+    w = _work(300, seed=84)
     with pytest.raises(sx.SxError) as e:
         sxctx.upload(G.with_(w, alpha_A=0.5 * w.alpha_B))
     assert e.value.code == sx.SX_EINVAL
