@@ -102,3 +102,24 @@ def test_malformed_request_reports_its_error():
     assert served[1][0]["status"] == sx.SX_EINVAL
     assert served[2][0]["status"] == sx.SX_OK
     assert stats["finished"] == 2 and stats["failed"] == 1
+
+
+def test_served_mixed_physics_equal_alone():
+    """Requests with combined transport, diffuse radiation and plain
+    direction-conserving transport, in both precisions, served together:
+    each result is the one of the grid solved alone."""
+    base = dict(box=3e21, rate=3e45, dt=3e13)
+    ws = [G.with_(G.small_random(1200, seed=86, n_bins=42, n_src=2, **base),
+                  transport=G.SX_TRANSPORT_COMBINED, tau_switch=1.0),
+          G.with_(G.small_random(900, seed=87, n_bins=21, n_src=1, precision=G.SX_FP32_TRANSPORT,
+                                 **base), alpha_A=G.ALPHA_A),
+          G.small_random(1500, seed=88, n_bins=42, n_src=3, **base),
+          G.with_(G.small_random(700, seed=89, n_bins=42, n_src=2, precision=G.SX_FP32_TRANSPORT,
+                                 **base), transport=G.SX_TRANSPORT_COMBINED, tau_switch=0.5,
+                  alpha_A=G.ALPHA_A)]
+    sweeps = [50, 35, 60, 45]
+    print("[case] serve mixed physics", flush=True)
+    ref = _alone(ws, sweeps)
+    served, stats = _serve(ws, sweeps, round_sweeps=15, max_active=4, prep_threads=2)
+    _check_same(ref, served)
+    assert stats["finished"] == 4 and stats["failed"] == 0
