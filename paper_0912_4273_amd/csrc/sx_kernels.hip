@@ -1048,8 +1048,25 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
     if (!rbal && !iedges) return ve;
     const P ti = tin[i];
     if (!iedges) {
+      // the sender's bins, eight gathers in flight at a time, added in order
+      int q = klp[e];
       const int q1 = klp[e + 1];
-      for (int q = klp[e]; q < q1; ++q) ve += mul_rn(oin[at((uint32_t)i, kl[q])], ti);
+      for (; q + 8 <= q1; q += 8) {
+        P a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = oin[at((uint32_t)i, kl[q + u])];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ve += mul_rn(a[u], ti);
+      }
+      for (; q + 4 <= q1; q += 4) {
+        const P a0 = oin[at((uint32_t)i, kl[q])], a1 = oin[at((uint32_t)i, kl[q + 1])];
+        const P a2 = oin[at((uint32_t)i, kl[q + 2])], a3 = oin[at((uint32_t)i, kl[q + 3])];
+        ve += mul_rn(a0, ti);
+        ve += mul_rn(a1, ti);
+        ve += mul_rn(a2, ti);
+        ve += mul_rn(a3, ti);
+      }
+      for (; q < q1; ++q) ve += mul_rn(oin[at((uint32_t)i, kl[q])], ti);
     } else {
       if (b4.x >= 0) ve += mul_rn(p0, ti);
       if (b4.y >= 0) ve += mul_rn(p1, ti);
