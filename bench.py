@@ -474,9 +474,10 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not "
-              "supported (independent grids shard across GPUs with no exchange, "
-              "see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent grids would shard across GPUs with no exchange; one grid "
+              "larger than a GPU would need a ghost exchange per step, not built)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
