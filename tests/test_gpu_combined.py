@@ -309,3 +309,43 @@ def test_edge_reference_combined(sxctx):
     rs, re_ = _oracle_run(w, 50)
     assert_state_close(st, rs, G.SX_FP64, unit, "edge reference combined")
     assert_edges_close(es, re_, G.SX_FP64, unit, "edge reference combined")
+
+
+def _knn_workload(n=1500, k=28, seed=5, **kw):
+    """A symmetric k-nearest-neighbour graph (not a Delaunay graph): about
+    32 neighbours per vertex, so a 64-vertex tile has ~2000 incoming edges,
+    more than the combined-transport kernel sums through LDS."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    box = 3e21
+    pos = rng.random((n, 3)) * box
+    _, nn = cKDTree(pos).query(pos, k=k + 1)
+    rows = [set() for _ in range(n)]
+    for i in range(n):
+        for j in nn[i, 1:]:
+            rows[i].add(int(j))
+            rows[int(j)].add(i)
+    ptr = np.zeros(n + 1, np.int64)
+    ptr[1:] = np.cumsum([len(r) for r in rows])
+    idx = np.array([j for r in rows for j in sorted(r)], np.int32)
+    src = np.array([0, n // 2], np.int32)
+    w = G.Workload(name="knn", pos=pos, nbr_ptr=ptr, nbr_idx=idx, n_H=np.full(n, 1e-3),
+                   volume=np.full(n, box ** 3 / n), bin_dirs=G.icosahedral_bins_42(),
+                   src_vertex=src, src_rate=np.full(2, 3e45), dt=3e13, n_sweeps=40, box=box)
+    return G.with_(w, **kw)
+
+
+@pytest.mark.parametrize("kw", [dict(transport=G.SX_TRANSPORT_COMBINED, tau_switch=1.0),
+                                dict(transport=G.SX_TRANSPORT_COMBINED, tau_switch=1.0,
+                                     alpha_A=G.ALPHA_A)])
+def test_tiles_with_many_incoming_edges(sxctx, kw):
+    """Tiles whose incoming edges exceed what the kernel sums through LDS take
+    the per-lane path; the result is the same as the oracle's."""
+    w = _knn_workload(**kw)
+    assert 64 * np.diff(w.nbr_ptr).mean() > 1536
+    print(f"[case] many incoming edges {kw}", flush=True)
+    st, es, unit = _gpu_run(sxctx, w, 40)
+    rs, re_ = _oracle_run(w, 40)
+    assert es["layout"].any() and (es["layout"] == 0).any()
+    assert_state_close(st, rs, G.SX_FP64, unit, "many incoming edges")
+    assert_edges_close(es, re_, G.SX_FP64, unit, "many incoming edges")
