@@ -199,8 +199,11 @@ int sx_grid_bytes(const sx_grid_desc *d, uint64_t *bytes);
 /* Validate, reorder for locality, copy to the device, build the bin
  * selection tables and the gather lists, and initialise the state.
  * Errors: SX_EINVAL (asymmetric or malformed graph, non-finite values,
- * non-unit bins, bad source ids), SX_ENOTSUP (K or degree over the
- * limits), SX_ENOMEM (budget; nothing stays allocated), SX_EDEVICE. */
+ * non-unit bins, bad source ids, unknown transport or bin reference, NaN
+ * tau_switch, alpha_A neither 0 nor >= alpha_B), SX_ENOTSUP (K or degree
+ * over the limits, or N K max_per_bin >= 2^31 with combined transport or
+ * diffuse radiation), SX_ENOMEM (budget; nothing stays allocated),
+ * SX_EDEVICE. */
 int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out);
 
 /* Recompute the bin -> neighbour tables and gather lists on the device
@@ -215,9 +218,10 @@ int sx_grid_restore(sx_ctx *ctx, sx_grid_id id, const sx_state_in *in);
 /* Release one grid. */
 int sx_grid_free(sx_ctx *ctx, sx_grid_id id);
 
-/* Enqueue n_sweeps steps on each of the n grids (one batched launch per
- * step when n > 1; grids must share the precision and the bin count's
- * kernel class).  Asynchronous on the context stream.
+/* Enqueue n_sweeps steps on each of the n grids: per step one launch for
+ * each precision and transport class present among them (the class of a
+ * grid with diffuse radiation is the combined-transport one), all tiles of
+ * those grids in it.  Asynchronous on the context stream.
  * Errors: SX_ENOTFOUND, SX_EINVAL, SX_EDEVICE. */
 int sx_step(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, int32_t n_sweeps);
 
