@@ -196,7 +196,18 @@ __global__ void k_inlist_count(const GridDev *__restrict__ gp) {
     const int j = tile * kTile + lane;
     if (j >= g.n) break;
     int c = 0;
-    for (int e = g.row_ptr[j]; e < g.row_ptr[j + 1]; ++e)
+    const int re = g.row_ptr[j + 1];
+    int e = g.row_ptr[j];
+    // four selection words in flight at a time
+    for (; e + 4 <= re; e += 4) {
+      const uint32_t f0 = g.fwd[(int64_t)g.nbr[e] * K + k];
+      const uint32_t f1 = g.fwd[(int64_t)g.nbr[e + 1] * K + k];
+      const uint32_t f2 = g.fwd[(int64_t)g.nbr[e + 2] * K + k];
+      const uint32_t f3 = g.fwd[(int64_t)g.nbr[e + 3] * K + k];
+      c += (fwd_selects(f0, g.rev[e]) ? 1 : 0) + (fwd_selects(f1, g.rev[e + 1]) ? 1 : 0) +
+           (fwd_selects(f2, g.rev[e + 2]) ? 1 : 0) + (fwd_selects(f3, g.rev[e + 3]) ? 1 : 0);
+    }
+    for (; e < re; ++e)
       c += fwd_selects(g.fwd[(int64_t)g.nbr[e] * K + k], g.rev[e]) ? 1 : 0;
     recs += c > kWordEntries ? c - kWordEntries : 0;
     for (int q = g.em_ptr[j]; q < g.em_ptr[j + 1]; ++q) recs += g.em_k[q] == k ? 1 : 0;
@@ -224,8 +235,7 @@ __global__ void k_inlist_fill(const GridDev *__restrict__ gp) {
       const int rb = g.row_ptr[j], re = g.row_ptr[j + 1];
       const uint32_t lbits = ((uint32_t)lane << 26) | ((uint32_t)b << 24);
       int c = 0;
-      for (int e = rb; e < re; ++e) {
-        if (!fwd_selects(g.fwd[(int64_t)g.nbr[e] * K + k], g.rev[e])) continue;
+      auto take = [&](int e) {
         const uint32_t idx = (uint32_t)sender_index(g, direct, e, rb);
         if (c < kWordEntries) {
           w = (w & ~(511ull << (9 * c))) | ((uint64_t)idx << (9 * c));
@@ -233,7 +243,21 @@ __global__ void k_inlist_fill(const GridDev *__restrict__ gp) {
           g.rec[rp++] = lbits | idx;
         }
         ++c;
+      };
+      int e = rb;
+      // four selection words in flight at a time, taken in row order
+      for (; e + 4 <= re; e += 4) {
+        const uint32_t f0 = g.fwd[(int64_t)g.nbr[e] * K + k];
+        const uint32_t f1 = g.fwd[(int64_t)g.nbr[e + 1] * K + k];
+        const uint32_t f2 = g.fwd[(int64_t)g.nbr[e + 2] * K + k];
+        const uint32_t f3 = g.fwd[(int64_t)g.nbr[e + 3] * K + k];
+        if (fwd_selects(f0, g.rev[e])) take(e);
+        if (fwd_selects(f1, g.rev[e + 1])) take(e + 1);
+        if (fwd_selects(f2, g.rev[e + 2])) take(e + 2);
+        if (fwd_selects(f3, g.rev[e + 3])) take(e + 3);
       }
+      for (; e < re; ++e)
+        if (fwd_selects(g.fwd[(int64_t)g.nbr[e] * K + k], g.rev[e])) take(e);
       // source shares come after the transported photons of the bin
       for (int q = g.em_ptr[j]; q < g.em_ptr[j + 1]; ++q)
         if (g.em_k[q] == k && rp < g.rec_cap) g.rec[rp++] = lbits | kRecEmission | (uint32_t)q;
