@@ -13,6 +13,7 @@
 //   gather lists per (vertex, bin) as 32-bit in-words [tile][K][64].
 #include <utility>
 
+#include "sx.h"
 #include "sx_internal.h"
 
 namespace sx {
@@ -96,66 +97,100 @@ static hipError_t fill(T *p, T v, int64_t n, hipStream_t s) {
 // backwards), ties to the lower original neighbour id.  Rows are sorted by
 // original id, so "lower slot" is "lower id".  With dct_ref the reference
 // direction is the vertex's edge closest to the bin (largest cosine over
-// cos_min, ties to the lower id) in place of the bin.  One lane per pair.
-__global__ void k_select(const GridDev *__restrict__ gp) {
-  const GridDev &g = *gp;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int K = g.k;
-  if (p >= (int64_t)g.npad * K) return;
-  const int i = (int)(p / K);
-  const int k = (int)(p - (int64_t)i * K);
+// cos_min, ties to the lower id) in place of the bin.  One wave per
+// vertex: the vertex's edge directions are staged in LDS once and every
+// lane runs bins lane and lane + 64 over them in row order.
+struct Top3 {
+  double c0 = -3.0, c1 = -3.0, c2 = -3.0;
   uint32_t s0 = kEmptySlot, s1 = kEmptySlot, s2 = kEmptySlot, cnt = 0;
-  if (i < g.n) {
-    double u[3] = {g.bins[3 * k], g.bins[3 * k + 1], g.bins[3 * k + 2]};
-    const int rb = g.row_ptr[i];
-    int re = g.row_ptr[i + 1];
-    if (g.dct_ref) {
-      int best = -1;
-      double cb = g.cos_min;
-      for (int e = rb; e < re; ++e) {
-        const double c = cosine3(&g.edir[3 * (int64_t)e], u);
-        if (c > cb) { cb = c; best = e; }
-      }
-      if (best >= 0) {
-        u[0] = g.edir[3 * (int64_t)best];
-        u[1] = g.edir[3 * (int64_t)best + 1];
-        u[2] = g.edir[3 * (int64_t)best + 2];
-      } else {
-        re = rb;   // no edge in the bin's forward cone: nothing selected
-      }
+  __device__ __forceinline__ void add(double c, uint32_t s, double cos_min) {
+    if (!(c > cos_min)) return;
+    if (c > c0) {
+      c2 = c1; s2 = s1; c1 = c0; s1 = s0; c0 = c; s0 = s;
+    } else if (c > c1) {
+      c2 = c1; s2 = s1; c1 = c; s1 = s;
+    } else if (c > c2) {
+      c2 = c; s2 = s;
     }
-    double c0 = -3.0, c1 = -3.0, c2 = -3.0;
-    for (int e = rb; e < re; ++e) {
-      const double c = cosine3(&g.edir[3 * (int64_t)e], u);
-      if (!(c > g.cos_min)) continue;
-      const uint32_t s = (uint32_t)(e - rb);
-      if (c > c0) {
-        c2 = c1; s2 = s1; c1 = c0; s1 = s0; c0 = c; s0 = s;
-      } else if (c > c1) {
-        c2 = c1; s2 = s1; c1 = c; s1 = s;
-      } else if (c > c2) {
-        c2 = c; s2 = s;
-      }
-      ++cnt;
-    }
-    if (cnt > (uint32_t)g.mpb) cnt = (uint32_t)g.mpb;
-    if (g.mpb < 3) s2 = kEmptySlot;
-    if (g.mpb < 2) s1 = kEmptySlot;
+    ++cnt;
   }
-  g.fwd[p] = s0 | (s1 << 7) | (s2 << 14) | (cnt << 21);
+  __device__ __forceinline__ uint32_t word(int mpb) const {
+    const uint32_t n = cnt > (uint32_t)mpb ? (uint32_t)mpb : cnt;
+    const uint32_t t2 = mpb < 3 ? (uint32_t)kEmptySlot : s2;
+    const uint32_t t1 = mpb < 2 ? (uint32_t)kEmptySlot : s1;
+    return s0 | (t1 << 7) | (t2 << 14) | (n << 21);
+  }
+};
+
+// the reference direction of bin u under dct_ref: the closest edge in the
+// forward cone; returns the number of edges to consider (0 if none)
+__device__ __forceinline__ int ref_edge(const SX_L double *ed, int deg, double cos_min,
+                                        double u[3]) {
+  int best = -1;
+  double cb = cos_min;
+  for (int t = 0; t < deg; ++t) {
+    const double d[3] = {ed[3 * t], ed[3 * t + 1], ed[3 * t + 2]};
+    const double c = cosine3(d, u);
+    if (c > cb) { cb = c; best = t; }
+  }
+  if (best < 0) return 0;
+  u[0] = ed[3 * best];
+  u[1] = ed[3 * best + 1];
+  u[2] = ed[3 * best + 2];
+  return deg;
+}
+
+__global__ __launch_bounds__(256) void k_select(const GridDev *__restrict__ gp) {
+  const GridDev &g = *gp;
+  __shared__ double sd[4][3 * SX_MAX_DEGREE];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + w;
+  const int K = g.k;
+  int rb = 0, deg = 0;
+  if (i < g.n) {
+    rb = g.row_ptr[i];
+    deg = g.row_ptr[i + 1] - rb;
+  }
+  SX_L double *ed = (SX_L double *)sd[w];
+  for (int q = lane; q < 3 * deg; q += 64) ed[q] = g.edir[3 * (int64_t)rb + q];
+  __syncthreads();
+  if (i >= g.npad) return;
+  const int k0 = lane, k1 = lane + 64;
+  double u0[3] = {0.0, 0.0, 0.0}, u1[3] = {0.0, 0.0, 0.0};
+  if (k0 < K) { u0[0] = g.bins[3 * k0]; u0[1] = g.bins[3 * k0 + 1]; u0[2] = g.bins[3 * k0 + 2]; }
+  if (k1 < K) { u1[0] = g.bins[3 * k1]; u1[1] = g.bins[3 * k1 + 1]; u1[2] = g.bins[3 * k1 + 2]; }
+  int n0 = deg, n1 = deg;
+  if (g.dct_ref) {
+    n0 = ref_edge(ed, deg, g.cos_min, u0);
+    n1 = k1 < K ? ref_edge(ed, deg, g.cos_min, u1) : 0;
+  }
+  Top3 a, b;
+  for (int t = 0; t < deg; ++t) {
+    const double d[3] = {ed[3 * t], ed[3 * t + 1], ed[3 * t + 2]};
+    if (t < n0) a.add(cosine3(d, u0), (uint32_t)t, g.cos_min);
+    if (t < n1) b.add(cosine3(d, u1), (uint32_t)t, g.cos_min);
+  }
+  if (k0 < K) g.fwd[i * K + k0] = a.word(g.mpb);
+  if (k1 < K) g.fwd[i * K + k1] = b.word(g.mpb);
 }
 
 // Bin of each directed edge: the bin whose direction is closest to the edge
 // (Sect. 2.2.4), ties to the lower bin.  One lane per edge.
-__global__ void k_edge_bins(const GridDev *__restrict__ gp) {
+__global__ __launch_bounds__(256) void k_edge_bins(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
+  // the bin directions, read by every lane in the same order
+  __shared__ double sb[3 * SX_MAX_BINS_FP32];
+  const int K = g.k;
+  for (int q = threadIdx.x; q < 3 * K; q += blockDim.x) sb[q] = g.bins[q];
+  __syncthreads();
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= g.n_edges) return;
-  const double *ed = &g.edir[3 * e];
+  const double ed[3] = {g.edir[3 * e], g.edir[3 * e + 1], g.edir[3 * e + 2]};
   int best = 0;
-  double cb = cosine3(ed, &g.bins[0]);
-  for (int k = 1; k < g.k; ++k) {
-    const double c = cosine3(ed, &g.bins[3 * k]);
+  double cb = cosine3(ed, &sb[0]);
+#pragma unroll 4
+  for (int k = 1; k < K; ++k) {
+    const double c = cosine3(ed, &sb[3 * k]);
     if (c > cb) { cb = c; best = k; }
   }
   g.ebin[e] = (uint8_t)best;
@@ -320,35 +355,58 @@ __global__ void k_ebin_in(const GridDev *__restrict__ gp) {
   g.ebin_in[e] = g.ebin[g.row_ptr[i] + g.rev[e]];
 }
 
-// Combined transport: how many bins of the sender i select the receiver j
-// of in-edge e (j sits in slot rev[e] of i's row), then the bins in
-// ascending order.  One lane per in-edge.
-__global__ void k_kl_count(const GridDev *__restrict__ gp) {
-  const GridDev &g = *gp;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e > g.n_edges) return;
-  if (e == g.n_edges) {   // the scan's total slot
-    g.kl_cnt[e] = 0;
-    return;
+// Combined transport: the bins of sender i whose selection holds receiver
+// j, ascending, for every in-edge e = (j, slot of i) (j sits in slot rev[e]
+// of i's row).  One wave per sender: lane L holds i's forward words of bins
+// L and L + 64, coalesced, and the wave walks i's out-edges; a ballot per
+// out-edge gives the bins that select it, and the out-edge (i, t) to j is
+// the in-edge row_ptr[j] + rev of j's row.  Pass 1 counts, pass 2 (after a
+// scan) writes each list in bin order.
+static_assert(SX_MAX_BINS_FP32 <= 128 && SX_MAX_BINS_FP64 <= 128 &&
+                  SX_MAX_BINS_FP64 <= SX_MAX_BINS_FP32,
+              "the bin-list kernels hold two bins per lane; edge bins stage up to "
+              "SX_MAX_BINS_FP32 directions");
+
+template <bool FILL>
+__device__ __forceinline__ void kl_sender(const GridDev &g, int64_t i, int lane) {
+  const int K = g.k;
+  const uint32_t *f = g.fwd + i * K;
+  // bins with m = 0 send nothing; a slot value of 127 is never an out-edge
+  uint32_t f0 = lane < K ? f[lane] : 0x7fffffffu;
+  uint32_t f1 = lane + 64 < K ? f[lane + 64] : 0x7fffffffu;
+  if (((f0 >> 21) & 3u) == 0u) f0 = 0x7fffffffu;
+  if (((f1 >> 21) & 3u) == 0u) f1 = 0x7fffffffu;
+  const int rb = g.row_ptr[i], re = g.row_ptr[i + 1];
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  for (int o = rb; o < re; ++o) {
+    const uint32_t t = (uint32_t)(o - rb);
+    const bool s0 = fwd_selects(f0, t), s1 = fwd_selects(f1, t);
+    const uint64_t m0 = __ballot(s0), m1 = __ballot(s1);
+    const int64_t e = (int64_t)g.row_ptr[g.nbr[o]] + g.rev[o];
+    if constexpr (!FILL) {
+      if (lane == 0) g.kl_cnt[e] = __popcll(m0) + __popcll(m1);
+    } else {
+      const int64_t p = g.kl_ptr[e];
+      if (s0) g.kl[p + __popcll(m0 & below)] = (uint8_t)lane;
+      if (s1) g.kl[p + __popcll(m0) + __popcll(m1 & below)] = (uint8_t)(lane + 64);
+    }
   }
-  const int64_t i = g.nbr[e];
-  const uint32_t t = g.rev[e];
-  const uint32_t *f = g.fwd + i * g.k;
-  int c = 0;
-  for (int k = 0; k < g.k; ++k) c += fwd_selects(f[k], t) && ((f[k] >> 21) & 3u) > 0 ? 1 : 0;
-  g.kl_cnt[e] = c;
 }
 
-__global__ void k_kl_fill(const GridDev *__restrict__ gp) {
+__global__ __launch_bounds__(256) void k_kl_count(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= g.n_edges) return;
-  const int64_t i = g.nbr[e];
-  const uint32_t t = g.rev[e];
-  const uint32_t *f = g.fwd + i * g.k;
-  int64_t p = g.kl_ptr[e];
-  for (int k = 0; k < g.k; ++k)
-    if (fwd_selects(f[k], t) && ((f[k] >> 21) & 3u) > 0) g.kl[p++] = (uint8_t)k;
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i == 0 && lane == 0) g.kl_cnt[g.n_edges] = 0;   // the scan's total slot
+  if (i >= g.n) return;
+  kl_sender<false>(g, i, lane);
+}
+
+__global__ __launch_bounds__(256) void k_kl_fill(const GridDev *__restrict__ gp) {
+  const GridDev &g = *gp;
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (i >= g.n) return;
+  kl_sender<true>(g, i, threadIdx.x & 63);
 }
 
 // Bin of each source share: the bin closest to its edge (the edge-bin rule).
@@ -1256,7 +1314,7 @@ static inline unsigned blocks_for(int64_t n, int t) {
 }
 
 hipError_t launch_select(const GridDev *dg, const GridDev &hg, hipStream_t s) {
-  hipLaunchKernelGGL(k_select, dim3(blocks_for((int64_t)hg.npad * hg.k, 256)),
+  hipLaunchKernelGGL(k_select, dim3(blocks_for((int64_t)hg.npad * 64, 256)),
                      dim3(256), 0, s, dg);
   return hipGetLastError();
 }
@@ -1304,14 +1362,16 @@ hipError_t launch_ebin_in(const GridDev *dg, const GridDev &hg, hipStream_t s) {
   return hipGetLastError();
 }
 
+// one wave per vertex (at least one wave, for the total slot)
 hipError_t launch_kl_count(const GridDev *dg, const GridDev &hg, hipStream_t s) {
-  hipLaunchKernelGGL(k_kl_count, dim3(blocks_for(hg.n_edges + 1, 256)), dim3(256), 0, s, dg);
+  hipLaunchKernelGGL(k_kl_count, dim3(blocks_for((int64_t)(hg.n > 0 ? hg.n : 1) * 64, 256)),
+                     dim3(256), 0, s, dg);
   return hipGetLastError();
 }
 
 hipError_t launch_kl_fill(const GridDev *dg, const GridDev &hg, hipStream_t s) {
-  if (hg.n_edges == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_kl_fill, dim3(blocks_for(hg.n_edges, 256)), dim3(256), 0, s, dg);
+  if (hg.n_edges == 0 || hg.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kl_fill, dim3(blocks_for((int64_t)hg.n * 64, 256)), dim3(256), 0, s, dg);
   return hipGetLastError();
 }
 
