@@ -389,7 +389,8 @@ uint64_t bytes_estimate(const Sizes &s, int64_t n_em, int64_t n_rec, int64_t n_h
   uint64_t b = 0;
   b += rnd(4 * (s.npad + 1)) + rnd(4 * s.E) + rnd(s.E) + rnd(24 * s.E) + rnd(24 * s.K);
   b += rnd(4 * s.npad * s.K) + rnd(s.E) + rnd(8 * s.npad * s.kb * s.bb) +
-       rnd(4 * s.npad * s.kw) + 2 * rnd(4 * (s.ntiles * s.K * sx::kRecGroups + 1)) + rnd(4 * n_rec + 4);
+       rnd(4 * s.npad * s.kw) + 2 * rnd(4 * (s.ntiles * s.K * sx::kRecGroups + 1)) + rnd(4 * n_rec + 4) +
+       rnd(16 * s.E + 16) + rnd(4 * s.E + 4);
   b += rnd(4 * (s.ntiles + 1)) + rnd(4 * n_halo + 4) + rnd(2 * s.E) + rnd(s.ntiles);
   b += rnd(4 * (s.npad + 1)) + rnd(4 * n_em + 4) + rnd(8 * n_em + 8);
   b += 6 * rnd(8 * s.npad);
@@ -944,6 +945,10 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   GA(d_rec_ptr, ntiles * K * sx::kRecGroups + 1);
   int64_t *d_part;
   GA(d_part, ntiles * K * sx::kRecGroups / 1024 + 2);
+  uint32_t *d_smask;
+  GA(d_smask, 4 * E + 4);
+  int32_t *d_erev;
+  GA(d_erev, E + 1);
   GA(d_hptr, ntiles + 1);
   GA(d_hvid, halo_vid.size() + 1);
   GA(d_ehidx, E);
@@ -979,6 +984,8 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   h.rec_cnt = d_rec_cnt;
   h.rec_ptr = d_rec_ptr;
   h.scan_part = d_part;
+  h.smask = d_smask;
+  h.erev = d_erev;
   h.rec = nullptr;
   h.rec_cap = 0;
   h.halo_ptr = d_hptr;
@@ -1041,6 +1048,7 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   };
   hipError_t he;
   const int32_t nrow = (int32_t)(ntiles * K * sx::kRecGroups);
+  if ((he = sx::launch_erev(dg, h, st)) != hipSuccess) return kfail(he);
   if ((he = sx::launch_select(dg, h, st)) != hipSuccess) return kfail(he);
   if ((he = sx::launch_edge_bins(dg, h, st)) != hipSuccess) return kfail(he);
   g->n_em = (int64_t)P->em_k.size();

@@ -82,6 +82,9 @@ struct GridDev {
   int32_t *rec_cnt;         // [ntiles*K*kRecGroups+1] scratch: records per (tile, bin, group)
   int32_t *rec_ptr;         // [ntiles*K*kRecGroups+1] first record of each
   int64_t *scan_part;       // [ntiles*K*kRecGroups/1024 + 2] scratch of the record scan
+  int32_t *erev;            // [E+1] the edge of nbr[e]'s row that points back at e's row
+  uint32_t *smask;          // [4*E+4] written by the selection: bit k of word 4e + k/32
+                            // is set iff bin k of sender nbr[e] selects j
   uint32_t *rec;            // [n_rec]
   int64_t rec_cap;
   const int32_t *halo_ptr;  // [ntiles+1]
@@ -138,6 +141,7 @@ struct GridDev {
 
 // Kernel launchers (sx_kernels.hip).  All enqueue on `stream`, return the
 // HIP error of the launch.
+hipError_t launch_erev(const GridDev *dg, const GridDev &hg, hipStream_t s);
 hipError_t launch_select(const GridDev *dg, const GridDev &hg, hipStream_t s);
 hipError_t launch_edge_bins(const GridDev *dg, const GridDev &hg, hipStream_t s);
 hipError_t launch_inlist_count(const GridDev *dg, const GridDev &hg, hipStream_t s);

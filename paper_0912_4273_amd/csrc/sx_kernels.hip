@@ -91,6 +91,15 @@ static hipError_t fill(T *p, T v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// The reverse of every directed edge: e in j's row points at i = nbr[e],
+// and j sits in slot rev[e] of i's row.  One lane per edge, once per upload.
+__global__ void k_erev(const GridDev *__restrict__ gp) {
+  const GridDev &g = *gp;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.n_edges) return;
+  g.erev[e] = g.row_ptr[g.nbr[e]] + g.rev[e];
+}
+
 // -------------------------------------------------------- bin selection --
 // For every (vertex, bin): the <= mpb neighbours with the largest cosine
 // between edge and bin direction, cosine > cos_min (photons never go
@@ -143,8 +152,11 @@ __device__ __forceinline__ int ref_edge(const SX_L double *ed, int deg, double c
 __global__ __launch_bounds__(256) void k_select(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
   __shared__ double sd[4][3 * SX_MAX_DEGREE];
+  // selection masks of the wave's out-edges, 4 words per slot
+  __shared__ __attribute__((aligned(16))) uint32_t sm[4][4 * SX_MAX_DEGREE];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + w;
+  const bool live = i < g.npad;   // the block's barriers are reached by all
   const int K = g.k;
   int rb = 0, deg = 0;
   if (i < g.n) {
@@ -152,26 +164,46 @@ __global__ __launch_bounds__(256) void k_select(const GridDev *__restrict__ gp) 
     deg = g.row_ptr[i + 1] - rb;
   }
   SX_L double *ed = (SX_L double *)sd[w];
+  SX_L uint32_t *ms = (SX_L uint32_t *)sm[w];
   for (int q = lane; q < 3 * deg; q += 64) ed[q] = g.edir[3 * (int64_t)rb + q];
+  for (int q = lane; q < 4 * deg; q += 64) ms[q] = 0u;
   __syncthreads();
-  if (i >= g.npad) return;
   const int k0 = lane, k1 = lane + 64;
-  double u0[3] = {0.0, 0.0, 0.0}, u1[3] = {0.0, 0.0, 0.0};
-  if (k0 < K) { u0[0] = g.bins[3 * k0]; u0[1] = g.bins[3 * k0 + 1]; u0[2] = g.bins[3 * k0 + 2]; }
-  if (k1 < K) { u1[0] = g.bins[3 * k1]; u1[1] = g.bins[3 * k1 + 1]; u1[2] = g.bins[3 * k1 + 2]; }
-  int n0 = deg, n1 = deg;
-  if (g.dct_ref) {
-    n0 = ref_edge(ed, deg, g.cos_min, u0);
-    n1 = k1 < K ? ref_edge(ed, deg, g.cos_min, u1) : 0;
+  if (live) {
+    double u0[3] = {0.0, 0.0, 0.0}, u1[3] = {0.0, 0.0, 0.0};
+    if (k0 < K) { u0[0] = g.bins[3 * k0]; u0[1] = g.bins[3 * k0 + 1]; u0[2] = g.bins[3 * k0 + 2]; }
+    if (k1 < K) { u1[0] = g.bins[3 * k1]; u1[1] = g.bins[3 * k1 + 1]; u1[2] = g.bins[3 * k1 + 2]; }
+    int n0 = deg, n1 = deg;
+    if (g.dct_ref) {
+      n0 = ref_edge(ed, deg, g.cos_min, u0);
+      n1 = k1 < K ? ref_edge(ed, deg, g.cos_min, u1) : 0;
+    }
+    Top3 a, b;
+    for (int t = 0; t < deg; ++t) {
+      const double d[3] = {ed[3 * t], ed[3 * t + 1], ed[3 * t + 2]};
+      if (t < n0) a.add(cosine3(d, u0), (uint32_t)t, g.cos_min);
+      if (t < n1) b.add(cosine3(d, u1), (uint32_t)t, g.cos_min);
+    }
+    const uint32_t w0 = a.word(g.mpb), w1 = b.word(g.mpb);
+    if (k0 < K) g.fwd[i * K + k0] = w0;
+    if (k1 < K) g.fwd[i * K + k1] = w1;
+    // each selected slot of (i, k) gets bit k in its out-edge's mask (an OR,
+    // so the order of the lanes does not matter)
+    auto mark = [&](uint32_t word, int k) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const uint32_t s = (word >> (7 * q)) & 127u;
+        if (s != (uint32_t)kEmptySlot) atomicOr((uint32_t *)&ms[4 * s + (k >> 5)], 1u << (k & 31));
+      }
+    };
+    if (k0 < K) mark(w0, k0);
+    if (k1 < K) mark(w1, k1);
   }
-  Top3 a, b;
-  for (int t = 0; t < deg; ++t) {
-    const double d[3] = {ed[3 * t], ed[3 * t + 1], ed[3 * t + 2]};
-    if (t < n0) a.add(cosine3(d, u0), (uint32_t)t, g.cos_min);
-    if (t < n1) b.add(cosine3(d, u1), (uint32_t)t, g.cos_min);
-  }
-  if (k0 < K) g.fwd[i * K + k0] = a.word(g.mpb);
-  if (k1 < K) g.fwd[i * K + k1] = b.word(g.mpb);
+  __syncthreads();
+  // out-edge (i, t) is the receiver's in-edge erev[rb + t]
+  typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+  for (int t = lane; t < deg; t += 64)
+    *(U4 *)(g.smask + 4 * (int64_t)g.erev[rb + t]) = *(const SX_L U4 *)(ms + 4 * t);
 }
 
 // Bin of each directed edge: the bin whose direction is closest to the edge
@@ -211,9 +243,21 @@ __device__ __forceinline__ int sender_index(const GridDev &g, bool direct,
 constexpr uint32_t kRecEmission = 1u << kRecIdxBits;
 constexpr uint32_t kRecIdxMask = (1u << kRecIdxBits) - 1u;
 
+static_assert(SX_MAX_BINS_FP32 <= 128 && SX_MAX_BINS_FP64 <= 128 &&
+                  SX_MAX_BINS_FP64 <= SX_MAX_BINS_FP32,
+              "selection masks hold 128 bins; edge bins stage up to "
+              "SX_MAX_BINS_FP32 directions");
+
+// The gather-list kernels read the selection from the receiving side: one
+// mask per in-edge e of j (bit k of word 4e + k/32 set iff bin k of sender
+// nbr[e] selects j), written by the selection kernel.
+__device__ __forceinline__ uint32_t sel_bit(const GridDev &g, int e, int k) {
+  return (g.smask[4 * (int64_t)e + (k >> 5)] >> (k & 31)) & 1u;
+}
+
 // Thread (tile, bin, group) walks the kRecGroupLanes receivers of its
 // group in lane order; threads of neighbouring bins are neighbours, so their
-// selection-table reads are contiguous.  Record counts and offsets are kept
+// mask reads fall in the same 16 bytes.  Record counts and offsets are kept
 // per (tile, bin, group), groups in lane order, so the records of a
 // (tile, bin) come out sorted by lane.
 __global__ void k_inlist_count(const GridDev *__restrict__ gp) {
@@ -230,21 +274,11 @@ __global__ void k_inlist_count(const GridDev *__restrict__ gp) {
   for (int lane = grp * kRecGroupLanes; lane < (grp + 1) * kRecGroupLanes; ++lane) {
     const int j = tile * kTile + lane;
     if (j >= g.n) break;
-    int c = 0;
+    uint32_t c = 0;
     const int re = g.row_ptr[j + 1];
-    int e = g.row_ptr[j];
-    // four selection words in flight at a time
-    for (; e + 4 <= re; e += 4) {
-      const uint32_t f0 = g.fwd[(int64_t)g.nbr[e] * K + k];
-      const uint32_t f1 = g.fwd[(int64_t)g.nbr[e + 1] * K + k];
-      const uint32_t f2 = g.fwd[(int64_t)g.nbr[e + 2] * K + k];
-      const uint32_t f3 = g.fwd[(int64_t)g.nbr[e + 3] * K + k];
-      c += (fwd_selects(f0, g.rev[e]) ? 1 : 0) + (fwd_selects(f1, g.rev[e + 1]) ? 1 : 0) +
-           (fwd_selects(f2, g.rev[e + 2]) ? 1 : 0) + (fwd_selects(f3, g.rev[e + 3]) ? 1 : 0);
-    }
-    for (; e < re; ++e)
-      c += fwd_selects(g.fwd[(int64_t)g.nbr[e] * K + k], g.rev[e]) ? 1 : 0;
-    recs += c > kWordEntries ? c - kWordEntries : 0;
+#pragma unroll 4
+    for (int e = g.row_ptr[j]; e < re; ++e) c += sel_bit(g, e, k);
+    recs += c > (uint32_t)kWordEntries ? (int)c - kWordEntries : 0;
     for (int q = g.em_ptr[j]; q < g.em_ptr[j + 1]; ++q) recs += g.em_k[q] == k ? 1 : 0;
   }
   g.rec_cnt[((int64_t)tile * K + k) * kRecGroups + grp] = recs;
@@ -280,19 +314,17 @@ __global__ void k_inlist_fill(const GridDev *__restrict__ gp) {
         ++c;
       };
       int e = rb;
-      // four selection words in flight at a time, taken in row order
+      // four masks in flight at a time, taken in row order
       for (; e + 4 <= re; e += 4) {
-        const uint32_t f0 = g.fwd[(int64_t)g.nbr[e] * K + k];
-        const uint32_t f1 = g.fwd[(int64_t)g.nbr[e + 1] * K + k];
-        const uint32_t f2 = g.fwd[(int64_t)g.nbr[e + 2] * K + k];
-        const uint32_t f3 = g.fwd[(int64_t)g.nbr[e + 3] * K + k];
-        if (fwd_selects(f0, g.rev[e])) take(e);
-        if (fwd_selects(f1, g.rev[e + 1])) take(e + 1);
-        if (fwd_selects(f2, g.rev[e + 2])) take(e + 2);
-        if (fwd_selects(f3, g.rev[e + 3])) take(e + 3);
+        const uint32_t s0 = sel_bit(g, e, k), s1 = sel_bit(g, e + 1, k);
+        const uint32_t s2 = sel_bit(g, e + 2, k), s3 = sel_bit(g, e + 3, k);
+        if (s0) take(e);
+        if (s1) take(e + 1);
+        if (s2) take(e + 2);
+        if (s3) take(e + 3);
       }
       for (; e < re; ++e)
-        if (fwd_selects(g.fwd[(int64_t)g.nbr[e] * K + k], g.rev[e])) take(e);
+        if (sel_bit(g, e, k)) take(e);
       // source shares come after the transported photons of the bin
       for (int q = g.em_ptr[j]; q < g.em_ptr[j + 1]; ++q)
         if (g.em_k[q] == k && rp < g.rec_cap) g.rec[rp++] = lbits | kRecEmission | (uint32_t)q;
@@ -356,57 +388,35 @@ __global__ void k_ebin_in(const GridDev *__restrict__ gp) {
 }
 
 // Combined transport: the bins of sender i whose selection holds receiver
-// j, ascending, for every in-edge e = (j, slot of i) (j sits in slot rev[e]
-// of i's row).  One wave per sender: lane L holds i's forward words of bins
-// L and L + 64, coalesced, and the wave walks i's out-edges; a ballot per
-// out-edge gives the bins that select it, and the out-edge (i, t) to j is
-// the in-edge row_ptr[j] + rev of j's row.  Pass 1 counts, pass 2 (after a
-// scan) writes each list in bin order.
-static_assert(SX_MAX_BINS_FP32 <= 128 && SX_MAX_BINS_FP64 <= 128 &&
-                  SX_MAX_BINS_FP64 <= SX_MAX_BINS_FP32,
-              "the bin-list kernels hold two bins per lane; edge bins stage up to "
-              "SX_MAX_BINS_FP32 directions");
+// j, ascending, for every in-edge e = (j, slot of i): the set bits of the
+// in-edge's selection mask (a bin with m = 0 selects no slot).  One lane per
+// in-edge; pass 1 counts, pass 2 (after a scan) writes each list.
+__global__ void k_kl_count(const GridDev *__restrict__ gp) {
+  const GridDev &g = *gp;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e > g.n_edges) return;
+  if (e == g.n_edges) {   // the scan's total slot
+    g.kl_cnt[e] = 0;
+    return;
+  }
+  const uint32_t *m = g.smask + 4 * e;
+  g.kl_cnt[e] = __popc(m[0]) + __popc(m[1]) + __popc(m[2]) + __popc(m[3]);
+}
 
-template <bool FILL>
-__device__ __forceinline__ void kl_sender(const GridDev &g, int64_t i, int lane) {
-  const int K = g.k;
-  const uint32_t *f = g.fwd + i * K;
-  // bins with m = 0 send nothing; a slot value of 127 is never an out-edge
-  uint32_t f0 = lane < K ? f[lane] : 0x7fffffffu;
-  uint32_t f1 = lane + 64 < K ? f[lane + 64] : 0x7fffffffu;
-  if (((f0 >> 21) & 3u) == 0u) f0 = 0x7fffffffu;
-  if (((f1 >> 21) & 3u) == 0u) f1 = 0x7fffffffu;
-  const int rb = g.row_ptr[i], re = g.row_ptr[i + 1];
-  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  for (int o = rb; o < re; ++o) {
-    const uint32_t t = (uint32_t)(o - rb);
-    const bool s0 = fwd_selects(f0, t), s1 = fwd_selects(f1, t);
-    const uint64_t m0 = __ballot(s0), m1 = __ballot(s1);
-    const int64_t e = (int64_t)g.row_ptr[g.nbr[o]] + g.rev[o];
-    if constexpr (!FILL) {
-      if (lane == 0) g.kl_cnt[e] = __popcll(m0) + __popcll(m1);
-    } else {
-      const int64_t p = g.kl_ptr[e];
-      if (s0) g.kl[p + __popcll(m0 & below)] = (uint8_t)lane;
-      if (s1) g.kl[p + __popcll(m0) + __popcll(m1 & below)] = (uint8_t)(lane + 64);
+__global__ void k_kl_fill(const GridDev *__restrict__ gp) {
+  const GridDev &g = *gp;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.n_edges) return;
+  const uint32_t *m = g.smask + 4 * e;
+  int64_t p = g.kl_ptr[e];
+  for (int q = 0; q < 4; ++q) {
+    uint32_t w = m[q];
+    while (w) {
+      const int bit = __ffs(w) - 1;
+      g.kl[p++] = (uint8_t)(32 * q + bit);
+      w &= w - 1u;
     }
   }
-}
-
-__global__ __launch_bounds__(256) void k_kl_count(const GridDev *__restrict__ gp) {
-  const GridDev &g = *gp;
-  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
-  if (i == 0 && lane == 0) g.kl_cnt[g.n_edges] = 0;   // the scan's total slot
-  if (i >= g.n) return;
-  kl_sender<false>(g, i, lane);
-}
-
-__global__ __launch_bounds__(256) void k_kl_fill(const GridDev *__restrict__ gp) {
-  const GridDev &g = *gp;
-  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (i >= g.n) return;
-  kl_sender<true>(g, i, threadIdx.x & 63);
 }
 
 // Bin of each source share: the bin closest to its edge (the edge-bin rule).
@@ -427,19 +437,23 @@ __global__ void k_em_bins(GridDev *__restrict__ gp, int64_t n_em) {
 // Packed m(j, k), 2 bits per bin, 16 bins per word.  One lane per vertex.
 __global__ void k_mbits(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= g.npad) return;
-  const int tile = j >> 6, lane = j & 63;
+  // thread = ((tile * kw + word) * 64 + lane), the index it writes
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)g.npad * g.kw) return;
+  const int lane = (int)(t & 63);
+  const int64_t tq = t >> 6;
+  const int q = (int)(tq % g.kw), tile = (int)(tq / g.kw);
+  const int j = tile * kTile + lane;
   const int K = g.k;
+  const int k0 = 16 * q;
+  uint32_t v[16];
+#pragma unroll
+  for (int b = 0; b < 16; ++b)
+    v[b] = (j < g.n && k0 + b < K) ? g.fwd[(int64_t)j * K + k0 + b] : 0u;
   uint32_t mword = 0;
-  for (int k = 0; k < K; ++k) {
-    const uint32_t m = j < g.n ? (g.fwd[(int64_t)j * K + k] >> 21) & 3u : 0u;
-    mword |= m << (2 * (k & 15));
-    if ((k & 15) == 15 || k == K - 1) {
-      g.mbits[((int64_t)tile * g.kw + (k >> 4)) * 64 + lane] = mword;
-      mword = 0;
-    }
-  }
+#pragma unroll
+  for (int b = 0; b < 16; ++b) mword |= ((v[b] >> 21) & 3u) << (2 * b);
+  g.mbits[t] = mword;
 }
 
 // Exclusive scan of n counts into ptr[0..n] (ptr[n] = total) in three
@@ -1313,6 +1327,12 @@ static inline unsigned blocks_for(int64_t n, int t) {
   return (unsigned)((n + t - 1) / t);
 }
 
+hipError_t launch_erev(const GridDev *dg, const GridDev &hg, hipStream_t s) {
+  if (hg.n_edges == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_erev, dim3(blocks_for(hg.n_edges, 256)), dim3(256), 0, s, dg);
+  return hipGetLastError();
+}
+
 hipError_t launch_select(const GridDev *dg, const GridDev &hg, hipStream_t s) {
   hipLaunchKernelGGL(k_select, dim3(blocks_for((int64_t)hg.npad * 64, 256)),
                      dim3(256), 0, s, dg);
@@ -1340,7 +1360,8 @@ hipError_t launch_clear_inw(const GridDev &hg, hipStream_t s) {
 }
 
 hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s) {
-  hipLaunchKernelGGL(k_mbits, dim3(blocks_for(hg.npad, 256)), dim3(256), 0, s, dg);
+  hipLaunchKernelGGL(k_mbits, dim3(blocks_for((int64_t)hg.npad * hg.kw, 256)), dim3(256), 0, s,
+                     dg);
   return hipGetLastError();
 }
 
@@ -1362,16 +1383,14 @@ hipError_t launch_ebin_in(const GridDev *dg, const GridDev &hg, hipStream_t s) {
   return hipGetLastError();
 }
 
-// one wave per vertex (at least one wave, for the total slot)
 hipError_t launch_kl_count(const GridDev *dg, const GridDev &hg, hipStream_t s) {
-  hipLaunchKernelGGL(k_kl_count, dim3(blocks_for((int64_t)(hg.n > 0 ? hg.n : 1) * 64, 256)),
-                     dim3(256), 0, s, dg);
+  hipLaunchKernelGGL(k_kl_count, dim3(blocks_for(hg.n_edges + 1, 256)), dim3(256), 0, s, dg);
   return hipGetLastError();
 }
 
 hipError_t launch_kl_fill(const GridDev *dg, const GridDev &hg, hipStream_t s) {
-  if (hg.n_edges == 0 || hg.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_kl_fill, dim3(blocks_for((int64_t)hg.n * 64, 256)), dim3(256), 0, s, dg);
+  if (hg.n_edges == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kl_fill, dim3(blocks_for(hg.n_edges, 256)), dim3(256), 0, s, dg);
   return hipGetLastError();
 }
 
