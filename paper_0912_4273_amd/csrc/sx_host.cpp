@@ -477,10 +477,11 @@ int rebuild_routing(sx_ctx *ctx, Grid *g, const double *bins, bool rescale) {
   HIP_TRY(ctx, hipMemcpyAsync(const_cast<double *>(h.bins), bins, sizeof(double) * 3 * h.k,
                               hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, sx::launch_select(dg, h, st));
-  if (rescale) HIP_TRY(ctx, sx::launch_rot_rescale(dg, h, st));
   HIP_TRY(ctx, sx::launch_em_bins(dg, h, g->n_em, st));
   g->ebin_stale = true;   // the full edge-bin table is rebuilt when read
-  HIP_TRY(ctx, sx::launch_mbits(dg, h, st));
+  // m words; with rescale the photons in flight are re-split first
+  if (rescale) HIP_TRY(ctx, sx::launch_mbits_rescale(dg, h, st));
+  else HIP_TRY(ctx, sx::launch_mbits(dg, h, st));
   HIP_TRY(ctx, sx::launch_clear_inw(h, st));
   HIP_TRY(ctx, sx::launch_inlist_count(dg, h, st));
   HIP_TRY(ctx, sx::launch_scan(h.rec_cnt, h.rec_ptr, h.scan_part, nrow, st));

@@ -150,7 +150,7 @@ hipError_t launch_inlist_fill(const GridDev *dg, const GridDev &hg, hipStream_t 
 // After a rotation of the bins: the photons each (vertex, bin) holds are
 // re-split over the new selection (from fwd; the old one is still in
 // mbits); those with no forward neighbour left move to the escape tally.
-hipError_t launch_rot_rescale(GridDev *dg, const GridDev &hg, hipStream_t s);
+hipError_t launch_mbits_rescale(GridDev *dg, const GridDev &hg, hipStream_t s);
 // Bin of each source share from its edge's bin.
 hipError_t launch_em_bins(GridDev *dg, const GridDev &hg, int64_t n_em, hipStream_t s);
 hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s);

@@ -333,50 +333,6 @@ __global__ void k_inlist_fill(const GridDev *__restrict__ gp) {
   }
 }
 
-// Re-split after a rotation of the bins, one wave per tile, lane = vertex.
-// Each (vertex, bin) holds m_old * Ipre * T photons (T of the step that
-// wrote them); they now go to m_new neighbours, Ipre' = Ipre m_old / m_new
-// (unchanged if m_new = m_old), or escape if m_new = 0.  The escaping
-// photons move from the tile's in-flight tally to its escape tally.
-template <typename P>
-__device__ __forceinline__ void rot_rescale(GridDev &g, int tile, int lane) {
-  constexpr int BB = kBlockBytes / sizeof(P);
-  const int K = g.k;
-  const int j = tile * kTile + lane;
-  const int par = g.parity;
-  P *o = (P *)g.o[par];
-  const double T = (double)((const P *)g.t[par])[j];
-  const uint32_t *mb = g.mbits + (int64_t)tile * g.kw * 64 + lane;
-  double esc = 0.0;
-  for (int k = 0; k < K; ++k) {
-    const uint32_t mo = (mb[(k >> 4) * 64] >> (2 * (k & 15))) & 3u;
-    const uint32_t mn = (g.fwd[(int64_t)j * K + k] >> 21) & 3u;
-    if (mn == mo) continue;
-    const int kb = k / BB, b = k - kb * BB;
-    P &v = o[(((int64_t)tile * g.kb + kb) * 64 + lane) * BB + b];
-    if (mn == 0u) {
-      esc += (double)v * (double)mo * T;
-      v = P(0);
-    } else {
-      v = (P)((double)v * (double)mo / (double)mn);
-    }
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) esc += __shfl_xor(esc, off);
-  if (lane == 0) {
-    g.tally[(int64_t)tile * 3 + 1] += esc;
-    g.tally[(int64_t)tile * 3 + 2] -= esc;
-  }
-}
-
-__global__ __launch_bounds__(64) void k_rot_rescale(GridDev *__restrict__ gp) {
-  GridDev &g = *gp;
-  if (g.precision == 0)
-    rot_rescale<double>(g, blockIdx.x, threadIdx.x);
-  else
-    rot_rescale<float>(g, blockIdx.x, threadIdx.x);
-}
-
 // Combined transport: the bin of each in-edge (j, slot of i), which is the
 // bin of the edge i -> j.  One lane per in-edge.
 __global__ void k_ebin_in(const GridDev *__restrict__ gp) {
@@ -435,14 +391,45 @@ __global__ void k_em_bins(GridDev *__restrict__ gp, int64_t n_em) {
 }
 
 // Packed m(j, k), 2 bits per bin, 16 bins per word.  One lane per vertex.
-__global__ void k_mbits(const GridDev *__restrict__ gp) {
-  const GridDev &g = *gp;
-  // thread = ((tile * kw + word) * 64 + lane), the index it writes
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)g.npad * g.kw) return;
-  const int lane = (int)(t & 63);
-  const int64_t tq = t >> 6;
-  const int q = (int)(tq % g.kw), tile = (int)(tq / g.kw);
+// Re-split after a rotation of the bins, for the 16 bins of one m word of
+// one vertex j: each (j, bin) holds m_old * Ipre * T photons (T of the step
+// that wrote them); they now go to m_new neighbours, Ipre' = Ipre m_old /
+// m_new (unchanged if m_new = m_old), or escape if m_new = 0.  Returns the
+// escaping photons, which move from the in-flight tally to the escape tally.
+template <typename P>
+__device__ __forceinline__ double rescale16(GridDev &g, int tile, int lane, int k0,
+                                            uint32_t mold, uint32_t mnew) {
+  constexpr int BB = kBlockBytes / sizeof(P);
+  const int j = tile * kTile + lane;
+  const int par = g.parity;
+  P *o = (P *)g.o[par];
+  const double T = (double)((const P *)g.t[par])[j];
+  double esc = 0.0;
+  for (int b = 0; b < 16 && k0 + b < g.k; ++b) {
+    const uint32_t mo = (mold >> (2 * b)) & 3u, mn = (mnew >> (2 * b)) & 3u;
+    if (mn == mo) continue;
+    const int k = k0 + b, kb = k / BB, kk = k - kb * BB;
+    P &v = o[(((int64_t)tile * g.kb + kb) * 64 + lane) * BB + kk];
+    if (mn == 0u) {
+      esc += (double)v * (double)mo * T;
+      v = P(0);
+    } else {
+      v = (P)((double)v * (double)mo / (double)mn);
+    }
+  }
+  return esc;
+}
+
+// Packed m(j, k) from the selection, one workgroup per tile and one wave
+// per 16-bin word (thread = word * 64 + lane).  With RESCALE (a rotation of
+// the bins) the photons in flight are first re-split from the old m to the
+// new, and the tile's escapes are summed in a fixed order: over the word's
+// bins, a butterfly over lanes, then over words.
+template <bool RESCALE>
+__global__ __launch_bounds__(64 * 6) void k_mbits(GridDev *__restrict__ gp) {
+  GridDev &g = *gp;
+  __shared__ double part[6];
+  const int tile = blockIdx.x, q = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = tile * kTile + lane;
   const int K = g.k;
   const int k0 = 16 * q;
@@ -453,7 +440,23 @@ __global__ void k_mbits(const GridDev *__restrict__ gp) {
   uint32_t mword = 0;
 #pragma unroll
   for (int b = 0; b < 16; ++b) mword |= ((v[b] >> 21) & 3u) << (2 * b);
-  g.mbits[t] = mword;
+  const int64_t wi = ((int64_t)tile * g.kw + q) * 64 + lane;
+  if constexpr (RESCALE) {
+    const uint32_t mold = g.mbits[wi];
+    double esc = g.precision == 0 ? rescale16<double>(g, tile, lane, k0, mold, mword)
+                                  : rescale16<float>(g, tile, lane, k0, mold, mword);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) esc += __shfl_xor(esc, off);
+    if (lane == 0) part[q] = esc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sum = 0.0;
+      for (int w = 0; w < g.kw; ++w) sum += part[w];
+      g.tally[(int64_t)tile * 3 + 1] += sum;
+      g.tally[(int64_t)tile * 3 + 2] -= sum;
+    }
+  }
+  g.mbits[wi] = mword;
 }
 
 // Exclusive scan of n counts into ptr[0..n] (ptr[n] = total) in three
@@ -1360,16 +1363,16 @@ hipError_t launch_clear_inw(const GridDev &hg, hipStream_t s) {
 }
 
 hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s) {
-  hipLaunchKernelGGL(k_mbits, dim3(blocks_for((int64_t)hg.npad * hg.kw, 256)), dim3(256), 0, s,
-                     dg);
+  // the plain variant writes the m words only
+  hipLaunchKernelGGL(k_mbits<false>, dim3((unsigned)hg.ntiles), dim3(64 * hg.kw), 0, s,
+                     const_cast<GridDev *>(dg));
   return hipGetLastError();
 }
 
-hipError_t launch_rot_rescale(GridDev *dg, const GridDev &hg, hipStream_t s) {
-  hipLaunchKernelGGL(k_rot_rescale, dim3((unsigned)hg.ntiles), dim3(64), 0, s, dg);
+hipError_t launch_mbits_rescale(GridDev *dg, const GridDev &hg, hipStream_t s) {
+  hipLaunchKernelGGL(k_mbits<true>, dim3((unsigned)hg.ntiles), dim3(64 * hg.kw), 0, s, dg);
   return hipGetLastError();
 }
-
 hipError_t launch_em_bins(GridDev *dg, const GridDev &hg, int64_t n_em, hipStream_t s) {
   (void)hg;
   if (n_em <= 0) return hipSuccess;
