@@ -390,7 +390,6 @@ __global__ void k_em_bins(GridDev *__restrict__ gp, int64_t n_em) {
   g.em_k[q] = best;
 }
 
-// Packed m(j, k), 2 bits per bin, 16 bins per word.  One lane per vertex.
 // Re-split after a rotation of the bins, for the 16 bins of one m word of
 // one vertex j: each (j, bin) holds m_old * Ipre * T photons (T of the step
 // that wrote them); they now go to m_new neighbours, Ipre' = Ipre m_old /
@@ -420,11 +419,12 @@ __device__ __forceinline__ double rescale16(GridDev &g, int tile, int lane, int 
   return esc;
 }
 
-// Packed m(j, k) from the selection, one workgroup per tile and one wave
-// per 16-bin word (thread = word * 64 + lane).  With RESCALE (a rotation of
-// the bins) the photons in flight are first re-split from the old m to the
-// new, and the tile's escapes are summed in a fixed order: over the word's
-// bins, a butterfly over lanes, then over words.
+// Packed m(j, k), 2 bits per bin and 16 bins per word, from the selection:
+// one workgroup per tile and one wave per 16-bin word (thread = word * 64 +
+// lane).  With RESCALE (a rotation of the bins) the photons in flight are
+// first re-split from the old m to the new, and the tile's escapes are
+// summed in a fixed order: over the word's bins, a butterfly over lanes,
+// then over words.
 template <bool RESCALE>
 __global__ __launch_bounds__(64 * 6) void k_mbits(GridDev *__restrict__ gp) {
   GridDev &g = *gp;
@@ -774,7 +774,9 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
     }
 #pragma unroll
     for (int h = 0; h < BB / 2; ++h) {
-      const W2 w2 = iw[(int64_t)kb * kTile * (BB / 2) + h];
+      // in-words are read once per sweep: a non-temporal load keeps them
+      // from displacing the photon planes that the next sweep reads back
+      const W2 w2 = __builtin_nontemporal_load(&iw[(int64_t)kb * kTile * (BB / 2) + h]);
       wq[slot][2 * h] = w2.x;
       wq[slot][2 * h + 1] = w2.y;
     }
