@@ -40,6 +40,11 @@ constexpr uint64_t kEmptyWord = 0x7FFFFFFFFFFFFFFFull;  // 7 x 511
 constexpr int kBlockBytes = 16;
 // Record counts and offsets per (tile, bin, group of kRecGroupLanes lanes).
 constexpr int kRecGroups = 8;
+// The last-level cache (Infinity Cache) of the GPU.  When the photon planes
+// of all grids in one direction-conserving launch fit in it, the sweep loads
+// its in-words non-temporal, so that the planes stay cached from one sweep to
+// the next; on larger launches the hint costs time and is not used.
+constexpr int64_t kLlcBytes = 256ll << 20;
 constexpr int kRecGroupLanes = kTile / kRecGroups;
 constexpr int kRecIdxBits = 23;
 // Forward word of a (vertex, bin) pair (selection result):
@@ -178,6 +183,7 @@ struct SweepLaunch {
   int32_t xcd_remap;
   int32_t tpb, precision;
   int32_t transport;
+  int32_t nt;   // in-words loaded non-temporal (the photon planes fit kLlcBytes)
 };
 hipError_t launch_sweep(const SweepLaunch &l, hipStream_t s);
 hipError_t add_sweep_node(hipGraph_t graph, const SweepLaunch &l, hipGraphNode_t *prev);

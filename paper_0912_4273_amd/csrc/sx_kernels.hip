@@ -698,7 +698,7 @@ __device__ __forceinline__ void ct_finish(const GridDev *__restrict__ G, int til
   }
 }
 
-template <typename P, bool DIRECT, bool CT = false>
+template <typename P, bool DIRECT, bool CT = false, bool NT = false>
 __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int tile,
                                            int lane, volatile SX_L P *hl,
                                            volatile SX_L P *xchg,
@@ -774,9 +774,14 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
     }
 #pragma unroll
     for (int h = 0; h < BB / 2; ++h) {
-      // in-words are read once per sweep: a non-temporal load keeps them
-      // from displacing the photon planes that the next sweep reads back
-      const W2 w2 = __builtin_nontemporal_load(&iw[(int64_t)kb * kTile * (BB / 2) + h]);
+      // in-words are read once per sweep.  With NT (the launch's photon
+      // planes fit in the last-level cache) they are loaded non-temporal, so
+      // that they do not displace the planes the next sweep reads back.
+      W2 w2;
+      if constexpr (NT)
+        w2 = __builtin_nontemporal_load(&iw[(int64_t)kb * kTile * (BB / 2) + h]);
+      else
+        w2 = iw[(int64_t)kb * kTile * (BB / 2) + h];
       wq[slot][2 * h] = w2.x;
       wq[slot][2 * h + 1] = w2.y;
     }
@@ -967,7 +972,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
 // list and its L2 sees one neighbourhood.  The workgroup that finishes last
 // flips the buffers of the listed grids and clears the completion counter,
 // so consecutive launches are identical and need no kernel between them.
-template <typename P, int TPB>
+template <typename P, int TPB, bool NT>
 __global__ __launch_bounds__(64 * TPB, 4) void k_sweep(
     GridDev *__restrict__ grids, const int2 *__restrict__ tile_map,
     int32_t n_tiles, const int32_t *__restrict__ adv, int32_t n_adv,
@@ -994,9 +999,9 @@ __global__ __launch_bounds__(64 * TPB, 4) void k_sweep(
       volatile SX_L P *hl = (volatile SX_L P *)hbuf[wave];
       volatile SX_L P *xc = (volatile SX_L P *)xbuf[wave];
       if (gld(G->tile_direct)[tile] != 0)
-        sweep_tile<P, true>(G, tile, lane, hl, xc);
+        sweep_tile<P, true, false, NT>(G, tile, lane, hl, xc);
       else
-        sweep_tile<P, false>(G, tile, lane, hl, xc);
+        sweep_tile<P, false, false, NT>(G, tile, lane, hl, xc);
     }
   }
   // completion count; the last workgroup advances the grids
@@ -1462,12 +1467,12 @@ hipError_t launch_reset_state(GridDev *dg, const GridDev &hg, const double *y0,
   return hipGetLastError();
 }
 
-template <typename P>
+template <typename P, bool NT>
 static const void *sweep_fn(int tpb) {
   switch (tpb) {
-    case 1: return (const void *)k_sweep<P, 1>;
-    case 2: return (const void *)k_sweep<P, 2>;
-    case 4: return (const void *)k_sweep<P, 4>;
+    case 1: return (const void *)k_sweep<P, 1, NT>;
+    case 2: return (const void *)k_sweep<P, 2, NT>;
+    case 4: return (const void *)k_sweep<P, 4, NT>;
   }
   return nullptr;
 }
@@ -1481,7 +1486,9 @@ static hipError_t sweep_shape(const SweepLaunch &l, const void **fn, dim3 *grid,
     *block = dim3(64u);
     return hipSuccess;
   }
-  const void *f = l.precision == 0 ? sweep_fn<double>(l.tpb) : sweep_fn<float>(l.tpb);
+  const void *f = l.precision == 0
+                      ? (l.nt ? sweep_fn<double, true>(l.tpb) : sweep_fn<double, false>(l.tpb))
+                      : (l.nt ? sweep_fn<float, true>(l.tpb) : sweep_fn<float, false>(l.tpb));
   if (!f || l.n_tiles <= 0 || !l.done) return hipErrorInvalidValue;
   *fn = f;
   // one workgroup per tpb tiles, rounded up to a multiple of 8

@@ -98,9 +98,23 @@ def test_combined_one_step_from_shared_state(sxctx, prec):
     mode decisions from the same neutral fractions)."""
     w = _work(3000, seed=64, prec=prec, tau_switch=1.0)
     print(f"[case] combined one step prec={prec}", flush=True)
+    _one_step_after(sxctx, w, prec, 50, f"one step prec {prec}")
+
+
+@pytest.mark.parametrize("prec", [G.SX_FP64, G.SX_FP32_TRANSPORT])
+def test_combined_largest_bin_count(sxctx, prec):
+    """96 bins: selection masks and per-edge bin lists past bin 64, and in
+    fp64 all 48 bin blocks of a vertex (the per-block flags of photons from
+    ballistic senders).  Mixed modes, one step from a shared state."""
+    w = _work(3000, seed=65, k=96, prec=prec, tau_switch=1.0)
+    print(f"[case] combined 96 bins prec={prec}", flush=True)
+    _one_step_after(sxctx, w, prec, 50, f"96 bins prec {prec}")
+
+
+def _one_step_after(sxctx, w, prec, steps, label):
     gid = sxctx.upload(w)
     try:
-        sxctx.solve([gid], 50)
+        sxctx.solve([gid], steps)
         s1, e1 = sxctx.state(gid, photons=True), sxctx.edge_state(gid)
         sxctx.solve([gid], 1)
         s2, e2 = sxctx.state(gid, photons=True), sxctx.edge_state(gid)
@@ -114,8 +128,8 @@ def test_combined_one_step_from_shared_state(sxctx, prec):
     o.run(1)
     rs, re_ = o.state(), o.edge_state()
     o.close()
-    assert_state_close(s2, rs, prec, unit, f"one step prec {prec}")
-    assert_edges_close(e2, re_, prec, unit, f"one step prec {prec}")
+    assert_state_close(s2, rs, prec, unit, label)
+    assert_edges_close(e2, re_, prec, unit, label)
 
 
 @pytest.mark.parametrize("prec", [G.SX_FP64, G.SX_FP32_TRANSPORT])
