@@ -173,9 +173,11 @@ __global__ __launch_bounds__(256) void k_select(const GridDev *__restrict__ gp) 
     double u0[3] = {0.0, 0.0, 0.0}, u1[3] = {0.0, 0.0, 0.0};
     if (k0 < K) { u0[0] = g.bins[3 * k0]; u0[1] = g.bins[3 * k0 + 1]; u0[2] = g.bins[3 * k0 + 2]; }
     if (k1 < K) { u1[0] = g.bins[3 * k1]; u1[1] = g.bins[3 * k1 + 1]; u1[2] = g.bins[3 * k1 + 2]; }
-    int n0 = deg, n1 = deg;
+    // edges each bin considers (none for a lane past the last bin, so that
+    // with K <= 64 the second bin's work is skipped by the whole wave)
+    int n0 = k0 < K ? deg : 0, n1 = k1 < K ? deg : 0;
     if (g.dct_ref) {
-      n0 = ref_edge(ed, deg, g.cos_min, u0);
+      n0 = k0 < K ? ref_edge(ed, deg, g.cos_min, u0) : 0;
       n1 = k1 < K ? ref_edge(ed, deg, g.cos_min, u1) : 0;
     }
     Top3 a, b;
