@@ -1235,6 +1235,9 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
       }
     }
   }
+  // the per-edge sums are dead from here on: their LDS becomes the halo
+  // planes of the tile code
+  __syncthreads();
 
   // 3. ballistic receivers only: no bins to gather
   if (balmask == validmask) {
@@ -1256,20 +1259,24 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
   if (valid) lout[j] = bal ? 1 : 0;
 }
 
-// LDS of one combined-transport workgroup: the tile code's halo plane and
-// hand-over slots, and the per-edge sums.
+// LDS of one combined-transport workgroup: the per-edge sums of the edge
+// phase share their space with the tile code's halo planes (the sums are
+// read before the tile code stages its first block, with a barrier
+// between), then the hand-over slots.
 template <typename P>
 struct CtLds {
   static constexpr int BB = kBlockBytes / sizeof(P);
-  P h[kHaloPlane * BB];
+  union {
+    P h[kHaloPlane * BB];
+    P ve[kVeCap];
+  };
   P x[kTile * BB];
-  P ve[kVeCap];
 };
 
 // One combined-transport step over a tile list: one tile per workgroup of
 // one wave, the same tile lists, XCD numbering and completion as k_sweep.
 template <typename P>
-__global__ __launch_bounds__(64) void k_sweep_ct(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_ct(
     GridDev *__restrict__ grids, const int2 *__restrict__ tile_map,
     int32_t n_tiles, const int32_t *__restrict__ adv, int32_t n_adv,
     uint32_t *__restrict__ done, int32_t xcd_remap) {
