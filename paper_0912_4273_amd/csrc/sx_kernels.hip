@@ -427,6 +427,9 @@ __device__ __forceinline__ double rescale16(GridDev &g, int tile, int lane, int 
 // first re-split from the old m to the new, and the tile's escapes are
 // summed in a fixed order: over the word's bins, a butterfly over lanes,
 // then over words.
+static_assert((SX_MAX_BINS_FP32 + 15) / 16 <= 6 && (SX_MAX_BINS_FP64 + 15) / 16 <= 6,
+              "k_mbits holds at most 6 m words per vertex (one wave each)");
+
 template <bool RESCALE>
 __global__ __launch_bounds__(64 * 6) void k_mbits(GridDev *__restrict__ gp) {
   GridDev &g = *gp;
