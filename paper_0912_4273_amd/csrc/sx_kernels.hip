@@ -306,8 +306,7 @@ __global__ void k_inlist_fill(const GridDev *__restrict__ gp) {
       const int rb = g.row_ptr[j], re = g.row_ptr[j + 1];
       const uint32_t lbits = ((uint32_t)lane << 26) | ((uint32_t)b << 24);
       int c = 0;
-      auto take = [&](int e) {
-        const uint32_t idx = (uint32_t)sender_index(g, direct, e, rb);
+      auto take = [&](uint32_t idx) {
         if (c < kWordEntries) {
           w = (w & ~(511ull << (9 * c))) | ((uint64_t)idx << (9 * c));
         } else if (rp < g.rec_cap) {
@@ -316,17 +315,21 @@ __global__ void k_inlist_fill(const GridDev *__restrict__ gp) {
         ++c;
       };
       int e = rb;
-      // four masks in flight at a time, taken in row order
+      // four masks and sender indices in flight at a time, taken in row order
       for (; e + 4 <= re; e += 4) {
         const uint32_t s0 = sel_bit(g, e, k), s1 = sel_bit(g, e + 1, k);
         const uint32_t s2 = sel_bit(g, e + 2, k), s3 = sel_bit(g, e + 3, k);
-        if (s0) take(e);
-        if (s1) take(e + 1);
-        if (s2) take(e + 2);
-        if (s3) take(e + 3);
+        const uint32_t i0 = (uint32_t)sender_index(g, direct, e, rb);
+        const uint32_t i1 = (uint32_t)sender_index(g, direct, e + 1, rb);
+        const uint32_t i2 = (uint32_t)sender_index(g, direct, e + 2, rb);
+        const uint32_t i3 = (uint32_t)sender_index(g, direct, e + 3, rb);
+        if (s0) take(i0);
+        if (s1) take(i1);
+        if (s2) take(i2);
+        if (s3) take(i3);
       }
       for (; e < re; ++e)
-        if (sel_bit(g, e, k)) take(e);
+        if (sel_bit(g, e, k)) take((uint32_t)sender_index(g, direct, e, rb));
       // source shares come after the transported photons of the bin
       for (int q = g.em_ptr[j]; q < g.em_ptr[j + 1]; ++q)
         if (g.em_k[q] == k && rp < g.rec_cap) g.rec[rp++] = lbits | kRecEmission | (uint32_t)q;
