@@ -257,35 +257,62 @@ __device__ __forceinline__ uint32_t sel_bit(const GridDev &g, int e, int k) {
   return (g.smask[4 * (int64_t)e + (k >> 5)] >> (k & 31)) & 1u;
 }
 
-// Thread (tile, bin, group) walks the kRecGroupLanes receivers of its
-// group in lane order; threads of neighbouring bins are neighbours, so their
-// mask reads fall in the same 16 bytes.  Record counts and offsets are kept
-// per (tile, bin, group), groups in lane order, so the records of a
+// Record counts and offsets are kept per (tile, bin, group of
+// kRecGroupLanes receivers), groups in lane order, so the records of a
 // (tile, bin) come out sorted by lane.
+//
+// The count pass takes 32 bins at a time: thread (tile, group, w) walks the
+// group's receivers and their in-edges, reading word w of each mask once,
+// and keeps the 32 senders-per-bin counts as bytes, four to a register (a
+// count is at most the degree, < 128).  Bits 4i..4i+3 of a mask word are
+// spread into the four bytes of counter i by one multiply: (x * 0x204081) &
+// 0x01010101 (the shifted copies 0, 7, 14, 21 do not overlap).
 __global__ void k_inlist_count(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
   const int K = g.k;
+  const int nw = (K + 31) / 32;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nt = (int64_t)g.ntiles * K * kRecGroups;
-  if (t >= nt) return;
-  // t = (tile * kRecGroups + group) * K + k
-  const int k = (int)(t % K);
-  const int64_t tg = t / K;
+  if (t >= (int64_t)g.ntiles * kRecGroups * nw) return;
+  const int w = (int)(t % nw);
+  const int64_t tg = t / nw;
   const int tile = (int)(tg / kRecGroups), grp = (int)(tg % kRecGroups);
-  int recs = 0;
+  int recs[32];
+#pragma unroll
+  for (int b = 0; b < 32; ++b) recs[b] = 0;
   for (int lane = grp * kRecGroupLanes; lane < (grp + 1) * kRecGroupLanes; ++lane) {
     const int j = tile * kTile + lane;
     if (j >= g.n) break;
-    uint32_t c = 0;
+    uint32_t cw[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) cw[i] = 0u;
     const int re = g.row_ptr[j + 1];
 #pragma unroll 4
-    for (int e = g.row_ptr[j]; e < re; ++e) c += sel_bit(g, e, k);
-    recs += c > (uint32_t)kWordEntries ? (int)c - kWordEntries : 0;
-    for (int q = g.em_ptr[j]; q < g.em_ptr[j + 1]; ++q) recs += g.em_k[q] == k ? 1 : 0;
+    for (int e = g.row_ptr[j]; e < re; ++e) {
+      const uint32_t m = g.smask[4 * (int64_t)e + w];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) cw[i] += (((m >> (4 * i)) & 15u) * 0x204081u) & 0x01010101u;
+    }
+#pragma unroll
+    for (int b = 0; b < 32; ++b) {
+      const int c = (int)((cw[b >> 2] >> (8 * (b & 3))) & 255u);
+      recs[b] += c > kWordEntries ? c - kWordEntries : 0;
+    }
+    for (int q = g.em_ptr[j]; q < g.em_ptr[j + 1]; ++q) {
+      const int kk = g.em_k[q] - 32 * w;
+#pragma unroll
+      for (int b = 0; b < 32; ++b) recs[b] += kk == b ? 1 : 0;
+    }
   }
-  g.rec_cnt[((int64_t)tile * K + k) * kRecGroups + grp] = recs;
+#pragma unroll
+  for (int b = 0; b < 32; ++b) {
+    const int k = 32 * w + b;
+    if (k < K) g.rec_cnt[((int64_t)tile * K + k) * kRecGroups + grp] = recs[b];
+  }
 }
 
+// The fill pass: thread (tile, bin, group) walks the group's receivers in
+// lane order; threads of neighbouring bins are neighbours, so their mask
+// reads fall in the same 16 bytes.
 __global__ void k_inlist_fill(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
   const int K = g.k;
@@ -1374,9 +1401,10 @@ hipError_t launch_edge_bins(const GridDev *dg, const GridDev &hg,
 
 hipError_t launch_inlist_count(const GridDev *dg, const GridDev &hg,
                                hipStream_t s) {
+  // one thread per (tile, group, 32-bin mask word)
   hipLaunchKernelGGL(k_inlist_count,
-                     dim3(blocks_for((int64_t)hg.ntiles * hg.k * kRecGroups, 256)), dim3(256),
-                     0, s, dg);
+                     dim3(blocks_for((int64_t)hg.ntiles * kRecGroups * ((hg.k + 31) / 32), 256)),
+                     dim3(256), 0, s, dg);
   return hipGetLastError();
 }
 
