@@ -107,12 +107,19 @@ struct sx_ctx {
   sx_schedule dflt{4, SX_ORDER_GRID, 1, 50};
   int32_t autotune = 0;
   uint32_t *done = nullptr;   // completion counter of the sweep launches
+  // pinned host staging of the routing rebuild: bin directions going in
+  // (offset 0), record and bin-list counts coming back (kPinCounts)
+  uint8_t *pin = nullptr;
   bool prof = false;
   std::vector<ProfEv> ev;     // pool
   size_t ev_used = 0;
 };
 
 namespace {
+
+constexpr size_t kPinCounts = 3 * 8 * 128;         // after 3 doubles per bin, up to 128 bins
+constexpr size_t kPinBytes = kPinCounts + 64;
+static_assert(SX_MAX_BINS_FP32 <= 128 && SX_MAX_BINS_FP64 <= 128, "pinned staging holds 128 bins");
 
 void drop_plans(sx_ctx *ctx, int slot);
 
@@ -446,9 +453,10 @@ int build_ct_tables(sx_ctx *ctx, Grid *g) {
   HIP_TRY(ctx, sx::launch_ebin_in(dg, h, st));
   HIP_TRY(ctx, sx::launch_kl_count(dg, h, st));
   HIP_TRY(ctx, sx::launch_scan(h.kl_cnt, h.kl_ptr, h.kl_part, (int32_t)h.n_edges, st));
-  int32_t total = 0;
-  HIP_TRY(ctx, hipMemcpyAsync(&total, h.kl_ptr + h.n_edges, 4, hipMemcpyDeviceToHost, st));
+  int32_t *pin_total = (int32_t *)(ctx->pin + kPinCounts + 4);
+  HIP_TRY(ctx, hipMemcpyAsync(pin_total, h.kl_ptr + h.n_edges, 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(ctx, hipStreamSynchronize(st));
+  const int32_t total = *pin_total;
   if (!h.kl || total > h.kl_cap) {
     if (h.kl) gfree(ctx, g, h.kl);
     uint8_t *d = nullptr;
@@ -474,7 +482,9 @@ int rebuild_routing(sx_ctx *ctx, Grid *g, const double *bins, bool rescale) {
   GridDev *dg = ctx->table + g->slot;
   hipStream_t st = ctx->stream;
   const int32_t nrow = h.ntiles * h.k * sx::kRecGroups;
-  HIP_TRY(ctx, hipMemcpyAsync(const_cast<double *>(h.bins), bins, sizeof(double) * 3 * h.k,
+  // the previous rebuild ended with a synchronisation: the staging is free
+  std::memcpy(ctx->pin, bins, sizeof(double) * 3 * h.k);
+  HIP_TRY(ctx, hipMemcpyAsync(const_cast<double *>(h.bins), ctx->pin, sizeof(double) * 3 * h.k,
                               hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, sx::launch_select(dg, h, st));
   HIP_TRY(ctx, sx::launch_em_bins(dg, h, g->n_em, st));
@@ -485,9 +495,14 @@ int rebuild_routing(sx_ctx *ctx, Grid *g, const double *bins, bool rescale) {
   HIP_TRY(ctx, sx::launch_clear_inw(h, st));
   HIP_TRY(ctx, sx::launch_inlist_count(dg, h, st));
   HIP_TRY(ctx, sx::launch_scan(h.rec_cnt, h.rec_ptr, h.scan_part, nrow, st));
-  int32_t n_rec = 0;
-  HIP_TRY(ctx, hipMemcpyAsync(&n_rec, h.rec_ptr + nrow, 4, hipMemcpyDeviceToHost, st));
+  // The fill keeps its records within the current pool, so it runs before
+  // the host has seen the count; if the new routing needs more, the pool
+  // grows and the fill runs again.
+  int32_t *pin_rec = (int32_t *)(ctx->pin + kPinCounts);
+  HIP_TRY(ctx, hipMemcpyAsync(pin_rec, h.rec_ptr + nrow, 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, sx::launch_inlist_fill(dg, h, st));
   HIP_TRY(ctx, hipStreamSynchronize(st));
+  const int32_t n_rec = *pin_rec;
   if (n_rec > h.rec_cap) {
     // Only the pool pointer and capacity change in the device table: the
     // per-sweep control there (parity, steps done) is the device's own and
@@ -511,10 +526,9 @@ int rebuild_routing(sx_ctx *ctx, Grid *g, const double *bins, bool rescale) {
     h.rec = d_rec;
     h.rec_cap = n_rec;
     HIP_TRY(ctx, put_pool());
+    HIP_TRY(ctx, sx::launch_inlist_fill(dg, h, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
   }
-  HIP_TRY(ctx, sx::launch_inlist_fill(dg, h, st));
-  HIP_TRY(ctx, hipStreamSynchronize(st));
   if (h.transport == SX_TRANSPORT_COMBINED) {
     // the in-edge bins need the full edge-bin table
     HIP_TRY(ctx, sx::launch_edge_bins(dg, h, st));
@@ -1248,6 +1262,14 @@ int sx_init(sx_ctx **out, const sx_ctx_opts *opts) {
     delete ctx;
     return SX_EDEVICE;
   }
+  if (hipHostMalloc((void **)&ctx->pin, kPinBytes, hipHostMallocDefault) != hipSuccess) {
+    ctx->pin = nullptr;
+    (void)hipFree(ctx->done);
+    (void)hipFree(ctx->table);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return SX_EDEVICE;
+  }
   for (int s = kMaxSlots - 1; s >= 0; --s) ctx->free_slots.push_back(s);
   *out = ctx;
   return SX_OK;
@@ -1266,6 +1288,7 @@ int sx_finalize(sx_ctx *ctx) {
   }
   (void)hipFree(ctx->done);
   (void)hipFree(ctx->table);
+  if (ctx->pin) (void)hipHostFree(ctx->pin);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return SX_OK;
