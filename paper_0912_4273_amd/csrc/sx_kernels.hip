@@ -106,9 +106,9 @@ __global__ void k_erev(const GridDev *__restrict__ gp) {
 // backwards), ties to the lower original neighbour id.  Rows are sorted by
 // original id, so "lower slot" is "lower id".  With dct_ref the reference
 // direction is the vertex's edge closest to the bin (largest cosine over
-// cos_min, ties to the lower id) in place of the bin.  One wave per
-// vertex: the vertex's edge directions are staged in LDS once and every
-// lane runs bins lane and lane + 64 over them in row order.
+// cos_min, ties to the lower id) in place of the bin.  A vertex's edge
+// directions are staged in LDS once and its bins run over them in row
+// order.
 struct Top3 {
   double c0 = -3.0, c1 = -3.0, c2 = -3.0;
   uint32_t s0 = kEmptySlot, s1 = kEmptySlot, s2 = kEmptySlot, cnt = 0;
@@ -149,63 +149,75 @@ __device__ __forceinline__ int ref_edge(const SX_L double *ed, int deg, double c
   return deg;
 }
 
+// The forward word of (vertex, bin k) over the vertex's n staged edge
+// directions, and the bits of its selected slots in the vertex's masks.
+__device__ __forceinline__ void select_bin(const GridDev &g, int64_t i, int k,
+                                           const SX_L double *ed, SX_L uint32_t *ms, int n) {
+  double u[3] = {g.bins[3 * k], g.bins[3 * k + 1], g.bins[3 * k + 2]};
+  if (g.dct_ref) n = ref_edge(ed, n, g.cos_min, u);
+  Top3 a;
+  for (int t = 0; t < n; ++t) {
+    const double d[3] = {ed[3 * t], ed[3 * t + 1], ed[3 * t + 2]};
+    a.add(cosine3(d, u), (uint32_t)t, g.cos_min);
+  }
+  const uint32_t word = a.word(g.mpb);
+  g.fwd[i * g.k + k] = word;
+  // each selected slot gets bit k in its out-edge's mask (an OR, so the
+  // order of the lanes does not matter)
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const uint32_t s = (word >> (7 * q)) & 127u;
+    if (s != (uint32_t)kEmptySlot) atomicOr((uint32_t *)&ms[4 * s + (k >> 5)], 1u << (k & 31));
+  }
+}
+
+// One wave per two vertices: bins 0..63 of the first vertex, then of the
+// second, then bins 64..95 of both at once (lanes 0..31 the first, 32..63
+// the second), so that with K = 84 few lanes idle.
 __global__ __launch_bounds__(256) void k_select(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
-  __shared__ double sd[4][3 * SX_MAX_DEGREE];
-  // selection masks of the wave's out-edges, 4 words per slot
-  __shared__ __attribute__((aligned(16))) uint32_t sm[4][4 * SX_MAX_DEGREE];
+  __shared__ double sd[8][3 * SX_MAX_DEGREE];
+  // selection masks of each vertex's out-edges, 4 words per slot
+  __shared__ __attribute__((aligned(16))) uint32_t sm[8][4 * SX_MAX_DEGREE];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + w;
-  const bool live = i < g.npad;   // the block's barriers are reached by all
+  const int64_t i0 = ((int64_t)blockIdx.x * 4 + w) * 2;   // npad is even
+  const bool live = i0 < g.npad;   // the block's barriers are reached by all
   const int K = g.k;
-  int rb = 0, deg = 0;
-  if (i < g.n) {
-    rb = g.row_ptr[i];
-    deg = g.row_ptr[i + 1] - rb;
-  }
-  SX_L double *ed = (SX_L double *)sd[w];
-  SX_L uint32_t *ms = (SX_L uint32_t *)sm[w];
-  for (int q = lane; q < 3 * deg; q += 64) ed[q] = g.edir[3 * (int64_t)rb + q];
-  for (int q = lane; q < 4 * deg; q += 64) ms[q] = 0u;
-  __syncthreads();
-  const int k0 = lane, k1 = lane + 64;
-  if (live) {
-    double u0[3] = {0.0, 0.0, 0.0}, u1[3] = {0.0, 0.0, 0.0};
-    if (k0 < K) { u0[0] = g.bins[3 * k0]; u0[1] = g.bins[3 * k0 + 1]; u0[2] = g.bins[3 * k0 + 2]; }
-    if (k1 < K) { u1[0] = g.bins[3 * k1]; u1[1] = g.bins[3 * k1 + 1]; u1[2] = g.bins[3 * k1 + 2]; }
-    // edges each bin considers (none for a lane past the last bin, so that
-    // with K <= 64 the second bin's work is skipped by the whole wave)
-    int n0 = k0 < K ? deg : 0, n1 = k1 < K ? deg : 0;
-    if (g.dct_ref) {
-      n0 = k0 < K ? ref_edge(ed, deg, g.cos_min, u0) : 0;
-      n1 = k1 < K ? ref_edge(ed, deg, g.cos_min, u1) : 0;
-    }
-    Top3 a, b;
-    for (int t = 0; t < deg; ++t) {
-      const double d[3] = {ed[3 * t], ed[3 * t + 1], ed[3 * t + 2]};
-      if (t < n0) a.add(cosine3(d, u0), (uint32_t)t, g.cos_min);
-      if (t < n1) b.add(cosine3(d, u1), (uint32_t)t, g.cos_min);
-    }
-    const uint32_t w0 = a.word(g.mpb), w1 = b.word(g.mpb);
-    if (k0 < K) g.fwd[i * K + k0] = w0;
-    if (k1 < K) g.fwd[i * K + k1] = w1;
-    // each selected slot of (i, k) gets bit k in its out-edge's mask (an OR,
-    // so the order of the lanes does not matter)
-    auto mark = [&](uint32_t word, int k) {
+  int rb[2], deg[2];
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const uint32_t s = (word >> (7 * q)) & 127u;
-        if (s != (uint32_t)kEmptySlot) atomicOr((uint32_t *)&ms[4 * s + (k >> 5)], 1u << (k & 31));
-      }
-    };
-    if (k0 < K) mark(w0, k0);
-    if (k1 < K) mark(w1, k1);
+  for (int v = 0; v < 2; ++v) {
+    rb[v] = 0;
+    deg[v] = 0;
+    if (i0 + v < g.n) {
+      rb[v] = g.row_ptr[i0 + v];
+      deg[v] = g.row_ptr[i0 + v + 1] - rb[v];
+    }
+    SX_L double *ed = (SX_L double *)sd[2 * w + v];
+    SX_L uint32_t *ms = (SX_L uint32_t *)sm[2 * w + v];
+    for (int q = lane; q < 3 * deg[v]; q += 64) ed[q] = g.edir[3 * (int64_t)rb[v] + q];
+    for (int q = lane; q < 4 * deg[v]; q += 64) ms[q] = 0u;
+  }
+  __syncthreads();
+  if (live) {
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+      if (lane < K)
+        select_bin(g, i0 + v, lane, (const SX_L double *)sd[2 * w + v],
+                   (SX_L uint32_t *)sm[2 * w + v], deg[v]);
+    const int v = lane >> 5, k = 64 + (lane & 31);
+    if (k < K)
+      select_bin(g, i0 + v, k, (const SX_L double *)sd[2 * w + v], (SX_L uint32_t *)sm[2 * w + v],
+                 v == 0 ? deg[0] : deg[1]);
   }
   __syncthreads();
   // out-edge (i, t) is the receiver's in-edge erev[rb + t]
   typedef uint32_t U4 __attribute__((ext_vector_type(4)));
-  for (int t = lane; t < deg; t += 64)
-    *(U4 *)(g.smask + 4 * (int64_t)g.erev[rb + t]) = *(const SX_L U4 *)(ms + 4 * t);
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    const SX_L uint32_t *ms = (const SX_L uint32_t *)sm[2 * w + v];
+    for (int t = lane; t < deg[v]; t += 64)
+      *(U4 *)(g.smask + 4 * (int64_t)g.erev[rb[v] + t]) = *(const SX_L U4 *)(ms + 4 * t);
+  }
 }
 
 // Bin of each directed edge: the bin whose direction is closest to the edge
@@ -1386,7 +1398,8 @@ hipError_t launch_erev(const GridDev *dg, const GridDev &hg, hipStream_t s) {
 }
 
 hipError_t launch_select(const GridDev *dg, const GridDev &hg, hipStream_t s) {
-  hipLaunchKernelGGL(k_select, dim3(blocks_for((int64_t)hg.npad * 64, 256)),
+  // one wave per two vertices, four waves per workgroup
+  hipLaunchKernelGGL(k_select, dim3(blocks_for((int64_t)hg.npad * 32, 256)),
                      dim3(256), 0, s, dg);
   return hipGetLastError();
 }
