@@ -492,7 +492,9 @@ int rebuild_routing(sx_ctx *ctx, Grid *g, const double *bins, bool rescale) {
   // m words; with rescale the photons in flight are re-split first
   if (rescale) HIP_TRY(ctx, sx::launch_mbits_rescale(dg, h, st));
   else HIP_TRY(ctx, sx::launch_mbits(dg, h, st));
-  HIP_TRY(ctx, sx::launch_clear_inw(h, st));
+  // no clearing of the in-words: the fill rewrites the word of every bin
+  // below K, and the padding bins of the last block keep their empty words
+  // from the upload
   HIP_TRY(ctx, sx::launch_inlist_count(dg, h, st));
   HIP_TRY(ctx, sx::launch_scan(h.rec_cnt, h.rec_ptr, h.scan_part, nrow, st));
   // The fill keeps its records within the current pool, so it runs before
