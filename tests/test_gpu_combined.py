@@ -201,15 +201,17 @@ def test_checkpoint_restore_edges(sxctx):
         sxctx.free(b)
 
 
-@pytest.mark.parametrize("prec", [G.SX_FP64, G.SX_FP32_TRANSPORT])
-def test_combined_rotated(sxctx, prec):
+@pytest.mark.parametrize("prec,k", [(G.SX_FP64, 42), (G.SX_FP32_TRANSPORT, 42),
+                                    (G.SX_FP32_TRANSPORT, 96)])
+def test_combined_rotated(sxctx, prec, k):
     """Combined transport with the bins rotated between steps (as the
     paper does for its direction-conserving part): the bin selection, the
     edge bins and the per-edge lists are rebuilt on the device.  fp64: whole
-    solve; fp32: one step from the GPU's state after the rotations."""
-    w = _work(2000, seed=75, prec=prec, tau_switch=1.0)
+    solve; fp32: one step from the GPU's state after the rotations.  96
+    bins: the selection's pass over bins 64..95 and mask bits past 64."""
+    w = _work(2000, seed=75, k=k, prec=prec, tau_switch=1.0)
     Rs = G.random_rotations(3, seed=11)
-    print(f"[case] combined rotated prec={prec}", flush=True)
+    print(f"[case] combined rotated prec={prec} k={k}", flush=True)
     gid = sxctx.upload(w)
     o = Oracle(w)
     try:
@@ -238,8 +240,8 @@ def test_combined_rotated(sxctx, prec):
         sxctx.free(gid)
         o.close()
     assert es["layout"].any() and (es["layout"] == 0).any()
-    assert_state_close(st, ref, prec, unit, f"combined rotated prec {prec}")
-    assert_edges_close(es, ref_e, prec, unit, f"combined rotated prec {prec}")
+    assert_state_close(st, ref, prec, unit, f"combined rotated prec {prec} k {k}")
+    assert_edges_close(es, ref_e, prec, unit, f"combined rotated prec {prec} k {k}")
 
 
 def test_combined_limits(sxctx):

@@ -17,13 +17,18 @@ def _conserved(t, tol):
     assert abs(r) <= tol * t["emitted"], r
 
 
-@pytest.mark.parametrize("prec", [G.SX_FP64, G.SX_FP32_TRANSPORT])
-def test_rotations_match_oracle(sxctx, prec):
-    w = G.small_random(1500, seed=41, n_bins=42, box=3e21, rate=1e48, n_src=3,
+@pytest.mark.parametrize("prec,k", [(G.SX_FP64, 42), (G.SX_FP32_TRANSPORT, 42),
+                                    (G.SX_FP64, 96), (G.SX_FP32_TRANSPORT, 21)])
+def test_rotations_match_oracle(sxctx, prec, k):
+    """Tables bit for bit after each rotation and the state at the end.
+    96 bins take the selection's pass over bins 64..95; 21 bins leave three
+    padding bins in the last fp32 block, whose in-words keep their upload
+    value through the rebuilds."""
+    w = G.small_random(1500, seed=41, n_bins=k, box=3e21, rate=1e48, n_src=3,
                        dt=3e13, precision=prec)
     Rs = G.random_rotations(3, seed=5)
     plan = [(6, Rs[0]), (9, Rs[1]), (5, Rs[2]), (7, None)]
-    print(f"[case] rotations prec={prec}", flush=True)
+    print(f"[case] rotations prec={prec} k={k}", flush=True)
     gid = sxctx.upload(w)
     ora = Oracle(w)
     try:
@@ -40,7 +45,7 @@ def test_rotations_match_oracle(sxctx, prec):
             got = sxctx.state(gid, photons=True)
             _conserved(got["tallies"], 1e-9 if prec == G.SX_FP64 else 1e-4)
         unit = sxctx.info(gid)["photon_unit"]
-        assert_state_close(got, ora.state(), prec, unit, f"rotations prec {prec}")
+        assert_state_close(got, ora.state(), prec, unit, f"rotations prec {prec} k {k}")
     finally:
         sxctx.free(gid)
         ora.close()
