@@ -232,13 +232,24 @@ __global__ __launch_bounds__(256) void k_edge_bins(const GridDev *__restrict__ g
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= g.n_edges) return;
   const double ed[3] = {g.edir[3 * e], g.edir[3 * e + 1], g.edir[3 * e + 2]};
-  int best = 0;
-  double cb = cosine3(ed, &sb[0]);
-#pragma unroll 4
-  for (int k = 1; k < K; ++k) {
-    const double c = cosine3(ed, &sb[3 * k]);
-    if (c > cb) { cb = c; best = k; }
+  // two independent chains, even and odd bins, each keeping its first
+  // largest cosine; the larger wins, a tie goes to the lower bin
+  int ba = 0, bo = -1;
+  double ca = cosine3(ed, &sb[0]), co = 0.0;
+  if (K > 1) {
+    co = cosine3(ed, &sb[3]);
+    bo = 1;
   }
+#pragma unroll 2
+  for (int k = 2; k < K; k += 2) {
+    const double c = cosine3(ed, &sb[3 * k]);
+    if (c > ca) { ca = c; ba = k; }
+    if (k + 1 < K) {
+      const double d = cosine3(ed, &sb[3 * (k + 1)]);
+      if (d > co) { co = d; bo = k + 1; }
+    }
+  }
+  const int best = (bo >= 0 && (co > ca || (co == ca && bo < ba))) ? bo : ba;
   g.ebin[e] = (uint8_t)best;
 }
 
@@ -403,19 +414,49 @@ __global__ void k_kl_count(const GridDev *__restrict__ gp) {
   g.kl_cnt[e] = __popc(m[0]) + __popc(m[1]) + __popc(m[2]) + __popc(m[3]);
 }
 
-__global__ void k_kl_fill(const GridDev *__restrict__ gp) {
+// A workgroup's 256 lists are contiguous in the pool: they are built in
+// LDS and written out as aligned words (the partial words at either end,
+// shared with the neighbouring workgroups, byte by byte).  A range longer
+// than the LDS buffer is written directly.
+constexpr int kKlStage = 16384;
+
+__global__ __launch_bounds__(256) void k_kl_fill(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= g.n_edges) return;
-  const uint32_t *m = g.smask + 4 * e;
-  int64_t p = g.kl_ptr[e];
-  for (int q = 0; q < 4; ++q) {
-    uint32_t w = m[q];
-    while (w) {
-      const int bit = __ffs(w) - 1;
-      g.kl[p++] = (uint8_t)(32 * q + bit);
-      w &= w - 1u;
+  __shared__ __attribute__((aligned(16))) uint8_t st[kKlStage];
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t e = e0 + threadIdx.x;
+  const int64_t e1 = e0 + blockDim.x < g.n_edges ? e0 + blockDim.x : g.n_edges;
+  const int64_t base = g.kl_ptr[e0], end = g.kl_ptr[e1];
+  const bool staged = end - base <= kKlStage;   // the same for the whole block
+  if (e < g.n_edges) {
+    const uint32_t *m = g.smask + 4 * e;
+    int64_t p = g.kl_ptr[e];
+    for (int q = 0; q < 4; ++q) {
+      uint32_t w = m[q];
+      while (w) {
+        const int bit = __ffs(w) - 1;
+        const uint8_t k = (uint8_t)(32 * q + bit);
+        if (staged) st[p - base] = k;
+        else g.kl[p] = k;
+        ++p;
+        w &= w - 1u;
+      }
     }
+  }
+  if (!staged) return;
+  __syncthreads();
+  const int64_t a = (base + 3) & ~(int64_t)3, b = end & ~(int64_t)3;
+  if (a < b) {
+    uint32_t *dst = (uint32_t *)(g.kl + a);
+    for (int64_t q = threadIdx.x; q < (b - a) / 4; q += blockDim.x) {
+      const int64_t o = a - base + 4 * q;
+      dst[q] = (uint32_t)st[o] | ((uint32_t)st[o + 1] << 8) | ((uint32_t)st[o + 2] << 16) |
+               ((uint32_t)st[o + 3] << 24);
+    }
+    for (int64_t q = base + threadIdx.x; q < a; q += blockDim.x) g.kl[q] = st[q - base];
+    for (int64_t q = b + threadIdx.x; q < end; q += blockDim.x) g.kl[q] = st[q - base];
+  } else {
+    for (int64_t q = base + threadIdx.x; q < end; q += blockDim.x) g.kl[q] = st[q - base];
   }
 }
 
