@@ -185,7 +185,10 @@ typedef struct sx_state_in {
     const sx_tally *tally;
 } sx_state_in;
 
-/* Create a context on opts->device (NULL opts = device 0, defaults).
+/* Create a context on opts->device (NULL opts = device 0, defaults).  The
+ * context holds, besides the grids, a table of grid slots and a completion
+ * counter in device memory and a 3 KiB pinned host buffer (the staging of
+ * the routing rebuilds); sx_finalize frees them.
  * Errors: SX_EINVAL (bad opts), SX_EDEVICE (no such device / HIP failure).*/
 int sx_init(sx_ctx **out, const sx_ctx_opts *opts);
 
