@@ -111,6 +111,21 @@ def test_combined_largest_bin_count(sxctx, prec):
     _one_step_after(sxctx, w, prec, 50, f"96 bins prec {prec}")
 
 
+@pytest.mark.parametrize("prec", [G.SX_FP64, G.SX_FP32_TRANSPORT])
+def test_bin_lists_longer_than_the_lds_stage(sxctx, prec):
+    """cos_min -0.99 on a chain: every bin of a vertex selects both
+    neighbours, so each in-edge's bin list holds all 96 bins, and the lists
+    of one workgroup (256 x 96 bytes) exceed the LDS stage of the list fill,
+    which then writes them directly.  Mixed modes, one step from a shared
+    state."""
+    kpc = G.KPC_CM
+    w = G.chain_graph(600, 0.02 * kpc, 1e-2, 1e62, bins=G.random_bins(96, 7))
+    w = G.with_(w, cos_min=-0.99, transport=CT, tau_switch=1.0, dt=3e13,
+                src_rate=np.array([1e48]), precision=prec)
+    print(f"[case] long bin lists prec={prec}", flush=True)
+    _one_step_after(sxctx, w, prec, 40, f"long bin lists prec {prec}")
+
+
 def _one_step_after(sxctx, w, prec, steps, label):
     gid = sxctx.upload(w)
     try:
