@@ -1463,7 +1463,7 @@ int plan_build(sx_ctx *ctx, Plan *p, const std::vector<Grid *> &gs) {
     int64_t plane_bytes = 0;   // both photon planes of every grid in the launch
     for (Grid *g : grp)
       plane_bytes += 2 * (int64_t)sx::kBlockBytes * g->hg.kb * (g->hg.npad + sx::kTile);
-    l.nt = tr == 0 && plane_bytes <= sx::kLlcBytes;
+    l.nt = plane_bytes <= sx::kLlcBytes;
     const bool any_direct = std::any_of(grp.begin(), grp.end(),
                                         [](Grid *g) { return g->n_direct > 0; });
     const bool reorder = p->sched.order == SX_ORDER_DIRECT_FIRST && any_direct;

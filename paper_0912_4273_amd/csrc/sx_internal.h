@@ -41,9 +41,9 @@ constexpr int kBlockBytes = 16;
 // Record counts and offsets per (tile, bin, group of kRecGroupLanes lanes).
 constexpr int kRecGroups = 8;
 // The last-level cache (Infinity Cache) of the GPU.  When the photon planes
-// of all grids in one direction-conserving launch fit in it, the sweep loads
-// its in-words non-temporal, so that the planes stay cached from one sweep to
-// the next; on larger launches the hint costs time and is not used.
+// of all grids in one sweep launch fit in it, the sweep loads its in-words
+// non-temporal, so that the planes stay cached from one sweep to the next;
+// on larger launches the hint costs time and is not used.
 constexpr int64_t kLlcBytes = 256ll << 20;
 constexpr int kRecGroupLanes = kTile / kRecGroups;
 constexpr int kRecIdxBits = 23;

@@ -1155,7 +1155,7 @@ __device__ __forceinline__ P div_m(P v, uint32_t m) {
   }
 }
 
-template <typename P>
+template <typename P, bool NT>
 __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int tile,
                                               int lane, SX_L P *veb,
                                               volatile SX_L P *hl, volatile SX_L P *xc) {
@@ -1218,7 +1218,7 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
       if (idx < hlen && lin[hvid[hp + idx]] != 0) edges = true;
     }
     if (__ballot(edges) == 0) {
-      sweep_tile<P, false>(G, tile, lane, hl, xc);
+      sweep_tile<P, false, false, NT>(G, tile, lane, hl, xc);
       if (valid) lout[j] = 0;
       return;
     }
@@ -1339,9 +1339,9 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
     return;
   }
   if (direct)
-    sweep_tile<P, true, true>(G, tile, lane, hl, xc, ci);
+    sweep_tile<P, true, true, NT>(G, tile, lane, hl, xc, ci);
   else
-    sweep_tile<P, false, true>(G, tile, lane, hl, xc, ci);
+    sweep_tile<P, false, true, NT>(G, tile, lane, hl, xc, ci);
   if (valid) lout[j] = bal ? 1 : 0;
 }
 
@@ -1361,7 +1361,7 @@ struct CtLds {
 
 // One combined-transport step over a tile list: one tile per workgroup of
 // one wave, the same tile lists, XCD numbering and completion as k_sweep.
-template <typename P>
+template <typename P, bool NT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_ct(
     GridDev *__restrict__ grids, const int2 *__restrict__ tile_map,
     int32_t n_tiles, const int32_t *__restrict__ adv, int32_t n_adv,
@@ -1381,7 +1381,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
     const GridDev *__restrict__ G = grids + gi;
     if (G->remaining > 0)
-      sweep_tile_ct<P>(G, tile, lane, (SX_L P *)lds.ve, (volatile SX_L P *)lds.h,
+      sweep_tile_ct<P, NT>(G, tile, lane, (SX_L P *)lds.ve, (volatile SX_L P *)lds.h,
                        (volatile SX_L P *)lds.x);
   }
   __syncthreads();
@@ -1578,7 +1578,9 @@ static hipError_t sweep_shape(const SweepLaunch &l, const void **fn, dim3 *grid,
                               dim3 *block) {
   if (l.transport != 0) {
     if (l.n_tiles <= 0 || !l.done) return hipErrorInvalidValue;
-    *fn = l.precision == 0 ? (const void *)k_sweep_ct<double> : (const void *)k_sweep_ct<float>;
+    *fn = l.precision == 0
+              ? (l.nt ? (const void *)k_sweep_ct<double, true> : (const void *)k_sweep_ct<double, false>)
+              : (l.nt ? (const void *)k_sweep_ct<float, true> : (const void *)k_sweep_ct<float, false>);
     *grid = dim3(((unsigned)l.n_tiles + 7u) & ~7u);
     *block = dim3(64u);
     return hipSuccess;
