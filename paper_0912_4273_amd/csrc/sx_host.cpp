@@ -923,6 +923,9 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   h.kb = (int32_t)S.kb;
   h.n_sub = P->n_sub;
   h.mpb = P->mpb;
+  h.max_deg = 1;
+  for (int64_t v = 0; v < n; ++v)
+    h.max_deg = std::max(h.max_deg, g->row_ptr_h[(size_t)v + 1] - g->row_ptr_h[(size_t)v]);
   h.precision = P->precision;
   h.parity = 0;
   h.remaining = 0;

@@ -63,6 +63,7 @@ struct GridDev {
   int32_t kb;         // blocks per vertex, ceil(k / bb)
   int32_t n_sub;      // chemistry substeps
   int32_t mpb;        // max neighbours per bin
+  int32_t max_deg;    // largest degree of the grid (sizes the selection's LDS)
   int32_t precision;  // 0 fp64, 1 fp32 transport
   // mutable per-sweep control, advanced by the last workgroup of each sweep launch
   int32_t parity;     // O buffer holding the current field

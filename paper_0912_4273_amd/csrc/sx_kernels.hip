@@ -174,11 +174,19 @@ __device__ __forceinline__ void select_bin(const GridDev &g, int64_t i, int k,
 // One wave per two vertices: bins 0..63 of the first vertex, then of the
 // second, then bins 64..95 of both at once (lanes 0..31 the first, 32..63
 // the second), so that with K = 84 few lanes idle.
+// LDS of k_select per workgroup (8 vertices), sized by the grid's largest
+// degree: the edge directions, then the selection masks
+__host__ __device__ constexpr int64_t select_lds_bytes(int max_deg) {
+  return 8 * (3 * 8 + 4 * 4) * (int64_t)max_deg;
+}
+
 __global__ __launch_bounds__(256) void k_select(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
-  __shared__ double sd[8][3 * SX_MAX_DEGREE];
-  // selection masks of each vertex's out-edges, 4 words per slot
-  __shared__ __attribute__((aligned(16))) uint32_t sm[8][4 * SX_MAX_DEGREE];
+  extern __shared__ __attribute__((aligned(16))) double sel_lds[];
+  const int md = g.max_deg;
+  // vertex slot s: edge directions at sd(s), masks (4 words per out-edge) at sm(s)
+  auto sd = [&](int s) { return sel_lds + (int64_t)s * 3 * md; };
+  auto sm = [&](int s) { return (uint32_t *)(sel_lds + (int64_t)8 * 3 * md) + (int64_t)s * 4 * md; };
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t i0 = ((int64_t)blockIdx.x * 4 + w) * 2;   // npad is even
   const bool live = i0 < g.npad;   // the block's barriers are reached by all
@@ -192,8 +200,8 @@ __global__ __launch_bounds__(256) void k_select(const GridDev *__restrict__ gp) 
       rb[v] = g.row_ptr[i0 + v];
       deg[v] = g.row_ptr[i0 + v + 1] - rb[v];
     }
-    SX_L double *ed = (SX_L double *)sd[2 * w + v];
-    SX_L uint32_t *ms = (SX_L uint32_t *)sm[2 * w + v];
+    SX_L double *ed = (SX_L double *)sd(2 * w + v);
+    SX_L uint32_t *ms = (SX_L uint32_t *)sm(2 * w + v);
     for (int q = lane; q < 3 * deg[v]; q += 64) ed[q] = g.edir[3 * (int64_t)rb[v] + q];
     for (int q = lane; q < 4 * deg[v]; q += 64) ms[q] = 0u;
   }
@@ -202,11 +210,11 @@ __global__ __launch_bounds__(256) void k_select(const GridDev *__restrict__ gp) 
 #pragma unroll
     for (int v = 0; v < 2; ++v)
       if (lane < K)
-        select_bin(g, i0 + v, lane, (const SX_L double *)sd[2 * w + v],
-                   (SX_L uint32_t *)sm[2 * w + v], deg[v]);
+        select_bin(g, i0 + v, lane, (const SX_L double *)sd(2 * w + v),
+                   (SX_L uint32_t *)sm(2 * w + v), deg[v]);
     const int v = lane >> 5, k = 64 + (lane & 31);
     if (k < K)
-      select_bin(g, i0 + v, k, (const SX_L double *)sd[2 * w + v], (SX_L uint32_t *)sm[2 * w + v],
+      select_bin(g, i0 + v, k, (const SX_L double *)sd(2 * w + v), (SX_L uint32_t *)sm(2 * w + v),
                  v == 0 ? deg[0] : deg[1]);
   }
   __syncthreads();
@@ -214,7 +222,7 @@ __global__ __launch_bounds__(256) void k_select(const GridDev *__restrict__ gp) 
   typedef uint32_t U4 __attribute__((ext_vector_type(4)));
 #pragma unroll
   for (int v = 0; v < 2; ++v) {
-    const SX_L uint32_t *ms = (const SX_L uint32_t *)sm[2 * w + v];
+    const SX_L uint32_t *ms = (const SX_L uint32_t *)sm(2 * w + v);
     for (int t = lane; t < deg[v]; t += 64)
       *(U4 *)(g.smask + 4 * (int64_t)g.erev[rb[v] + t]) = *(const SX_L U4 *)(ms + 4 * t);
   }
@@ -1441,7 +1449,7 @@ hipError_t launch_erev(const GridDev *dg, const GridDev &hg, hipStream_t s) {
 hipError_t launch_select(const GridDev *dg, const GridDev &hg, hipStream_t s) {
   // one wave per two vertices, four waves per workgroup
   hipLaunchKernelGGL(k_select, dim3(blocks_for((int64_t)hg.npad * 32, 256)),
-                     dim3(256), 0, s, dg);
+                     dim3(256), (unsigned)select_lds_bytes(hg.max_deg), s, dg);
   return hipGetLastError();
 }
 
