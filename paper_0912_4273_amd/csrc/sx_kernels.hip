@@ -180,7 +180,10 @@ __host__ __device__ constexpr int64_t select_lds_bytes(int max_deg) {
   return 8 * (3 * 8 + 4 * 4) * (int64_t)max_deg;
 }
 
-__global__ __launch_bounds__(256) void k_select(const GridDev *__restrict__ gp) {
+// 8 waves per SIMD: the compiler then fits the kernel in 48 VGPRs without
+// spilling (88 by default, 5 waves), and the FP64 chains hide each other
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_select(
+    const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
   extern __shared__ __attribute__((aligned(16))) double sel_lds[];
   const int md = g.max_deg;
