@@ -533,9 +533,24 @@ __global__ __launch_bounds__(64 * 6) void k_mbits(GridDev *__restrict__ gp) {
   const int K = g.k;
   const int k0 = 16 * q;
   uint32_t v[16];
+  if ((K & 3) == 0) {
+    // the row segment is 16-byte aligned: four 16-byte loads, each either
+    // wholly below K or skipped
+    typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+    const U4 *f4 = (const U4 *)(g.fwd + (int64_t)j * K + k0);
 #pragma unroll
-  for (int b = 0; b < 16; ++b)
-    v[b] = (j < g.n && k0 + b < K) ? g.fwd[(int64_t)j * K + k0 + b] : 0u;
+    for (int c = 0; c < 4; ++c) {
+      const U4 x = (j < g.n && k0 + 4 * c < K) ? f4[c] : U4{0u, 0u, 0u, 0u};
+      v[4 * c] = x.x;
+      v[4 * c + 1] = x.y;
+      v[4 * c + 2] = x.z;
+      v[4 * c + 3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+      v[b] = (j < g.n && k0 + b < K) ? g.fwd[(int64_t)j * K + k0 + b] : 0u;
+  }
   uint32_t mword = 0;
 #pragma unroll
   for (int b = 0; b < 16; ++b) mword |= ((v[b] >> 21) & 3u) << (2 * b);
