@@ -111,6 +111,20 @@ static int select_slots(const ora_grid *g, int64_t i, const double *u,
     return cnt;
 }
 
+/* The bin whose direction is closest to the unit direction d (largest
+ * cosine, ties to the lower bin): where photons of a known direction of
+ * travel are filed (Sect. 2.2.4 for photons arriving along an edge; a beam's
+ * photons travel along the beam). */
+static int32_t nearest_bin(const ora_grid *g, const double *d) {
+    int32_t best = 0;
+    double cb = cosine(d, &g->bins[0]);
+    for (int32_t k = 1; k < g->K; k++) {
+        double c = cosine(d, &g->bins[3 * k]);
+        if (c > cb) { cb = c; best = k; }
+    }
+    return best;
+}
+
 /* ---------------------------------------------------------------------- */
 /* Chemistry of one vertex over one transport step (Sect. 4.5).
  *
@@ -233,15 +247,7 @@ static void build_routing(ora_grid *g) {
     /* Bin of each directed edge: photons sent along an edge are filed in
      * the solid angle whose direction is closest to the edge (Sect. 2.2.4);
      * ties go to the lower bin. */
-    for (int64_t e = 0; e < E; e++) {
-        int32_t best = 0;
-        double cb = cosine(&g->edir[3 * e], &g->bins[0]);
-        for (int32_t k = 1; k < K; k++) {
-            double c = cosine(&g->edir[3 * e], &g->bins[3 * k]);
-            if (c > cb) { cb = c; best = k; }
-        }
-        g->ebin[e] = best;
-    }
+    for (int64_t e = 0; e < E; e++) g->ebin[e] = nearest_bin(g, &g->edir[3 * e]);
 }
 
 ora_grid *ora_create(int64_t n, const double *pos, const int64_t *nbr_ptr,
@@ -408,7 +414,10 @@ static void sweep(ora_grid *g) {
      * of the edge they came along (Sect. 2.2.4).  The source itself does
      * not absorb them.  A source with a direction emits a beam instead: the
      * photons are split over the neighbours selected for that direction by
-     * the rule used for bins (used for a plane-parallel front). */
+     * the rule used for bins (used for a plane-parallel front), and every
+     * receiver files them in the bin closest to the beam's direction, the
+     * direction they travel in (reading: the bin of the edge would turn a
+     * collimated beam into a fan of edge directions). */
     for (int32_t s = 0; s < g->n_src; s++) {
         int64_t v = g->src_v[s];
         double E = g->src_rate[s] * g->dt;
@@ -425,9 +434,10 @@ static void sweep(ora_grid *g) {
             int c = select_slots(g, v, d, slots);
             if (c == 0) { g->escaped += E; continue; }
             double share = E / (double)c;
+            int32_t kb = nearest_bin(g, d);
             for (int t = 0; t < c; t++) {
                 int64_t e = b + slots[t];
-                g->I[(int64_t)g->nbr[e] * K + g->ebin[e]] += share;
+                g->I[(int64_t)g->nbr[e] * K + kb] += share;
             }
         }
     }
@@ -570,10 +580,8 @@ static void sweep_combined(ora_grid *g) {
             int c = select_slots(g, v, d, slots);
             if (c == 0) { g->escaped += En; continue; }
             double share = En / (double)c;
-            for (int t = 0; t < c; t++) {
-                int64_t e = b + slots[t];
-                deliver(g, e, g->ebin[e], share);
-            }
+            int32_t kb = nearest_bin(g, d);
+            for (int t = 0; t < c; t++) deliver(g, b + slots[t], kb, share);
         }
     }
     diffuse_send(g);
@@ -739,15 +747,28 @@ void ora_set_state(ora_grid *g, const double *y, const double *photons,
  * preferential directions (Sect. 2.2.3): the bins become R u_k of the bins
  * given at creation (R row-major, applied as ((R_r0 u_x + R_r1 u_y) +
  * R_r2 u_z) with no fused multiply-add) and the routing is recomputed.
- * Reading of what happens to photons in flight (the paper does not say):
- * the photons a vertex holds in a bin, O m, keep their bin and are split over
- * the neighbours selected for the bin's new direction (unchanged where the
- * number selected is the same); where none is selected they leave the
- * domain. */
+ * What happens to the photons in flight is not spelled out; the paper notes
+ * that every rotation brings a small amount of numerical diffusion, which
+ * grows with the number of rotations a photon undergoes and shrinks with
+ * more bins (Sect. 5.2).  Reading: photons keep their direction as closely
+ * as the rotated bins allow.  The photons a vertex holds in old bin k, O m,
+ * move to the rotated bin closest in direction to old bin k (largest cosine,
+ * ties to the lower bin); what several old bins bring to one new bin adds up
+ * in ascending old bin; it is split equally over the neighbours selected for
+ * the new bin, and leaves the domain where none is selected.  A new bin fed
+ * by exactly one old bin with the same number of selected neighbours keeps
+ * that bin's share as it is. */
 int ora_rotate(ora_grid *g, const double *R) {
     int64_t n = g->n, K = g->K;
     int32_t *m_old = (int32_t *)xcalloc(n * K, sizeof(int32_t));
+    double *O_old = (double *)xcalloc(n * K, sizeof(double));
+    double *b_old = (double *)xcalloc(3 * K, sizeof(double));
+    int32_t *to = (int32_t *)xcalloc(K, sizeof(int32_t));
+    int32_t *feeds = (int32_t *)xcalloc(K, sizeof(int32_t));
+    int32_t *from = (int32_t *)xcalloc(K, sizeof(int32_t));
     memcpy(m_old, g->m, (size_t)(n * K) * sizeof(int32_t));
+    memcpy(O_old, g->O, (size_t)(n * K) * sizeof(double));
+    memcpy(b_old, g->bins, (size_t)(3 * K) * sizeof(double));
     for (int64_t k = 0; k < K; k++) {
         const double *u = &g->bins0[3 * k];
         for (int r = 0; r < 3; r++) {
@@ -758,18 +779,32 @@ int ora_rotate(ora_grid *g, const double *R) {
         }
     }
     build_routing(g);
-    for (int64_t i = 0; i < n * K; i++) {
-        if (g->m[i] == m_old[i]) continue;   /* same share per neighbour */
-        double held = g->O[i] * (double)m_old[i];
-        if (g->m[i] == 0) {
-            g->escaped += held;
-            g->in_flight -= held;
-            g->O[i] = 0.0;
-        } else {
-            g->O[i] = held / (double)g->m[i];
+    /* old bin k -> the new bin nearest its direction */
+    for (int64_t k = 0; k < K; k++) {
+        to[k] = nearest_bin(g, &b_old[3 * k]);
+        feeds[to[k]] += 1;
+        from[to[k]] = (int32_t)k;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        for (int64_t kn = 0; kn < K; kn++) {
+            int32_t mn = g->m[i * K + kn];
+            if (feeds[kn] == 1 && mn == m_old[i * K + from[kn]] && mn > 0) {
+                g->O[i * K + kn] = O_old[i * K + from[kn]];
+                continue;
+            }
+            double held = 0.0;
+            for (int64_t k = 0; k < K; k++)
+                if (to[k] == kn) held += O_old[i * K + k] * (double)m_old[i * K + k];
+            if (mn == 0) {
+                g->escaped += held;
+                g->in_flight -= held;
+                g->O[i * K + kn] = 0.0;
+            } else {
+                g->O[i * K + kn] = held / (double)mn;
+            }
         }
     }
-    free(m_old);
+    free(m_old); free(O_old); free(b_old); free(to); free(feeds); free(from);
     return 0;
 }
 

@@ -57,14 +57,16 @@ void ora_get_state(const ora_grid *g, double *y, double *x, double *photons,
 void ora_set_state(ora_grid *g, const double *y, const double *photons,
                    const double *tallies);
 
+/* Rotate the direction bins to R u_k (u_k as given at creation; R a
+ * row-major 3x3 rotation) and recompute the routing.  The photons each
+ * vertex holds in a bin move to the rotated bin nearest that bin's previous
+ * direction (summed where several arrive) and are split over its new
+ * selection (escaping where none is selected). */
+int ora_rotate(ora_grid *g, const double *R);
+
 /* Selection tables.  sel_nbr [N*K*max_per_bin] neighbour vertex ids (best
  * first, -1 padding), sel_m [N*K], edge_bin [E] (bin of each directed edge
  * in the caller's CSR order), dL [N], tau [N] (n_H sigma dL).  Nullable. */
-/* Rotate the direction bins to R u_k (u_k as given at creation; R a
- * row-major 3x3 rotation), recompute the routing and re-split the photons
- * in flight over the new selection (escaping where none is selected). */
-int ora_rotate(ora_grid *g, const double *R);
-
 void ora_get_tables(const ora_grid *g, int32_t *sel_nbr, int32_t *sel_m,
                     int32_t *edge_bin, double *dL, double *tau);
 

@@ -560,6 +560,141 @@ def pin_combined_conservation(lib=None):
     assert np.count_nonzero(lay0 == 1) > np.count_nonzero(lay == 1)   # fronts switch vertices
 
 
+# ----------------------------------------------------------------- beams ---
+
+def beam_star(spacing=1.0):
+    """A beam source at the centre of a star whose five spokes point 30, 35,
+    50, 70 and 180 degrees away from +x; each of the first four spokes is
+    continued by one vertex a further spacing along +x.  Bins: the six axis
+    directions followed by the four forward spoke directions, so the bin of
+    a spoke's edge is never the bin of the beam's own direction.  No gas
+    opacity (sigma = 0), so every vertex passes on all it receives."""
+    ang = [(30.0, "y"), (35.0, "z"), (50.0, "-y"), (70.0, "-z")]
+    d = []
+    for a, ax in ang:
+        c, s_ = math.cos(math.radians(a)), math.sin(math.radians(a))
+        d.append({"y": (c, s_, 0.0), "z": (c, 0.0, s_), "-y": (c, -s_, 0.0),
+                  "-z": (c, 0.0, -s_)}[ax])
+    d = np.array(d)
+    pos = np.zeros((10, 3))
+    pos[1:5] = d * spacing
+    pos[5] = (-spacing, 0.0, 0.0)
+    pos[6:10] = pos[1:5] + np.array([spacing, 0.0, 0.0])
+    rows = [[1, 2, 3, 4, 5]] + [[0, 5 + i] for i in range(1, 5)] + [[0]] + [[i] for i in range(1, 5)]
+    ptr = np.zeros(11, np.int64)
+    ptr[1:] = np.cumsum([len(r) for r in rows])
+    idx = np.array([j for r in rows for j in r], np.int32)
+    bins = np.concatenate([G.axis_bins(), d])
+    return G.Workload(
+        name="beam_star", pos=pos, nbr_ptr=ptr, nbr_idx=idx, n_H=np.full(10, 1e-3),
+        volume=np.full(10, spacing ** 3), bin_dirs=bins,
+        src_vertex=np.array([0], np.int32), src_rate=np.array([3e40]),
+        src_dir=np.array([[1.0, 0.0, 0.0]]), sigma=0.0, dt=1e10, n_sweeps=2,
+        box=3 * spacing)
+
+
+def pin_beam_filing(lib=None):
+    """A beam (the plane-parallel source of the shadowing problem) goes to
+    the three neighbours most aligned with its direction, cosine > 0
+    (Sect. 2.2.3's rule), and travels on in the bin of its own direction:
+    after one step the three forward spokes hold E/3 each in the +x bin and
+    nothing else anywhere; in the second step the vertices beyond them
+    receive it, and having no neighbour ahead of them in the +x bin's cone,
+    let it escape.  The same in combined transport with every vertex
+    direction-conserving."""
+    w = beam_star()
+    E = float(w.src_rate[0] * w.dt)
+    for combined in (False, True):
+        ww = G.with_(w, transport=G.SX_TRANSPORT_COMBINED, tau_switch=1e300) if combined else w
+        o = Oracle(ww, lib)
+        o.run(1)
+        st = o.state()
+        want = np.zeros((10, w.k))
+        want[1:4, 0] = E / 3.0
+        assert np.array_equal(st["photons"], want), (combined, st["photons"])
+        t = st["tallies"]
+        assert t["escaped"] == 0.0 and t["absorbed"] == 0.0 and t["in_flight"] == E
+        o.run(1)
+        st = o.state()
+        assert np.array_equal(st["photons"], want), (combined, st["photons"])
+        nin = np.zeros(10)
+        nin[1:4] = E / 3.0          # the second step's beam
+        nin[6:9] = E / 3.0          # the first step's beam, one vertex on
+        assert np.array_equal(st["nin"], nin), (combined, st["nin"])
+        assert math.isclose(st["tallies"]["escaped"], E, rel_tol=1e-15)
+
+
+# ------------------------------------------------------- bin rotations ---
+
+def _cyclic_axes():
+    """The 120-degree turn about (1, 1, 1) that maps (x, y, z) to (z, x, y):
+    a symmetry of the icosahedron with vertices (0, +-1, +-phi) and their
+    cyclic permutations, so it maps the 42-bin set onto itself."""
+    return np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
+
+
+def pin_rotation_symmetry(lib=None):
+    """Rotating the bins by a symmetry of the bin set only relabels them.
+    Photons keep their direction through a rotation (the small numerical
+    diffusion per rotation of Sect. 5.2 vanishes when a bin's direction is
+    itself among the rotated bins), so the run with two such rotations
+    between steps is the run without them, with every bin's photons under
+    the label of the bin that now points their way (equal up to the order in
+    which a vertex sums its bins)."""
+    w = G.with_(G.small_random(400, seed=41, n_bins=42, box=3e21, rate=1e48, n_src=2,
+                               dt=3e13), bin_dirs=G.icosahedral_bins_42())
+    sd = np.zeros((2, 3))
+    sd[1] = [0.0, 0.0, 1.0]     # a beam along +z (the direction of bin 12 + ...)
+    w = G.with_(w, src_dir=sd)
+    R1 = _cyclic_axes()
+    R2 = R1 @ R1
+    u0 = w.bin_dirs
+    a = Oracle(w, lib)
+    b = Oracle(w, lib)
+    a.run(6)
+    b.run(6)
+    b.rotate(R1)
+    a.run(5)
+    b.run(5)
+    b.rotate(R2)
+    a.run(5)
+    b.run(5)
+    # label under R2 of the bin pointing along old bin k: R2 u0[k'] = u0[k]
+    ru = u0 @ R2.T
+    perm = np.array([int(np.argmin(np.linalg.norm(ru - u0[k], axis=1))) for k in range(w.k)])
+    assert np.allclose(ru[perm], u0, atol=1e-15, rtol=0) and len(set(perm)) == w.k
+    sa, sb = a.state(), b.state()
+    np.testing.assert_allclose(sb["y"], sa["y"], rtol=1e-12, atol=1e-300)
+    pa, pb = sa["photons"], sb["photons"][:, perm]
+    scale = float(w.src_rate.sum() * w.dt)
+    np.testing.assert_allclose(pb, pa, rtol=1e-10, atol=1e-12 * scale)
+    for key in ("emitted", "absorbed", "escaped", "in_flight"):
+        assert math.isclose(sb["tallies"][key], sa["tallies"][key], rel_tol=1e-12), key
+
+
+def pin_rotation_conservation(lib=None):
+    """Photons re-binned at a rotation are neither made nor lost: emitted =
+    absorbed + escaped + in flight after every step with a random rotation
+    before it, with isotropic and beam sources; and a rotation changes
+    nothing but the escapes and what is in flight."""
+    w = G.small_random(300, seed=42, n_bins=21, box=3e21, rate=1e48, n_src=2, dt=3e13)
+    sd = np.zeros((2, 3))
+    sd[0] = [0.0, 1.0, 0.0]
+    w = G.with_(w, src_dir=sd)
+    o = Oracle(w, lib)
+    for R in G.random_rotations(10, seed=43):
+        o.run(1)
+        t0 = o.state()["tallies"]
+        o.rotate(R)
+        t1 = o.state()["tallies"]
+        assert t1["emitted"] == t0["emitted"] and t1["absorbed"] == t0["absorbed"]
+        lost = t1["escaped"] - t0["escaped"]
+        assert lost >= 0.0 and math.isclose(t1["in_flight"], t0["in_flight"] - lost,
+                                            rel_tol=1e-12, abs_tol=1e-300)
+    h = o.run(1, history=True)
+    assert abs(h[0, 0] - (h[0, 1] + h[0, 2] + h[0, 3])) <= 1e-12 * h[0, 0]
+
+
 FAST_PINS = [pin_recombination_closed_form, pin_equilibrium_fixed_point,
              pin_ode_convergence, pin_photon_accounting,
              pin_selection_brute_force, pin_axis_star, pin_ties,
@@ -567,4 +702,5 @@ FAST_PINS = [pin_recombination_closed_form, pin_equilibrium_fixed_point,
              pin_ballistic_brute_force, pin_combined_lattice,
              pin_combined_conservation, pin_edge_reference_brute_force,
              pin_diffuse_off_is_on_the_spot, pin_diffuse_recombination_budget,
-             pin_diffuse_lattice, pin_diffuse_conservation]
+             pin_diffuse_lattice, pin_diffuse_conservation, pin_beam_filing,
+             pin_rotation_symmetry, pin_rotation_conservation]

@@ -59,6 +59,17 @@ MUTANTS = {
     "diffuse_not_counted": ("    g->emitted += Dj;\n", "\n"),
     "diffuse_sent_late": ("    diffuse_send(g);\n\n    /* Interaction and chemistry at every vertex",
                           "\n    /* Interaction and chemistry at every vertex"),
+    "beam_filed_in_edge_bin": ("g->I[(int64_t)g->nbr[e] * K + kb] += share;",
+                               "g->I[(int64_t)g->nbr[e] * K + g->ebin[e]] += share;"),
+    "beam_combined_filed_in_edge_bin": ("deliver(g, b + slots[t], kb, share);",
+                                        "deliver(g, b + slots[t], g->ebin[b + slots[t]], share);"),
+    "rotation_keeps_bin_index": ("to[k] = nearest_bin(g, &b_old[3 * k]);", "to[k] = (int32_t)k;"),
+    "rotation_maps_from_given_bins": ("to[k] = nearest_bin(g, &b_old[3 * k]);",
+                                      "to[k] = nearest_bin(g, &g->bins0[3 * k]);"),
+    "rotation_keeps_last_merged_bin": ("if (to[k] == kn) held += O_old",
+                                       "if (to[k] == kn) held = O_old"),
+    "rotation_escape_not_tallied": ("g->escaped += held;\n                g->in_flight -= held;",
+                                    "g->in_flight -= held;"),
     "nin_skips_first_bin": ("\n        for (int64_t k = 0; k < K; k++) nin += g->I[j * K + k];",
                             "\n        for (int64_t k = 1; k < K; k++) nin += g->I[j * K + k];"),
 }

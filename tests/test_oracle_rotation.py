@@ -1,8 +1,9 @@
 """The oracle's rotation of the direction bins (Sect. 2.2.3), checked
 against what the method fixes: the routing after a rotation is the routing
 of the rotated bins built from scratch (rotations are absolute, not
-compounded), photons in flight are conserved up to the ones that lose their
-way out, and the ionisation front still follows its analytic law."""
+compounded), photons in flight move to the rotated bin nearest their old
+bin's direction and are conserved up to the ones that lose their way out,
+and the ionisation front still follows its analytic law."""
 import math
 
 import numpy as np
@@ -40,24 +41,38 @@ def test_rotated_routing_equals_fresh_routing():
     assert np.array_equal(o.tables()["sel_m"], base["sel_m"])
 
 
-def test_rotation_keeps_photons_in_flight():
+def test_rotation_moves_photons_to_nearest_bins():
     w = G.small_random(800, seed=32, n_bins=42, box=3e21, rate=1e48, n_src=3, dt=3e13)
+    R = G.random_rotations(1, seed=9)[0]
     o = Oracle(w)
     o.run(12)
     before = o.state()
     m0 = o.tables()["sel_m"]
     held0 = before["photons"] * m0          # photons each (vertex, bin) holds
-    o.rotate(G.random_rotations(1, seed=9)[0])
+    o.rotate(R)
     after = o.state()
     m1 = o.tables()["sel_m"]
     held1 = after["photons"] * m1
-    lost = held0[m1 == 0].sum()
+    # new bin of each old bin: largest cosine between the old direction and
+    # the rotated ones, ties to the lower bin
+    new = _rotated_bins(w.bin_dirs, R)
+    old = w.bin_dirs
+    cos = (old[:, None, 0] * new[None, :, 0] + old[:, None, 1] * new[None, :, 1]) \
+        + old[:, None, 2] * new[None, :, 2]
+    to = np.argmax(cos, axis=1)
+    moved = np.zeros_like(held0)
+    for k in range(w.k):
+        moved[:, to[k]] += held0[:, k]
+    lost = moved[m1 == 0].sum()
     keep = m1 > 0
-    np.testing.assert_allclose(held1[keep], held0[keep], rtol=1e-15, atol=0)
+    np.testing.assert_allclose(held1[keep], moved[keep], rtol=1e-14, atol=0)
+    assert np.all(after["photons"][~keep] == 0.0)
     t0, t1 = before["tallies"], after["tallies"]
     assert math.isclose(t1["escaped"] - t0["escaped"], lost, rel_tol=1e-12, abs_tol=1e-300)
     assert math.isclose(t1["in_flight"], t0["in_flight"] - lost, rel_tol=1e-12)
     assert np.array_equal(after["y"], before["y"])
+    # the rotation mixes bins: some new bins take several old ones, some none
+    assert len(set(to.tolist())) < w.k
 
 
 def test_conservation_with_rotations_every_step():
