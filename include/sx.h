@@ -278,15 +278,22 @@ int sx_profile_read(sx_ctx *ctx, int64_t *launches, double *total_ms,
  * method rotates its bins over random angles between transport steps
  * against preferential directions (Sect. 2.2.3); the caller draws the
  * rotations.  The routing (selection, edge bins, bins of the source shares,
- * gather lists) is rebuilt on the device.  Photons in flight keep their bin:
- * what a vertex holds in a bin is split over the neighbours selected for
- * the bin's new direction (unchanged where their number is the same), and
- * escapes where none is selected (tallied as escaped).  sx_grid_reset
+ * gather lists) is rebuilt on the device.  Photons in flight keep their
+ * direction as closely as the rotated bins allow (the paper's small
+ * numerical diffusion per rotation, Sect. 5.2): what a vertex holds in an
+ * old bin moves to the rotated bin closest to that bin's previous direction
+ * (largest cosine, ties to the lower bin; holdings that meet in one bin add
+ * up in ascending old bin), is split over the neighbours selected for it
+ * (kept as it is where one old bin with the same number selected feeds it),
+ * and escapes where none is selected (tallied as escaped).  sx_grid_reset
  * restores the given bins.  With combined transport or diffuse radiation
  * the bin of each incoming edge and the per-edge bin lists are rebuilt too
  * (ballistic routing does not depend on the bins; what ballistic vertices
  * hold is untouched).  Synchronous.  Errors: SX_EINVAL (not a rotation),
- * SX_ENOTFOUND, SX_ENOMEM, SX_EDEVICE. */
+ * SX_ENOTFOUND, SX_ENOMEM, SX_EDEVICE.  SX_ENOMEM from the per-edge bin
+ * lists (their pool could not grow within the budget) leaves the grid
+ * unusable: sx_step and sx_solve refuse it with SX_ENOMEM, launching
+ * nothing, until sx_grid_reset rebuilds its tables (or it is freed). */
 int sx_rotate_bins(sx_ctx *ctx, sx_grid_id id, const double *R);
 
 /* ---- combined transport -------------------------------------------------

@@ -58,7 +58,12 @@ struct Grid {
   double base_sweeps = 0.0, base_emitted = 0.0, base_escaped = 0.0;
   int64_t n_direct = 0;     // tiles whose halo is too large for LDS staging
   std::vector<double> bins0;   // [3K] bin directions given at upload
+  std::vector<double> bins_cur;   // [3K] bin directions on the device now
   bool rotated = false;
+  // A routing rebuild that could not finish (its bin-list pool could not
+  // grow) leaves the device tables inconsistent: no sweep may run on the
+  // grid until a reset rebuilds them.
+  bool unusable = false;
   bool ebin_stale = false;
   std::vector<uint8_t> tile_direct;
   int32_t transport = SX_TRANSPORT_DCT;   // as uploaded (the kernel class may differ)
@@ -370,6 +375,7 @@ struct Sizes {
   int64_t n, npad, ntiles, E, K, kw, sp, bb, kb;
   int32_t transport, mpb;   // transport: the kernel class (1 also for diffuse radiation)
   bool diffuse;
+  int64_t n_src;
 };
 
 Sizes sizes_of(const sx_grid_desc *d) {
@@ -387,6 +393,7 @@ Sizes sizes_of(const sx_grid_desc *d) {
   s.transport = (d->transport == SX_TRANSPORT_COMBINED || s.diffuse) ? SX_TRANSPORT_COMBINED
                                                                      : SX_TRANSPORT_DCT;
   s.mpb = d->max_per_bin;
+  s.n_src = d->n_src;
   return s;
 }
 
@@ -400,6 +407,7 @@ uint64_t bytes_estimate(const Sizes &s, int64_t n_em, int64_t n_rec, int64_t n_h
        rnd(16 * s.E + 16) + rnd(4 * s.E + 4);
   b += rnd(4 * (s.ntiles + 1)) + rnd(4 * n_halo + 4) + rnd(2 * s.E) + rnd(s.ntiles);
   b += rnd(4 * (s.npad + 1)) + rnd(4 * n_em + 4) + rnd(8 * n_em + 8);
+  b += rnd(4 * n_em + 4) + rnd(24 * s.n_src + 8);   // beam shares: their sources and directions
   b += 6 * rnd(8 * s.npad);
   b += 2 * rnd((uint64_t)sx::kBlockBytes * s.kb * (s.npad + sx::kTile));
   b += 2 * rnd((uint64_t)s.sp * (s.npad + sx::kTile));
@@ -458,15 +466,23 @@ int build_ct_tables(sx_ctx *ctx, Grid *g) {
   HIP_TRY(ctx, hipStreamSynchronize(st));
   const int32_t total = *pin_total;
   if (!h.kl || total > h.kl_cap) {
-    if (h.kl) gfree(ctx, g, h.kl);
+    // the larger pool is allocated before the old one is released; if it
+    // cannot be, the list offsets already describe the new routing and the
+    // grid is marked unusable (sweeps are refused until a reset)
     uint8_t *d = nullptr;
     const int r = galloc(ctx, g, &d, (uint64_t)total + 1);
-    h.kl = r ? nullptr : d;
-    h.kl_cap = r ? 0 : total;
+    if (r) {
+      g->unusable = true;
+      return fail(ctx, SX_ENOMEM,
+                  "bin lists of combined transport need %d entries and the pool could not "
+                  "grow; the grid is unusable until sx_grid_reset", total);
+    }
+    if (h.kl) gfree(ctx, g, h.kl);
+    h.kl = d;
+    h.kl_cap = total;
     HIP_TRY(ctx, hipMemcpyAsync(&dg->kl, &h.kl, sizeof(h.kl), hipMemcpyHostToDevice, st));
     HIP_TRY(ctx, hipMemcpyAsync(&dg->kl_cap, &h.kl_cap, sizeof(h.kl_cap), hipMemcpyHostToDevice, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
-    if (r) return fail(ctx, SX_ENOMEM, "bin lists of combined transport: %d entries", total);
   }
   HIP_TRY(ctx, sx::launch_kl_fill(dg, h, st));
   HIP_TRY(ctx, hipStreamSynchronize(st));
@@ -474,10 +490,11 @@ int build_ct_tables(sx_ctx *ctx, Grid *g) {
 }
 
 // Rebuild a grid's routing on the device for bin directions `bins` [3K]:
-// selection, (with rescale) the photons in flight re-split over the new
-// selection, edge bins, source-share bins, m, gather lists; the overflow
-// record pool grows when the new routing needs more.  Synchronous.
-int rebuild_routing(sx_ctx *ctx, Grid *g, const double *bins, bool rescale) {
+// selection, (with a re-binning map) the photons in flight moved to their
+// new bins and split over the new selection, edge bins, source-share bins,
+// m, gather lists; the overflow record pool grows when the new routing
+// needs more.  Synchronous.
+int rebuild_routing(sx_ctx *ctx, Grid *g, const double *bins, const sx::RebinMap *rebin) {
   GridDev &h = g->hg;
   GridDev *dg = ctx->table + g->slot;
   hipStream_t st = ctx->stream;
@@ -489,9 +506,10 @@ int rebuild_routing(sx_ctx *ctx, Grid *g, const double *bins, bool rescale) {
   HIP_TRY(ctx, sx::launch_select(dg, h, st));
   HIP_TRY(ctx, sx::launch_em_bins(dg, h, g->n_em, st));
   g->ebin_stale = true;   // the full edge-bin table is rebuilt when read
-  // m words; with rescale the photons in flight are re-split first
-  if (rescale) HIP_TRY(ctx, sx::launch_mbits_rescale(dg, h, st));
+  // m words; after a rotation the photons in flight are re-binned first
+  if (rebin) HIP_TRY(ctx, sx::launch_rebin(dg, h, *rebin, st));
   else HIP_TRY(ctx, sx::launch_mbits(dg, h, st));
+  g->bins_cur.assign(bins, bins + 3 * h.k);
   // no clearing of the in-words: the fill rewrites the word of every bin
   // below K, and the padding bins of the last block keep their empty words
   // from the upload
@@ -557,6 +575,8 @@ struct sx_prepared {
   std::vector<double> tau, dtnhv, bco, y0;
   std::vector<int32_t> em_ptr, em_k, em_edge;
   std::vector<double> em_amt;
+  std::vector<int32_t> em_beam;    // [n_em] source of a beam share, -1 isotropic (empty: no beams)
+  std::vector<double> beam_dir;    // [3 n_src] source directions (empty: no beams)
   int32_t transport = 0, dct_ref = 0;   // transport: the kernel class
   double tau_switch = 0.0, alpha_A = 0.0, alpha_B = 0.0;
   std::vector<double> nhv;
@@ -738,8 +758,7 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
   // source's photons and the bin of the edge it arrives along.  The edge bin
   // is the device's rule (largest cosine, ties to the lower bin) evaluated
   // the same way, so both sides agree bit for bit.
-  auto edge_bin = [&](int64_t e) -> int32_t {
-    const double *ed = &edir[(size_t)(3 * e)];
+  auto nearest_bin = [&](const double *ed) -> int32_t {
     int32_t best = 0;
     double cb = 0.0;
     for (int32_t k = 0; k < (int32_t)S.K; ++k) {
@@ -750,6 +769,7 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
     }
     return best;
   };
+  auto edge_bin = [&](int64_t e) -> int32_t { return nearest_bin(&edir[(size_t)(3 * e)]); };
   // The <= mpb edges of v's row most aligned with direction u, cosine >
   // cos_min, ties to the lower original id (rows are in original-id order):
   // the rule of the bins, used for beams and for ballistic transport.
@@ -777,9 +797,11 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
     int32_t k;
     double amt;
     int32_t edge;   // the source's edge it travels along (new edge id)
+    int32_t beam;   // the source of a beam share (its bin is the beam's), -1 isotropic
   };
   std::vector<Em> em;
   double esc_emit = 0.0;
+  bool has_beam = false;
   for (int s = 0; s < d->n_src; ++s) {
     const int32_t vi = d->src_vertex[s];
     if (g->is_src_h.empty()) g->is_src_h.assign((size_t)n, 0);
@@ -794,16 +816,19 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
       const double share = (Es / unit) / (double)deg;
       for (int64_t p = d->nbr_ptr[vi]; p < d->nbr_ptr[vi + 1]; ++p) {
         const int32_t e = g->orig_to_new_e[(size_t)p];
-        em.push_back({g->nbr_h[(size_t)e], edge_bin(e), share, e});
+        em.push_back({g->nbr_h[(size_t)e], edge_bin(e), share, e, -1});
       }
     } else {
-      // beam: the <= mpb neighbours most aligned with u
+      // beam: the <= mpb neighbours most aligned with u; the photons travel
+      // along u and are filed in the bin closest to it
       int32_t sl[3];
       const int cnt = pick(v, u, sl);
       if (cnt == 0) { esc_emit += Es; continue; }
       const double share = (Es / unit) / (double)cnt;
+      const int32_t kb = nearest_bin(u);
       for (int q = 0; q < cnt; ++q)
-        em.push_back({g->nbr_h[(size_t)sl[q]], edge_bin(sl[q]), share, sl[q]});
+        em.push_back({g->nbr_h[(size_t)sl[q]], kb, share, sl[q], s});
+      has_beam = true;
     }
   }
   g->esc_emit = esc_emit;
@@ -818,11 +843,20 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
   em_k.assign(em.size(), 0);
   em_edge.assign(em.size(), 0);
   em_amt.assign(em.size(), 0.0);
+  P->em_beam.clear();
+  P->beam_dir.clear();
+  if (has_beam) {
+    P->em_beam.assign(em.size(), -1);
+    P->beam_dir.assign((size_t)3 * d->n_src, 0.0);
+    for (int s = 0; s < d->n_src; ++s)
+      for (int c = 0; c < 3; ++c) P->beam_dir[(size_t)(3 * s + c)] = d->src_dir[3 * s + c];
+  }
   for (size_t q = 0; q < em.size(); ++q) {
     em_ptr[(size_t)em[q].recv + 1]++;
     em_k[q] = em[q].k;
     em_edge[q] = em[q].edge;
     em_amt[q] = em[q].amt;
+    if (has_beam) P->em_beam[q] = em[q].beam;
   }
   for (int64_t v = 0; v < npad; ++v) em_ptr[(size_t)v + 1] += em_ptr[(size_t)v];
   g->n_em = (int64_t)em.size();
@@ -1089,8 +1123,21 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
     h.em_k = d_emk;
     h.em_edge = d_eme;
     h.em_amt = d_ema;
+    h.em_beam = nullptr;
+    h.beam_dir = nullptr;
+    if (!P->em_beam.empty()) {
+      int32_t *d_emb;
+      double *d_bd;
+      GA(d_emb, g->n_em + 1);
+      GA(d_bd, P->beam_dir.size());
+      UP(d_emb, P->em_beam.data(), 4 * g->n_em);
+      UP(d_bd, P->beam_dir.data(), 8 * P->beam_dir.size());
+      h.em_beam = d_emb;
+      h.beam_dir = d_bd;
+    }
   }
   g->bins0 = P->bins;
+  g->bins_cur = P->bins;
   if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
   if ((he = sx::launch_mbits(dg, h, st)) != hipSuccess) return kfail(he);
   if ((he = sx::launch_clear_inw(h, st)) != hipSuccess) return kfail(he);
@@ -1370,9 +1417,10 @@ int sx_grid_reset(sx_ctx *ctx, sx_grid_id id) {
   Grid *g = find(ctx, id);
   if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  int r = rebuild_routing(ctx, g, g->bins0.data(), false);
+  int r = rebuild_routing(ctx, g, g->bins0.data(), nullptr);
   if (r) return r;
   g->rotated = false;
+  g->unusable = false;
   HIP_TRY(ctx, sx::launch_reset_state(ctx->table + g->slot, g->hg, g->y_init, ctx->stream));
   g->base_sweeps = g->base_emitted = g->base_escaped = 0.0;
   return SX_OK;
@@ -1406,7 +1454,31 @@ int sx_rotate_bins(sx_ctx *ctx, sx_grid_id id, const double *R) {
       b[(size_t)(3 * k + r)] = (p0 + p1) + p2;
     }
   }
-  int r = rebuild_routing(ctx, g, b.data(), true);
+  // Each old bin's photons go to the rotated bin closest to its direction
+  // (largest cosine ((d_x n_x + d_y n_y) + d_z n_z), ties to the lower new
+  // bin); the map lists, per new bin, the old bins it takes, ascending.
+  sx::RebinMap map{};
+  {
+    std::vector<int32_t> to((size_t)K), cnt((size_t)K + 1, 0);
+    for (int64_t k = 0; k < K; ++k) {
+      const double *d = &g->bins_cur[(size_t)(3 * k)];
+      int32_t best = 0;
+      double cb = 0.0;
+      for (int64_t q = 0; q < K; ++q) {
+        const double *u = &b[(size_t)(3 * q)];
+        const double p0 = d[0] * u[0], p1 = d[1] * u[1], p2 = d[2] * u[2];
+        const double c = (p0 + p1) + p2;
+        if (q == 0 || c > cb) { cb = c; best = (int32_t)q; }
+      }
+      to[(size_t)k] = best;
+      cnt[(size_t)best + 1]++;
+    }
+    for (int64_t q = 0; q < K; ++q) cnt[(size_t)q + 1] += cnt[(size_t)q];
+    for (int64_t q = 0; q <= K; ++q) map.ptr[q] = (uint8_t)cnt[(size_t)q];
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t k = 0; k < K; ++k) map.list[fill[(size_t)to[(size_t)k]]++] = (uint8_t)k;
+  }
+  int r = rebuild_routing(ctx, g, b.data(), &map);
   if (r) return r;
   g->rotated = true;
   return SX_OK;
@@ -1678,6 +1750,9 @@ int collect(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, std::vector<Grid *> &
   for (int32_t i = 0; i < n; ++i) {
     Grid *g = find(ctx, ids[i]);
     if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)ids[i]);
+    if (g->unusable)
+      return fail(ctx, SX_ENOMEM, "grid %lld: a rotation could not finish its tables; "
+                  "reset or free it", (long long)ids[i]);
     for (Grid *o : gs)
       if (o == g) return fail(ctx, SX_EINVAL, "grid %lld listed twice", (long long)ids[i]);
     gs.push_back(g);

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sx.h"
+
 namespace sx {
 
 constexpr int kTile = 64;           // vertices per tile = one wavefront
@@ -102,6 +104,9 @@ struct GridDev {
   int32_t *em_k;            // [n_em] bin of each share (from its edge)
   const int32_t *em_edge;   // [n_em] the source's edge the share travels along
   const double *em_amt;     // [n_em] photons / unit
+  const int32_t *em_beam;   // [n_em] source of a beam share (filed in the bin
+                            // closest to the beam), -1 isotropic; null: no beams
+  const double *beam_dir;   // [3 n_src] source directions (null: no beams)
   // chemistry coefficients
   const double *tau;        // [npad] n_H sigma dL
   const double *dtnhv;      // [npad] dt * n_H * V
@@ -153,10 +158,18 @@ hipError_t launch_edge_bins(const GridDev *dg, const GridDev &hg, hipStream_t s)
 hipError_t launch_inlist_count(const GridDev *dg, const GridDev &hg, hipStream_t s);
 hipError_t launch_scan(int32_t *cnt, int32_t *ptr, int64_t *part, int32_t n, hipStream_t s);
 hipError_t launch_inlist_fill(const GridDev *dg, const GridDev &hg, hipStream_t s);
-// After a rotation of the bins: the photons each (vertex, bin) holds are
-// re-split over the new selection (from fwd; the old one is still in
-// mbits); those with no forward neighbour left move to the escape tally.
-hipError_t launch_mbits_rescale(GridDev *dg, const GridDev &hg, hipStream_t s);
+// After a rotation of the bins: for every new bin, the old bins whose
+// photons it takes (the old bins closest in direction to it), ascending:
+// list[ptr[kn] .. ptr[kn+1]).
+struct RebinMap {
+  uint8_t ptr[132];
+  uint8_t list[128];
+};
+static_assert(SX_MAX_BINS_FP32 < 128 && SX_MAX_BINS_FP64 < 128, "rebin map holds 127 bins");
+// The photons each vertex holds move to their new bins (map) and are split
+// over the new selection (from fwd; the old m is still in mbits, and is
+// replaced); those with no forward neighbour left move to the escape tally.
+hipError_t launch_rebin(GridDev *dg, const GridDev &hg, const RebinMap &map, hipStream_t s);
 // Bin of each source share from its edge's bin.
 hipError_t launch_em_bins(GridDev *dg, const GridDev &hg, int64_t n_em, hipStream_t s);
 hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s);

@@ -174,6 +174,8 @@ __device__ __forceinline__ void select_bin(const GridDev &g, int64_t i, int k,
 // One wave per two vertices: bins 0..63 of the first vertex, then of the
 // second, then bins 64..95 of both at once (lanes 0..31 the first, 32..63
 // the second), so that with K = 84 few lanes idle.
+static_assert(SX_MAX_BINS_FP32 <= 96 && SX_MAX_BINS_FP64 <= 96,
+              "k_select covers bins 0..95: a larger bin limit needs another pass");
 // LDS of k_select per workgroup (8 vertices), sized by the grid's largest
 // degree: the edge directions, then the selection masks
 __host__ __device__ constexpr int64_t select_lds_bytes(int max_deg) {
@@ -471,12 +473,15 @@ __global__ __launch_bounds__(256) void k_kl_fill(const GridDev *__restrict__ gp)
   }
 }
 
-// Bin of each source share: the bin closest to its edge (the edge-bin rule).
+// Bin of each source share: the bin closest to the direction its photons
+// travel in, the edge from the source (the edge-bin rule) or, for a beam
+// share, the beam's direction.
 __global__ void k_em_bins(GridDev *__restrict__ gp, int64_t n_em) {
   GridDev &g = *gp;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n_em) return;
-  const double *ed = &g.edir[3 * (int64_t)g.em_edge[q]];
+  const int32_t bs = g.em_beam ? g.em_beam[q] : -1;
+  const double *ed = bs >= 0 ? &g.beam_dir[3 * (int64_t)bs] : &g.edir[3 * (int64_t)g.em_edge[q]];
   int best = 0;
   double cb = cosine3(ed, &g.bins[0]);
   for (int k = 1; k < g.k; ++k) {
@@ -486,48 +491,14 @@ __global__ void k_em_bins(GridDev *__restrict__ gp, int64_t n_em) {
   g.em_k[q] = best;
 }
 
-// Re-split after a rotation of the bins, for the 16 bins of one m word of
-// one vertex j: each (j, bin) holds m_old * Ipre * T photons (T of the step
-// that wrote them); they now go to m_new neighbours, Ipre' = Ipre m_old /
-// m_new (unchanged if m_new = m_old), or escape if m_new = 0.  Returns the
-// escaping photons, which move from the in-flight tally to the escape tally.
-template <typename P>
-__device__ __forceinline__ double rescale16(GridDev &g, int tile, int lane, int k0,
-                                            uint32_t mold, uint32_t mnew) {
-  constexpr int BB = kBlockBytes / sizeof(P);
-  const int j = tile * kTile + lane;
-  const int par = g.parity;
-  P *o = (P *)g.o[par];
-  const double T = (double)((const P *)g.t[par])[j];
-  double esc = 0.0;
-  for (int b = 0; b < 16 && k0 + b < g.k; ++b) {
-    const uint32_t mo = (mold >> (2 * b)) & 3u, mn = (mnew >> (2 * b)) & 3u;
-    if (mn == mo) continue;
-    const int k = k0 + b, kb = k / BB, kk = k - kb * BB;
-    P &v = o[(((int64_t)tile * g.kb + kb) * 64 + lane) * BB + kk];
-    if (mn == 0u) {
-      esc += (double)v * (double)mo * T;
-      v = P(0);
-    } else {
-      v = (P)((double)v * (double)mo / (double)mn);
-    }
-  }
-  return esc;
-}
-
 // Packed m(j, k), 2 bits per bin and 16 bins per word, from the selection:
 // one workgroup per tile and one wave per 16-bin word (thread = word * 64 +
-// lane).  With RESCALE (a rotation of the bins) the photons in flight are
-// first re-split from the old m to the new, and the tile's escapes are
-// summed in a fixed order: over the word's bins, a butterfly over lanes,
-// then over words.
+// lane).
 static_assert((SX_MAX_BINS_FP32 + 15) / 16 <= 6 && (SX_MAX_BINS_FP64 + 15) / 16 <= 6,
               "k_mbits holds at most 6 m words per vertex (one wave each)");
 
-template <bool RESCALE>
 __global__ __launch_bounds__(64 * 6) void k_mbits(GridDev *__restrict__ gp) {
   GridDev &g = *gp;
-  __shared__ double part[6];
   const int tile = blockIdx.x, q = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = tile * kTile + lane;
   const int K = g.k;
@@ -554,23 +525,84 @@ __global__ __launch_bounds__(64 * 6) void k_mbits(GridDev *__restrict__ gp) {
   uint32_t mword = 0;
 #pragma unroll
   for (int b = 0; b < 16; ++b) mword |= ((v[b] >> 21) & 3u) << (2 * b);
-  const int64_t wi = ((int64_t)tile * g.kw + q) * 64 + lane;
-  if constexpr (RESCALE) {
-    const uint32_t mold = g.mbits[wi];
-    double esc = g.precision == 0 ? rescale16<double>(g, tile, lane, k0, mold, mword)
-                                  : rescale16<float>(g, tile, lane, k0, mold, mword);
+  g.mbits[((int64_t)tile * g.kw + q) * 64 + lane] = mword;
+}
+
+// Re-binning after a rotation of the bins.  Photons keep their direction as
+// closely as the rotated bins allow: what vertex j holds in old bin k (m_old
+// Ipre, times T_j) moves to the new bin whose direction is closest to old
+// bin k's.  The map gives, for every new bin, the old bins it takes
+// (ascending); their holdings add up in that order and are split over the
+// new bin's m_new selected neighbours, or leave the domain (escape tally)
+// where m_new = 0.  A new bin fed by one old bin with the same m keeps its
+// Ipre as it is.  One workgroup (one wave) per tile, lane = vertex: the old
+// bins and m go to LDS (each lane reads back only its own column), then the
+// new bins are written in place, with the new m words (from the new
+// selection in fwd).  The tile's escapes are summed by a butterfly.
+template <typename P>
+__global__ __launch_bounds__(64) void k_rebin(GridDev *__restrict__ gp, RebinMap map) {
+  GridDev &g = *gp;
+  constexpr int BB = kBlockBytes / sizeof(P);
+  constexpr int KM = sizeof(P) == 8 ? SX_MAX_BINS_FP64 : SX_MAX_BINS_FP32;
+  typedef P V __attribute__((ext_vector_type(BB)));
+  __shared__ P held[KM * 64];
+  __shared__ uint8_t mo[KM * 64];
+  const int tile = blockIdx.x, lane = threadIdx.x;
+  const int j = tile * kTile + lane;
+  const int K = g.k, KB = g.kb;
+  const int par = g.parity;
+  V *o = (V *)g.o[par];
+  for (int w = 0; w < g.kw; ++w) {
+    const uint32_t mw = g.mbits[((int64_t)tile * g.kw + w) * 64 + lane];
+    for (int b = 0; b < 16 && 16 * w + b < K; ++b)
+      mo[(16 * w + b) * 64 + lane] = (uint8_t)((mw >> (2 * b)) & 3u);
+  }
+  for (int kb = 0; kb < KB; ++kb) {
+    const V v = o[((int64_t)tile * KB + kb) * 64 + lane];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) esc += __shfl_xor(esc, off);
-    if (lane == 0) part[q] = esc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double sum = 0.0;
-      for (int w = 0; w < g.kw; ++w) sum += part[w];
-      g.tally[(int64_t)tile * 3 + 1] += sum;
-      g.tally[(int64_t)tile * 3 + 2] -= sum;
+    for (int b = 0; b < BB; ++b)
+      if (kb * BB + b < K) held[(kb * BB + b) * 64 + lane] = v[b];
+  }
+  const double T = (double)((const P *)g.t[par])[j];
+  double esc = 0.0;
+  uint32_t mword = 0;
+  V out = V(0);
+  for (int kn = 0; kn < K; ++kn) {
+    const uint32_t mn = j < g.n ? (g.fwd[(int64_t)j * K + kn] >> 21) & 3u : 0u;
+    const int q0 = map.ptr[kn], q1 = map.ptr[kn + 1];
+    P val;
+    if (q1 - q0 == 1 && mn > 0u && mn == mo[map.list[q0] * 64 + lane]) {
+      val = held[map.list[q0] * 64 + lane];
+    } else {
+      double h = 0.0;
+      for (int q = q0; q < q1; ++q) {
+        const int k = map.list[q];
+        h += (double)held[k * 64 + lane] * (double)mo[k * 64 + lane];
+      }
+      if (mn == 0u) {
+        esc += h * T;
+        val = P(0);
+      } else {
+        val = (P)(h / (double)mn);
+      }
+    }
+    out[kn % BB] = val;
+    if (kn % BB == BB - 1 || kn == K - 1) {
+      o[((int64_t)tile * KB + kn / BB) * 64 + lane] = out;
+      out = V(0);
+    }
+    mword |= mn << (2 * (kn & 15));
+    if ((kn & 15) == 15 || kn == K - 1) {
+      g.mbits[((int64_t)tile * g.kw + kn / 16) * 64 + lane] = mword;
+      mword = 0;
     }
   }
-  g.mbits[wi] = mword;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) esc += __shfl_xor(esc, off);
+  if (lane == 0) {
+    g.tally[(int64_t)tile * 3 + 1] += esc;
+    g.tally[(int64_t)tile * 3 + 2] -= esc;
+  }
 }
 
 // Exclusive scan of n counts into ptr[0..n] (ptr[n] = total) in three
@@ -1494,13 +1526,16 @@ hipError_t launch_clear_inw(const GridDev &hg, hipStream_t s) {
 
 hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s) {
   // the plain variant writes the m words only
-  hipLaunchKernelGGL(k_mbits<false>, dim3((unsigned)hg.ntiles), dim3(64 * hg.kw), 0, s,
+  hipLaunchKernelGGL(k_mbits, dim3((unsigned)hg.ntiles), dim3(64 * hg.kw), 0, s,
                      const_cast<GridDev *>(dg));
   return hipGetLastError();
 }
 
-hipError_t launch_mbits_rescale(GridDev *dg, const GridDev &hg, hipStream_t s) {
-  hipLaunchKernelGGL(k_mbits<true>, dim3((unsigned)hg.ntiles), dim3(64 * hg.kw), 0, s, dg);
+hipError_t launch_rebin(GridDev *dg, const GridDev &hg, const RebinMap &map, hipStream_t s) {
+  if (hg.precision == 0)
+    hipLaunchKernelGGL(k_rebin<double>, dim3((unsigned)hg.ntiles), dim3(64), 0, s, dg, map);
+  else
+    hipLaunchKernelGGL(k_rebin<float>, dim3((unsigned)hg.ntiles), dim3(64), 0, s, dg, map);
   return hipGetLastError();
 }
 hipError_t launch_em_bins(GridDev *dg, const GridDev &hg, int64_t n_em, hipStream_t s) {
@@ -1545,6 +1580,7 @@ hipError_t launch_inlist_fill(const GridDev *dg, const GridDev &hg,
                      0, s, dg);
   return hipGetLastError();
 }
+
 
 hipError_t launch_reset_state(GridDev *dg, const GridDev &hg, const double *y0,
                               hipStream_t s) {

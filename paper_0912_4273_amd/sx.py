@@ -242,10 +242,15 @@ def sx_init(device: int = 0, hbm_budget: int = 0, stream: Optional[int] = None,
                      alloc_user=None)
     if use_torch_allocator:
         import torch
+        # blocks are tagged with the stream the library's kernels run on, so
+        # that the caching allocator orders their reuse after that stream's
+        # work (the context's stream is known once sx_init returns; blocks
+        # allocated during sx_init are tagged with the current stream)
+        on = {"stream": None}
 
         def _alloc(nbytes, _user):
             try:
-                s = torch.cuda.current_stream(device)
+                s = on["stream"] or torch.cuda.current_stream(device)
                 return int(torch.cuda.caching_allocator_alloc(int(nbytes), device, s))
             except Exception:
                 return None
@@ -259,6 +264,9 @@ def sx_init(device: int = 0, hbm_budget: int = 0, stream: Optional[int] = None,
     h = C.c_void_p()
     rc = lib.sx_init(C.byref(h), C.byref(opts))
     _check(None, rc)
+    if use_torch_allocator:
+        on["stream"] = torch.cuda.ExternalStream(int(lib.sx_stream(h) or 0), device=device)
+        keep.append(on)
     return h, keep
 
 

@@ -311,7 +311,10 @@ def test_edge_reference_rotated(sxctx):
     gid = sxctx.upload(w)
     try:
         sxctx.solve([gid], 11)
+        before = sxctx.info(gid)["bytes"]
         sxctx.rotate(gid, R)
+        # the rotated routing needs more overflow records: the pool grew
+        assert sxctx.info(gid)["bytes"] > before
         tab = sxctx.tables(gid)
         sxctx.solve([gid], 9)
         st = sxctx.state(gid, photons=True)

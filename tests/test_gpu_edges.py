@@ -116,6 +116,6 @@ def test_thick_cells_pass_their_tiny_share(sxctx, prec):
     o.close()
     assert np.median(tau) > 20
     assert ref["escaped"] > 0
-    rel = 1e-9 if prec == G.SX_FP64 else 1e-3
+    rel = 1e-9 if prec == G.SX_FP64 else 1e-4
     for key in ("emitted", "absorbed", "escaped", "in_flight"):
         assert abs(got[key] - ref[key]) <= rel * abs(ref[key]), (key, got[key], ref[key])
