@@ -228,6 +228,26 @@ int sx_grid_free(sx_ctx *ctx, sx_grid_id id);
  * Errors: SX_ENOTFOUND, SX_EINVAL, SX_EDEVICE. */
 int sx_step(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, int32_t n_sweeps);
 
+/* sx_step for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  Same
+ * arguments, kernels and results (bit for bit) as sx_step, but it calls no
+ * hipMalloc, hipFree or other allocating routine: its launch tables (tile
+ * maps, grids to advance) and completion counter live in one static device
+ * array per GPU (8 bytes per tile of SX_NOALLOC_MAX_TILES plus 8 KiB, about
+ * 1 MiB; its address is looked up at sx_init and the array is held until
+ * the process ends), filled by a kernel at every call, and
+ * each step is one plain kernel launch per launch class (no graph).  Limits:
+ * n <= SX_NOALLOC_MAX_GRIDS grids and at most SX_NOALLOC_MAX_TILES tiles of
+ * 64 vertices over all of them (8.4M vertices); beyond either it returns
+ * SX_EINVAL and launches nothing.  Every call on one GPU uses that GPU's
+ * array: calls from different contexts or streams that overlap in time on
+ * one GPU race (calls on one stream are ordered and safe).  Asynchronous on
+ * the context stream.  Errors: SX_ENOTFOUND, SX_EINVAL, SX_ENOMEM (grid left
+ * unusable by a rotation), SX_EDEVICE. */
+#define SX_NOALLOC_MAX_GRIDS 256
+#define SX_NOALLOC_MAX_TILES 131072
+int sx_step_noalloc(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, int32_t n_sweeps);
+
 /* Run grid ids[i] for n_sweeps[i] steps (grids finish independently and
  * drop out of the batch), then wait for the device. */
 int sx_solve(sx_ctx *ctx, const sx_grid_id *ids, int32_t n,

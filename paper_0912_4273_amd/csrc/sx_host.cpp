@@ -117,6 +117,7 @@ struct sx_ctx {
   uint8_t *pin = nullptr;
   bool prof = false;
   std::vector<ProfEv> ev;     // pool
+  uint8_t *scratch = nullptr; // device address of this device's sx_step_noalloc array
   size_t ev_used = 0;
 };
 
@@ -1322,6 +1323,21 @@ int sx_init(sx_ctx **out, const sx_ctx_opts *opts) {
     delete ctx;
     return SX_EDEVICE;
   }
+  // the device address of the no-allocation step's scratch array, once per
+  // device (kept by the library for later contexts)
+  {
+    void *sp = nullptr;
+    if (sx::noalloc_scratch_init(o.device, &sp) != hipSuccess || !sp) {
+      (void)hipGetLastError();
+      (void)hipHostFree(ctx->pin);
+      (void)hipFree(ctx->done);
+      (void)hipFree(ctx->table);
+      if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+      delete ctx;
+      return SX_EDEVICE;
+    }
+    ctx->scratch = (uint8_t *)sp;
+  }
   for (int s = kMaxSlots - 1; s >= 0; --s) ctx->free_slots.push_back(s);
   *out = ctx;
   return SX_OK;
@@ -1779,6 +1795,85 @@ int sx_step(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, int32_t n_sweeps) {
   HIP_TRY(ctx, sx::launch_set_remaining(ctx->table, slots.data(), vals.data(), n, 1,
                                         ctx->stream));
   return launch_steps(ctx, gs, n_sweeps);
+}
+
+int sx_step_noalloc(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, int32_t n_sweeps) {
+  if (!ctx) return SX_EINVAL;
+  if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
+  if (n_sweeps < 0) return fail(ctx, SX_EINVAL, "n_sweeps < 0");
+  if (n < 0 || (n > 0 && !ids)) return fail(ctx, SX_EINVAL, "bad id list");
+  if (n > SX_NOALLOC_MAX_GRIDS)
+    return fail(ctx, SX_EINVAL, "%d grids exceed the no-allocation limit of %d", n,
+                SX_NOALLOC_MAX_GRIDS);
+  if (!ctx->scratch) return fail(ctx, SX_EDEVICE, "no-allocation scratch not set up");
+  // fixed-size host arrays: nothing is allocated on either side
+  Grid *gs[SX_NOALLOC_MAX_GRIDS];
+  int32_t slots[SX_NOALLOC_MAX_GRIDS], vals[SX_NOALLOC_MAX_GRIDS];
+  int64_t tiles = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    Grid *g = find(ctx, ids[i]);
+    if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)ids[i]);
+    if (g->unusable)
+      return fail(ctx, SX_ENOMEM, "grid %lld: a rotation could not finish its tables; "
+                  "reset or free it", (long long)ids[i]);
+    for (int32_t q = 0; q < i; ++q)
+      if (gs[q] == g) return fail(ctx, SX_EINVAL, "grid %lld listed twice", (long long)ids[i]);
+    gs[i] = g;
+    slots[i] = g->slot;
+    vals[i] = n_sweeps;
+    tiles += g->hg.ntiles;
+  }
+  if (tiles > SX_NOALLOC_MAX_TILES)
+    return fail(ctx, SX_EINVAL, "%lld tiles exceed the no-allocation limit of %d",
+                (long long)tiles, SX_NOALLOC_MAX_TILES);
+  if (n_sweeps == 0 || n == 0) return SX_OK;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, sx::launch_set_remaining(ctx->table, slots, vals, n, 1, ctx->stream));
+  // one launch per precision and transport class present, grids in the
+  // caller's order and tiles in each grid's order, as a plan of sx_step lays
+  // them out; the tables are written into the scratch array by a kernel
+  sx::SweepLaunch ls[4];
+  int nl = 0;
+  int32_t map_first = 0;
+  sx::NoAllocList L;
+  for (int cls = 0; cls < 4; ++cls) {
+    const int prec = cls & 1 ? SX_FP32_TRANSPORT : SX_FP64;
+    const int tr = cls >> 1;
+    L.n = 0;
+    L.first[0] = 0;
+    int64_t plane_bytes = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      const Grid *g = gs[i];
+      if (g->hg.precision != prec || g->hg.transport != tr) continue;
+      L.slot[L.n] = g->slot;
+      L.first[L.n + 1] = L.first[L.n] + g->hg.ntiles;
+      ++L.n;
+      plane_bytes += 2 * (int64_t)sx::kBlockBytes * g->hg.kb * (g->hg.npad + sx::kTile);
+    }
+    if (L.n == 0) continue;
+    L.cls = cls;
+    L.map_first = map_first;
+    L.clear_done = nl == 0 ? 1 : 0;
+    HIP_TRY(ctx, sx::launch_noalloc_tables(ctx->scratch, L, ctx->stream));
+    sx::SweepLaunch &l = ls[nl++];
+    l = sx::SweepLaunch{};
+    l.grids = ctx->table;
+    l.map = (const int2 *)(ctx->scratch + sx::kNoAllocMapOffset) + map_first;
+    l.n_tiles = L.first[L.n];
+    l.adv = (const int32_t *)(ctx->scratch + sx::kNoAllocAdvOffset) +
+            (int64_t)cls * SX_NOALLOC_MAX_GRIDS;
+    l.n_adv = L.n;
+    l.done = (uint32_t *)ctx->scratch;
+    l.xcd_remap = ctx->dflt.xcd_contiguous;
+    l.tpb = tr ? 1 : ctx->dflt.tiles_per_group;
+    l.precision = prec;
+    l.transport = tr;
+    l.nt = plane_bytes <= sx::kLlcBytes;
+    map_first += L.first[L.n];
+  }
+  for (int32_t s = 0; s < n_sweeps; ++s)
+    for (int i = 0; i < nl; ++i) HIP_TRY(ctx, sx::launch_sweep(ls[i], ctx->stream));
+  return SX_OK;
 }
 
 int sx_solve(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, const int32_t *n_sweeps) {

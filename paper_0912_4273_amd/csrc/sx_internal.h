@@ -201,6 +201,27 @@ struct SweepLaunch {
 };
 hipError_t launch_sweep(const SweepLaunch &l, hipStream_t s);
 hipError_t add_sweep_node(hipGraph_t graph, const SweepLaunch &l, hipGraphNode_t *prev);
+// sx_step_noalloc's device scratch (one file-scope array per device): the
+// completion counter at offset 0, per launch class c (< 4) the grids to
+// advance at kNoAllocAdvOffset + 4 SX_NOALLOC_MAX_GRIDS c, the tile maps
+// from kNoAllocMapOffset (SX_NOALLOC_MAX_TILES int2 shared by the classes).
+constexpr int kNoAllocDevices = 64;
+constexpr int64_t kNoAllocAdvOffset = 256;
+constexpr int64_t kNoAllocMapOffset = 8192;
+static_assert(kNoAllocAdvOffset + 4 * 4 * SX_NOALLOC_MAX_GRIDS <= kNoAllocMapOffset,
+              "advance lists fit below the tile maps");
+// The address of the scratch array on `device` (the current device),
+// looked up on the first call for that device and kept.
+hipError_t noalloc_scratch_init(int device, void **out);
+// Tables of one launch class, by value: grids slot[0..n) (caller order),
+// their tiles from first[g] (first[n] = the class's tiles), written at tile
+// map entry map_first; clear_done zeroes the completion counter.
+struct NoAllocList {
+  int32_t n, cls, map_first, clear_done;
+  int32_t slot[SX_NOALLOC_MAX_GRIDS];
+  int32_t first[SX_NOALLOC_MAX_GRIDS + 1];
+};
+hipError_t launch_noalloc_tables(uint8_t *base, const NoAllocList &L, hipStream_t s);
 hipError_t launch_set_remaining(GridDev *table, const int32_t *slots,
                                 const int32_t *values, int32_t n, int32_t add,
                                 hipStream_t s);

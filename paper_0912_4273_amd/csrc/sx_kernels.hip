@@ -11,6 +11,7 @@
 //   and the in-word / m-bit loads are fully coalesced, and the gathers of a
 //   wave hit the few cache lines of the tile's Hilbert neighbourhood;
 //   gather lists per (vertex, bin) as 32-bit in-words [tile][K][64].
+#include <mutex>
 #include <utility>
 
 #include "sx.h"
@@ -1489,6 +1490,62 @@ __global__ void k_reset_ctl(GridDev *gp) {
 static inline unsigned blocks_for(int64_t n, int t) {
   return (unsigned)((n + t - 1) / t);
 }
+
+// ------------------------------------------------ no-allocation steps ---
+// sx_step_noalloc keeps its launch tables (per launch class: the tile map
+// and the list of grids to advance) and its completion counter in one
+// file-scope device array, so that a step allocates nothing.  Each device
+// holds its own copy of the array; host code never passes `scratch` itself
+// to a kernel, only the device address looked up once per device.
+constexpr int64_t kScratchBytes = kNoAllocMapOffset + 8 * (int64_t)SX_NOALLOC_MAX_TILES;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kNoAllocDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device, void **out) {
+  if (device < 0 || device >= kNoAllocDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+// The tile map of one launch class in the scratch array: tile t of the
+// list goes to grid slot[g], tile t - first[g], for first[g] <= t <
+// first[g+1] (grids in the caller's order); the first n threads also write
+// the list of grids to advance, and thread 0 clears the completion counter
+// when asked (once per call, before the first sweep).
+__global__ void k_noalloc_tables(uint8_t *__restrict__ base, NoAllocList L) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int2 *map = (int2 *)(base + kNoAllocMapOffset) + L.map_first;
+  int32_t *adv = (int32_t *)(base + kNoAllocAdvOffset) + (int64_t)L.cls * SX_NOALLOC_MAX_GRIDS;
+  if (t == 0 && L.clear_done) *(uint32_t *)base = 0u;
+  if (t < L.n) adv[t] = L.slot[t];
+  if (t >= L.first[L.n]) return;
+  int lo = 0, hi = L.n - 1;   // last g with first[g] <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (L.first[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  map[t] = make_int2(L.slot[lo], (int)(t - L.first[lo]));
+}
+
+hipError_t launch_noalloc_tables(uint8_t *base, const NoAllocList &L, hipStream_t s) {
+  const int64_t n = L.first[L.n] > L.n ? L.first[L.n] : L.n;
+  hipLaunchKernelGGL(k_noalloc_tables, dim3(blocks_for(n > 0 ? n : 1, 256)), dim3(256), 0, s,
+                     base, L);
+  return hipGetLastError();
+}
+
 
 hipError_t launch_erev(const GridDev *dg, const GridDev &hg, hipStream_t s) {
   if (hg.n_edges == 0) return hipSuccess;

@@ -28,6 +28,8 @@ SX_FP32_TRANSPORT = 1
 SX_ORDER_GRID = 0
 SX_ORDER_DIRECT_FIRST = 1
 SX_MAX_GRAPH_SWEEPS = 4096
+SX_NOALLOC_MAX_GRIDS = 256
+SX_NOALLOC_MAX_TILES = 131072
 SX_MAX_BINS = 96
 SX_MAX_DEGREE = 127
 SX_TRANSPORT_DCT = 0
@@ -37,7 +39,7 @@ SX_DCT_REF_EDGE = 1
 
 EXPORTED = [
     "sx_init", "sx_finalize", "sx_grid_bytes", "sx_grid_upload",
-    "sx_grid_reset", "sx_grid_restore", "sx_grid_free", "sx_step",
+    "sx_grid_reset", "sx_grid_restore", "sx_grid_free", "sx_step", "sx_step_noalloc",
     "sx_solve", "sx_sync", "sx_read_state", "sx_read_tables",
     "sx_grid_info", "sx_mem_info", "sx_stream", "sx_profile",
     "sx_profile_read", "sx_set_schedule", "sx_get_schedule", "sx_autotune",
@@ -149,6 +151,7 @@ def load(path: Optional[str] = None):
         "sx_grid_restore": (C.c_int, [P, I64, C.POINTER(SxStateIn)]),
         "sx_grid_free": (C.c_int, [P, I64]),
         "sx_step": (C.c_int, [P, P, I32, I32]),
+        "sx_step_noalloc": (C.c_int, [P, P, I32, I32]),
         "sx_solve": (C.c_int, [P, P, I32, P]),
         "sx_sync": (C.c_int, [P]),
         "sx_read_state": (C.c_int, [P, I64, C.POINTER(SxStateOut)]),
@@ -357,6 +360,11 @@ def sx_step(ctx, ids: Sequence[int], n_sweeps: int) -> None:
     _check(ctx, load().sx_step(ctx, _ptr(a), int(a.shape[0]), int(n_sweeps)))
 
 
+def sx_step_noalloc(ctx, ids: Sequence[int], n_sweeps: int) -> None:
+    a = np.ascontiguousarray(ids, np.int64)
+    _check(ctx, load().sx_step_noalloc(ctx, _ptr(a), int(a.shape[0]), int(n_sweeps)))
+
+
 def sx_solve(ctx, ids: Sequence[int], n_sweeps) -> None:
     a = np.ascontiguousarray(ids, np.int64)
     s = np.broadcast_to(np.asarray(n_sweeps, np.int32), a.shape).copy()
@@ -546,6 +554,10 @@ class Context:
 
     def step(self, ids, n_sweeps):
         sx_step(self.h, ids, n_sweeps)
+
+    def step_noalloc(self, ids, n_sweeps):
+        """sx_step with no device allocation (static scratch tables)."""
+        sx_step_noalloc(self.h, ids, n_sweeps)
 
     def solve(self, ids, n_sweeps):
         sx_solve(self.h, ids, n_sweeps)
