@@ -27,7 +27,8 @@ constexpr uint64_t kEmptyWord = 0x7FFFFFFFFFFFFFFFull;  // 7 x 511
 //
 // In-word of a (vertex, bin) pair (uint64): which neighbours send this bin
 // here.  Bits 9e..9e+8 (e = 0..6) hold the e-th sender, ascending sender
-// id, as a halo index (or row slot in a direct tile); 511 = none.
+// id, as a halo index (or row slot in a direct tile); 511 = none.  Bit 63
+// is set when the pair also has records (below).
 // Records (uint32, grouped by (tile, bin), sorted by bin then lane) carry
 // what does not fit: senders beyond the seventh, then the vertex's shares of
 // source emission for the bin.  Record = lane << 26 | (bin mod BB) << 24 |

@@ -70,6 +70,48 @@ __device__ __forceinline__ P mul_rn(P a, P b) {
   return a * b;
 }
 
+// DPP lane moves (GFX9 controls): row_shr:n within rows of 16 lanes, the
+// broadcast of lane 15 (31) of a row to the next rows, and a shift of the
+// whole wave by one lane towards lane 0.  Lanes with no source (or outside
+// row_mask) keep `old`.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114,
+              kDppRowShr8 = 0x118, kDppBcast15 = 0x142, kDppBcast31 = 0x143,
+              kDppWaveShl1 = 0x130;
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i32(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS, typename P>
+__device__ __forceinline__ P dpp_val(P v) {
+  if constexpr (sizeof(P) == 8) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)dpp_i32<CTRL, ROWS>(0, (int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)dpp_i32<CTRL, ROWS>(0, (int)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(P, ((uint64_t)hi << 32) | lo);
+  } else {
+    return __builtin_bit_cast(P, dpp_i32<CTRL, ROWS>(0, __builtin_bit_cast(int, v)));
+  }
+}
+// Inclusive scan of v over runs of equal key (keys ascending along the
+// lanes, so a run is contiguous): row-local steps 1, 2, 4, 8, then the rows'
+// last lanes carried into the following rows.  A lane adds a source only
+// when the source lane carries the same key, so sums never cross runs.
+template <typename P>
+__device__ __forceinline__ void seg_scan(P &v, int key) {
+  auto step = [&](auto ctrl, auto rows) {
+    constexpr int C = decltype(ctrl)::value, R = decltype(rows)::value;
+    const int ks = dpp_i32<C, R>(-2000, key);
+    const P vs = dpp_val<C, R>(v);
+    if (ks == key) v += vs;
+  };
+  step(std::integral_constant<int, kDppRowShr1>{}, std::integral_constant<int, 0xF>{});
+  step(std::integral_constant<int, kDppRowShr2>{}, std::integral_constant<int, 0xF>{});
+  step(std::integral_constant<int, kDppRowShr4>{}, std::integral_constant<int, 0xF>{});
+  step(std::integral_constant<int, kDppRowShr8>{}, std::integral_constant<int, 0xF>{});
+  step(std::integral_constant<int, kDppBcast15>{}, std::integral_constant<int, 0xA>{});
+  step(std::integral_constant<int, kDppBcast31>{}, std::integral_constant<int, 0xC>{});
+}
+
 __device__ __forceinline__ bool fwd_selects(uint32_t f, uint32_t slot) {
   return ((f & 127u) == slot) | (((f >> 7) & 127u) == slot) |
          (((f >> 14) & 127u) == slot);
@@ -395,8 +437,14 @@ __global__ void k_inlist_fill(const GridDev *__restrict__ gp) {
       for (; e < re; ++e)
         if (sel_bit(g, e, k)) take((uint32_t)sender_index(g, direct, e, rb));
       // source shares come after the transported photons of the bin
+      bool recs = c > kWordEntries;
       for (int q = g.em_ptr[j]; q < g.em_ptr[j + 1]; ++q)
-        if (g.em_k[q] == k && rp < g.rec_cap) g.rec[rp++] = lbits | kRecEmission | (uint32_t)q;
+        if (g.em_k[q] == k) {
+          recs = true;
+          if (rp < g.rec_cap) g.rec[rp++] = lbits | kRecEmission | (uint32_t)q;
+        }
+      // bit 63: this (vertex, bin) has records to collect
+      if (recs) w |= 1ull << 63;
     }
     out[(int64_t)lane * g.bb] = w;
   }
@@ -985,6 +1033,13 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
         acc[b] = a;
       }
     }
+    // The block's records (senders beyond an in-word's seventh, then source
+    // shares), sorted by bin then receiver: lane r fetches record r's
+    // photons, runs of one receiver and bin are summed by a segmented scan
+    // across lanes (DPP, no LDS), and the last lane of each run hands the
+    // sum over through LDS.  With at most 64 records, only receivers whose
+    // in-word flags records (bit 63) read the hand-over slots, so they need
+    // no clearing; a larger block clears them for every 64.
     const int nrec = __builtin_amdgcn_readfirstlane(rn[slot]);
     for (int c0 = 0; c0 < nrec; c0 += 64) {
       const uint32_t r = lane >= nrec - c0 ? ~0u
@@ -1005,25 +1060,23 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
           v = mul_rn(((const SX_G P *)oin)[blk(src, kb) * BB + rb_], tin[src]);
         }
       }
-      const int knext = __shfl_down(key, 1);
-      if (__ballot(has && lane < 63 && knext == key)) {
-        // a receiver with several records in one bin: segmented scan
+      const int knext = dpp_i32<kDppWaveShl1, 0xF>(-3000, key);
+      if (__ballot(has && knext == key)) seg_scan<P>(v, key);
+      const bool many = nrec > 64;
+      if (many) *(volatile SX_L V *)(xchg + lane * BB) = V(0);
+      __builtin_amdgcn_wave_barrier();
+      if (has && knext != key) xchg[(int)(r >> 26) * BB + rb_] = v;
+      __builtin_amdgcn_wave_barrier();
+      uint32_t fl = 0;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-          const P vo = __shfl_up(v, off);
-          const int ko = __shfl_up(key, off);
-          if (lane >= off && ko == key) v += vo;
-        }
+      for (int b = 0; b < BB; ++b) fl |= (uint32_t)(wq[slot][b] >> 63) << b;
+      if (many) fl = (1u << BB) - 1u;
+      if (fl) {
+        const V got = *(volatile SX_L V *)(xchg + lane * BB);
+#pragma unroll
+        for (int b = 0; b < BB; ++b)
+          if ((fl >> b) & 1u) acc[b] += got[b];
       }
-      // hand-over slot of (receiver lane, bin in block): lane * BB + bin
-      *(volatile SX_L V *)(xchg + lane * BB) = V(0);
-      __builtin_amdgcn_wave_barrier();
-      if (has && (lane == 63 || knext != key))
-        xchg[(int)(r >> 26) * BB + rb_] = v;
-      __builtin_amdgcn_wave_barrier();
-      const V got = *(volatile SX_L V *)(xchg + lane * BB);
-#pragma unroll
-      for (int b = 0; b < BB; ++b) acc[b] += got[b];
       __builtin_amdgcn_wave_barrier();
     }
     __builtin_amdgcn_wave_barrier();
