@@ -26,6 +26,16 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, GB/s
 
 
+def _analytic():
+    """The analytic references of the tests (front laws, equilibrium
+    profiles), imported from tests/analytic.py."""
+    p = os.path.join(ROOT, "tests")
+    if p not in sys.path:
+        sys.path.insert(0, p)
+    import analytic
+    return analytic
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -126,14 +136,16 @@ def shadow_leg(ctx, w, log, profile):
     rperp = np.hypot(p[:, 1] - cy, p[:, 2] - m["clump_c_kpc"][2])
     inclump = np.sum((p - np.array(m["clump_c_kpc"])) ** 2, axis=1) < m["clump_r_kpc"] ** 2
     x = st["x"]
+    A = _analytic()
     lit = m["clump_c_kpc"][0] - m["clump_r_kpc"]
-    ax = inclump & (rperp < 0.25) & (x > 0.5)
-    depth = float(p[ax, 0].max() - lit) if ax.any() else None
-    back = m["clump_c_kpc"][0] + m["clump_r_kpc"] + 0.2
-    behind = (p[:, 0] > back) & (rperp < 0.4)
-    off = (p[:, 0] > back) & (rperp > 1.5)
+    back = m["clump_c_kpc"][0] + m["clump_r_kpc"]
+    axis = (rperp < 0.25) & (p[:, 0] >= lit) & (p[:, 0] <= back)
+    depth = float(A.half_crossing(p[axis, 0] - lit, x[axis], 0.05))
+    behind = (p[:, 0] > back) & (p[:, 0] < back + 0.3) & (rperp < 0.25)
+    off = (p[:, 0] > back) & (p[:, 0] < back + 0.3) & (rperp > 1.5)
     n_c = m["n_H"] * m["contrast"]
     l_s = m["flux"] / (G.ALPHA_B * n_c * n_c) / kpc
+    z_ode = A.slab_front(m["flux"], n_c, w.sigma, w.alpha_B) / kpc
     tl = st["tallies"]
     kern = pr["total_ms"] / max(pr["launches"], 1)
     upd = w.n * w.k * w.n_sweeps
@@ -144,12 +156,13 @@ def shadow_leg(ctx, w, log, profile):
                                    / (kern * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         device_bytes=info["bytes"],
         clump_axis_depth_kpc=depth, stromgren_length_1d_kpc=l_s,
-        x_behind_clump=float(x[behind].mean()), x_off_shadow=float(x[off].mean()),
+        clump_depth_over_1d_equilibrium_profile=round(depth / z_ode, 4),
+        x_axis_behind_clump=float(x[behind].mean()), x_off_shadow=float(x[off].mean()),
         conservation_residual=abs(tl["emitted"] - tl["absorbed"] - tl["escaped"]
                                   - tl["in_flight"]) / tl["emitted"])
     log(f"shadow: {res['value']:.3e} updates/s, sweep {1e3 * kern:.1f} us, depth "
-        f"{depth} kpc (1-D {l_s:.3f}), behind {res['x_behind_clump']:.3f} off "
-        f"{res['x_off_shadow']:.3f}")
+        f"{depth:.3f} kpc (1-D profile {z_ode:.3f}), axis behind {res['x_axis_behind_clump']:.3f} "
+        f"off {res['x_off_shadow']:.3f}")
     return res
 
 
@@ -232,9 +245,28 @@ def rotation_leg(ctx, w, every: int, log):
         t_rot += time.perf_counter() - t1
     st = ctx.state(gid, nin=False)
     el = time.perf_counter() - t0
-    ctx.free(gid)
     r_s = (3 * w.meta["rate"] / (4 * math.pi * w.alpha_B * w.meta["n_H"] ** 2)) ** (1 / 3)
     t_rec = 1.0 / (w.alpha_B * w.meta["n_H"])
+    # the front law over time (untimed repeat of the same rotations, the
+    # ionised-volume radius every 50 sweeps) and the equilibrium profile
+    A = _analytic()
+    ctx.reset(gid)
+    dev, done = [], 0
+    for i in range(n_rot):
+        n = min(every, w.n_sweeps - done)
+        ctx.step([gid], n)
+        done += n
+        ctx.rotate(gid, Rs[i])
+        if done % 50 == 0 and done * w.dt >= 100 * 3.15576e13:
+            xr = ctx.state(gid, nin=False)["x"]
+            dev.append(abs(A.ionised_volume_radius(w.volume, xr)
+                           / A.front_radius(done * w.dt, r_s, t_rec) - 1.0))
+    ctx.free(gid)
+    c = w.pos[w.src_vertex[0]]
+    r = np.linalg.norm(w.pos - c, axis=1)
+    shell = 1.237 * (w.box ** 3 / w.n) ** (1.0 / 3.0)
+    r_half = A.half_crossing(r, st["x"], shell, exclude=w.src_vertex[0])
+    r_ode = A.inner_profile_front(w.meta["rate"], w.meta["n_H"], w.sigma, w.alpha_B)
     rv = (3 / (4 * math.pi) * float(np.sum(w.volume * st["x"]))) ** (1 / 3)
     tl = st["tallies"]
     res = dict(value=w.n * w.k * w.n_sweeps / el, unit="vertex·direction updates/s",
@@ -242,6 +274,8 @@ def rotation_leg(ctx, w, every: int, log):
                ms_per_rotation=1e3 * t_rot / n_rot,
                front_radius_over_analytic=round(
                    rv / (r_s * (1 - math.exp(-w.n_sweeps * w.dt / t_rec)) ** (1 / 3)), 4),
+               front_law_max_dev_from_100myr=round(max(dev), 4) if dev else None,
+               inner_profile_half_crossing_over_ode=round(r_half / r_ode, 4),
                conservation_residual=abs(tl["emitted"] - tl["absorbed"] - tl["escaped"]
                                          - tl["in_flight"]) / tl["emitted"])
     log(f"rotating every {every}: {res['value']:.3e} updates/s, "
@@ -413,19 +447,125 @@ def regrid_leg(ctx, w, passes: int, n_min: int, tau_remove: float, log, prof):
     return res
 
 
-def cpu_baseline(w, sweeps: int):
-    """The FP64 oracle (single thread) on the same grid, from the initial
-    state, for a bounded number of sweeps."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, sweeps: int, sweeps_mt: int):
+    """The FP64 oracle on the same grid from the initial state, for a bounded
+    number of sweeps: sequential (one thread, the parity reference) and its
+    pull form on all the host cores this process may use (at most 16, the
+    GPU machine's share)."""
     from oracle import Oracle
     o = Oracle(w)
     t0 = time.perf_counter()
     o.run(sweeps)
-    dt = time.perf_counter() - t0
-    return dict(value=w.n * w.k * sweeps / dt, unit="vertex·direction updates/s",
-                cores=1, kind="oracle",
-                sample=f"{sweeps} sweeps of the same {w.n}-vertex, {w.k}-bin grid "
-                       f"from the neutral initial state, FP64, one thread "
-                       f"({dt:.1f} s)")
+    dt1 = time.perf_counter() - t0
+    threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                         else (os.cpu_count() or 1)))
+    om = Oracle(w)
+    om.run_threads(1, threads)       # builds its sender lists
+    t0 = time.perf_counter()
+    om.run_threads(sweeps_mt, threads)
+    dtm = time.perf_counter() - t0
+    return dict(value=w.n * w.k * sweeps_mt / dtm, unit="vertex·direction updates/s",
+                cores=threads, kind="oracle",
+                sample=f"{sweeps_mt} sweeps of the same {w.n}-vertex, {w.k}-bin grid after one "
+                       f"from the neutral initial state, FP64, pull form on {threads} threads "
+                       f"({dtm:.1f} s)",
+                cpu_model=cpu_model(),
+                single_thread=dict(value=w.n * w.k * sweeps / dt1, cores=1,
+                                   sample=f"{sweeps} sweeps from the neutral initial state, "
+                                          f"sequential oracle ({dt1:.1f} s)"))
+
+
+def _err_stats(got, ref, atol):
+    """Max and 99th percentile of |got - ref| / (|ref| + atol)."""
+    import numpy as np
+    got = np.asarray(got, np.float64).ravel()
+    ref = np.asarray(ref, np.float64).ravel()
+    if got.size == 0:
+        return None
+    e = np.abs(got - ref) / (np.abs(ref) + atol)
+    return dict(max=float(e.max()), p99=float(np.quantile(e, 0.99)))
+
+
+def precision_stats(got, ref, unit, n_sub_atol=True):
+    """Per-result error of a GPU state against the oracle: x, y, y where y
+    >= 1e-6 (what FP64 chemistry protects), the photon field (relative to
+    the value plus 1e-9 of a photon unit, below which FP32 underflow makes
+    relative error meaningless) and the tallies."""
+    import numpy as np
+    msk = ref["y"] >= 1e-6
+    out = dict(x=_err_stats(got["x"], ref["x"], 1e-12), y=_err_stats(got["y"], ref["y"], 1e-12),
+               y_ge_1e6=_err_stats(got["y"][msk], ref["y"][msk], 0.0),
+               photons=_err_stats(got["photons"], ref["photons"], 1e-9 * unit))
+    tl = {}
+    for k in ("emitted", "absorbed", "escaped", "in_flight"):
+        a, b = got["tallies"][k], ref["tallies"][k]
+        tl[k] = abs(a - b) / max(abs(b), 1e-300)
+    out["tallies_rel"] = tl
+    return out
+
+
+def precision_leg(ctx, w2, log):
+    """Error against the FP64 oracle, per result: the 4096-vertex Stromgren
+    test whole (200 sweeps) in both precisions, and one sweep of the
+    262144-vertex benchmark grid from the GPU's state after 300 sweeps.
+    Also the plain FP64 throughput of the small test (the launch-bound
+    configuration) with graph replays and with single launches."""
+    from paper_0912_4273_amd import gridgen as G
+    from oracle import Oracle
+    w1 = G.config1()
+    ora = Oracle(w1)
+    ora.run(w1.n_sweeps)
+    ref1 = ora.state()
+    ora.close()
+    out = dict(stromgren_4096_200_sweeps={}, stromgren_262144_one_sweep={})
+    for prec, name in ((G.SX_FP64, "fp64"), (G.SX_FP32_TRANSPORT, "fp32")):
+        gid = ctx.upload(G.with_(w1, precision=prec))
+        ctx.solve([gid], w1.n_sweeps)
+        got = ctx.state(gid, photons=True)
+        unit = ctx.info(gid)["photon_unit"]
+        out["stromgren_4096_200_sweeps"][name] = precision_stats(got, ref1, unit)
+        # throughput of the small grid: graph replays (default) and single launches
+        for gs in (50, 0):
+            ctx.set_schedule([gid], graph_sweeps=gs)
+            ctx.reset(gid)
+            ctx.solve([gid], 20)
+            ctx.reset(gid)
+            ctx.sync()
+            t0 = time.perf_counter()
+            ctx.solve([gid], w1.n_sweeps)
+            el = time.perf_counter() - t0
+            out["stromgren_4096_200_sweeps"][name][f"updates_per_s_graph{gs}"] = \
+                w1.n * w1.k * w1.n_sweeps / el
+        ctx.free(gid)
+    # one sweep at the benchmark's size, both precisions, from the GPU state
+    ora2 = Oracle(w2)
+    for prec, name in ((G.SX_FP32_TRANSPORT, "fp32"), (G.SX_FP64, "fp64")):
+        gid = ctx.upload(G.with_(w2, precision=prec))
+        ctx.solve([gid], 300)
+        s1 = ctx.state(gid, photons=True)
+        ctx.solve([gid], 1)
+        s2 = ctx.state(gid, photons=True)
+        unit = ctx.info(gid)["photon_unit"]
+        ctx.free(gid)
+        ora2.set_state(y=s1["y"], photons=s1["photons"], tallies=s1["tallies"])
+        ora2.run(1)
+        out["stromgren_262144_one_sweep"][name] = precision_stats(s2, ora2.state(), unit)
+    ora2.close()
+    f1 = out["stromgren_4096_200_sweeps"]
+    log(f"precision: 4096 whole fp32 x max {f1['fp32']['x']['max']:.2e}, fp64 x max "
+        f"{f1['fp64']['x']['max']:.2e}; small fp64 {f1['fp64']['updates_per_s_graph50']:.3e} "
+        f"updates/s (graphs) / {f1['fp64']['updates_per_s_graph0']:.3e} (single launches)")
+    return out
 
 
 def main():
@@ -437,19 +577,21 @@ def main():
     ap.add_argument("--bins", type=int, default=84)
     ap.add_argument("--sweeps", type=int, default=1000)
     ap.add_argument("--cpu-sweeps", type=int, default=25)
+    ap.add_argument("--cpu-sweeps-mt", type=int, default=100,
+                    help="sweeps of the all-cores oracle baseline")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the per-result error statement against the oracle")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--batch-grids", type=int, default=64,
                     help="grids in the batched leg (0 = skip it)")
     ap.add_argument("--batch-sweeps", type=int, default=200)
     ap.add_argument("--autotune-trials", type=int, default=2)
-    ap.add_argument("--serve-seconds", type=float, default=20.0,
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="arrival window of the serving leg (0 = skip it)")
     ap.add_argument("--serve-rate", type=float, default=20.0)
-    ap.add_argument("--serve-max-n", type=int, default=524288,
-                    help="largest pool grid (the full request range goes to 2e6)")
-    ap.add_argument("--serve-full", action="store_true",
-                    help="pool up to 2e6 vertices (building it takes minutes)")
+    ap.add_argument("--serve-max-n", type=int, default=2000000,
+                    help="largest pool grid (the request range is [1e4, 2e6])")
     ap.add_argument("--serve-round", type=int, default=50)
     ap.add_argument("--serve-prep-threads", type=int, default=12)
     ap.add_argument("--serve-only", action="store_true",
@@ -488,8 +630,6 @@ def main():
     if args.serve_only:
         args.batch_grids = 0
         args.shadow_n = 0
-    if args.serve_full:
-        args.serve_max_n = 2000000
     pool_sizes = (G.serve_pool_sizes(1e4, args.serve_max_n, 8)
                   if args.serve_seconds > 0 else [])
     t = time.perf_counter()
@@ -661,6 +801,11 @@ def main():
     if shadow is not None:
         shadowed = shadow_leg(ctx, shadow, log, prof)
 
+    precision = None
+    if not args.no_precision:
+        precision = precision_leg(ctx, w, log)
+        ctx.set_schedule([], graph_sweeps=args.graph_sweeps)
+
     if pool:
         served = serve_leg(ctx, pool, args, log)
         log(f"served: {served['finished']}/{served['requests']} requests, "
@@ -698,7 +843,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         log(f"cpu oracle: {args.cpu_sweeps} sweeps")
-        cpu = cpu_baseline(G.with_(w, precision=G.SX_FP64), args.cpu_sweeps)
+        cpu = cpu_baseline(G.with_(w, precision=G.SX_FP64), args.cpu_sweeps, args.cpu_sweeps_mt)
 
     ctx.close()
     out = {
@@ -730,6 +875,7 @@ def main():
         "roofline": roof,
         "algorithmic_bytes_per_update": bpu,
         "accuracy": acc,
+        "precision_vs_oracle": precision,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -22,7 +22,7 @@ def build_oracle(force: bool = False, src: str = _SRC, out: str = None) -> str:
             os.path.getmtime(out) < os.path.getmtime(src):
         tmp = out + ".tmp"
         subprocess.check_call([
-            "gcc", "-O2", "-std=c99", "-fPIC", "-shared",
+            "gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
             "-ffp-contract=off", "-fno-fast-math", "-fexcess-precision=standard",
             "-Wall", "-I", _HERE, "-o", tmp, src, "-lm"])
         os.replace(tmp, out)
@@ -49,6 +49,8 @@ def _load(path=None):
             C.c_double, C.c_double, C.c_int32]
         lib.ora_run.restype = C.c_int
         lib.ora_run.argtypes = [P, C.c_int32, P]
+        lib.ora_run_threads.restype = C.c_int
+        lib.ora_run_threads.argtypes = [P, C.c_int32, C.c_int32]
         lib.ora_get_state.restype = None
         lib.ora_get_state.argtypes = [P, P, P, P, P, P]
         lib.ora_set_state.restype = None
@@ -145,6 +147,12 @@ class Oracle:
         hist = np.zeros((n_sweeps, 4)) if history else None
         self._lib.ora_run(self._h, int(n_sweeps), _p(hist))
         return hist
+
+    def run_threads(self, n_sweeps: int, threads: int):
+        """Timing-only pull form of run() on `threads` OpenMP threads
+        (direction-conserving, on the spot)."""
+        if self._lib.ora_run_threads(self._h, int(n_sweeps), int(threads)) != 0:
+            raise ValueError("oracle: threaded run covers direction-conserving, on-the-spot grids")
 
     def state(self):
         n, k = self.n, self.k

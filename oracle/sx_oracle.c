@@ -64,6 +64,10 @@ struct ora_grid {
      * alpha_A == 0 (on the spot). */
     double alpha_A;
     double *D;           /* [N] recombination photons to send next sweep */
+    /* Timing-only pull form (ora_run_threads): senders of each receiver,
+     * built on first use from the current routing; NULL when stale. */
+    int64_t *pull_ptr;
+    int32_t *pull_from, *pull_bin;
 };
 
 static void *xcalloc(size_t n, size_t s) {
@@ -208,8 +212,14 @@ double ora_chem_cell(double y, double n_in, double dt, double nHV, double tau,
 /* The routing of direction-conserving transport for the current bins:
  * which neighbours each bin of each vertex goes to, and the bin of every
  * directed edge. */
+static void drop_pull(ora_grid *g) {
+    free(g->pull_ptr); free(g->pull_from); free(g->pull_bin);
+    g->pull_ptr = NULL; g->pull_from = NULL; g->pull_bin = NULL;
+}
+
 static void build_routing(ora_grid *g) {
     int64_t n = g->n, K = g->K, E = g->n_edges;
+    drop_pull(g);
     int max_per_bin = g->mpb;
     /* Direction-bin -> neighbour selection of direction-conserving transport
      * (Sect. 2.2.3): every bin goes to the mpb (= dimension d = 3) most
@@ -699,6 +709,138 @@ void ora_get_ballistic(const ora_grid *g, int32_t *bsel, int32_t *bm) {
     if (bm) memcpy(bm, g->bm, (size_t)g->n_edges * sizeof(int32_t));
 }
 
+/* ---------------------------------------------------------------------- */
+/* Timing only: the CPU baseline on all cores.  The same sweeps of
+ * direction-conserving transport with on-the-spot chemistry as sweep(), in
+ * pull form so that every vertex is written by one thread: each receiver j
+ * sums, for every bin, what its senders hand it, in ascending sender id (the
+ * order sweep() adds them in), then its source shares, then takes its
+ * chemistry and outgoing step.  Only the tallies are summed in another order
+ * (per thread, then over threads).  Combined transport and diffuse radiation
+ * are not covered (returns -1). */
+typedef struct {
+    int64_t *ptr;    /* [N+1] */
+    int32_t *from;   /* sender */
+    int32_t *bin;    /* bin */
+} ora_inlist;
+
+static ora_inlist build_inlist(const ora_grid *g) {
+    ora_inlist L;
+    int64_t n = g->n, K = g->K;
+    L.ptr = (int64_t *)xcalloc(n + 1, sizeof(int64_t));
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t k = 0; k < K; k++)
+            for (int t = 0; t < g->m[i * K + k]; t++)
+                L.ptr[g->sel[(i * K + k) * g->mpb + t] + 1]++;
+    for (int64_t j = 0; j < n; j++) L.ptr[j + 1] += L.ptr[j];
+    int64_t *fill = (int64_t *)xcalloc(n, sizeof(int64_t));
+    L.from = (int32_t *)xcalloc(L.ptr[n], sizeof(int32_t));
+    L.bin = (int32_t *)xcalloc(L.ptr[n], sizeof(int32_t));
+    /* senders in ascending id, so each (j, k) sums in sweep()'s order */
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t k = 0; k < K; k++)
+            for (int t = 0; t < g->m[i * K + k]; t++) {
+                int32_t j = g->sel[(i * K + k) * g->mpb + t];
+                int64_t q = L.ptr[j] + fill[j]++;
+                L.from[q] = (int32_t)i;
+                L.bin[q] = (int32_t)k;
+            }
+    free(fill);
+    return L;
+}
+
+int ora_run_threads(ora_grid *g, int32_t n_sweeps, int32_t threads) {
+    if (g->combined || g->alpha_A > 0.0 || threads < 1) return -1;
+    int64_t n = g->n, K = g->K;
+    if (!g->pull_ptr) {
+        ora_inlist B = build_inlist(g);
+        g->pull_ptr = B.ptr; g->pull_from = B.from; g->pull_bin = B.bin;
+    }
+    ora_inlist L = {g->pull_ptr, g->pull_from, g->pull_bin};
+    /* source shares per receiver: (bin, amount), in source order */
+    int64_t *sp = (int64_t *)xcalloc(n + 1, sizeof(int64_t));
+    for (int32_t s = 0; s < g->n_src; s++) {
+        int64_t v = g->src_v[s], b = g->ptr[v], deg = g->ptr[v + 1] - b;
+        const double *d = &g->src_dir[3 * s];
+        if (d[0] == 0.0 && d[1] == 0.0 && d[2] == 0.0) {
+            for (int64_t e = b; e < b + deg; e++) sp[g->nbr[e] + 1]++;
+        } else {
+            int32_t slots[16];
+            int c = select_slots(g, v, d, slots);
+            for (int t = 0; t < c; t++) sp[g->nbr[b + slots[t]] + 1]++;
+        }
+    }
+    for (int64_t j = 0; j < n; j++) sp[j + 1] += sp[j];
+    int64_t *sf = (int64_t *)xcalloc(n, sizeof(int64_t));
+    int32_t *sk = (int32_t *)xcalloc(sp[n] + 1, sizeof(int32_t));
+    double *sa = (double *)xcalloc(sp[n] + 1, sizeof(double));
+    double esc_src = 0.0;
+    for (int32_t s = 0; s < g->n_src; s++) {
+        int64_t v = g->src_v[s], b = g->ptr[v], deg = g->ptr[v + 1] - b;
+        double E = g->src_rate[s] * g->dt;
+        const double *d = &g->src_dir[3 * s];
+        if (d[0] == 0.0 && d[1] == 0.0 && d[2] == 0.0) {
+            if (deg == 0) { esc_src += E; continue; }
+            for (int64_t e = b; e < b + deg; e++) {
+                int64_t q = sp[g->nbr[e]] + sf[g->nbr[e]]++;
+                sk[q] = g->ebin[e];
+                sa[q] = E / (double)deg;
+            }
+        } else {
+            int32_t slots[16];
+            int c = select_slots(g, v, d, slots);
+            if (c == 0) { esc_src += E; continue; }
+            int32_t kb = nearest_bin(g, d);
+            for (int t = 0; t < c; t++) {
+                int32_t j = g->nbr[b + slots[t]];
+                int64_t q = sp[j] + sf[j]++;
+                sk[q] = kb;
+                sa[q] = E / (double)c;
+            }
+        }
+    }
+    double e_sweep = 0.0;
+    for (int32_t s = 0; s < g->n_src; s++) e_sweep += g->src_rate[s] * g->dt;
+    double *On = (double *)xcalloc(n * K, sizeof(double));
+    for (int32_t s = 0; s < n_sweeps; s++) {
+        double absorbed = 0.0, escaped = 0.0, fly = 0.0;
+#pragma omp parallel for num_threads(threads) schedule(static) reduction(+ : absorbed, escaped, fly)
+        for (int64_t j = 0; j < n; j++) {
+            double *I = &g->I[j * K];
+            for (int64_t k = 0; k < K; k++) I[k] = 0.0;
+            for (int64_t q = L.ptr[j]; q < L.ptr[j + 1]; q++)
+                I[L.bin[q]] += g->O[(int64_t)L.from[q] * K + L.bin[q]];
+            for (int64_t q = sp[j]; q < sp[j + 1]; q++) I[sk[q]] += sa[q];
+            double nin = 0.0;
+            for (int64_t k = 0; k < K; k++) nin += I[k];
+            g->nin[j] = nin;
+            double A, T, R;
+            g->y[j] = chem(g->y[j], nin, g->dt, g->nH[j] * g->vol[j], g->tau[j],
+                           g->alpha_B * g->nH[j], g->n_sub, &A, &T, &R);
+            absorbed += A;
+            for (int64_t k = 0; k < K; k++) {
+                double out = I[k] * T;
+                int32_t mm = g->m[j * K + k];
+                if (mm > 0) {
+                    On[j * K + k] = out / (double)mm;
+                    fly += out;
+                } else {
+                    On[j * K + k] = 0.0;
+                    escaped += out;
+                }
+            }
+        }
+        double *t = g->O; g->O = On; On = t;
+        g->emitted += e_sweep;
+        g->absorbed += absorbed;
+        g->escaped += escaped + esc_src;
+        g->in_flight = fly;
+        g->sweeps += 1.0;
+    }
+    free(On); free(sp); free(sf); free(sk); free(sa);
+    return 0;
+}
+
 int ora_run(ora_grid *g, int32_t n_sweeps, double *history) {
     for (int32_t s = 0; s < n_sweeps; s++) {
         if (g->combined) sweep_combined(g);
@@ -826,5 +968,6 @@ void ora_free(ora_grid *g) {
     free(g->src_dir); free(g->y); free(g->O); free(g->I); free(g->nin);
     free(g->rev); free(g->bsel); free(g->bm); free(g->Oe); free(g->Ie);
     free(g->layout); free(g->mode); free(g->D);
+    drop_pull(g);
     free(g);
 }

@@ -44,6 +44,13 @@ ora_grid *ora_create(int64_t n, const double *pos, const int64_t *nbr_ptr,
  * cumulative tallies emitted, absorbed, escaped, in_flight after each sweep. */
 int ora_run(ora_grid *g, int32_t n_sweeps, double *history);
 
+/* Timing only (the CPU baseline on all cores): the same sweeps of
+ * direction-conserving transport with on-the-spot chemistry as ora_run, in
+ * pull form over `threads` OpenMP threads; fields as ora_run, the tallies
+ * summed in another order.  Returns -1 for combined transport or diffuse
+ * radiation. */
+int ora_run_threads(ora_grid *g, int32_t n_sweeps, int32_t threads);
+
 /* Copy out the state.  Any pointer may be NULL.
  *   y, x        [N]   neutral and ionised fraction
  *   photons     [N*K] outgoing photons per selected neighbour, O[j][k]
