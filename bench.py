@@ -534,18 +534,28 @@ def precision_leg(ctx, w2, log):
         got = ctx.state(gid, photons=True)
         unit = ctx.info(gid)["photon_unit"]
         out["stromgren_4096_200_sweeps"][name] = precision_stats(got, ref1, unit)
-        # throughput of the small grid: graph replays (default) and single launches
-        for gs in (50, 0):
-            ctx.set_schedule([gid], graph_sweeps=gs)
+        # throughput of the small grid (64 tiles: one wave per tile leaves
+        # most of the GPU idle): graph replays, single launches, and each
+        # tile's bins split over four waves
+        for label, kw in (("graph50", dict(graph_sweeps=50)),
+                          ("graph0", dict(graph_sweeps=0)),
+                          ("graph50_split4", dict(tiles_per_group=1, work_split=4,
+                                                  graph_sweeps=50))):
+            ctx.set_schedule([gid], **kw)
             ctx.reset(gid)
             ctx.solve([gid], 20)
             ctx.reset(gid)
             ctx.sync()
+            ctx.profile(True)
+            ctx.profile_read()
             t0 = time.perf_counter()
             ctx.solve([gid], w1.n_sweeps)
             el = time.perf_counter() - t0
-            out["stromgren_4096_200_sweeps"][name][f"updates_per_s_graph{gs}"] = \
-                w1.n * w1.k * w1.n_sweeps / el
+            pr = ctx.profile_read()
+            ctx.profile(False)
+            f = out["stromgren_4096_200_sweeps"][name]
+            f[f"updates_per_s_{label}"] = w1.n * w1.k * w1.n_sweeps / el
+            f[f"sweep_us_{label}"] = 1e3 * pr["total_ms"] / max(pr["launches"], 1)
         ctx.free(gid)
     # one sweep at the benchmark's size, both precisions, from the GPU state
     ora2 = Oracle(w2)
@@ -564,7 +574,8 @@ def precision_leg(ctx, w2, log):
     f1 = out["stromgren_4096_200_sweeps"]
     log(f"precision: 4096 whole fp32 x max {f1['fp32']['x']['max']:.2e}, fp64 x max "
         f"{f1['fp64']['x']['max']:.2e}; small fp64 {f1['fp64']['updates_per_s_graph50']:.3e} "
-        f"updates/s (graphs) / {f1['fp64']['updates_per_s_graph0']:.3e} (single launches)")
+        f"updates/s (graphs) / {f1['fp64']['updates_per_s_graph0']:.3e} (single launches) / "
+        f"{f1['fp64']['updates_per_s_graph50_split4']:.3e} (four waves per tile)")
     return out
 
 

@@ -408,6 +408,12 @@ int sx_prepared_free(sx_prepared *p);
  * sum order are fixed), so results are bitwise the same under every
  * schedule.
  *   tiles_per_group  tiles per workgroup: 1, 2 or 4
+ *   work_split       waves per tile: 1, 2 or 4, with tiles_per_group x
+ *                    work_split <= 4 (0 reads as 1).  The waves of a tile
+ *                    split its direction bins into contiguous ranges and
+ *                    one of them runs the chemistry; more, shorter waves
+ *                    fill the GPU better when a launch has few tiles.
+ *                    Combined-transport launches always use 1.
  *   order            SX_ORDER_GRID: grid by grid, each in its internal
  *                    (Hilbert) order; SX_ORDER_DIRECT_FIRST: tiles too large
  *                    for LDS staging first, then the rest
@@ -417,7 +423,7 @@ int sx_prepared_free(sx_prepared *p);
  *   graph_sweeps     > 0: sweeps are launched as replays of one HIP graph of
  *                    that many sweeps (the rest singly); 0: one launch per
  *                    sweep and precision
- * Default {4, SX_ORDER_GRID, 1, 50}. */
+ * Default {4, SX_ORDER_GRID, 1, 50, 1}. */
 #define SX_ORDER_GRID 0
 #define SX_ORDER_DIRECT_FIRST 1
 #define SX_MAX_GRAPH_SWEEPS 4096
@@ -426,6 +432,7 @@ typedef struct sx_schedule {
     int32_t order;
     int32_t xcd_contiguous;
     int32_t graph_sweeps;
+    int32_t work_split;
 } sx_schedule;
 
 /* Schedule for steps over exactly this list of grids, in this order (n = 0:
@@ -442,8 +449,11 @@ int sx_get_schedule(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, sx_schedule *
 /* trials > 0 turns the autotuner on: the first sx_step / sx_solve over a grid
  * list that has no schedule of its own, if it asks for at least 4 x trials x
  * (number of candidates) sweeps, runs `trials` of those sweeps under each
- * candidate schedule (tiles per group 1, 2, 4; XCD-contiguous or not; direct
- * tiles first or not when the list has any), timed with HIP events, and
+ * candidate schedule, timed with HIP events, in two stages: the launch shape
+ * (tiles per group 1, 2, 4 and work split 1, 2, 4, at most 4 waves per
+ * group; 6 candidates) in XCD-contiguous grid order, then for the fastest
+ * shape the other tile orders (XCD round-robin, and direct tiles first when
+ * the list has any; 1 or 3 candidates), and
  * keeps the fastest for that list (graph_sweeps is kept from the default).
  * The sweeps count toward the step; the step synchronises the stream while
  * tuning.  trials = 0 turns it off.  Errors: SX_EINVAL (trials outside

@@ -109,7 +109,7 @@ struct sx_ctx {
   std::string err;
   bool poisoned = false;
   std::vector<Plan *> plans;
-  sx_schedule dflt{4, SX_ORDER_GRID, 1, 50};
+  sx_schedule dflt{4, SX_ORDER_GRID, 1, 50, 1};
   int32_t autotune = 0;
   uint32_t *done = nullptr;   // completion counter of the sweep launches
   // pinned host staging of the routing rebuild: bin directions going in
@@ -1515,8 +1515,12 @@ int sx_grid_free(sx_ctx *ctx, sx_grid_id id) {
 
 namespace {
 
+int split_of(const sx_schedule &s) { return s.work_split > 1 ? s.work_split : 1; }
+
 bool valid_schedule(const sx_schedule &s) {
   return (s.tiles_per_group == 1 || s.tiles_per_group == 2 || s.tiles_per_group == 4) &&
+         (s.work_split >= 0 && s.work_split <= 4 && s.work_split != 3) &&
+         s.tiles_per_group * split_of(s) <= 4 &&
          (s.order == SX_ORDER_GRID || s.order == SX_ORDER_DIRECT_FIRST) &&
          (s.xcd_contiguous == 0 || s.xcd_contiguous == 1) && s.graph_sweeps >= 0 &&
          s.graph_sweeps <= SX_MAX_GRAPH_SWEEPS;
@@ -1547,7 +1551,8 @@ int plan_build(sx_ctx *ctx, Plan *p, const std::vector<Grid *> &gs) {
     if (grp.empty()) continue;
     sx::SweepLaunch l{};
     l.done = ctx->done;
-    l.tpb = tr ? 1 : p->sched.tiles_per_group;
+    l.split = tr ? 1 : split_of(p->sched);
+    l.tpb = tr ? 1 : p->sched.tiles_per_group * l.split;
     l.xcd_remap = p->sched.xcd_contiguous;
     l.precision = prec;
     l.transport = tr;
@@ -1686,15 +1691,13 @@ int autotune(sx_ctx *ctx, Plan *p, const std::vector<Grid *> &gs, int32_t trials
   *used = 0;
   bool any_direct = false;
   for (Grid *g : gs) any_direct = any_direct || g->n_direct > 0;
-  std::vector<sx_schedule> cand;
-  for (int tpb : {4, 2, 1})
-    for (int xcd : {1, 0})
-      for (int order : {SX_ORDER_GRID, SX_ORDER_DIRECT_FIRST}) {
-        if (order == SX_ORDER_DIRECT_FIRST && !any_direct) continue;
-        cand.push_back({tpb, order, xcd, 0});
-      }
+  // Two stages: the launch shape (tiles per group x waves per tile) under
+  // the XCD-contiguous grid order, then the tile order for the best shape.
+  const int shapes[6][2] = {{4, 1}, {2, 1}, {1, 1}, {2, 2}, {1, 2}, {1, 4}};
+  const int n_orders = any_direct ? 4 : 2;
+  const int64_t n_cand = 6 + (n_orders - 1);
   // only when tuning takes at most a quarter of the sweeps asked for
-  if ((int64_t)n_launch < 4 * (int64_t)trials * (int64_t)cand.size()) return SX_OK;
+  if ((int64_t)n_launch < 4 * (int64_t)trials * n_cand) return SX_OK;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev((size_t)trials);
   for (auto &e : ev) {
     HIP_TRY(ctx, hipEventCreate(&e.first));
@@ -1704,9 +1707,9 @@ int autotune(sx_ctx *ctx, Plan *p, const std::vector<Grid *> &gs, int32_t trials
   double best = 1e300;
   sx_schedule best_s = p->sched;
   int rc = SX_OK;
-  for (const sx_schedule &c : cand) {
+  auto time_one = [&](const sx_schedule &c) {
     p->sched = c;
-    if ((rc = plan_build(ctx, p, gs))) break;
+    if ((rc = plan_build(ctx, p, gs))) return;
     std::vector<double> t;
     for (int32_t i = 0; i < trials && rc == SX_OK; ++i) {
       if (hipEventRecord(ev[(size_t)i].first, ctx->stream) != hipSuccess ||
@@ -1714,10 +1717,10 @@ int autotune(sx_ctx *ctx, Plan *p, const std::vector<Grid *> &gs, int32_t trials
           hipEventRecord(ev[(size_t)i].second, ctx->stream) != hipSuccess)
         rc = fail(ctx, SX_EDEVICE, "autotune launch failed");
     }
-    if (rc) break;
+    if (rc) return;
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
       rc = fail(ctx, SX_EDEVICE, "autotune sync failed");
-      break;
+      return;
     }
     for (int32_t i = 0; i < trials; ++i) {
       float ms = 0.0f;
@@ -1732,6 +1735,17 @@ int autotune(sx_ctx *ctx, Plan *p, const std::vector<Grid *> &gs, int32_t trials
       best = v;
       best_s = c;
     }
+  };
+  for (const auto &sh : shapes) {
+    if (rc) break;
+    time_one({sh[0], SX_ORDER_GRID, 1, 0, sh[1]});
+  }
+  const sx_schedule shape = best_s;
+  for (int o = 1; o < n_orders && rc == SX_OK; ++o) {
+    sx_schedule c = shape;
+    c.xcd_contiguous = (o & 1) ? 0 : 1;
+    c.order = (o & 2) ? SX_ORDER_DIRECT_FIRST : SX_ORDER_GRID;
+    time_one(c);
   }
   for (auto &e : ev) {
     (void)hipEventDestroy(e.first);
@@ -1865,7 +1879,8 @@ int sx_step_noalloc(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, int32_t n_swe
     l.n_adv = L.n;
     l.done = (uint32_t *)ctx->scratch;
     l.xcd_remap = ctx->dflt.xcd_contiguous;
-    l.tpb = tr ? 1 : ctx->dflt.tiles_per_group;
+    l.split = tr ? 1 : split_of(ctx->dflt);
+    l.tpb = tr ? 1 : ctx->dflt.tiles_per_group * l.split;
     l.precision = prec;
     l.transport = tr;
     l.nt = plane_bytes <= sx::kLlcBytes;

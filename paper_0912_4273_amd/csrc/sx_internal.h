@@ -196,7 +196,8 @@ struct SweepLaunch {
   int32_t n_adv;
   uint32_t *done;
   int32_t xcd_remap;
-  int32_t tpb, precision;
+  int32_t tpb, precision;   // tpb: waves per workgroup
+  int32_t split;            // waves per tile (1, 2, 4; tpb a multiple)
   int32_t transport;
   int32_t nt;   // in-words loaded non-temporal (the photon planes fit kLlcBytes)
 };

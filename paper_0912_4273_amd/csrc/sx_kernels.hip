@@ -893,11 +893,84 @@ __device__ __forceinline__ void ct_finish(const GridDev *__restrict__ G, int til
   }
 }
 
+// A lane's N_in and escaping photons, summed over the bins in an order that
+// does not depend on how the tile's bin blocks are split over waves: the
+// blocks fall into four groups (group g holds blocks [g KB / 4, (g + 1) KB /
+// 4)), each group is summed bin by bin, and the group sums are added left to
+// right.  A wave that runs groups [g0, g1) keeps the running total of its
+// groups and the sums of its first two (to hand over to the wave that adds
+// them to its own).
+template <typename P>
+struct BinSums {
+  P tot_n = P(0), tot_e = P(0);
+  P cur_n = P(0), cur_e = P(0);
+  P hn0 = P(0), hn1 = P(0), he0 = P(0), he1 = P(0);
+  int g = 0, gi = 0;
+  __device__ __forceinline__ void close() {
+    tot_n += cur_n;
+    tot_e += cur_e;
+    if (gi == 0) {
+      hn0 = cur_n;
+      he0 = cur_e;
+    } else {
+      hn1 = cur_n;
+      he1 = cur_e;
+    }
+    cur_n = P(0);
+    cur_e = P(0);
+    ++g;
+    ++gi;
+  }
+};
+
+// Chemistry and accounting of one lane of a direction-conserving tile after
+// its bins: the backward-Euler update from N_in, T for the next sweep, and
+// the tile's tallies by a fixed butterfly.
+template <typename P>
+__device__ __forceinline__ void dct_finish(const GridDev *__restrict__ G, int tile, int lane,
+                                           P nin_p, P esc_p) {
+  const int j = tile * kTile + lane;
+  const int par = G->parity;
+  double A = 0.0, T = 1.0;
+  const double nin = (double)nin_p;
+  if (j < G->n) {
+    SX_G double *__restrict__ yv = gst(G->y);
+    const double y0 = yv[j];
+    if (!(nin == 0.0 && y0 == 1.0)) {
+      const double yn = chem_step(y0, nin * G->unit, G->dt, gld(G->dtnhv)[j],
+                                  gld(G->tau)[j], gld(G->bcoef)[j], G->n_sub, A, T);
+      yv[j] = yn;
+    }
+    gst(G->nin)[j] = nin * G->unit;
+    gst((P *)G->t[par ^ 1])[j] = (P)T;
+  }
+  A /= G->unit;   // tallies in stored units; scaled back on read
+  double esc = (double)esc_p * T;
+  double fly = (nin - (double)esc_p) * T;
+
+  // Fixed butterfly: every lane ends with the same, order-determined sum.
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    A += __shfl_xor(A, off);
+    esc += __shfl_xor(esc, off);
+    fly += __shfl_xor(fly, off);
+  }
+  if (lane == 0) {
+    SX_G double *t = gst(G->tally) + (int64_t)tile * 3;
+    t[0] += A;
+    t[1] += esc;
+    t[2] = fly;
+  }
+}
+
+// The bins of one tile in blocks [kb0, kb1) (groups [g0, g1) of BinSums):
+// gather, overflow records, outgoing photons; the sums go to bs.
 template <typename P, bool DIRECT, bool CT = false, bool NT = false>
-__device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int tile,
+__device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int tile,
                                            int lane, volatile SX_L P *hl,
-                                           volatile SX_L P *xchg,
-                                           const CtIn<P> &ci = CtIn<P>()) {
+                                           volatile SX_L P *xchg, const CtIn<P> &ci,
+                                           int kb0, int kb1, int g0, int g1,
+                                           BinSums<P> &bs) {
   // hl and xchg carry data between lanes of this wave through LDS.  The
   // accesses are volatile so that the compiler keeps every store and load in
   // program order (it may not forward a lane's own store past another
@@ -921,9 +994,10 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
       gld((const W2 *)(G->inw + ((int64_t)tile * KB * kTile + lane) * BB));
   const SX_G int32_t *__restrict__ rptr = gld(G->rec_ptr) + (int64_t)tile * K * kRecGroups;
   const SX_G uint32_t *__restrict__ rec = gld(G->rec);
-  // first record of every block of the tile, lane kb holding block kb's
+  // first record of every block of the range, lane l holding block kb0 + l's
   // (KB < 64), so that no load inside the block loop waits on another
-  const int rpl = lane <= KB ? rptr[(lane * BB < K ? lane * BB : K) * kRecGroups] : 0;
+  const int kl_ = kb0 + lane;
+  const int rpl = kl_ <= kb1 ? rptr[(kl_ * BB < K ? kl_ * BB : K) * kRecGroups] : 0;
   const SX_G double *__restrict__ ema = gld(G->em_amt);
   // block of (vertex v, block kb)
   auto blk = [&](uint32_t v, int kb) -> uint32_t {
@@ -950,11 +1024,15 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
       for (int b = 0; b < BB; ++b) hl[b * kHaloPlane + kZeroSlot] = P(0);
     }
   }
-  // packed m(j, k), 16 bins per word, consumed 2 bits at a time
-  const SX_G uint32_t *__restrict__ mbp = gld(G->mbits) + (int64_t)tile * G->kw * 64 + lane;
+  // packed m(j, k), 16 bins per word, consumed 2 bits at a time from the
+  // range's first bin
+  const int k0 = kb0 * BB;
+  const SX_G uint32_t *__restrict__ mbp =
+      gld(G->mbits) + ((int64_t)tile * G->kw + (k0 >> 4)) * 64 + lane;
   uint32_t mwv[6];
 #pragma unroll
-  for (int q = 0; q < 6; ++q) mwv[q] = q < G->kw ? mbp[q * 64] : 0u;
+  for (int q = 0; q < 6; ++q) mwv[q] = (k0 >> 4) + q < G->kw ? mbp[q * 64] : 0u;
+  mwv[0] >>= 2 * (k0 & 15);
 
   // ring of loads in flight, slot = block mod 2
   V st[2][NQ];
@@ -980,8 +1058,8 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
       wq[slot][2 * h] = w2.x;
       wq[slot][2 * h + 1] = w2.y;
     }
-    const int r0 = __builtin_amdgcn_readlane(rpl, kb);
-    const int nr = __builtin_amdgcn_readlane(rpl, kb + 1) - r0;
+    const int r0 = __builtin_amdgcn_readlane(rpl, kb - kb0);
+    const int nr = __builtin_amdgcn_readlane(rpl, kb - kb0 + 1) - r0;
     rn[slot] = nr;
     rs[slot] = r0;
     // unconditional and in bounds (the pool holds one spare entry); lanes
@@ -989,13 +1067,13 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
     rq[slot] = rec[r0 + (lane < nr ? lane : (nr > 0 ? nr - 1 : 0))];
   };
 
-  P nin_p = P(0);    // sum over bins of I, in bin order
-  P esc_p = P(0);    // sum of I over bins that leave the domain
+  bs.g = g0;
   auto block = [&](int kb, int slot) {
     // always issued (the last block re-reads itself from L2): a load that
     // is skipped on some path leaves the wait counts conservative, and the
     // wave would stall on the loads it has just issued
-    issue(kb + 1 < KB ? kb + 1 : kb, slot ^ 1);
+    issue(kb + 1 < kb1 ? kb + 1 : kb, slot ^ 1);
+    while (((bs.g + 1) * KB >> 2) <= kb) bs.close();
     P acc[BB];
     if constexpr (!DIRECT) {
       // one LDS plane per bin of the block: a bin's reads spread over all
@@ -1101,8 +1179,8 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
 #pragma unroll
           for (int q = 0; q < 5; ++q) mwv[q] = mwv[q + 1];
         }
-        nin_p += acc[b];
-        esc_p += m == 0u ? acc[b] : P(0);
+        bs.cur_n += acc[b];
+        bs.cur_e += m == 0u ? acc[b] : P(0);
         if constexpr (sizeof(P) == 8) {
           ipre = m == 0u ? 0.0 : (m == 1u ? acc[b] : (m == 2u ? acc[b] * 0.5 : acc[b] / 3.0));
         } else {
@@ -1119,90 +1197,117 @@ __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int ti
     if (valid) oout[blk((uint32_t)j, kb)] = out;
   };
 
-  if (0 < KB) issue(0, 0);
-  for (int kb = 0; kb < KB; kb += 2) {
+  if (kb0 < kb1) issue(kb0, 0);
+  for (int kb = kb0; kb < kb1; kb += 2) {
     block(kb, 0);
-    if (kb + 1 < KB) block(kb + 1, 1);
+    if (kb + 1 < kb1) block(kb + 1, 1);
   }
+  while (bs.g < g1) bs.close();
+}
 
+// One whole direction-conserving tile (every bin, then chemistry); with CT,
+// the direction-conserving part of a combined-transport tile.
+template <typename P, bool DIRECT, bool CT = false, bool NT = false>
+__device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int tile,
+                                           int lane, volatile SX_L P *hl,
+                                           volatile SX_L P *xchg,
+                                           const CtIn<P> &ci = CtIn<P>()) {
+  BinSums<P> bs;
+  sweep_bins<P, DIRECT, CT, NT>(G, tile, lane, hl, xchg, ci, 0, G->kb, 0, 4, bs);
   if constexpr (CT) {
+    P nin_p = bs.tot_n, esc_p = bs.tot_e;
     if (ci.bal) {
       nin_p = ci.nin_b;
       esc_p = ci.esc_b;
     }
-    ct_finish<P>(G, tile, lane, valid, ci.y0, nin_p, esc_p);
+    ct_finish<P>(G, tile, lane, tile * kTile + lane < G->n, ci.y0, nin_p, esc_p);
     return;
   }
-  double A = 0.0, T = 1.0;
-  const double nin = (double)nin_p;
-  if (valid) {
-    SX_G double *__restrict__ yv = gst(G->y);
-    const double y0 = yv[j];
-    if (!(nin == 0.0 && y0 == 1.0)) {
-      const double yn = chem_step(y0, nin * G->unit, G->dt, gld(G->dtnhv)[j],
-                                  gld(G->tau)[j], gld(G->bcoef)[j], G->n_sub, A, T);
-      yv[j] = yn;
-    }
-    gst(G->nin)[j] = nin * G->unit;
-    gst((P *)G->t[par ^ 1])[j] = (P)T;
-  }
-  A /= G->unit;   // tallies in stored units; scaled back on read
-  double esc = (double)esc_p * T;
-  double fly = (nin - (double)esc_p) * T;
-
-  // Fixed butterfly: every lane ends with the same, order-determined sum.
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    A += __shfl_xor(A, off);
-    esc += __shfl_xor(esc, off);
-    fly += __shfl_xor(fly, off);
-  }
-  if (lane == 0) {
-    SX_G double *t = gst(G->tally) + (int64_t)tile * 3;
-    t[0] += A;
-    t[1] += esc;
-    t[2] = fly;
-  }
+  dct_finish<P>(G, tile, lane, bs.tot_n, bs.tot_e);
 }
 
 // One sweep over a list of tiles (a batch of grids, or one grid when
-// tile_map is null): workgroups of TPB waves, one tile per wave.  With
-// xcd_remap, workgroup numbers are rearranged so that each XCD (workgroups
-// are dealt to the 8 XCDs round-robin) runs a contiguous eighth of the tile
-// list and its L2 sees one neighbourhood.  The workgroup that finishes last
-// flips the buffers of the listed grids and clears the completion counter,
-// so consecutive launches are identical and need no kernel between them.
-template <typename P, int TPB, bool NT>
+// tile_map is null): workgroups of TPB waves, S waves per tile (TPB / S
+// tiles per workgroup).  The S waves of a tile split its bin blocks into S
+// contiguous ranges (S = 1, 2 or 4: one, two or one of the four BinSums
+// groups each); the first adds the others' group sums to its own in group
+// order after a barrier and runs the chemistry, so the results are bitwise
+// the same for every S.  With xcd_remap, workgroup numbers are rearranged
+// so that each XCD (workgroups are dealt to the 8 XCDs round-robin) runs a
+// contiguous eighth of the tile list and its L2 sees one neighbourhood.
+// The workgroup that finishes last flips the buffers of the listed grids and
+// clears the completion counter, so consecutive launches are identical and
+// need no kernel between them.
+template <typename P, int TPB, int S, bool NT>
 __global__ __launch_bounds__(64 * TPB, 4) void k_sweep(
     GridDev *__restrict__ grids, const int2 *__restrict__ tile_map,
     int32_t n_tiles, const int32_t *__restrict__ adv, int32_t n_adv,
     uint32_t *__restrict__ done, int32_t xcd_remap) {
+  static_assert((S == 1 || S == 2 || S == 4) && TPB % S == 0, "split");
   constexpr int BB = kBlockBytes / sizeof(P);
+  constexpr int GPW = 4 / S;   // BinSums groups per wave
   __shared__ P hbuf[TPB][kHaloPlane * BB];
   __shared__ P xbuf[TPB][kTile * BB];
   __shared__ int last;
   const int lane = threadIdx.x & 63;
   const int wave = TPB == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int part = wave % S;
   const uint32_t nb = gridDim.x;   // a multiple of 8
   const uint32_t b = blockIdx.x;
   const uint32_t grp = xcd_remap ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
-  const int gt = (int)grp * TPB + wave;
+  const int gt = ((int)grp * TPB + wave) / S;
+  const GridDev *__restrict__ G = grids;
+  int tile = gt;
+  bool act = false;
+  BinSums<P> bs;
   if (gt < n_tiles) {
-    int gi = 0, tile = gt;
+    int gi = 0;
     if (tile_map) {
       const int2 tm = tile_map[gt];
       gi = __builtin_amdgcn_readfirstlane(tm.x);
       tile = __builtin_amdgcn_readfirstlane(tm.y);
     }
-    const GridDev *__restrict__ G = grids + gi;
+    G = grids + gi;
     if (G->remaining > 0) {
+      act = true;
       volatile SX_L P *hl = (volatile SX_L P *)hbuf[wave];
       volatile SX_L P *xc = (volatile SX_L P *)xbuf[wave];
+      const int KB = G->kb;
+      const int kb0 = part * KB / S, kb1 = (part + 1) * KB / S;
       if (gld(G->tile_direct)[tile] != 0)
-        sweep_tile<P, true, false, NT>(G, tile, lane, hl, xc);
+        sweep_bins<P, true, false, NT>(G, tile, lane, hl, xc, CtIn<P>(), kb0, kb1,
+                                       part * GPW, (part + 1) * GPW, bs);
       else
-        sweep_tile<P, false, false, NT>(G, tile, lane, hl, xc);
+        sweep_bins<P, false, false, NT>(G, tile, lane, hl, xc, CtIn<P>(), kb0, kb1,
+                                        part * GPW, (part + 1) * GPW, bs);
+      if constexpr (S > 1) {
+        // hand the group sums over in this wave's halo planes (its last
+        // block has read them)
+        if (part > 0) {
+          hl[lane] = bs.hn0;
+          hl[128 + lane] = bs.he0;
+          if constexpr (GPW > 1) {
+            hl[64 + lane] = bs.hn1;
+            hl[192 + lane] = bs.he1;
+          }
+        }
+      }
     }
+  }
+  if constexpr (S > 1) __syncthreads();
+  if (act && part == 0) {
+    if constexpr (S > 1) {
+#pragma unroll
+      for (int q = 1; q < S; ++q) {
+        const volatile SX_L P *o = (const volatile SX_L P *)hbuf[wave + q];
+#pragma unroll
+        for (int g = 0; g < GPW; ++g) {
+          bs.tot_n += o[64 * g + lane];
+          bs.tot_e += o[128 + 64 * g + lane];
+        }
+      }
+    }
+    dct_finish<P>(G, tile, lane, bs.tot_n, bs.tot_e);
   }
   // completion count; the last workgroup advances the grids
   __syncthreads();
@@ -1737,11 +1842,14 @@ hipError_t launch_reset_state(GridDev *dg, const GridDev &hg, const double *y0,
 }
 
 template <typename P, bool NT>
-static const void *sweep_fn(int tpb) {
-  switch (tpb) {
-    case 1: return (const void *)k_sweep<P, 1, NT>;
-    case 2: return (const void *)k_sweep<P, 2, NT>;
-    case 4: return (const void *)k_sweep<P, 4, NT>;
+static const void *sweep_fn(int tpb, int split) {
+  switch (tpb * 8 + split) {
+    case 1 * 8 + 1: return (const void *)k_sweep<P, 1, 1, NT>;
+    case 2 * 8 + 1: return (const void *)k_sweep<P, 2, 1, NT>;
+    case 4 * 8 + 1: return (const void *)k_sweep<P, 4, 1, NT>;
+    case 2 * 8 + 2: return (const void *)k_sweep<P, 2, 2, NT>;
+    case 4 * 8 + 2: return (const void *)k_sweep<P, 4, 2, NT>;
+    case 4 * 8 + 4: return (const void *)k_sweep<P, 4, 4, NT>;
   }
   return nullptr;
 }
@@ -1757,13 +1865,17 @@ static hipError_t sweep_shape(const SweepLaunch &l, const void **fn, dim3 *grid,
     *block = dim3(64u);
     return hipSuccess;
   }
+  const int split = l.split > 1 ? l.split : 1;
   const void *f = l.precision == 0
-                      ? (l.nt ? sweep_fn<double, true>(l.tpb) : sweep_fn<double, false>(l.tpb))
-                      : (l.nt ? sweep_fn<float, true>(l.tpb) : sweep_fn<float, false>(l.tpb));
+                      ? (l.nt ? sweep_fn<double, true>(l.tpb, split)
+                              : sweep_fn<double, false>(l.tpb, split))
+                      : (l.nt ? sweep_fn<float, true>(l.tpb, split)
+                              : sweep_fn<float, false>(l.tpb, split));
   if (!f || l.n_tiles <= 0 || !l.done) return hipErrorInvalidValue;
   *fn = f;
-  // one workgroup per tpb tiles, rounded up to a multiple of 8
-  *grid = dim3((((unsigned)l.n_tiles + l.tpb - 1) / l.tpb + 7u) & ~7u);
+  // one workgroup per tpb / split tiles, rounded up to a multiple of 8
+  const unsigned tpg = (unsigned)(l.tpb / split);
+  *grid = dim3((((unsigned)l.n_tiles + tpg - 1) / tpg + 7u) & ~7u);
   *block = dim3(64u * (unsigned)l.tpb);
   return hipSuccess;
 }

@@ -97,7 +97,8 @@ class SxStateIn(C.Structure):
 
 class SxSchedule(C.Structure):
     _fields_ = [("tiles_per_group", C.c_int32), ("order", C.c_int32),
-                ("xcd_contiguous", C.c_int32), ("graph_sweeps", C.c_int32)]
+                ("xcd_contiguous", C.c_int32), ("graph_sweeps", C.c_int32),
+                ("work_split", C.c_int32)]
 
 
 class SxServeOpts(C.Structure):
@@ -457,9 +458,9 @@ def _ids(ids):
 
 
 def sx_set_schedule(ctx, ids, tiles_per_group=4, order=SX_ORDER_GRID,
-                    xcd_contiguous=1, graph_sweeps=50) -> None:
+                    xcd_contiguous=1, graph_sweeps=50, work_split=1) -> None:
     a, p, n = _ids(ids)
-    s = SxSchedule(tiles_per_group, order, xcd_contiguous, graph_sweeps)
+    s = SxSchedule(tiles_per_group, order, xcd_contiguous, graph_sweeps, work_split)
     _check(ctx, load().sx_set_schedule(ctx, p, n, C.byref(s)))
 
 
@@ -470,7 +471,7 @@ def sx_get_schedule(ctx, ids) -> dict:
     _check(ctx, load().sx_get_schedule(ctx, p, n, C.byref(s), C.byref(us)))
     return dict(tiles_per_group=s.tiles_per_group, order=s.order,
                 xcd_contiguous=s.xcd_contiguous, graph_sweeps=s.graph_sweeps,
-                us_per_sweep=us.value)
+                work_split=max(1, s.work_split), us_per_sweep=us.value)
 
 
 def sx_autotune(ctx, trials: int) -> None:

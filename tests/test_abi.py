@@ -89,7 +89,7 @@ int main(void) {
   printf("sx_state_out %zu\n", sizeof(sx_state_out));
   printf("sx_tally %zu\n", sizeof(sx_tally));
   printf("sx_schedule %zu\n", sizeof(sx_schedule));
-  P(sx_schedule, order) P(sx_schedule, graph_sweeps)
+  P(sx_schedule, order) P(sx_schedule, graph_sweeps) P(sx_schedule, work_split)
   printf("sx_serve_opts %zu\n", sizeof(sx_serve_opts));
   printf("sx_serve_result %zu\n", sizeof(sx_serve_result));
   printf("sx_serve_stats %zu\n", sizeof(sx_serve_stats));
@@ -120,7 +120,7 @@ def test_ctypes_struct_layout_matches_c():
     assert C.sizeof(sx.SxStateOut) == lay["sx_state_out"]
     assert C.sizeof(sx.SxTally) == lay["sx_tally"]
     assert C.sizeof(sx.SxSchedule) == lay["sx_schedule"]
-    for f in ("order", "graph_sweeps"):
+    for f in ("order", "graph_sweeps", "work_split"):
         assert getattr(sx.SxSchedule, f).offset == lay[f"sx_schedule.{f}"], f
     for name, cls, fields in (
             ("sx_serve_opts", sx.SxServeOpts, ("hbm_budget",)),

@@ -10,6 +10,8 @@ from paper_0912_4273_amd import sx
 pytestmark = pytest.mark.gpu
 
 PLAIN = dict(tiles_per_group=4, order=sx.SX_ORDER_GRID, xcd_contiguous=1, graph_sweeps=0)
+# (tiles per workgroup, waves per tile)
+SHAPES = [(4, 1), (2, 1), (1, 1), (2, 2), (1, 2), (1, 4)]
 
 
 def _mixed_batch():
@@ -53,18 +55,48 @@ def test_every_schedule_gives_the_same_bits(monkeypatch):
         ctx.set_schedule(ids, **PLAIN)
         ctx.solve(ids, sweeps)
         ref = _states(ctx, ids)
-        for tpb in (1, 2, 4):
+        for tpb, split in SHAPES:
             for order in (sx.SX_ORDER_GRID, sx.SX_ORDER_DIRECT_FIRST):
                 for xcd in (0, 1):
                     for gsw in (0, 7):
-                        what = f"tpb={tpb} order={order} xcd={xcd} graph={gsw}"
+                        what = f"tpb={tpb} split={split} order={order} xcd={xcd} graph={gsw}"
                         print("[case]", what, flush=True)
                         for g in ids:
                             ctx.reset(g)
                         ctx.set_schedule(ids, tiles_per_group=tpb, order=order,
-                                         xcd_contiguous=xcd, graph_sweeps=gsw)
+                                         xcd_contiguous=xcd, graph_sweeps=gsw,
+                                         work_split=split)
                         ctx.solve(ids, sweeps)
                         _same(ref, _states(ctx, ids), what)
+
+
+def test_work_split_with_fewer_blocks_than_waves():
+    """Grids with fewer bin blocks than waves per tile (1, 2 and 3 bins, 5
+    in FP64): the waves past the last block hand over zeros."""
+    ws = [G.small_random(500, seed=75 + k, n_bins=k, box=3e21, rate=1e48, n_src=2, dt=3e13,
+                         precision=G.SX_FP32_TRANSPORT if k < 5 else G.SX_FP64)
+          for k in (1, 2, 3, 5)]
+    with sx.Context(0) as ctx:
+        ids = [ctx.upload(w) for w in ws]
+        ctx.set_schedule(ids, **PLAIN)
+        ctx.solve(ids, 25)
+        ref = _states(ctx, ids)
+        for tpb, split in SHAPES[1:]:
+            print(f"[case] few bins tpb={tpb} split={split}", flush=True)
+            for g in ids:
+                ctx.reset(g)
+            ctx.set_schedule(ids, tiles_per_group=tpb, order=sx.SX_ORDER_GRID,
+                             xcd_contiguous=1, graph_sweeps=0, work_split=split)
+            ctx.solve(ids, 25)
+            _same(ref, _states(ctx, ids), f"few bins tpb={tpb} split={split}")
+
+
+def test_invalid_work_split_is_refused():
+    with sx.Context(0) as ctx:
+        for tpb, split in ((4, 2), (2, 4), (1, 3), (1, 8), (1, -1)):
+            with pytest.raises(sx.SxError):
+                ctx.set_schedule([], tiles_per_group=tpb, order=sx.SX_ORDER_GRID,
+                                 xcd_contiguous=1, graph_sweeps=0, work_split=split)
 
 
 def test_single_grid_schedules(monkeypatch):
@@ -74,14 +106,14 @@ def test_single_grid_schedules(monkeypatch):
         ctx.set_schedule([gid], **PLAIN)
         ctx.solve([gid], 40)
         ref = _states(ctx, [gid])
-        for tpb in (1, 2):
+        for tpb, split in ((1, 1), (2, 1), (2, 2), (1, 4)):
             for gsw in (0, 3, 40):
-                print(f"[case] single tpb={tpb} graph={gsw}", flush=True)
+                print(f"[case] single tpb={tpb} split={split} graph={gsw}", flush=True)
                 ctx.reset(gid)
                 ctx.set_schedule([gid], tiles_per_group=tpb, order=sx.SX_ORDER_DIRECT_FIRST,
-                                 xcd_contiguous=0, graph_sweeps=gsw)
+                                 xcd_contiguous=0, graph_sweeps=gsw, work_split=split)
                 ctx.solve([gid], 40)
-                _same(ref, _states(ctx, [gid]), f"tpb={tpb} graph={gsw}")
+                _same(ref, _states(ctx, [gid]), f"tpb={tpb} split={split} graph={gsw}")
 
 
 def test_graph_replays_with_eager_work_between(monkeypatch):
