@@ -447,6 +447,49 @@ def regrid_leg(ctx, w, passes: int, n_min: int, tau_remove: float, log, prof):
     return res
 
 
+def small_leg(ctx, log, prof, graph_sweeps: int):
+    """The plain single-source test (4096 vertices, 42 bins, all-FP64, 200
+    sweeps over 500 Myr): a grid too small to fill the GPU, so the time per
+    sweep is launch and latency bound.  Timed whole (reset, 200 sweeps,
+    read-back) under each work split, as HIP-graph replays and as plain
+    launches; the sweep launch's time comes from HIP events on the library
+    stream, gaps included."""
+    w1 = G.config1()
+    gid = ctx.upload(w1)
+    sweeps = w1.n_sweeps
+    out = dict(workload=f"stromgren_{w1.n}_k{w1.k}_{sweeps}sweeps", vertices=w1.n, bins=w1.k,
+               sweeps=sweeps, precision="fp64")
+    runs = {}
+    for split in (1, 2, 4):
+        for label, gs in (("graph", graph_sweeps), ("launches", 0)):
+            ctx.set_schedule([gid], tiles_per_group=4, graph_sweeps=gs, work_split=split)
+            for _ in range(2):   # warm-up (graph instantiation)
+                ctx.reset(gid)
+                ctx.solve([gid], sweeps)
+            reps = 5
+            prof(True)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.reset(gid)
+                ctx.solve([gid], sweeps)
+                ctx.state(gid, nin=False)
+            el = (time.perf_counter() - t0) / reps
+            pr = prof(False)
+            runs[f"split{split}_{label}"] = dict(
+                ms_per_solve=round(1e3 * el, 3),
+                sweep_launch_us=round(1e3 * pr["total_ms"] / max(pr["launches"], 1), 2),
+                updates_per_s=w1.n * w1.k * sweeps / el)
+    ctx.set_schedule([gid], graph_sweeps=graph_sweeps)
+    ctx.free(gid)
+    best = min(runs, key=lambda r: runs[r]["ms_per_solve"])
+    out.update(runs=runs, best=best, value=runs[best]["updates_per_s"],
+               unit="vertex·direction updates/s")
+    log(f"small grid (fp64, 4096 x 42, 200 sweeps): best {best} "
+        f"{runs[best]['ms_per_solve']:.2f} ms/solve, {out['value']:.3e} updates/s; "
+        + ", ".join(f"{k} {v['sweep_launch_us']:.1f} us" for k, v in runs.items()))
+    return out
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -594,6 +637,8 @@ def main():
                     help="skip the per-result error statement against the oracle")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 4096-vertex all-FP64 leg")
     ap.add_argument("--batch-grids", type=int, default=64,
                     help="grids in the batched leg (0 = skip it)")
     ap.add_argument("--batch-sweeps", type=int, default=200)
@@ -796,6 +841,10 @@ def main():
         ctx.profile(False)
         return r
 
+    small = None
+    if not args.no_small:
+        small = small_leg(ctx, log, prof, args.graph_sweeps)
+
     combined = None
     if args.combined_tau >= 0:
         combined = combined_leg(ctx, w, args.combined_tau, log, prof)
@@ -874,6 +923,7 @@ def main():
                    "sweeps_per_step": args.sweeps, "precision": "fp32_transport",
                    "physics": "Stromgren test: n_H 1e-3, 5e48 photons/s, 13.2 kpc box, 500 Myr"},
         "fp64_plain": fp64,
+        "small_fp64": small,
         "batched": batched,
         "served": served,
         "shadow": shadowed,

@@ -232,6 +232,63 @@ uint64_t hilbert_key(uint32_t x0, uint32_t x1, uint32_t x2, int b) {
   return key;
 }
 
+// Storage order of the bins: blocks of bb bins that point in nearby
+// directions.  Greedy grouping: walk the bins in some order and give each
+// bin not yet taken the bb - 1 closest bins not yet taken (largest cosine,
+// ties to the lower index); the group with fewer bins, if K is not a
+// multiple of bb, comes last.  Several walk orders are tried (the given
+// order, then seeded shuffles) and the grouping whose groups are tightest
+// (largest sum over groups of the smallest cosine within the group) is
+// kept.  Returns the bin at each position; the bins of a group are
+// ascending.
+std::vector<uint8_t> cluster_bins(const double *u, int K, int bb) {
+  auto dot = [&](int a, int b) {
+    return (u[3 * a] * u[3 * b] + u[3 * a + 1] * u[3 * b + 1]) + u[3 * a + 2] * u[3 * b + 2];
+  };
+  std::vector<uint8_t> best;
+  double best_score = -INFINITY;
+  std::vector<int> order((size_t)K);
+  uint64_t rs = 0x9E3779B97F4A7C15ull;
+  auto next = [&]() {   // xorshift64*
+    rs ^= rs >> 12;
+    rs ^= rs << 25;
+    rs ^= rs >> 27;
+    return rs * 0x2545F4914F6CDD1Dull;
+  };
+  std::vector<std::pair<double, int>> cand;
+  for (int trial = 0; trial < 64; ++trial) {
+    for (int k = 0; k < K; ++k) order[(size_t)k] = k;
+    if (trial > 0)
+      for (int k = K - 1; k > 0; --k) std::swap(order[(size_t)k], order[next() % (uint64_t)(k + 1)]);
+    std::vector<char> used((size_t)K, 0);
+    std::vector<uint8_t> perm;
+    double score = 0.0;
+    for (int a : order) {
+      if (used[(size_t)a]) continue;
+      cand.clear();
+      for (int k = 0; k < K; ++k)
+        if (!used[(size_t)k] && k != a) cand.push_back({-dot(a, k), k});
+      std::sort(cand.begin(), cand.end());
+      std::vector<int> grp{a};
+      for (size_t c = 0; c < cand.size() && (int)grp.size() < bb; ++c) grp.push_back(cand[c].second);
+      std::sort(grp.begin(), grp.end());
+      double mn = 1.0;
+      for (size_t x = 0; x < grp.size(); ++x)
+        for (size_t y = x + 1; y < grp.size(); ++y) mn = std::min(mn, dot(grp[x], grp[y]));
+      score += mn;
+      for (int k : grp) {
+        used[(size_t)k] = 1;
+        perm.push_back((uint8_t)k);
+      }
+    }
+    if (score > best_score) {
+      best_score = score;
+      best = perm;
+    }
+  }
+  return best;
+}
+
 std::vector<int32_t> hilbert_order(const double *pos, int64_t n) {
   double lo[3] = {INFINITY, INFINITY, INFINITY};
   double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -403,7 +460,7 @@ uint64_t rnd(uint64_t b) { return (b + 255) & ~uint64_t(255); }
 uint64_t bytes_estimate(const Sizes &s, int64_t n_em, int64_t n_rec, int64_t n_halo) {
   uint64_t b = 0;
   b += rnd(4 * (s.npad + 1)) + rnd(4 * s.E) + rnd(s.E) + rnd(24 * s.E) + rnd(24 * s.K);
-  b += rnd(4 * s.npad * s.K) + rnd(s.E) + rnd(8 * s.npad * s.kb * s.bb) +
+  b += rnd(4 * s.npad * s.K) + rnd(s.E) + rnd(8 * s.npad * s.kb) +
        rnd(4 * s.npad * s.kw) + 2 * rnd(4 * (s.ntiles * s.K * sx::kRecGroups + 1)) + rnd(4 * n_rec + 4) +
        rnd(16 * s.E + 16) + rnd(4 * s.E + 4);
   b += rnd(4 * (s.ntiles + 1)) + rnd(4 * n_halo + 4) + rnd(2 * s.E) + rnd(s.ntiles);
@@ -569,6 +626,7 @@ struct sx_prepared {
   int32_t n_sub = 0, mpb = 0, precision = 0;
   double dt = 0.0, cos_min = 0.0, unit = 1.0;
   std::vector<double> bins;
+  std::vector<uint8_t> bperm;    // bin at each storage position
   std::vector<uint8_t> rev;
   std::vector<double> edir;
   std::vector<int32_t> halo_ptr, halo_vid;
@@ -604,6 +662,7 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
   P->dt = d->dt;
   P->cos_min = d->cos_min;
   P->bins.assign(d->bin_dirs, d->bin_dirs + 3 * S.K);
+  P->bperm = cluster_bins(d->bin_dirs, (int)S.K, (int)S.bb);
   const int64_t n = S.n, E = S.E, K = S.K, npad = S.npad;
   (void)K;
   Grid *g = new Grid();
@@ -962,6 +1021,19 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   for (int64_t v = 0; v < n; ++v)
     h.max_deg = std::max(h.max_deg, g->row_ptr_h[(size_t)v + 1] - g->row_ptr_h[(size_t)v]);
   h.precision = P->precision;
+  {
+    // SX_INW_ENTRIES=n (n >= 0) fills at most n entries of each in-word, so
+    // that the rest become records (a test knob for the record path)
+    h.inw_cap = sx::inw_entries((int)S.bb);
+    const char *ie = std::getenv("SX_INW_ENTRIES");
+    if (ie && ie[0] >= '0' && ie[0] <= '9') h.inw_cap = std::min(h.inw_cap, std::atoi(ie));
+    std::memset(h.bperm, 0, sizeof(h.bperm));
+    std::memset(h.bpos, 0, sizeof(h.bpos));
+    for (int64_t p = 0; p < K; ++p) {
+      h.bperm[p] = P->bperm[(size_t)p];
+      h.bpos[P->bperm[(size_t)p]] = (uint8_t)p;
+    }
+  }
   h.parity = 0;
   h.remaining = 0;
   h.sweeps = 0;
@@ -994,7 +1066,7 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   GA(d_bins, 3 * K);
   GA(d_fwd, npad * K);
   GA(d_ebin, E);
-  GA(d_inw, npad * S.kb * S.bb);
+  GA(d_inw, npad * S.kb);
   GA(d_mb, npad * S.kw);
   GA(d_rec_cnt, ntiles * K * sx::kRecGroups + 1);
   GA(d_rec_ptr, ntiles * K * sx::kRecGroups + 1);
@@ -2042,7 +2114,8 @@ int sx_read_state(sx_ctx *ctx, sx_grid_id id, const sx_state_out *out) {
     // O = Ipre * T in the stored precision, as the next step would form it
     const int64_t words = (h.ntiles + 1) * (int64_t)h.kb * sx::kTile * h.bb;
     auto at = [&](int64_t v, int64_t k) {
-      return (((v >> 6) * h.kb + k / h.bb) * sx::kTile + (v & 63)) * h.bb + k % h.bb;
+      const int64_t p = h.bpos[k];
+      return (((v >> 6) * h.kb + p / h.bb) * sx::kTile + (v & 63)) * h.bb + p % h.bb;
     };
     const void *src = h.o[cur.parity];
     const void *tsrc = h.t[cur.parity];
@@ -2134,7 +2207,8 @@ int sx_grid_restore(sx_ctx *ctx, sx_grid_id id, const sx_state_in *in) {
     // the restored field is the outgoing share itself: Ipre = O, T = 1
     const int64_t words = (h.ntiles + 1) * (int64_t)h.kb * sx::kTile * h.bb;
     auto at = [&](int64_t v, int64_t k) {
-      return (((v >> 6) * h.kb + k / h.bb) * sx::kTile + (v & 63)) * h.bb + k % h.bb;
+      const int64_t p = h.bpos[k];
+      return (((v >> 6) * h.kb + p / h.bb) * sx::kTile + (v & 63)) * h.bb + p % h.bb;
     };
     void *dst = h.o[cur.parity];
     void *tdst = h.t[cur.parity];
@@ -2309,8 +2383,8 @@ int sx_grid_restore_edges(sx_ctx *ctx, sx_grid_id id, const double *photons_e,
       t[(size_t)v] = (T)1;
       for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e)
         o[(size_t)e] = photons_e ? (T)(photons_e[to_orig[(size_t)e]] / h.unit) : zero;
-      for (int64_t k = 0; k < h.k; ++k)
-        bins[(size_t)((((v >> 6) * h.kb + k / h.bb) * sx::kTile + (v & 63)) * h.bb + k % h.bb)] = zero;
+      for (int64_t p = 0; p < h.k; ++p)   // every position of the vertex
+        bins[(size_t)((((v >> 6) * h.kb + p / h.bb) * sx::kTile + (v & 63)) * h.bb + p % h.bb)] = zero;
     }
     HIP_TRY(ctx, hipMemcpy(h.oe[par], o.data(), sizeof(T) * E, hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipMemcpy(h.t[par], t.data(), sizeof(T) * h.plane, hipMemcpyHostToDevice));

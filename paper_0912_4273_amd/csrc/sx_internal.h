@@ -12,34 +12,47 @@ namespace sx {
 constexpr int kTile = 64;           // vertices per tile = one wavefront
 constexpr int kEmptySlot = 127;     // unused slot marker in packed tables
 
-constexpr int kStageQ = 5;         // halo staging loads per lane and bin
-constexpr int kHaloMax = 64 * kStageQ;   // halo vertices a staged tile may have
-constexpr int kZeroSlot = 511;     // in-word index that reads 0
-constexpr int kWordEntries = 7;    // sender entries held by an in-word
-constexpr uint64_t kEmptyWord = 0x7FFFFFFFFFFFFFFFull;  // 7 x 511
+constexpr int kStageQ = 5;         // halo staging loads per lane and block
+constexpr int kHaloMax = 64 * kStageQ;   // halo vertices a staged tile may have;
+                                         // LDS entry kHaloMax reads 0
 
 // Halo of a tile: the sorted list of every vertex that neighbours one of
-// the tile's 64 vertices.  Each bin's photons of the halo are staged in LDS
-// once per wave, and the gathers read LDS through 9-bit halo indices.  A
-// tile whose halo exceeds kHaloMax vertices is "direct": its entries are
-// slots into the receiver's neighbour row and the gathers go to global
-// memory.
+// the tile's 64 vertices.  A block of bins of the halo is staged in LDS once
+// per wave; the gathers find a sender there through its 9-bit halo index.  A
+// tile whose halo exceeds kHaloMax vertices is "direct": its gathers go to
+// global memory through the receiver's neighbour row.
 //
-// In-word of a (vertex, bin) pair (uint64): which neighbours send this bin
-// here.  Bits 9e..9e+8 (e = 0..6) hold the e-th sender, ascending sender
-// id, as a halo index (or row slot in a direct tile); 511 = none.  Bit 63
-// is set when the pair also has records (below).
-// Records (uint32, grouped by (tile, bin), sorted by bin then lane) carry
-// what does not fit: senders beyond the seventh, then the vertex's shares of
-// source emission for the bin.  Record = lane << 26 | (bin mod BB) << 24 |
-// kind << 23 | index; kind 0 = sender (halo index or row slot), kind 1 =
-// emission amount index.
+// Bins are stored in an order of the library's own: the grid's bins are
+// grouped into blocks of BB bins that point in nearby directions (bperm /
+// bpos below), so the neighbours that send a block's bins to one vertex are
+// few and mostly the same for all of them.  Every kernel that stores or
+// reads photons per bin goes through that order; the caller's bin numbers
+// are kept everywhere else (selection, edge bins, source shares).
+//
+// In-word of a (vertex j, block of BB bins) (uint64): which neighbours send
+// which of the block's bins to j.  Entry e (bits EB e .. EB e + EB - 1,
+// EB = 5 + BB) holds in its low 5 bits the slot of the sender in j's row
+// and in the next BB bits the bins of the block it sends; entries are in
+// ascending slot (= ascending original sender id), unused entries are 0 (no
+// bins).  A word holds 63 / EB entries (7 with 4 bins, 9 with 2).  Bit 63
+// is set when the pair also has records (below).  Only slots below
+// kSlotRows go into entries; a staged tile finds the halo index of a slot in
+// a per-wave LDS table.
+// Records (uint32, grouped by (tile, bin position), sorted by position then
+// lane) carry what does not fit: senders beyond the in-word's entries (or at
+// a slot >= kSlotRows), one record per bin sent, then the vertex's shares of
+// source emission for the bin.  Record = lane << 26 | (position mod BB) <<
+// 24 | kind << 23 | index; kind 0 = sender (halo index, or row slot in a
+// direct tile), kind 1 = emission amount index.
 //
 // Photon field layout: 16-byte blocks of BB = 16 / sizeof(photon) bins per
-// vertex (4 fp32 or 2 fp64), element (v, k) at block
-// ((v / 64) * KB + k / BB) * 64 + v % 64, component k % BB, KB = ceil(K/BB).
-// One extra tile past the last holds zeros.  In-words use the same block
-// order with BB 64-bit words per block.
+// vertex (4 fp32 or 2 fp64), element (v, bin at position p) at block
+// ((v / 64) * KB + p / BB) * 64 + v % 64, component p % BB, KB =
+// ceil(K/BB).  One extra tile past the last holds zeros.  In-words: one
+// per (vertex, block), in the same block order.
+constexpr int kSlotRows = 30;      // row slots an in-word entry can name
+__host__ __device__ constexpr int inw_entry_bits(int bb) { return 5 + bb; }
+__host__ __device__ constexpr int inw_entries(int bb) { return 63 / (5 + bb); }
 constexpr int kBlockBytes = 16;
 // Record counts and offsets per (tile, bin, group of kRecGroupLanes lanes).
 constexpr int kRecGroups = 8;
@@ -68,6 +81,10 @@ struct GridDev {
   int32_t mpb;        // max neighbours per bin
   int32_t max_deg;    // largest degree of the grid (sizes the selection's LDS)
   int32_t precision;  // 0 fp64, 1 fp32 transport
+  int32_t inw_cap;    // in-word entries the gather-list build fills (<= inw_entries(bb);
+                      // fewer only to exercise the record path)
+  uint8_t bperm[128]; // bin stored at position p (caller's numbering)
+  uint8_t bpos[128];  // position of bin k
   // mutable per-sweep control, advanced by the last workgroup of each sweep launch
   int32_t parity;     // O buffer holding the current field
   int32_t remaining;  // steps still to run in the current request
@@ -86,7 +103,7 @@ struct GridDev {
   // selection products
   uint32_t *fwd;            // [npad*K]
   uint8_t *ebin;            // [E]
-  uint64_t *inw;            // [ntiles][kb][64][bb]
+  uint64_t *inw;            // [ntiles][kb][64]
   uint32_t *mbits;          // [ntiles][kw][64]
   int32_t *rec_cnt;         // [ntiles*K*kRecGroups+1] scratch: records per (tile, bin, group)
   int32_t *rec_ptr;         // [ntiles*K*kRecGroups+1] first record of each
@@ -125,7 +142,8 @@ struct GridDev {
   int32_t dct_ref;          // bin selection w.r.t. 0: the bin, 1: its closest edge
   double tau_switch;        // ballistic where y tau >= tau_switch
   int32_t *kl_ptr;          // [E+1]
-  uint8_t *kl;              // bins of i whose selection holds j, ascending
+  uint8_t *kl;              // bins of i whose selection holds j, ascending by bin,
+                            // each as its storage position
   int64_t kl_cap;           // entries kl holds
   int32_t *kl_cnt;          // [E+1] scratch: entries per in-edge
   int64_t *kl_part;         // [E/1024 + 2] scratch of their scan

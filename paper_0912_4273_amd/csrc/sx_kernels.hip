@@ -311,11 +311,10 @@ __global__ __launch_bounds__(256) void k_edge_bins(const GridDev *__restrict__ g
 
 // ------------------------------------------------------- gather lists ---
 // The receiver side of the selection: neighbour t of j sends bin k to j iff
-// j is among the selected slots of (nbr_t, k).  One thread per (tile, bin)
-// walks the tile's 64 receivers in lane order, so that the in-words of a
-// (tile, bin) and its records are produced together and the records come
-// out grouped by (tile, bin).  Pass 1 counts the records, pass 2 (after a
-// scan) writes in-words and records.
+// j is among the selected slots of (nbr_t, k).  The gather-list kernels read
+// it from the receiving side: one mask per in-edge e of j (bit k of word 4e
+// + k/32 set iff bin k of sender nbr[e] selects j), written by the
+// selection kernel.
 __device__ __forceinline__ int sender_index(const GridDev &g, bool direct,
                                             int e, int rb) {
   return direct ? e - rb : (int)g.edge_hidx[e];
@@ -329,124 +328,95 @@ static_assert(SX_MAX_BINS_FP32 <= 128 && SX_MAX_BINS_FP64 <= 128 &&
               "selection masks hold 128 bins; edge bins stage up to "
               "SX_MAX_BINS_FP32 directions");
 
-// The gather-list kernels read the selection from the receiving side: one
-// mask per in-edge e of j (bit k of word 4e + k/32 set iff bin k of sender
-// nbr[e] selects j), written by the selection kernel.
-__device__ __forceinline__ uint32_t sel_bit(const GridDev &g, int e, int k) {
-  return (g.smask[4 * (int64_t)e + (k >> 5)] >> (k & 31)) & 1u;
-}
-
-// Record counts and offsets are kept per (tile, bin, group of
-// kRecGroupLanes receivers), groups in lane order, so the records of a
-// (tile, bin) come out sorted by lane.
-//
-// The count pass takes 32 bins at a time: thread (tile, group, w) walks the
-// group's receivers and their in-edges, reading word w of each mask once,
-// and keeps the 32 senders-per-bin counts as bytes, four to a register (a
-// count is at most the degree, < 128).  Bits 4i..4i+3 of a mask word are
-// spread into the four bytes of counter i by one multiply: (x * 0x204081) &
-// 0x01010101 (the shifted copies 0, 7, 14, 21 do not overlap).
-__global__ void k_inlist_count(const GridDev *__restrict__ gp) {
-  const GridDev &g = *gp;
-  const int K = g.k;
-  const int nw = (K + 31) / 32;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)g.ntiles * kRecGroups * nw) return;
-  const int w = (int)(t % nw);
-  const int64_t tg = t / nw;
-  const int tile = (int)(tg / kRecGroups), grp = (int)(tg % kRecGroups);
-  int recs[32];
-#pragma unroll
-  for (int b = 0; b < 32; ++b) recs[b] = 0;
-  for (int lane = grp * kRecGroupLanes; lane < (grp + 1) * kRecGroupLanes; ++lane) {
-    const int j = tile * kTile + lane;
-    if (j >= g.n) break;
-    uint32_t cw[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) cw[i] = 0u;
-    const int re = g.row_ptr[j + 1];
-#pragma unroll 4
-    for (int e = g.row_ptr[j]; e < re; ++e) {
-      const uint32_t m = g.smask[4 * (int64_t)e + w];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) cw[i] += (((m >> (4 * i)) & 15u) * 0x204081u) & 0x01010101u;
-    }
-#pragma unroll
-    for (int b = 0; b < 32; ++b) {
-      const int c = (int)((cw[b >> 2] >> (8 * (b & 3))) & 255u);
-      recs[b] += c > kWordEntries ? c - kWordEntries : 0;
-    }
-    for (int q = g.em_ptr[j]; q < g.em_ptr[j + 1]; ++q) {
-      const int kk = g.em_k[q] - 32 * w;
-#pragma unroll
-      for (int b = 0; b < 32; ++b) recs[b] += kk == b ? 1 : 0;
+// Which bins of block kb (positions kb BB .. kb BB + BB - 1) the in-edge
+// with selection mask m sends, as BB bits.
+__device__ __forceinline__ uint32_t block_bits(const GridDev &g, const uint4 &m, int kb) {
+  uint32_t nib = 0;
+  const int p0 = kb * g.bb;
+  for (int b = 0; b < g.bb; ++b) {
+    const int p = p0 + b;
+    if (p < g.k) {
+      const int k = g.bperm[p];
+      const uint32_t w = (k >> 5) == 0 ? m.x : (k >> 5) == 1 ? m.y : (k >> 5) == 2 ? m.z : m.w;
+      nib |= ((w >> (k & 31)) & 1u) << b;
     }
   }
-#pragma unroll
-  for (int b = 0; b < 32; ++b) {
-    const int k = 32 * w + b;
-    if (k < K) g.rec_cnt[((int64_t)tile * K + k) * kRecGroups + grp] = recs[b];
-  }
+  return nib;
 }
 
-// The fill pass: thread (tile, bin, group) walks the group's receivers in
-// lane order; threads of neighbouring bins are neighbours, so their mask
-// reads fall in the same 16 bytes.
-__global__ void k_inlist_fill(const GridDev *__restrict__ gp) {
+// One thread per (tile, block, group of kRecGroupLanes receivers) walks the
+// group's receivers in lane order and each receiver's in-edges in row order.
+// A sender with bins in the block takes the next in-word entry while there
+// is one (and its slot fits), otherwise it becomes records, one per bin; the
+// receiver's source shares of the block's bins come after.  Counts and
+// offsets are kept per (tile, position, group), so the records of a (tile,
+// position) come out sorted by lane.  Pass 1 counts the records, pass 2
+// (after a scan) writes in-words and records.
+template <bool FILL>
+__global__ void k_inlist(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
-  const int K = g.k;
+  const int K = g.k, KB = g.kb, BB = g.bb;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nt = (int64_t)g.ntiles * K * kRecGroups;
-  if (t >= nt) return;
-  const int k = (int)(t % K);
-  const int64_t tg = t / K;
-  const int tile = (int)(tg / kRecGroups), grp = (int)(tg % kRecGroups);
+  if (t >= (int64_t)g.ntiles * KB * kRecGroups) return;
+  const int grp = (int)(t % kRecGroups);
+  const int64_t tk = t / kRecGroups;
+  const int kb = (int)(tk % KB), tile = (int)(tk / KB);
   const bool direct = g.tile_direct[tile] != 0;
-  int64_t rp = g.rec_ptr[((int64_t)tile * K + k) * kRecGroups + grp];
-  const int kb = k / g.bb, b = k - kb * g.bb;
-  uint64_t *out = g.inw + (((int64_t)tile * g.kb + kb) * kTile) * g.bb + b;
+  const int eb = inw_entry_bits(BB);
+  const int cap = g.inw_cap;
+  const uint4 *sm = (const uint4 *)g.smask;
+  int rp[4] = {0, 0, 0, 0};   // record counts (pass 1) or next record (pass 2), per bin
+  if (FILL) {
+    for (int b = 0; b < BB; ++b) {
+      const int p = kb * BB + b;
+      if (p < K) rp[b] = g.rec_ptr[((int64_t)tile * K + p) * kRecGroups + grp];
+    }
+  }
   for (int lane = grp * kRecGroupLanes; lane < (grp + 1) * kRecGroupLanes; ++lane) {
     const int j = tile * kTile + lane;
-    uint64_t w = kEmptyWord;
+    uint64_t w = 0;
     if (j < g.n) {
       const int rb = g.row_ptr[j], re = g.row_ptr[j + 1];
-      const uint32_t lbits = ((uint32_t)lane << 26) | ((uint32_t)b << 24);
+      const uint32_t lbits = (uint32_t)lane << 26;
       int c = 0;
-      auto take = [&](uint32_t idx) {
-        if (c < kWordEntries) {
-          w = (w & ~(511ull << (9 * c))) | ((uint64_t)idx << (9 * c));
-        } else if (rp < g.rec_cap) {
-          g.rec[rp++] = lbits | idx;
-        }
-        ++c;
-      };
-      int e = rb;
-      // four masks and sender indices in flight at a time, taken in row order
-      for (; e + 4 <= re; e += 4) {
-        const uint32_t s0 = sel_bit(g, e, k), s1 = sel_bit(g, e + 1, k);
-        const uint32_t s2 = sel_bit(g, e + 2, k), s3 = sel_bit(g, e + 3, k);
-        const uint32_t i0 = (uint32_t)sender_index(g, direct, e, rb);
-        const uint32_t i1 = (uint32_t)sender_index(g, direct, e + 1, rb);
-        const uint32_t i2 = (uint32_t)sender_index(g, direct, e + 2, rb);
-        const uint32_t i3 = (uint32_t)sender_index(g, direct, e + 3, rb);
-        if (s0) take(i0);
-        if (s1) take(i1);
-        if (s2) take(i2);
-        if (s3) take(i3);
-      }
-      for (; e < re; ++e)
-        if (sel_bit(g, e, k)) take((uint32_t)sender_index(g, direct, e, rb));
-      // source shares come after the transported photons of the bin
-      bool recs = c > kWordEntries;
-      for (int q = g.em_ptr[j]; q < g.em_ptr[j + 1]; ++q)
-        if (g.em_k[q] == k) {
+      bool recs = false;
+      for (int e = rb; e < re; ++e) {
+        const uint32_t nib = block_bits(g, sm[e], kb);
+        if (nib == 0u) continue;
+        const int s = e - rb;
+        if (c < cap && s < kSlotRows) {
+          w |= (uint64_t)((uint32_t)s | (nib << 5)) << (eb * c);
+          ++c;
+        } else {
           recs = true;
-          if (rp < g.rec_cap) g.rec[rp++] = lbits | kRecEmission | (uint32_t)q;
+          const uint32_t idx = (uint32_t)sender_index(g, direct, e, rb);
+          for (int b = 0; b < BB; ++b) {
+            if (!((nib >> b) & 1u)) continue;
+            if (!FILL) ++rp[b];
+            else if (rp[b] < g.rec_cap) g.rec[rp[b]++] = lbits | ((uint32_t)b << 24) | idx;
+          }
         }
-      // bit 63: this (vertex, bin) has records to collect
+      }
+      // source shares come after the transported photons of the bin
+      for (int q = g.em_ptr[j]; q < g.em_ptr[j + 1]; ++q) {
+        const int p = g.bpos[g.em_k[q]];
+        if (p / BB != kb) continue;
+        recs = true;
+        const int b = p - kb * BB;
+        if (!FILL) ++rp[b];
+        else if (rp[b] < g.rec_cap)
+          g.rec[rp[b]++] = lbits | ((uint32_t)b << 24) | kRecEmission | (uint32_t)q;
+      }
+      // bit 63: this (vertex, block) has records to collect
       if (recs) w |= 1ull << 63;
     }
-    out[(int64_t)lane * g.bb] = w;
+    if (FILL) g.inw[((int64_t)tile * KB + kb) * kTile + lane] = w;
+  }
+  if (!FILL) {
+    for (int b = 0; b < BB; ++b) {
+      const int p = kb * BB + b;
+      if (p < K) g.rec_cnt[((int64_t)tile * K + p) * kRecGroups + grp] = rp[b];
+    }
   }
 }
 
@@ -462,8 +432,9 @@ __global__ void k_ebin_in(const GridDev *__restrict__ gp) {
 
 // Combined transport: the bins of sender i whose selection holds receiver
 // j, ascending, for every in-edge e = (j, slot of i): the set bits of the
-// in-edge's selection mask (a bin with m = 0 selects no slot).  One lane per
-// in-edge; pass 1 counts, pass 2 (after a scan) writes each list.
+// in-edge's selection mask (a bin with m = 0 selects no slot), each written
+// as its storage position.  One lane per in-edge; pass 1 counts, pass 2
+// (after a scan) writes each list.
 __global__ void k_kl_count(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -497,7 +468,7 @@ __global__ __launch_bounds__(256) void k_kl_fill(const GridDev *__restrict__ gp)
       uint32_t w = m[q];
       while (w) {
         const int bit = __ffs(w) - 1;
-        const uint8_t k = (uint8_t)(32 * q + bit);
+        const uint8_t k = g.bpos[32 * q + bit];   // stored by position
         if (staged) st[p - base] = k;
         else g.kl[p] = k;
         ++p;
@@ -540,8 +511,9 @@ __global__ void k_em_bins(GridDev *__restrict__ gp, int64_t n_em) {
   g.em_k[q] = best;
 }
 
-// Packed m(j, k), 2 bits per bin and 16 bins per word, from the selection:
-// one workgroup per tile and one wave per 16-bin word (thread = word * 64 +
+// Packed m(j, k), 2 bits per bin and 16 bins per word in storage order
+// (position p at bits 2 (p mod 16) of word p / 16), from the selection: one
+// workgroup per tile and one wave per 16-bin word (thread = word * 64 +
 // lane).
 static_assert((SX_MAX_BINS_FP32 + 15) / 16 <= 6 && (SX_MAX_BINS_FP64 + 15) / 16 <= 6,
               "k_mbits holds at most 6 m words per vertex (one wave each)");
@@ -552,25 +524,11 @@ __global__ __launch_bounds__(64 * 6) void k_mbits(GridDev *__restrict__ gp) {
   const int j = tile * kTile + lane;
   const int K = g.k;
   const int k0 = 16 * q;
+  // positions k0 .. k0 + 15 of the storage order
   uint32_t v[16];
-  if ((K & 3) == 0) {
-    // the row segment is 16-byte aligned: four 16-byte loads, each either
-    // wholly below K or skipped
-    typedef uint32_t U4 __attribute__((ext_vector_type(4)));
-    const U4 *f4 = (const U4 *)(g.fwd + (int64_t)j * K + k0);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const U4 x = (j < g.n && k0 + 4 * c < K) ? f4[c] : U4{0u, 0u, 0u, 0u};
-      v[4 * c] = x.x;
-      v[4 * c + 1] = x.y;
-      v[4 * c + 2] = x.z;
-      v[4 * c + 3] = x.w;
-    }
-  } else {
-#pragma unroll
-    for (int b = 0; b < 16; ++b)
-      v[b] = (j < g.n && k0 + b < K) ? g.fwd[(int64_t)j * K + k0 + b] : 0u;
-  }
+  for (int b = 0; b < 16; ++b)
+    v[b] = (j < g.n && k0 + b < K) ? g.fwd[(int64_t)j * K + g.bperm[k0 + b]] : 0u;
   uint32_t mword = 0;
 #pragma unroll
   for (int b = 0; b < 16; ++b) mword |= ((v[b] >> 21) & 3u) << (2 * b);
@@ -601,22 +559,25 @@ __global__ __launch_bounds__(64) void k_rebin(GridDev *__restrict__ gp, RebinMap
   const int K = g.k, KB = g.kb;
   const int par = g.parity;
   V *o = (V *)g.o[par];
+  // old m and holdings by (caller's) bin number, from storage order
   for (int w = 0; w < g.kw; ++w) {
     const uint32_t mw = g.mbits[((int64_t)tile * g.kw + w) * 64 + lane];
     for (int b = 0; b < 16 && 16 * w + b < K; ++b)
-      mo[(16 * w + b) * 64 + lane] = (uint8_t)((mw >> (2 * b)) & 3u);
+      mo[g.bperm[16 * w + b] * 64 + lane] = (uint8_t)((mw >> (2 * b)) & 3u);
   }
   for (int kb = 0; kb < KB; ++kb) {
     const V v = o[((int64_t)tile * KB + kb) * 64 + lane];
 #pragma unroll
     for (int b = 0; b < BB; ++b)
-      if (kb * BB + b < K) held[(kb * BB + b) * 64 + lane] = v[b];
+      if (kb * BB + b < K) held[g.bperm[kb * BB + b] * 64 + lane] = v[b];
   }
   const double T = (double)((const P *)g.t[par])[j];
   double esc = 0.0;
   uint32_t mword = 0;
   V out = V(0);
-  for (int kn = 0; kn < K; ++kn) {
+  // new bins in storage order: position p holds bin kn
+  for (int p = 0; p < K; ++p) {
+    const int kn = g.bperm[p];
     const uint32_t mn = j < g.n ? (g.fwd[(int64_t)j * K + kn] >> 21) & 3u : 0u;
     const int q0 = map.ptr[kn], q1 = map.ptr[kn + 1];
     P val;
@@ -635,14 +596,14 @@ __global__ __launch_bounds__(64) void k_rebin(GridDev *__restrict__ gp, RebinMap
         val = (P)(h / (double)mn);
       }
     }
-    out[kn % BB] = val;
-    if (kn % BB == BB - 1 || kn == K - 1) {
-      o[((int64_t)tile * KB + kn / BB) * 64 + lane] = out;
+    out[p % BB] = val;
+    if (p % BB == BB - 1 || p == K - 1) {
+      o[((int64_t)tile * KB + p / BB) * 64 + lane] = out;
       out = V(0);
     }
-    mword |= mn << (2 * (kn & 15));
-    if ((kn & 15) == 15 || kn == K - 1) {
-      g.mbits[((int64_t)tile * g.kw + kn / 16) * 64 + lane] = mword;
+    mword |= mn << (2 * (p & 15));
+    if ((p & 15) == 15 || p == K - 1) {
+      g.mbits[((int64_t)tile * g.kw + p / 16) * 64 + lane] = mword;
       mword = 0;
     }
   }
@@ -826,7 +787,17 @@ __device__ __forceinline__ double chem_step_r(double y, double nin, double dt,
 //    bins with no forward neighbour (m = 0, they leave the domain) add up.
 // 2. Chemistry in fp64 -> y, absorbed A, transmitted fraction T' of j.
 // 3. Per-tile photon accounting in fp64, fixed-order wave reduction.
-constexpr int kHaloPlane = kZeroSlot + 1;   // LDS words per staged bin
+// LDS of one wave of the tile code: the staged halo block (vertex-major, one
+// 16-byte block per halo vertex; entry kHaloMax reads 0), the halo index of
+// every row slot of every lane (row s at s * 64 + lane), and the hand-over
+// slots of the records.
+template <typename P>
+struct __attribute__((aligned(16))) TileLds {
+  static constexpr int BB = kBlockBytes / sizeof(P);
+  P h[(kHaloMax + 1) * BB];
+  uint16_t slot[kSlotRows * kTile];
+  P x[kTile * BB];
+};
 
 // What a combined-transport step hands the tile code (CT = true): whether
 // this lane's vertex is ballistic (then its bins are written as zeros and
@@ -967,18 +938,22 @@ __device__ __forceinline__ void dct_finish(const GridDev *__restrict__ G, int ti
 // gather, overflow records, outgoing photons; the sums go to bs.
 template <typename P, bool DIRECT, bool CT = false, bool NT = false>
 __device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int tile,
-                                           int lane, volatile SX_L P *hl,
-                                           volatile SX_L P *xchg, const CtIn<P> &ci,
+                                           int lane, SX_L TileLds<P> *L, const CtIn<P> &ci,
                                            int kb0, int kb1, int g0, int g1,
                                            BinSums<P> &bs) {
-  // hl and xchg carry data between lanes of this wave through LDS.  The
-  // accesses are volatile so that the compiler keeps every store and load in
-  // program order (it may not forward a lane's own store past another
-  // lane's); LDS executes a wave's operations in issue order.
+  // The LDS carries data between lanes of this wave.  The accesses are
+  // volatile so that the compiler keeps every store and load in program
+  // order (it may not forward a lane's own store past another lane's); LDS
+  // executes a wave's operations in issue order.
   constexpr int BB = kBlockBytes / sizeof(P);
   typedef P V __attribute__((ext_vector_type(BB)));
-  typedef uint64_t W2 __attribute__((ext_vector_type(2)));
   constexpr int NQ = DIRECT ? 1 : kStageQ;
+  constexpr int EB = inw_entry_bits(BB);
+  constexpr int NE = inw_entries(BB);
+  constexpr uint32_t EM = (1u << EB) - 1u;
+  volatile SX_L V *hl = (volatile SX_L V *)L->h;
+  volatile SX_L uint16_t *stab = (volatile SX_L uint16_t *)L->slot;
+  volatile SX_L P *xchg = (volatile SX_L P *)L->x;
   const int K = G->k;
   const int KB = G->kb;
   const int j = tile * kTile + lane;
@@ -990,8 +965,7 @@ __device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int ti
   const SX_G int32_t *__restrict__ nbr = gld(G->nbr);
   const SX_G int32_t *__restrict__ rowp = gld(G->row_ptr);
   const int rb = rowp[j];
-  const SX_G W2 *__restrict__ iw =
-      gld((const W2 *)(G->inw + ((int64_t)tile * KB * kTile + lane) * BB));
+  const SX_G uint64_t *__restrict__ iw = gld(G->inw + (int64_t)tile * KB * kTile + lane);
   const SX_G int32_t *__restrict__ rptr = gld(G->rec_ptr) + (int64_t)tile * K * kRecGroups;
   const SX_G uint32_t *__restrict__ rec = gld(G->rec);
   // first record of every block of the range, lane l holding block kb0 + l's
@@ -1004,7 +978,8 @@ __device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int ti
     return ((v >> 6) * (uint32_t)KB + (uint32_t)kb) * 64u + (v & 63u);
   };
 
-  // halo of the tile and its senders' T (once per step)
+  // halo of the tile and its senders' T (once per step), and the halo index
+  // of every row slot an in-word entry can name
   uint32_t hv[NQ];
   P th[NQ];
   if constexpr (!DIRECT) {
@@ -1019,9 +994,14 @@ __device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int ti
       hv[q] = idx < hlen ? (uint32_t)hvid[hp + idx] : zero;
       th[q] = tin[hv[q]];
     }
-    if (lane == 63) {
+    if (lane == 0) hl[kHaloMax] = V(0);
+    const int deg = valid ? rowp[j + 1] - rb : 0;
+    const SX_G uint16_t *__restrict__ eh = gld(G->edge_hidx) + rb;
 #pragma unroll
-      for (int b = 0; b < BB; ++b) hl[b * kHaloPlane + kZeroSlot] = P(0);
+    for (int s = 0; s < kSlotRows; ++s) {
+      uint16_t h = (uint16_t)kHaloMax;
+      if (s < deg) h = eh[s];
+      stab[s * kTile + lane] = h;
     }
   }
   // packed m(j, k), 16 bins per word, consumed 2 bits at a time from the
@@ -1036,7 +1016,7 @@ __device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int ti
 
   // ring of loads in flight, slot = block mod 2
   V st[2][NQ];
-  uint64_t wq[2][BB];
+  uint64_t wq[2];
   uint32_t rq[2];   // this lane's first record of the block (if lane < rn)
   int rn[2];        // records of the block
   int rs[2];        // index of the block's first record
@@ -1045,19 +1025,13 @@ __device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int ti
 #pragma unroll
       for (int q = 0; q < NQ; ++q) st[slot][q] = oin[blk(hv[q], kb)];
     }
-#pragma unroll
-    for (int h = 0; h < BB / 2; ++h) {
-      // in-words are read once per sweep.  With NT (the launch's photon
-      // planes fit in the last-level cache) they are loaded non-temporal, so
-      // that they do not displace the planes the next sweep reads back.
-      W2 w2;
-      if constexpr (NT)
-        w2 = __builtin_nontemporal_load(&iw[(int64_t)kb * kTile * (BB / 2) + h]);
-      else
-        w2 = iw[(int64_t)kb * kTile * (BB / 2) + h];
-      wq[slot][2 * h] = w2.x;
-      wq[slot][2 * h + 1] = w2.y;
-    }
+    // in-words are read once per sweep.  With NT (the launch's photon planes
+    // fit in the last-level cache) they are loaded non-temporal, so that they
+    // do not displace the planes the next sweep reads back.
+    if constexpr (NT)
+      wq[slot] = __builtin_nontemporal_load(&iw[(int64_t)kb * kTile]);
+    else
+      wq[slot] = iw[(int64_t)kb * kTile];
     const int r0 = __builtin_amdgcn_readlane(rpl, kb - kb0);
     const int nr = __builtin_amdgcn_readlane(rpl, kb - kb0 + 1) - r0;
     rn[slot] = nr;
@@ -1074,51 +1048,55 @@ __device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int ti
     // wave would stall on the loads it has just issued
     issue(kb + 1 < kb1 ? kb + 1 : kb, slot ^ 1);
     while (((bs.g + 1) * KB >> 2) <= kb) bs.close();
+    const uint64_t w = wq[slot];
     P acc[BB];
+#pragma unroll
+    for (int b = 0; b < BB; ++b) acc[b] = P(0);
     if constexpr (!DIRECT) {
-      // one LDS plane per bin of the block: a bin's reads spread over all
-      // 64 banks
+      // the halo's block, attenuated by each sender's T, one 16-byte entry
+      // per halo vertex
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const V v = st[slot][q];
+        V a;
 #pragma unroll
-        for (int b = 0; b < BB; ++b) hl[b * kHaloPlane + 64 * q + lane] = mul_rn(v[b], th[q]);
+        for (int b = 0; b < BB; ++b) a[b] = mul_rn(v[b], th[q]);
+        hl[64 * q + lane] = a;
       }
       __builtin_amdgcn_wave_barrier();
+      // every entry: its sender's block from LDS, added to the bins it
+      // sends (an entry without bins adds zeros)
 #pragma unroll
-      for (int b = 0; b < BB; ++b) {
-        const uint64_t w = wq[slot][b];
-        P a = P(0);
+      for (int e = 0; e < NE; ++e) {
+        const uint32_t x = (uint32_t)(w >> (EB * e)) & EM;
+        const uint32_t h = stab[(x & 31u) * kTile + lane];
+        const V v = hl[h];
 #pragma unroll
-        for (int e = 0; e < kWordEntries; ++e)
-          a += hl[b * kHaloPlane + ((uint32_t)(w >> (9 * e)) & 511u)];
-        acc[b] = a;
+        for (int b = 0; b < BB; ++b) acc[b] += ((x >> (5 + b)) & 1u) ? v[b] : P(0);
       }
     } else {
-      const SX_G P *__restrict__ oin_p = (const SX_G P *)oin;
 #pragma unroll
-      for (int b = 0; b < BB; ++b) {
-        const uint64_t w = wq[slot][b];
-        P a = P(0);
+      for (int e = 0; e < NE; ++e) {
+        const uint32_t x = (uint32_t)(w >> (EB * e)) & EM;
+        const uint32_t nib = x >> 5;
+        if (nib != 0u) {
+          const uint32_t src = (uint32_t)nbr[rb + (int)(x & 31u)];
+          const V v = oin[blk(src, kb)];
+          const P t = tin[src];
 #pragma unroll
-        for (int e = 0; e < kWordEntries; ++e) {
-          const uint32_t idx = (uint32_t)(w >> (9 * e)) & 511u;
-          if (idx != 511u) {
-            const uint32_t src = (uint32_t)nbr[rb + idx];
-            a += mul_rn(oin_p[blk(src, kb) * BB + b], tin[src]);
-          }
+          for (int b = 0; b < BB; ++b)
+            if ((nib >> b) & 1u) acc[b] += mul_rn(v[b], t);
         }
-        acc[b] = a;
       }
     }
-    // The block's records (senders beyond an in-word's seventh, then source
+    // The block's records (senders beyond the in-word's entries, then source
     // shares), sorted by bin then receiver: lane r fetches record r's
     // photons, runs of one receiver and bin are summed by a segmented scan
     // across lanes (DPP, no LDS), and the last lane of each run hands the
-    // sum over through LDS.  With at most 64 records, only receivers whose
-    // in-word flags records (bit 63) read the hand-over slots, so they need
-    // no clearing; a larger block clears them for every 64.
+    // sum over through LDS.  Receivers whose in-word flags records (bit 63)
+    // clear their hand-over slots first and read them back after.
     const int nrec = __builtin_amdgcn_readfirstlane(rn[slot]);
+    const bool fl = (w >> 63) != 0ull;
     for (int c0 = 0; c0 < nrec; c0 += 64) {
       const uint32_t r = lane >= nrec - c0 ? ~0u
                          : (c0 == 0 ? rq[slot] : rec[rs[slot] + c0 + lane]);
@@ -1132,7 +1110,7 @@ __device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int ti
         if (r & kRecEmission) {
           v = (P)ema[idx];
         } else if constexpr (!DIRECT) {
-          v = hl[rb_ * kHaloPlane + idx];
+          v = ((volatile SX_L P *)hl)[idx * BB + rb_];
         } else {
           const uint32_t src = (uint32_t)nbr[rowp[tile * kTile + (int)(r >> 26)] + idx];
           v = mul_rn(((const SX_G P *)oin)[blk(src, kb) * BB + rb_], tin[src]);
@@ -1140,20 +1118,16 @@ __device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int ti
       }
       const int knext = dpp_i32<kDppWaveShl1, 0xF>(-3000, key);
       if (__ballot(has && knext == key)) seg_scan<P>(v, key);
-      const bool many = nrec > 64;
-      if (many) *(volatile SX_L V *)(xchg + lane * BB) = V(0);
+      // with more than 64 records every lane takes part in every round
+      const bool take = fl || nrec > 64;
+      if (take) *(volatile SX_L V *)(xchg + lane * BB) = V(0);
       __builtin_amdgcn_wave_barrier();
       if (has && knext != key) xchg[(int)(r >> 26) * BB + rb_] = v;
       __builtin_amdgcn_wave_barrier();
-      uint32_t fl = 0;
-#pragma unroll
-      for (int b = 0; b < BB; ++b) fl |= (uint32_t)(wq[slot][b] >> 63) << b;
-      if (many) fl = (1u << BB) - 1u;
-      if (fl) {
+      if (take) {
         const V got = *(volatile SX_L V *)(xchg + lane * BB);
 #pragma unroll
-        for (int b = 0; b < BB; ++b)
-          if ((fl >> b) & 1u) acc[b] += got[b];
+        for (int b = 0; b < BB; ++b) acc[b] += got[b];
       }
       __builtin_amdgcn_wave_barrier();
     }
@@ -1209,11 +1183,10 @@ __device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int ti
 // the direction-conserving part of a combined-transport tile.
 template <typename P, bool DIRECT, bool CT = false, bool NT = false>
 __device__ __forceinline__ void sweep_tile(const GridDev *__restrict__ G, int tile,
-                                           int lane, volatile SX_L P *hl,
-                                           volatile SX_L P *xchg,
+                                           int lane, SX_L TileLds<P> *L,
                                            const CtIn<P> &ci = CtIn<P>()) {
   BinSums<P> bs;
-  sweep_bins<P, DIRECT, CT, NT>(G, tile, lane, hl, xchg, ci, 0, G->kb, 0, 4, bs);
+  sweep_bins<P, DIRECT, CT, NT>(G, tile, lane, L, ci, 0, G->kb, 0, 4, bs);
   if constexpr (CT) {
     P nin_p = bs.tot_n, esc_p = bs.tot_e;
     if (ci.bal) {
@@ -1244,10 +1217,8 @@ __global__ __launch_bounds__(64 * TPB, 4) void k_sweep(
     int32_t n_tiles, const int32_t *__restrict__ adv, int32_t n_adv,
     uint32_t *__restrict__ done, int32_t xcd_remap) {
   static_assert((S == 1 || S == 2 || S == 4) && TPB % S == 0, "split");
-  constexpr int BB = kBlockBytes / sizeof(P);
   constexpr int GPW = 4 / S;   // BinSums groups per wave
-  __shared__ P hbuf[TPB][kHaloPlane * BB];
-  __shared__ P xbuf[TPB][kTile * BB];
+  __shared__ TileLds<P> lds[TPB];
   __shared__ int last;
   const int lane = threadIdx.x & 63;
   const int wave = TPB == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1270,19 +1241,19 @@ __global__ __launch_bounds__(64 * TPB, 4) void k_sweep(
     G = grids + gi;
     if (G->remaining > 0) {
       act = true;
-      volatile SX_L P *hl = (volatile SX_L P *)hbuf[wave];
-      volatile SX_L P *xc = (volatile SX_L P *)xbuf[wave];
+      SX_L TileLds<P> *L = (SX_L TileLds<P> *)&lds[wave];
+      volatile SX_L P *hl = (volatile SX_L P *)L->h;
       const int KB = G->kb;
       const int kb0 = part * KB / S, kb1 = (part + 1) * KB / S;
       if (gld(G->tile_direct)[tile] != 0)
-        sweep_bins<P, true, false, NT>(G, tile, lane, hl, xc, CtIn<P>(), kb0, kb1,
+        sweep_bins<P, true, false, NT>(G, tile, lane, L, CtIn<P>(), kb0, kb1,
                                        part * GPW, (part + 1) * GPW, bs);
       else
-        sweep_bins<P, false, false, NT>(G, tile, lane, hl, xc, CtIn<P>(), kb0, kb1,
+        sweep_bins<P, false, false, NT>(G, tile, lane, L, CtIn<P>(), kb0, kb1,
                                         part * GPW, (part + 1) * GPW, bs);
       if constexpr (S > 1) {
-        // hand the group sums over in this wave's halo planes (its last
-        // block has read them)
+        // hand the group sums over in this wave's halo block (its last
+        // block has read it)
         if (part > 0) {
           hl[lane] = bs.hn0;
           hl[128 + lane] = bs.he0;
@@ -1299,7 +1270,7 @@ __global__ __launch_bounds__(64 * TPB, 4) void k_sweep(
     if constexpr (S > 1) {
 #pragma unroll
       for (int q = 1; q < S; ++q) {
-        const volatile SX_L P *o = (const volatile SX_L P *)hbuf[wave + q];
+        const volatile SX_L P *o = (const volatile SX_L P *)lds[wave + q].h;
 #pragma unroll
         for (int g = 0; g < GPW; ++g) {
           bs.tot_n += o[64 * g + lane];
@@ -1374,8 +1345,7 @@ __device__ __forceinline__ P div_m(P v, uint32_t m) {
 
 template <typename P, bool NT>
 __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int tile,
-                                              int lane, SX_L P *veb,
-                                              volatile SX_L P *hl, volatile SX_L P *xc) {
+                                              int lane, SX_L P *veb, SX_L TileLds<P> *L) {
   constexpr int BB = kBlockBytes / sizeof(P);
   typedef P V __attribute__((ext_vector_type(BB)));
   const int KB = G->kb;
@@ -1406,10 +1376,10 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
   SX_G P *__restrict__ xin = gst((P *)G->xin);
   const SX_G P *__restrict__ dshin = gld((const P *)G->dsh[par]);
   const bool diffuse = G->diffuse != 0;
-  // element (v, k) of the bin field
-  auto at = [&](uint32_t v, int k) -> uint32_t {
-    return (((v >> 6) * (uint32_t)KB + (uint32_t)(k / BB)) * 64u + (v & 63u)) * BB +
-           (uint32_t)(k % BB);
+  // element (v, bin at storage position p) of the bin field
+  auto at = [&](uint32_t v, int p) -> uint32_t {
+    return (((v >> 6) * (uint32_t)KB + (uint32_t)(p / BB)) * 64u + (v & 63u)) * BB +
+           (uint32_t)(p % BB);
   };
   const bool direct = gld(G->tile_direct)[tile] != 0;
 
@@ -1435,7 +1405,7 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
       if (idx < hlen && lin[hvid[hp + idx]] != 0) edges = true;
     }
     if (__ballot(edges) == 0) {
-      sweep_tile<P, false, false, NT>(G, tile, lane, hl, xc);
+      sweep_tile<P, false, false, NT>(G, tile, lane, L);
       if (valid) lout[j] = 0;
       return;
     }
@@ -1532,9 +1502,9 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
         ci.nin_b += ve;
         ci.esc_b += bmv[e] == 0 ? ve : P(0);
       } else if (ve != P(0)) {
-        const int k = ebin_in[e];
-        xin[at((uint32_t)j, k)] += ve;
-        ci.xmask |= 1ull << (k / BB);
+        const int p = G->bpos[ebin_in[e]];
+        xin[at((uint32_t)j, p)] += ve;
+        ci.xmask |= 1ull << (p / BB);
       }
     }
   }
@@ -1556,24 +1526,20 @@ __device__ __forceinline__ void sweep_tile_ct(const GridDev *__restrict__ G, int
     return;
   }
   if (direct)
-    sweep_tile<P, true, true, NT>(G, tile, lane, hl, xc, ci);
+    sweep_tile<P, true, true, NT>(G, tile, lane, L, ci);
   else
-    sweep_tile<P, false, true, NT>(G, tile, lane, hl, xc, ci);
+    sweep_tile<P, false, true, NT>(G, tile, lane, L, ci);
   if (valid) lout[j] = bal ? 1 : 0;
 }
 
 // LDS of one combined-transport workgroup: the per-edge sums of the edge
-// phase share their space with the tile code's halo planes (the sums are
-// read before the tile code stages its first block, with a barrier
-// between), then the hand-over slots.
+// phase share their space with the tile code's LDS (the sums are read
+// before the tile code writes its slot table and stages its first block,
+// with a barrier between).
 template <typename P>
-struct CtLds {
-  static constexpr int BB = kBlockBytes / sizeof(P);
-  union {
-    P h[kHaloPlane * BB];
-    P ve[kVeCap];
-  };
-  P x[kTile * BB];
+union CtLds {
+  TileLds<P> t;
+  P ve[kVeCap];
 };
 
 // One combined-transport step over a tile list: one tile per workgroup of
@@ -1598,8 +1564,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
     const GridDev *__restrict__ G = grids + gi;
     if (G->remaining > 0)
-      sweep_tile_ct<P, NT>(G, tile, lane, (SX_L P *)lds.ve, (volatile SX_L P *)lds.h,
-                       (volatile SX_L P *)lds.x);
+      sweep_tile_ct<P, NT>(G, tile, lane, (SX_L P *)lds.ve, (SX_L TileLds<P> *)&lds.t);
   }
   __syncthreads();
   if (threadIdx.x == 0)
@@ -1728,15 +1693,15 @@ hipError_t launch_edge_bins(const GridDev *dg, const GridDev &hg,
 
 hipError_t launch_inlist_count(const GridDev *dg, const GridDev &hg,
                                hipStream_t s) {
-  // one thread per (tile, group, 32-bin mask word)
-  hipLaunchKernelGGL(k_inlist_count,
-                     dim3(blocks_for((int64_t)hg.ntiles * kRecGroups * ((hg.k + 31) / 32), 256)),
+  // one thread per (tile, block, group of receivers)
+  hipLaunchKernelGGL(k_inlist<false>,
+                     dim3(blocks_for((int64_t)hg.ntiles * hg.kb * kRecGroups, 256)),
                      dim3(256), 0, s, dg);
   return hipGetLastError();
 }
 
 hipError_t launch_clear_inw(const GridDev &hg, hipStream_t s) {
-  return fill<uint64_t>(hg.inw, kEmptyWord, (int64_t)hg.ntiles * hg.kb * kTile * hg.bb, s);
+  return fill<uint64_t>(hg.inw, 0ull, (int64_t)hg.ntiles * hg.kb * kTile, s);
 }
 
 hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s) {
@@ -1790,9 +1755,9 @@ hipError_t launch_scan(int32_t *cnt, int32_t *ptr, int64_t *part, int32_t n,
 
 hipError_t launch_inlist_fill(const GridDev *dg, const GridDev &hg,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_inlist_fill,
-                     dim3(blocks_for((int64_t)hg.ntiles * hg.k * kRecGroups, 256)), dim3(256),
-                     0, s, dg);
+  hipLaunchKernelGGL(k_inlist<true>,
+                     dim3(blocks_for((int64_t)hg.ntiles * hg.kb * kRecGroups, 256)),
+                     dim3(256), 0, s, dg);
   return hipGetLastError();
 }
 

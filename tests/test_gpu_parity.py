@@ -258,8 +258,24 @@ def test_direct_gather_path_matches(sxctx, monkeypatch):
 
 
 def test_many_records_per_bin(sxctx):
-    """A coarse grid where hull vertices receive a bin from many senders:
-    more than 64 senders-beyond-the-seventh in one (tile, bin)."""
+    """A coarse grid where hull vertices receive a bin from many senders."""
     w = G.small_random(400, seed=61, n_bins=84, box=3e21, rate=1e48, n_src=4)
     got, ref, tab, ot, unit = _both(sxctx, w, 15)
     assert_state_close(got, ref, 0, unit, "records")
+
+
+@pytest.mark.parametrize("entries", [0, 2])
+@pytest.mark.parametrize("prec", [G.SX_FP64, G.SX_FP32_TRANSPORT])
+def test_senders_as_records(sxctx, monkeypatch, entries, prec):
+    """In-words cut to `entries` senders, so that the rest of every
+    (vertex, block) goes through the record path: with none, every sender of
+    every tile is a record, well over 64 per (tile, block).  The staged and
+    the direct gathers both match the oracle."""
+    w = G.small_random(700, seed=62, n_bins=42, box=3e21, rate=1e48, n_src=3,
+                       precision=prec)
+    monkeypatch.setenv("SX_INW_ENTRIES", str(entries))
+    got, ref, tab, ot, unit = _both(sxctx, w, 12)
+    assert_state_close(got, ref, prec, unit, f"records only ({entries} entries)")
+    monkeypatch.setenv("SX_FORCE_DIRECT", "1")
+    got, ref, tab, ot, unit = _both(sxctx, w, 12)
+    assert_state_close(got, ref, prec, unit, f"direct, records ({entries} entries)")
