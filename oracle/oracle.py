@@ -65,6 +65,8 @@ def _load(path=None):
         lib.ora_get_diffuse.argtypes = [P, P]
         lib.ora_set_diffuse_pending.restype = None
         lib.ora_set_diffuse_pending.argtypes = [P, P]
+        lib.ora_set_hops.restype = C.c_int
+        lib.ora_set_hops.argtypes = [P, C.c_int32]
         lib.ora_set_dct_reference.restype = C.c_int
         lib.ora_set_dct_reference.argtypes = [P, C.c_int32]
         lib.ora_set_transport.restype = C.c_int
@@ -142,6 +144,8 @@ class Oracle:
         self.combined = int(getattr(w, "transport", 0)) == 1
         if self.combined:
             lib.ora_set_transport(h, 1, float(w.tau_switch))
+        if int(getattr(w, "hops", 1)) > 1:
+            self.set_hops(int(w.hops))
 
     def run(self, n_sweeps: int, history: bool = False):
         hist = np.zeros((n_sweeps, 4)) if history else None
@@ -184,6 +188,11 @@ class Oracle:
 
     def set_diffuse_pending(self, pending):
         self._lib.ora_set_diffuse_pending(self._h, _p(np.ascontiguousarray(pending, np.float64)))
+
+    def set_hops(self, hops: int):
+        """Hops per step (multi-hop steps, Sect. 4.6); every sweep is a hop."""
+        if self._lib.ora_set_hops(self._h, int(hops)) != 0:
+            raise ValueError("oracle: " + self._lib.ora_last_error().decode())
 
     def set_transport(self, combined: bool, tau_switch: float = 1.0):
         """Switch between direction-conserving and combined transport."""

@@ -64,6 +64,10 @@ struct ora_grid {
      * alpha_A == 0 (on the spot). */
     double alpha_A;
     double *D;           /* [N] recombination photons to send next sweep */
+    /* Multi-hop steps (Sect. 4.6); one hop per step while hops <= 1. */
+    int32_t hops;
+    double *habs;        /* [N] photons absorbed so far in the current step */
+    double *hnin;        /* [N] photons that arrived so far in the step */
     /* Timing-only pull form (ora_run_threads): senders of each receiver,
      * built on first use from the current routing; NULL when stale. */
     int64_t *pull_ptr;
@@ -195,6 +199,34 @@ static double chem(double y, double n_in, double dt, double nHV, double tau,
     *A = abs_sum;
     *T = (n_in > 0.0) ? tr_sum / (double)n_sub : 1.0;
     if (Rsum) *Rsum = rec_sum;
+    return y;
+}
+
+/* Multi-hop steps (Sect. 4.6: the subcycled chemistry allows a radiative
+ * transfer step in which photons cross more than one Delaunay edge; the
+ * paper's tests do not do it and the paper does not fix the scheme).
+ * Reading: a step of dt is H hops.  Photons move one edge per hop, sources
+ * emit N_dot dt / H per hop, and the neutral fraction y of a vertex is
+ * updated once, after the last hop.  During the step a vertex absorbs from
+ * each hop's photons the fraction 1 - exp(-y tau) of Eq. intensity_absorbed
+ * with y frozen at its value at the start of the step, but never more atoms
+ * than it had neutral at the start (n_H V y, less what it absorbed in the
+ * earlier hops of the step); the rest goes on (Eq. intensity_out).  After
+ * the last hop the absorbed photons ionise exactly as many atoms, spread
+ * evenly over the n_sub substeps, and the recombinations are taken backward
+ * Euler per substep:
+ *     y' = y - i + h b (1 - y')^2,  i = A / (n_H V n_sub),
+ * whose root in [0, 1] is y' = 1 - z with z = 2c / (1 + sqrt(1 + 4 h b c)),
+ * c = 1 - y + i (z = c when h b = 0).  Photons are conserved exactly
+ * (absorbed = ionisations), and y' >= 0 since A <= n_H V y. */
+static double chem_fixed(double y, double ion, double hb, int n_sub) {
+    double is = ion / (double)n_sub;
+    for (int s = 0; s < n_sub; s++) {
+        double c = (1.0 - y) + is;
+        double z = hb > 0.0 ? (2.0 * c) / (1.0 + sqrt(1.0 + 4.0 * hb * c)) : c;
+        y = 1.0 - z;
+        if (y < 0.0) y = 0.0;
+    }
     return y;
 }
 
@@ -428,9 +460,13 @@ static void sweep(ora_grid *g) {
      * receiver files them in the bin closest to the beam's direction, the
      * direction they travel in (reading: the bin of the edge would turn a
      * collimated beam into a fan of edge directions). */
+    /* which hop of the step this sweep is (multi-hop steps) */
+    int32_t H = g->hops > 1 ? g->hops : 1;
+    int32_t hop = (int32_t)fmod(g->sweeps, (double)H);
     for (int32_t s = 0; s < g->n_src; s++) {
         int64_t v = g->src_v[s];
         double E = g->src_rate[s] * g->dt;
+        if (H > 1) E = E / (double)H;
         g->emitted += E;
         const double *d = &g->src_dir[3 * s];
         int64_t b = g->ptr[v], deg = g->ptr[v + 1] - g->ptr[v];
@@ -459,12 +495,39 @@ static void sweep(ora_grid *g) {
     for (int64_t j = 0; j < n; j++) {
         double nin = 0.0;
         for (int64_t k = 0; k < K; k++) nin += g->I[j * K + k];
-        g->nin[j] = nin;
         double A, T, R;
-        g->y[j] = chem(g->y[j], nin, g->dt, g->nH[j] * g->vol[j], g->tau[j],
-                       recomb_coeff(g) * g->nH[j], g->n_sub, &A, &T, &R);
-        g->absorbed += A;
-        diffuse_made(g, j, R);
+        if (H > 1) {
+            /* a hop of a multi-hop step: absorption at the frozen y, capped
+             * by the atoms left; the chemistry after the last hop */
+            double nHV = g->nH[j] * g->vol[j];
+            double y0 = g->y[j];
+            double cap = nHV * y0 - g->habs[j];
+            if (cap < 0.0) cap = 0.0;
+            /* passed on: exp(-y tau) of the photons, or all beyond the cap */
+            T = exp(-y0 * g->tau[j]);
+            double a = nin - nin * T;
+            if (a > cap) {
+                a = cap;
+                T = (nin - a) / nin;
+            }
+            g->habs[j] += a;
+            g->hnin[j] += nin;
+            A = a;
+            if (hop == H - 1) {
+                double hb = (g->dt / (double)g->n_sub) * (g->alpha_B * g->nH[j]);
+                g->y[j] = chem_fixed(y0, g->habs[j] / nHV, hb, g->n_sub);
+                g->nin[j] = g->hnin[j];
+                g->habs[j] = 0.0;
+                g->hnin[j] = 0.0;
+            }
+            g->absorbed += A;
+        } else {
+            g->nin[j] = nin;
+            g->y[j] = chem(g->y[j], nin, g->dt, g->nH[j] * g->vol[j], g->tau[j],
+                           recomb_coeff(g) * g->nH[j], g->n_sub, &A, &T, &R);
+            g->absorbed += A;
+            diffuse_made(g, j, R);
+        }
         for (int64_t k = 0; k < K; k++) {
             double out = g->I[j * K + k] * T;
             int32_t mm = g->m[j * K + k];
@@ -643,6 +706,10 @@ int ora_set_diffuse(ora_grid *g, double alpha_A) {
         snprintf(g_err, sizeof g_err, "alpha_A must be 0 or >= alpha_B");
         return -1;
     }
+    if (alpha_A > 0.0 && g->hops > 1) {
+        snprintf(g_err, sizeof g_err, "diffuse radiation takes one hop per step");
+        return -1;
+    }
     g->alpha_A = alpha_A;
     if (alpha_A > 0.0 && !g->D) g->D = (double *)xcalloc(g->n, sizeof(double));
     return 0;
@@ -656,6 +723,28 @@ void ora_get_diffuse(const ora_grid *g, double *pending) {
 void ora_set_diffuse_pending(ora_grid *g, const double *pending) {
     if (!g->D || !pending) return;
     memcpy(g->D, pending, (size_t)g->n * sizeof(double));
+}
+
+/* Hops per step (multi-hop steps, see chem_fixed); 1 is the paper's one
+ * hop per step.  Direction-conserving, on-the-spot grids only; the next
+ * sweep starts a step. */
+int ora_set_hops(ora_grid *g, int32_t hops) {
+    g_err[0] = 0;
+    if (hops < 1 || (hops > 1 && (g->combined || g->alpha_A > 0.0))) {
+        snprintf(g_err, sizeof g_err,
+                 "hops must be >= 1, and 1 with combined transport or diffuse radiation");
+        return -1;
+    }
+    g->hops = hops;
+    if (hops > 1 && !g->habs) {
+        g->habs = (double *)xcalloc(g->n, sizeof(double));
+        g->hnin = (double *)xcalloc(g->n, sizeof(double));
+    }
+    if (g->habs) {
+        memset(g->habs, 0, (size_t)g->n * sizeof(double));
+        memset(g->hnin, 0, (size_t)g->n * sizeof(double));
+    }
+    return 0;
 }
 
 int ora_set_dct_reference(ora_grid *g, int32_t edge) {
@@ -673,6 +762,10 @@ int ora_set_transport(ora_grid *g, int32_t combined, double tau_switch) {
     g_err[0] = 0;
     if (combined != 0 && combined != 1) {
         snprintf(g_err, sizeof g_err, "bad transport");
+        return -1;
+    }
+    if (combined && g->hops > 1) {
+        snprintf(g_err, sizeof g_err, "combined transport takes one hop per step");
         return -1;
     }
     g->combined = combined;
@@ -750,7 +843,7 @@ static ora_inlist build_inlist(const ora_grid *g) {
 }
 
 int ora_run_threads(ora_grid *g, int32_t n_sweeps, int32_t threads) {
-    if (g->combined || g->alpha_A > 0.0 || threads < 1) return -1;
+    if (g->combined || g->alpha_A > 0.0 || g->hops > 1 || threads < 1) return -1;
     int64_t n = g->n, K = g->K;
     if (!g->pull_ptr) {
         ora_inlist B = build_inlist(g);
@@ -968,6 +1061,7 @@ void ora_free(ora_grid *g) {
     free(g->src_dir); free(g->y); free(g->O); free(g->I); free(g->nin);
     free(g->rev); free(g->bsel); free(g->bm); free(g->Oe); free(g->Ie);
     free(g->layout); free(g->mode); free(g->D);
+    free(g->habs); free(g->hnin);
     drop_pull(g);
     free(g);
 }

@@ -96,6 +96,15 @@ void ora_set_diffuse_pending(ora_grid *g, const double *pending);
  * (largest cosine, > cos_min, ties to the lower id): the bin then goes to
  * the neighbours most aligned with that edge.  Rebuilds the routing; call
  * before the first sweep.  Returns 0, or -1 for a bad argument. */
+/* Multi-hop steps (Sect. 4.6): hops per step, >= 1 (1: one edge per step,
+ * the paper's tests).  With hops H > 1 every sweep is one hop; sources emit
+ * N_dot dt / H per hop; each vertex absorbs at the neutral fraction of the
+ * start of the step, capped by the atoms it had neutral, and its neutral
+ * fraction is updated once, after the step's last hop, from the photons it
+ * absorbed (ionisations = absorbed photons).  Direction-conserving,
+ * on-the-spot grids only.  Returns 0, or -1 (ora_last_error). */
+int ora_set_hops(ora_grid *g, int32_t hops);
+
 int ora_set_dct_reference(ora_grid *g, int32_t edge);
 
 /* Combined transport (Sects. 2.2.2-2.2.4).  combined = 1: from the next

@@ -64,6 +64,7 @@ class Workload:
     tau_switch: float = 1.0
     dct_reference: int = SX_DCT_REF_BIN
     alpha_A: float = 0.0             # > 0: diffuse recombination radiation
+    hops: int = 1                    # edges photons cross per step (multi-hop)
     box: float = 0.0
     meta: dict = field(default_factory=dict)
 

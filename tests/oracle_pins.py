@@ -695,6 +695,115 @@ def pin_rotation_conservation(lib=None):
     assert abs(h[0, 0] - (h[0, 1] + h[0, 2] + h[0, 3])) <= 1e-12 * h[0, 0]
 
 
+# ------------------------------------------------------ multi-hop steps ---
+
+def _hop_count(S, H, j):
+    """Packets (one per hop, from hop g = 0, 1, ...) that reach vertex j of
+    the chain (one edge per hop: hop g + j - 1) within step S (hops
+    (S - 1) H .. S H - 1)."""
+    lo = max(0, (S - 1) * H - j + 1)
+    hi = S * H - j
+    return max(0, hi - lo + 1)
+
+
+def pin_multihop_chain(lib=None):
+    """Multi-hop steps (Sect. 4.6: photons may cross more than one edge per
+    step): on a straight chain with a weak source, a step of H hops carries
+    the source's N_dot dt / H of every hop up to H edges, each vertex passing
+    on exp(-y tau) of what reaches it (y frozen over the step; a weak source
+    leaves y = 1 to 1e-20).  The photons that reach vertex j within step S
+    are counted by hand from the hop each packet was sent at."""
+    n = 14
+    sp = 3e21
+    rng = np.random.default_rng(2)
+    nH = 10 ** rng.uniform(-4, -2.5, n)
+    for H in (2, 3, 5):
+        w = G.chain_graph(n, sp, 1e-3, sp ** 3)
+        w = G.with_(w, n_H=nH, src_rate=np.array([1e30]), dt=1e10, hops=H)
+        o = Oracle(w, lib)
+        E = 1e30 * 1e10
+        tau = nH * G.SIGMA_H * sp
+        for S in range(1, 6):
+            o.run(H)
+            st = o.state()
+            nin = st["nin"]
+            assert nin[0] == 0.0
+            for j in range(1, n):
+                want = E / H * math.exp(-float(np.sum(tau[1:j]))) * _hop_count(S, H, j)
+                assert abs(nin[j] - want) <= 1e-9 * want + 1e-300, (H, S, j, nin[j], want)
+            t = st["tallies"]
+            assert abs(t["emitted"] - S * E) <= 1e-12 * S * E
+
+
+def pin_multihop_atom_budget(lib=None):
+    """A multi-hop step ionises no more atoms than a vertex holds (the
+    absorption cap of the frozen-state reading): with no recombination and a
+    source far brighter than a cell's atoms, each hop's photons ionise the
+    next vertex completely and pass the rest on, so after one step of H hops
+    the first H vertices are fully ionised, the rest untouched, and exactly
+    H cells' worth of atoms were absorbed."""
+    n = 12
+    sp = 3e21
+    V = sp ** 3
+    nH = 1e-3
+    atoms = nH * V
+    for H in (2, 4):
+        w = G.chain_graph(n, sp, nH, V)
+        w = G.with_(w, src_rate=np.array([1e5 * atoms / 1e10]), dt=1e10, alpha_B=0.0, hops=H)
+        o = Oracle(w, lib)
+        o.run(H)
+        st = o.state()
+        y = st["y"]
+        assert np.all(y[1:H + 1] <= 1e-12), y[1:H + 1]
+        assert np.all(y[H + 1:] == 1.0) and y[0] == 1.0
+        t = st["tallies"]
+        assert abs(t["absorbed"] - H * atoms) <= 1e-12 * H * atoms, (t["absorbed"], H * atoms)
+        r = t["emitted"] - (t["absorbed"] + t["escaped"] + t["in_flight"])
+        assert abs(r) <= 1e-12 * t["emitted"]
+
+
+def pin_multihop_conservation(lib=None):
+    """Photons are conserved at every hop of multi-hop steps, with isotropic
+    and beam sources, while the fronts ionise the grid."""
+    w = G.small_random(600, seed=9, n_bins=42, box=3e21, n_H=1e-3, rate=1e48,
+                       n_src=3, dt=1.2e14)
+    sd = np.zeros((3, 3))
+    sd[2] = [1.0, 0.0, 0.0]
+    for H in (2, 5):
+        h = Oracle(G.with_(w, src_dir=sd, hops=H), lib).run(10 * H, history=True)
+        res = h[:, 0] - (h[:, 1] + h[:, 2] + h[:, 3])
+        assert np.all(np.abs(res) <= 1e-12 * h[:, 0]), res / h[:, 0]
+        assert h[-1, 1] > 0 and h[-1, 3] > 0
+
+
+def pin_multihop_front_law(lib=None):
+    """Test 1 with a 25 Myr step (20 steps over 500 Myr).  With one edge per
+    step the front cannot keep up (the paper's remark on large steps, Sect.
+    5.1.3): it lags the law of Eq. IFront_pos by over 30% at 25 and 75 Myr.
+    With 10 hops per step it stays within 8% of the law from 60 Myr on, the
+    bound of the one-hop test at a 2.5 Myr step."""
+    base = G.config1()
+    nh, rate = base.meta["n_H"], base.meta["rate"]
+    r_s = A.stromgren_radius(rate, nh, base.alpha_B)
+    t_rec = A.recombination_time(nh, base.alpha_B)
+    steps = 20
+    dt = 500.0 * G.MYR_S / steps
+    out = {}
+    for H in (1, 10):
+        o = Oracle(G.with_(base, dt=dt, n_sweeps=steps * H, hops=H), lib)
+        r = []
+        for s in range(steps):
+            o.run(H)
+            t = (s + 1) * dt
+            r.append(A.ionised_volume_radius(base.volume, o.state()["x"])
+                     / A.front_radius(t, r_s, t_rec))
+        out[H] = np.array(r)
+    assert out[1][0] < 0.7 and out[1][2] < 0.7, out[1][:3]
+    late = (np.arange(1, steps + 1) * dt) >= 60.0 * G.MYR_S
+    assert np.all(np.abs(out[10][late] - 1.0) <= 0.08), out[10]
+    return out
+
+
 FAST_PINS = [pin_recombination_closed_form, pin_equilibrium_fixed_point,
              pin_ode_convergence, pin_photon_accounting,
              pin_selection_brute_force, pin_axis_star, pin_ties,
@@ -703,4 +812,5 @@ FAST_PINS = [pin_recombination_closed_form, pin_equilibrium_fixed_point,
              pin_combined_conservation, pin_edge_reference_brute_force,
              pin_diffuse_off_is_on_the_spot, pin_diffuse_recombination_budget,
              pin_diffuse_lattice, pin_diffuse_conservation, pin_beam_filing,
-             pin_rotation_symmetry, pin_rotation_conservation]
+             pin_rotation_symmetry, pin_rotation_conservation,
+             pin_multihop_chain, pin_multihop_atom_budget, pin_multihop_conservation]

@@ -70,6 +70,11 @@ MUTANTS = {
                                        "if (to[k] == kn) held = O_old"),
     "rotation_escape_not_tallied": ("g->escaped += held;\n                g->in_flight -= held;",
                                     "g->in_flight -= held;"),
+    "multihop_emission_not_split": ("if (H > 1) E = E / (double)H;", "if (H > 1) E = E;"),
+    "multihop_no_atom_cap": ("            if (a > cap) {\n                a = cap;",
+                             "            if (a > 2.0 * cap + 1e300) {\n                a = cap;"),
+    "multihop_chemistry_every_hop": ("            if (hop == H - 1) {\n                double hb",
+                                     "            if (hop >= 0) {\n                double hb"),
     "nin_skips_first_bin": ("\n        for (int64_t k = 0; k < K; k++) nin += g->I[j * K + k];",
                             "\n        for (int64_t k = 1; k < K; k++) nin += g->I[j * K + k];"),
 }

@@ -48,6 +48,11 @@ def test_front_law_combined(tau_switch):
     assert worst < 0.08
 
 
+def test_multihop_front_law():
+    """Multi-hop steps let a 25 Myr step keep up with the front (Sect. 4.6)."""
+    P.pin_multihop_front_law()
+
+
 def test_diffuse_front_follows_case_b():
     P.pin_diffuse_front_follows_case_b()
 
