@@ -454,6 +454,7 @@ def small_leg(ctx, log, prof, graph_sweeps: int):
     read-back) under each work split, as HIP-graph replays and as plain
     launches; the sweep launch's time comes from HIP events on the library
     stream, gaps included."""
+    from paper_0912_4273_amd import gridgen as G
     w1 = G.config1()
     gid = ctx.upload(w1)
     sweeps = w1.n_sweeps

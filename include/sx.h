@@ -61,6 +61,7 @@ extern "C" {
 #define SX_MAX_BINS_FP64 96   /* K <= 96  in SX_FP64                       */
 #define SX_MAX_DEGREE 127     /* Delaunay degree of any vertex             */
 #define SX_MAX_PER_BIN 3      /* neighbours per bin (the paper's p = d = 3) */
+#define SX_MAX_HOPS 1024      /* hops per step of a multi-hop grid          */
 
 /* Transport modes (Sect. 2.2).  SX_TRANSPORT_DCT: direction-conserving
  * transport everywhere (Sect. 2.2.3).  SX_TRANSPORT_COMBINED: combined
@@ -151,6 +152,19 @@ typedef struct sx_grid_desc {
                                     all its neighbours, filed like those of
                                     a source.  They count as emitted when
                                     made and in flight until sent            */
+    int32_t hops;                /* multi-hop steps (Sect. 4.6): edges
+                                    photons cross per step, 0 or 1 = one (the
+                                    paper's tests).  With H > 1 every sweep
+                                    is one hop of a step of dt: sources emit
+                                    N_dot dt / H per hop, each vertex absorbs
+                                    1 - exp(-y tau) of each hop's photons at
+                                    its y of the start of the step, capped by
+                                    the atoms it had neutral, and its y is
+                                    updated once, after the step's last hop,
+                                    from the photons it absorbed.  Direction-
+                                    conserving transport with on-the-spot
+                                    recombination only (else SX_ENOTSUP);
+                                    at most SX_MAX_HOPS                      */
 } sx_grid_desc;
 
 /* Cumulative photon accounting of one grid (photons, double). */
@@ -215,7 +229,9 @@ int sx_grid_upload(sx_ctx *ctx, const sx_grid_desc *d, sx_grid_id *out);
  * y = 1 - x_init, no photons in flight, tallies zero.  Asynchronous. */
 int sx_grid_reset(sx_ctx *ctx, sx_grid_id id);
 
-/* Restore y, photons and tallies (checkpoint).  Synchronous. */
+/* Restore y, photons and tallies (checkpoint).  Synchronous.  A multi-hop
+ * grid (hops > 1) restarts at the beginning of a step: its steps done (from
+ * the tally, or as they are) must be a multiple of hops, else SX_EINVAL. */
 int sx_grid_restore(sx_ctx *ctx, sx_grid_id id, const sx_state_in *in);
 
 /* Release one grid. */
@@ -364,7 +380,8 @@ int sx_grid_select_removal(sx_ctx *ctx, sx_grid_id id, double tau_remove,
  * split over that vertex's selection on the new grid; where none is
  * selected (or a removed vertex has no kept neighbour) it is counted as
  * escaped.  Tallies carry over.  Synchronous.  Errors: SX_EINVAL,
- * SX_ENOTSUP (combined transport or diffuse radiation), SX_ENOTFOUND. */
+ * SX_ENOTSUP (combined transport, diffuse radiation or multi-hop steps),
+ * SX_ENOTFOUND. */
 int sx_grid_remap(sx_ctx *ctx, sx_grid_id from, sx_grid_id to, const int32_t *new_of_old);
 
 /* Diffuse recombination radiation: the photons each vertex made in the last

@@ -341,6 +341,12 @@ int validate(sx_ctx *ctx, const sx_grid_desc *d) {
   if ((d->transport == SX_TRANSPORT_COMBINED || d->alpha_A > 0.0) &&
       (double)n * (double)d->n_bins * (double)d->max_per_bin >= 2147483647.0)
     return fail(ctx, SX_ENOTSUP, "grid too large for the per-edge lists of combined transport");
+  if (d->hops < 0 || d->hops > SX_MAX_HOPS)
+    return fail(ctx, SX_EINVAL, "hops must be in 0..%d", SX_MAX_HOPS);
+  if (d->hops > 1 && (d->transport != SX_TRANSPORT_DCT || d->alpha_A > 0.0))
+    return fail(ctx, SX_ENOTSUP,
+                "multi-hop steps take direction-conserving transport with on-the-spot "
+                "recombination");
   if (d->dct_reference != SX_DCT_REF_BIN && d->dct_reference != SX_DCT_REF_EDGE)
     return fail(ctx, SX_EINVAL, "dct_reference must be SX_DCT_REF_BIN or SX_DCT_REF_EDGE");
   const int K = d->n_bins;
@@ -432,6 +438,7 @@ int validate(sx_ctx *ctx, const sx_grid_desc *d) {
 struct Sizes {
   int64_t n, npad, ntiles, E, K, kw, sp, bb, kb;
   int32_t transport, mpb;   // transport: the kernel class (1 also for diffuse radiation)
+  int32_t hops;             // hops per step (1: one edge per step)
   bool diffuse;
   int64_t n_src;
 };
@@ -451,6 +458,7 @@ Sizes sizes_of(const sx_grid_desc *d) {
   s.transport = (d->transport == SX_TRANSPORT_COMBINED || s.diffuse) ? SX_TRANSPORT_COMBINED
                                                                      : SX_TRANSPORT_DCT;
   s.mpb = d->max_per_bin;
+  s.hops = d->hops > 1 ? d->hops : 1;
   s.n_src = d->n_src;
   return s;
 }
@@ -481,6 +489,7 @@ uint64_t bytes_estimate(const Sizes &s, int64_t n_em, int64_t n_rec, int64_t n_h
   }
   if (s.diffuse) b += rnd(8 * s.npad) + 2 * rnd((uint64_t)s.sp * (s.npad + sx::kTile)) +
                      rnd(8 * s.ntiles);
+  if (s.hops > 1) b += 3 * rnd(8 * s.npad);
   return b;
 }
 
@@ -810,6 +819,11 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
   for (int s = 0; s < d->n_src; ++s) e_sweep += d->src_rate[s] * d->dt;
   double unit = 1.0;
   if (e_sweep > 0.0 && std::isfinite(e_sweep)) unit = std::ldexp(1.0, (int)std::lround(std::log2(e_sweep)));
+  // with multi-hop steps each sweep is a hop and emits N_dot dt / hops
+  if (S.hops > 1) {
+    e_sweep = 0.0;
+    for (int s = 0; s < d->n_src; ++s) e_sweep += (d->src_rate[s] * d->dt) / (double)S.hops;
+  }
   g->e_sweep = e_sweep;
 
   P->unit = unit;
@@ -867,7 +881,8 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
     if (g->is_src_h.empty()) g->is_src_h.assign((size_t)n, 0);
     g->is_src_h[(size_t)g->inv[(size_t)vi]] = 1;
     const int32_t v = g->inv[(size_t)vi];
-    const double Es = d->src_rate[s] * d->dt;
+    double Es = d->src_rate[s] * d->dt;
+    if (S.hops > 1) Es = Es / (double)S.hops;
     const double *u = d->src_dir ? d->src_dir + 3 * s : nullptr;
     const bool iso = !u || (u[0] == 0.0 && u[1] == 0.0 && u[2] == 0.0);
     const int64_t deg = d->nbr_ptr[vi + 1] - d->nbr_ptr[vi];
@@ -933,7 +948,7 @@ int prepare(sx_ctx *ctx, const sx_grid_desc *d, sx_prepared *P) {
   P->dct_ref = d->dct_reference;
   P->alpha_A = d->alpha_A;
   P->alpha_B = d->alpha_B;
-  if (d->alpha_A > 0.0) {
+  if (d->alpha_A > 0.0 || S.hops > 1) {
     P->nhv.assign((size_t)npad, 0.0);
     for (int64_t v = 0; v < n; ++v) {
       const int32_t i = g->perm[(size_t)v];
@@ -1045,6 +1060,9 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   h.transport = P->transport;
   h.dct_ref = P->dct_ref;
   h.diffuse = P->alpha_A > 0.0 ? 1 : 0;
+  h.hops = (int32_t)S.hops;
+  h.habs = nullptr;
+  h.hnin = nullptr;
   h.dfrac = P->alpha_A > 0.0 ? (P->alpha_A - P->alpha_B) / P->alpha_A : 0.0;
   h.tau_switch = P->transport == SX_TRANSPORT_COMBINED ? P->tau_switch : 0.0;
   int32_t *d_rp, *d_nbr, *d_rec_cnt, *d_rec_ptr, *d_hptr, *d_hvid;
@@ -1273,6 +1291,17 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
     // the bin of each in-edge and the per-in-edge bin lists, on the device
     if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
     if ((r = build_ct_tables(ctx, g))) { grid_release(ctx, g); return r; }
+  }
+  if (h.hops > 1) {
+    double *d_nhv, *d_ha, *d_hn;
+    GA(d_nhv, npad);
+    GA(d_ha, npad);
+    GA(d_hn, npad);
+    UP(d_nhv, P->nhv.data(), 8 * npad);
+    if ((he = hipStreamSynchronize(st)) != hipSuccess) return kfail(he);
+    h.nhv = d_nhv;
+    h.habs = d_ha;
+    h.hnin = d_hn;
   }
   if (h.diffuse) {
     double *d_nhv, *d_dt;
@@ -2191,6 +2220,15 @@ int sx_grid_restore(sx_ctx *ctx, sx_grid_id id, const sx_state_in *in) {
   const int64_t n = h.n, npad = h.npad, K = h.k;
   GridDev cur;
   HIP_TRY(ctx, hipMemcpy(&cur, ctx->table + g->slot, sizeof cur, hipMemcpyDeviceToHost));
+  if (h.hops > 1) {
+    const double sw = in->tally ? in->tally->sweeps : (double)cur.sweeps;
+    if (!(sw >= 0.0) || std::fmod(sw, (double)h.hops) != 0.0)
+      return fail(ctx, SX_EINVAL, "a multi-hop grid restores at the start of a step "
+                                  "(steps done a multiple of %d)", h.hops);
+    // nothing absorbed yet in the step that starts
+    HIP_TRY(ctx, hipMemset(h.habs, 0, 8 * npad));
+    HIP_TRY(ctx, hipMemset(h.hnin, 0, 8 * npad));
+  }
   if (in->y) {
     std::vector<double> y((size_t)npad, 1.0);
     for (int64_t i = 0; i < n; ++i) {
@@ -2496,8 +2534,10 @@ int sx_grid_remap(sx_ctx *ctx, sx_grid_id from, sx_grid_id to, const int32_t *ne
   if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
   Grid *a = find(ctx, from), *b = find(ctx, to);
   if (!a || !b) return fail(ctx, SX_ENOTFOUND, "grid not found");
-  if (a->hg.transport != SX_TRANSPORT_DCT || b->hg.transport != SX_TRANSPORT_DCT)
-    return fail(ctx, SX_ENOTSUP, "remap needs direction-conserving, on-the-spot grids");
+  if (a->hg.transport != SX_TRANSPORT_DCT || b->hg.transport != SX_TRANSPORT_DCT ||
+      a->hg.hops > 1 || b->hg.hops > 1)
+    return fail(ctx, SX_ENOTSUP,
+                "remap needs direction-conserving, on-the-spot grids of one hop per step");
   const int64_t na = a->hg.n, nb = b->hg.n, K = a->hg.k;
   if (b->hg.k != K || a->bins0 != b->bins0 || a->rotated || b->rotated)
     return fail(ctx, SX_EINVAL, "remap needs the same unrotated bins on both grids");

@@ -109,8 +109,9 @@ struct GridDev {
   int32_t *rec_ptr;         // [ntiles*K*kRecGroups+1] first record of each
   int64_t *scan_part;       // [ntiles*K*kRecGroups/1024 + 2] scratch of the record scan
   int32_t *erev;            // [E+1] the edge of nbr[e]'s row that points back at e's row
-  uint32_t *smask;          // [4*E+4] written by the selection: bit k of word 4e + k/32
-                            // is set iff bin k of sender nbr[e] selects j
+  uint32_t *smask;          // [4*E+4] written by the selection: bit p of word 4e + p/32
+                            // is set iff the bin at storage position p of sender
+                            // nbr[e] selects j
   uint32_t *rec;            // [n_rec]
   int64_t rec_cap;
   const int32_t *halo_ptr;  // [ntiles+1]
@@ -142,8 +143,8 @@ struct GridDev {
   int32_t dct_ref;          // bin selection w.r.t. 0: the bin, 1: its closest edge
   double tau_switch;        // ballistic where y tau >= tau_switch
   int32_t *kl_ptr;          // [E+1]
-  uint8_t *kl;              // bins of i whose selection holds j, ascending by bin,
-                            // each as its storage position
+  uint8_t *kl;              // bins of i whose selection holds j, as storage
+                            // positions, ascending
   int64_t kl_cap;           // entries kl holds
   int32_t *kl_cnt;          // [E+1] scratch: entries per in-edge
   int64_t *kl_part;         // [E/1024 + 2] scratch of their scan
@@ -161,6 +162,12 @@ struct GridDev {
                             // step from the vertex's recombinations (the whole
                             // amount for a vertex with no neighbour)
   double *dtally;           // [ntiles] recombination photons made (cum), / unit
+  // multi-hop steps (hops > 1; null otherwise): each sweep is one hop, y is
+  // updated after the step's last hop (sweeps % hops == hops - 1)
+  int32_t hops;
+  int32_t pad2;
+  double *habs;             // [npad] photons absorbed so far in the step
+  double *hnin;             // [npad] photons that arrived so far in the step
   void *xin;                // bin field (layout of o[]): photons from ballistic
                             // senders waiting for their receiver's bin code; zero
                             // between steps

@@ -153,18 +153,22 @@ __global__ void k_erev(const GridDev *__restrict__ gp) {
 // directions are staged in LDS once and its bins run over them in row
 // order.
 struct Top3 {
-  double c0 = -3.0, c1 = -3.0, c2 = -3.0;
+  double c0, c1, c2;
   uint32_t s0 = kEmptySlot, s1 = kEmptySlot, s2 = kEmptySlot, cnt = 0;
-  __device__ __forceinline__ void add(double c, uint32_t s, double cos_min) {
-    if (!(c > cos_min)) return;
-    if (c > c0) {
-      c2 = c1; s2 = s1; c1 = c0; s1 = s0; c0 = c; s0 = s;
-    } else if (c > c1) {
-      c2 = c1; s2 = s1; c1 = c; s1 = s;
-    } else if (c > c2) {
-      c2 = c; s2 = s;
-    }
-    ++cnt;
+  // the floor is the eligibility bound: only cosines above it enter
+  __device__ __forceinline__ explicit Top3(double floor) : c0(floor), c1(floor), c2(floor) {}
+  // Branch-free insertion: a cosine enters above every held one it exceeds
+  // strictly, so an equal later one (a higher slot) never displaces.  cnt
+  // counts entries; it reaches min(eligible, 3), all that m needs.
+  __device__ __forceinline__ void add(double c, uint32_t s) {
+    const bool g0 = c > c0, g1 = c > c1, g2 = c > c2;
+    c2 = g1 ? c1 : (g2 ? c : c2);
+    s2 = g1 ? s1 : (g2 ? s : s2);
+    c1 = g0 ? c0 : (g1 ? c : c1);
+    s1 = g0 ? s0 : (g1 ? s : s1);
+    c0 = g0 ? c : c0;
+    s0 = g0 ? s : s0;
+    cnt += g2 ? 1u : 0u;
   }
   __device__ __forceinline__ uint32_t word(int mpb) const {
     const uint32_t n = cnt > (uint32_t)mpb ? (uint32_t)mpb : cnt;
@@ -198,19 +202,21 @@ __device__ __forceinline__ void select_bin(const GridDev &g, int64_t i, int k,
                                            const SX_L double *ed, SX_L uint32_t *ms, int n) {
   double u[3] = {g.bins[3 * k], g.bins[3 * k + 1], g.bins[3 * k + 2]};
   if (g.dct_ref) n = ref_edge(ed, n, g.cos_min, u);
-  Top3 a;
+  Top3 a(g.cos_min);
+#pragma unroll 4
   for (int t = 0; t < n; ++t) {
     const double d[3] = {ed[3 * t], ed[3 * t + 1], ed[3 * t + 2]};
-    a.add(cosine3(d, u), (uint32_t)t, g.cos_min);
+    a.add(cosine3(d, u), (uint32_t)t);
   }
   const uint32_t word = a.word(g.mpb);
   g.fwd[i * g.k + k] = word;
-  // each selected slot gets bit k in its out-edge's mask (an OR, so the
-  // order of the lanes does not matter)
+  // each selected slot gets the bit of bin k's storage position in its
+  // out-edge's mask (an OR, so the order of the lanes does not matter)
+  const int p = g.bpos[k];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const uint32_t s = (word >> (7 * q)) & 127u;
-    if (s != (uint32_t)kEmptySlot) atomicOr((uint32_t *)&ms[4 * s + (k >> 5)], 1u << (k & 31));
+    if (s != (uint32_t)kEmptySlot) atomicOr((uint32_t *)&ms[4 * s + (p >> 5)], 1u << (p & 31));
   }
 }
 
@@ -312,9 +318,9 @@ __global__ __launch_bounds__(256) void k_edge_bins(const GridDev *__restrict__ g
 // ------------------------------------------------------- gather lists ---
 // The receiver side of the selection: neighbour t of j sends bin k to j iff
 // j is among the selected slots of (nbr_t, k).  The gather-list kernels read
-// it from the receiving side: one mask per in-edge e of j (bit k of word 4e
-// + k/32 set iff bin k of sender nbr[e] selects j), written by the
-// selection kernel.
+// it from the receiving side: one mask per in-edge e of j (bit p of word 4e
+// + p/32 set iff the bin at storage position p of sender nbr[e] selects j),
+// written by the selection kernel.
 __device__ __forceinline__ int sender_index(const GridDev &g, bool direct,
                                             int e, int rb) {
   return direct ? e - rb : (int)g.edge_hidx[e];
@@ -328,95 +334,136 @@ static_assert(SX_MAX_BINS_FP32 <= 128 && SX_MAX_BINS_FP64 <= 128 &&
               "selection masks hold 128 bins; edge bins stage up to "
               "SX_MAX_BINS_FP32 directions");
 
-// Which bins of block kb (positions kb BB .. kb BB + BB - 1) the in-edge
-// with selection mask m sends, as BB bits.
-__device__ __forceinline__ uint32_t block_bits(const GridDev &g, const uint4 &m, int kb) {
-  uint32_t nib = 0;
-  const int p0 = kb * g.bb;
-  for (int b = 0; b < g.bb; ++b) {
-    const int p = p0 + b;
-    if (p < g.k) {
-      const int k = g.bperm[p];
-      const uint32_t w = (k >> 5) == 0 ? m.x : (k >> 5) == 1 ? m.y : (k >> 5) == 2 ? m.z : m.w;
-      nib |= ((w >> (k & 31)) & 1u) << b;
-    }
-  }
-  return nib;
-}
+// One wave per (tile, group of 16 bin positions), lane = receiver j: the
+// lane walks j's in-edges once, in row order, reading the 16 bits of each
+// mask that cover the group (blocks kq KQ .. kq KQ + KQ - 1, KQ = 16 / BB).
+// A sender with bins in a block takes the block's next in-word entry while
+// there is one (and its slot fits), otherwise it becomes records, one per
+// bin; j's source shares of those bins come after.  Counts and offsets are
+// kept per (tile, position, group of kRecGroupLanes receivers), so the
+// records of a (tile, position) come out sorted by lane; a lane's place in
+// its group comes from a shuffle scan of the counts.  Pass 1 counts the
+// records, pass 2 (after a scan) writes in-words and records.
+constexpr int kInlistBins = 16;   // bin positions per wave of the gather-list build
+static_assert(kRecGroupLanes == 8, "the record scan below works on groups of 8 lanes");
 
-// One thread per (tile, block, group of kRecGroupLanes receivers) walks the
-// group's receivers in lane order and each receiver's in-edges in row order.
-// A sender with bins in the block takes the next in-word entry while there
-// is one (and its slot fits), otherwise it becomes records, one per bin; the
-// receiver's source shares of the block's bins come after.  Counts and
-// offsets are kept per (tile, position, group), so the records of a (tile,
-// position) come out sorted by lane.  Pass 1 counts the records, pass 2
-// (after a scan) writes in-words and records.
-template <bool FILL>
-__global__ void k_inlist(const GridDev *__restrict__ gp) {
+template <bool FILL, int BB>
+__global__ __launch_bounds__(256) void k_inlist(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
-  const int K = g.k, KB = g.kb, BB = g.bb;
+  const int K = g.k, KB = g.kb;
+  constexpr int KQ = kInlistBins / BB;
+  const int nkq = (K + kInlistBins - 1) / kInlistBins;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)g.ntiles * KB * kRecGroups) return;
-  const int grp = (int)(t % kRecGroups);
-  const int64_t tk = t / kRecGroups;
-  const int kb = (int)(tk % KB), tile = (int)(tk / KB);
+  const int lane = (int)(t & 63);
+  const int64_t tk = t >> 6;
+  if (tk >= (int64_t)g.ntiles * nkq) return;   // whole waves
+  const int kq = (int)(tk % nkq), tile = (int)(tk / nkq);
+  const int grp = lane / kRecGroupLanes;
+  const int p0 = kq * kInlistBins;
   const bool direct = g.tile_direct[tile] != 0;
   const int eb = inw_entry_bits(BB);
   const int cap = g.inw_cap;
-  const uint4 *sm = (const uint4 *)g.smask;
-  int rp[4] = {0, 0, 0, 0};   // record counts (pass 1) or next record (pass 2), per bin
-  if (FILL) {
-    for (int b = 0; b < BB; ++b) {
-      const int p = kb * BB + b;
-      if (p < K) rp[b] = g.rec_ptr[((int64_t)tile * K + p) * kRecGroups + grp];
+  const int j = tile * kTile + lane;
+  const bool valid = j < g.n;
+  const int rb = valid ? g.row_ptr[j] : 0;
+  const int re = valid ? g.row_ptr[j + 1] : 0;
+  const uint32_t *mw = g.smask + (p0 >> 5);
+  const int sh = p0 & 31;
+  // records per bin position of the group: this lane's count, then (fill)
+  // where its next record goes
+  int rc[kInlistBins];
+#pragma unroll
+  for (int b = 0; b < kInlistBins; ++b) rc[b] = 0;
+  uint64_t w[KQ];
+  int c[KQ];
+  uint32_t flag = 0;
+  auto walk = [&](bool write) {
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      w[q] = 0;
+      c[q] = 0;
     }
-  }
-  for (int lane = grp * kRecGroupLanes; lane < (grp + 1) * kRecGroupLanes; ++lane) {
-    const int j = tile * kTile + lane;
-    uint64_t w = 0;
-    if (j < g.n) {
-      const int rb = g.row_ptr[j], re = g.row_ptr[j + 1];
-      const uint32_t lbits = (uint32_t)lane << 26;
-      int c = 0;
-      bool recs = false;
-      for (int e = rb; e < re; ++e) {
-        const uint32_t nib = block_bits(g, sm[e], kb);
+    flag = 0;
+    for (int e = rb; e < re; ++e) {
+      const uint32_t m16 = (mw[4 * (int64_t)e] >> sh) & 0xFFFFu;
+      if (m16 == 0u) continue;
+      const int s = e - rb;
+      const uint32_t idx = (uint32_t)sender_index(g, direct, e, rb);
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        const uint32_t nib = (m16 >> (q * BB)) & ((1u << BB) - 1u);
         if (nib == 0u) continue;
-        const int s = e - rb;
-        if (c < cap && s < kSlotRows) {
-          w |= (uint64_t)((uint32_t)s | (nib << 5)) << (eb * c);
-          ++c;
+        if (c[q] < cap && s < kSlotRows) {
+          w[q] |= (uint64_t)((uint32_t)s | (nib << 5)) << (eb * c[q]);
+          ++c[q];
         } else {
-          recs = true;
-          const uint32_t idx = (uint32_t)sender_index(g, direct, e, rb);
+          flag |= 1u << q;
+#pragma unroll
           for (int b = 0; b < BB; ++b) {
             if (!((nib >> b) & 1u)) continue;
-            if (!FILL) ++rp[b];
-            else if (rp[b] < g.rec_cap) g.rec[rp[b]++] = lbits | ((uint32_t)b << 24) | idx;
+            const int pb = q * BB + b;
+            if (!write) ++rc[pb];
+            else if (rc[pb] < g.rec_cap)
+              g.rec[rc[pb]++] = ((uint32_t)lane << 26) | ((uint32_t)b << 24) | idx;
           }
         }
       }
-      // source shares come after the transported photons of the bin
-      for (int q = g.em_ptr[j]; q < g.em_ptr[j + 1]; ++q) {
-        const int p = g.bpos[g.em_k[q]];
-        if (p / BB != kb) continue;
-        recs = true;
-        const int b = p - kb * BB;
-        if (!FILL) ++rp[b];
-        else if (rp[b] < g.rec_cap)
-          g.rec[rp[b]++] = lbits | ((uint32_t)b << 24) | kRecEmission | (uint32_t)q;
+    }
+    // source shares come after the transported photons of the bin
+    if (valid) {
+      for (int qq = g.em_ptr[j]; qq < g.em_ptr[j + 1]; ++qq) {
+        const int pe = (int)g.bpos[g.em_k[qq]] - p0;
+        if (pe < 0 || pe >= kInlistBins) continue;
+        flag |= 1u << (pe / BB);
+        // the counter by a compile-time index (no indexed register array)
+#pragma unroll
+        for (int pb = 0; pb < kInlistBins; ++pb) {
+          if (pb != pe) continue;
+          if (!write) ++rc[pb];
+          else if (rc[pb] < g.rec_cap)
+            g.rec[rc[pb]++] = ((uint32_t)lane << 26) | ((uint32_t)(pb % BB) << 24) |
+                              kRecEmission | (uint32_t)qq;
+        }
       }
-      // bit 63: this (vertex, block) has records to collect
-      if (recs) w |= 1ull << 63;
     }
-    if (FILL) g.inw[((int64_t)tile * KB + kb) * kTile + lane] = w;
-  }
+  };
+  walk(false);
   if (!FILL) {
-    for (int b = 0; b < BB; ++b) {
-      const int p = kb * BB + b;
-      if (p < K) g.rec_cnt[((int64_t)tile * K + p) * kRecGroups + grp] = rp[b];
+    // sum over the 8 lanes of the group; its first lane writes
+#pragma unroll
+    for (int b = 0; b < kInlistBins; ++b) {
+      int v = rc[b];
+      v += __shfl_xor(v, 1);
+      v += __shfl_xor(v, 2);
+      v += __shfl_xor(v, 4);
+      const int p = p0 + b;
+      if ((lane & 7) == 0 && p < K) g.rec_cnt[((int64_t)tile * K + p) * kRecGroups + grp] = v;
     }
+    return;
+  }
+  // this lane's first record per bin: the group's offset plus the counts of
+  // the group's lower lanes (inclusive scan over 8 lanes, minus its own)
+#pragma unroll
+  for (int b = 0; b < kInlistBins; ++b) {
+    const int own = rc[b];
+    int v = own;
+#pragma unroll
+    for (int d = 1; d < 8; d <<= 1) {
+      const int u = __shfl_up(v, d, 8);
+      if ((lane & 7) >= d) v += u;
+    }
+    const int p = p0 + b;
+    rc[b] = p < K ? g.rec_ptr[((int64_t)tile * K + p) * kRecGroups + grp] + (v - own) : 0;
+  }
+  walk(true);
+  // in-words of the group's blocks; bit 63: the (vertex, block) has records
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) {
+    const int kb = kq * KQ + q;
+    if (kb >= KB) break;
+    uint64_t x = valid ? w[q] : 0ull;
+    if (valid && ((flag >> q) & 1u)) x |= 1ull << 63;
+    g.inw[((int64_t)tile * KB + kb) * kTile + lane] = x;
   }
 }
 
@@ -431,10 +478,10 @@ __global__ void k_ebin_in(const GridDev *__restrict__ gp) {
 }
 
 // Combined transport: the bins of sender i whose selection holds receiver
-// j, ascending, for every in-edge e = (j, slot of i): the set bits of the
-// in-edge's selection mask (a bin with m = 0 selects no slot), each written
-// as its storage position.  One lane per in-edge; pass 1 counts, pass 2
-// (after a scan) writes each list.
+// j, for every in-edge e = (j, slot of i): the set bits of the in-edge's
+// selection mask (a bin with m = 0 selects no slot), as storage positions,
+// ascending.  One lane per in-edge; pass 1 counts, pass 2 (after a scan)
+// writes each list.
 __global__ void k_kl_count(const GridDev *__restrict__ gp) {
   const GridDev &g = *gp;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -468,7 +515,7 @@ __global__ __launch_bounds__(256) void k_kl_fill(const GridDev *__restrict__ gp)
       uint32_t w = m[q];
       while (w) {
         const int bit = __ffs(w) - 1;
-        const uint8_t k = g.bpos[32 * q + bit];   // stored by position
+        const uint8_t k = (uint8_t)(32 * q + bit);   // the bin's storage position
         if (staged) st[p - base] = k;
         else g.kl[p] = k;
         ++p;
@@ -542,52 +589,55 @@ __global__ __launch_bounds__(64 * 6) void k_mbits(GridDev *__restrict__ gp) {
 // (ascending); their holdings add up in that order and are split over the
 // new bin's m_new selected neighbours, or leave the domain (escape tally)
 // where m_new = 0.  A new bin fed by one old bin with the same m keeps its
-// Ipre as it is.  One workgroup (one wave) per tile, lane = vertex: the old
-// bins and m go to LDS (each lane reads back only its own column), then the
-// new bins are written in place, with the new m words (from the new
-// selection in fwd).  The tile's escapes are summed by a butterfly.
+// Ipre as it is.  Thread = vertex, tile = wave; the new field is written to
+// the other photon buffer (the one the next sweep would overwrite), with T
+// and any per-step state of combined transport and diffuse radiation copied
+// across, and k_flip then makes it current.  The map is the same for every
+// thread, so each read of an old bin is one coalesced wave load.  The
+// tile's escapes are summed by a butterfly.
 template <typename P>
-__global__ __launch_bounds__(64) void k_rebin(GridDev *__restrict__ gp, RebinMap map) {
+__global__ __launch_bounds__(256) void k_rebin(GridDev *__restrict__ gp, RebinMap map) {
   GridDev &g = *gp;
   constexpr int BB = kBlockBytes / sizeof(P);
-  constexpr int KM = sizeof(P) == 8 ? SX_MAX_BINS_FP64 : SX_MAX_BINS_FP32;
   typedef P V __attribute__((ext_vector_type(BB)));
-  __shared__ P held[KM * 64];
-  __shared__ uint8_t mo[KM * 64];
-  const int tile = blockIdx.x, lane = threadIdx.x;
-  const int j = tile * kTile + lane;
-  const int K = g.k, KB = g.kb;
+  const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (j >= g.npad) return;   // whole waves: npad is a multiple of 64
+  const int tile = j >> 6, lane = j & 63;
+  const int K = g.k, KB = g.kb, kw = g.kw;
   const int par = g.parity;
-  V *o = (V *)g.o[par];
-  // old m and holdings by (caller's) bin number, from storage order
-  for (int w = 0; w < g.kw; ++w) {
-    const uint32_t mw = g.mbits[((int64_t)tile * g.kw + w) * 64 + lane];
-    for (int b = 0; b < 16 && 16 * w + b < K; ++b)
-      mo[g.bperm[16 * w + b] * 64 + lane] = (uint8_t)((mw >> (2 * b)) & 3u);
-  }
-  for (int kb = 0; kb < KB; ++kb) {
-    const V v = o[((int64_t)tile * KB + kb) * 64 + lane];
+  const P *oin = (const P *)g.o[par];
+  V *oout = (V *)g.o[par ^ 1];
+  // old m, 16 bins per word in storage order, read before any is replaced
+  uint32_t mo[6];
 #pragma unroll
-    for (int b = 0; b < BB; ++b)
-      if (kb * BB + b < K) held[g.bperm[kb * BB + b] * 64 + lane] = v[b];
-  }
-  const double T = (double)((const P *)g.t[par])[j];
+  for (int q = 0; q < 6; ++q) mo[q] = q < kw ? g.mbits[((int64_t)tile * kw + q) * 64 + lane] : 0u;
+  auto m_old = [&](int p) -> uint32_t {
+    const int q = p >> 4;
+    const uint32_t w = q == 0 ? mo[0] : q == 1 ? mo[1] : q == 2 ? mo[2] : q == 3 ? mo[3]
+                                                               : q == 4 ? mo[4] : mo[5];
+    return (w >> (2 * (p & 15))) & 3u;
+  };
+  auto held = [&](int p) -> P {
+    return oin[(((int64_t)tile * KB + p / BB) * 64 + lane) * BB + p % BB];
+  };
+  const P Tp = ((const P *)g.t[par])[j];
+  const double T = (double)Tp;
   double esc = 0.0;
   uint32_t mword = 0;
   V out = V(0);
-  // new bins in storage order: position p holds bin kn
   for (int p = 0; p < K; ++p) {
     const int kn = g.bperm[p];
     const uint32_t mn = j < g.n ? (g.fwd[(int64_t)j * K + kn] >> 21) & 3u : 0u;
     const int q0 = map.ptr[kn], q1 = map.ptr[kn + 1];
     P val;
-    if (q1 - q0 == 1 && mn > 0u && mn == mo[map.list[q0] * 64 + lane]) {
-      val = held[map.list[q0] * 64 + lane];
+    const int p1 = g.bpos[map.list[q0 < q1 ? q0 : 0]];
+    if (q1 - q0 == 1 && mn > 0u && mn == m_old(p1)) {
+      val = held(p1);
     } else {
       double h = 0.0;
       for (int q = q0; q < q1; ++q) {
-        const int k = map.list[q];
-        h += (double)held[k * 64 + lane] * (double)mo[k * 64 + lane];
+        const int po = g.bpos[map.list[q]];
+        h += (double)held(po) * (double)m_old(po);
       }
       if (mn == 0u) {
         esc += h * T;
@@ -598,15 +648,21 @@ __global__ __launch_bounds__(64) void k_rebin(GridDev *__restrict__ gp, RebinMap
     }
     out[p % BB] = val;
     if (p % BB == BB - 1 || p == K - 1) {
-      o[((int64_t)tile * KB + p / BB) * 64 + lane] = out;
+      oout[((int64_t)tile * KB + p / BB) * 64 + lane] = out;
       out = V(0);
     }
     mword |= mn << (2 * (p & 15));
     if ((p & 15) == 15 || p == K - 1) {
-      g.mbits[((int64_t)tile * g.kw + p / 16) * 64 + lane] = mword;
+      g.mbits[((int64_t)tile * kw + p / 16) * 64 + lane] = mword;
       mword = 0;
     }
   }
+  ((P *)g.t[par ^ 1])[j] = Tp;
+  if (g.lay[0]) g.lay[par ^ 1][j] = g.lay[par][j];
+  if (g.oe[0])
+    for (int e = g.row_ptr[j]; e < g.row_ptr[j + 1]; ++e)
+      ((P *)g.oe[par ^ 1])[e] = ((const P *)g.oe[par])[e];
+  if (g.dsh[0]) ((P *)g.dsh[par ^ 1])[j] = ((const P *)g.dsh[par])[j];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) esc += __shfl_xor(esc, off);
   if (lane == 0) {
@@ -614,6 +670,9 @@ __global__ __launch_bounds__(64) void k_rebin(GridDev *__restrict__ gp, RebinMap
     g.tally[(int64_t)tile * 3 + 2] -= esc;
   }
 }
+
+// After a re-binning: the other photon buffer becomes current.
+__global__ void k_flip(GridDev *gp) { gp->parity ^= 1; }
 
 // Exclusive scan of n counts into ptr[0..n] (ptr[n] = total) in three
 // passes: each workgroup of 1024 scans its part and leaves its total in
@@ -765,6 +824,23 @@ __device__ __forceinline__ double chem_step_r(double y, double nin, double dt,
   return y;
 }
 
+// After the last hop of a multi-hop step: the photons a vertex absorbed
+// over the step (ion per atom, at most y) ionise exactly as many atoms,
+// spread evenly over the substeps; each substep takes the recombinations
+// backward Euler, y' = y - i + hb (1 - y')^2, whose root in [0, 1] is
+// y' = 1 - z, z = 2c / (1 + sqrt(1 + 4 hb c)), c = 1 - y + i (z = c when
+// hb = 0).
+__device__ __forceinline__ double chem_fixed(double y, double ion, double hb, int n_sub) {
+  const double is = ion / (double)n_sub;
+  for (int s = 0; s < n_sub; ++s) {
+    const double c = (1.0 - y) + is;
+    const double z = hb > 0.0 ? (2.0 * c) / (1.0 + sqrt(1.0 + 4.0 * hb * c)) : c;
+    y = 1.0 - z;
+    if (y < 0.0) y = 0.0;
+  }
+  return y;
+}
+
 // -------------------------------------------------------------- sweep ---
 // State between steps: for every vertex i and bin k, Ipre[k][i] = I/m, the
 // photons that entered i in bin k divided over its m selected neighbours,
@@ -791,6 +867,26 @@ __device__ __forceinline__ double chem_step_r(double y, double nin, double dt,
 // 16-byte block per halo vertex; entry kHaloMax reads 0), the halo index of
 // every row slot of every lane (row s at s * 64 + lane), and the hand-over
 // slots of the records.
+// Orders this wave's LDS accesses at this point: the wave barrier keeps the
+// hardware's issue order, the empty asm with a memory clobber stops the
+// compiler from moving a memory access across it.  Between two of these, a
+// wave may read LDS through plain pointers, so that its loads batch.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// a + v where bit b of x is set, else a + 0 (the same bits as skipping the
+// add: the sums are never -0); branch-free, by masking v's bits
+__device__ __forceinline__ float add_if_bit(float a, float v, uint32_t x, int b) {
+  const int m = (int)(x << (31 - b)) >> 31;
+  return a + __int_as_float(__float_as_int(v) & m);
+}
+__device__ __forceinline__ double add_if_bit(double a, double v, uint32_t x, int b) {
+  const long long m = (long long)((int)(x << (31 - b)) >> 31);
+  return a + __longlong_as_double(__double_as_longlong(v) & m);
+}
+
 template <typename P>
 struct __attribute__((aligned(16))) TileLds {
   static constexpr int BB = kBlockBytes / sizeof(P);
@@ -907,12 +1003,44 @@ __device__ __forceinline__ void dct_finish(const GridDev *__restrict__ G, int ti
   if (j < G->n) {
     SX_G double *__restrict__ yv = gst(G->y);
     const double y0 = yv[j];
-    if (!(nin == 0.0 && y0 == 1.0)) {
-      const double yn = chem_step(y0, nin * G->unit, G->dt, gld(G->dtnhv)[j],
-                                  gld(G->tau)[j], gld(G->bcoef)[j], G->n_sub, A, T);
-      yv[j] = yn;
+    if (G->hops > 1) {
+      // one hop of a multi-hop step: absorb 1 - exp(-y tau) of the photons
+      // at the y of the start of the step, capped by the atoms left
+      const double nph = nin * G->unit;
+      const double nhv = gld(G->nhv)[j];
+      SX_G double *__restrict__ ha = gst(G->habs);
+      SX_G double *__restrict__ hn = gst(G->hnin);
+      double hab = ha[j];
+      double cap = nhv * y0 - hab;
+      if (cap < 0.0) cap = 0.0;
+      T = exp(-y0 * gld(G->tau)[j]);
+      double a = nph - nph * T;
+      if (a > cap) {
+        a = cap;
+        T = (nph - a) / nph;
+      }
+      A = a;
+      hab += a;
+      const double hin = hn[j] + nph;
+      if (G->sweeps % G->hops == G->hops - 1) {
+        // the step's last hop: the neutral fraction from what was absorbed
+        const double hb = (G->dt / (double)G->n_sub) * gld(G->bcoef)[j];
+        yv[j] = chem_fixed(y0, hab / nhv, hb, G->n_sub);
+        gst(G->nin)[j] = hin;
+        ha[j] = 0.0;
+        hn[j] = 0.0;
+      } else {
+        ha[j] = hab;
+        hn[j] = hin;
+      }
+    } else {
+      if (!(nin == 0.0 && y0 == 1.0)) {
+        const double yn = chem_step(y0, nin * G->unit, G->dt, gld(G->dtnhv)[j],
+                                    gld(G->tau)[j], gld(G->bcoef)[j], G->n_sub, A, T);
+        yv[j] = yn;
+      }
+      gst(G->nin)[j] = nin * G->unit;
     }
-    gst(G->nin)[j] = nin * G->unit;
     gst((P *)G->t[par ^ 1])[j] = (P)T;
   }
   A /= G->unit;   // tallies in stored units; scaled back on read
@@ -979,8 +1107,9 @@ __device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int ti
   };
 
   // halo of the tile and its senders' T (once per step), and the halo index
-  // of every row slot an in-word entry can name
-  uint32_t hv[NQ];
+  // of every row slot an in-word entry can name; hb: the block index of each
+  // staged halo vertex's block 0 (block kb is 64 kb further on)
+  uint32_t hv[NQ], hb[NQ];
   P th[NQ];
   if constexpr (!DIRECT) {
     const SX_G int32_t *__restrict__ hptr = gld(G->halo_ptr);
@@ -993,6 +1122,7 @@ __device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int ti
       const int idx = 64 * q + lane;
       hv[q] = idx < hlen ? (uint32_t)hvid[hp + idx] : zero;
       th[q] = tin[hv[q]];
+      hb[q] = ((hv[q] >> 6) * (uint32_t)KB) * 64u + (hv[q] & 63u);
     }
     if (lane == 0) hl[kHaloMax] = V(0);
     const int deg = valid ? rowp[j + 1] - rb : 0;
@@ -1023,7 +1153,8 @@ __device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int ti
   auto issue = [&](int kb, int slot) {
     if constexpr (!DIRECT) {
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) st[slot][q] = oin[blk(hv[q], kb)];
+      for (int q = 0; q < NQ; ++q)
+        st[slot][q] = oin[hb[q] + (uint32_t)kb * 64u];
     }
     // in-words are read once per sweep.  With NT (the launch's photon planes
     // fit in the last-level cache) they are loaded non-temporal, so that they
@@ -1063,16 +1194,21 @@ __device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int ti
         for (int b = 0; b < BB; ++b) a[b] = mul_rn(v[b], th[q]);
         hl[64 * q + lane] = a;
       }
-      __builtin_amdgcn_wave_barrier();
+      wave_sync();
       // every entry: its sender's block from LDS, added to the bins it
-      // sends (an entry without bins adds zeros)
+      // sends (an entry without bins adds zeros); the slot-table reads of
+      // all entries go out together, then the halo reads
+      const SX_L uint16_t *stn = (const SX_L uint16_t *)L->slot + lane;
+      const SX_L V *hln = (const SX_L V *)L->h;
+      uint32_t hx[NE];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) hx[e] = stn[((uint32_t)(w >> (EB * e)) & 31u) * kTile];
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
-        const uint32_t x = (uint32_t)(w >> (EB * e)) & EM;
-        const uint32_t h = stab[(x & 31u) * kTile + lane];
-        const V v = hl[h];
+        const V v = hln[hx[e]];
+        const uint32_t x = (uint32_t)(w >> (EB * e + 5));
 #pragma unroll
-        for (int b = 0; b < BB; ++b) acc[b] += ((x >> (5 + b)) & 1u) ? v[b] : P(0);
+        for (int b = 0; b < BB; ++b) acc[b] = add_if_bit(acc[b], v[b], x, b);
       }
     } else {
 #pragma unroll
@@ -1121,17 +1257,17 @@ __device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int ti
       // with more than 64 records every lane takes part in every round
       const bool take = fl || nrec > 64;
       if (take) *(volatile SX_L V *)(xchg + lane * BB) = V(0);
-      __builtin_amdgcn_wave_barrier();
+      wave_sync();
       if (has && knext != key) xchg[(int)(r >> 26) * BB + rb_] = v;
-      __builtin_amdgcn_wave_barrier();
+      wave_sync();
       if (take) {
         const V got = *(volatile SX_L V *)(xchg + lane * BB);
 #pragma unroll
         for (int b = 0; b < BB; ++b) acc[b] += got[b];
       }
-      __builtin_amdgcn_wave_barrier();
+      wave_sync();
     }
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
     if constexpr (CT) {
       if ((ci.xmask >> kb) & 1ull) {
         SX_G V *xp = (SX_G V *)ci.xin + blk((uint32_t)j, kb);
@@ -1601,6 +1737,10 @@ __global__ void k_reset(GridDev *__restrict__ gp, const double *__restrict__ y0)
   if (j >= g.npad) return;
   g.y[j] = y0[j];
   g.nin[j] = 0.0;
+  if (g.habs) {
+    g.habs[j] = 0.0;
+    g.hnin[j] = 0.0;
+  }
 }
 
 __global__ void k_reset_ctl(GridDev *gp) {
@@ -1693,10 +1833,12 @@ hipError_t launch_edge_bins(const GridDev *dg, const GridDev &hg,
 
 hipError_t launch_inlist_count(const GridDev *dg, const GridDev &hg,
                                hipStream_t s) {
-  // one thread per (tile, block, group of receivers)
-  hipLaunchKernelGGL(k_inlist<false>,
-                     dim3(blocks_for((int64_t)hg.ntiles * hg.kb * kRecGroups, 256)),
-                     dim3(256), 0, s, dg);
+  // one wave per (tile, group of 16 bin positions)
+  const int64_t waves = (int64_t)hg.ntiles * ((hg.k + kInlistBins - 1) / kInlistBins);
+  if (hg.bb == 4)
+    hipLaunchKernelGGL((k_inlist<false, 4>), dim3(blocks_for(waves * 64, 256)), dim3(256), 0, s, dg);
+  else
+    hipLaunchKernelGGL((k_inlist<false, 2>), dim3(blocks_for(waves * 64, 256)), dim3(256), 0, s, dg);
   return hipGetLastError();
 }
 
@@ -1713,9 +1855,12 @@ hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s) {
 
 hipError_t launch_rebin(GridDev *dg, const GridDev &hg, const RebinMap &map, hipStream_t s) {
   if (hg.precision == 0)
-    hipLaunchKernelGGL(k_rebin<double>, dim3((unsigned)hg.ntiles), dim3(64), 0, s, dg, map);
+    hipLaunchKernelGGL(k_rebin<double>, dim3(blocks_for(hg.npad, 256)), dim3(256), 0, s, dg, map);
   else
-    hipLaunchKernelGGL(k_rebin<float>, dim3((unsigned)hg.ntiles), dim3(64), 0, s, dg, map);
+    hipLaunchKernelGGL(k_rebin<float>, dim3(blocks_for(hg.npad, 256)), dim3(256), 0, s, dg, map);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_flip, dim3(1), dim3(1), 0, s, dg);
   return hipGetLastError();
 }
 hipError_t launch_em_bins(GridDev *dg, const GridDev &hg, int64_t n_em, hipStream_t s) {
@@ -1755,9 +1900,11 @@ hipError_t launch_scan(int32_t *cnt, int32_t *ptr, int64_t *part, int32_t n,
 
 hipError_t launch_inlist_fill(const GridDev *dg, const GridDev &hg,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_inlist<true>,
-                     dim3(blocks_for((int64_t)hg.ntiles * hg.kb * kRecGroups, 256)),
-                     dim3(256), 0, s, dg);
+  const int64_t waves = (int64_t)hg.ntiles * ((hg.k + kInlistBins - 1) / kInlistBins);
+  if (hg.bb == 4)
+    hipLaunchKernelGGL((k_inlist<true, 4>), dim3(blocks_for(waves * 64, 256)), dim3(256), 0, s, dg);
+  else
+    hipLaunchKernelGGL((k_inlist<true, 2>), dim3(blocks_for(waves * 64, 256)), dim3(256), 0, s, dg);
   return hipGetLastError();
 }
 

@@ -32,6 +32,7 @@ SX_NOALLOC_MAX_GRIDS = 256
 SX_NOALLOC_MAX_TILES = 131072
 SX_MAX_BINS = 96
 SX_MAX_DEGREE = 127
+SX_MAX_HOPS = 1024
 SX_TRANSPORT_DCT = 0
 SX_TRANSPORT_COMBINED = 1
 SX_DCT_REF_BIN = 0
@@ -75,7 +76,7 @@ class SxGridDesc(C.Structure):
         ("alpha_B", C.c_double), ("dt", C.c_double),
         ("precision", C.c_int32), ("transport", C.c_int32),
         ("dct_reference", C.c_int32), ("tau_switch", C.c_double),
-        ("alpha_A", C.c_double)]
+        ("alpha_A", C.c_double), ("hops", C.c_int32)]
 
 
 class SxTally(C.Structure):
@@ -231,7 +232,8 @@ class _Desc:
             transport=int(getattr(w, "transport", SX_TRANSPORT_DCT)),
             dct_reference=int(getattr(w, "dct_reference", SX_DCT_REF_BIN)),
             tau_switch=float(getattr(w, "tau_switch", 1.0)),
-            alpha_A=float(getattr(w, "alpha_A", 0.0)))
+            alpha_A=float(getattr(w, "alpha_A", 0.0)),
+            hops=int(getattr(w, "hops", 1)))
 
 
 # ------------------------------------------------------ C entry points ----

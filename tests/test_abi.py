@@ -44,7 +44,7 @@ def test_binding_constants_match_header():
                  "SX_ENOTSUP", "SX_EAGAIN", "SX_FP64", "SX_FP32_TRANSPORT",
                  "SX_ORDER_GRID", "SX_ORDER_DIRECT_FIRST", "SX_MAX_GRAPH_SWEEPS",
                  "SX_MAX_DEGREE", "SX_TRANSPORT_DCT", "SX_TRANSPORT_COMBINED",
-                 "SX_DCT_REF_BIN", "SX_DCT_REF_EDGE"):
+                 "SX_DCT_REF_BIN", "SX_DCT_REF_EDGE", "SX_MAX_HOPS"):
         assert int(defs[name]) == getattr(sx, name), name
     assert sx.SX_MAX_BINS == int(defs["SX_MAX_BINS_FP32"]) == int(defs["SX_MAX_BINS_FP64"])
 
