@@ -463,7 +463,9 @@ def small_leg(ctx, log, prof, graph_sweeps: int):
     runs = {}
     for split in (1, 2, 4):
         for label, gs in (("graph", graph_sweeps), ("launches", 0)):
-            ctx.set_schedule([gid], tiles_per_group=4, graph_sweeps=gs, work_split=split)
+            # at most 4 waves per workgroup
+            ctx.set_schedule([gid], tiles_per_group=4 // split, graph_sweeps=gs,
+                             work_split=split)
             for _ in range(2):   # warm-up (graph instantiation)
                 ctx.reset(gid)
                 ctx.solve([gid], sweeps)

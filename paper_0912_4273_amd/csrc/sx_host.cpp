@@ -119,6 +119,11 @@ struct sx_ctx {
   std::vector<ProfEv> ev;     // pool
   uint8_t *scratch = nullptr; // device address of this device's sx_step_noalloc array
   size_t ev_used = 0;
+  // A second stream for uploads and read-backs that overlap the sweeps of
+  // other grids (the request loop's): while io_on, the upload, read-back and
+  // release calls work on it and wait only for it.
+  hipStream_t io = nullptr;
+  bool io_on = false;
 };
 
 namespace {
@@ -128,6 +133,10 @@ constexpr size_t kPinBytes = kPinCounts + 64;
 static_assert(SX_MAX_BINS_FP32 <= 128 && SX_MAX_BINS_FP64 <= 128, "pinned staging holds 128 bins");
 
 void drop_plans(sx_ctx *ctx, int slot);
+
+// The stream of the calls that move a grid's data (upload, read-back,
+// release): the context's own, or its second stream while io_on.
+hipStream_t wstream(const sx_ctx *ctx) { return ctx->io_on ? ctx->io : ctx->stream; }
 
 int fail(sx_ctx *ctx, int code, const char *fmt, ...) {
   char buf[512];
@@ -469,7 +478,7 @@ uint64_t bytes_estimate(const Sizes &s, int64_t n_em, int64_t n_rec, int64_t n_h
   uint64_t b = 0;
   b += rnd(4 * (s.npad + 1)) + rnd(4 * s.E) + rnd(s.E) + rnd(24 * s.E) + rnd(24 * s.K);
   b += rnd(4 * s.npad * s.K) + rnd(s.E) + rnd(8 * s.npad * s.kb) +
-       rnd(4 * s.npad * s.kw) + 2 * rnd(4 * (s.ntiles * s.K * sx::kRecGroups + 1)) + rnd(4 * n_rec + 4) +
+       2 * rnd(4 * s.npad * s.kw) + 2 * rnd(4 * (s.ntiles * s.K * sx::kRecGroups + 1)) + rnd(4 * n_rec + 4) +
        rnd(16 * s.E + 16) + rnd(4 * s.E + 4);
   b += rnd(4 * (s.ntiles + 1)) + rnd(4 * n_halo + 4) + rnd(2 * s.E) + rnd(s.ntiles);
   b += rnd(4 * (s.npad + 1)) + rnd(4 * n_em + 4) + rnd(8 * n_em + 8);
@@ -500,8 +509,8 @@ Grid *find(sx_ctx *ctx, sx_grid_id id) {
 
 int write_slot(sx_ctx *ctx, Grid *g) {
   HIP_TRY(ctx, hipMemcpyAsync(ctx->table + g->slot, &g->hg, sizeof(GridDev),
-                              hipMemcpyHostToDevice, ctx->stream));
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+                              hipMemcpyHostToDevice, wstream(ctx)));
+  HIP_TRY(ctx, hipStreamSynchronize(wstream(ctx)));
   return SX_OK;
 }
 
@@ -524,7 +533,7 @@ void gfree(sx_ctx *ctx, Grid *g, void *p) {
 int build_ct_tables(sx_ctx *ctx, Grid *g) {
   GridDev &h = g->hg;
   GridDev *dg = ctx->table + g->slot;
-  hipStream_t st = ctx->stream;
+  hipStream_t st = wstream(ctx);
   HIP_TRY(ctx, sx::launch_ebin_in(dg, h, st));
   HIP_TRY(ctx, sx::launch_kl_count(dg, h, st));
   HIP_TRY(ctx, sx::launch_scan(h.kl_cnt, h.kl_ptr, h.kl_part, (int32_t)h.n_edges, st));
@@ -1086,12 +1095,14 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   GA(d_ebin, E);
   GA(d_inw, npad * S.kb);
   GA(d_mb, npad * S.kw);
+  uint32_t *d_mb2;
+  GA(d_mb2, npad * S.kw);
   GA(d_rec_cnt, ntiles * K * sx::kRecGroups + 1);
   GA(d_rec_ptr, ntiles * K * sx::kRecGroups + 1);
   int64_t *d_part;
   GA(d_part, ntiles * K * sx::kRecGroups / 1024 + 2);
   uint32_t *d_smask;
-  GA(d_smask, 4 * E + 4);
+  GA(d_smask, 4 * (E + 1));
   int32_t *d_erev;
   GA(d_erev, E + 1);
   GA(d_hptr, ntiles + 1);
@@ -1126,6 +1137,7 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   h.ebin = d_ebin;
   h.inw = d_inw;
   h.mbits = d_mb;
+  h.mbits2 = d_mb2;
   h.rec_cnt = d_rec_cnt;
   h.rec_ptr = d_rec_ptr;
   h.scan_part = d_part;
@@ -1151,7 +1163,7 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   g->slot = ctx->free_slots.back();
   ctx->free_slots.pop_back();
 
-  hipStream_t st = ctx->stream;
+  hipStream_t st = wstream(ctx);
   auto H2D = [&](void *dst, const void *src, size_t bytes) {
     if (bytes == 0) return hipSuccess;
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
@@ -1439,6 +1451,15 @@ int sx_init(sx_ctx **out, const sx_ctx_opts *opts) {
     }
     ctx->scratch = (uint8_t *)sp;
   }
+  if (hipStreamCreateWithFlags(&ctx->io, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipHostFree(ctx->pin);
+    (void)hipFree(ctx->done);
+    (void)hipFree(ctx->table);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return SX_EDEVICE;
+  }
   for (int s = kMaxSlots - 1; s >= 0; --s) ctx->free_slots.push_back(s);
   *out = ctx;
   return SX_OK;
@@ -1448,6 +1469,8 @@ int sx_finalize(sx_ctx *ctx) {
   if (!ctx) return SX_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  (void)hipStreamSynchronize(ctx->io);
+  ctx->io_on = false;
   for (auto &kv : ctx->grids) grid_release(ctx, kv.second);
   ctx->grids.clear();
   drop_plans(ctx, -1);
@@ -1458,6 +1481,7 @@ int sx_finalize(sx_ctx *ctx) {
   (void)hipFree(ctx->done);
   (void)hipFree(ctx->table);
   if (ctx->pin) (void)hipHostFree(ctx->pin);
+  if (ctx->io) (void)hipStreamDestroy(ctx->io);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return SX_OK;
@@ -1591,9 +1615,20 @@ int sx_rotate_bins(sx_ctx *ctx, sx_grid_id id, const double *R) {
       cnt[(size_t)best + 1]++;
     }
     for (int64_t q = 0; q < K; ++q) cnt[(size_t)q + 1] += cnt[(size_t)q];
-    for (int64_t q = 0; q <= K; ++q) map.ptr[q] = (uint8_t)cnt[(size_t)q];
+    std::vector<uint8_t> list((size_t)K);
     std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
-    for (int64_t k = 0; k < K; ++k) map.list[fill[(size_t)to[(size_t)k]]++] = (uint8_t)k;
+    for (int64_t k = 0; k < K; ++k) list[(size_t)fill[(size_t)to[(size_t)k]]++] = (uint8_t)k;
+    // the same lists by storage position, for the device
+    const GridDev &hg = g->hg;
+    int32_t at = 0;
+    for (int64_t p = 0; p < K; ++p) {
+      const int kn = hg.bperm[p];
+      map.ptr[p] = (uint8_t)at;
+      map.bin[p] = (uint8_t)kn;
+      for (int32_t q = cnt[(size_t)kn]; q < cnt[(size_t)kn + 1]; ++q)
+        map.list[at++] = hg.bpos[list[(size_t)q]];
+    }
+    map.ptr[K] = (uint8_t)at;
   }
   int r = rebuild_routing(ctx, g, b.data(), &map);
   if (r) return r;
@@ -1606,8 +1641,9 @@ int sx_grid_free(sx_ctx *ctx, sx_grid_id id) {
   Grid *g = find(ctx, id);
   if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
   (void)hipSetDevice(ctx->device);
-  (void)hipStreamSynchronize(ctx->stream);
-  // launch plans that reference this grid's slot
+  (void)hipStreamSynchronize(wstream(ctx));
+  // launch plans that reference this grid's slot (none of them is running
+  // while io_on: the caller frees only grids outside the running sweeps)
   drop_plans(ctx, g->slot);
   ctx->grids.erase(id);
   grid_release(ctx, g);
@@ -1711,7 +1747,7 @@ int plan_build(sx_ctx *ctx, Plan *p, const std::vector<Grid *> &gs) {
 
 // Plans that hold `slot` (all plans for slot < 0), after the stream drains.
 void drop_plans(sx_ctx *ctx, int slot) {
-  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipStreamSynchronize(wstream(ctx));
   std::vector<Plan *> keep;
   for (Plan *p : ctx->plans) {
     if (slot < 0 || std::find(p->key.begin(), p->key.end(), slot) != p->key.end()) {
@@ -1993,6 +2029,16 @@ int sx_step_noalloc(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, int32_t n_swe
 }
 
 int sx_solve(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, const int32_t *n_sweeps) {
+  int r = sx::solve_launch(ctx, ids, n, n_sweeps);
+  if (r) return r;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  HIP_TRY(ctx, hipGetLastError());
+  return SX_OK;
+}
+
+}  // extern "C"
+
+int sx::solve_launch(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, const int32_t *n_sweeps) {
   if (!ctx) return SX_EINVAL;
   if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
   std::vector<Grid *> gs;
@@ -2011,12 +2057,18 @@ int sx_solve(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, const int32_t *n_swe
   }
   HIP_TRY(ctx, sx::launch_set_remaining(ctx->table, slots.data(), vals.data(), n, 0,
                                         ctx->stream));
-  r = launch_steps(ctx, gs, mx);
-  if (r) return r;
+  return launch_steps(ctx, gs, mx);
+}
+
+void sx::set_io_stream(sx_ctx *ctx, bool on) { ctx->io_on = on; }
+
+int sx::wait_sweeps(sx_ctx *ctx) {
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   HIP_TRY(ctx, hipGetLastError());
   return SX_OK;
 }
+
+extern "C" {
 
 int sx_profile(sx_ctx *ctx, int32_t enable) {
   if (!ctx) return SX_EINVAL;
@@ -2115,7 +2167,7 @@ int sx_read_state(sx_ctx *ctx, sx_grid_id id, const sx_state_out *out) {
   Grid *g = find(ctx, id);
   if (!g) return fail(ctx, SX_ENOTFOUND, "grid %lld not found", (long long)id);
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  hipStream_t st = ctx->stream;
+  hipStream_t st = wstream(ctx);
   const GridDev &h = g->hg;
   const int64_t n = h.n, npad = h.npad, K = h.k;
   GridDev cur;

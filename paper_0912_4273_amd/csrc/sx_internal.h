@@ -105,13 +105,14 @@ struct GridDev {
   uint8_t *ebin;            // [E]
   uint64_t *inw;            // [ntiles][kb][64]
   uint32_t *mbits;          // [ntiles][kw][64]
+  uint32_t *mbits2;         // [ntiles][kw][64] scratch: the new m words of a re-binning
   int32_t *rec_cnt;         // [ntiles*K*kRecGroups+1] scratch: records per (tile, bin, group)
   int32_t *rec_ptr;         // [ntiles*K*kRecGroups+1] first record of each
   int64_t *scan_part;       // [ntiles*K*kRecGroups/1024 + 2] scratch of the record scan
   int32_t *erev;            // [E+1] the edge of nbr[e]'s row that points back at e's row
-  uint32_t *smask;          // [4*E+4] written by the selection: bit p of word 4e + p/32
-                            // is set iff the bin at storage position p of sender
-                            // nbr[e] selects j
+  uint32_t *smask;          // [4*(E+1)] written by the selection: bit p % 32 of word
+                            // (p / 32) (E + 1) + e is set iff the bin at storage
+                            // position p of sender nbr[e] selects j (four planes)
   uint32_t *rec;            // [n_rec]
   int64_t rec_cap;
   const int32_t *halo_ptr;  // [ntiles+1]
@@ -184,12 +185,13 @@ hipError_t launch_edge_bins(const GridDev *dg, const GridDev &hg, hipStream_t s)
 hipError_t launch_inlist_count(const GridDev *dg, const GridDev &hg, hipStream_t s);
 hipError_t launch_scan(int32_t *cnt, int32_t *ptr, int64_t *part, int32_t n, hipStream_t s);
 hipError_t launch_inlist_fill(const GridDev *dg, const GridDev &hg, hipStream_t s);
-// After a rotation of the bins: for every new bin, the old bins whose
-// photons it takes (the old bins closest in direction to it), ascending:
-// list[ptr[kn] .. ptr[kn+1]).
+// After a rotation of the bins: for every new bin (by storage position), the
+// old bins whose photons it takes (the old bins closest in direction to
+// it), as storage positions in ascending old bin.
 struct RebinMap {
-  uint8_t ptr[132];
-  uint8_t list[128];
+  uint8_t ptr[132];   // by new storage position p: list[ptr[p] .. ptr[p+1])
+  uint8_t list[128];  // the old storage positions, in ascending old bin
+  uint8_t bin[128];   // the bin at each new position
 };
 static_assert(SX_MAX_BINS_FP32 < 128 && SX_MAX_BINS_FP64 < 128, "rebin map holds 127 bins");
 // The photons each vertex holds move to their new bins (map) and are split
@@ -252,6 +254,15 @@ hipError_t launch_noalloc_tables(uint8_t *base, const NoAllocList &L, hipStream_
 hipError_t launch_set_remaining(GridDev *table, const int32_t *slots,
                                 const int32_t *values, int32_t n, int32_t add,
                                 hipStream_t s);
+
+// For the request loop (sx_serve.cpp), which owns its context:
+// sx_solve without the final wait (the sweeps are enqueued on the context
+// stream); the wait for them; and the switch that puts the upload, read-back
+// and release calls on the context's second stream, so that they overlap
+// sweeps of other grids.
+int solve_launch(sx_ctx *ctx, const sx_grid_id *ids, int32_t n, const int32_t *n_sweeps);
+int wait_sweeps(sx_ctx *ctx);
+void set_io_stream(sx_ctx *ctx, bool on);
 
 
 }  // namespace sx

@@ -153,22 +153,18 @@ __global__ void k_erev(const GridDev *__restrict__ gp) {
 // directions are staged in LDS once and its bins run over them in row
 // order.
 struct Top3 {
-  double c0, c1, c2;
+  double c0 = -3.0, c1 = -3.0, c2 = -3.0;
   uint32_t s0 = kEmptySlot, s1 = kEmptySlot, s2 = kEmptySlot, cnt = 0;
-  // the floor is the eligibility bound: only cosines above it enter
-  __device__ __forceinline__ explicit Top3(double floor) : c0(floor), c1(floor), c2(floor) {}
-  // Branch-free insertion: a cosine enters above every held one it exceeds
-  // strictly, so an equal later one (a higher slot) never displaces.  cnt
-  // counts entries; it reaches min(eligible, 3), all that m needs.
-  __device__ __forceinline__ void add(double c, uint32_t s) {
-    const bool g0 = c > c0, g1 = c > c1, g2 = c > c2;
-    c2 = g1 ? c1 : (g2 ? c : c2);
-    s2 = g1 ? s1 : (g2 ? s : s2);
-    c1 = g0 ? c0 : (g1 ? c : c1);
-    s1 = g0 ? s0 : (g1 ? s : s1);
-    c0 = g0 ? c : c0;
-    s0 = g0 ? s : s0;
-    cnt += g2 ? 1u : 0u;
+  __device__ __forceinline__ void add(double c, uint32_t s, double cos_min) {
+    if (!(c > cos_min)) return;
+    if (c > c0) {
+      c2 = c1; s2 = s1; c1 = c0; s1 = s0; c0 = c; s0 = s;
+    } else if (c > c1) {
+      c2 = c1; s2 = s1; c1 = c; s1 = s;
+    } else if (c > c2) {
+      c2 = c; s2 = s;
+    }
+    ++cnt;
   }
   __device__ __forceinline__ uint32_t word(int mpb) const {
     const uint32_t n = cnt > (uint32_t)mpb ? (uint32_t)mpb : cnt;
@@ -202,11 +198,10 @@ __device__ __forceinline__ void select_bin(const GridDev &g, int64_t i, int k,
                                            const SX_L double *ed, SX_L uint32_t *ms, int n) {
   double u[3] = {g.bins[3 * k], g.bins[3 * k + 1], g.bins[3 * k + 2]};
   if (g.dct_ref) n = ref_edge(ed, n, g.cos_min, u);
-  Top3 a(g.cos_min);
-#pragma unroll 4
+  Top3 a;
   for (int t = 0; t < n; ++t) {
     const double d[3] = {ed[3 * t], ed[3 * t + 1], ed[3 * t + 2]};
-    a.add(cosine3(d, u), (uint32_t)t);
+    a.add(cosine3(d, u), (uint32_t)t, g.cos_min);
   }
   const uint32_t word = a.word(g.mpb);
   g.fwd[i * g.k + k] = word;
@@ -272,13 +267,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                  v == 0 ? deg[0] : deg[1]);
   }
   __syncthreads();
-  // out-edge (i, t) is the receiver's in-edge erev[rb + t]
+  // out-edge (i, t) is the receiver's in-edge erev[rb + t]; the masks are
+  // four planes of E + 1 words (word q of edge e at q (E + 1) + e)
   typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+  const int64_t pl = g.n_edges + 1;
 #pragma unroll
   for (int v = 0; v < 2; ++v) {
     const SX_L uint32_t *ms = (const SX_L uint32_t *)sm(2 * w + v);
-    for (int t = lane; t < deg[v]; t += 64)
-      *(U4 *)(g.smask + 4 * (int64_t)g.erev[rb[v] + t]) = *(const SX_L U4 *)(ms + 4 * t);
+    for (int t = lane; t < deg[v]; t += 64) {
+      const U4 m = *(const SX_L U4 *)(ms + 4 * t);
+      const int64_t e = g.erev[rb[v] + t];
+      g.smask[e] = m.x;
+      g.smask[pl + e] = m.y;
+      g.smask[2 * pl + e] = m.z;
+      g.smask[3 * pl + e] = m.w;
+    }
   }
 }
 
@@ -318,9 +321,9 @@ __global__ __launch_bounds__(256) void k_edge_bins(const GridDev *__restrict__ g
 // ------------------------------------------------------- gather lists ---
 // The receiver side of the selection: neighbour t of j sends bin k to j iff
 // j is among the selected slots of (nbr_t, k).  The gather-list kernels read
-// it from the receiving side: one mask per in-edge e of j (bit p of word 4e
-// + p/32 set iff the bin at storage position p of sender nbr[e] selects j),
-// written by the selection kernel.
+// it from the receiving side: one mask per in-edge e of j (bit p % 32 of
+// word e of plane p / 32 set iff the bin at storage position p of sender
+// nbr[e] selects j), written by the selection kernel.
 __device__ __forceinline__ int sender_index(const GridDev &g, bool direct,
                                             int e, int rb) {
   return direct ? e - rb : (int)g.edge_hidx[e];
@@ -367,7 +370,7 @@ __global__ __launch_bounds__(256) void k_inlist(const GridDev *__restrict__ gp) 
   const bool valid = j < g.n;
   const int rb = valid ? g.row_ptr[j] : 0;
   const int re = valid ? g.row_ptr[j + 1] : 0;
-  const uint32_t *mw = g.smask + (p0 >> 5);
+  const uint32_t *mw = g.smask + (int64_t)(p0 >> 5) * (g.n_edges + 1);
   const int sh = p0 & 31;
   // records per bin position of the group: this lane's count, then (fill)
   // where its next record goes
@@ -384,11 +387,11 @@ __global__ __launch_bounds__(256) void k_inlist(const GridDev *__restrict__ gp) 
       c[q] = 0;
     }
     flag = 0;
+#pragma unroll 4
     for (int e = rb; e < re; ++e) {
-      const uint32_t m16 = (mw[4 * (int64_t)e] >> sh) & 0xFFFFu;
+      const uint32_t m16 = (mw[e] >> sh) & 0xFFFFu;
       if (m16 == 0u) continue;
       const int s = e - rb;
-      const uint32_t idx = (uint32_t)sender_index(g, direct, e, rb);
 #pragma unroll
       for (int q = 0; q < KQ; ++q) {
         const uint32_t nib = (m16 >> (q * BB)) & ((1u << BB) - 1u);
@@ -398,6 +401,7 @@ __global__ __launch_bounds__(256) void k_inlist(const GridDev *__restrict__ gp) 
           ++c[q];
         } else {
           flag |= 1u << q;
+          const uint32_t idx = (uint32_t)sender_index(g, direct, e, rb);
 #pragma unroll
           for (int b = 0; b < BB; ++b) {
             if (!((nib >> b) & 1u)) continue;
@@ -490,8 +494,9 @@ __global__ void k_kl_count(const GridDev *__restrict__ gp) {
     g.kl_cnt[e] = 0;
     return;
   }
-  const uint32_t *m = g.smask + 4 * e;
-  g.kl_cnt[e] = __popc(m[0]) + __popc(m[1]) + __popc(m[2]) + __popc(m[3]);
+  const int64_t pl = g.n_edges + 1;
+  const uint32_t *m = g.smask + e;
+  g.kl_cnt[e] = __popc(m[0]) + __popc(m[pl]) + __popc(m[2 * pl]) + __popc(m[3 * pl]);
 }
 
 // A workgroup's 256 lists are contiguous in the pool: they are built in
@@ -509,10 +514,11 @@ __global__ __launch_bounds__(256) void k_kl_fill(const GridDev *__restrict__ gp)
   const int64_t base = g.kl_ptr[e0], end = g.kl_ptr[e1];
   const bool staged = end - base <= kKlStage;   // the same for the whole block
   if (e < g.n_edges) {
-    const uint32_t *m = g.smask + 4 * e;
+    const uint32_t *m = g.smask + e;
+    const int64_t pl = g.n_edges + 1;
     int64_t p = g.kl_ptr[e];
     for (int q = 0; q < 4; ++q) {
-      uint32_t w = m[q];
+      uint32_t w = m[q * pl];
       while (w) {
         const int bit = __ffs(w) - 1;
         const uint8_t k = (uint8_t)(32 * q + bit);   // the bin's storage position
@@ -565,7 +571,8 @@ __global__ void k_em_bins(GridDev *__restrict__ gp, int64_t n_em) {
 static_assert((SX_MAX_BINS_FP32 + 15) / 16 <= 6 && (SX_MAX_BINS_FP64 + 15) / 16 <= 6,
               "k_mbits holds at most 6 m words per vertex (one wave each)");
 
-__global__ __launch_bounds__(64 * 6) void k_mbits(GridDev *__restrict__ gp) {
+__global__ __launch_bounds__(64 * 6) void k_mbits(GridDev *__restrict__ gp,
+                                                  uint32_t *__restrict__ out) {
   GridDev &g = *gp;
   const int tile = blockIdx.x, q = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = tile * kTile + lane;
@@ -579,14 +586,14 @@ __global__ __launch_bounds__(64 * 6) void k_mbits(GridDev *__restrict__ gp) {
   uint32_t mword = 0;
 #pragma unroll
   for (int b = 0; b < 16; ++b) mword |= ((v[b] >> 21) & 3u) << (2 * b);
-  g.mbits[((int64_t)tile * g.kw + q) * 64 + lane] = mword;
+  out[((int64_t)tile * g.kw + q) * 64 + lane] = mword;
 }
 
 // Re-binning after a rotation of the bins.  Photons keep their direction as
 // closely as the rotated bins allow: what vertex j holds in old bin k (m_old
 // Ipre, times T_j) moves to the new bin whose direction is closest to old
-// bin k's.  The map gives, for every new bin, the old bins it takes
-// (ascending); their holdings add up in that order and are split over the
+// bin k's.  The map gives, for every new bin (by storage position), the old
+// bins it takes (ascending); their holdings add up in that order and are split over the
 // new bin's m_new selected neighbours, or leave the domain (escape tally)
 // where m_new = 0.  A new bin fed by one old bin with the same m keeps its
 // Ipre as it is.  Thread = vertex, tile = wave; the new field is written to
@@ -607,16 +614,21 @@ __global__ __launch_bounds__(256) void k_rebin(GridDev *__restrict__ gp, RebinMa
   const int par = g.parity;
   const P *oin = (const P *)g.o[par];
   V *oout = (V *)g.o[par ^ 1];
-  // old m, 16 bins per word in storage order, read before any is replaced
-  uint32_t mo[6];
+  // old and new m, 16 bins per word in storage order, read before any old
+  // word is replaced
+  uint32_t mo[6], mw[6];
 #pragma unroll
-  for (int q = 0; q < 6; ++q) mo[q] = q < kw ? g.mbits[((int64_t)tile * kw + q) * 64 + lane] : 0u;
-  auto m_old = [&](int p) -> uint32_t {
+  for (int q = 0; q < 6; ++q) {
+    mo[q] = q < kw ? g.mbits[((int64_t)tile * kw + q) * 64 + lane] : 0u;
+    mw[q] = q < kw ? g.mbits2[((int64_t)tile * kw + q) * 64 + lane] : 0u;
+  }
+  auto pick = [](const uint32_t *a, int p) -> uint32_t {
     const int q = p >> 4;
-    const uint32_t w = q == 0 ? mo[0] : q == 1 ? mo[1] : q == 2 ? mo[2] : q == 3 ? mo[3]
-                                                               : q == 4 ? mo[4] : mo[5];
+    const uint32_t w = q == 0 ? a[0] : q == 1 ? a[1] : q == 2 ? a[2] : q == 3 ? a[3]
+                                                             : q == 4 ? a[4] : a[5];
     return (w >> (2 * (p & 15))) & 3u;
   };
+  auto m_old = [&](int p) -> uint32_t { return pick(mo, p); };
   auto held = [&](int p) -> P {
     return oin[(((int64_t)tile * KB + p / BB) * 64 + lane) * BB + p % BB];
   };
@@ -625,18 +637,19 @@ __global__ __launch_bounds__(256) void k_rebin(GridDev *__restrict__ gp, RebinMa
   double esc = 0.0;
   uint32_t mword = 0;
   V out = V(0);
+  // new bins in storage order
+#pragma unroll 2
   for (int p = 0; p < K; ++p) {
-    const int kn = g.bperm[p];
-    const uint32_t mn = j < g.n ? (g.fwd[(int64_t)j * K + kn] >> 21) & 3u : 0u;
-    const int q0 = map.ptr[kn], q1 = map.ptr[kn + 1];
+    const uint32_t mn = pick(mw, p);
+    const int q0 = map.ptr[p], q1 = map.ptr[p + 1];
     P val;
-    const int p1 = g.bpos[map.list[q0 < q1 ? q0 : 0]];
+    const int p1 = map.list[q0 < q1 ? q0 : 0];
     if (q1 - q0 == 1 && mn > 0u && mn == m_old(p1)) {
       val = held(p1);
     } else {
       double h = 0.0;
       for (int q = q0; q < q1; ++q) {
-        const int po = g.bpos[map.list[q]];
+        const int po = map.list[q];
         h += (double)held(po) * (double)m_old(po);
       }
       if (mn == 0u) {
@@ -1847,13 +1860,15 @@ hipError_t launch_clear_inw(const GridDev &hg, hipStream_t s) {
 }
 
 hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s) {
-  // the plain variant writes the m words only
   hipLaunchKernelGGL(k_mbits, dim3((unsigned)hg.ntiles), dim3(64 * hg.kw), 0, s,
-                     const_cast<GridDev *>(dg));
+                     const_cast<GridDev *>(dg), hg.mbits);
   return hipGetLastError();
 }
 
 hipError_t launch_rebin(GridDev *dg, const GridDev &hg, const RebinMap &map, hipStream_t s) {
+  // the new m words first, into the spare m array (coalesced reads for the
+  // re-binning, which replaces the old words with them)
+  hipLaunchKernelGGL(k_mbits, dim3((unsigned)hg.ntiles), dim3(64 * hg.kw), 0, s, dg, hg.mbits2);
   if (hg.precision == 0)
     hipLaunchKernelGGL(k_rebin<double>, dim3(blocks_for(hg.npad, 256)), dim3(256), 0, s, dg, map);
   else

@@ -3,12 +3,14 @@
 // Requests (a grid, its physics and a sweep count) arrive at any time from
 // any thread.  Worker threads run the host part of the upload
 // (sx_grid_prepare) while the GPU sweeps.  One scheduler thread owns the
-// context: between rounds it admits prepared requests in arrival order as
-// the HBM budget and the active-grid limit allow (sx_grid_commit), runs one
-// round of up to round_sweeps sweeps over every resident grid as a single
-// batch (each grid runs only the sweeps it still needs), and retires the
-// grids that are done: their state is read back into the server and their
-// device memory released, which makes room for the next admissions.
+// context.  It keeps one round in flight: a round is up to round_sweeps
+// sweeps over every resident grid as a single batch (each grid runs only the
+// sweeps it still needs), enqueued without waiting.  While it runs, the
+// scheduler admits prepared requests in arrival order as the HBM budget and
+// the active-grid limit allow (sx_grid_commit), and reads back and releases
+// the grids the previous round finished; these go on the context's second
+// stream, so the GPU keeps sweeping.  When the round ends, the next one is
+// enqueued at once over the grids still resident and those just admitted.
 // A grid's result does not depend on what it was batched with (each tile's
 // arithmetic is independent of the tile list), so it equals the result of
 // solving it alone.
@@ -25,6 +27,7 @@
 #include <vector>
 
 #include "sx.h"
+#include "sx_internal.h"
 
 namespace {
 
@@ -160,13 +163,19 @@ void worker(sx_server *s) {
 }
 
 void scheduler(sx_server *s) {
-  std::vector<Req *> active;
+  // active: resident grids; the running round is over `running`.  Uploads
+  // (admission), read-backs and releases go on the context's second stream,
+  // so that they overlap the round the GPU is running.
+  std::vector<Req *> active, running;
+  std::vector<int32_t> run_cnt;
   std::vector<sx_grid_id> ids;
-  std::vector<int32_t> cnt;
+  bool round_on = false;
+  auto t_round = std::chrono::steady_clock::now();
   std::unique_lock<std::mutex> lk(s->mu);
   bool dead = false;   // the context failed: finish everything with its error
+  sx::set_io_stream(s->ctx, true);
   for (;;) {
-    // ---- admission, in arrival order
+    // ---- admission, in arrival order (while a round runs, if one does)
     while (!s->ready.empty() && (int32_t)active.size() < s->opts.max_active) {
       Req *r = s->ready.front();
       if (dead) {
@@ -205,36 +214,69 @@ void scheduler(sx_server *s) {
       active.push_back(r);
     }
     s->peak_active = std::max(s->peak_active, (int32_t)active.size());
-    if (active.empty()) {
-      if (s->stopping && s->submitted.empty() && s->ready.empty() && s->in_prep == 0) return;
+    if (!round_on && active.empty()) {
+      if (s->stopping && s->submitted.empty() && s->ready.empty() && s->in_prep == 0) break;
       s->cv_sched.wait(lk);
       continue;
     }
-    // ---- one round over every resident grid
-    ids.clear();
-    cnt.clear();
-    for (Req *r : active) {
-      ids.push_back(r->gid);
-      cnt.push_back(std::min(r->left, s->opts.round_sweeps));
-    }
-    lk.unlock();
-    const auto tr = std::chrono::steady_clock::now();
-    int rc = dead ? SX_EDEVICE
-                  : sx_solve(s->ctx, ids.data(), (int32_t)ids.size(), cnt.data());
-    const double round_s =
-        std::chrono::duration<double>(std::chrono::steady_clock::now() - tr).count();
-    // ---- retire what is done (state read back, memory released)
-    std::vector<std::pair<Req *, int>> out;
-    std::vector<Req *> keep;
-    for (size_t i = 0; i < active.size(); ++i) {
-      Req *r = active[i];
-      if (rc) {
-        out.push_back({r, rc});
-        continue;
+    // ---- the end of the running round: what is done retires
+    std::vector<Req *> retire;
+    int rc = SX_OK;
+    if (round_on) {
+      lk.unlock();
+      rc = sx::wait_sweeps(s->ctx);
+      const double round_s =
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t_round).count();
+      lk.lock();
+      round_on = false;
+      s->rounds++;
+      s->gpu_s += round_s;
+      if (rc) dead = true;
+      for (size_t i = 0; i < running.size(); ++i) {
+        Req *r = running[i];
+        if (!rc) r->left -= run_cnt[i];
+        if (rc || r->left <= 0) retire.push_back(r);
       }
-      r->left -= cnt[i];
-      if (r->left > 0) {
-        keep.push_back(r);
+      running.clear();
+      std::vector<Req *> keep;
+      for (Req *r : active)
+        if (std::find(retire.begin(), retire.end(), r) == retire.end()) keep.push_back(r);
+      active.swap(keep);
+    }
+    if (dead) {
+      for (Req *r : active) retire.push_back(r);
+      active.clear();
+    }
+    // ---- the next round over every resident grid, enqueued at once
+    if (!active.empty()) {
+      ids.clear();
+      run_cnt.clear();
+      for (Req *r : active) {
+        ids.push_back(r->gid);
+        run_cnt.push_back(std::min(r->left, s->opts.round_sweeps));
+      }
+      running = active;
+      lk.unlock();
+      t_round = std::chrono::steady_clock::now();
+      const int lr = sx::solve_launch(s->ctx, ids.data(), (int32_t)ids.size(), run_cnt.data());
+      lk.lock();
+      if (lr) {
+        dead = true;
+        rc = lr;
+        for (Req *r : active) retire.push_back(r);
+        active.clear();
+        running.clear();
+      } else {
+        round_on = true;
+      }
+    }
+    // ---- read back and release the retired grids while that round runs
+    std::vector<std::pair<Req *, int>> out;
+    lk.unlock();
+    for (Req *r : retire) {
+      if (dead) {
+        (void)sx_grid_free(s->ctx, r->gid);
+        out.push_back({r, rc ? rc : SX_EDEVICE});
         continue;
       }
       r->x.resize((size_t)r->n);
@@ -244,19 +286,13 @@ void scheduler(sx_server *s) {
       so.y = r->y.data();
       so.tally = &r->tally;
       int rr = sx_read_state(s->ctx, r->gid, &so);
-      if (rr == SX_OK) rr = sx_grid_free(s->ctx, r->gid);
-      out.push_back({r, rr});
-    }
-    if (rc) {
-      dead = true;
-      for (Req *r : active) (void)sx_grid_free(s->ctx, r->gid);
+      const int fr = sx_grid_free(s->ctx, r->gid);
+      out.push_back({r, rr ? rr : fr});
     }
     lk.lock();
-    s->rounds++;
-    s->gpu_s += round_s;
     for (auto &o : out) finish(s, o.first, o.second);
-    active.swap(keep);
   }
+  sx::set_io_stream(s->ctx, false);
 }
 
 }  // namespace
