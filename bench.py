@@ -140,7 +140,10 @@ def shadow_leg(ctx, w, log, profile):
     lit = m["clump_c_kpc"][0] - m["clump_r_kpc"]
     back = m["clump_c_kpc"][0] + m["clump_r_kpc"]
     axis = (rperp < 0.25) & (p[:, 0] >= lit) & (p[:, 0] <= back)
-    depth = float(A.half_crossing(p[axis, 0] - lit, x[axis], 0.05))
+    try:
+        depth = float(A.half_crossing(p[axis, 0] - lit, x[axis], 0.05))
+    except AssertionError:   # a short run: the front has not reached the clump
+        depth = None
     behind = (p[:, 0] > back) & (p[:, 0] < back + 0.3) & (rperp < 0.25)
     off = (p[:, 0] > back) & (p[:, 0] < back + 0.3) & (rperp > 1.5)
     n_c = m["n_H"] * m["contrast"]
@@ -154,14 +157,15 @@ def shadow_leg(ctx, w, log, profile):
         sweeps=w.n_sweeps, ms_per_solve=1e3 * el, upload_s=up, sweep_kernel_us=1e3 * kern,
         algorithmic_hbm_frac=round(algorithmic_bytes_per_update(w.k, 4) * w.n * w.k
                                    / (kern * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        counter_bytes_per_launch=measured_traffic(f"shadow_{w.n}_k{w.k}"),
         device_bytes=info["bytes"],
         clump_axis_depth_kpc=depth, stromgren_length_1d_kpc=l_s,
-        clump_depth_over_1d_equilibrium_profile=round(depth / z_ode, 4),
+        clump_depth_over_1d_equilibrium_profile=None if depth is None else round(depth / z_ode, 4),
         x_axis_behind_clump=float(x[behind].mean()), x_off_shadow=float(x[off].mean()),
         conservation_residual=abs(tl["emitted"] - tl["absorbed"] - tl["escaped"]
                                   - tl["in_flight"]) / tl["emitted"])
     log(f"shadow: {res['value']:.3e} updates/s, sweep {1e3 * kern:.1f} us, depth "
-        f"{depth:.3f} kpc (1-D profile {z_ode:.3f}), axis behind {res['x_axis_behind_clump']:.3f} "
+        f"{depth} kpc (1-D profile {z_ode:.3f}), axis behind {res['x_axis_behind_clump']:.3f} "
         f"off {res['x_off_shadow']:.3f}")
     return res
 
@@ -823,6 +827,7 @@ def main():
             upload_s=up_b, sweep_kernel_us=1e3 * kb,
             algorithmic_hbm_frac=round(bpu_b * upd_b / args.batch_sweeps
                                        / (kb * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            counter_bytes_per_launch=measured_traffic(f"batched_{len(batch)}_k42"),
             schedule=sched,
             front_radius_over_analytic=dict(min=round(min(ratios), 4),
                                             median=round(float(np.median(ratios)), 4),
