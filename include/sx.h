@@ -371,17 +371,24 @@ int sx_grid_restore_edges(sx_ctx *ctx, sx_grid_id id, const double *photons_e,
 int sx_grid_select_removal(sx_ctx *ctx, sx_grid_id id, double tau_remove,
                            double min_spacing, uint8_t *remove, int64_t *n_removed);
 
-/* Move the state of grid `from` onto grid `to` (both direction-conserving,
- * on the spot, the same unrotated bins): new_of_old [N_from] gives each old
- * vertex's index in `to`, or -1 for a removed one; every vertex of `to`
- * must be hit once.  Kept vertices keep y.  What a vertex holds in a bin,
- * m O, stays in that bin with the vertex it maps to (a removed vertex's
- * goes to its nearest kept former neighbour, ties to the lower id) and is
- * split over that vertex's selection on the new grid; where none is
- * selected (or a removed vertex has no kept neighbour) it is counted as
- * escaped.  Tallies carry over.  Synchronous.  Errors: SX_EINVAL,
- * SX_ENOTSUP (combined transport, diffuse radiation or multi-hop steps),
- * SX_ENOTFOUND. */
+/* Move the state of grid `from` onto grid `to` (the same transport, the
+ * same recombination radiation, one hop per step, the same unrotated bins):
+ * new_of_old [N_from] gives each old vertex's index in `to`, or -1 for a
+ * removed one; every vertex of `to` must be hit once.  Kept vertices keep
+ * y.  What a vertex holds in a bin, m O, stays in that bin with the vertex
+ * it maps to (a removed vertex's goes to its nearest kept former neighbour,
+ * ties to the lower id) and is split over that vertex's selection on the
+ * new grid; where none is selected (or a removed vertex has no kept
+ * neighbour) it is counted as escaped.  Combined transport: a vertex that
+ * holds its photons per incoming edge first files each packet, bm O_e in
+ * all, in the bin of the edge it came along (i -> j), the bin a
+ * direction-conserving vertex takes it in (Sect. 2.2.4); every vertex of
+ * `to` starts holding bins.  Diffuse recombination radiation: the photons
+ * a vertex still has to send (sx_read_diffuse) move the same way and are
+ * sent from there at the next step.  Tallies carry over (in_flight counts
+ * what was moved, escaped what was not).  Synchronous.  Errors: SX_EINVAL
+ * (bad map, different transport, radiation or bins), SX_ENOTSUP
+ * (multi-hop steps), SX_ENOTFOUND. */
 int sx_grid_remap(sx_ctx *ctx, sx_grid_id from, sx_grid_id to, const int32_t *new_of_old);
 
 /* Diffuse recombination radiation: the photons each vertex made in the last

@@ -2586,10 +2586,11 @@ int sx_grid_remap(sx_ctx *ctx, sx_grid_id from, sx_grid_id to, const int32_t *ne
   if (ctx->poisoned) return fail(ctx, SX_EDEVICE, "context poisoned: %s", ctx->err.c_str());
   Grid *a = find(ctx, from), *b = find(ctx, to);
   if (!a || !b) return fail(ctx, SX_ENOTFOUND, "grid not found");
-  if (a->hg.transport != SX_TRANSPORT_DCT || b->hg.transport != SX_TRANSPORT_DCT ||
-      a->hg.hops > 1 || b->hg.hops > 1)
-    return fail(ctx, SX_ENOTSUP,
-                "remap needs direction-conserving, on-the-spot grids of one hop per step");
+  if (a->hg.hops > 1 || b->hg.hops > 1)
+    return fail(ctx, SX_ENOTSUP, "remap needs grids of one hop per step");
+  if (a->hg.transport != b->hg.transport || a->hg.diffuse != b->hg.diffuse)
+    return fail(ctx, SX_EINVAL, "remap needs the same transport and the same recombination "
+                                "radiation on both grids");
   const int64_t na = a->hg.n, nb = b->hg.n, K = a->hg.k;
   if (b->hg.k != K || a->bins0 != b->bins0 || a->rotated || b->rotated)
     return fail(ctx, SX_EINVAL, "remap needs the same unrotated bins on both grids");
@@ -2604,6 +2605,7 @@ int sx_grid_remap(sx_ctx *ctx, sx_grid_id from, sx_grid_id to, const int32_t *ne
   }
   for (int64_t j = 0; j < nb; ++j)
     if (!hit[(size_t)j]) return fail(ctx, SX_EINVAL, "vertex %lld of the new grid has no old vertex", (long long)j);
+  const bool comb = a->hg.transport != SX_TRANSPORT_DCT;
   std::vector<double> ya((size_t)na), oa((size_t)(na * K));
   std::vector<int32_t> ma((size_t)(na * K)), mb((size_t)(nb * K));
   sx_tally t{};
@@ -2612,16 +2614,43 @@ int sx_grid_remap(sx_ctx *ctx, sx_grid_id from, sx_grid_id to, const int32_t *ne
   if (!r) r = sx_read_tables(ctx, from, nullptr, ma.data(), nullptr, nullptr, nullptr);
   if (!r) r = sx_read_tables(ctx, to, nullptr, mb.data(), nullptr, nullptr, nullptr);
   if (r) return r;
-  // what each vertex holds per bin, m O, moves with it; a removed vertex's
-  // goes to its nearest kept former neighbour (ties: lower id), in the same
-  // bin, added in ascending old id
-  std::vector<double> held((size_t)(nb * K), 0.0), yb((size_t)nb, 1.0);
-  double lost = 0.0;
+  // combined transport: a vertex that holds edges holds bm O_e for the packet
+  // that came along i -> j, filed here in the bin of that edge (the bin a
+  // direction-conserving vertex files it in, Sect. 2.2.4); the thinned grid
+  // starts with every vertex holding bins
+  std::vector<double> extra;
+  if (comb) {
+    const int64_t E = a->hg.n_edges;
+    std::vector<double> pe((size_t)E);
+    std::vector<uint8_t> lay((size_t)na);
+    std::vector<int32_t> eb((size_t)E), bm((size_t)E);
+    r = sx_read_edge_state(ctx, from, pe.data(), lay.data());
+    if (!r) r = sx_read_ballistic(ctx, from, nullptr, bm.data());
+    if (!r) r = sx_read_tables(ctx, from, nullptr, nullptr, eb.data(), nullptr, nullptr);
+    if (r) return r;
+    const std::vector<int32_t> n2o = new_to_orig_edges(a);
+    const std::vector<int32_t> &rp = a->row_ptr_h, &nbr = a->nbr_h;
+    extra.assign((size_t)(na * K), 0.0);
+    for (int64_t i = 0; i < na; ++i) {
+      if (!lay[(size_t)i]) continue;
+      const int32_t v = (int32_t)a->inv[(size_t)i];
+      for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) {
+        const int32_t u = nbr[(size_t)e];
+        int32_t back = -1;   // the edge u -> v in u's row
+        for (int32_t f = rp[(size_t)u]; f < rp[(size_t)u + 1]; ++f)
+          if (nbr[(size_t)f] == v) { back = f; break; }
+        if (back < 0) return fail(ctx, SX_EDEVICE, "neighbour rows are not symmetric");
+        const int32_t p = n2o[(size_t)e];
+        extra[(size_t)(i * K + eb[(size_t)n2o[(size_t)back]])] += pe[(size_t)p] * (double)bm[(size_t)p];
+      }
+    }
+  }
+  // where each old vertex's holdings go: the vertex it maps to, or for a
+  // removed one its nearest kept former neighbour (ties: lower id); -1 none
+  std::vector<int32_t> dest((size_t)na);
   for (int64_t i = 0; i < na; ++i) {
     int32_t j = new_of_old[i];
-    if (j >= 0) {
-      yb[(size_t)j] = ya[(size_t)i];
-    } else {
+    if (j < 0) {
       const int64_t v = a->inv[(size_t)i];
       double best = 0.0;
       int32_t bo = -1;
@@ -2633,8 +2662,17 @@ int sx_grid_remap(sx_ctx *ctx, sx_grid_id from, sx_grid_id to, const int32_t *ne
       }
       j = bo >= 0 ? new_of_old[bo] : -1;
     }
+    dest[(size_t)i] = j;
+  }
+  // m O per bin moves to dest in the same bin, added in ascending old id
+  std::vector<double> held((size_t)(nb * K), 0.0), yb((size_t)nb, 1.0);
+  double lost = 0.0;
+  for (int64_t i = 0; i < na; ++i) {
+    const int32_t j = dest[(size_t)i];
+    if (new_of_old[i] >= 0) yb[(size_t)j] = ya[(size_t)i];
     for (int64_t k = 0; k < K; ++k) {
-      const double hk = oa[(size_t)(i * K + k)] * (double)ma[(size_t)(i * K + k)];
+      double hk = oa[(size_t)(i * K + k)] * (double)ma[(size_t)(i * K + k)];
+      if (comb) hk = hk + extra[(size_t)(i * K + k)];
       if (j >= 0) held[(size_t)(j * K + k)] += hk;
       else lost += hk;
     }
@@ -2650,11 +2688,42 @@ int sx_grid_remap(sx_ctx *ctx, sx_grid_id from, sx_grid_id to, const int32_t *ne
       lost += held[(size_t)q];
     }
   }
+  // diffuse recombination photons still to be sent move the same way
+  std::vector<double> pb;
+  if (a->hg.diffuse) {
+    std::vector<double> pa((size_t)na);
+    r = sx_read_diffuse(ctx, from, pa.data());
+    if (r) return r;
+    pb.assign((size_t)nb, 0.0);
+    for (int64_t i = 0; i < na; ++i) {
+      const int32_t j = dest[(size_t)i];
+      if (j >= 0) pb[(size_t)j] += pa[(size_t)i];
+      else lost += pa[(size_t)i];
+    }
+    for (int64_t j = 0; j < nb; ++j) fly += pb[(size_t)j];
+  }
   sx_tally tb = t;
   tb.escaped = t.escaped + lost;
   tb.in_flight = fly;
   sx_state_in si{yb.data(), ob.data(), &tb};
-  return sx_grid_restore(ctx, to, &si);
+  r = sx_grid_restore(ctx, to, &si);
+  if (r || pb.empty()) return r;
+  // the pending photons go in as each vertex's share per neighbour
+  const GridDev &h = b->hg;
+  GridDev cur;
+  HIP_TRY(ctx, hipMemcpy(&cur, ctx->table + b->slot, sizeof cur, hipMemcpyDeviceToHost));
+  auto put = [&](auto zero) -> int {
+    using T = decltype(zero);
+    std::vector<T> d((size_t)h.plane, zero);
+    for (int64_t j = 0; j < nb; ++j) {
+      const int64_t v = b->inv[(size_t)j];
+      const int deg = b->row_ptr_h[(size_t)v + 1] - b->row_ptr_h[(size_t)v];
+      d[(size_t)v] = (T)(pb[(size_t)j] / (deg > 0 ? (double)deg : 1.0) / h.unit);
+    }
+    HIP_TRY(ctx, hipMemcpy(h.dsh[cur.parity], d.data(), sizeof(T) * h.plane, hipMemcpyHostToDevice));
+    return SX_OK;
+  };
+  return h.precision == SX_FP64 ? put(0.0) : put(0.0f);
 }
 
 int sx_grid_info(sx_ctx *ctx, sx_grid_id id, int64_t *n, int32_t *k, int64_t *n_edges,
