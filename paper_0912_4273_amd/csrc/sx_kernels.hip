@@ -891,13 +891,18 @@ __device__ __forceinline__ void wave_sync() {
 
 // a + v where bit b of x is set, else a + 0 (the same bits as skipping the
 // add: the sums are never -0); branch-free, by masking v's bits
-__device__ __forceinline__ float add_if_bit(float a, float v, uint32_t x, int b) {
-  const int m = (int)(x << (31 - b)) >> 31;
-  return a + __int_as_float(__float_as_int(v) & m);
+// a + v where bit `pos` (0..63, a constant once unrolled) of w is set, else
+// a + 0: the bit is extended to a mask of all ones or zeros (one bit-field
+// extract, no compare and select) and ANDed into v.
+__device__ __forceinline__ int bit_mask(uint64_t w, int pos) {
+  return pos < 32 ? __builtin_amdgcn_sbfe((int)(uint32_t)w, pos, 1)
+                  : __builtin_amdgcn_sbfe((int)(uint32_t)(w >> 32), pos - 32, 1);
 }
-__device__ __forceinline__ double add_if_bit(double a, double v, uint32_t x, int b) {
-  const long long m = (long long)((int)(x << (31 - b)) >> 31);
-  return a + __longlong_as_double(__double_as_longlong(v) & m);
+__device__ __forceinline__ float add_if_bit(float a, float v, uint64_t w, int pos) {
+  return a + __int_as_float(__float_as_int(v) & bit_mask(w, pos));
+}
+__device__ __forceinline__ double add_if_bit(double a, double v, uint64_t w, int pos) {
+  return a + __longlong_as_double(__double_as_longlong(v) & (long long)bit_mask(w, pos));
 }
 
 template <typename P>
@@ -1219,9 +1224,8 @@ __device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int ti
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
         const V v = hln[hx[e]];
-        const uint32_t x = (uint32_t)(w >> (EB * e + 5));
 #pragma unroll
-        for (int b = 0; b < BB; ++b) acc[b] = add_if_bit(acc[b], v[b], x, b);
+        for (int b = 0; b < BB; ++b) acc[b] = add_if_bit(acc[b], v[b], w, EB * e + 5 + b);
       }
     } else {
 #pragma unroll
@@ -1303,13 +1307,18 @@ __device__ __forceinline__ void sweep_bins(const GridDev *__restrict__ G, int ti
           for (int q = 0; q < 5; ++q) mwv[q] = mwv[q + 1];
         }
         bs.cur_n += acc[b];
-        bs.cur_e += m == 0u ? acc[b] : P(0);
         if constexpr (sizeof(P) == 8) {
+          bs.cur_e += m == 0u ? acc[b] : P(0);
           ipre = m == 0u ? 0.0 : (m == 1u ? acc[b] : (m == 2u ? acc[b] * 0.5 : acc[b] / 3.0));
         } else {
-          // 1/m for m = 1, 2, 3 as (m^2 - 6m + 11) / 6 (no table lookup)
-          const float fm = (float)(int)(m * m - 6u * m + 11u) * (1.0f / 6.0f);
-          ipre = m == 0u ? 0.0f : acc[b] * fm;
+          // no branches: the escape share through a mask that is all ones
+          // iff m = 0, and 1/m for m = 0..3 as m (85 + m (11 m - 60)) / 36
+          // (0, 1, 1/2 and 1/3 rounded to float; 0 where nothing is chosen)
+          const int em = ((int)m - 1) >> 31;
+          bs.cur_e += __int_as_float(__float_as_int(acc[b]) & em);
+          const int mi = (int)m;
+          const float fm = (float)(mi * (85 + mi * (11 * mi - 60))) * (1.0f / 36.0f);
+          ipre = acc[b] * fm;
         }
       }
       out[b] = ipre;
