@@ -478,7 +478,8 @@ uint64_t bytes_estimate(const Sizes &s, int64_t n_em, int64_t n_rec, int64_t n_h
   uint64_t b = 0;
   b += rnd(4 * (s.npad + 1)) + rnd(4 * s.E) + rnd(s.E) + rnd(24 * s.E) + rnd(24 * s.K);
   b += rnd(4 * s.npad * s.K) + rnd(s.E) + rnd(8 * s.npad * s.kb) +
-       2 * rnd(4 * s.npad * s.kw) + 2 * rnd(4 * (s.ntiles * s.K * sx::kRecGroups + 1)) + rnd(4 * n_rec + 4) +
+       2 * rnd(4 * s.npad * s.kw) + 2 * rnd(4 * (s.ntiles * s.K * sx::kRecGroups + 1)) +
+       rnd(s.ntiles * s.K * sx::kTile) + rnd(4 * n_rec + 4) +
        rnd(16 * s.E + 16) + rnd(4 * s.E + 4);
   b += rnd(4 * (s.ntiles + 1)) + rnd(4 * n_halo + 4) + rnd(2 * s.E) + rnd(s.ntiles);
   b += rnd(4 * (s.npad + 1)) + rnd(4 * n_em + 4) + rnd(8 * n_em + 8);
@@ -1098,6 +1099,8 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   uint32_t *d_mb2;
   GA(d_mb2, npad * S.kw);
   GA(d_rec_cnt, ntiles * K * sx::kRecGroups + 1);
+  uint8_t *d_rlane;
+  GA(d_rlane, ntiles * K * sx::kTile);
   GA(d_rec_ptr, ntiles * K * sx::kRecGroups + 1);
   int64_t *d_part;
   GA(d_part, ntiles * K * sx::kRecGroups / 1024 + 2);
@@ -1139,6 +1142,7 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   h.mbits = d_mb;
   h.mbits2 = d_mb2;
   h.rec_cnt = d_rec_cnt;
+  h.rec_lane = d_rlane;
   h.rec_ptr = d_rec_ptr;
   h.scan_part = d_part;
   h.smask = d_smask;

@@ -107,6 +107,8 @@ struct GridDev {
   uint32_t *mbits;          // [ntiles][kw][64]
   uint32_t *mbits2;         // [ntiles][kw][64] scratch: the new m words of a re-binning
   int32_t *rec_cnt;         // [ntiles*K*kRecGroups+1] scratch: records per (tile, bin, group)
+  uint8_t *rec_lane;        // [ntiles*K*64] scratch: records per (tile, bin, receiver lane),
+                            // 255 standing for 255 or more
   int32_t *rec_ptr;         // [ntiles*K*kRecGroups+1] first record of each
   int64_t *scan_part;       // [ntiles*K*kRecGroups/1024 + 2] scratch of the record scan
   int32_t *erev;            // [E+1] the edge of nbr[e]'s row that points back at e's row

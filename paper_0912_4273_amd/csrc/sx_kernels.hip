@@ -346,7 +346,9 @@ static_assert(SX_MAX_BINS_FP32 <= 128 && SX_MAX_BINS_FP64 <= 128 &&
 // kept per (tile, position, group of kRecGroupLanes receivers), so the
 // records of a (tile, position) come out sorted by lane; a lane's place in
 // its group comes from a shuffle scan of the counts.  Pass 1 counts the
-// records, pass 2 (after a scan) writes in-words and records.
+// records (per group for the scan, and per lane as bytes for pass 2), pass
+// 2 (after a scan) writes in-words and records.  Pass 2 walks again only
+// in a wave where a lane's count reached 255.
 constexpr int kInlistBins = 16;   // bin positions per wave of the gather-list build
 static_assert(kRecGroupLanes == 8, "the record scan below works on groups of 8 lanes");
 
@@ -431,19 +433,34 @@ __global__ __launch_bounds__(256) void k_inlist(const GridDev *__restrict__ gp) 
       }
     }
   };
-  walk(false);
+  uint8_t *rl = g.rec_lane + (int64_t)tile * K * kTile + lane;
   if (!FILL) {
+    walk(false);
     // sum over the 8 lanes of the group; its first lane writes
 #pragma unroll
     for (int b = 0; b < kInlistBins; ++b) {
       int v = rc[b];
+      const int p = p0 + b;
+      if (p < K) rl[p * kTile] = (uint8_t)(v < 255 ? v : 255);
       v += __shfl_xor(v, 1);
       v += __shfl_xor(v, 2);
       v += __shfl_xor(v, 4);
-      const int p = p0 + b;
       if ((lane & 7) == 0 && p < K) g.rec_cnt[((int64_t)tile * K + p) * kRecGroups + grp] = v;
     }
     return;
+  }
+  // this lane's counts from pass 1
+  bool sat = false;
+#pragma unroll
+  for (int b = 0; b < kInlistBins; ++b) {
+    const int p = p0 + b;
+    rc[b] = p < K ? (int)rl[p * kTile] : 0;
+    sat |= rc[b] == 255;
+  }
+  if (__ballot(sat)) {
+#pragma unroll
+    for (int b = 0; b < kInlistBins; ++b) rc[b] = 0;
+    walk(false);
   }
   // this lane's first record per bin: the group's offset plus the counts of
   // the group's lower lanes (inclusive scan over 8 lanes, minus its own)
