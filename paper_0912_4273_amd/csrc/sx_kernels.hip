@@ -152,22 +152,33 @@ __global__ void k_erev(const GridDev *__restrict__ gp) {
 // cos_min, ties to the lower id) in place of the bin.  A vertex's edge
 // directions are staged in LDS once and its bins run over them in row
 // order.
+// The three largest cosines so far, c0 >= c1 >= c2, all above cos_min (an
+// empty place holds cos_min and kEmptySlot, so "c > c2" also tests the
+// cone).  A candidate is tested against the third place first: most fail
+// there once the places are full.  Strict comparisons keep the earlier
+// (lower) slot on ties.
 struct Top3 {
-  double c0 = -3.0, c1 = -3.0, c2 = -3.0;
-  uint32_t s0 = kEmptySlot, s1 = kEmptySlot, s2 = kEmptySlot, cnt = 0;
-  __device__ __forceinline__ void add(double c, uint32_t s, double cos_min) {
-    if (!(c > cos_min)) return;
-    if (c > c0) {
-      c2 = c1; s2 = s1; c1 = c0; s1 = s0; c0 = c; s0 = s;
-    } else if (c > c1) {
-      c2 = c1; s2 = s1; c1 = c; s1 = s;
-    } else if (c > c2) {
-      c2 = c; s2 = s;
+  double c0, c1, c2;
+  uint32_t s0 = kEmptySlot, s1 = kEmptySlot, s2 = kEmptySlot;
+  __device__ __forceinline__ explicit Top3(double cos_min) : c0(cos_min), c1(cos_min), c2(cos_min) {}
+  __device__ __forceinline__ void add(double c, uint32_t s) {
+    if (c > c2) {
+      if (c > c1) {
+        c2 = c1; s2 = s1;
+        if (c > c0) {
+          c1 = c0; s1 = s0; c0 = c; s0 = s;
+        } else {
+          c1 = c; s1 = s;
+        }
+      } else {
+        c2 = c; s2 = s;
+      }
     }
-    ++cnt;
   }
   __device__ __forceinline__ uint32_t word(int mpb) const {
-    const uint32_t n = cnt > (uint32_t)mpb ? (uint32_t)mpb : cnt;
+    const uint32_t filled = (s0 != (uint32_t)kEmptySlot) + (s1 != (uint32_t)kEmptySlot) +
+                            (s2 != (uint32_t)kEmptySlot);
+    const uint32_t n = filled > (uint32_t)mpb ? (uint32_t)mpb : filled;
     const uint32_t t2 = mpb < 3 ? (uint32_t)kEmptySlot : s2;
     const uint32_t t1 = mpb < 2 ? (uint32_t)kEmptySlot : s1;
     return s0 | (t1 << 7) | (t2 << 14) | (n << 21);
@@ -198,10 +209,10 @@ __device__ __forceinline__ void select_bin(const GridDev &g, int64_t i, int k,
                                            const SX_L double *ed, SX_L uint32_t *ms, int n) {
   double u[3] = {g.bins[3 * k], g.bins[3 * k + 1], g.bins[3 * k + 2]};
   if (g.dct_ref) n = ref_edge(ed, n, g.cos_min, u);
-  Top3 a;
+  Top3 a(g.cos_min);
   for (int t = 0; t < n; ++t) {
     const double d[3] = {ed[3 * t], ed[3 * t + 1], ed[3 * t + 2]};
-    a.add(cosine3(d, u), (uint32_t)t, g.cos_min);
+    a.add(cosine3(d, u), (uint32_t)t);
   }
   const uint32_t word = a.word(g.mpb);
   g.fwd[i * g.k + k] = word;
@@ -616,88 +627,114 @@ __global__ __launch_bounds__(64 * 6) void k_mbits(GridDev *__restrict__ gp,
 // Ipre as it is.  Thread = vertex, tile = wave; the new field is written to
 // the other photon buffer (the one the next sweep would overwrite), with T
 // and any per-step state of combined transport and diffuse radiation copied
-// across, and k_flip then makes it current.  The map is the same for every
-// thread, so each read of an old bin is one coalesced wave load.  The
-// tile's escapes are summed by a butterfly.
+// across, and k_flip then makes it current.  A workgroup is one tile: it
+// stages the tile's old field in LDS first (one 16-byte load per lane and
+// block, all in flight together) and the map beside it, so the walk over
+// the new bins reads only LDS.  The tile's escapes are summed by a
+// butterfly.
+constexpr int kRebinChunk = 12;   // 16-byte loads per lane in flight
 template <typename P>
-__global__ __launch_bounds__(256) void k_rebin(GridDev *__restrict__ gp, RebinMap map) {
-  GridDev &g = *gp;
+__host__ __device__ constexpr int64_t rebin_lds_bytes(int kb) {
+  // old holdings by storage position, then the old m words
+  return (int64_t)kb * (kBlockBytes / sizeof(P)) * 64 * sizeof(P) + 6 * 64 * 4;
+}
+template <typename P>
+__global__ __launch_bounds__(64) void k_rebin(GridDev *__restrict__ gp, RebinMap map) {
   constexpr int BB = kBlockBytes / sizeof(P);
   typedef P V __attribute__((ext_vector_type(BB)));
-  const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (j >= g.npad) return;   // whole waves: npad is a multiple of 64
-  const int tile = j >> 6, lane = j & 63;
-  const int K = g.k, KB = g.kb, kw = g.kw;
-  const int par = g.parity;
-  const P *oin = (const P *)g.o[par];
-  V *oout = (V *)g.o[par ^ 1];
-  // old and new m, 16 bins per word in storage order, read before any old
-  // word is replaced
-  uint32_t mo[6], mw[6];
+  extern __shared__ __attribute__((aligned(16))) unsigned char rebin_lds[];
+  __shared__ uint8_t mptr[132], mlist[128];
+  const int tile = (int)blockIdx.x, lane = (int)threadIdx.x;
+  const int j = tile * 64 + lane;
+  // everything the walk needs, read once
+  const int K = gp->k, KB = gp->kb, kw = gp->kw;
+  const int par = gp->parity;
+  const SX_G V *__restrict__ oin = gld((const V *)gp->o[par]) + (int64_t)tile * KB * 64 + lane;
+  SX_G V *__restrict__ oout = gst((V *)gp->o[par ^ 1]) + (int64_t)tile * KB * 64 + lane;
+  SX_G uint32_t *__restrict__ mb = gst(gp->mbits) + (int64_t)tile * kw * 64 + lane;
+  const SX_G uint32_t *__restrict__ mb2 = gld(gp->mbits2) + (int64_t)tile * kw * 64 + lane;
+  P *ro = (P *)rebin_lds;                                            // [p * 64 + lane]
+  uint32_t *mol = (uint32_t *)(rebin_lds + (int64_t)KB * BB * 64 * sizeof(P));   // [q * 64 + lane]
+  for (int i = lane; i < 132; i += 64) mptr[i] = map.ptr[i];
+  for (int i = lane; i < 128; i += 64) mlist[i] = map.list[i];
+  for (int c = 0; c < KB; c += kRebinChunk) {
+    V v[kRebinChunk];
+#pragma unroll
+    for (int i = 0; i < kRebinChunk; ++i)
+      if (c + i < KB) v[i] = oin[(c + i) * 64];
+#pragma unroll
+    for (int i = 0; i < kRebinChunk; ++i)
+      if (c + i < KB) {
+#pragma unroll
+        for (int b = 0; b < BB; ++b) ro[((c + i) * BB + b) * 64 + lane] = v[i][b];
+      }
+  }
+  // old and new m, 16 bins per word in storage order; the old words go to
+  // LDS before the new ones replace them
+  uint32_t mw[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    mo[q] = q < kw ? g.mbits[((int64_t)tile * kw + q) * 64 + lane] : 0u;
-    mw[q] = q < kw ? g.mbits2[((int64_t)tile * kw + q) * 64 + lane] : 0u;
+    mw[q] = q < kw ? mb2[q * 64] : 0u;
+    if (q < kw) mol[q * 64 + lane] = mb[q * 64];
   }
-  auto pick = [](const uint32_t *a, int p) -> uint32_t {
-    const int q = p >> 4;
-    const uint32_t w = q == 0 ? a[0] : q == 1 ? a[1] : q == 2 ? a[2] : q == 3 ? a[3]
-                                                             : q == 4 ? a[4] : a[5];
-    return (w >> (2 * (p & 15))) & 3u;
-  };
-  auto m_old = [&](int p) -> uint32_t { return pick(mo, p); };
-  auto held = [&](int p) -> P {
-    return oin[(((int64_t)tile * KB + p / BB) * 64 + lane) * BB + p % BB];
-  };
-  const P Tp = ((const P *)g.t[par])[j];
+  const P Tp = gld((const P *)gp->t[par])[j];
   const double T = (double)Tp;
+  __syncthreads();
+  auto m_old = [&](int po) -> uint32_t {
+    return (mol[(po >> 4) * 64 + lane] >> (2 * (po & 15))) & 3u;
+  };
   double esc = 0.0;
-  uint32_t mword = 0;
+  uint32_t mword = 0, cw = mw[0];
   V out = V(0);
-  // new bins in storage order
-#pragma unroll 2
+  // new bins in storage order; every lane takes the same map entries
+#pragma unroll 4
   for (int p = 0; p < K; ++p) {
-    const uint32_t mn = pick(mw, p);
-    const int q0 = map.ptr[p], q1 = map.ptr[p + 1];
-    P val;
-    const int p1 = map.list[q0 < q1 ? q0 : 0];
-    if (q1 - q0 == 1 && mn > 0u && mn == m_old(p1)) {
-      val = held(p1);
-    } else {
-      double h = 0.0;
-      for (int q = q0; q < q1; ++q) {
-        const int po = map.list[q];
-        h += (double)held(po) * (double)m_old(po);
-      }
-      if (mn == 0u) {
-        esc += h * T;
-        val = P(0);
-      } else {
-        val = (P)(h / (double)mn);
-      }
+    if ((p & 15) == 0 && p > 0) {
+      const int q = p >> 4;
+      cw = q == 1 ? mw[1] : q == 2 ? mw[2] : q == 3 ? mw[3] : q == 4 ? mw[4] : mw[5];
     }
+    const uint32_t mn = (cw >> (2 * (p & 15))) & 3u;
+    const int q0 = mptr[p], q1 = mptr[p + 1];
+    // holdings m_old Ipre of the old bins, added in the map's order; the
+    // first one's Ipre and m kept for the one-to-one case
+    double h = 0.0;
+    P first = P(0);
+    uint32_t mfirst = 0;
+    for (int q = q0; q < q1; ++q) {
+      const int po = mlist[q];
+      const P v = ro[po * 64 + lane];
+      const uint32_t mo = m_old(po);
+      if (q == q0) {
+        first = v;
+        mfirst = mo;
+      }
+      h += (double)v * (double)mo;
+    }
+    const bool keep = q1 - q0 == 1 && mn > 0u && mn == mfirst;
+    esc += mn == 0u ? h * T : 0.0;
+    const P val = keep ? first : (mn == 0u ? P(0) : (P)(h / (double)mn));
     out[p % BB] = val;
     if (p % BB == BB - 1 || p == K - 1) {
-      oout[((int64_t)tile * KB + p / BB) * 64 + lane] = out;
+      oout[(p / BB) * 64] = out;
       out = V(0);
     }
     mword |= mn << (2 * (p & 15));
     if ((p & 15) == 15 || p == K - 1) {
-      g.mbits[((int64_t)tile * kw + p / 16) * 64 + lane] = mword;
+      mb[(p / 16) * 64] = mword;
       mword = 0;
     }
   }
-  ((P *)g.t[par ^ 1])[j] = Tp;
-  if (g.lay[0]) g.lay[par ^ 1][j] = g.lay[par][j];
-  if (g.oe[0])
-    for (int e = g.row_ptr[j]; e < g.row_ptr[j + 1]; ++e)
-      ((P *)g.oe[par ^ 1])[e] = ((const P *)g.oe[par])[e];
-  if (g.dsh[0]) ((P *)g.dsh[par ^ 1])[j] = ((const P *)g.dsh[par])[j];
+  gst((P *)gp->t[par ^ 1])[j] = Tp;
+  if (gp->lay[0]) gp->lay[par ^ 1][j] = gp->lay[par][j];
+  if (gp->oe[0])
+    for (int e = gp->row_ptr[j]; e < gp->row_ptr[j + 1]; ++e)
+      ((P *)gp->oe[par ^ 1])[e] = ((const P *)gp->oe[par])[e];
+  if (gp->dsh[0]) ((P *)gp->dsh[par ^ 1])[j] = ((const P *)gp->dsh[par])[j];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) esc += __shfl_xor(esc, off);
   if (lane == 0) {
-    g.tally[(int64_t)tile * 3 + 1] += esc;
-    g.tally[(int64_t)tile * 3 + 2] -= esc;
+    gp->tally[(int64_t)tile * 3 + 1] += esc;
+    gp->tally[(int64_t)tile * 3 + 2] -= esc;
   }
 }
 
@@ -1895,10 +1932,13 @@ hipError_t launch_rebin(GridDev *dg, const GridDev &hg, const RebinMap &map, hip
   // the new m words first, into the spare m array (coalesced reads for the
   // re-binning, which replaces the old words with them)
   hipLaunchKernelGGL(k_mbits, dim3((unsigned)hg.ntiles), dim3(64 * hg.kw), 0, s, dg, hg.mbits2);
+  // one workgroup per tile (npad is a multiple of 64)
   if (hg.precision == 0)
-    hipLaunchKernelGGL(k_rebin<double>, dim3(blocks_for(hg.npad, 256)), dim3(256), 0, s, dg, map);
+    hipLaunchKernelGGL(k_rebin<double>, dim3((unsigned)hg.ntiles), dim3(64),
+                       (size_t)rebin_lds_bytes<double>(hg.kb), s, dg, map);
   else
-    hipLaunchKernelGGL(k_rebin<float>, dim3(blocks_for(hg.npad, 256)), dim3(256), 0, s, dg, map);
+    hipLaunchKernelGGL(k_rebin<float>, dim3((unsigned)hg.ntiles), dim3(64),
+                       (size_t)rebin_lds_bytes<float>(hg.kb), s, dg, map);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_flip, dim3(1), dim3(1), 0, s, dg);
