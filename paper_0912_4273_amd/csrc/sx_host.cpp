@@ -580,12 +580,12 @@ int rebuild_routing(sx_ctx *ctx, Grid *g, const double *bins, const sx::RebinMap
   std::memcpy(ctx->pin, bins, sizeof(double) * 3 * h.k);
   HIP_TRY(ctx, hipMemcpyAsync(const_cast<double *>(h.bins), ctx->pin, sizeof(double) * 3 * h.k,
                               hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, sx::launch_select(dg, h, st));
+  // the selection writes the m words: into the spare array when the photons
+  // in flight are re-binned (which replaces the old words with them)
+  HIP_TRY(ctx, sx::launch_select(dg, h, rebin ? h.mbits2 : h.mbits, st));
   HIP_TRY(ctx, sx::launch_em_bins(dg, h, g->n_em, st));
   g->ebin_stale = true;   // the full edge-bin table is rebuilt when read
-  // m words; after a rotation the photons in flight are re-binned first
   if (rebin) HIP_TRY(ctx, sx::launch_rebin(dg, h, *rebin, st));
-  else HIP_TRY(ctx, sx::launch_mbits(dg, h, st));
   g->bins_cur.assign(bins, bins + 3 * h.k);
   // no clearing of the in-words: the fill rewrites the word of every bin
   // below K, and the padding bins of the last block keep their empty words
@@ -1210,7 +1210,7 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   hipError_t he;
   const int32_t nrow = (int32_t)(ntiles * K * sx::kRecGroups);
   if ((he = sx::launch_erev(dg, h, st)) != hipSuccess) return kfail(he);
-  if ((he = sx::launch_select(dg, h, st)) != hipSuccess) return kfail(he);
+  if ((he = sx::launch_select(dg, h, h.mbits, st)) != hipSuccess) return kfail(he);
   if ((he = sx::launch_edge_bins(dg, h, st)) != hipSuccess) return kfail(he);
   g->n_em = (int64_t)P->em_k.size();
   {
@@ -1246,7 +1246,6 @@ int commit(sx_ctx *ctx, sx_prepared *P, sx_grid_id *out) {
   g->bins0 = P->bins;
   g->bins_cur = P->bins;
   if ((r = write_slot(ctx, g))) { grid_release(ctx, g); return r; }
-  if ((he = sx::launch_mbits(dg, h, st)) != hipSuccess) return kfail(he);
   if ((he = sx::launch_clear_inw(h, st)) != hipSuccess) return kfail(he);
   if ((he = sx::launch_inlist_count(dg, h, st)) != hipSuccess) return kfail(he);
   if ((he = sx::launch_scan(h.rec_cnt, h.rec_ptr, h.scan_part, nrow, st)) != hipSuccess) return kfail(he);

@@ -182,7 +182,9 @@ struct GridDev {
 // Kernel launchers (sx_kernels.hip).  All enqueue on `stream`, return the
 // HIP error of the launch.
 hipError_t launch_erev(const GridDev *dg, const GridDev &hg, hipStream_t s);
-hipError_t launch_select(const GridDev *dg, const GridDev &hg, hipStream_t s);
+// Selection: forward words, selection masks, and the m words into mout
+// (mbits, or mbits2 ahead of a re-binning).
+hipError_t launch_select(const GridDev *dg, const GridDev &hg, uint32_t *mout, hipStream_t s);
 hipError_t launch_edge_bins(const GridDev *dg, const GridDev &hg, hipStream_t s);
 hipError_t launch_inlist_count(const GridDev *dg, const GridDev &hg, hipStream_t s);
 hipError_t launch_scan(int32_t *cnt, int32_t *ptr, int64_t *part, int32_t n, hipStream_t s);
@@ -202,7 +204,6 @@ static_assert(SX_MAX_BINS_FP32 < 128 && SX_MAX_BINS_FP64 < 128, "rebin map holds
 hipError_t launch_rebin(GridDev *dg, const GridDev &hg, const RebinMap &map, hipStream_t s);
 // Bin of each source share from its edge's bin.
 hipError_t launch_em_bins(GridDev *dg, const GridDev &hg, int64_t n_em, hipStream_t s);
-hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s);
 // Combined transport, from the selection and the edge bins: the bin of each
 // in-edge, and per in-edge the sender's bins that hold the receiver (count,
 // then fill after a scan of the counts into kl_ptr).

@@ -206,7 +206,8 @@ __device__ __forceinline__ int ref_edge(const SX_L double *ed, int deg, double c
 // The forward word of (vertex, bin k) over the vertex's n staged edge
 // directions, and the bits of its selected slots in the vertex's masks.
 __device__ __forceinline__ void select_bin(const GridDev &g, int64_t i, int k,
-                                           const SX_L double *ed, SX_L uint32_t *ms, int n) {
+                                           const SX_L double *ed, SX_L uint32_t *ms,
+                                           SX_L uint32_t *mw, int n) {
   double u[3] = {g.bins[3 * k], g.bins[3 * k + 1], g.bins[3 * k + 2]};
   if (g.dct_ref) n = ref_edge(ed, n, g.cos_min, u);
   Top3 a(g.cos_min);
@@ -224,6 +225,9 @@ __device__ __forceinline__ void select_bin(const GridDev &g, int64_t i, int k,
     const uint32_t s = (word >> (7 * q)) & 127u;
     if (s != (uint32_t)kEmptySlot) atomicOr((uint32_t *)&ms[4 * s + (p >> 5)], 1u << (p & 31));
   }
+  // and m at bits 2 (p mod 16) of the vertex's m word p / 16
+  const uint32_t m = (word >> 21) & 3u;
+  if (m) atomicOr((uint32_t *)&mw[p >> 4], m << (2 * (p & 15)));
 }
 
 // One wave per two vertices: bins 0..63 of the first vertex, then of the
@@ -232,21 +236,28 @@ __device__ __forceinline__ void select_bin(const GridDev &g, int64_t i, int k,
 static_assert(SX_MAX_BINS_FP32 <= 96 && SX_MAX_BINS_FP64 <= 96,
               "k_select covers bins 0..95: a larger bin limit needs another pass");
 // LDS of k_select per workgroup (8 vertices), sized by the grid's largest
-// degree: the edge directions, then the selection masks
+// degree: the edge directions, the selection masks, then 6 m words per vertex
+constexpr int kSelMWords = 6;
+static_assert((SX_MAX_BINS_FP32 + 15) / 16 <= kSelMWords && (SX_MAX_BINS_FP64 + 15) / 16 <= kSelMWords,
+              "k_select keeps at most 6 m words per vertex");
 __host__ __device__ constexpr int64_t select_lds_bytes(int max_deg) {
-  return 8 * (3 * 8 + 4 * 4) * (int64_t)max_deg;
+  return 8 * (3 * 8 + 4 * 4) * (int64_t)max_deg + 8 * kSelMWords * 4;
 }
 
 // 8 waves per SIMD: the compiler then fits the kernel in 48 VGPRs without
 // spilling (88 by default, 5 waves), and the FP64 chains hide each other
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_select(
-    const GridDev *__restrict__ gp) {
+    const GridDev *__restrict__ gp, uint32_t *__restrict__ mout) {
   const GridDev &g = *gp;
   extern __shared__ __attribute__((aligned(16))) double sel_lds[];
   const int md = g.max_deg;
   // vertex slot s: edge directions at sd(s), masks (4 words per out-edge) at sm(s)
   auto sd = [&](int s) { return sel_lds + (int64_t)s * 3 * md; };
   auto sm = [&](int s) { return (uint32_t *)(sel_lds + (int64_t)8 * 3 * md) + (int64_t)s * 4 * md; };
+  // m words of vertex slot s
+  auto smw = [&](int s) {
+    return (uint32_t *)(sel_lds + (int64_t)8 * 3 * md) + (int64_t)8 * 4 * md + s * kSelMWords;
+  };
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t i0 = ((int64_t)blockIdx.x * 4 + w) * 2;   // npad is even
   const bool live = i0 < g.npad;   // the block's barriers are reached by all
@@ -264,6 +275,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     SX_L uint32_t *ms = (SX_L uint32_t *)sm(2 * w + v);
     for (int q = lane; q < 3 * deg[v]; q += 64) ed[q] = g.edir[3 * (int64_t)rb[v] + q];
     for (int q = lane; q < 4 * deg[v]; q += 64) ms[q] = 0u;
+    if (lane < kSelMWords) ((SX_L uint32_t *)smw(2 * w + v))[lane] = 0u;
   }
   __syncthreads();
   if (live) {
@@ -271,13 +283,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     for (int v = 0; v < 2; ++v)
       if (lane < K)
         select_bin(g, i0 + v, lane, (const SX_L double *)sd(2 * w + v),
-                   (SX_L uint32_t *)sm(2 * w + v), deg[v]);
+                   (SX_L uint32_t *)sm(2 * w + v), (SX_L uint32_t *)smw(2 * w + v), deg[v]);
     const int v = lane >> 5, k = 64 + (lane & 31);
     if (k < K)
       select_bin(g, i0 + v, k, (const SX_L double *)sd(2 * w + v), (SX_L uint32_t *)sm(2 * w + v),
-                 v == 0 ? deg[0] : deg[1]);
+                 (SX_L uint32_t *)smw(2 * w + v), v == 0 ? deg[0] : deg[1]);
   }
   __syncthreads();
+  // the m words, tile-major ([tile][word][lane]); padding vertices get zeros
+  if (live && lane < g.kw) {
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int64_t i = i0 + v;
+      mout[((i >> 6) * g.kw + lane) * 64 + (i & 63)] = ((const SX_L uint32_t *)smw(2 * w + v))[lane];
+    }
+  }
   // out-edge (i, t) is the receiver's in-edge erev[rb + t]; the masks are
   // four planes of E + 1 words (word q of edge e at q (E + 1) + e)
   typedef uint32_t U4 __attribute__((ext_vector_type(4)));
@@ -590,31 +610,6 @@ __global__ void k_em_bins(GridDev *__restrict__ gp, int64_t n_em) {
     if (c > cb) { cb = c; best = k; }
   }
   g.em_k[q] = best;
-}
-
-// Packed m(j, k), 2 bits per bin and 16 bins per word in storage order
-// (position p at bits 2 (p mod 16) of word p / 16), from the selection: one
-// workgroup per tile and one wave per 16-bin word (thread = word * 64 +
-// lane).
-static_assert((SX_MAX_BINS_FP32 + 15) / 16 <= 6 && (SX_MAX_BINS_FP64 + 15) / 16 <= 6,
-              "k_mbits holds at most 6 m words per vertex (one wave each)");
-
-__global__ __launch_bounds__(64 * 6) void k_mbits(GridDev *__restrict__ gp,
-                                                  uint32_t *__restrict__ out) {
-  GridDev &g = *gp;
-  const int tile = blockIdx.x, q = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int j = tile * kTile + lane;
-  const int K = g.k;
-  const int k0 = 16 * q;
-  // positions k0 .. k0 + 15 of the storage order
-  uint32_t v[16];
-#pragma unroll
-  for (int b = 0; b < 16; ++b)
-    v[b] = (j < g.n && k0 + b < K) ? g.fwd[(int64_t)j * K + g.bperm[k0 + b]] : 0u;
-  uint32_t mword = 0;
-#pragma unroll
-  for (int b = 0; b < 16; ++b) mword |= ((v[b] >> 21) & 3u) << (2 * b);
-  out[((int64_t)tile * g.kw + q) * 64 + lane] = mword;
 }
 
 // Re-binning after a rotation of the bins.  Photons keep their direction as
@@ -1892,10 +1887,10 @@ hipError_t launch_erev(const GridDev *dg, const GridDev &hg, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_select(const GridDev *dg, const GridDev &hg, hipStream_t s) {
+hipError_t launch_select(const GridDev *dg, const GridDev &hg, uint32_t *mout, hipStream_t s) {
   // one wave per two vertices, four waves per workgroup
   hipLaunchKernelGGL(k_select, dim3(blocks_for((int64_t)hg.npad * 32, 256)),
-                     dim3(256), (unsigned)select_lds_bytes(hg.max_deg), s, dg);
+                     dim3(256), (unsigned)select_lds_bytes(hg.max_deg), s, dg, mout);
   return hipGetLastError();
 }
 
@@ -1922,16 +1917,7 @@ hipError_t launch_clear_inw(const GridDev &hg, hipStream_t s) {
   return fill<uint64_t>(hg.inw, 0ull, (int64_t)hg.ntiles * hg.kb * kTile, s);
 }
 
-hipError_t launch_mbits(const GridDev *dg, const GridDev &hg, hipStream_t s) {
-  hipLaunchKernelGGL(k_mbits, dim3((unsigned)hg.ntiles), dim3(64 * hg.kw), 0, s,
-                     const_cast<GridDev *>(dg), hg.mbits);
-  return hipGetLastError();
-}
-
 hipError_t launch_rebin(GridDev *dg, const GridDev &hg, const RebinMap &map, hipStream_t s) {
-  // the new m words first, into the spare m array (coalesced reads for the
-  // re-binning, which replaces the old words with them)
-  hipLaunchKernelGGL(k_mbits, dim3((unsigned)hg.ntiles), dim3(64 * hg.kw), 0, s, dg, hg.mbits2);
   // one workgroup per tile (npad is a multiple of 64)
   if (hg.precision == 0)
     hipLaunchKernelGGL(k_rebin<double>, dim3((unsigned)hg.ntiles), dim3(64),
