@@ -28,3 +28,19 @@ def test_algorithmic_bytes():
     assert abs(all_dct - w.n * w.k * bench.algorithmic_bytes_per_update(w.k, 4)) < 1e-6
     all_bal = bench.combined_bytes_per_step(w, np.ones(w.n, np.int8), 4)
     assert abs(all_bal - (w.n_edges * 9.0 + 110.0 * w.n)) < 1e-6
+
+
+def test_traffic_only_for_the_profiled_kernel_source(monkeypatch):
+    """`roofline.traffic` quotes the committed counter summary only while it
+    was taken on the current kernel source; any other source gives null."""
+    import json
+    d = json.load(open(os.path.join(ROOT, "profiles", "sweep_traffic.json")))
+    key = "stromgren_262144_k84_1000sweeps"
+    e = d[key]
+    assert abs(e["bytes_per_launch"] - (e["fetch_bytes"] + e["write_bytes"])) <= 2
+    assert e["bytes_per_launch"] >= e["algorithmic_bytes"]
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: e["kernel_sha"])
+    assert bench.measured_traffic(key) == e["bytes_per_launch"]
+    assert bench.measured_traffic("no_such_workload") is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.measured_traffic(key) is None
