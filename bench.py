@@ -205,7 +205,12 @@ def serve_leg(ctx, pool, args, log):
         srv.submit(w, w.n_sweeps)
         if (r + 1) % 100 == 0:
             log(f"serve: {r + 1}/{len(arr)} submitted, {len(results)} done")
-    th.join(timeout=max(600.0, 4 * args.serve_seconds))
+    # drain: the requests still queued or on the GPU, reported as they finish
+    deadline = time.perf_counter() + max(600.0, 4 * args.serve_seconds)
+    while th.is_alive() and time.perf_counter() < deadline:
+        th.join(timeout=30.0)
+        if th.is_alive():
+            log(f"serve: all {len(arr)} submitted, {len(results)} done")
     wall = time.perf_counter() - t0
     st = srv.stop()
     ctx.set_schedule([], graph_sweeps=args.graph_sweeps)
